@@ -1,0 +1,65 @@
+"""Dense brute-force references for small inputs (n <= 64).
+
+They pin the oracle from outside: each is written from the dense linear
+algebra definition (LAPACK through scipy, or an explicit O(n^3) loop in a
+different loop order than the oracle's), never by calling the oracle.
+"""
+import numpy as np
+import scipy.linalg as sl
+
+
+def solve_lower(ld, b):
+    return sl.solve_triangular(ld, b, lower=True)
+
+
+def solve_upper_t(ld, c):
+    return sl.solve_triangular(ld.T, c, lower=False)
+
+
+def ic0_right_looking(ad, mask):
+    """Zero fill-in incomplete Cholesky by the right-looking (outer-product)
+    recurrence on a dense copy: column k is scaled, then every later entry
+    (i, j) that is inside the lower pattern is updated.  Returns (L, first
+    failing column or -1)."""
+    n = ad.shape[0]
+    a = np.tril(ad).astype(np.float64).copy()
+    m = np.tril(mask).astype(bool)
+    fail = -1
+    for k in range(n):
+        if not (a[k, k] > 0) and fail < 0:
+            fail = k
+        a[k, k] = np.sqrt(a[k, k]) if a[k, k] > 0 else np.nan
+        for i in range(k + 1, n):
+            if m[i, k]:
+                a[i, k] = a[i, k] / a[k, k]
+        for j in range(k + 1, n):
+            if not m[j, k]:
+                continue
+            for i in range(j, n):
+                if m[i, k] and m[i, j]:
+                    a[i, j] -= a[i, k] * a[j, k]
+    return np.where(m, a, 0.0), fail
+
+
+def levels_longest_path(ld):
+    """Longest path from any source in the DAG j -> i for L_ij != 0 (j < i),
+    by dynamic programming over a dense adjacency with the Bellman recurrence
+    iterated to a fixed point (independent of row order)."""
+    n = ld.shape[0]
+    adj = (ld != 0) & ~np.eye(n, dtype=bool)
+    lv = np.zeros(n, dtype=np.int64)
+    for _ in range(n + 1):
+        cand = np.where(adj, lv[None, :] + 1, 0).max(axis=1) if n else lv
+        new = np.maximum(lv, cand)
+        if np.array_equal(new, lv):
+            break
+        lv = new
+    return lv
+
+
+def dense_gradients(ld, ad, b, w):
+    """loss = w^T A L^{-1} b.  Returns (x, grad_b, grad_L dense masked)."""
+    x = solve_lower(ld, b)
+    lam = solve_upper_t(ld, ad.T @ w)
+    gl = -np.outer(lam, x) * (ld != 0)
+    return x, lam, gl
