@@ -1,0 +1,324 @@
+"""Benchmark: fused SpTRSV -> SpMV GB/s and fraction of HBM peak on one
+MI355X, against the unfused two-phase GPU baseline, with forward+backward
+and SpIC0 -> SpTRSV timings beside it.
+
+One step = one fused execution x = L^{-1} b, y = A x on each matrix of the
+workload (the 3D 7-point Laplacian on a 128^3 grid and the random sparse SPD
+matrix with n = 1,000,000), FP64, one right-hand side, inputs resident in
+HBM.  value = algorithmic bytes of the step / step time.
+
+Algorithmic bytes of one SpTRSV -> SpMV execution (FP64, int32 indices):
+    nnz(L) * 12 + nnz(A) * 12 + (n + 1) * 4 + (m + 1) * 4 + (2n + m) * 8
+(values + column indices of L and A, both row-pointer arrays, b read, x and
+y written).  Flags, cached x re-reads and polling traffic are excluded.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_ts_fused.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_12238_amd", "csrc", f) for f in ("k_ts.hip", "dev_common.h")]
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def ts_bytes(n, m, nnz_l, nnz_a, vb=8):
+    return nnz_l * (vb + 4) + nnz_a * (vb + 4) + (n + 1) * 4 + (m + 1) * 4 + (2 * n + m) * vb
+
+
+def it_bytes(n, nnz_l):
+    # read lower(A) (values + indices + row pointers), write L values, read b, write x
+    return nnz_l * 12 + (n + 1) * 4 + nnz_l * 8 + 16 * n
+
+
+def bwd_bytes(n, m, nnz_l, nnz_a, vb):
+    # forward SpTRSV -> SpMV plus: A^T and L^T patterns + values, the L^T map,
+    # g, x, lambda, grad_L
+    fwd = ts_bytes(n, m, nnz_l, nnz_a, vb)
+    back = nnz_a * (vb + 4) + 4 * (n + 1) + nnz_l * (vb + 4) + 4 * (n + 1) + 4 * nnz_l + 3 * n * vb + nnz_l * vb
+    return fwd + back
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_bytes_key):
+    """Measured HBM bytes per launch from the committed rocprofv3 --pmc
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha") != sources_sha():
+        return None
+    return t.get(kernel_bytes_key)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (every GPU box here "
+              "has one GPU); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2111_12238_amd as sfm
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    work = []
+    for name in ("lap3d7_128", "randspd_1m"):
+        t0 = time.time()
+        L, A = synth.workload(name)
+        log("generated %s n=%d nnz(L)=%d nnz(A)=%d in %.1fs" % (name, L.nrows, L.nnz, A.nnz, time.time() - t0))
+        s = sfm.Schedule(L, A)
+        st = s.info()
+        b = synth.vec_uniform(L.nrows, seed=1)
+        d = dict(name=name, L=L, A=A, s=s, b=b,
+                 Lv=torch.as_tensor(L.val, device=dev), Av=torch.as_tensor(A.val, device=dev),
+                 B=torch.as_tensor(b, device=dev),
+                 X=torch.empty(L.nrows, dtype=torch.float64, device=dev),
+                 Y=torch.empty(A.nrows, dtype=torch.float64, device=dev),
+                 bytes=ts_bytes(L.nrows, A.nrows, L.nnz, A.nnz), depth=st.depth, joint_depth=st.joint_depth,
+                 inspect_s=st.inspect_seconds)
+        if not args.no_autotune:
+            t0 = time.time()
+            sfm.autotune(s, d["Lv"], d["Av"], d["B"])
+            log("autotuned %s in %.1fs: lanes_trsv=%d lanes_spmv=%d rows_per_item=%d waves_per_cu=%d" % (
+                name, time.time() - t0, s.get_param("lanes_trsv"), s.get_param("lanes_spmv"),
+                s.get_param("rows_per_item"), s.get_param("waves_per_cu")))
+        work.append(d)
+
+    def step(unfused=False, events=None):
+        for k, d in enumerate(work):
+            if events is not None:
+                events[k][0].record(stream)
+            sfm.trsv_spmv(d["s"], d["Lv"], d["Av"], d["B"], X=d["X"], Y=d["Y"], unfused=unfused)
+            if events is not None:
+                events[k][1].record(stream)
+
+    def timed(unfused):
+        for _ in range(args.warmup):
+            step(unfused)
+        torch.cuda.synchronize()
+        per = [[0.0, 0] for _ in work]
+        e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in work] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        e_start.record(stream)
+        for k in range(args.steps):
+            step(unfused, evs[k])
+        e_end.record(stream)
+        torch.cuda.synchronize()
+        for d in work:
+            sfm.sync_status(d["s"])
+        total_ms = e_start.elapsed_time(e_end)
+        for k in range(args.steps):
+            for j in range(len(work)):
+                per[j][0] += evs[k][j][0].elapsed_time(evs[k][j][1])
+                per[j][1] += 1
+        return total_ms / args.steps, [p[0] / p[1] for p in per]
+
+    log("timing fused (%d warmup, %d steps)" % (args.warmup, args.steps))
+    ms_step, per_launch = timed(False)
+    xs = [d["X"].cpu().numpy() for d in work]
+    ys = [d["Y"].cpu().numpy() for d in work]
+    log("timing unfused level-set baseline")
+    ms_step_u, per_launch_u = timed(True)
+    step_bytes = sum(d["bytes"] for d in work)
+    value = step_bytes / (ms_step * 1e-3) / 1e9
+
+    # roofline of the dominant kernel (the fused launch with the most time)
+    j = int(np.argmax(per_launch))
+    dk = work[j]
+    achieved = dk["bytes"] / (per_launch[j] * 1e-3) / 1e9
+    traffic = load_traffic("bytes_per_launch_" + dk["name"])
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "k_ts_fused (%s)" % dk["name"], "algorithmic_bytes_per_launch": dk["bytes"],
+                "avg_launch_ms": round(per_launch[j], 4)}
+
+    per_matrix = {}
+    for k, d in enumerate(work):
+        gbs = d["bytes"] / (per_launch[k] * 1e-3) / 1e9
+        gbs_u = d["bytes"] / (per_launch_u[k] * 1e-3) / 1e9
+        per_matrix[d["name"]] = {
+            "n": d["L"].nrows, "nnz_L": d["L"].nnz, "nnz_A": d["A"].nnz, "depth": d["depth"],
+            "joint_depth": d["joint_depth"], "bytes": d["bytes"],
+            "fused_ms": round(per_launch[k], 4), "fused_GBps": round(gbs, 1),
+            "fused_frac_peak": round(gbs / HBM_PEAK_GBPS, 4),
+            "unfused_ms": round(per_launch_u[k], 4), "unfused_GBps": round(gbs_u, 1),
+            "speedup_vs_unfused": round(per_launch_u[k] / per_launch[k], 3),
+            "inspect_s": round(d["inspect_s"], 3),
+            "NER_vs_unfused": round(d["inspect_s"] * 1e3 / (per_launch_u[k] - per_launch[k]), 1)
+            if per_launch_u[k] > per_launch[k] else None,
+            "critical_path_us_per_level": round(per_launch[k] * 1e3 / max(d["joint_depth"], 1), 3),
+        }
+
+    extras = {}
+    if not args.no_extras:
+        extras = run_extras(args, sfm, synth, torch, dev, stream)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, work, xs, ys, per_matrix)
+
+    line = {
+        "metric": "fused SpTRSV+SpMV GB/s & %HBM peak vs unfused GPU at 1e-10 err; fwd+bwd ms",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "SpTRSV->SpMV FP64 1 RHS: 3D 7-point Laplacian 128^3 (n=2,097,152) + "
+                               "random sparse SPD n=1,000,000 (2-30 off-diagonals per row, symmetrized)",
+                   "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
+        "frac_peak": round(value / HBM_PEAK_GBPS, 4),
+        "unfused_GBps": round(step_bytes / (ms_step_u * 1e-3) / 1e9, 1),
+        "speedup_vs_unfused": round(ms_step_u / ms_step, 3),
+        "per_matrix": per_matrix,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_extras(args, sfm, synth, torch, dev, stream):
+    """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted) and forward +
+    backward (7-point 96^3, FP64 and FP32): fused vs unfused times."""
+    out = {}
+
+    def time_it(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(3, args.steps // 2)
+    for name in ("lap3d27_64", "lap3d27_64_perm"):
+        Lp, _ = synth.workload(name)
+        s = sfm.Schedule(Lp, None, sfm.SF_IC0_TRSV)
+        Av = torch.as_tensor(Lp.val, device=dev)
+        b = torch.as_tensor(synth.vec_normal(Lp.nrows, seed=1), device=dev)
+        Lv = torch.empty_like(Av)
+        X = torch.empty_like(b)
+        f = lambda: sfm.ic0_trsv(s, Av, b, L_val=Lv, X=X, check_info=False)
+        u = lambda: sfm.ic0_trsv(s, Av, b, L_val=Lv, X=X, check_info=False, unfused=True)
+        tf, tu = time_it(f, reps), time_it(u, reps)
+        sfm.sync_status(s)
+        nb = it_bytes(Lp.nrows, Lp.nnz)
+        out["ic0_trsv_" + name] = {"depth": s.info().depth, "fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
+                                   "speedup_vs_unfused": round(tu / tf, 3),
+                                   "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
+                                   "inspect_s": round(s.info().inspect_seconds, 3)}
+        log("ic0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
+    L, A = synth.workload("lap3d7_96")
+    s = sfm.Schedule(L, A, want_backward=True)
+    for dt, tname, vb in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
+        Lv = torch.as_tensor(L.val, device=dev).to(dt)
+        Av = torch.as_tensor(A.val, device=dev).to(dt)
+        b = torch.as_tensor(synth.vec_uniform(L.nrows, seed=1), device=dev).to(dt)
+        w = torch.as_tensor(synth.vec_normal(A.nrows, seed=2), device=dev).to(dt)
+        X = torch.empty_like(b)
+        Y = torch.empty_like(w)
+
+        def fb():
+            sfm.trsv_spmv(s, Lv, Av, b, X=X, Y=Y)
+            sfm.backward(s, Lv, Av, w, X=X)
+
+        t = time_it(fb, reps)
+        nb = bwd_bytes(L.nrows, A.nrows, L.nnz, A.nnz, vb)
+        out["fwd_bwd_lap3d7_96_" + tname] = {"ms": round(t, 4), "GBps": round(nb / (t * 1e-3) / 1e9, 1),
+                                             "bytes": nb, "back_depth": s.info().back_depth}
+        log("fwd+bwd 96^3 %s %.3f ms" % (tname, t))
+    sfm.sync_status(s)
+    return out
+
+
+def cpu_baseline(args, work, xs, ys, per_matrix):
+    """The sequential FP64 oracle on the host, single thread, on the same
+    matrices; also gives each GPU result's error against it."""
+    import numpy as np
+
+    import oracle
+    total_bytes, total_s, runs = 0.0, 0.0, 0
+    errs = {}
+    for k, d in enumerate(work):
+        L, A, b = d["L"], d["A"], d["b"]
+        t0 = time.perf_counter()
+        x = oracle.trsv_lower(L.rowptr, L.col, L.val, b)
+        y = oracle.spmv(A.rowptr, A.col, A.val, x)
+        dt = time.perf_counter() - t0
+        total_bytes += d["bytes"]
+        total_s += dt
+        runs += 1
+        ex = float(np.abs(xs[k] - x).max() / np.abs(x).max())
+        ey = float(np.abs(ys[k] - y).max() / np.abs(y).max())
+        errs[d["name"]] = {"x_rel_err": ex, "y_rel_err": ey}
+        per_matrix[d["name"]]["x_rel_err_vs_oracle"] = ex
+        per_matrix[d["name"]]["y_rel_err_vs_oracle"] = ey
+        per_matrix[d["name"]]["oracle_ms"] = round(dt * 1e3, 2)
+    # repeat whole passes until the time budget is used
+    while total_s < args.cpu_seconds:
+        for d in work:
+            L, A, b = d["L"], d["A"], d["b"]
+            t0 = time.perf_counter()
+            x = oracle.trsv_lower(L.rowptr, L.col, L.val, b)
+            oracle.spmv(A.rowptr, A.col, A.val, x)
+            total_s += time.perf_counter() - t0
+            total_bytes += d["bytes"]
+            runs += 1
+    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "%d sequential oracle SpTRSV+SpMV passes over the two full workload matrices "
+                      "(%.1f s, single thread of %d host cores)" % (runs, total_s, os.cpu_count() or 0),
+            "errors_vs_oracle": errs}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,294 @@
+/*
+ * sf.h — C ABI of the MI355X fused sparse executor (libsparsefusion.so).
+ *
+ * The library runs two sparse kernels, at least one of which carries loop
+ * dependences, as one schedule over their joint dependence DAG (Cheshmi,
+ * Strout, Mehri Dehnavi, "Composing Loop-carried Dependence with Other
+ * Loops", arXiv 2111.12238):
+ *   - SpTRSV -> SpMV:  x = L^{-1} b, then y = A x       (Sec. 1, Fig. 2;
+ *                                                        Table 2, comb. 4)
+ *   - SpIC0 -> SpTRSV: L L^T ~= A (zero fill), then x = L^{-1} b
+ *                                                       (Table 2, comb. 5)
+ * plus the adjoint of y = A L^{-1} b, batched right-hand sides and FP32
+ * solves with FP64 residual refinement.
+ *
+ * Following the paper's inspector-executor driver (Sec. 2, Fig. 3b): the
+ * inspector runs once on the host from the sparsity patterns and builds a
+ * schedule (dependence levels, the joint claim order, work items); the
+ * executor calls then run that schedule on the GPU as many times as needed.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns sf_status; nothing throws across the ABI.
+ *   - Sparse matrices are CSR with int32 row pointers and column indices,
+ *     columns strictly ascending inside a row (no duplicates).
+ *   - Patterns passed to sf_inspect are HOST pointers, read during the call
+ *     only; the schedule keeps its own copies.
+ *   - Values and vectors passed to the executor calls are DEVICE pointers
+ *     owned by the caller, laid out in the CSR order of the inspected
+ *     pattern.  Dense blocks of right-hand sides are column-major
+ *     (element (i, c) at ptr[i + c * ld]).
+ *   - Executor calls are asynchronous and stream-ordered on the hipStream_t
+ *     given (cast to void*; NULL = the default stream).  Launch and HIP
+ *     errors are returned synchronously as SF_ERR_HIP.  Numerical
+ *     breakdown of SpIC0 is reported through a device word (see
+ *     sf_exec_ic0_trsv); a spin watchdog that fires is reported by
+ *     sf_sync_status.
+ *   - A schedule is immutable after sf_inspect except for the small device
+ *     state it owns (readiness flags, claim counters); executions of one
+ *     schedule must therefore not overlap (issue them on one stream, or
+ *     synchronise between streams).
+ *   - NaN and Inf in values propagate and are not checked.  A diagonal
+ *     entry whose value is exactly 0.0 gives Inf/NaN in the solution.
+ */
+#ifndef SF_H_
+#define SF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SF_OK = 0,
+  SF_ERR_ARG = 1,          /* NULL pointer, bad size, bad option value */
+  SF_ERR_CSR = 2,          /* rowptr not monotone, column out of range, unsorted or duplicate */
+  SF_ERR_NOT_LOWER = 3,    /* L has an entry above the diagonal */
+  SF_ERR_ZERO_DIAG = 4,    /* a row of L has no stored diagonal entry */
+  SF_ERR_SHAPE = 5,        /* dimensions of L, A, B, X, Y do not agree */
+  SF_ERR_NOT_SPD = 6,      /* reserved: SpIC0 breakdown is reported through d_info */
+  SF_ERR_HIP = 7,          /* a HIP runtime call or kernel launch failed */
+  SF_ERR_OOM = 8,          /* device or host allocation failed */
+  SF_ERR_TIMEOUT = 9,      /* the executor's spin watchdog fired (a dependence never became ready) */
+  SF_ERR_UNSUPPORTED = 10  /* valid request this build does not implement */
+} sf_status;
+
+typedef enum { SF_F64 = 0, SF_F32 = 1 } sf_dtype;
+
+typedef enum {
+  SF_TRSV_SPMV = 0, /* L and A given: x = L^{-1} b, y = A x */
+  SF_IC0_TRSV = 1   /* lower(A) given as L: L L^T ~= A, x = L^{-1} b */
+} sf_kind;
+
+/* A sparsity pattern on the host: nrows x ncols, rowptr[nrows + 1],
+ * colind[rowptr[nrows]]. */
+typedef struct {
+  int32_t nrows;
+  int32_t ncols;
+  const int32_t* rowptr;
+  const int32_t* colind;
+} sf_csr_pattern;
+
+/* Opaque, library-owned schedule. */
+typedef struct sf_schedule_s* sf_schedule;
+
+/* Inspector options; 0 in any field selects the default. */
+typedef struct {
+  int32_t kind;           /* sf_kind */
+  int32_t rows_per_item;  /* maximum rows in one work item (default: from lanes_per_row) */
+  int32_t max_item_nnz;   /* nonzero budget of one work item, the paper's cost c(v) = nonzeros
+                             touched (Sec. 3.1); default 4096 */
+  int32_t rhs_block;      /* right-hand sides walked together per DAG pass (default: autotuned
+                             / all) */
+  int32_t lanes_per_row;  /* lanes of a 64-wide wavefront cooperating on one SpTRSV row
+                             (1, 2, 4, 8, 16, 32, 64; default from the mean row length) */
+  int32_t want_backward;  /* 1: also build the transposed (upper-solve) schedule for sf_backward */
+  int32_t validate;       /* 1: check the built schedule against every DAG edge before returning */
+  int32_t no_fusion;      /* 1: executor calls run the unfused two-phase baseline instead (the
+                             paper's fusion = False switch, Sec. 2.4) */
+} sf_inspect_opts;
+
+/* Summary of a schedule (host values). */
+typedef struct {
+  int64_t n;               /* rows of L */
+  int64_t m;               /* rows of A (SpMV iterations); 0 for SF_IC0_TRSV */
+  int64_t nnz_l;
+  int64_t nnz_a;
+  int32_t depth;           /* number of wavefronts (levels) of the SpTRSV DAG */
+  int32_t joint_depth;     /* number of wavefronts of the joint DAG */
+  int32_t back_depth;      /* levels of the transposed solve (0 if not built) */
+  int32_t n_items;         /* work items of the fused forward schedule */
+  int32_t n_back_items;    /* work items of the backward schedule */
+  int32_t max_level_width; /* widest SpTRSV wavefront */
+  int32_t lanes_per_row;   /* lanes per SpTRSV row in effect */
+  int32_t lanes_per_spmv;  /* lanes per SpMV row in effect */
+  double reuse_ratio;      /* Sec. 2.2: common / max(per-kernel) accesses */
+  double inspect_seconds;  /* host time spent in sf_inspect */
+} sf_schedule_stats;
+
+/*
+ * sf_inspect — build a schedule from sparsity patterns (host only; does not
+ * touch the GPU).
+ *   L: n x n lower-triangular pattern, every row holding its diagonal
+ *      (for SF_IC0_TRSV: the lower triangle of A, diagonal included).
+ *   A: m x n pattern of the SpMV operand (SF_TRSV_SPMV), NULL for
+ *      SF_IC0_TRSV.
+ * Dependence DAGs (Sec. 2.2): each stored L_ij, j < i, is an edge j -> i
+ * (structural: stored zeros count); F = pattern(A) for a CSR SpMV, so SpMV
+ * row r depends on every x_j it reads; for SpIC0 -> SpTRSV, F = I.
+ * Levels, the joint order (joint level, SpTRSV before SpMV, row) and the
+ * work items (runs of one level and one kind, at most rows_per_item rows
+ * and max_item_nnz nonzeros) are computed here.
+ * Errors: SF_ERR_ARG, SF_ERR_CSR, SF_ERR_NOT_LOWER, SF_ERR_ZERO_DIAG,
+ * SF_ERR_SHAPE, SF_ERR_OOM.  On error *out is set to NULL.
+ */
+sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A,
+                     const sf_inspect_opts* opts, sf_schedule* out);
+
+/* Release a schedule and every host and device buffer it owns.  Waits for
+ * the device to finish work that uses it.  NULL is accepted. */
+sf_status sf_schedule_free(sf_schedule s);
+
+/* Fill *st with the schedule's summary. */
+sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st);
+
+/*
+ * Copy the schedule to host arrays (for validation against the DAG):
+ *   level[n]       wavefront of each SpTRSV row;
+ *   order[n + m]   iteration ids in claim order.  SF_TRSV_SPMV: SpTRSV row i
+ *                  is id i, SpMV row r is id n + r.  SF_IC0_TRSV: SpIC0 row
+ *                  i is id i and SpTRSV row i is id n + i (n + n ids);
+ *   item_ptr[n_items + 1]  item t holds order[item_ptr[t] .. item_ptr[t+1]).
+ * Any pointer may be NULL to skip that array.
+ */
+sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int32_t* item_ptr);
+
+/* Backward (transposed-solve) schedule: rlevel[n], order[n] (rows),
+ * item_ptr[n_back_items + 1].  SF_ERR_ARG if it was not built. */
+sf_status sf_schedule_export_backward(sf_schedule s, int32_t* rlevel, int32_t* order,
+                                      int32_t* item_ptr);
+
+/*
+ * sf_exec_trsv_spmv — fused SpTRSV -> SpMV (Sec. 1; Table 2, comb. 4, with a
+ * CSR SpMV).  For each right-hand side c < nrhs:
+ *     X[:, c] = L^{-1} B[:, c],    Y[:, c] = A X[:, c]
+ * in one persistent kernel launch: wavefronts claim work items in the joint
+ * order, wait on per-row readiness flags of the rows they read, and start
+ * each SpMV row as soon as the x entries it reads are final.
+ *   dtype:  SF_F64 or SF_F32 (values, vectors and accumulation).
+ *   L_val:  device, nnz(L) values in the inspected order.
+ *   A_val:  device, nnz(A) values; may be NULL when Y is NULL.
+ *   B:      device n x nrhs, leading dimension ldb >= n.
+ *   X:      device n x nrhs output, ldx >= n.  Must not alias B.
+ *   Y:      device m x nrhs output, ldy >= m; NULL runs the solve only.
+ *   nrhs:   1..64.
+ * Errors: SF_ERR_ARG, SF_ERR_SHAPE, SF_ERR_HIP, SF_ERR_OOM.
+ */
+sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
+                            const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
+                            void* Y, int32_t ldy, void* stream);
+
+/*
+ * The unfused two-phase baseline on the same GPU (the paper's unfused
+ * comparison, Sec. 4): a level-set SpTRSV that takes one grid-wide barrier
+ * per wavefront (one persistent cooperative launch), then a separate CSR
+ * SpMV launch.  Same arguments and results as sf_exec_trsv_spmv.
+ */
+sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val,
+                                    const void* A_val, const void* B, int32_t ldb, int32_t nrhs,
+                                    void* X, int32_t ldx, void* Y, int32_t ldy, void* stream);
+
+/*
+ * sf_exec_ic0_trsv — fused SpIC0 -> SpTRSV (Table 2, comb. 5), FP64.
+ * The schedule must be of kind SF_IC0_TRSV.  Computes the zero fill-in
+ * incomplete Cholesky factor L of A (pattern = lower(A)) by the up-looking
+ * row recurrence
+ *     L_ij = (A_ij - sum_{k<j, k in P_i and P_j} L_ik L_jk) / L_jj,
+ *     L_ii = sqrt(A_ii - sum_{k<i} L_ik^2),
+ * and in the same work item x_i = (b_i - sum_{j<i} L_ij x_j) / L_ii (the
+ * interleaved packing of Sec. 3.3: reuse ratio >= 1).
+ *   A_lower_val: device, values of lower(A) in the inspected pattern.
+ *   L_val:       device output, same pattern.
+ *   B, X:        device n x nrhs (nrhs == 1 in this build).
+ *   d_info:      device int32 written at the end of the launch: -1 if every
+ *                pivot was > 0, else the smallest row whose pivot was <= 0
+ *                or NaN (its dependents still run; values are then NaN).
+ */
+sf_status sf_exec_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
+                           const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
+                           int32_t* d_info, void* stream);
+
+/* Unfused baseline for SpIC0 -> SpTRSV: a level-set SpIC0 with a grid
+ * barrier per wavefront, then a level-set SpTRSV.  Same arguments. */
+sf_status sf_exec_unfused_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val,
+                                   void* L_val, const void* B, int32_t ldb, int32_t nrhs, void* X,
+                                   int32_t ldx, int32_t* d_info, void* stream);
+
+/*
+ * sf_backward — adjoint of y = A L^{-1} b (not in the paper).  Given
+ * G = dloss/dy (m values), computes with one persistent launch over the
+ * transposed schedule (needs want_backward at inspection):
+ *     c = A^T G,  lambda = L^{-T} c   (upper solve, reversed levels),
+ *     grad_B = lambda,  grad_L_val[p] = -lambda_i x_j  for stored p = (i, j).
+ * X holds x = L^{-1} B from the forward pass; if X is NULL it is recomputed
+ * from B into the caller's workspace (activation recomputation instead of
+ * storage).  workspace may be NULL when X is given; otherwise it must hold
+ * sf_backward_workspace_bytes(s, dtype, 1) bytes.  Single right-hand side.
+ */
+sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
+                      const void* X, const void* B, const void* G, void* grad_B, void* grad_L_val,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs);
+
+/*
+ * sf_refine_trsv_spmv — FP32 solves with FP64 residual refinement.
+ *   1. x0 = L32^{-1} b in FP32 (fused kernel, FP32 accumulation);
+ *   2. n_corrections times: r = b - L64 x in FP64, d = L32^{-1} r in FP32,
+ *      x += d in FP64;
+ *   3. y = A64 x with FP64 values and accumulation, and the final relative
+ *      residual max_i |b - L64 x|_i / max_i |b_i| per column.
+ *   L32/L64: device values of L in FP32 and FP64 (same pattern); A64:
+ *   device FP64 values of A.  B, X (n x nrhs, ld), Y (m x nrhs, ldy): FP64.
+ *   out_relres: HOST array of nrhs doubles, filled after a stream sync
+ *   (this call synchronises the stream when out_relres is not NULL).
+ *   n_corrections: 0..8 (2 is the usual choice).
+ *   workspace: device scratch of sf_refine_workspace_bytes(s, nrhs) bytes.
+ */
+sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64,
+                              const double* A64, const double* B, int32_t ldb, int32_t nrhs,
+                              double* X, int32_t ldx, double* Y, int32_t ldy,
+                              int32_t n_corrections, double* out_relres, void* workspace,
+                              size_t ws_bytes, void* stream);
+
+size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
+
+/*
+ * Tuning knobs of the executor (defaults are set by sf_inspect):
+ *   "lanes_trsv", "lanes_spmv"  lanes per row (1..64, power of two);
+ *   "rhs_block"                 right-hand sides per DAG pass (1..64);
+ *   "waves_per_cu"              persistent-grid residency target (1..32);
+ *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT.
+ */
+sf_status sf_set_param(sf_schedule s, const char* key, int64_t value);
+sf_status sf_get_param(sf_schedule s, const char* key, int64_t* value);
+
+/*
+ * sf_autotune — time executor variants on the device with the caller's
+ * data and keep the fastest (lanes per row, RHS block width, residency).
+ * Results are cached in the schedule.  Synchronises the stream.
+ *   out_best_ms: HOST, the best time per execution (may be NULL).
+ */
+sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
+                      const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx, void* Y,
+                      int32_t ldy, void* stream, double* out_best_ms);
+
+/* Synchronise the stream and report a watchdog timeout of an earlier
+ * execution on this schedule (SF_ERR_TIMEOUT), clearing it; SF_OK else. */
+sf_status sf_sync_status(sf_schedule s, void* stream);
+
+/* Time of the last kernel launched by an executor call, measured with HIP
+ * events on the executor's stream when enabled with
+ * sf_set_param(s, "timing", 1); *ms is filled after a stream sync. */
+sf_status sf_last_kernel_ms(sf_schedule s, double* ms);
+
+const char* sf_status_str(sf_status st);
+
+/* Library version string. */
+const char* sf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SF_H_ */

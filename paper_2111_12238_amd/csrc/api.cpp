@@ -1,0 +1,841 @@
+// C ABI of the fused sparse executor: schedule lifecycle, device upload,
+// executor calls, refinement driver and autotuner.  See include/sf.h for the
+// contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "kargs.h"
+#include "schedule.h"
+
+using namespace sf;
+
+namespace {
+
+sf_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return SF_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SF_ERR_OOM;
+  return SF_ERR_HIP;
+}
+
+#define SF_HIP(x)                                  \
+  do {                                             \
+    const hipError_t e_ = (x);                     \
+    if (e_ != hipSuccess) return hip_status(e_);   \
+  } while (0)
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return cus;
+}
+
+// Sub-allocator over one hipMalloc'ed block: arrays are placed at 256-byte
+// aligned offsets.
+struct Packer {
+  size_t off = 0;
+  std::vector<std::pair<size_t, const std::vector<int32_t>*>> items;
+  size_t add(const std::vector<int32_t>* v) {
+    const size_t at = off;
+    items.emplace_back(at, v);
+    off += (v->size() * sizeof(int32_t) + 255) / 256 * 256;
+    if (v->empty()) off += 256;
+    return at;
+  }
+};
+
+void free_device(sf_schedule_s* s) {
+  DeviceBuffers& d = s->dev;
+  if (d.device >= 0) {
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(d.device);
+    hipDeviceSynchronize();
+    if (d.block) hipFree(d.block);
+    if (d.state) hipFree(d.state);
+    if (d.flags) hipFree(d.flags);
+    if (d.xi) hipFree(d.xi);
+    hipSetDevice(cur);
+  }
+  d = DeviceBuffers();
+}
+
+// Upload the constant arrays and the work items; allocate the state block
+// and one flag per row.  Called at the first executor call (and again after
+// the items are re-cut by the autotuner).
+sf_status upload(sf_schedule_s* s, hipStream_t st) {
+  DeviceBuffers& d = s->dev;
+  int cur = 0;
+  SF_HIP(hipGetDevice(&cur));
+  if (d.ready && d.device == cur) return SF_OK;
+  if (d.ready && d.device != cur) return SF_ERR_ARG;  // a schedule lives on one device
+  Packer pk;
+  const size_t oLrp = pk.add(&s->L.rp), oLci = pk.add(&s->L.ci);
+  const size_t oArp = pk.add(&s->A.rp), oAci = pk.add(&s->A.ci);
+  const size_t oOrd = pk.add(&s->order), oIp = pk.add(&s->item_ptr), oTi = pk.add(&s->trsv_items);
+  const size_t oLi = pk.add(&s->lvl_items), oLip = pk.add(&s->lvl_item_ptr);
+  const size_t oLTrp = pk.add(&s->LT.rp), oLTci = pk.add(&s->LT.ci), oLTm = pk.add(&s->LT_map);
+  const size_t oATrp = pk.add(&s->AT.rp), oATci = pk.add(&s->AT.ci), oATm = pk.add(&s->AT_map);
+  const size_t oBo = pk.add(&s->border), oBip = pk.add(&s->bitem_ptr);
+  const size_t oPp = pk.add(&s->pair_ptr), oPu = pk.add(&s->pair_u), oPq = pk.add(&s->pair_q);
+  void* block = nullptr;
+  SF_HIP(hipMalloc(&block, pk.off));
+  char* b = static_cast<char*>(block);
+  for (auto& it : pk.items)
+    if (!it.second->empty())
+      if (hipMemcpyAsync(b + it.first, it.second->data(), it.second->size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st) != hipSuccess) {
+        hipFree(block);
+        return SF_ERR_HIP;
+      }
+  auto P = [&](size_t o) { return reinterpret_cast<int32_t*>(b + o); };
+  d.block = block;
+  d.block_bytes = pk.off;
+  d.Lrp = P(oLrp); d.Lci = P(oLci); d.Arp = P(oArp); d.Aci = P(oAci);
+  d.order = P(oOrd); d.item_ptr = P(oIp); d.trsv_items = P(oTi);
+  d.lvl_items = P(oLi); d.lvl_item_ptr = P(oLip);
+  d.LTrp = P(oLTrp); d.LTci = P(oLTci); d.LTmap = P(oLTm);
+  d.ATrp = P(oATrp); d.ATci = P(oATci); d.ATmap = P(oATm);
+  d.border = P(oBo); d.bitem_ptr = P(oBip);
+  d.pair_ptr = P(oPp); d.pair_u = P(oPu); d.pair_q = P(oPq);
+  if (!d.state) {
+    std::vector<int32_t> init(kStateWords, 0);
+    for (int p = 0; p < 2; ++p) init[info_off(p)] = kInfoNone;
+    SF_HIP(hipMalloc(&d.state, kStateWords * sizeof(int32_t)));
+    SF_HIP(hipMemcpy(d.state, init.data(), kStateWords * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  if (!d.flags) {
+    const size_t bytes = std::max<int64_t>(s->n, 1) * sizeof(int32_t);
+    SF_HIP(hipMalloc(&d.flags, bytes));
+    SF_HIP(hipMemsetAsync(d.flags, 0, bytes, st));
+    d.flag_blocks = 1;
+    d.epoch = 0;
+  }
+  SF_HIP(hipStreamSynchronize(st));  // host vectors may change after a re-cut
+  d.device = cur;
+  d.ready = true;
+  return SF_OK;
+}
+
+sf_status ensure_flags(sf_schedule_s* s, int64_t blocks, hipStream_t st) {
+  DeviceBuffers& d = s->dev;
+  if (d.flag_blocks >= blocks) return SF_OK;
+  SF_HIP(hipStreamSynchronize(st));
+  if (d.flags) SF_HIP(hipFree(d.flags));
+  d.flags = nullptr;
+  const size_t bytes = size_t(std::max<int64_t>(s->n, 1)) * size_t(blocks) * sizeof(int32_t);
+  SF_HIP(hipMalloc(&d.flags, bytes));
+  SF_HIP(hipMemsetAsync(d.flags, 0, bytes, st));
+  d.flag_blocks = blocks;
+  return SF_OK;
+}
+
+sf_status ensure_xi(sf_schedule_s* s, size_t bytes, hipStream_t st) {
+  DeviceBuffers& d = s->dev;
+  if (d.xi_bytes >= bytes) return SF_OK;
+  SF_HIP(hipStreamSynchronize(st));
+  if (d.xi) SF_HIP(hipFree(d.xi));
+  d.xi = nullptr;
+  d.xi_bytes = 0;
+  SF_HIP(hipMalloc(&d.xi, bytes));
+  d.xi_bytes = bytes;
+  return SF_OK;
+}
+
+// Next launch epoch.  Flags equal to the epoch mean "final in this launch";
+// before the counter could wrap, the flags are cleared and the epoch
+// restarts with the same parity (the state block alternates by parity).
+sf_status next_epoch(sf_schedule_s* s, hipStream_t st, LaunchState& ls) {
+  DeviceBuffers& d = s->dev;
+  uint32_t e = d.epoch + 1;
+  if (e >= (1u << 30)) {
+    SF_HIP(hipMemsetAsync(d.flags, 0, size_t(std::max<int64_t>(s->n, 1)) * size_t(d.flag_blocks) * 4, st));
+    e = (e & 1u) ? 1u : 2u;
+  }
+  d.epoch = e;
+  ls.state = d.state;
+  ls.epoch = int32_t(e);
+  ls.spin_limit = int32_t(std::min<int64_t>(s->spin_limit, std::numeric_limits<int32_t>::max()));
+  ls.streams = std::max(1, std::min(s->claim_streams, kStreams));
+  return SF_OK;
+}
+
+int persistent_grid(sf_schedule_s* s, int occupancy_blocks_per_cu) {
+  const int cus = std::max(1, device_cus());
+  const int want = std::max(1, s->waves_per_cu * 64 / kBlockThreads);
+  const int per_cu = std::min(want, std::max(1, occupancy_blocks_per_cu));
+  return std::max(cus * per_cu, kStreams);
+}
+
+struct Timer {
+  sf_schedule_s* s;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  Timer(sf_schedule_s* s_, hipStream_t st_) : s(s_), st(st_) {
+    if (s->timing) {
+      hipEventCreate(&e0);
+      hipEventCreate(&e1);
+      hipEventRecord(e0, st);
+    }
+  }
+  void stop() {
+    if (s->timing && e0) {
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      s->last_kernel_ms = ms;
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      e0 = e1 = nullptr;
+    }
+  }
+  ~Timer() { stop(); }
+};
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int default_kb(int nrhs) {
+  int kb = 2;
+  while (kb < nrhs && kb < 64) kb *= 2;
+  return kb;
+}
+
+TsArgs ts_args(sf_schedule_s* s, const void* Lv, const void* Av, const void* B, int ldb, int nrhs,
+               void* X, int ldx, void* Y, int ldy) {
+  const DeviceBuffers& d = s->dev;
+  TsArgs a{};
+  a.n = int32_t(s->n);
+  a.m = int32_t(s->m);
+  a.Lrp = d.Lrp; a.Lci = d.Lci; a.Lv = Lv;
+  a.Arp = d.Arp; a.Aci = d.Aci; a.Av = Av;
+  a.B = B; a.ldb = ldb; a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy;
+  a.nrhs = nrhs;
+  a.order = d.order;
+  a.item_ptr = d.item_ptr;
+  if (Y) {
+    a.item_list = nullptr;
+    a.n_work = int32_t(s->item_ptr.size() - 1);
+  } else {
+    a.item_list = d.trsv_items;
+    a.n_work = int32_t(s->trsv_items.size());
+  }
+  a.flags = d.flags;
+  return a;
+}
+
+sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
+                        int ldb, int nrhs, void* X, int ldx, void* Y, int ldy, hipStream_t st) {
+  const int dtype = dt == SF_F64 ? 0 : 1;
+  const size_t es = dt == SF_F64 ? 8 : 4;
+  TsArgs a = ts_args(s, Lv, Av, B, ldb, nrhs, X, ldx, Y, ldy);
+  if (a.n_work == 0) return SF_OK;
+  if (nrhs == 1) {
+    sf_status r = next_epoch(s, st, a.ls);
+    if (r != SF_OK) return r;
+    a.flags = s->dev.flags;
+    a.kb = 1;
+    a.nblk = 1;
+    const int grid = persistent_grid(s, occupancy_ts_fused(dtype, s->lanes_trsv, s->lanes_spmv));
+    Timer tm(s, st);
+    return hip_status(launch_ts_fused(a, dtype, s->lanes_trsv, s->lanes_spmv, grid, st));
+  }
+  const int kb = s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
+  const int nblk = (nrhs + kb - 1) / kb;
+  sf_status r = ensure_flags(s, nblk, st);
+  if (r != SF_OK) return r;
+  r = ensure_xi(s, size_t(nblk) * size_t(s->n) * size_t(kb) * es, st);
+  if (r != SF_OK) return r;
+  r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  a.flags = s->dev.flags;
+  a.kb = kb;
+  a.nblk = nblk;
+  a.xi = s->dev.xi;
+  const int grid = persistent_grid(s, occupancy_ts_multi(dtype, kb));
+  Timer tm(s, st);
+  return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
+}
+
+sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
+                          int ldb, int nrhs, void* X, int ldx, void* Y, int ldy, hipStream_t st) {
+  const int dtype = dt == SF_F64 ? 0 : 1;
+  const size_t es = dt == SF_F64 ? 8 : 4;
+  LevelArgs la{};
+  la.ts = ts_args(s, Lv, Av, B, ldb, nrhs, X, ldx, Y, ldy);
+  la.ts.item_list = s->dev.lvl_items;
+  la.ts.n_work = int32_t(s->lvl_items.size());
+  la.lvl_item_ptr = s->dev.lvl_item_ptr;
+  la.depth = s->depth;
+  int kb = 1, nblk = 1;
+  if (nrhs > 1) {
+    kb = 8;  // the level-set multi-RHS path is compiled for blocks of 8
+    nblk = (nrhs + kb - 1) / kb;
+    sf_status r = ensure_xi(s, size_t(nblk) * size_t(s->n) * size_t(kb) * es, st);
+    if (r != SF_OK) return r;
+    la.ts.xi = s->dev.xi;
+  }
+  la.ts.kb = kb;
+  la.ts.nblk = nblk;
+  sf_status r = next_epoch(s, st, la.ts.ls);
+  if (r != SF_OK) return r;
+  Timer tm(s, st);
+  if (s->n > 0 && s->depth > 0) {
+    const int cus = std::max(1, device_cus());
+    const int occ = occupancy_trsv_levelset(dtype, s->lanes_trsv);
+    int grid = cus * std::min(occ, std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+    SF_HIP(launch_trsv_levelset(la, dtype, s->lanes_trsv, grid, st));
+  }
+  if (Y && s->m > 0) {
+    SpmvArgs sa{};
+    sa.m = int32_t(s->m);
+    sa.nrhs = nrhs;
+    sa.Arp = s->dev.Arp;
+    sa.Aci = s->dev.Aci;
+    sa.Av = Av;
+    sa.X = X;
+    sa.ldx = ldx;
+    sa.Y = Y;
+    sa.ldy = ldy;
+    SF_HIP(launch_spmv(sa, dtype, s->lanes_spmv, st));
+  }
+  return SF_OK;
+}
+
+sf_status check_ts_args(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
+                        int ldb, int nrhs, void* X, int ldx, void* Y, int ldy) {
+  if (!s) return SF_ERR_ARG;
+  if (s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+  if (dt != SF_F64 && dt != SF_F32) return SF_ERR_ARG;
+  if (nrhs < 1 || nrhs > 64) return SF_ERR_ARG;
+  if (s->n > 0 && (!Lv || !B || !X)) return SF_ERR_ARG;
+  if (Y && s->m > 0 && !Av) return SF_ERR_ARG;
+  if (ldb < s->n || ldx < s->n || (Y && ldy < s->m)) return SF_ERR_SHAPE;
+  if (B == X && s->n > 0) return SF_ERR_ARG;
+  return SF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sf_version(void) { return "sparsefusion-mi355x 0.1 (gfx950)"; }
+
+const char* sf_status_str(sf_status st) {
+  switch (st) {
+    case SF_OK: return "ok";
+    case SF_ERR_ARG: return "invalid argument";
+    case SF_ERR_CSR: return "malformed CSR (row pointers, column range, order or duplicates)";
+    case SF_ERR_NOT_LOWER: return "L has an entry above the diagonal";
+    case SF_ERR_ZERO_DIAG: return "a row of L has no stored diagonal";
+    case SF_ERR_SHAPE: return "dimension mismatch";
+    case SF_ERR_NOT_SPD: return "incomplete Cholesky breakdown (non-positive pivot)";
+    case SF_ERR_HIP: return "HIP runtime or launch error";
+    case SF_ERR_OOM: return "out of memory";
+    case SF_ERR_TIMEOUT: return "executor watchdog: a dependence never became ready";
+    case SF_ERR_UNSUPPORTED: return "unsupported in this build";
+  }
+  return "unknown status";
+}
+
+sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_inspect_opts* opts,
+                     sf_schedule* out) {
+  if (!out) return SF_ERR_ARG;
+  *out = nullptr;
+  sf_inspect_opts o{};
+  if (opts) o = *opts;
+  if (o.kind != SF_TRSV_SPMV && o.kind != SF_IC0_TRSV) return SF_ERR_ARG;
+  if (o.lanes_per_row != 0 && !pow2_in(o.lanes_per_row, 2, 64)) return SF_ERR_ARG;
+  if (o.rows_per_item < 0 || o.max_item_nnz < 0 || o.rhs_block < 0 || o.rhs_block > 64) return SF_ERR_ARG;
+  if (o.kind == SF_TRSV_SPMV && !A) return SF_ERR_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  sf_status st = sf::check_lower(L);
+  if (st != SF_OK) return st;
+  if (o.kind == SF_TRSV_SPMV) {
+    st = sf::check_general(A, L->nrows);
+    if (st != SF_OK) return st;
+  }
+  sf_schedule_s* s = new (std::nothrow) sf_schedule_s();
+  if (!s) return SF_ERR_OOM;
+  try {
+    st = sf::build_schedule(s, L, A, o);
+  } catch (const std::bad_alloc&) {
+    st = SF_ERR_OOM;
+  }
+  if (st == SF_OK && o.validate && sf::validate_forward(s) != 0) st = SF_ERR_ARG;
+  if (st != SF_OK) {
+    delete s;
+    return st;
+  }
+  s->claim_streams = kStreams;
+  s->inspect_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = s;
+  return SF_OK;
+}
+
+sf_status sf_schedule_free(sf_schedule s) {
+  if (!s) return SF_OK;
+  free_device(s);
+  delete s;
+  return SF_OK;
+}
+
+sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st) {
+  if (!s || !st) return SF_ERR_ARG;
+  st->n = s->n;
+  st->m = s->m;
+  st->nnz_l = s->L.nnz();
+  st->nnz_a = s->A.nnz();
+  st->depth = s->depth;
+  st->joint_depth = s->joint_depth;
+  st->back_depth = s->back_depth;
+  st->n_items = int32_t(s->item_ptr.size()) - 1;
+  st->n_back_items = s->has_back ? int32_t(s->bitem_ptr.size()) - 1 : 0;
+  st->max_level_width = s->max_level_width;
+  st->lanes_per_row = s->lanes_trsv;
+  st->lanes_per_spmv = s->lanes_spmv;
+  st->reuse_ratio = s->reuse;
+  st->inspect_seconds = s->inspect_seconds;
+  return SF_OK;
+}
+
+sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int32_t* item_ptr) {
+  if (!s) return SF_ERR_ARG;
+  if (level) std::copy(s->level.begin(), s->level.end(), level);
+  if (order) {
+    if (s->kind == SF_TRSV_SPMV) {
+      std::copy(s->order.begin(), s->order.end(), order);
+    } else {
+      // each row contributes its SpIC0 iteration (id i) then its SpTRSV one (id n + i)
+      for (size_t q = 0; q < s->order.size(); ++q) {
+        order[2 * q] = s->order[q];
+        order[2 * q + 1] = int32_t(s->n) + s->order[q];
+      }
+    }
+  }
+  if (item_ptr) {
+    const int mult = s->kind == SF_TRSV_SPMV ? 1 : 2;
+    for (size_t t = 0; t < s->item_ptr.size(); ++t) item_ptr[t] = mult * s->item_ptr[t];
+  }
+  return SF_OK;
+}
+
+sf_status sf_schedule_export_backward(sf_schedule s, int32_t* rlevel, int32_t* order, int32_t* item_ptr) {
+  if (!s || !s->has_back) return SF_ERR_ARG;
+  if (rlevel) std::copy(s->rlevel.begin(), s->rlevel.end(), rlevel);
+  if (order) std::copy(s->border.begin(), s->border.end(), order);
+  if (item_ptr) std::copy(s->bitem_ptr.begin(), s->bitem_ptr.end(), item_ptr);
+  return SF_OK;
+}
+
+sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
+                            const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx, void* Y,
+                            int32_t ldy, void* stream) {
+  sf_status r = check_ts_args(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy);
+  if (r != SF_OK) return r;
+  if (s->n == 0) return SF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  r = upload(s, st);
+  if (r != SF_OK) return r;
+  if (s->no_fusion) return exec_ts_unfused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
+  return exec_ts_fused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
+}
+
+sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
+                                    const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
+                                    void* Y, int32_t ldy, void* stream) {
+  sf_status r = check_ts_args(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy);
+  if (r != SF_OK) return r;
+  if (s->n == 0) return SF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  r = upload(s, st);
+  if (r != SF_OK) return r;
+  return exec_ts_unfused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
+}
+
+static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
+                            const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
+                            int32_t* d_info, bool fused, void* stream) {
+  if (!s || s->kind != SF_IC0_TRSV) return SF_ERR_ARG;
+  if (dtype != SF_F64) return SF_ERR_UNSUPPORTED;
+  if (nrhs != 1) return SF_ERR_UNSUPPORTED;
+  if (s->n > 0 && (!A_lower_val || !L_val)) return SF_ERR_ARG;
+  if (ldb < s->n || ldx < s->n) return SF_ERR_SHAPE;
+  const bool solve = B != nullptr;
+  if (solve && !X) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (s->max_offdiag > s->lanes_trsv) return SF_ERR_UNSUPPORTED;  // one lane per entry of a row
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sf_status r = upload(s, st);
+  if (r != SF_OK) return r;
+  const DeviceBuffers& d = s->dev;
+  Ic0Args a{};
+  a.n = int32_t(s->n);
+  a.Lrp = d.Lrp;
+  a.Lci = d.Lci;
+  a.Aval = static_cast<const double*>(A_lower_val);
+  a.Lval = static_cast<double*>(L_val);
+  a.B = static_cast<const double*>(B);
+  a.X = static_cast<double*>(X);
+  a.pair_ptr = d.pair_ptr;
+  a.pair_u = d.pair_u;
+  a.pair_q = d.pair_q;
+  a.order = d.order;
+  a.item_ptr = d.item_ptr;
+  a.flags = d.flags;
+  a.d_info = d_info;
+  a.factor = 1;
+  const int cus = std::max(1, device_cus());
+  Timer tm(s, st);
+  if (fused) {
+    r = next_epoch(s, st, a.ls);
+    if (r != SF_OK) return r;
+    a.item_list = nullptr;
+    a.n_work = int32_t(s->item_ptr.size() - 1);
+    a.solve = solve ? 1 : 0;
+    const int grid = persistent_grid(s, occupancy_ic0(s->lanes_trsv, 0));
+    return hip_status(launch_ic0_fused(a, s->lanes_trsv, grid, st));
+  }
+  // unfused: level-set factorisation, then a level-set solve
+  r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  a.item_list = d.lvl_items;
+  a.n_work = int32_t(s->lvl_items.size());
+  a.lvl_item_ptr = d.lvl_item_ptr;
+  a.depth = s->depth;
+  a.solve = 0;
+  int grid = cus * std::min(occupancy_ic0(s->lanes_trsv, 1), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  SF_HIP(launch_ic0_levelset(a, s->lanes_trsv, grid, st));
+  if (!solve) return SF_OK;
+  LevelArgs la{};
+  la.ts.n = int32_t(s->n);
+  la.ts.Lrp = d.Lrp;
+  la.ts.Lci = d.Lci;
+  la.ts.Lv = L_val;
+  la.ts.B = B;
+  la.ts.ldb = ldb;
+  la.ts.X = X;
+  la.ts.ldx = ldx;
+  la.ts.nrhs = 1;
+  la.ts.kb = 1;
+  la.ts.nblk = 1;
+  la.ts.order = d.order;
+  la.ts.item_ptr = d.item_ptr;
+  la.ts.item_list = d.lvl_items;
+  la.ts.n_work = a.n_work;
+  la.ts.flags = d.flags;
+  la.lvl_item_ptr = d.lvl_item_ptr;
+  la.depth = s->depth;
+  r = next_epoch(s, st, la.ts.ls);
+  if (r != SF_OK) return r;
+  const int g = std::min(s->lanes_trsv, 32);
+  grid = cus * std::min(occupancy_trsv_levelset(0, g), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  return hip_status(launch_trsv_levelset(la, 0, g, grid, st));
+}
+
+sf_status sf_exec_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
+                           const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
+                           int32_t* d_info, void* stream) {
+  if (s && s->no_fusion)
+    return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, false, stream);
+  return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, true, stream);
+}
+
+sf_status sf_exec_unfused_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
+                                   const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
+                                   int32_t* d_info, void* stream) {
+  return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, false, stream);
+}
+
+size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs) {
+  if (!s) return 0;
+  const size_t es = dtype == SF_F64 ? 8 : 4;
+  return size_t(std::max<int64_t>(s->n, 1)) * size_t(std::max(nrhs, 1)) * es;
+}
+
+sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val, const void* X,
+                      const void* B, const void* G, void* grad_B, void* grad_L_val, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  if (!s || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+  if (!s->has_back) return SF_ERR_ARG;
+  if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (!L_val || !G || !grad_B || !grad_L_val || (s->m > 0 && !A_val)) return SF_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sf_status r = upload(s, st);
+  if (r != SF_OK) return r;
+  const int dt = dtype == SF_F64 ? 0 : 1;
+  const void* x = X;
+  if (!x) {
+    if (!B || !workspace || ws_bytes < sf_backward_workspace_bytes(s, dtype, 1)) return SF_ERR_ARG;
+    r = exec_ts_fused(s, dtype, L_val, nullptr, B, int32_t(s->n), 1, workspace, int32_t(s->n), nullptr, 0, st);
+    if (r != SF_OK) return r;
+    x = workspace;
+  }
+  const DeviceBuffers& d = s->dev;
+  BwdArgs a{};
+  a.n = int32_t(s->n);
+  a.LTrp = d.LTrp; a.LTci = d.LTci; a.LTmap = d.LTmap;
+  a.ATrp = d.ATrp; a.ATci = d.ATci; a.ATmap = d.ATmap;
+  a.Lrp = d.Lrp; a.Lci = d.Lci;
+  a.Lv = L_val; a.Av = A_val; a.X = x; a.G = G;
+  a.lam = grad_B; a.gradL = grad_L_val;
+  a.order = d.border;
+  a.item_ptr = d.bitem_ptr;
+  a.n_work = int32_t(s->bitem_ptr.size() - 1);
+  a.flags = d.flags;
+  r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  const int grid = persistent_grid(s, occupancy_bwd(dt, s->lanes_trsv));
+  Timer tm(s, st);
+  return hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st));
+}
+
+size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs) {
+  if (!s) return 0;
+  const size_t nk = size_t(std::max<int64_t>(s->n, 1)) * size_t(std::max(nrhs, 1));
+  // r32 | d32 | x ping | x pong | max-abs accumulators
+  return nk * 4 * 2 + nk * 8 * 2 + 2 * 64 * 8 + 4 * 256;
+}
+
+sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64, const double* A64,
+                              const double* B, int32_t ldb, int32_t nrhs, double* X, int32_t ldx,
+                              double* Y, int32_t ldy, int32_t n_corrections, double* out_relres,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  if (!s || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+  if (nrhs < 1 || nrhs > 64 || n_corrections < 0 || n_corrections > 8) return SF_ERR_ARG;
+  if (ldb < s->n || ldx < s->n || (Y && ldy < s->m)) return SF_ERR_SHAPE;
+  if (s->n == 0) return SF_OK;
+  if (!L32 || !L64 || !B || !X || (Y && !A64)) return SF_ERR_ARG;
+  if (!workspace || ws_bytes < sf_refine_workspace_bytes(s, nrhs)) return SF_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sf_status r = upload(s, st);
+  if (r != SF_OK) return r;
+  const size_t nk = size_t(s->n) * size_t(nrhs);
+  auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+  char* w = static_cast<char*>(workspace);
+  float* r32 = reinterpret_cast<float*>(w);
+  float* d32 = reinterpret_cast<float*>(w + align(nk * 4));
+  double* xa = reinterpret_cast<double*>(w + 2 * align(nk * 4));
+  double* xb = reinterpret_cast<double*>(w + 2 * align(nk * 4) + align(nk * 8));
+  unsigned long long* mx = reinterpret_cast<unsigned long long*>(w + 2 * align(nk * 4) + 2 * align(nk * 8));
+  const int n = int32_t(s->n);
+  // 1. x0 = L32^{-1} b in FP32 (b rounded to FP32)
+  SF_HIP(launch_convert_f64_f32(B, ldb, r32, n, nrhs, st));
+  r = exec_ts_fused(s, SF_F32, L32, nullptr, r32, n, nrhs, d32, n, nullptr, 0, st);
+  if (r != SF_OK) return r;
+  // 2. corrections: x <- x + d, r = b - L64 x, d = L32^{-1} r
+  const double* xin = nullptr;
+  double* xout = xa;
+  for (int t = 0; t < n_corrections; ++t) {
+    ResArgs ra{};
+    ra.n = n;
+    ra.m = int32_t(s->m);
+    ra.nrhs = nrhs;
+    ra.Lrp = s->dev.Lrp;
+    ra.Lci = s->dev.Lci;
+    ra.L64 = L64;
+    ra.B = B;
+    ra.ldb = ldb;
+    ra.xin = xin;
+    ra.d = d32;
+    ra.xout = xout;
+    ra.ldxo = n;
+    ra.r32 = r32;
+    SF_HIP(launch_residual(ra, st));
+    r = exec_ts_fused(s, SF_F32, L32, nullptr, r32, n, nrhs, d32, n, nullptr, 0, st);
+    if (r != SF_OK) return r;
+    xin = xout;
+    xout = (xout == xa) ? xb : xa;
+  }
+  // 3. x_final = x + d; y = A64 x_final; r = b - L64 x_final (FP64)
+  SF_HIP(launch_fill_u64(mx, 2 * nrhs, st));
+  ResArgs fa{};
+  fa.n = n;
+  fa.m = Y ? int32_t(s->m) : 0;
+  fa.nrhs = nrhs;
+  fa.Lrp = s->dev.Lrp;
+  fa.Lci = s->dev.Lci;
+  fa.L64 = L64;
+  fa.Arp = s->dev.Arp;
+  fa.Aci = s->dev.Aci;
+  fa.A64 = A64;
+  fa.B = B;
+  fa.ldb = ldb;
+  fa.xin = xin;
+  fa.d = d32;
+  fa.xout = X;
+  fa.ldxo = ldx;
+  fa.r32 = nullptr;
+  fa.Y = Y;
+  fa.ldy = ldy;
+  fa.maxabs = mx;
+  SF_HIP(launch_final(fa, st));
+  if (out_relres) {
+    std::vector<unsigned long long> h(size_t(2 * nrhs));
+    SF_HIP(hipMemcpyAsync(h.data(), mx, h.size() * 8, hipMemcpyDeviceToHost, st));
+    SF_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < nrhs; ++c) {
+      double rm, bm;
+      std::memcpy(&rm, &h[2 * c], 8);
+      std::memcpy(&bm, &h[2 * c + 1], 8);
+      out_relres[c] = bm > 0 ? rm / bm : rm;
+    }
+  }
+  return SF_OK;
+}
+
+sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
+  if (!s || !key) return SF_ERR_ARG;
+  const std::string k(key);
+  if (k == "lanes_trsv") {
+    const int lo = s->kind == SF_IC0_TRSV ? 4 : 2;
+    if (!pow2_in(int(v), lo, s->kind == SF_IC0_TRSV ? 64 : 32)) return SF_ERR_ARG;
+    s->lanes_trsv = int32_t(v);
+  } else if (k == "lanes_spmv") {
+    if (!pow2_in(int(v), 2, 32)) return SF_ERR_ARG;
+    s->lanes_spmv = int32_t(v);
+  } else if (k == "rhs_block") {
+    if (v != 0 && !pow2_in(int(v), 2, 64)) return SF_ERR_ARG;
+    s->rhs_block = int32_t(v);
+  } else if (k == "waves_per_cu") {
+    if (v < 4 || v > 32) return SF_ERR_ARG;
+    s->waves_per_cu = int32_t(v);
+  } else if (k == "spin_limit") {
+    if (v < 1) return SF_ERR_ARG;
+    s->spin_limit = v;
+  } else if (k == "claim_streams") {
+    if (v < 1 || v > kStreams) return SF_ERR_ARG;
+    s->claim_streams = int32_t(v);
+  } else if (k == "rows_per_item" || k == "max_item_nnz") {
+    if (v < 1 || v > (int64_t(1) << 30)) return SF_ERR_ARG;
+    if (k == "rows_per_item") s->rows_per_item = int32_t(v);
+    else s->max_item_nnz = int32_t(v);
+    try {
+      sf::cut_items(s);
+    } catch (const std::bad_alloc&) {
+      return SF_ERR_OOM;
+    }
+    if (s->dev.ready) {
+      // the item arrays changed size: rebuild the constant block
+      hipDeviceSynchronize();
+      if (s->dev.block) hipFree(s->dev.block);
+      s->dev.block = nullptr;
+      s->dev.ready = false;
+    }
+  } else if (k == "no_fusion") {
+    s->no_fusion = v ? 1 : 0;
+  } else if (k == "timing") {
+    s->timing = v ? 1 : 0;
+  } else {
+    return SF_ERR_ARG;
+  }
+  return SF_OK;
+}
+
+sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
+  if (!s || !key || !v) return SF_ERR_ARG;
+  const std::string k(key);
+  if (k == "lanes_trsv") *v = s->lanes_trsv;
+  else if (k == "lanes_spmv") *v = s->lanes_spmv;
+  else if (k == "rhs_block") *v = s->rhs_block;
+  else if (k == "waves_per_cu") *v = s->waves_per_cu;
+  else if (k == "spin_limit") *v = s->spin_limit;
+  else if (k == "claim_streams") *v = s->claim_streams;
+  else if (k == "rows_per_item") *v = s->rows_per_item;
+  else if (k == "max_item_nnz") *v = s->max_item_nnz;
+  else if (k == "no_fusion") *v = s->no_fusion;
+  else if (k == "timing") *v = s->timing;
+  else return SF_ERR_ARG;
+  return SF_OK;
+}
+
+sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val, const void* B,
+                      int32_t ldb, int32_t nrhs, void* X, int32_t ldx, void* Y, int32_t ldy, void* stream,
+                      double* out_best_ms) {
+  sf_status r = check_ts_args(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy);
+  if (r != SF_OK) return r;
+  if (s->n == 0) return SF_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  SF_HIP(hipEventCreate(&e0));
+  SF_HIP(hipEventCreate(&e1));
+  const int saved_timing = s->timing;
+  s->timing = 0;
+  auto time_once = [&](double& best) -> sf_status {
+    sf_status rr = upload(s, st);
+    if (rr != SF_OK) return rr;
+    best = 1e30;
+    for (int rep = 0; rep < 4; ++rep) {
+      hipEventRecord(e0, st);
+      rr = exec_ts_fused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
+      if (rr != SF_OK) return rr;
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, double(ms));  // first run warms up
+    }
+    return SF_OK;
+  };
+  double best = 1e30;
+  r = time_once(best);
+  // coordinate search: lanes per row, rows per item, residency, RHS block
+  auto try_param = [&](const char* key, const std::vector<int64_t>& cands) -> sf_status {
+    int64_t keep = 0;
+    sf_get_param(s, key, &keep);
+    for (int64_t c : cands) {
+      if (c == keep) continue;
+      if (sf_set_param(s, key, c) != SF_OK) continue;
+      double t = 0;
+      sf_status rr = time_once(t);
+      if (rr != SF_OK) return rr;
+      if (t < best * 0.98) {
+        best = t;
+        keep = c;
+      }
+    }
+    return sf_set_param(s, key, keep);
+  };
+  if (r == SF_OK && nrhs == 1) r = try_param("lanes_trsv", {2, 4, 8, 16, 32});
+  if (r == SF_OK && nrhs == 1 && Y) r = try_param("lanes_spmv", {4, 8, 16, 32});
+  if (r == SF_OK && nrhs > 1) r = try_param("rhs_block", {8, 16, 32, 64});
+  if (r == SF_OK) r = try_param("rows_per_item", {16, 32, 64, 128, 256});
+  if (r == SF_OK) r = try_param("waves_per_cu", {4, 8, 16});
+  if (r == SF_OK) r = upload(s, st);
+  s->timing = saved_timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (out_best_ms) *out_best_ms = best;
+  return r;
+}
+
+sf_status sf_sync_status(sf_schedule s, void* stream) {
+  if (!s) return SF_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SF_HIP(hipStreamSynchronize(st));
+  if (!s->dev.state) return SF_OK;
+  int32_t v = 0;
+  SF_HIP(hipMemcpy(&v, s->dev.state + kStatusOff, sizeof(v), hipMemcpyDeviceToHost));
+  if (v != 0) {
+    const int32_t z = 0;
+    SF_HIP(hipMemcpy(s->dev.state + kStatusOff, &z, sizeof(z), hipMemcpyHostToDevice));
+    return SF_ERR_TIMEOUT;
+  }
+  return SF_OK;
+}
+
+sf_status sf_last_kernel_ms(sf_schedule s, double* ms) {
+  if (!s || !ms) return SF_ERR_ARG;
+  *ms = s->last_kernel_ms;
+  return SF_OK;
+}
+
+}  // extern "C"

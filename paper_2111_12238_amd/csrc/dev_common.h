@@ -1,0 +1,152 @@
+// Device-side building blocks of the persistent executors (gfx950).
+//
+// Readiness protocol.  A row's result (x_i, L row i, lambda_i) is stored
+// with device-coherent (agent-scope) stores, the wavefront waits for its
+// stores to complete (s_waitcnt vmcnt(0)), then stores the row's flag =
+// launch epoch, also device-coherent.  A consumer polls the flags of the rows
+// it reads with device-coherent loads and then reads the values with
+// device-coherent loads.  Device-coherent accesses are served at the point of
+// coherence shared by the 8 XCDs, so no L2 writeback (buffer_wbl2) or
+// invalidate (buffer_inv) is needed; the completion wait orders value before
+// flag.  Read-only data (patterns, matrix values, right-hand sides) uses
+// ordinary cached loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kargs.h"
+#include "schedule.h"
+
+namespace sf {
+namespace dev {
+
+template <typename T>
+__device__ __forceinline__ T ld_co(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_co(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every store this wavefront issued has completed.
+__device__ __forceinline__ void stores_complete() {
+  __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory");
+}
+// Compiler barrier: keep the value loads after the flag polls.
+__device__ __forceinline__ void after_wait() { __asm__ __volatile__("" ::: "memory"); }
+
+// Poll flag *f until it equals epoch.  Returns false if the watchdog fired
+// (spin_limit polls) or another wavefront already reported a timeout; the
+// caller then proceeds with whatever value is there so the grid drains.
+__device__ __forceinline__ bool wait_flag(const int32_t* f, const LaunchState& ls) {
+  if (ld_co(f) == ls.epoch) return true;
+  int32_t spins = 0;
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (ld_co(f) == ls.epoch) return true;
+    if (++spins >= ls.spin_limit) {
+      st_co(ls.state + kStatusOff, kStatusTimeout);
+      return false;
+    }
+    if ((spins & 255) == 0 && ld_co(ls.state + kStatusOff) != 0) return false;
+  }
+}
+
+// Clear the state fields the next launch on this schedule will use.
+__device__ __forceinline__ void reset_next_launch(const LaunchState& ls) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int np = (ls.epoch + 1) & 1;
+    for (int s = 0; s < kStreams; ++s) st_co(ls.state + ctr_off(np, s), 0);
+    st_co(ls.state + done_off(np), 0);
+    st_co(ls.state + info_off(np), kInfoNone);
+    st_co(ls.state + bar_off(np), 0);
+  }
+}
+
+// Work claiming.  Block b claims from counter b % streams; the k-th ticket of
+// counter s is global work index k * streams + s.  Each counter hands out
+// its indices in increasing order and blocks 0..streams-1 are resident from
+// the start, so the smallest claimed-but-unfinished index only waits on
+// finished work: the claim order is deadlock-free at any grid size.
+__device__ __forceinline__ int32_t claim(const LaunchState& ls, int lane) {
+  const int s = blockIdx.x % ls.streams;
+  int32_t k = 0;
+  if (lane == 0)
+    k = __hip_atomic_fetch_add(ls.state + ctr_off(ls.epoch & 1, s), 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+  k = __builtin_amdgcn_readfirstlane(k);
+  return k * ls.streams + s;
+}
+
+// Count finished wavefronts; true for the last one of the grid.
+__device__ __forceinline__ bool last_wave_done(const LaunchState& ls, int lane) {
+  int32_t old = 0;
+  if (lane == 0)
+    old = __hip_atomic_fetch_add(ls.state + done_off(ls.epoch & 1), 1, __ATOMIC_ACQ_REL,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  old = __builtin_amdgcn_readfirstlane(old);
+  const int32_t total = int32_t(gridDim.x) * int32_t(blockDim.x / 64);
+  return old == total - 1;
+}
+
+// Grid-wide barrier for cooperative (all-resident) launches whose shared
+// values are written and read with device-coherent accesses: every
+// wavefront waits for its stores to complete, the block meets, one lane
+// counts the block in and waits for the whole grid.  The counter grows by
+// gridDim.x per barrier; `gen` counts barriers passed.
+__device__ __forceinline__ void grid_barrier(const LaunchState& ls, int32_t& gen) {
+  stores_complete();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t* bar = ls.state + bar_off(ls.epoch & 1);
+    __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t target = (gen + 1) * int32_t(gridDim.x);
+    int32_t spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins >= ls.spin_limit) {  // watchdog: report and let the grid drain
+        st_co(ls.state + kStatusOff, kStatusTimeout);
+        break;
+      }
+      if ((spins & 255) == 0 && ld_co(ls.state + kStatusOff) != 0) break;
+    }
+  }
+  ++gen;
+  __syncthreads();
+  after_wait();
+}
+
+// ---- cross-lane sums over groups of G consecutive lanes (DPP inside a row
+// of 16 lanes, ds_bpermute beyond) ----
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp(T v) {
+  if constexpr (sizeof(T) == 8) return dpp_d<CTRL>(v);
+  else return dpp_f<CTRL>(v);
+}
+
+// Every lane of each aligned group of G lanes receives the group's sum.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  if constexpr (G >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  if constexpr (G >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  if constexpr (G >= 8) v += dpp<0x141>(v);  // row_half_mirror: other quad of 8
+  if constexpr (G >= 16) v += dpp<0x140>(v); // row_mirror: other half of 16
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+}  // namespace dev
+}  // namespace sf

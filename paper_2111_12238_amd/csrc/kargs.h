@@ -1,0 +1,136 @@
+// Kernel argument blocks and launcher declarations shared by the C ABI
+// (api.cpp) and the kernel translation units (*.hip).  Plain structs of
+// device pointers and sizes; every pointer is a device address.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sf {
+
+// Per-launch bookkeeping shared by every persistent kernel.
+struct LaunchState {
+  int32_t* state;     // device state block (schedule.h layout)
+  int32_t epoch;      // readiness flags hold this value once a row is final
+  int32_t spin_limit; // polls before the watchdog fires
+  int32_t streams;    // claim counters in use (1..kStreams)
+};
+
+// Fused SpTRSV -> SpMV (also SpTRSV alone when A == nullptr / Y == nullptr).
+struct TsArgs {
+  int32_t n, m;
+  const int32_t *Lrp, *Lci;
+  const void* Lv;
+  const int32_t *Arp, *Aci;
+  const void* Av;
+  const void* B;
+  int32_t ldb;
+  void* X;
+  int32_t ldx;
+  void* Y;
+  int32_t ldy;
+  int32_t nrhs, kb, nblk;  // right-hand sides, block width, number of blocks
+  void* xi;                // nblk * n * kb interleaved solution workspace (nrhs > 1)
+  const int32_t *order, *item_ptr, *item_list;
+  int32_t n_work;          // items to run (entries of item_list, or all items)
+  int32_t* flags;          // n per right-hand-side block
+  LaunchState ls;
+};
+
+// Level-set (unfused) SpTRSV: items grouped by level, one grid barrier each.
+struct LevelArgs {
+  TsArgs ts;               // patterns, values, vectors (item_list = level items)
+  const int32_t* lvl_item_ptr;
+  int32_t depth;
+};
+
+// Standalone CSR SpMV: Y = A X (column-major blocks).
+struct SpmvArgs {
+  int32_t m, nrhs;
+  const int32_t *Arp, *Aci;
+  const void* Av;
+  const void* X;
+  int32_t ldx;
+  void* Y;
+  int32_t ldy;
+};
+
+// Fused SpIC0 -> SpTRSV (FP64).
+struct Ic0Args {
+  int32_t n;
+  const int32_t *Lrp, *Lci;
+  const double* Aval;      // lower(A) values in the pattern of L
+  double* Lval;            // output factor
+  const double* B;
+  double* X;
+  const int32_t *pair_ptr, *pair_u, *pair_q;
+  const int32_t *order, *item_ptr, *item_list;
+  int32_t n_work;
+  const int32_t* lvl_item_ptr;  // level-set variant
+  int32_t depth;
+  int32_t solve;           // 1: also solve L x = b in the same item
+  int32_t factor;          // 1: compute the factor (0: solve with a given factor)
+  int32_t* flags;
+  int32_t* d_info;         // written by the last wave (may be nullptr)
+  LaunchState ls;
+};
+
+// Backward: upper solve with L^T fused with c = A^T g and grad_L.
+struct BwdArgs {
+  int32_t n;
+  const int32_t *LTrp, *LTci, *LTmap;
+  const int32_t *ATrp, *ATci, *ATmap;
+  const int32_t *Lrp, *Lci;
+  const void *Lv, *Av, *X, *G;
+  void *lam, *gradL;
+  const int32_t *order, *item_ptr;
+  int32_t n_work;
+  int32_t* flags;
+  LaunchState ls;
+};
+
+// Refinement passes (FP64 residual, final product).
+struct ResArgs {
+  int32_t n, m, nrhs;
+  const int32_t *Lrp, *Lci;
+  const double* L64;
+  const int32_t *Arp, *Aci;
+  const double* A64;
+  const double* B;
+  int32_t ldb;
+  const double* xin;   // n x nrhs (ld n) current iterate, nullptr = 0
+  const float* d;      // n x nrhs (ld n) correction to add, nullptr = none
+  double* xout;        // n x nrhs updated iterate (ld = ldxo)
+  int32_t ldxo;
+  float* r32;          // n x nrhs residual (ld n), nullptr = not needed
+  double* Y;           // final product (ld ldy), nullptr = none
+  int32_t ldy;
+  unsigned long long* maxabs;  // 2 * nrhs: max |r| and max |b| bit patterns
+};
+
+// Launchers (return the HIP error of the launch).
+hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid, hipStream_t st);
+hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
+hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st);
+hipError_t launch_spmv(const SpmvArgs& a, int dtype, int gs, hipStream_t st);
+hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);
+hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st);
+hipError_t launch_bwd(const BwdArgs& a, int dtype, int g, int grid, hipStream_t st);
+hipError_t launch_residual(const ResArgs& a, hipStream_t st);
+hipError_t launch_final(const ResArgs& a, hipStream_t st);
+hipError_t launch_convert_f64_f32(const double* src, int32_t lds, float* dst, int32_t n,
+                                  int32_t nrhs, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int32_t count, hipStream_t st);
+
+
+// Occupancy queries per kernel family (blocks per CU).
+int occupancy_ts_fused(int dtype, int gt, int gs);
+int occupancy_ts_multi(int dtype, int kb);
+int occupancy_trsv_levelset(int dtype, int gt);
+int occupancy_ic0(int g, int levelset);
+int occupancy_bwd(int dtype, int g);
+
+constexpr int kBlockThreads = 256;  // 4 wavefronts of 64 lanes
+
+}  // namespace sf

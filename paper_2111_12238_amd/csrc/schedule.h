@@ -1,0 +1,119 @@
+// Internal definitions shared by the host inspector, the C ABI and the
+// kernel launchers.  Not part of the public interface (include/sf.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sf.h"
+
+namespace sf {
+
+// A CSR pattern owned by the schedule (host copy).
+struct Pattern {
+  int32_t nrows = 0, ncols = 0;
+  std::vector<int32_t> rp, ci;
+  int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Layout of the small per-schedule device state block (int32 words).  Each
+// field sits on its own 256-byte line.  Fields indexed by parity p = epoch & 1
+// belong to the launch with that epoch parity; every launch clears the fields
+// of the other parity for the launch that follows it on the stream.
+constexpr int kLine = 64;                 // int32 words per 256-byte line
+constexpr int kStreams = 8;               // claim counters per parity
+inline constexpr int ctr_off(int p, int s) { return (p * kStreams + s) * kLine; }
+inline constexpr int done_off(int p) { return (2 * kStreams + p) * kLine; }
+inline constexpr int info_off(int p) { return (2 * kStreams + 2 + p) * kLine; }
+inline constexpr int bar_off(int p) { return (2 * kStreams + 4 + p) * kLine; }
+constexpr int kStatusOff = (2 * kStreams + 6) * kLine;
+constexpr int kStateWords = (2 * kStreams + 8) * kLine;
+constexpr int kInfoNone = 0x7f7f7f7f;     // "no failing row" (byte-fill value of the block)
+constexpr int kStatusTimeout = 1;
+
+struct DeviceBuffers {
+  int device = -1;
+  bool ready = false;
+  void* block = nullptr;    // single allocation holding every array below
+  size_t block_bytes = 0;
+  // patterns
+  int32_t *Lrp = nullptr, *Lci = nullptr, *Arp = nullptr, *Aci = nullptr;
+  // forward schedule
+  int32_t *order = nullptr, *item_ptr = nullptr, *trsv_items = nullptr;
+  int32_t *lvl_items = nullptr;     // item list of the level-set baseline
+  int32_t *lvl_item_ptr = nullptr;  // per level, into lvl_items
+  // backward
+  int32_t *LTrp = nullptr, *LTci = nullptr, *LTmap = nullptr;
+  int32_t *ATrp = nullptr, *ATci = nullptr, *ATmap = nullptr;
+  int32_t *border = nullptr, *bitem_ptr = nullptr;
+  // SpIC0 intersection lists
+  int32_t *pair_ptr = nullptr, *pair_u = nullptr, *pair_q = nullptr;
+  // mutable state
+  int32_t* state = nullptr;
+  int32_t* flags = nullptr;     // n * flag_blocks words
+  int64_t flag_blocks = 0;
+  void* xi = nullptr;           // interleaved right-hand-side workspace
+  size_t xi_bytes = 0;
+  uint32_t epoch = 0;
+};
+
+}  // namespace sf
+
+struct sf_schedule_s {
+  int kind = SF_TRSV_SPMV;
+  sf::Pattern L, A;
+  int64_t n = 0, m = 0;
+
+  // Forward analysis.
+  std::vector<int32_t> level;        // n: wavefront of each SpTRSV row
+  std::vector<int32_t> ready;        // m: joint wavefront of each SpMV row
+  int32_t depth = 0, joint_depth = 0, max_level_width = 0;
+  int32_t max_offdiag = 0;           // longest row of L, diagonal excluded
+
+  // Fused forward schedule: iteration ids in claim order cut into items.
+  // SF_TRSV_SPMV: id i < n is SpTRSV row i, id n + r is SpMV row r.
+  // SF_IC0_TRSV: ids are rows; row i's item runs SpIC0 row i then SpTRSV row i.
+  std::vector<int32_t> order, item_ptr;
+  std::vector<int32_t> trsv_items;   // items holding SpTRSV rows, in claim order
+  // Level-set baseline: items of SpTRSV rows grouped by level.
+  std::vector<int32_t> lvl_items, lvl_item_ptr;
+
+  // Backward (transposed solve) schedule.
+  bool has_back = false;
+  sf::Pattern LT, AT;                // CSR of L^T and A^T
+  std::vector<int32_t> LT_map, AT_map;  // entry of the transpose -> entry of the source
+  std::vector<int32_t> rlevel, border, bitem_ptr;
+  int32_t back_depth = 0;
+
+  // SpIC0 intersection lists, one list per stored L entry (i, j), j < i:
+  // pairs (u, q): u = index inside row i of a column k in both rows with
+  // k < j, q = position of L_jk.
+  std::vector<int32_t> pair_ptr, pair_u, pair_q;
+
+  // Executor parameters.
+  int32_t lanes_trsv = 4, lanes_spmv = 8, rhs_block = 0, waves_per_cu = 8;
+  int32_t rows_per_item = 64, max_item_nnz = 4096;
+  int64_t spin_limit = int64_t(1) << 22;
+  int32_t claim_streams = 1;
+  int32_t no_fusion = 0;
+  int32_t timing = 0;
+  double last_kernel_ms = -1.0;
+  double reuse = 0.0, inspect_seconds = 0.0;
+
+  sf::DeviceBuffers dev;
+};
+
+namespace sf {
+
+// Host inspector entry points (inspect.cpp).
+sf_status check_lower(const sf_csr_pattern* L);
+sf_status check_general(const sf_csr_pattern* A, int32_t ncols);
+sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* L, const sf_csr_pattern* A,
+                         const sf_inspect_opts& o);
+// Re-cut the work items after a change of rows_per_item / max_item_nnz.
+void cut_items(sf_schedule_s* s);
+// Check every DAG edge of the built forward schedule (0 = valid).
+int validate_forward(const sf_schedule_s* s);
+
+}  // namespace sf

@@ -1,0 +1,228 @@
+"""GPU parity of the fused SpTRSV -> SpMV executor (and its unfused
+baseline) against the oracle.  FP64 tolerance: 1e-12 normwise relative;
+integer manufactured solutions must match bit for bit."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2111_12238_amd as sfm
+import synth
+from gpu_util import announce, dev, dev_colmajor, host, relerr
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def run(s, L, A, b, dtype="f64", unfused=False, k=None):
+    import torch
+    td = torch.float64 if dtype == "f64" else torch.float32
+    Lv, Av = dev(L.val, td), dev(A.val, td)
+    B = dev(b, td) if b.ndim == 1 else dev_colmajor(b, td)
+    X, Y = sfm.trsv_spmv(s, Lv, Av, B, unfused=unfused)
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    return host(X), host(Y)
+
+
+def oracle_ts(orc, L, A, b):
+    if b.ndim == 1:
+        x = orc.trsv_lower(L.rowptr, L.col, L.val, b)
+        return x, orc.spmv(A.rowptr, A.col, A.val, x)
+    xs, ys = [], []
+    for c in range(b.shape[1]):
+        x, y = oracle_ts(orc, L, A, b[:, c])
+        xs.append(x)
+        ys.append(y)
+    return np.stack(xs, 1), np.stack(ys, 1)
+
+
+def test_s1_lap2d5_64_fp64(orc):
+    announce("ts fused lap2d5_64 fp64")
+    L, A = synth.workload("lap2d5_64")
+    b = synth.vec_uniform(L.nrows, seed=1)
+    s = sfm.Schedule(L, A)
+    x, y = run(s, L, A, b)
+    xr, yr = oracle_ts(orc, L, A, b)
+    assert relerr(x, xr) <= TOL64 and relerr(y, yr) <= TOL64
+
+
+def test_integer_manufactured_solution_bit_exact():
+    """Integer L, A and x_true: every partial sum is an exact integer and the
+    divisions are exact, so the GPU result must equal x_true and A x_true in
+    any summation order."""
+    announce("ts fused integer manufactured lap2d5_64 + random int")
+    L, A = synth.workload("lap2d5_64")
+    xt = synth.int_vector(L.nrows, seed=7)
+    b = L.to_scipy() @ xt
+    s = sfm.Schedule(L, A)
+    x, y = run(s, L, A, b)
+    assert np.array_equal(x, xt)
+    assert np.array_equal(y, A.to_scipy() @ xt)
+    Li = synth.random_lower(3001, 0.003, seed=4, int_values=True)
+    Ai = synth.from_scipy(sp.random(1500, 3001, density=0.004, random_state=np.random.default_rng(1),
+                                    format="csr", data_rvs=lambda k: np.random.default_rng(2).integers(-3, 4, k)))
+    xt = synth.int_vector(3001, seed=8)
+    b = Li.to_scipy() @ xt
+    for lanes in (2, 4, 8, 16, 32):
+        s = sfm.Schedule(Li, Ai, lanes_per_row=lanes, rows_per_item=37)
+        x, y = run(s, Li, Ai, b)
+        assert np.array_equal(x, xt), lanes
+        assert np.array_equal(y, Ai.to_scipy() @ xt), lanes
+
+
+@pytest.mark.parametrize("seed,n,m,rows,gt,gs", [
+    (0, 1000, 1000, 64, 4, 8), (1, 2049, 777, 13, 8, 4), (2, 4097, 5000, 1, 2, 32),
+    (3, 10007, 333, 200, 16, 16), (4, 65, 1, 64, 32, 4)])
+def test_random_ragged(orc, seed, n, m, rows, gt, gs):
+    announce("ts fused random n=%d m=%d rows=%d gt=%d gs=%d" % (n, m, rows, gt, gs))
+    L = synth.random_lower(n, min(0.5, 6.0 / n), seed=seed)
+    rng = np.random.default_rng(seed)
+    a = sp.random(m, n, density=min(1.0, 9.0 / n), random_state=rng, format="csr")
+    a = sp.csr_matrix(a.toarray() * (np.arange(m) % 7 != 3)[:, None])  # some empty rows
+    A = synth.from_scipy(a)
+    b = synth.vec_uniform(n, seed=seed + 1)
+    s = sfm.Schedule(L, A, rows_per_item=rows)
+    s.set_param("lanes_trsv", gt)
+    s.set_param("lanes_spmv", gs)
+    x, y = run(s, L, A, b)
+    xr, yr = oracle_ts(orc, L, A, b)
+    assert relerr(x, xr) <= TOL64
+    assert relerr(y, yr) <= TOL64
+    xu, yu = run(s, L, A, b, unfused=True)
+    assert relerr(xu, xr) <= TOL64 and relerr(yu, yr) <= TOL64
+
+
+def test_fp32_within_rounding_bound(orc):
+    """FP32 values, vectors and accumulation: the computed x satisfies the
+    componentwise backward-error bound of substitution in FP32,
+    |b - L x| <= gamma_m |L| |x| (u = 2^-24), with L and b rounded to FP32."""
+    announce("ts fused fp32 random spd 20000")
+    a = synth.random_spd(20000, seed=3)
+    L = synth.lower(a)
+    b = synth.vec_uniform(a.nrows, seed=1)
+    s = sfm.Schedule(L, a)
+    x, y = run(s, L, a, b, dtype="f32")
+    L32 = L.to_scipy().astype(np.float32).astype(np.float64)
+    b32 = b.astype(np.float32).astype(np.float64)
+    m = int(np.diff(L.rowptr).max())
+    u = 2.0 ** -24
+    gam = m * u / (1 - m * u)
+    r = np.abs(b32 - L32 @ x)
+    assert np.all(r <= 2 * gam * (abs(L32) @ np.abs(x)) + 1e-30)
+    xr, yr = oracle_ts(orc, L, a, b)
+    print("fp32 relative error vs FP64 oracle: x %.2e y %.2e" % (relerr(x, xr), relerr(y, yr)))
+    assert relerr(x, xr) < 1e-4
+
+
+@pytest.mark.parametrize("k,kb", [(2, 0), (3, 2), (8, 8), (13, 8), (13, 16), (64, 64), (64, 16), (33, 32)])
+def test_multi_rhs(orc, k, kb):
+    announce("ts fused multi-rhs k=%d kb=%d" % (k, kb))
+    L, A = synth.workload("lap2d5_64")
+    b = synth.vec_uniform(L.nrows, k=k, seed=1)
+    s = sfm.Schedule(L, A, rhs_block=kb)
+    x, y = run(s, L, A, b)
+    xr, yr = oracle_ts(orc, L, A, b)
+    assert relerr(x, xr) <= TOL64 and relerr(y, yr) <= TOL64
+    xu, yu = run(s, L, A, b, unfused=True)
+    assert relerr(xu, xr) <= TOL64 and relerr(yu, yr) <= TOL64
+
+
+def test_multi_rhs_integer_bit_exact():
+    announce("ts fused multi-rhs integer")
+    L, A = synth.workload("lap2d5_64")
+    xt = np.stack([synth.int_vector(L.nrows, seed=s) for s in range(12)], 1)
+    b = L.to_scipy() @ xt
+    for kb in (4, 8, 16):
+        s = sfm.Schedule(L, A, rhs_block=kb)
+        x, y = run(s, L, A, b)
+        assert np.array_equal(x, xt) and np.array_equal(y, A.to_scipy() @ xt)
+
+
+def test_repeated_launches_and_modes(orc):
+    """Epoch-tagged flags: many launches of one schedule (fused, unfused,
+    solve only, multi-RHS) interleaved, each result exact."""
+    announce("ts repeated launches")
+    import torch
+    L, A = synth.workload("lap2d5_64")
+    xt = synth.int_vector(L.nrows, seed=3)
+    b = L.to_scipy() @ xt
+    yt = A.to_scipy() @ xt
+    s = sfm.Schedule(L, A)
+    Lv, Av, B = dev(L.val), dev(A.val), dev(b)
+    for it in range(12):
+        if it % 3 == 0:
+            X, Y = sfm.trsv_spmv(s, Lv, Av, B)
+        elif it % 3 == 1:
+            X, Y = sfm.trsv_spmv(s, Lv, Av, B, unfused=True)
+        else:
+            X, Y = sfm.trsv_spmv(s, Lv, Av, B, want_y=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(X), xt), it
+        if Y is not None:
+            assert np.array_equal(host(Y), yt), it
+    Bk = dev_colmajor(np.stack([b, 2 * b, -b], 1))
+    X, Y = sfm.trsv_spmv(s, Lv, Av, Bk)
+    assert np.array_equal(host(X), np.stack([xt, 2 * xt, -xt], 1))
+    sfm.sync_status(s)
+
+
+def test_degenerate(orc):
+    announce("ts degenerate n=1 and diagonal")
+    L = synth.from_scipy(sp.csr_matrix(np.array([[2.0]])))
+    A = synth.from_scipy(sp.csr_matrix(np.array([[3.0], [0.0]])))
+    s = sfm.Schedule(L, A)
+    x, y = run(s, L, A, np.array([5.0]))
+    assert x.tolist() == [2.5] and y.tolist() == [7.5, 0.0]
+    d = synth.from_scipy(sp.diags(np.arange(1.0, 301.0), format="csr"))
+    s = sfm.Schedule(d, d)
+    b = synth.vec_uniform(300, seed=2)
+    x, y = run(s, d, d, b)
+    assert np.array_equal(x, b / np.arange(1.0, 301.0))
+
+
+def test_watchdog_reports_timeout_and_recovers(orc):
+    """A spin limit of one poll makes waits on not-yet-final rows give up:
+    the launch drains, SF_ERR_TIMEOUT is reported, and the next launch with
+    the default limit is exact again."""
+    announce("ts watchdog (forced from host)")
+    L, A = synth.workload("lap2d5_64")
+    xt = synth.int_vector(L.nrows, seed=3)
+    b = L.to_scipy() @ xt
+    s = sfm.Schedule(L, A)
+    default = s.get_param("spin_limit")
+    s.set_param("spin_limit", 1)
+    s.set_param("rows_per_item", 1)
+    import torch
+    Lv, Av, B = dev(L.val), dev(A.val), dev(b)
+    hit = False
+    for _ in range(5):
+        sfm.trsv_spmv(s, Lv, Av, B)
+        try:
+            sfm.sync_status(s)
+        except sfm.SparseFusionError as e:
+            assert e.name == "SF_ERR_TIMEOUT"
+            hit = True
+            break
+    assert hit, "a one-poll watchdog never fired on a 127-level DAG"
+    s.set_param("spin_limit", default)
+    X, Y = sfm.trsv_spmv(s, Lv, Av, B)
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    assert np.array_equal(host(X), xt)
+
+
+@pytest.mark.parametrize("name", ["lap3d7_128", "randspd_1m"])
+def test_full_size_configs(orc, name):
+    """The benchmark's workloads at full size, whole vectors against the oracle."""
+    announce("ts fused full size " + name)
+    L, A = synth.workload(name)
+    b = synth.vec_uniform(L.nrows, seed=1)
+    s = sfm.Schedule(L, A)
+    x, y = run(s, L, A, b)
+    xr, yr = oracle_ts(orc, L, A, b)
+    ex, ey = relerr(x, xr), relerr(y, yr)
+    print("%s fused: x err %.2e  y err %.2e" % (name, ex, ey))
+    assert ex <= TOL64 and ey <= TOL64
+    xu, yu = run(s, L, A, b, unfused=True)
+    assert relerr(xu, xr) <= TOL64 and relerr(yu, yr) <= TOL64

@@ -1,0 +1,171 @@
+"""Host inspector (sf_inspect) against the oracle: levels, joint order,
+items, reversed levels and structural errors.  Host only, no GPU."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2111_12238_amd as sfm
+import synth
+
+CASES = ["lap2d5_16", "lap2d5_64"]
+
+
+def _random_pair(n, seed, m=None, empty_rows=False):
+    L = synth.random_lower(n, 0.01 if n > 500 else 0.1, seed=seed)
+    m = n if m is None else m
+    rng = np.random.default_rng(seed + 100)
+    a = sp.random(m, n, density=min(1.0, 8.0 / n), random_state=rng, format="csr")
+    if empty_rows:
+        a = sp.csr_matrix(a.toarray() * (np.arange(m) % 5 != 0)[:, None])
+    return L, synth.from_scipy(a)
+
+
+def _check_schedule(orc, L, A, s):
+    level, order, item_ptr = s.export()
+    lv, depth = orc.levels(L.rowptr, L.col)
+    assert np.array_equal(level, lv), "levels differ from the oracle"
+    st = s.info()
+    assert st.depth == depth
+    ready = orc.spmv_ready(A.rowptr, A.col, lv)
+    want = orc.joint_order_ts(lv, ready)
+    assert np.array_equal(order, want), "claim order differs from the canonical joint order"
+    assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, item_ptr) == 0
+    assert st.joint_depth == max(depth, int(ready.max()) + 1 if len(ready) else 0)
+    widths = np.bincount(lv)
+    assert st.max_level_width == widths.max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_stencil_schedules(orc, name):
+    L, A = synth.workload(name)
+    s = sfm.Schedule(L, A, validate=True)
+    _check_schedule(orc, L, A, s)
+    assert abs(s.info().reuse_ratio - orc.reuse_ts(L.nrows, L.nnz, A.nrows, A.nnz)) < 1e-15
+
+
+@pytest.mark.parametrize("seed,n,m,empty", [(0, 60, None, False), (1, 1000, None, True), (2, 777, 300, True),
+                                              (3, 500, 900, False)])
+def test_random_schedules(orc, seed, n, m, empty):
+    L, A = _random_pair(n, seed, m, empty)
+    for rows in (1, 7, 64):
+        s = sfm.Schedule(L, A, rows_per_item=rows, max_item_nnz=50, validate=True)
+        _check_schedule(orc, L, A, s)
+        _, _, ip = s.export()
+        sizes = np.diff(ip)
+        assert sizes.max() <= rows
+
+
+def test_item_nnz_budget():
+    L, A = synth.workload("lap2d5_64")
+    s = sfm.Schedule(L, A, rows_per_item=1000, max_item_nnz=40)
+    level, order, ip = s.export()
+    n = L.nrows
+    cost = np.concatenate([np.diff(L.rowptr), np.maximum(1, np.diff(A.rowptr))])
+    for t in range(len(ip) - 1):
+        ids = order[ip[t]:ip[t + 1]]
+        assert len(ids) == 1 or cost[ids].sum() <= 40
+        kinds = ids >= n
+        assert kinds.all() or not kinds.any(), "an item mixes SpTRSV and SpMV rows"
+
+
+def test_backward_schedule(orc):
+    L, A = synth.workload("lap2d5_16")
+    s = sfm.Schedule(L, A, want_backward=True)
+    rl, order, ip = s.export_backward()
+    want, depth = orc.reverse_levels(L.rowptr, L.col)
+    assert np.array_equal(rl, want)
+    assert s.info().back_depth == depth
+    # rows sorted by (reversed level, row); items hold one reversed level
+    assert np.array_equal(order, np.lexsort((np.arange(L.nrows), want)))
+    for t in range(len(ip) - 1):
+        assert len(set(rl[order[ip[t]:ip[t + 1]]])) == 1
+    # every edge of the transposed solve (lambda_j -> lambda_i for L_ji, j > i)
+    # points from an earlier item to a later one
+    item = np.empty(L.nrows, int)
+    for t in range(len(ip) - 1):
+        item[order[ip[t]:ip[t + 1]]] = t
+    rows = np.repeat(np.arange(L.nrows), np.diff(L.rowptr))
+    off = L.col < rows
+    assert np.all(item[rows[off]] < item[L.col[off]])
+
+
+def test_ic0_schedule(orc):
+    a = synth.laplacian_3d27(6, 5, 4, 26.1)
+    L = synth.lower(a)
+    s = sfm.Schedule(L, None, sfm.SF_IC0_TRSV, validate=True)
+    level, order, ip = s.export()
+    lv, depth = orc.levels(L.rowptr, L.col)
+    assert np.array_equal(level, lv)
+    n = L.nrows
+    assert sorted(order.tolist()) == list(range(2 * n))
+    # each row's SpIC0 iteration directly precedes its SpTRSV iteration, in one item
+    assert np.array_equal(order[1::2], order[0::2] + n)
+    item = np.empty(2 * n, int)
+    for t in range(len(ip) - 1):
+        assert (ip[t + 1] - ip[t]) % 2 == 0
+        item[order[ip[t]:ip[t + 1]]] = t
+    rows = np.repeat(np.arange(n), np.diff(L.rowptr))
+    off = L.col < rows
+    assert np.all(item[L.col[off]] < item[rows[off]])            # SpIC0 j -> SpIC0 i
+    assert np.all(item[n + L.col[off]] < item[n + rows[off]])    # SpTRSV j -> SpTRSV i
+    assert abs(s.info().reuse_ratio - orc.reuse_it(n, L.nnz)) < 1e-15
+    assert s.info().reuse_ratio >= 1.0
+
+
+def _err(fn):
+    with pytest.raises(sfm.SparseFusionError) as e:
+        fn()
+    return e.value.name
+
+
+def test_structural_errors():
+    L, A = synth.workload("lap2d5_16")
+    bad = L.col.copy()
+    bad[[1, 2]] = bad[[2, 1]]  # row 1 unsorted (two entries)
+    assert _err(lambda: sfm.Schedule((L.rowptr, bad, L.ncols), A)) == "SF_ERR_CSR"
+    dup = L.col.copy()
+    dup[2] = dup[1]
+    assert _err(lambda: sfm.Schedule((L.rowptr, dup, L.ncols), A)) == "SF_ERR_CSR"
+    oor = L.col.copy()
+    oor[0] = L.ncols
+    assert _err(lambda: sfm.Schedule((L.rowptr, oor, L.ncols), A)) == "SF_ERR_CSR"
+    # A itself (has upper entries) given as L
+    assert _err(lambda: sfm.Schedule(A, A)) == "SF_ERR_NOT_LOWER"
+    # strictly lower part only: no diagonal
+    sl = synth.from_scipy(sp.tril(L.to_scipy(), k=-1) + sp.csr_matrix((L.nrows, L.nrows)))
+    nodiag_rp = np.concatenate([[0], np.cumsum(np.diff(sl.rowptr))]).astype(np.int32)
+    assert _err(lambda: sfm.Schedule((nodiag_rp, sl.col, L.ncols), A)) == "SF_ERR_ZERO_DIAG"
+    # A with the wrong number of columns
+    assert _err(lambda: sfm.Schedule(L, (A.rowptr, A.col, A.ncols + 1))) == "SF_ERR_SHAPE"
+    # decreasing row pointer
+    rp = L.rowptr.copy()
+    rp[5] = rp[6] + 1
+    assert _err(lambda: sfm.Schedule((rp, L.col, L.ncols), A)) == "SF_ERR_CSR"
+    # SpTRSV -> SpMV needs A
+    assert _err(lambda: sfm.Schedule(L, None)) == "SF_ERR_ARG"
+
+
+def test_degenerate_sizes(orc):
+    # n = 0
+    s = sfm.Schedule((np.zeros(1, np.int32), np.zeros(0, np.int32), 0), (np.zeros(1, np.int32), np.zeros(0, np.int32), 0))
+    st = s.info()
+    assert st.n == 0 and st.n_items == 0 and st.depth == 0
+    # n = 1, A with one empty row and one full row
+    L = (np.array([0, 1], np.int32), np.array([0], np.int32), 1)
+    A = (np.array([0, 0, 1], np.int32), np.array([0], np.int32), 1)
+    s = sfm.Schedule(L, A, validate=True)
+    level, order, ip = s.export()
+    assert level.tolist() == [0]
+    # empty SpMV row 0 has joint level 0 (after SpTRSV row 0 in the order), row 1 level 1
+    assert order.tolist() == [0, 1, 2]
+    assert s.info().joint_depth == 2
+    # a diagonal L has one level
+    d = synth.from_scipy(sp.identity(50, format="csr"))
+    s = sfm.Schedule(d, d)
+    assert s.info().depth == 1 and s.info().joint_depth == 2
+
+
+def test_inspector_time_reported():
+    L, A = synth.workload("lap2d5_64")
+    s = sfm.Schedule(L, A, want_backward=True)
+    assert 0.0 < s.info().inspect_seconds < 5.0
