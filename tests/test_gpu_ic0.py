@@ -61,17 +61,28 @@ def test_tridiagonal_closed_form():
     assert np.abs(ld.diagonal(-1) + np.sqrt(i[:-1] / i[1:])).max() <= 64 * 2.0 ** -53
 
 
-@pytest.mark.parametrize("lanes", [16, 32, 64])
-def test_random_spd_patterns(orc, lanes):
+@pytest.mark.parametrize("lanes,lo,hi", [(16, 1, 3), (32, 2, 6), (64, 2, 6)])
+def test_random_spd_patterns(orc, lanes, lo, hi):
     announce("ic0 fused random spd lanes=%d" % lanes)
-    a = synth.random_spd(5000, seed=9, lo=2, hi=6)
+    a = synth.random_spd(5000, seed=9, lo=lo, hi=hi)
     Lp = synth.lower(a)
+    assert np.diff(Lp.rowptr).max() - 1 <= lanes  # one lane per stored entry of a row
     b = synth.vec_normal(a.nrows, seed=2)
     s = sfm.Schedule(Lp, None, sfm.SF_IC0_TRSV, lanes_per_row=lanes, rows_per_item=17)
     l, x, info = run_ic0(s, Lp, b)
     lr, xr, fail = oracle_it(orc, Lp, b)
     assert info == fail == -1
     assert relerr(l, lr) <= TOL64 and relerr(x, xr) <= TOL64
+
+
+def test_rows_longer_than_lanes_rejected():
+    announce("ic0 long rows rejected (host check)")
+    a = synth.random_spd(5000, seed=9, lo=2, hi=6)
+    Lp = synth.lower(a)
+    s = sfm.Schedule(Lp, None, sfm.SF_IC0_TRSV, lanes_per_row=16)
+    with pytest.raises(sfm.SparseFusionError) as e:
+        run_ic0(s, Lp, np.ones(a.nrows))
+    assert e.value.name == "SF_ERR_UNSUPPORTED"
 
 
 def test_breakdown_reports_first_row(orc):
