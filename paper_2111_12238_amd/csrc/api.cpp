@@ -700,7 +700,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     if (!pow2_in(int(v), lo, s->kind == SF_IC0_TRSV ? 64 : 32)) return SF_ERR_ARG;
     s->lanes_trsv = int32_t(v);
   } else if (k == "lanes_spmv") {
-    if (!pow2_in(int(v), 2, 32)) return SF_ERR_ARG;
+    if (!pow2_in(int(v), 4, 32)) return SF_ERR_ARG;
     s->lanes_spmv = int32_t(v);
   } else if (k == "rhs_block") {
     if (v != 0 && !pow2_in(int(v), 2, 64)) return SF_ERR_ARG;

@@ -288,7 +288,7 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
   const double mean_l = n ? double(s->L.nnz() - n) / double(n) : 1.0;
   const double mean_a = m ? double(s->A.nnz()) / double(m) : 1.0;
   s->lanes_trsv = o.lanes_per_row > 0 ? o.lanes_per_row : pick(mean_l);
-  s->lanes_spmv = pick(mean_a);
+  s->lanes_spmv = std::max(4, pick(mean_a));  // SpMV kernels exist for 4..32 lanes
   if (s->kind == SF_IC0_TRSV) {
     // one lane per stored entry of an SpIC0 row
     int32_t maxlen = 1;
