@@ -259,7 +259,14 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "lanes_trsv", "lanes_spmv"  lanes per row (1..64, power of two);
  *   "rhs_block"                 right-hand sides per DAG pass (1..64);
  *   "waves_per_cu"              persistent-grid residency target (1..32);
- *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT.
+ *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT;
+ *   "claim_streams"             work-claim counters (1..32);
+ *   "rows_per_item", "max_item_nnz"  re-cut the work items (rows <= 64);
+ *   "spmv_delay"                place each SpMV row this many wavefronts after
+ *                               the one where its inputs are final (0 = the
+ *                               canonical joint order; any value keeps the
+ *                               order topological);
+ *   "no_fusion", "timing", "trace"   switches (0/1).
  */
 sf_status sf_set_param(sf_schedule s, const char* key, int64_t value);
 sf_status sf_get_param(sf_schedule s, const char* key, int64_t* value);
@@ -277,6 +284,14 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
 /* Synchronise the stream and report a watchdog timeout of an earlier
  * execution on this schedule (SF_ERR_TIMEOUT), clearing it; SF_OK else. */
 sf_status sf_sync_status(sf_schedule s, void* stream);
+
+/* Trace mode (sf_set_param(s, "trace", 1)): the fused single-RHS
+ * SpTRSV -> SpMV executor records, per work item t, four timestamps of the
+ * device's 100 MHz real-time counter in out[4t .. 4t+3]: processing start,
+ * indices and values loaded, every x read ready, end.  out holds at least
+ * 4 * n_items values (host); the call synchronises the device.  A debugging
+ * and tuning aid: tracing adds stores to every item. */
+sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count);
 
 /* Time of the last kernel launched by an executor call, measured with HIP
  * events on the executor's stream when enabled with

@@ -87,6 +87,7 @@ _SIGS = {
     "sf_autotune": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P, ctypes.POINTER(ctypes.c_double)],
     "sf_sync_status": [_P, _P],
     "sf_last_kernel_ms": [_P, ctypes.POINTER(ctypes.c_double)],
+    "sf_trace_export": [_P, _P, ctypes.c_int64],
 }
 
 
@@ -206,6 +207,14 @@ class Schedule:
         v = ctypes.c_double()
         _check(_lib().sf_last_kernel_ms(self.handle, ctypes.byref(v)), "sf_last_kernel_ms")
         return float(v.value)
+
+    def trace(self):
+        """Per-item timestamps (n_items, 4) of the last traced fused launch, in
+        100 MHz real-time-counter ticks (needs set_param("trace", 1))."""
+        n_items = int(self.info().n_items)
+        out = np.zeros(4 * max(n_items, 1), np.uint64)
+        _check(_lib().sf_trace_export(self.handle, out.ctypes.data, out.size), "sf_trace_export")
+        return out[:4 * n_items].reshape(n_items, 4)
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:

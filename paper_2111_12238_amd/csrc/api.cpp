@@ -80,6 +80,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oLrp = pk.add(&s->L.rp), oLci = pk.add(&s->L.ci);
   const size_t oArp = pk.add(&s->A.rp), oAci = pk.add(&s->A.ci);
   const size_t oOrd = pk.add(&s->order), oIp = pk.add(&s->item_ptr), oTi = pk.add(&s->trsv_items);
+  const size_t oSi = pk.add(&s->spmv_items);
   const size_t oLi = pk.add(&s->lvl_items), oLip = pk.add(&s->lvl_item_ptr);
   const size_t oLTrp = pk.add(&s->LT.rp), oLTci = pk.add(&s->LT.ci), oLTm = pk.add(&s->LT_map);
   const size_t oATrp = pk.add(&s->AT.rp), oATci = pk.add(&s->AT.ci), oATm = pk.add(&s->AT_map);
@@ -99,7 +100,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.block = block;
   d.block_bytes = pk.off;
   d.Lrp = P(oLrp); d.Lci = P(oLci); d.Arp = P(oArp); d.Aci = P(oAci);
-  d.order = P(oOrd); d.item_ptr = P(oIp); d.trsv_items = P(oTi);
+  d.order = P(oOrd); d.item_ptr = P(oIp); d.trsv_items = P(oTi); d.spmv_items = P(oSi);
   d.lvl_items = P(oLi); d.lvl_item_ptr = P(oLip);
   d.LTrp = P(oLTrp); d.LTci = P(oLTci); d.LTmap = P(oLTm);
   d.ATrp = P(oATrp); d.ATci = P(oATci); d.ATmap = P(oATm);
@@ -237,30 +238,32 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   const size_t es = dt == SF_F64 ? 8 : 4;
   TsArgs a = ts_args(s, Lv, Av, B, ldb, nrhs, X, ldx, Y, ldy);
   if (a.n_work == 0) return SF_OK;
+  // x doubles as its own readiness flag: it is filled with the pending
+  // pattern first (part of the timed execution).
   if (nrhs == 1) {
     sf_status r = next_epoch(s, st, a.ls);
     if (r != SF_OK) return r;
-    a.flags = s->dev.flags;
     a.kb = 1;
     a.nblk = 1;
+    a.trace = s->trace;
     const int grid = persistent_grid(s, occupancy_ts_fused(dtype, s->lanes_trsv, s->lanes_spmv));
     Timer tm(s, st);
+    SF_HIP(launch_fill_pending(X, size_t(s->n), dtype, st));
     return hip_status(launch_ts_fused(a, dtype, s->lanes_trsv, s->lanes_spmv, grid, st));
   }
   const int kb = s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
   const int nblk = (nrhs + kb - 1) / kb;
-  sf_status r = ensure_flags(s, nblk, st);
-  if (r != SF_OK) return r;
-  r = ensure_xi(s, size_t(nblk) * size_t(s->n) * size_t(kb) * es, st);
+  const size_t xi_count = size_t(nblk) * size_t(s->n) * size_t(kb);
+  sf_status r = ensure_xi(s, xi_count * es, st);
   if (r != SF_OK) return r;
   r = next_epoch(s, st, a.ls);
   if (r != SF_OK) return r;
-  a.flags = s->dev.flags;
   a.kb = kb;
   a.nblk = nblk;
   a.xi = s->dev.xi;
   const int grid = persistent_grid(s, occupancy_ts_multi(dtype, kb));
   Timer tm(s, st);
+  SF_HIP(launch_fill_pending(s->dev.xi, xi_count, dtype, st));
   return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
 }
 
@@ -293,7 +296,12 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
     int grid = cus * std::min(occ, std::max(1, s->waves_per_cu * 64 / kBlockThreads));
     SF_HIP(launch_trsv_levelset(la, dtype, s->lanes_trsv, grid, st));
   }
-  if (Y && s->m > 0) {
+  if (Y && s->m > 0 && nrhs == 1) {
+    TsArgs sa = ts_args(s, Lv, Av, B, ldb, nrhs, X, ldx, Y, ldy);
+    sa.item_list = s->dev.spmv_items;
+    sa.n_work = int32_t(s->spmv_items.size());
+    SF_HIP(launch_spmv_items(sa, dtype, st));
+  } else if (Y && s->m > 0) {
     SpmvArgs sa{};
     sa.m = int32_t(s->m);
     sa.nrhs = nrhs;
@@ -382,6 +390,10 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
 
 sf_status sf_schedule_free(sf_schedule s) {
   if (!s) return SF_OK;
+  if (s->trace) {
+    hipDeviceSynchronize();
+    hipFree(s->trace);
+  }
   free_device(s);
   delete s;
   return SF_OK;
@@ -714,14 +726,22 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "claim_streams") {
     if (v < 1 || v > kStreams) return SF_ERR_ARG;
     s->claim_streams = int32_t(v);
-  } else if (k == "rows_per_item" || k == "max_item_nnz") {
-    if (v < 1 || v > (int64_t(1) << 30)) return SF_ERR_ARG;
+  } else if (k == "rows_per_item" || k == "max_item_nnz" || k == "spmv_delay") {
+    if (k == "spmv_delay" ? (v < 0 || v > (int64_t(1) << 30)) : (v < 1 || v > (int64_t(1) << 30)))
+      return SF_ERR_ARG;
+    if (k == "rows_per_item" && v > 64) return SF_ERR_ARG;  // one lane finishes each row
     if (k == "rows_per_item") s->rows_per_item = int32_t(v);
-    else s->max_item_nnz = int32_t(v);
+    else if (k == "max_item_nnz") s->max_item_nnz = int32_t(v);
+    else s->spmv_delay = int32_t(v);
     try {
       sf::cut_items(s);
     } catch (const std::bad_alloc&) {
       return SF_ERR_OOM;
+    }
+    if (s->trace) {  // sized for the old items
+      hipDeviceSynchronize();
+      hipFree(s->trace);
+      s->trace = nullptr;
     }
     if (s->dev.ready) {
       // the item arrays changed size: rebuild the constant block
@@ -734,6 +754,18 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     s->no_fusion = v ? 1 : 0;
   } else if (k == "timing") {
     s->timing = v ? 1 : 0;
+  } else if (k == "trace") {
+    // trace mode: the fused single-RHS executor stamps every item (debug aid)
+    if (s->trace) {
+      hipDeviceSynchronize();
+      hipFree(s->trace);
+      s->trace = nullptr;
+    }
+    if (v) {
+      const size_t bytes = (s->item_ptr.size() + 1) * 4 * sizeof(unsigned long long);
+      if (hipMalloc(&s->trace, bytes) != hipSuccess) return SF_ERR_OOM;
+      if (hipMemset(s->trace, 0, bytes) != hipSuccess) return SF_ERR_HIP;
+    }
   } else {
     return SF_ERR_ARG;
   }
@@ -751,8 +783,10 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "claim_streams") *v = s->claim_streams;
   else if (k == "rows_per_item") *v = s->rows_per_item;
   else if (k == "max_item_nnz") *v = s->max_item_nnz;
+  else if (k == "spmv_delay") *v = s->spmv_delay;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "timing") *v = s->timing;
+  else if (k == "trace") *v = s->trace ? 1 : 0;
   else return SF_ERR_ARG;
   return SF_OK;
 }
@@ -807,7 +841,9 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK && nrhs == 1) r = try_param("lanes_trsv", {2, 4, 8, 16, 32});
   if (r == SF_OK && nrhs == 1 && Y) r = try_param("lanes_spmv", {4, 8, 16, 32});
   if (r == SF_OK && nrhs > 1) r = try_param("rhs_block", {8, 16, 32, 64});
-  if (r == SF_OK) r = try_param("rows_per_item", {16, 32, 64, 128, 256});
+  if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 1 << 20});
+  if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});
+  if (r == SF_OK && nrhs == 1) r = try_param("max_item_nnz", {128, 256, 512, 1024, 2048});
   if (r == SF_OK) r = try_param("waves_per_cu", {4, 8, 16});
   if (r == SF_OK) r = upload(s, st);
   s->timing = saved_timing;
@@ -829,6 +865,15 @@ sf_status sf_sync_status(sf_schedule s, void* stream) {
     SF_HIP(hipMemcpy(s->dev.state + kStatusOff, &z, sizeof(z), hipMemcpyHostToDevice));
     return SF_ERR_TIMEOUT;
   }
+  return SF_OK;
+}
+
+sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count) {
+  if (!s || !out || !s->trace) return SF_ERR_ARG;
+  const int64_t have = int64_t(s->item_ptr.size() - 1) * 4;
+  if (count < have) return SF_ERR_SHAPE;
+  if (hipDeviceSynchronize() != hipSuccess) return SF_ERR_HIP;
+  if (hipMemcpy(out, s->trace, size_t(have) * 8, hipMemcpyDeviceToHost) != hipSuccess) return SF_ERR_HIP;
   return SF_OK;
 }
 

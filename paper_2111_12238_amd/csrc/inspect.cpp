@@ -125,19 +125,32 @@ static void cut_runs(const std::vector<int32_t>& order, const std::vector<int32_
 void cut_items(sf_schedule_s* s) {
   const int64_t n = s->n, m = s->m;
   if (s->kind == SF_TRSV_SPMV) {
+    // Claim order: SpTRSV rows by level; an SpMV row (a slack iteration: any
+    // slot at or after its joint level is valid) goes spmv_delay wavefronts
+    // after the level where its inputs are final, so on the claim counters
+    // it never gets ahead of the SpTRSV rows that form the critical path.
+    // With spmv_delay = 0 this is the canonical joint order (joint level,
+    // SpTRSV before SpMV, row).
     std::vector<int32_t> key(size_t(n + m)), cost(size_t(n + m));
+    int32_t last = std::max(s->depth - 1, 0);
+    for (int64_t r = 0; r < m; ++r) last = std::max(last, s->ready[r]);
     for (int64_t i = 0; i < n; ++i) {
       key[i] = 2 * s->level[i];
-      cost[i] = s->L.rp[i + 1] - s->L.rp[i];
+      cost[i] = std::max(1, s->L.rp[i + 1] - s->L.rp[i] - 1);
     }
     for (int64_t r = 0; r < m; ++r) {
-      key[n + r] = 2 * s->ready[r] + 1;
+      const int64_t slot = std::min<int64_t>(int64_t(s->ready[r]) + s->spmv_delay, last);
+      key[n + r] = int32_t(2 * slot + 1);
       cost[n + r] = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
     }
+    counting_order(key, 2 * (last + 1), s->order);
     cut_runs(s->order, key, cost, s->rows_per_item, s->max_item_nnz, s->item_ptr);
     s->trsv_items.clear();
-    for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t)
+    s->spmv_items.clear();
+    for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) {
       if (s->order[s->item_ptr[t]] < n) s->trsv_items.push_back(int32_t(t));
+      else s->spmv_items.push_back(int32_t(t));
+    }
   } else {
     std::vector<int32_t> key(static_cast<size_t>(n)), cost(static_cast<size_t>(n));
     for (int64_t i = 0; i < n; ++i) {
@@ -246,11 +259,6 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
       jd = std::max(jd, lv + 1);
     }
     s->joint_depth = jd;
-    // Claim order: (joint level, SpTRSV before SpMV, row).
-    std::vector<int32_t> key(size_t(n + m));
-    for (int64_t i = 0; i < n; ++i) key[i] = 2 * s->level[i];
-    for (int64_t r = 0; r < m; ++r) key[n + r] = 2 * s->ready[r] + 1;
-    counting_order(key, 2 * jd, s->order);
     const double nn = double(n), mm = double(m);
     const double ka = double(s->A.nnz()) + nn + mm, kl = double(s->L.nnz()) + 2.0 * nn;
     s->reuse = (ka > 0 || kl > 0) ? 2.0 * nn / std::max(ka, kl) : 0.0;
@@ -297,8 +305,9 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
     while (g < 64 && g < maxlen) g *= 2;
     s->lanes_trsv = o.lanes_per_row > 0 ? o.lanes_per_row : g;
   }
-  s->rows_per_item = o.rows_per_item > 0 ? o.rows_per_item : 64;
-  s->max_item_nnz = o.max_item_nnz > 0 ? o.max_item_nnz : 4096;
+  // one lane of a 64-wide wavefront finishes each row of an item
+  s->rows_per_item = o.rows_per_item > 0 ? std::min(o.rows_per_item, 64) : 64;
+  s->max_item_nnz = o.max_item_nnz > 0 ? o.max_item_nnz : 512;
   s->rhs_block = o.rhs_block;
   s->no_fusion = o.no_fusion;
   cut_items(s);

@@ -1,116 +1,247 @@
 // Fused SpTRSV -> SpMV executor and its unfused baseline (gfx950).
 //
-// One persistent launch runs the whole joint schedule (Sec. 2-3 of the
-// paper: the two kernels as one schedule over their joint DAG).  Each
-// 64-lane wavefront claims work items in the joint wavefront order; an item
-// holds rows of one wavefront and one kind, so its rows are independent and
-// are processed 64/G at a time with G lanes per row.  A SpTRSV row waits on
-// the readiness flags of the x_j it reads, computes
-//     x_i = (b_i - sum_{j<i} L_ij x_j) / L_ii,
-// stores x_i and publishes its flag; a SpMV row waits on the flags of every
-// x_j it reads (F = pattern of A) and stores y_r = sum_j A_rj x_j.  The
-// diagonal is the last stored entry of each row of L (checked by the
-// inspector).  Row sums: G lanes take every G-th entry, then a DPP group sum.
+// One persistent launch runs the whole joint schedule (the two kernels as
+// one schedule over their joint DAG).  Each 64-lane wavefront claims work
+// items in the joint wavefront order; an item holds up to 64 rows of one
+// wavefront and one kind, so its rows are independent.  A SpTRSV row computes
+//     x_i = (b_i - sum_{j<i} L_ij x_j) / L_ii
+// from the x_j it reads, each observed ready through the value-as-flag
+// protocol (dev_common.h), and publishes x_i with one device-coherent store;
+// a SpMV row reads every x_j it needs (F = pattern of A) the same way and
+// stores y_r = sum_j A_rj x_j.  The diagonal is the last stored entry of each
+// row of L (checked by the inspector).
+//
+// Item processing ("entry stream").  The off-diagonal entries of the item's
+// rows are concatenated and dealt to the 64 lanes, kRounds per lane, so a
+// single round of independent loads fetches every index, value and x of the
+// item (one memory round trip on the critical path whatever the row lengths).
+// Each product L_ij * x_j is rounded once into LDS; then the lane that owns
+// row i subtracts them from b_i in ascending column order and divides by
+// L_ii -- exactly the sequential definition's operations in its order, so
+// FP64 results are bit-identical to forward substitution done row by row.
+// SpMV rows add their products to 0 the same way.  No multiply-add
+// contraction is allowed in this file.
+#pragma clang fp contract(off)
+
 #include "dev_common.h"
 
 namespace sf {
 namespace {
 
-using dev::after_wait;
 using dev::group_sum;
+using dev::is_pending;
 using dev::ld_co;
+using dev::ld_stream;
+using dev::poll_value;
+using dev::publishable;
 using dev::st_co;
-using dev::stores_complete;
-using dev::wait_flag;
 
-// ---------------------------------------------------------------- k = 1 ----
-// FLAGS = true: fused executor (wait on flags, publish flags).
-// FLAGS = false: level-set baseline (rows of one level after a grid barrier).
-// Both read and write x with device-coherent accesses (see dev_common.h).
-template <typename T, int G, bool FLAGS>
-__device__ __forceinline__ void trsv_rows(const TsArgs& a, int q0, int q1, int lane) {
-  constexpr int RPB = 64 / G;
-  const int sub = lane & (G - 1);
-  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
-  const T* __restrict__ B = static_cast<const T*>(a.B);
-  T* X = static_cast<T*>(a.X);
-  for (int base = q0; base < q1; base += RPB) {
-    const int q = base + lane / G;
-    const bool act = q < q1;
-    const int i = act ? a.order[q] : 0;
-    const int r0 = act ? a.Lrp[i] : 0;
-    const int rd = act ? a.Lrp[i + 1] - 1 : 0;  // position of the diagonal
-    T s = T(0);
-    for (int p0 = r0; p0 < rd; p0 += G) {
-      const int p = p0 + sub;
-      const bool have = p < rd;
-      const int j = have ? a.Lci[p] : 0;
-      const T v = have ? Lv[p] : T(0);
-      if constexpr (FLAGS) {
-        if (have) wait_flag(a.flags + j, a.ls);
-        after_wait();
-      }
-      if (have) s += v * ld_co(X + j);
-    }
-    s = group_sum<G>(s);
-    if (act && sub == 0) {
-      st_co(X + i, (B[i] - s) / Lv[rd]);
-    }
-    if constexpr (FLAGS) {
-      stores_complete();
-      if (act && sub == 0) st_co(a.flags + i, a.ls.epoch);
-    }
-  }
-}
+constexpr int kRounds = 8;           // entries per lane per pass
+constexpr int kPass = 64 * kRounds;  // entries per pass of one wavefront
+constexpr int kWaves = kBlockThreads / 64;
 
-template <typename T, int G>
-__device__ __forceinline__ void spmv_rows(const TsArgs& a, int q0, int q1, int lane) {
-  constexpr int RPB = 64 / G;
-  const int sub = lane & (G - 1);
-  const T* __restrict__ Av = static_cast<const T*>(a.Av);
-  const T* X = static_cast<const T*>(a.X);
-  T* __restrict__ Y = static_cast<T*>(a.Y);
-  for (int base = q0; base < q1; base += RPB) {
-    const int q = base + lane / G;
-    const bool act = q < q1;
-    const int r = act ? a.order[q] - a.n : 0;
-    const int p0 = act ? a.Arp[r] : 0;
-    const int p1 = act ? a.Arp[r + 1] : 0;
-    T s = T(0);
-    for (int pb = p0; pb < p1; pb += G) {
-      const int p = pb + sub;
-      const bool have = p < p1;
-      const int j = have ? a.Aci[p] : 0;
-      const T v = have ? Av[p] : T(0);
-      if (have) wait_flag(a.flags + j, a.ls);
-      after_wait();
-      if (have) s += v * ld_co(X + j);
-    }
-    s = group_sum<G>(s);
-    if (act && sub == 0) __builtin_nontemporal_store(s, Y + r);
-  }
-}
+template <typename T>
+struct WaveLds {
+  int32_t off[64];    // first entry of each row slot in the item's stream
+  int32_t start[64];  // CSR position of that row's first entry
+  T prod[kPass];      // rounded products of the current pass
+};
 
-template <typename T, int GT, int GS>
-__global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
-  const int lane = threadIdx.x & 63;
-  dev::reset_next_launch(a.ls);
+// Process one item (rows order[q0..q1), q1 - q0 <= 64) of SpTRSV rows
+// (TRSV = true) or SpMV rows.  POLL: wait for x through the readiness
+// protocol (fused executor) or read it directly (level-set baseline, after a
+// grid barrier).
+// Wait until every x[j[e]] of the wavefront (j[e] < 0: unused slot) is
+// published, updating xv.  Only one lane polls at a time: the first lane
+// with a pending entry watches that entry; when it is published, every lane
+// re-reads all its still-pending entries in one round, and the election
+// repeats.  Dependences of an item come from earlier wavefronts that finish
+// close together, so this converges in a few rounds while keeping the
+// polling traffic of a waiting wavefront at one request instead of one per
+// pending entry.
+template <typename T, int R>
+__device__ __forceinline__ void wait_ready(const T* X, const int (&j)[R], T (&xv)[R], int lane,
+                                           const LaunchState& ls) {
   for (;;) {
-    const int t = dev::claim(a.ls, lane);
-    if (t >= a.n_work) break;
+    int first = -1;
+#pragma unroll
+    for (int e = R - 1; e >= 0; --e)
+      if (j[e] >= 0 && is_pending(xv[e])) first = e;
+    const unsigned long long mask = __ballot(first >= 0);
+    if (mask == 0) return;
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    if (lane == leader) {
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (e == first) xv[e] = poll_value(X + j[e], ls);
+    }
+    if (dev::ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (j[e] >= 0 && is_pending(xv[e])) xv[e] = ld_co(X + j[e]);
+  }
+}
+
+// Trace mode (a.trace != nullptr): per item, timestamps of the 100 MHz
+// real-time counter at the start of processing, once the item's indices and
+// values are loaded, once every x it reads is ready, and at the end.
+__device__ __forceinline__ void trace_mark(const TsArgs& a, int it, int k, int lane) {
+  if (a.trace && lane == 0) a.trace[size_t(it) * 4 + k] = __builtin_amdgcn_s_memrealtime();
+}
+
+template <typename T, bool TRSV, bool POLL>
+__device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
+                                            int it = -1) {
+  const int nr = q1 - q0;
+  const bool mine = lane < nr;
+  const int32_t* __restrict__ rp = TRSV ? a.Lrp : a.Arp;
+  const int32_t* __restrict__ ci = TRSV ? a.Lci : a.Aci;
+  const T* __restrict__ val = static_cast<const T*>(TRSV ? a.Lv : a.Av);
+  T* X = static_cast<T*>(a.X);
+  const int id = mine ? a.order[q0 + lane] : 0;
+  const int row = TRSV ? id : id - a.n;
+  const int r0 = mine ? rp[row] : 0;
+  const int r1 = mine ? rp[row + 1] - (TRSV ? 1 : 0) : 0;  // SpTRSV: stop before the diagonal
+  const int len = r1 - r0;
+  T acc = T(0), dii = T(1);
+  if (TRSV && mine) {
+    acc = static_cast<const T*>(a.B)[row];
+    dii = ld_stream(val + r1);
+  }
+  // exclusive prefix sum of the row lengths over the item's row slots
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  w.off[lane] = off;
+  w.start[lane] = r0;
+  __builtin_amdgcn_wave_barrier();
+  for (int base = 0; base < total; base += kPass) {
+    int j[kRounds];
+    T v[kRounds], xv[kRounds];
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      j[e] = -1;
+      v[e] = T(0);
+      if (k < total) {
+        int s = 0;  // the last row slot whose stream offset is <= k
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+          if (s + step < nr && w.off[s + step] <= k) s += step;
+        const int p = w.start[s] + (k - w.off[s]);
+        j[e] = ld_stream(ci + p);
+        v[e] = ld_stream(val + p);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? ld_co(X + j[e]) : T(0);
+    if (it >= 0) trace_mark(a, it, 1, lane);
+    if constexpr (POLL) wait_ready<T, kRounds>(X, j, xv, lane, a.ls);
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      if (k < total) w.prod[k - base] = v[e] * xv[e];
+    }
+    if (it >= 0) trace_mark(a, it, 2, lane);
+    __builtin_amdgcn_wave_barrier();
+    if (mine) {
+      // ascending order, one rounding per term; LDS reads issued 8 ahead
+      const int lo = max(off, base) - base;
+      const int hi = min(off + len, base + kPass) - base;
+      int t = lo;
+      for (; t + 8 <= hi; t += 8) {
+        T pr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pr[u] = w.prod[t + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if constexpr (TRSV) acc = acc - pr[u];
+          else acc = acc + pr[u];
+        }
+      }
+      for (; t < hi; ++t) {
+        if constexpr (TRSV) acc = acc - w.prod[t];
+        else acc = acc + w.prod[t];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (mine) {
+    if constexpr (TRSV) st_co(X + row, publishable(acc / dii));
+    else __builtin_nontemporal_store(acc, static_cast<T*>(a.Y) + row);
+  }
+  if (it >= 0) trace_mark(a, it, 3, lane);
+}
+
+// The next ticket is claimed before the current item is processed, so the
+// claim's round trip overlaps the item's loads.  Deadlock freedom still
+// holds: a wave's prefetched ticket is larger than the item it works on, so
+// the smallest claimed-but-unfinished item is always one being processed.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
+  __shared__ WaveLds<T> lds[kWaves];
+  const int lane = threadIdx.x & 63;
+  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  dev::reset_next_launch(a.ls);
+  int t = dev::claim(a.ls, lane);
+  while (t < a.n_work) {
+    const int tn = dev::claim(a.ls, lane);
     const int it = a.item_list ? a.item_list[t] : t;
     const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-    if (a.order[q0] < a.n) trsv_rows<T, GT, true>(a, q0, q1, lane);
-    else spmv_rows<T, GS>(a, q0, q1, lane);
+    trace_mark(a, it, 0, lane);
+    if (a.order[q0] < a.n) item_stream<T, true, true>(a, q0, q1, lane, w, it);
+    else item_stream<T, false, true>(a, q0, q1, lane, w, it);
+    t = tn;
   }
 }
 
 // ------------------------------------------------------------- k > 1 ------
 // KB lanes per row, one lane per right-hand side of the block; 64/KB rows
 // at a time.  The solution of block b is kept interleaved in a workspace,
-// xi[(b * n + j) * KB + c], so the KB values a row reads from x_j are
-// contiguous; X and Y are column-major.  Work index t = item * nblk + block.
-template <typename T, int KB, bool FLAGS>
+// xi[(b * n + j) * KB + c] (filled with the pending pattern before the
+// launch), so the KB values a row reads from x_j are contiguous; X and Y are
+// column-major.  Work index t = item * nblk + block.  Each lane runs its
+// row's entries in ascending order (b_i minus each rounded product), loads
+// issued kU at a time.
+constexpr int kU = 4;
+
+template <typename T, int KB, bool TRSV, bool POLL>
+__device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T* __restrict__ val, const T* xi,
+                                       int p0, int p1, int c, T acc, const LaunchState& ls) {
+  for (int c0 = p0; c0 < p1; c0 += kU) {
+    int j[kU];
+    T v[kU], xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int p = c0 + u;
+      const bool h = p < p1;
+      j[u] = h ? col[p] : -1;
+      v[u] = h ? val[p] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) xv[u] = j[u] >= 0 ? ld_co(xi + size_t(j[u]) * KB + c) : T(0);
+    if constexpr (POLL) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (j[u] >= 0 && is_pending(xv[u])) xv[u] = poll_value(xi + size_t(j[u]) * KB + c, ls);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (j[u] < 0) break;
+      const T pr = v[u] * xv[u];
+      if constexpr (TRSV) acc = acc - pr;
+      else acc = acc + pr;
+    }
+  }
+  return acc;
+}
+
+template <typename T, int KB, bool POLL>
 __device__ __forceinline__ void trsv_rows_multi(const TsArgs& a, int q0, int q1, int blk, int lane) {
   constexpr int RPB = 64 / KB;
   const int c = lane % KB;
@@ -120,28 +251,19 @@ __device__ __forceinline__ void trsv_rows_multi(const TsArgs& a, int q0, int q1,
   const T* __restrict__ B = static_cast<const T*>(a.B);
   T* __restrict__ X = static_cast<T*>(a.X);
   T* xi = static_cast<T*>(a.xi) + size_t(blk) * size_t(a.n) * KB;
-  int32_t* flags = a.flags + size_t(blk) * size_t(a.n);
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / KB;
     const bool act = q < q1;
     const int i = act ? a.order[q] : 0;
     const int r0 = act ? a.Lrp[i] : 0;
     const int rd = act ? a.Lrp[i + 1] - 1 : 0;
-    if constexpr (FLAGS) {
-      for (int p = r0 + c; p < rd; p += KB) wait_flag(flags + a.Lci[p], a.ls);
-      after_wait();
-    }
-    T s = T(0);
-    for (int p = r0; p < rd; ++p) s += Lv[p] * ld_co(xi + size_t(a.Lci[p]) * KB + c);
+    const T bi = (act && colok) ? B[size_t(i) + size_t(cc) * a.ldb] : T(0);
+    const T dii = act ? Lv[rd] : T(1);
+    const T s = row_multi<T, KB, true, POLL>(a.Lci, Lv, xi, r0, rd, c, bi, a.ls);
     if (act) {
-      const T bi = colok ? B[size_t(i) + size_t(cc) * a.ldb] : T(0);
-      const T xv = (bi - s) / Lv[rd];
+      const T xv = publishable(s / dii);
       st_co(xi + size_t(i) * KB + c, xv);
-      if (colok) X[size_t(i) + size_t(cc) * a.ldx] = xv;
-    }
-    if constexpr (FLAGS) {
-      stores_complete();
-      if (act && c == 0) st_co(flags + i, a.ls.epoch);
+      if (colok) __builtin_nontemporal_store(xv, X + size_t(i) + size_t(cc) * a.ldx);
     }
   }
 }
@@ -155,17 +277,13 @@ __device__ __forceinline__ void spmv_rows_multi(const TsArgs& a, int q0, int q1,
   const T* __restrict__ Av = static_cast<const T*>(a.Av);
   T* __restrict__ Y = static_cast<T*>(a.Y);
   const T* xi = static_cast<const T*>(a.xi) + size_t(blk) * size_t(a.n) * KB;
-  const int32_t* flags = a.flags + size_t(blk) * size_t(a.n);
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / KB;
     const bool act = q < q1;
     const int r = act ? a.order[q] - a.n : 0;
     const int p0 = act ? a.Arp[r] : 0;
     const int p1 = act ? a.Arp[r + 1] : 0;
-    for (int p = p0 + c; p < p1; p += KB) wait_flag(flags + a.Aci[p], a.ls);
-    after_wait();
-    T s = T(0);
-    for (int p = p0; p < p1; ++p) s += Av[p] * ld_co(xi + size_t(a.Aci[p]) * KB + c);
+    const T s = row_multi<T, KB, false, true>(a.Aci, Av, xi, p0, p1, c, T(0), a.ls);
     if (act && colok) __builtin_nontemporal_store(s, Y + size_t(r) + size_t(cc) * a.ldy);
   }
 }
@@ -175,80 +293,95 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_multi(TsArgs a) {
   const int lane = threadIdx.x & 63;
   dev::reset_next_launch(a.ls);
   const int total = a.n_work * a.nblk;
-  for (;;) {
-    const int t = dev::claim(a.ls, lane);
-    if (t >= total) break;
+  int t = dev::claim(a.ls, lane);
+  while (t < total) {
+    const int tn = dev::claim(a.ls, lane);
     const int w = t / a.nblk;
     const int blk = t - w * a.nblk;
     const int it = a.item_list ? a.item_list[w] : w;
     const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
     if (a.order[q0] < a.n) trsv_rows_multi<T, KB, true>(a, q0, q1, blk, lane);
     else spmv_rows_multi<T, KB>(a, q0, q1, blk, lane);
+    t = tn;
   }
 }
 
+// Fill a solution buffer with the pending pattern before a launch.
+template <typename T>
+__global__ void k_fill_pending(T* p, size_t count) {
+  const T v = __builtin_bit_cast(T, dev::Pending<T>::bits);
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < count; k += size_t(gridDim.x) * blockDim.x)
+    p[k] = v;
+}
+
 // ---------------------------------------------------------- level set ----
-// Unfused baseline: items of one level are spread over all wavefronts of a
-// cooperative grid, then a grid-wide barrier; no readiness flags.
-template <typename T, int G>
+// Unfused baseline, same per-item arithmetic: the SpTRSV items of one level
+// are spread over all wavefronts of a cooperative grid, then a grid-wide
+// barrier (no readiness protocol); afterwards a separate launch runs the
+// SpMV items.  x is read and written with device-coherent accesses so the
+// barrier only has to wait for stores to complete (dev::grid_barrier).
+template <typename T>
 __global__ __launch_bounds__(kBlockThreads) void k_trsv_levelset(LevelArgs la) {
+  __shared__ WaveLds<T> lds[kWaves];
   const TsArgs& a = la.ts;
   const int lane = threadIdx.x & 63;
+  WaveLds<T>& w = lds[threadIdx.x >> 6];
   dev::reset_next_launch(a.ls);
-  const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
-  const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
+  const int wave = int(blockIdx.x) * kWaves + int(threadIdx.x >> 6);
+  const int nwaves = int(gridDim.x) * kWaves;
   int32_t gen = 0;
   for (int lv = 0; lv < la.depth; ++lv) {
     const int t0 = la.lvl_item_ptr[lv], t1 = la.lvl_item_ptr[lv + 1];
     for (int t = t0 + wave; t < t1; t += nwaves) {
       const int it = a.item_list[t];
       const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-      if (a.nrhs == 1) trsv_rows<T, G, false>(a, q0, q1, lane);
+      if (a.nrhs == 1) item_stream<T, true, false>(a, q0, q1, lane, w);
       else for (int blk = 0; blk < a.nblk; ++blk) trsv_rows_multi<T, 8, false>(a, q0, q1, blk, lane);
     }
     if (lv + 1 < la.depth) dev::grid_barrier(a.ls, gen);
   }
 }
 
-// Plain CSR SpMV, G lanes per row (grid-stride), any number of columns.
-template <typename T, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_spmv(SpmvArgs a) {
-  constexpr int RPB = 64 / G;
+// SpMV items (all inputs final), grid-stride over the item list.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void k_spmv_items(TsArgs a) {
+  __shared__ WaveLds<T> lds[kWaves];
   const int lane = threadIdx.x & 63;
-  const int sub = lane & (G - 1);
+  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  const int wave = int(blockIdx.x) * kWaves + int(threadIdx.x >> 6);
+  const int nwaves = int(gridDim.x) * kWaves;
+  for (int t = wave; t < a.n_work; t += nwaves) {
+    const int it = a.item_list[t];
+    item_stream<T, false, false>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, w);
+  }
+}
+
+// Plain CSR SpMV over column-major blocks (multi-RHS baseline), one lane
+// per row, ascending entries.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void k_spmv(SpmvArgs a) {
   const T* __restrict__ Av = static_cast<const T*>(a.Av);
   const T* __restrict__ X = static_cast<const T*>(a.X);
   T* __restrict__ Y = static_cast<T*>(a.Y);
-  const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
-  const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
-  for (int base = wave * RPB; base < a.m; base += nwaves * RPB) {
-    const int r = base + lane / G;
-    const bool act = r < a.m;
-    const int p0 = act ? a.Arp[r] : 0, p1 = act ? a.Arp[r + 1] : 0;
+  for (int r = blockIdx.x * kBlockThreads + threadIdx.x; r < a.m; r += gridDim.x * kBlockThreads) {
+    const int p0 = a.Arp[r], p1 = a.Arp[r + 1];
     for (int c = 0; c < a.nrhs; ++c) {
       const T* x = X + size_t(c) * a.ldx;
       T s = T(0);
-      for (int p = p0 + sub; p < p1; p += G) s += Av[p] * x[a.Aci[p]];
-      s = group_sum<G>(s);
-      if (act && sub == 0) __builtin_nontemporal_store(s, Y + size_t(r) + size_t(c) * a.ldy);
+      for (int p = p0; p < p1; ++p) {
+        const T pr = Av[p] * x[a.Aci[p]];
+        s = s + pr;
+      }
+      Y[size_t(r) + size_t(c) * a.ldy] = s;
     }
   }
 }
 
 template <typename T>
-hipError_t ts_fused_dispatch(const TsArgs& a, int gt, int gs, int grid, hipStream_t st) {
-#define SF_TS(GT, GS)                                                                   \
-  if (gt == GT && gs == GS) {                                                           \
-    hipLaunchKernelGGL((k_ts_fused<T, GT, GS>), dim3(grid), dim3(kBlockThreads), 0, st, a); \
-    return hipGetLastError();                                                           \
-  }
-  SF_TS(2, 4) SF_TS(2, 8) SF_TS(2, 16) SF_TS(2, 32)
-  SF_TS(4, 4) SF_TS(4, 8) SF_TS(4, 16) SF_TS(4, 32)
-  SF_TS(8, 4) SF_TS(8, 8) SF_TS(8, 16) SF_TS(8, 32)
-  SF_TS(16, 4) SF_TS(16, 8) SF_TS(16, 16) SF_TS(16, 32)
-  SF_TS(32, 4) SF_TS(32, 8) SF_TS(32, 16) SF_TS(32, 32)
-#undef SF_TS
-  return hipErrorInvalidValue;
+hipError_t levelset_launch(const LevelArgs& a, int grid, hipStream_t st) {
+  void* args[] = {const_cast<LevelArgs*>(&a)};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_trsv_levelset<T>), dim3(grid),
+                                    dim3(kBlockThreads), args, 0, st);
 }
 
 template <typename T>
@@ -263,36 +396,6 @@ hipError_t ts_multi_dispatch(const TsArgs& a, int kb, int grid, hipStream_t st) 
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t levelset_dispatch(const LevelArgs& a, int gt, int grid, hipStream_t st) {
-  void* args[] = {const_cast<LevelArgs*>(&a)};
-#define SF_LS(G)                                                                          \
-  if (gt == G)                                                                            \
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_trsv_levelset<T, G>), \
-                                      dim3(grid), dim3(kBlockThreads), args, 0, st);
-  SF_LS(2) SF_LS(4) SF_LS(8) SF_LS(16) SF_LS(32)
-#undef SF_LS
-  return hipErrorInvalidValue;
-}
-
-template <typename T>
-hipError_t spmv_dispatch(const SpmvArgs& a, int gs, hipStream_t st) {
-  int dev = 0, cus = 256;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int rows_per_block = (kBlockThreads / 64) * (64 / gs);
-  int grid = (a.m + rows_per_block - 1) / rows_per_block;
-  grid = grid < 1 ? 1 : (grid > cus * 32 ? cus * 32 : grid);
-#define SF_SP(G)                                                                   \
-  if (gs == G) {                                                                   \
-    hipLaunchKernelGGL((k_spmv<T, G>), dim3(grid), dim3(kBlockThreads), 0, st, a); \
-    return hipGetLastError();                                                      \
-  }
-  SF_SP(2) SF_SP(4) SF_SP(8) SF_SP(16) SF_SP(32)
-#undef SF_SP
-  return hipErrorInvalidValue;
-}
-
 template <typename K>
 int occ(K kernel) {
   int b = 0;
@@ -302,48 +405,65 @@ int occ(K kernel) {
   return b < 1 ? 1 : b;
 }
 
+int cu_count() {
+  int dev = 0, cus = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus;
+}
+
 }  // namespace
 
 hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid, hipStream_t st) {
-  return dtype == 0 ? ts_fused_dispatch<double>(a, gt, gs, grid, st)
-                    : ts_fused_dispatch<float>(a, gt, gs, grid, st);
+  (void)gt;
+  (void)gs;
+  if (dtype == 0) hipLaunchKernelGGL(k_ts_fused<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  else hipLaunchKernelGGL(k_ts_fused<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  return hipGetLastError();
 }
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st) {
   return dtype == 0 ? ts_multi_dispatch<double>(a, kb, grid, st) : ts_multi_dispatch<float>(a, kb, grid, st);
 }
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st) {
-  return dtype == 0 ? levelset_dispatch<double>(a, gt, grid, st) : levelset_dispatch<float>(a, gt, grid, st);
+  (void)gt;
+  return dtype == 0 ? levelset_launch<double>(a, grid, st) : levelset_launch<float>(a, grid, st);
+}
+hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st) {
+  const int grid = cu_count() * 8;
+  if (dtype == 0) hipLaunchKernelGGL(k_spmv_items<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  else hipLaunchKernelGGL(k_spmv_items<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  return hipGetLastError();
 }
 hipError_t launch_spmv(const SpmvArgs& a, int dtype, int gs, hipStream_t st) {
-  return dtype == 0 ? spmv_dispatch<double>(a, gs, st) : spmv_dispatch<float>(a, gs, st);
+  (void)gs;
+  int grid = (a.m + kBlockThreads - 1) / kBlockThreads;
+  grid = grid < 1 ? 1 : (grid > cu_count() * 32 ? cu_count() * 32 : grid);
+  if (dtype == 0) hipLaunchKernelGGL(k_spmv<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  else hipLaunchKernelGGL(k_spmv<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  size_t g = (count + 255) / 256;
+  const int grid = int(g > 16384 ? 16384 : g);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill_pending<double>, dim3(grid), dim3(256), 0, st, static_cast<double*>(p), count);
+  else
+    hipLaunchKernelGGL(k_fill_pending<float>, dim3(grid), dim3(256), 0, st, static_cast<float*>(p), count);
+  return hipGetLastError();
 }
 int occupancy_ts_fused(int dtype, int gt, int gs) {
   (void)gt;
   (void)gs;
-  // every instantiation has the same resource shape to within a few VGPRs
-  return dtype == 0 ? occ(k_ts_fused<double, 4, 8>) : occ(k_ts_fused<float, 4, 8>);
+  return dtype == 0 ? occ(k_ts_fused<double>) : occ(k_ts_fused<float>);
 }
 int occupancy_ts_multi(int dtype, int kb) {
   (void)kb;
   return dtype == 0 ? occ(k_ts_multi<double, 8>) : occ(k_ts_multi<float, 8>);
 }
 int occupancy_trsv_levelset(int dtype, int gt) {
-  if (dtype == 0) {
-    switch (gt) {
-      case 2: return occ(k_trsv_levelset<double, 2>);
-      case 4: return occ(k_trsv_levelset<double, 4>);
-      case 8: return occ(k_trsv_levelset<double, 8>);
-      case 16: return occ(k_trsv_levelset<double, 16>);
-      default: return occ(k_trsv_levelset<double, 32>);
-    }
-  }
-  switch (gt) {
-    case 2: return occ(k_trsv_levelset<float, 2>);
-    case 4: return occ(k_trsv_levelset<float, 4>);
-    case 8: return occ(k_trsv_levelset<float, 8>);
-    case 16: return occ(k_trsv_levelset<float, 16>);
-    default: return occ(k_trsv_levelset<float, 32>);
-  }
+  (void)gt;
+  return dtype == 0 ? occ(k_trsv_levelset<double>) : occ(k_trsv_levelset<float>);
 }
 
 }  // namespace sf

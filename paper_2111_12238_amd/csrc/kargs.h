@@ -35,6 +35,7 @@ struct TsArgs {
   const int32_t *order, *item_ptr, *item_list;
   int32_t n_work;          // items to run (entries of item_list, or all items)
   int32_t* flags;          // n per right-hand-side block
+  unsigned long long* trace;  // optional: 4 timestamps per item (see k_ts.hip)
   LaunchState ls;
 };
 
@@ -114,6 +115,8 @@ hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid,
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st);
 hipError_t launch_spmv(const SpmvArgs& a, int dtype, int gs, hipStream_t st);
+// SpMV items of a schedule (a.item_list / a.n_work), all inputs final.
+hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st);
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);
 hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st);
 hipError_t launch_bwd(const BwdArgs& a, int dtype, int g, int grid, hipStream_t st);
@@ -122,6 +125,8 @@ hipError_t launch_final(const ResArgs& a, hipStream_t st);
 hipError_t launch_convert_f64_f32(const double* src, int32_t lds, float* dst, int32_t n,
                                   int32_t nrhs, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int32_t count, hipStream_t st);
+// Fill a solution buffer with the pending (not yet published) pattern.
+hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st);
 
 
 // Occupancy queries per kernel family (blocks per CU).

@@ -22,7 +22,7 @@ struct Pattern {
 // belong to the launch with that epoch parity; every launch clears the fields
 // of the other parity for the launch that follows it on the stream.
 constexpr int kLine = 64;                 // int32 words per 256-byte line
-constexpr int kStreams = 8;               // claim counters per parity
+constexpr int kStreams = 32;              // claim counters per parity
 inline constexpr int ctr_off(int p, int s) { return (p * kStreams + s) * kLine; }
 inline constexpr int done_off(int p) { return (2 * kStreams + p) * kLine; }
 inline constexpr int info_off(int p) { return (2 * kStreams + 2 + p) * kLine; }
@@ -40,7 +40,7 @@ struct DeviceBuffers {
   // patterns
   int32_t *Lrp = nullptr, *Lci = nullptr, *Arp = nullptr, *Aci = nullptr;
   // forward schedule
-  int32_t *order = nullptr, *item_ptr = nullptr, *trsv_items = nullptr;
+  int32_t *order = nullptr, *item_ptr = nullptr, *trsv_items = nullptr, *spmv_items = nullptr;
   int32_t *lvl_items = nullptr;     // item list of the level-set baseline
   int32_t *lvl_item_ptr = nullptr;  // per level, into lvl_items
   // backward
@@ -76,6 +76,7 @@ struct sf_schedule_s {
   // SF_IC0_TRSV: ids are rows; row i's item runs SpIC0 row i then SpTRSV row i.
   std::vector<int32_t> order, item_ptr;
   std::vector<int32_t> trsv_items;   // items holding SpTRSV rows, in claim order
+  std::vector<int32_t> spmv_items;   // items holding SpMV rows, in claim order
   // Level-set baseline: items of SpTRSV rows grouped by level.
   std::vector<int32_t> lvl_items, lvl_item_ptr;
 
@@ -94,10 +95,12 @@ struct sf_schedule_s {
   // Executor parameters.
   int32_t lanes_trsv = 4, lanes_spmv = 8, rhs_block = 0, waves_per_cu = 8;
   int32_t rows_per_item = 64, max_item_nnz = 4096;
+  int32_t spmv_delay = 0;            // wavefronts an SpMV row waits after its inputs are final
   int64_t spin_limit = int64_t(1) << 22;
   int32_t claim_streams = 1;
   int32_t no_fusion = 0;
   int32_t timing = 0;
+  unsigned long long* trace = nullptr;  // device buffer of 4 stamps per item (trace mode)
   double last_kernel_ms = -1.0;
   double reuse = 0.0, inspect_seconds = 0.0;
 

@@ -47,6 +47,35 @@ def test_s1_lap2d5_64_fp64(orc):
     assert relerr(x, xr) <= TOL64 and relerr(y, yr) <= TOL64
 
 
+@pytest.mark.parametrize("case", ["lap2d5_64", "random", "spd", "multi"])
+def test_fp64_bit_identical_to_oracle(orc, case):
+    """Each row subtracts the rounded products L_ij x_j from b_i in ascending
+    column order and divides by L_ii, like the sequential definition, so the
+    fused and unfused FP64 results equal the oracle's bit for bit."""
+    announce("ts bit-identical " + case)
+    if case == "lap2d5_64":
+        L, A = synth.workload("lap2d5_64")
+    elif case == "random":
+        L = synth.random_lower(5003, 0.002, seed=11)
+        A = synth.from_scipy(sp.random(2500, 5003, density=0.003, random_state=np.random.default_rng(3),
+                                       format="csr"))
+    else:
+        A = synth.random_spd(30000, seed=5)
+        L = synth.lower(A)
+    k = 5 if case == "multi" else None
+    b = synth.vec_uniform(L.nrows, k=k or 1, seed=2)
+    s = sfm.Schedule(L, A, rows_per_item=23)
+    xr, yr = oracle_ts(orc, L, A, b)
+    for unfused in (False, True):
+        x, y = run(s, L, A, b, unfused=unfused)
+        assert np.array_equal(x, xr), ("x", unfused)
+        assert np.array_equal(y, yr), ("y", unfused)
+    for delay in (2, 1 << 20):  # SpMV rows placed later in the claim order
+        s.set_param("spmv_delay", delay)
+        x, y = run(s, L, A, b)
+        assert np.array_equal(x, xr) and np.array_equal(y, yr), delay
+
+
 def test_integer_manufactured_solution_bit_exact():
     """Integer L, A and x_true: every partial sum is an exact integer and the
     divisions are exact, so the GPU result must equal x_true and A x_true in

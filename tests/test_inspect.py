@@ -55,12 +55,39 @@ def test_random_schedules(orc, seed, n, m, empty):
         assert sizes.max() <= rows
 
 
+@pytest.mark.parametrize("delay", [1, 3, 1000])
+def test_spmv_delay_orders_stay_valid(orc, delay):
+    """SpMV rows are slack iterations: placing them `delay` wavefronts after
+    their joint level keeps every DAG edge respected (the oracle's
+    validator), keeps the SpTRSV rows in canonical order, and puts no SpMV row
+    before its joint level."""
+    for L, A in (synth.workload("lap2d5_64"), _random_pair(1500, 7, 900, True)):
+        s = sfm.Schedule(L, A, rows_per_item=20, validate=True)
+        s.set_param("spmv_delay", delay)
+        level, order, ip = s.export()
+        assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, ip) == 0
+        n = L.nrows
+        trsv = order[order < n]
+        assert np.array_equal(trsv, np.lexsort((np.arange(n), level)))
+        ready = orc.spmv_ready(A.rowptr, A.col, level)
+        pos = np.empty(len(order), int)
+        pos[order] = np.arange(len(order))
+        # the SpTRSV rows of level ready + delay (when that level exists) come before it
+        for r in range(0, A.nrows, 37):
+            want_after = np.nonzero(level == min(ready[r] + delay, level.max()))[0]
+            if ready[r] + delay <= level.max() and len(want_after):
+                assert pos[n + r] > pos[want_after].max()
+        s.set_param("spmv_delay", 0)
+        assert np.array_equal(s.export()[1], orc.joint_order_ts(level, ready))
+
+
 def test_item_nnz_budget():
     L, A = synth.workload("lap2d5_64")
     s = sfm.Schedule(L, A, rows_per_item=1000, max_item_nnz=40)
     level, order, ip = s.export()
     n = L.nrows
-    cost = np.concatenate([np.diff(L.rowptr), np.maximum(1, np.diff(A.rowptr))])
+    # cost c(v) = entries an iteration streams (SpTRSV: off-diagonals; at least 1)
+    cost = np.concatenate([np.maximum(1, np.diff(L.rowptr) - 1), np.maximum(1, np.diff(A.rowptr))])
     for t in range(len(ip) - 1):
         ids = order[ip[t]:ip[t + 1]]
         assert len(ids) == 1 or cost[ids].sum() <= 40
