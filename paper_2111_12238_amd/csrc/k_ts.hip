@@ -42,15 +42,10 @@ constexpr int kWaves = kBlockThreads / 64;
 
 template <typename T>
 struct WaveLds {
-  int32_t off[64];    // first entry of each row slot in the item's stream
-  int32_t start[64];  // CSR position of that row's first entry
-  T prod[kPass];      // rounded products of the current pass
+  int32_t pos[kPass];  // CSR position of each stream entry of the current pass
+  T prod[kPass];       // rounded products of the current pass
 };
 
-// Process one item (rows order[q0..q1), q1 - q0 <= 64) of SpTRSV rows
-// (TRSV = true) or SpMV rows.  POLL: wait for x through the readiness
-// protocol (fused executor) or read it directly (level-set baseline, after a
-// grid barrier).
 // Wait until every x[j[e]] of the wavefront (j[e] < 0: unused slot) is
 // published, updating xv.  Only one lane polls at a time: the first lane
 // with a pending entry watches that entry; when it is published, every lane
@@ -89,7 +84,13 @@ __device__ __forceinline__ void trace_mark(const TsArgs& a, int it, int k, int l
   if (a.trace && lane == 0) a.trace[size_t(it) * 4 + k] = __builtin_amdgcn_s_memrealtime();
 }
 
-template <typename T, bool TRSV, bool POLL>
+// Process one item (rows order[q0..q1), q1 - q0 <= 64) of SpTRSV rows
+// (TRSV = true) or SpMV rows.  POLL: wait for x through the readiness
+// protocol (fused executor) or read it directly (level-set baseline, after a
+// grid barrier).  CACHED_X: x was final before this launch started (the
+// unfused SpMV), so it is read through the caches instead of the
+// device-coherent path.
+template <typename T, bool TRSV, bool POLL, bool CACHED_X = false>
 __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
                                             int it = -1) {
   const int nr = q1 - q0;
@@ -117,10 +118,13 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
   }
   const int off = incl - len;
   const int total = __shfl(incl, 63, 64);
-  w.off[lane] = off;
-  w.start[lane] = r0;
-  __builtin_amdgcn_wave_barrier();
   for (int base = 0; base < total; base += kPass) {
+    // each row's lane lays its entries' CSR positions into this pass's window
+    if (mine) {
+      const int lo = max(off, base), hi = min(off + len, base + kPass);
+      for (int t = lo; t < hi; ++t) w.pos[t - base] = r0 + (t - off);
+    }
+    __builtin_amdgcn_wave_barrier();
     int j[kRounds];
     T v[kRounds], xv[kRounds];
 #pragma unroll
@@ -129,17 +133,13 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
       j[e] = -1;
       v[e] = T(0);
       if (k < total) {
-        int s = 0;  // the last row slot whose stream offset is <= k
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-          if (s + step < nr && w.off[s + step] <= k) s += step;
-        const int p = w.start[s] + (k - w.off[s]);
+        const int p = w.pos[k - base];
         j[e] = ld_stream(ci + p);
         v[e] = ld_stream(val + p);
       }
     }
 #pragma unroll
-    for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? ld_co(X + j[e]) : T(0);
+    for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? (CACHED_X ? X[j[e]] : ld_co(X + j[e])) : T(0);
     if (it >= 0) trace_mark(a, it, 1, lane);
     if constexpr (POLL) wait_ready<T, kRounds>(X, j, xv, lane, a.ls);
 #pragma unroll
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_spmv_items(TsArgs a) {
   const int nwaves = int(gridDim.x) * kWaves;
   for (int t = wave; t < a.n_work; t += nwaves) {
     const int it = a.item_list[t];
-    item_stream<T, false, false>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, w);
+    item_stream<T, false, false, true>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, w);
   }
 }
 
