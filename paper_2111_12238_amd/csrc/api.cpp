@@ -513,6 +513,9 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
     a.n_work = int32_t(s->item_ptr.size() - 1);
     a.solve = solve ? 1 : 0;
     const int grid = persistent_grid(s, occupancy_ic0(s->lanes_trsv, 0));
+    // every factor value and x_i is its own readiness flag
+    SF_HIP(launch_fill_pending(L_val, size_t(s->L.nnz()), 0, st));
+    if (solve) SF_HIP(launch_fill_pending(X, size_t(s->n), 0, st));
     return hip_status(launch_ic0_fused(a, s->lanes_trsv, grid, st));
   }
   // unfused: level-set factorisation, then a level-set solve
@@ -607,6 +610,8 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r != SF_OK) return r;
   const int grid = persistent_grid(s, occupancy_bwd(dt, s->lanes_trsv));
   Timer tm(s, st);
+  // grad_B is the lambda buffer and its own readiness flag
+  SF_HIP(launch_fill_pending(grad_B, size_t(s->n), dt, st));
   return hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st));
 }
 

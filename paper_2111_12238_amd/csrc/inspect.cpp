@@ -200,7 +200,7 @@ static void build_pairs(sf_schedule_s* s) {
       while (pi < p && pj < ej) {
         const int32_t ki = L.ci[pi], kj = L.ci[pj];
         if (ki == kj) {
-          s->pair_u.push_back(pi - r0);
+          s->pair_u.push_back(((p - r0) << 16) | (pi - r0));  // (entry of row i, matching entry)
           s->pair_q.push_back(pj);
           ++pi;
           ++pj;

@@ -5,32 +5,55 @@
 //     L_ij = (A_ij - sum_{k<j, k in P_i and P_j} L_ik L_jk) / L_jj,  j in P_i, j < i
 //     L_ii = sqrt(A_ii - sum_{k<i} L_ik^2)
 // and, in the same work item (the paper's interleaved packing: F = I, the
-// solve of row i needs only the factor rows it already waited for),
+// solve of row i needs only factor rows it already reads),
 //     x_i = (b_i - sum_{j<i} L_ij x_j) / L_ii.
-// One flag per row covers both kernels: it is published once row i of L and
-// x_i are stored.
 //
 // G lanes per row, lane t owns the t-th off-diagonal entry (rows with more
 // than G off-diagonals are rejected by the caller).  The k-intersections
 // come from inspector-built lists (u, q): u indexes row i, q is the position
-// of L_jk.  Lane t gathers its list into a private LDS row M[t][u] = L_{j_t,k_u};
-// the entries of row i are then resolved in ascending u: the lane owning u
-// divides by its pivot L_jj, the value is broadcast inside the group, and
-// every lane t > u subtracts M[t][u] * L_iu -- the same terms in the same
-// ascending order as the recurrence above.
+// of L_jk.  Lane t gathers its list into a private LDS row M[t][u] =
+// L_{j_t,k_u}; the entries of row i are then resolved in ascending u: the
+// lane owning u divides by its pivot L_jj, the value is broadcast inside the
+// group, every lane t > u with a pair at u subtracts M[t][u] * L_iu, and the
+// row's first lane subtracts L_iu^2 from the pivot and L_iu x_{j_u} from
+// b_i -- every term of the recurrences above, rounded once, in their order.
+// FP64 results therefore equal the sequential definition's bit for bit.
+//
+// Readiness (fused launch): the factor values and x are filled with the
+// pending pattern before the launch and every value is its own flag; a row
+// issues all its loads, then polls whichever came back pending.  The
+// level-set baseline reads them after a grid barrier instead.
+#pragma clang fp contract(off)
+
 #include "dev_common.h"
 
 namespace sf {
 namespace {
 
-using dev::after_wait;
-using dev::group_sum;
+using dev::is_pending;
 using dev::ld_co;
+using dev::poll_value;
+using dev::publishable;
 using dev::st_co;
-using dev::stores_complete;
-using dev::wait_flag;
 
-template <int G, bool FLAGS>
+// Marker of an absent (u, t) pair in the LDS rows: a signalling NaN with a
+// payload no stored factor value can carry (stored values come out of
+// arithmetic, which returns NaNs quiet).
+constexpr unsigned long long kAbsentBits = 0xFFF4000000000001ull;
+constexpr double kAbsent = __builtin_bit_cast(double, kAbsentBits);
+__device__ __forceinline__ bool is_absent(double v) {
+  return __builtin_bit_cast(unsigned long long, v) == kAbsentBits;
+}
+
+template <bool FUSED>
+__device__ __forceinline__ double ready(const double* p, double v, const LaunchState& ls) {
+  if constexpr (FUSED) {
+    if (is_pending(v)) v = poll_value(p, ls);
+  }
+  return v;
+}
+
+template <int G, bool FUSED>
 __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* lds_row) {
   constexpr int RPB = 64 / G;
   const int sub = lane & (G - 1);
@@ -45,58 +68,72 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     const bool mine = act && sub < len;
     const int p = r0 + sub;
     const int j = mine ? a.Lci[p] : 0;
-    double l = 0.0;
-    if (a.factor) {
-      double acc = mine ? a.Aval[p] : 0.0;
-      if constexpr (FLAGS) {
-        if (mine) wait_flag(a.flags + j, a.ls);
-        after_wait();
-      }
-      const double djj = mine ? ld_co(a.Lval + (a.Lrp[j + 1] - 1)) : 1.0;
-      // private LDS row M[t][0..G): the factor entries L_{j_t, k_u}
-      for (int u = 0; u < G; ++u) lds_row[u] = 0.0;
-      if (mine) {
-        const int e0 = a.pair_ptr[p], e1 = a.pair_ptr[p + 1];
-        for (int e = e0; e < e1; ++e) lds_row[a.pair_u[e]] = ld_co(a.Lval + a.pair_q[e]);
-      }
-      // longest row of this batch bounds the sweep (wave-uniform)
-      int maxlen = act ? len : 0;
-      for (int off = 32; off >= 1; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
+    const int pjj = mine ? a.Lrp[j + 1] - 1 : 0;
+    // the pairs of row i are contiguous: every entry's list, in entry order
+    const int e0 = act ? a.pair_ptr[r0] : 0, e1 = act ? a.pair_ptr[rd] : 0;
+    // issue every load of the row before waiting on any of them
+    double acc = mine ? a.Aval[p] : 0.0;
+    double djj = mine ? ld_co(a.Lval + pjj) : 1.0;
+    double xj = (mine && a.solve) ? ld_co(a.X + j) : 0.0;
+    // M[t][u] = L_{j_t, k_u} where row j_t meets row i below column j_t, else absent
+    for (int u = 0; u < G; ++u) lds_row[u] = kAbsent;
+    __builtin_amdgcn_wave_barrier();
+    double* group_rows = lds_row - size_t(sub) * G;  // LDS rows of this row's G lanes
+    for (int eb = e0; eb < e1; eb += G * 4) {
+      int tu[4];
+      double v[4];
 #pragma unroll
-      for (int u = 0; u < G; ++u) {
-        if (u >= maxlen) break;
-        if (sub == u) l = acc / djj;  // entry u is final: every k < j_u was subtracted
-        const double lu = __shfl(l, u, G);
-        if (mine && sub > u) acc -= lds_row[u] * lu;
+      for (int k = 0; k < 4; ++k) {
+        const int e = eb + sub + G * k;
+        tu[k] = e < e1 ? a.pair_u[e] : -1;
+        v[k] = e < e1 ? ld_co(a.Lval + a.pair_q[e]) : 0.0;
       }
-      if (mine) st_co(a.Lval + p, l);
-      const double sq = group_sum<G>(mine ? l * l : 0.0);
-      const double piv = act ? a.Aval[rd] - sq : 1.0;
-      const double lii = sqrt(piv);
-      if (act && sub == 0) {
-        if (!(piv > 0.0))
-          __hip_atomic_fetch_min(a.ls.state + info_off(par), i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        st_co(a.Lval + rd, lii);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (tu[k] < 0) continue;
+        if constexpr (FUSED) {
+          if (is_pending(v[k])) v[k] = poll_value(a.Lval + a.pair_q[eb + sub + G * k], a.ls);
+        }
+        group_rows[size_t(tu[k] >> 16) * G + (tu[k] & 0xffff)] = v[k];
       }
-      if (a.solve) {
-        double s = 0.0;
-        if (mine) s = l * ld_co(a.X + j);
-        s = group_sum<G>(s);
-        if (act && sub == 0) st_co(a.X + i, (a.B[i] - s) / lii);
-      }
-    } else {
-      // solve only, with a factor already in Lval
-      if constexpr (FLAGS) {
-        if (mine) wait_flag(a.flags + j, a.ls);
-        after_wait();
-      }
-      double s = mine ? ld_co(a.Lval + p) * ld_co(a.X + j) : 0.0;
-      s = group_sum<G>(s);
-      if (act && sub == 0) st_co(a.X + i, (a.B[i] - s) / ld_co(a.Lval + rd));
     }
-    if constexpr (FLAGS) {
-      stores_complete();
-      if (act && sub == 0) st_co(a.flags + i, a.ls.epoch);
+    if (mine) {
+      djj = ready<FUSED>(a.Lval + pjj, djj, a.ls);
+      if (a.solve) xj = ready<FUSED>(a.X + j, xj, a.ls);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // longest row of this batch bounds the sweep (wave-uniform)
+    int maxlen = act ? len : 0;
+    for (int off = 32; off >= 1; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
+    double l = 0.0;
+    double d = act ? a.Aval[rd] : 1.0;            // pivot, accumulated on the row's first lane
+    double s = (act && a.solve) ? a.B[i] : 0.0;   // right-hand side, same lane
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (u >= maxlen) break;
+      double pr = 0.0;
+      if (sub == u && mine) {  // entry u is final: every k < j_u has been subtracted
+        l = acc / djj;
+        pr = l * xj;
+      }
+      const double lu = __shfl(l, u, G);
+      const double pu = __shfl(pr, u, G);
+      if (mine && sub > u) {
+        const double m = lds_row[u];
+        if (!is_absent(m)) acc = acc - m * lu;
+      }
+      if (act && sub == 0 && u < len) {
+        d = d - lu * lu;
+        s = s - pu;
+      }
+    }
+    if (mine) st_co(a.Lval + p, publishable(l));
+    if (act && sub == 0) {
+      const double lii = sqrt(d);
+      if (!(d > 0.0))
+        __hip_atomic_fetch_min(a.ls.state + info_off(par), i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_co(a.Lval + rd, publishable(lii));
+      if (a.solve) st_co(a.X + i, publishable(s / lii));
     }
   }
 }
@@ -116,11 +153,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
   const int lane = threadIdx.x & 63;
   double* lds_row = lds + size_t(threadIdx.x) * G;
   dev::reset_next_launch(a.ls);
-  for (;;) {
-    const int t = dev::claim(a.ls, lane);
-    if (t >= a.n_work) break;
+  int t = dev::claim(a.ls, lane);
+  while (t < a.n_work) {
+    const int tn = dev::claim(a.ls, lane);  // prefetched (see k_ts_fused)
     const int it = a.item_list ? a.item_list[t] : t;
     ic0_rows<G, true>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, lds_row);
+    t = tn;
   }
   write_info(a, lane);
 }

@@ -23,159 +23,58 @@
 // contraction is allowed in this file.
 #pragma clang fp contract(off)
 
-#include "dev_common.h"
+#include "stream.h"
 
 namespace sf {
 namespace {
 
-using dev::group_sum;
 using dev::is_pending;
+using dev::kWaves;
 using dev::ld_co;
 using dev::ld_stream;
 using dev::poll_value;
 using dev::publishable;
 using dev::st_co;
-
-constexpr int kRounds = 8;           // entries per lane per pass
-constexpr int kPass = 64 * kRounds;  // entries per pass of one wavefront
-constexpr int kWaves = kBlockThreads / 64;
-
-template <typename T>
-struct WaveLds {
-  int32_t pos[kPass];  // CSR position of each stream entry of the current pass
-  T prod[kPass];       // rounded products of the current pass
-};
-
-// Wait until every x[j[e]] of the wavefront (j[e] < 0: unused slot) is
-// published, updating xv.  Only one lane polls at a time: the first lane
-// with a pending entry watches that entry; when it is published, every lane
-// re-reads all its still-pending entries in one round, and the election
-// repeats.  Dependences of an item come from earlier wavefronts that finish
-// close together, so this converges in a few rounds while keeping the
-// polling traffic of a waiting wavefront at one request instead of one per
-// pending entry.
-template <typename T, int R>
-__device__ __forceinline__ void wait_ready(const T* X, const int (&j)[R], T (&xv)[R], int lane,
-                                           const LaunchState& ls) {
-  for (;;) {
-    int first = -1;
-#pragma unroll
-    for (int e = R - 1; e >= 0; --e)
-      if (j[e] >= 0 && is_pending(xv[e])) first = e;
-    const unsigned long long mask = __ballot(first >= 0);
-    if (mask == 0) return;
-    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
-    if (lane == leader) {
-#pragma unroll
-      for (int e = 0; e < R; ++e)
-        if (e == first) xv[e] = poll_value(X + j[e], ls);
-    }
-    if (dev::ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
-#pragma unroll
-    for (int e = 0; e < R; ++e)
-      if (j[e] >= 0 && is_pending(xv[e])) xv[e] = ld_co(X + j[e]);
-  }
-}
+using dev::stream_accumulate;
+using dev::WaveLds;
 
 // Trace mode (a.trace != nullptr): per item, timestamps of the 100 MHz
 // real-time counter at the start of processing, once the item's indices and
 // values are loaded, once every x it reads is ready, and at the end.
-__device__ __forceinline__ void trace_mark(const TsArgs& a, int it, int k, int lane) {
-  if (a.trace && lane == 0) a.trace[size_t(it) * 4 + k] = __builtin_amdgcn_s_memrealtime();
+__device__ __forceinline__ unsigned long long* trace_slots(const TsArgs& a, int it) {
+  return (a.trace && it >= 0) ? a.trace + size_t(it) * 4 : nullptr;
 }
 
 // Process one item (rows order[q0..q1), q1 - q0 <= 64) of SpTRSV rows
-// (TRSV = true) or SpMV rows.  POLL: wait for x through the readiness
-// protocol (fused executor) or read it directly (level-set baseline, after a
-// grid barrier).  CACHED_X: x was final before this launch started (the
-// unfused SpMV), so it is read through the caches instead of the
-// device-coherent path.
-template <typename T, bool TRSV, bool POLL, bool CACHED_X = false>
+// (TRSV = true) or SpMV rows.  VEC selects how x is read (stream.h): 2 in
+// the fused executor (readiness protocol), 1 in the level-set baseline
+// (after a grid barrier), 0 in the unfused SpMV (x final before the launch).
+template <typename T, bool TRSV, int VEC>
 __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
                                             int it = -1) {
   const int nr = q1 - q0;
   const bool mine = lane < nr;
   const int32_t* __restrict__ rp = TRSV ? a.Lrp : a.Arp;
-  const int32_t* __restrict__ ci = TRSV ? a.Lci : a.Aci;
   const T* __restrict__ val = static_cast<const T*>(TRSV ? a.Lv : a.Av);
   T* X = static_cast<T*>(a.X);
+  unsigned long long* tr = trace_slots(a, it);
+  if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
   const int id = mine ? a.order[q0 + lane] : 0;
   const int row = TRSV ? id : id - a.n;
   const int r0 = mine ? rp[row] : 0;
   const int r1 = mine ? rp[row + 1] - (TRSV ? 1 : 0) : 0;  // SpTRSV: stop before the diagonal
-  const int len = r1 - r0;
   T acc = T(0), dii = T(1);
   if (TRSV && mine) {
     acc = static_cast<const T*>(a.B)[row];
     dii = ld_stream(val + r1);
   }
-  // exclusive prefix sum of the row lengths over the item's row slots
-  int incl = len;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  const int off = incl - len;
-  const int total = __shfl(incl, 63, 64);
-  for (int base = 0; base < total; base += kPass) {
-    // each row's lane lays its entries' CSR positions into this pass's window
-    if (mine) {
-      const int lo = max(off, base), hi = min(off + len, base + kPass);
-      for (int t = lo; t < hi; ++t) w.pos[t - base] = r0 + (t - off);
-    }
-    __builtin_amdgcn_wave_barrier();
-    int j[kRounds];
-    T v[kRounds], xv[kRounds];
-#pragma unroll
-    for (int e = 0; e < kRounds; ++e) {
-      const int k = base + lane + 64 * e;
-      j[e] = -1;
-      v[e] = T(0);
-      if (k < total) {
-        const int p = w.pos[k - base];
-        j[e] = ld_stream(ci + p);
-        v[e] = ld_stream(val + p);
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? (CACHED_X ? X[j[e]] : ld_co(X + j[e])) : T(0);
-    if (it >= 0) trace_mark(a, it, 1, lane);
-    if constexpr (POLL) wait_ready<T, kRounds>(X, j, xv, lane, a.ls);
-#pragma unroll
-    for (int e = 0; e < kRounds; ++e) {
-      const int k = base + lane + 64 * e;
-      if (k < total) w.prod[k - base] = v[e] * xv[e];
-    }
-    if (it >= 0) trace_mark(a, it, 2, lane);
-    __builtin_amdgcn_wave_barrier();
-    if (mine) {
-      // ascending order, one rounding per term; LDS reads issued 8 ahead
-      const int lo = max(off, base) - base;
-      const int hi = min(off + len, base + kPass) - base;
-      int t = lo;
-      for (; t + 8 <= hi; t += 8) {
-        T pr[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) pr[u] = w.prod[t + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if constexpr (TRSV) acc = acc - pr[u];
-          else acc = acc + pr[u];
-        }
-      }
-      for (; t < hi; ++t) {
-        if constexpr (TRSV) acc = acc - w.prod[t];
-        else acc = acc + w.prod[t];
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
+  acc = stream_accumulate<T, TRSV, VEC, false>(nr, r0, r1 - r0, acc, TRSV ? a.Lci : a.Aci, nullptr, val, X,
+                                               lane, w, a.ls, tr);
   if (mine) {
     if constexpr (TRSV) st_co(X + row, publishable(acc / dii));
     else __builtin_nontemporal_store(acc, static_cast<T*>(a.Y) + row);
   }
-  if (it >= 0) trace_mark(a, it, 3, lane);
+  if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
 // The next ticket is claimed before the current item is processed, so the
@@ -193,9 +92,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
     const int tn = dev::claim(a.ls, lane);
     const int it = a.item_list ? a.item_list[t] : t;
     const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-    trace_mark(a, it, 0, lane);
-    if (a.order[q0] < a.n) item_stream<T, true, true>(a, q0, q1, lane, w, it);
-    else item_stream<T, false, true>(a, q0, q1, lane, w, it);
+    if (a.order[q0] < a.n) item_stream<T, true, 2>(a, q0, q1, lane, w, it);
+    else item_stream<T, false, 2>(a, q0, q1, lane, w, it);
     t = tn;
   }
 }
@@ -335,7 +233,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_trsv_levelset(LevelArgs la) {
     for (int t = t0 + wave; t < t1; t += nwaves) {
       const int it = a.item_list[t];
       const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-      if (a.nrhs == 1) item_stream<T, true, false>(a, q0, q1, lane, w);
+      if (a.nrhs == 1) item_stream<T, true, 1>(a, q0, q1, lane, w);
       else for (int blk = 0; blk < a.nblk; ++blk) trsv_rows_multi<T, 8, false>(a, q0, q1, blk, lane);
     }
     if (lv + 1 < la.depth) dev::grid_barrier(a.ls, gen);
@@ -352,7 +250,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_spmv_items(TsArgs a) {
   const int nwaves = int(gridDim.x) * kWaves;
   for (int t = wave; t < a.n_work; t += nwaves) {
     const int it = a.item_list[t];
-    item_stream<T, false, false, true>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, w);
+    item_stream<T, false, 0>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, w);
   }
 }
 

@@ -88,8 +88,9 @@ struct sf_schedule_s {
   int32_t back_depth = 0;
 
   // SpIC0 intersection lists, one list per stored L entry (i, j), j < i:
-  // pairs (u, q): u = index inside row i of a column k in both rows with
-  // k < j, q = position of L_jk.
+  // pairs (t << 16 | u, q): t = index inside row i of the entry (i, j), u =
+  // index inside row i of a column k in both rows with k < j, q = position
+  // of L_jk.  The lists of a row's entries are contiguous, in entry order.
   std::vector<int32_t> pair_ptr, pair_u, pair_q;
 
   // Executor parameters.

@@ -1,0 +1,140 @@
+// Row-sum building block shared by the forward and adjoint executors.
+//
+// A work item holds up to 64 independent rows; row slot s (lane s) owns the
+// CSR range [r0, r0 + len).  stream_accumulate computes, for every row slot,
+//     acc_s  (-|+)=  val[p] * vec[col[p]]   for p = r0 .. r0 + len - 1
+// one rounded product at a time in ascending p, which is exactly the
+// sequential definition's arithmetic.  The entries of all rows are
+// concatenated and dealt to the 64 lanes, kRounds per lane, so one round of
+// independent loads fetches every index, value and vec element of the item;
+// products go through LDS and each row's lane folds its own.  vec may be
+// read through the value-as-flag readiness protocol (dev_common.h).
+// Every file that includes this header must keep multiply-add contraction
+// off so the products are rounded as written.
+#pragma once
+
+#include "dev_common.h"
+
+namespace sf {
+namespace dev {
+
+constexpr int kRounds = 8;           // entries per lane per pass
+constexpr int kPass = 64 * kRounds;  // entries per pass of one wavefront
+constexpr int kWaves = kBlockThreads / 64;
+
+template <typename T>
+struct WaveLds {
+  int32_t pos[kPass];  // CSR position of each stream entry of the current pass
+  T prod[kPass];       // rounded products of the current pass
+};
+
+// Wait until every vec[j[e]] of the wavefront (j[e] < 0: unused slot) is
+// published, updating xv.  Only one lane polls at a time: the first lane
+// with a pending entry watches that entry; when it is published, every lane
+// re-reads all its still-pending entries in one round, and the election
+// repeats.  Dependences of an item come from earlier wavefronts that finish
+// close together, so this converges in a few rounds while keeping the
+// polling traffic of a waiting wavefront at one request instead of one per
+// pending entry.
+template <typename T, int R>
+__device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&xv)[R], int lane,
+                                           const LaunchState& ls) {
+  for (;;) {
+    int first = -1;
+#pragma unroll
+    for (int e = R - 1; e >= 0; --e)
+      if (j[e] >= 0 && is_pending(xv[e])) first = e;
+    const unsigned long long mask = __ballot(first >= 0);
+    if (mask == 0) return;
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    if (lane == leader) {
+      int jf = 0;  // select the watched index first so the poll loop is emitted once
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (e == first) jf = j[e];
+      const T got = poll_value(vec + jf, ls);
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (e == first) xv[e] = got;
+    }
+    if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (j[e] >= 0 && is_pending(xv[e])) xv[e] = ld_co(vec + j[e]);
+  }
+}
+
+// VEC: 0 = vec final and read through the caches, 1 = vec final but written
+// in this launch by another kernel phase (device-coherent read), 2 = vec
+// produced concurrently (device-coherent read + readiness protocol).
+// MAPPED: the value of entry p is val[map[p]] (a transposed view).
+// trace: optional per-item timestamp slots (see the trace mode of k_ts.hip).
+// Returns the row slot's accumulator (meaningful on lanes < nr).
+template <typename T, bool SUB, int VEC, bool MAPPED>
+__device__ __forceinline__ T stream_accumulate(int nr, int r0, int len, T acc, const int32_t* __restrict__ col,
+                                               const int32_t* __restrict__ map, const T* __restrict__ val,
+                                               const T* vec, int lane, WaveLds<T>& w, const LaunchState& ls,
+                                               unsigned long long* trace = nullptr) {
+  const bool mine = lane < nr;
+  if (!mine) len = 0;
+  // exclusive prefix sum of the row lengths over the item's row slots
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  for (int base = 0; base < total; base += kPass) {
+    // each row's lane lays its entries' CSR positions into this pass's window
+    if (mine) {
+      const int lo = max(off, base), hi = min(off + len, base + kPass);
+      for (int t = lo; t < hi; ++t) w.pos[t - base] = r0 + (t - off);
+    }
+    __builtin_amdgcn_wave_barrier();
+    int j[kRounds];
+    T v[kRounds], xv[kRounds];
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      j[e] = -1;
+      v[e] = T(0);
+      if (k < total) {
+        const int p = w.pos[k - base];
+        j[e] = ld_stream(col + p);
+        v[e] = MAPPED ? val[ld_stream(map + p)] : ld_stream(val + p);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? (VEC == 0 ? vec[j[e]] : ld_co(vec + j[e])) : T(0);
+    if (trace && lane == 0) trace[1] = __builtin_amdgcn_s_memrealtime();  // loads issued
+    if constexpr (VEC == 2) wait_ready<T, kRounds>(vec, j, xv, lane, ls);
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      if (k < total) w.prod[k - base] = v[e] * xv[e];
+    }
+    if (trace && lane == 0) trace[2] = __builtin_amdgcn_s_memrealtime();  // inputs ready
+    __builtin_amdgcn_wave_barrier();
+    if (mine) {
+      // ascending order, one rounding per term; LDS reads issued 8 ahead
+      const int lo = max(off, base) - base;
+      const int hi = min(off + len, base + kPass) - base;
+      int t = lo;
+      for (; t + 8 <= hi; t += 8) {
+        T pr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pr[u] = w.prod[t + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = SUB ? acc - pr[u] : acc + pr[u];
+      }
+      for (; t < hi; ++t) acc = SUB ? acc - w.prod[t] : acc + w.prod[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return acc;
+}
+
+}  // namespace dev
+}  // namespace sf

@@ -43,6 +43,8 @@ def test_lap2d5_16(orc):
     _, gbr, glr = oracle_grads(orc, L, A, b, w)
     gb, gl = gpu_grads(s, L, A, b, w)
     assert relerr(gb, gbr) <= TOL64 and relerr(gl, glr) <= TOL64
+    # the adjoint runs the definition's terms in its order: equal bit for bit
+    assert np.array_equal(gb, gbr) and np.array_equal(gl, glr)
     gb2, gl2 = gpu_grads(s, L, A, b, w, recompute=True)
     assert np.array_equal(gb, gb2) and np.array_equal(gl, gl2)
 
@@ -94,6 +96,7 @@ def test_s5_lap3d7_96(orc):
     gb, gl = gpu_grads(s, L, A, b, w)
     print("96^3 FP64 grad errors: b %.2e L %.2e" % (relerr(gb, gbr), relerr(gl, glr)))
     assert relerr(gb, gbr) <= TOL64 and relerr(gl, glr) <= TOL64
+    assert np.array_equal(gb, gbr) and np.array_equal(gl, glr)
     gb32, gl32 = gpu_grads(s, L, A, b, w, dtype=torch.float32)
     print("96^3 FP32 grad errors vs FP64 oracle: b %.2e L %.2e" % (relerr(gb32, gbr), relerr(gl32, glr)))
     assert relerr(gb32, gbr) < 1e-4 and relerr(gl32, glr) < 1e-4

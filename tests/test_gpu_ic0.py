@@ -44,6 +44,11 @@ def test_27pt_12cube(orc, perm):
     lu, xu, infou = run_ic0(s, Lp, b, unfused=True)
     assert infou == -1
     assert relerr(lu, lr) <= TOL64 and relerr(xu, xr) <= TOL64
+    # every term of the recurrences, rounded once, in the oracle's order
+    nd = int(np.sum(l != lr)), int(np.sum(x != xr))
+    print("27pt perm=%s values differing from the oracle: L %d x %d" % (perm, nd[0], nd[1]))
+    assert np.array_equal(l, lr) and np.array_equal(x, xr)
+    assert np.array_equal(lu, lr) and np.array_equal(xu, xr)
 
 
 def test_tridiagonal_closed_form():
