@@ -258,6 +258,7 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                                    "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
                                    "inspect_s": round(s.info().inspect_seconds, 3)}
         log("ic0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
+    out.update(run_batched(args, sfm, synth, torch, dev, time_it))
     L, A = synth.workload("lap3d7_96")
     s = sfm.Schedule(L, A, want_backward=True)
     for dt, tname, vb in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
@@ -278,6 +279,55 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                                              "bytes": nb, "back_depth": s.info().back_depth}
         log("fwd+bwd 96^3 %s %.3f ms" % (tname, t))
     sfm.sync_status(s)
+    return out
+
+
+REFINE_SAMPLES = {}  # (matrix, k) -> (L, A, B, X, Y) host copies for the oracle check
+
+
+def refine_pass_bytes(n, m, nnz_l, nnz_a, k):
+    """Algorithmic bytes of one FP32 fused SpTRSV -> SpMV pass over k RHS."""
+    return nnz_l * 8 + nnz_a * 8 + (n + 1) * 4 + (m + 1) * 4 + 3 * n * k * 4
+
+
+def run_batched(args, sfm, synth, torch, dev, time_it):
+    """Batched right-hand sides with FP32 solves and FP64 refinement (2
+    corrections), against the FP64 fused and unfused executors on the same
+    k right-hand sides, for the random SPD matrix and the 2D 9-point
+    Laplacian on a 2048^2 grid."""
+    import numpy as np
+    out = {}
+    for name in ("randspd_1m", "lap2d9_2048"):
+        L, A = synth.workload(name)
+        s = sfm.Schedule(L, A)
+        L64 = torch.as_tensor(L.val, device=dev)
+        A64 = torch.as_tensor(A.val, device=dev)
+        L32 = L64.float()
+        A32 = A64.float()
+        for k in (1, 8, 32, 64):
+            b = synth.vec_uniform(L.nrows, k=k, seed=1)
+            B = torch.as_tensor(np.ascontiguousarray(b.T), device=dev).t() if k > 1 else torch.as_tensor(b, device=dev)
+            B32 = B.float() if k == 1 else torch.as_tensor(np.ascontiguousarray(b.T), dtype=torch.float32, device=dev).t()
+            res = {}
+            reps = 3 if name == "lap2d9_2048" else 5
+            t_ref = time_it(lambda: sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=2), reps)
+            X, Y, rel = sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=2)
+            t_f32 = time_it(lambda: sfm.trsv_spmv(s, L32, A32, B32), reps)
+            t_f64 = time_it(lambda: sfm.trsv_spmv(s, L64, A64, B), reps)
+            t_u64 = time_it(lambda: sfm.trsv_spmv(s, L64, A64, B, unfused=True), max(1, reps // 2))
+            nb = refine_pass_bytes(L.nrows, A.nrows, L.nnz, A.nnz, k)
+            res = {"k": k, "refined_ms": round(t_ref, 3), "fp32_pass_ms": round(t_f32, 3),
+                   "fp32_pass_GBps": round(nb / (t_f32 * 1e-3) / 1e9, 1),
+                   "fp64_fused_ms": round(t_f64, 3), "fp64_unfused_ms": round(t_u64, 3),
+                   "refined_relres_max": float(rel.max()),
+                   "refined_vs_fp64_unfused_speedup": round(t_u64 / t_ref, 3)}
+            out["batched_%s_k%d" % (name, k)] = res
+            if k in (1, 8):
+                REFINE_SAMPLES[(name, k)] = (L, A, b, X.cpu().numpy(), Y.cpu().numpy())
+            log("batched %s k=%d: refine %.3f ms, fp32 pass %.3f ms, fp64 fused %.3f, unfused %.3f" % (
+                name, k, t_ref, t_f32, t_f64, t_u64))
+        del L64, A64, L32, A32
+        torch.cuda.empty_cache()
     return out
 
 
@@ -304,6 +354,18 @@ def cpu_baseline(args, work, xs, ys, per_matrix):
         per_matrix[d["name"]]["x_rel_err_vs_oracle"] = ex
         per_matrix[d["name"]]["y_rel_err_vs_oracle"] = ey
         per_matrix[d["name"]]["oracle_ms"] = round(dt * 1e3, 2)
+    # refined batched results against the FP64 oracle, column by column
+    for (name, k), (L, A, b, X, Y) in REFINE_SAMPLES.items():
+        bb = b if b.ndim == 2 else b[:, None]
+        XX = X if X.ndim == 2 else X[:, None]
+        YY = Y if Y.ndim == 2 else Y[:, None]
+        ex = ey = 0.0
+        for c in range(bb.shape[1]):
+            x = oracle.trsv_lower(L.rowptr, L.col, L.val, bb[:, c])
+            y = oracle.spmv(A.rowptr, A.col, A.val, x)
+            ex = max(ex, float(np.abs(XX[:, c] - x).max() / np.abs(x).max()))
+            ey = max(ey, float(np.abs(YY[:, c] - y).max() / np.abs(y).max()))
+        errs["refined_%s_k%d" % (name, k)] = {"x_rel_err": ex, "y_rel_err": ey}
     # repeat whole passes until the time budget is used
     while total_s < args.cpu_seconds:
         for d in work:

@@ -22,20 +22,24 @@ __device__ __forceinline__ double xval(const ResArgs& a, size_t k) {
   return v;
 }
 
-// Non-negative doubles order like their bit patterns.
-__device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) {
-  __hip_atomic_fetch_max(p, (unsigned long long)__double_as_longlong(fabs(v)), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-}
+// Maxima of |r| and |b| are kept as bit patterns: non-negative doubles
+// order like their bit patterns.
 
+// The final pass keeps the per-column maxima of a block in LDS and issues one
+// device atomic per column and block at the end (64 right-hand sides max).
 template <bool FINAL>
 __global__ __launch_bounds__(kBlockThreads) void k_resid(ResArgs a) {
   constexpr int RPB = 64 / kG;
+  __shared__ unsigned long long smax[FINAL ? 2 * 64 : 1];
   const int lane = threadIdx.x & 63;
   const int sub = lane & (kG - 1);
   const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
   const int rows = FINAL ? max(a.n, a.m) : a.n;
+  if (FINAL) {
+    for (int k = threadIdx.x; k < 2 * 64; k += kBlockThreads) smax[k] = 0ull;
+    __syncthreads();
+  }
   for (int base = wave * RPB; base < rows; base += nwaves * RPB) {
     const int i = base + lane / kG;
     for (int c = 0; c < a.nrhs; ++c) {
@@ -60,12 +64,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_resid(ResArgs a) {
           for (int p = a.Arp[i] + sub; p < a.Arp[i + 1]; p += kG) y += a.A64[p] * xval(a, off + a.Aci[p]);
         y = group_sum<kG>(y);
         if (i < a.m && sub == 0) a.Y[size_t(i) + size_t(c) * a.ldy] = y;
-        if (i < a.n && sub == 0 && a.maxabs) {
-          atomic_max_abs(a.maxabs + 2 * c, rmax);
-          atomic_max_abs(a.maxabs + 2 * c + 1, bmax);
+        if (i < a.n && sub == 0) {
+          atomicMax(&smax[2 * c], (unsigned long long)__double_as_longlong(fabs(rmax)));
+          atomicMax(&smax[2 * c + 1], (unsigned long long)__double_as_longlong(fabs(bmax)));
         }
       }
     }
+  }
+  if (FINAL) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < 2 * a.nrhs; k += kBlockThreads)
+      if (a.maxabs && smax[k] != 0ull)
+        __hip_atomic_fetch_max(a.maxabs + k, smax[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -97,7 +107,9 @@ hipError_t launch_residual(const ResArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_final(const ResArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_resid<true>), dim3(grid_for(a.n > a.m ? a.n : a.m)), dim3(kBlockThreads), 0, st, a);
+  int grid = grid_for(a.n > a.m ? a.n : a.m);
+  grid = grid > 2048 ? 2048 : grid;  // bounds the number of per-block maxima atomics
+  hipLaunchKernelGGL((k_resid<true>), dim3(grid), dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
 }
 
