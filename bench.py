@@ -27,8 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_ts_fused.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_12238_amd", "csrc", f) for f in ("k_ts.hip", "dev_common.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ts_fused_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_12238_amd", "csrc", f)
+                  for f in ("k_ts.hip", "stream.h", "dev_common.h", "kargs.h", "schedule.h", "inspect.cpp")]
 
 
 def log(msg):
@@ -61,16 +62,25 @@ def sources_sha():
 
 
 def load_traffic(kernel_bytes_key):
-    """Measured HBM bytes per launch from the committed rocprofv3 --pmc
-    summary, or None when the kernel sources changed since it was taken."""
+    """Measured bytes per launch beyond L2 (rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE, calibrated on a copy kernel) from the committed summary, or
+    None when the kernel or inspector sources changed since it was taken.
+    The summary holds "key: value" lines."""
+    t = {}
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            for line in f:
+                if ":" in line and not line.startswith((" ", "#", "|")):
+                    k, v = line.split(":", 1)
+                    t[k.strip()] = v.strip()
+    except OSError:
         return None
-    if t.get("sources_sha") != sources_sha():
+    if t.get("sources_sha") != sources_sha() or kernel_bytes_key not in t:
         return None
-    return t.get(kernel_bytes_key)
+    try:
+        return int(float(t[kernel_bytes_key]))
+    except ValueError:
+        return None
 
 
 def main():

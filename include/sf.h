@@ -34,7 +34,7 @@
  *     sf_exec_ic0_trsv); a spin watchdog that fires is reported by
  *     sf_sync_status.
  *   - A schedule is immutable after sf_inspect except for the small device
- *     state it owns (readiness flags, claim counters); executions of one
+ *     state it owns (claim counters, workspaces); executions of one
  *     schedule must therefore not overlap (issue them on one stream, or
  *     synchronise between streams).
  *   - NaN and Inf in values propagate and are not checked.  A diagonal
@@ -87,8 +87,9 @@ typedef struct sf_schedule_s* sf_schedule;
 typedef struct {
   int32_t kind;           /* sf_kind */
   int32_t rows_per_item;  /* maximum rows in one work item (default: from lanes_per_row) */
-  int32_t max_item_nnz;   /* nonzero budget of one work item, the paper's cost c(v) = nonzeros
-                             touched (Sec. 3.1); default 4096 */
+  int32_t max_item_nnz;   /* cost budget of one work item, summing the paper's vertex
+                             cost c(v) (Sec. 3.1) = max(1, off-diagonals of the row);
+                             default 512 */
   int32_t rhs_block;      /* right-hand sides walked together per DAG pass (default: autotuned
                              / all) */
   int32_t lanes_per_row;  /* lanes of a 64-wide wavefront cooperating on one SpTRSV row
@@ -96,7 +97,11 @@ typedef struct {
   int32_t want_backward;  /* 1: also build the transposed (upper-solve) schedule for sf_backward */
   int32_t validate;       /* 1: check the built schedule against every DAG edge before returning */
   int32_t no_fusion;      /* 1: executor calls run the unfused two-phase baseline instead (the
-                             paper's fusion = False switch, Sec. 2.4) */
+                             paper's fusion = False switch, Sec. 2.3) */
+  int32_t coarsen;        /* work items of the one-right-hand-side fused SpTRSV -> SpMV
+                             executor: 0 = choose by the inspector's critical-path estimate,
+                             1 = one wavefront per item, 2 = coarsened items spanning several
+                             wavefronts (the paper's w-partitions of an s-partition, Sec. 3.2) */
 } sf_inspect_opts;
 
 /* Summary of a schedule (host values). */
@@ -115,6 +120,12 @@ typedef struct {
   int32_t lanes_per_spmv;  /* lanes per SpMV row in effect */
   double reuse_ratio;      /* Sec. 2.2: common / max(per-kernel) accesses */
   double inspect_seconds;  /* host time spent in sf_inspect */
+  int32_t coarsened;       /* 1: the one-right-hand-side fused executor runs coarsened items */
+  int32_t chunk_items;     /* SpTRSV items of the coarsened plan (0 if none was built) */
+  int32_t chunk_chain;     /* longest chain of dependent coarsened items */
+  int32_t max_local_depth; /* most wavefronts spanned by one coarsened item */
+  double est_level_us;     /* critical-path estimates (microseconds) the inspector compares: */
+  double est_chunk_us;     /*   one wavefront per item vs coarsened items */
 } sf_schedule_stats;
 
 /*
@@ -129,7 +140,9 @@ typedef struct {
  * row r depends on every x_j it reads; for SpIC0 -> SpTRSV, F = I.
  * Levels, the joint order (joint level, SpTRSV before SpMV, row) and the
  * work items (runs of one level and one kind, at most rows_per_item rows
- * and max_item_nnz nonzeros) are computed here.
+ * and max_item_nnz cost) are computed here, and for SF_TRSV_SPMV also the
+ * coarsened plan (opts.coarsen): SpTRSV items that span several wavefronts,
+ * cut from one topological order so the item graph stays acyclic.
  * Errors: SF_ERR_ARG, SF_ERR_CSR, SF_ERR_NOT_LOWER, SF_ERR_ZERO_DIAG,
  * SF_ERR_SHAPE, SF_ERR_OOM.  On error *out is set to NULL.
  */
@@ -144,7 +157,9 @@ sf_status sf_schedule_free(sf_schedule s);
 sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st);
 
 /*
- * Copy the schedule to host arrays (for validation against the DAG):
+ * Copy the schedule to host arrays (for validation against the DAG).  The
+ * plan exported is the one the one-right-hand-side fused executor runs
+ * (coarsened items when sf_schedule_stats.coarsened is 1):
  *   level[n]       wavefront of each SpTRSV row;
  *   order[n + m]   iteration ids in claim order.  SF_TRSV_SPMV: SpTRSV row i
  *                  is id i, SpMV row r is id n + r.  SF_IC0_TRSV: SpIC0 row
@@ -153,6 +168,19 @@ sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st);
  * Any pointer may be NULL to skip that array.
  */
 sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int32_t* item_ptr);
+
+/*
+ * Item-local structure of the exported plan (Sec. 3.2: a w-partition runs
+ * its vertices in dependence order on one worker):
+ *   local_level[n + m]  wavefront of each claim position inside its item
+ *                       (2n positions for SF_IC0_TRSV); all 0 when items
+ *                       hold one wavefront;
+ *   entry_slot[nnz(L)]  per stored L entry (i, j), j < i: the position of
+ *                       row j inside row i's item when both share an item,
+ *                       else 0xFF (also for the diagonal).
+ * Rows of an item are sorted by local_level.  NULL skips an array.
+ */
+sf_status sf_schedule_export_local(sf_schedule s, uint8_t* local_level, uint8_t* entry_slot);
 
 /* Backward (transposed-solve) schedule: rlevel[n], order[n] (rows),
  * item_ptr[n_back_items + 1].  SF_ERR_ARG if it was not built. */
@@ -197,7 +225,7 @@ sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L
  *     L_ij = (A_ij - sum_{k<j, k in P_i and P_j} L_ik L_jk) / L_jj,
  *     L_ii = sqrt(A_ii - sum_{k<i} L_ik^2),
  * and in the same work item x_i = (b_i - sum_{j<i} L_ij x_j) / L_ii (the
- * interleaved packing of Sec. 3.3: reuse ratio >= 1).
+ * interleaved packing of Sec. 3.2, step 3: reuse ratio >= 1).
  *   A_lower_val: device, values of lower(A) in the inspected pattern.
  *   L_val:       device output, same pattern.
  *   B, X:        device n x nrhs (nrhs == 1 in this build).

@@ -54,7 +54,7 @@ class CsrPattern(ctypes.Structure):
 class InspectOpts(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in
                 ("kind", "rows_per_item", "max_item_nnz", "rhs_block", "lanes_per_row",
-                 "want_backward", "validate", "no_fusion")]
+                 "want_backward", "validate", "no_fusion", "coarsen")]
 
 
 class ScheduleStats(ctypes.Structure):
@@ -63,7 +63,10 @@ class ScheduleStats(ctypes.Structure):
                 ("back_depth", ctypes.c_int32), ("n_items", ctypes.c_int32),
                 ("n_back_items", ctypes.c_int32), ("max_level_width", ctypes.c_int32),
                 ("lanes_per_row", ctypes.c_int32), ("lanes_per_spmv", ctypes.c_int32),
-                ("reuse_ratio", ctypes.c_double), ("inspect_seconds", ctypes.c_double)]
+                ("reuse_ratio", ctypes.c_double), ("inspect_seconds", ctypes.c_double),
+                ("coarsened", ctypes.c_int32), ("chunk_items", ctypes.c_int32),
+                ("chunk_chain", ctypes.c_int32), ("max_local_depth", ctypes.c_int32),
+                ("est_level_us", ctypes.c_double), ("est_chunk_us", ctypes.c_double)]
 
 
 _LIB = None
@@ -75,6 +78,7 @@ _SIGS = {
     "sf_schedule_free": [_P],
     "sf_schedule_info": [_P, ctypes.POINTER(ScheduleStats)],
     "sf_schedule_export": [_P, _P, _P, _P],
+    "sf_schedule_export_local": [_P, _P, _P],
     "sf_schedule_export_backward": [_P, _P, _P, _P],
     "sf_exec_trsv_spmv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P],
     "sf_exec_unfused_trsv_spmv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P],
@@ -141,7 +145,8 @@ class Schedule:
     """Host-built schedule (``sf_inspect``); lives until ``free()`` or GC."""
 
     def __init__(self, L, A=None, kind: int = SF_TRSV_SPMV, *, rows_per_item=0, max_item_nnz=0,
-                 rhs_block=0, lanes_per_row=0, want_backward=False, validate=False, no_fusion=False):
+                 rhs_block=0, lanes_per_row=0, want_backward=False, validate=False, no_fusion=False,
+                 coarsen=0):
         lib = _lib()
         lrp, lci, lnc = _csr_parts(L)
         pl, keep_l = _pattern(lrp, lci, lnc)
@@ -152,7 +157,7 @@ class Schedule:
             pa, keep_a = _pattern(arp, aci, anc)
             pa_ptr = ctypes.byref(pa)
         opts = InspectOpts(kind, rows_per_item, max_item_nnz, rhs_block, lanes_per_row,
-                           int(want_backward), int(validate), int(no_fusion))
+                           int(want_backward), int(validate), int(no_fusion), int(coarsen))
         h = _P()
         _check(lib.sf_inspect(ctypes.byref(pl), pa_ptr, ctypes.byref(opts), ctypes.byref(h)), "sf_inspect")
         del keep_l, keep_a
@@ -184,6 +189,19 @@ class Schedule:
         _check(_lib().sf_schedule_export(self.handle, level.ctypes.data, order.ctypes.data,
                                          item_ptr.ctypes.data), "sf_schedule_export")
         return level[:n], order[:nids], item_ptr
+
+    def export_local(self):
+        """(local_level[ids], entry_slot[nnz(L)]) of the exported plan: each
+        claim position's wavefront inside its item, and per stored L entry the
+        slot of its column in the row's item (255: another item)."""
+        st = self.info()
+        n = int(st.n)
+        nids = n + int(st.m) if self.kind == SF_TRSV_SPMV else 2 * n
+        loc = np.empty(max(nids, 1), np.uint8)
+        slot = np.empty(max(int(st.nnz_l), 1), np.uint8)
+        _check(_lib().sf_schedule_export_local(self.handle, loc.ctypes.data, slot.ctypes.data),
+               "sf_schedule_export_local")
+        return loc[:nids], slot[:int(st.nnz_l)]
 
     def export_backward(self):
         st = self.info()

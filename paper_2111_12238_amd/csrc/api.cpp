@@ -40,13 +40,20 @@ int device_cus() {
 // Sub-allocator over one hipMalloc'ed block: arrays are placed at 256-byte
 // aligned offsets.
 struct Packer {
+  struct Item {
+    size_t at;
+    const void* data;
+    size_t bytes;
+  };
   size_t off = 0;
-  std::vector<std::pair<size_t, const std::vector<int32_t>*>> items;
-  size_t add(const std::vector<int32_t>* v) {
+  std::vector<Item> items;
+  template <typename E>
+  size_t add(const std::vector<E>* v) {
     const size_t at = off;
-    items.emplace_back(at, v);
-    off += (v->size() * sizeof(int32_t) + 255) / 256 * 256;
-    if (v->empty()) off += 256;
+    const size_t bytes = v->size() * sizeof(E);
+    items.push_back({at, v->data(), bytes});
+    off += (bytes + 255) / 256 * 256;
+    if (bytes == 0) off += 256;
     return at;
   }
 };
@@ -60,7 +67,6 @@ void free_device(sf_schedule_s* s) {
     hipDeviceSynchronize();
     if (d.block) hipFree(d.block);
     if (d.state) hipFree(d.state);
-    if (d.flags) hipFree(d.flags);
     if (d.xi) hipFree(d.xi);
     hipSetDevice(cur);
   }
@@ -86,13 +92,14 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oATrp = pk.add(&s->AT.rp), oATci = pk.add(&s->AT.ci), oATm = pk.add(&s->AT_map);
   const size_t oBo = pk.add(&s->border), oBip = pk.add(&s->bitem_ptr);
   const size_t oPp = pk.add(&s->pair_ptr), oPu = pk.add(&s->pair_u), oPq = pk.add(&s->pair_q);
+  const size_t oCo = pk.add(&s->corder), oCip = pk.add(&s->citem_ptr), oCti = pk.add(&s->ctrsv_items);
+  const size_t oCl = pk.add(&s->clloc), oCe = pk.add(&s->celoc);
   void* block = nullptr;
   SF_HIP(hipMalloc(&block, pk.off));
   char* b = static_cast<char*>(block);
   for (auto& it : pk.items)
-    if (!it.second->empty())
-      if (hipMemcpyAsync(b + it.first, it.second->data(), it.second->size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice, st) != hipSuccess) {
+    if (it.bytes)
+      if (hipMemcpyAsync(b + it.at, it.data, it.bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
         hipFree(block);
         return SF_ERR_HIP;
       }
@@ -106,35 +113,18 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.ATrp = P(oATrp); d.ATci = P(oATci); d.ATmap = P(oATm);
   d.border = P(oBo); d.bitem_ptr = P(oBip);
   d.pair_ptr = P(oPp); d.pair_u = P(oPu); d.pair_q = P(oPq);
+  d.corder = P(oCo); d.citem_ptr = P(oCip); d.ctrsv_items = P(oCti);
+  d.clloc = reinterpret_cast<uint8_t*>(b + oCl);
+  d.celoc = reinterpret_cast<uint8_t*>(b + oCe);
   if (!d.state) {
     std::vector<int32_t> init(kStateWords, 0);
     for (int p = 0; p < 2; ++p) init[info_off(p)] = kInfoNone;
     SF_HIP(hipMalloc(&d.state, kStateWords * sizeof(int32_t)));
     SF_HIP(hipMemcpy(d.state, init.data(), kStateWords * sizeof(int32_t), hipMemcpyHostToDevice));
   }
-  if (!d.flags) {
-    const size_t bytes = std::max<int64_t>(s->n, 1) * sizeof(int32_t);
-    SF_HIP(hipMalloc(&d.flags, bytes));
-    SF_HIP(hipMemsetAsync(d.flags, 0, bytes, st));
-    d.flag_blocks = 1;
-    d.epoch = 0;
-  }
   SF_HIP(hipStreamSynchronize(st));  // host vectors may change after a re-cut
   d.device = cur;
   d.ready = true;
-  return SF_OK;
-}
-
-sf_status ensure_flags(sf_schedule_s* s, int64_t blocks, hipStream_t st) {
-  DeviceBuffers& d = s->dev;
-  if (d.flag_blocks >= blocks) return SF_OK;
-  SF_HIP(hipStreamSynchronize(st));
-  if (d.flags) SF_HIP(hipFree(d.flags));
-  d.flags = nullptr;
-  const size_t bytes = size_t(std::max<int64_t>(s->n, 1)) * size_t(blocks) * sizeof(int32_t);
-  SF_HIP(hipMalloc(&d.flags, bytes));
-  SF_HIP(hipMemsetAsync(d.flags, 0, bytes, st));
-  d.flag_blocks = blocks;
   return SF_OK;
 }
 
@@ -150,16 +140,13 @@ sf_status ensure_xi(sf_schedule_s* s, size_t bytes, hipStream_t st) {
   return SF_OK;
 }
 
-// Next launch epoch.  Flags equal to the epoch mean "final in this launch";
-// before the counter could wrap, the flags are cleared and the epoch
-// restarts with the same parity (the state block alternates by parity).
+// Next launch epoch.  Only its parity matters on the device (the state
+// block alternates by parity); the counter restarts before it could wrap,
+// keeping the parity sequence.
 sf_status next_epoch(sf_schedule_s* s, hipStream_t st, LaunchState& ls) {
   DeviceBuffers& d = s->dev;
   uint32_t e = d.epoch + 1;
-  if (e >= (1u << 30)) {
-    SF_HIP(hipMemsetAsync(d.flags, 0, size_t(std::max<int64_t>(s->n, 1)) * size_t(d.flag_blocks) * 4, st));
-    e = (e & 1u) ? 1u : 2u;
-  }
+  if (e >= (1u << 30)) e = (e & 1u) ? 1u : 2u;
   d.epoch = e;
   ls.state = d.state;
   ls.epoch = int32_t(e);
@@ -228,7 +215,6 @@ TsArgs ts_args(sf_schedule_s* s, const void* Lv, const void* Av, const void* B, 
     a.item_list = d.trsv_items;
     a.n_work = int32_t(s->trsv_items.size());
   }
-  a.flags = d.flags;
   return a;
 }
 
@@ -246,6 +232,14 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     a.kb = 1;
     a.nblk = 1;
     a.trace = s->trace;
+    if (s->chunked) {
+      a.order = s->dev.corder;
+      a.item_ptr = s->dev.citem_ptr;
+      a.item_list = Y ? nullptr : s->dev.ctrsv_items;
+      a.n_work = Y ? int32_t(s->citem_ptr.size() - 1) : int32_t(s->ctrsv_items.size());
+      a.lloc = s->dev.clloc;
+      a.eloc = s->dev.celoc;
+    }
     const int grid = persistent_grid(s, occupancy_ts_fused(dtype, s->lanes_trsv, s->lanes_spmv));
     Timer tm(s, st);
     SF_HIP(launch_fill_pending(X, size_t(s->n), dtype, st));
@@ -362,6 +356,7 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
   if (o.kind != SF_TRSV_SPMV && o.kind != SF_IC0_TRSV) return SF_ERR_ARG;
   if (o.lanes_per_row != 0 && !pow2_in(o.lanes_per_row, 2, 64)) return SF_ERR_ARG;
   if (o.rows_per_item < 0 || o.max_item_nnz < 0 || o.rhs_block < 0 || o.rhs_block > 64) return SF_ERR_ARG;
+  if (o.coarsen < 0 || o.coarsen > 2) return SF_ERR_ARG;
   if (o.kind == SF_TRSV_SPMV && !A) return SF_ERR_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   sf_status st = sf::check_lower(L);
@@ -408,13 +403,19 @@ sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st) {
   st->depth = s->depth;
   st->joint_depth = s->joint_depth;
   st->back_depth = s->back_depth;
-  st->n_items = int32_t(s->item_ptr.size()) - 1;
+  st->n_items = int32_t(s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
   st->n_back_items = s->has_back ? int32_t(s->bitem_ptr.size()) - 1 : 0;
   st->max_level_width = s->max_level_width;
   st->lanes_per_row = s->lanes_trsv;
   st->lanes_per_spmv = s->lanes_spmv;
   st->reuse_ratio = s->reuse;
   st->inspect_seconds = s->inspect_seconds;
+  st->coarsened = s->chunked ? 1 : 0;
+  st->chunk_items = int32_t(s->ctrsv_items.size());
+  st->chunk_chain = s->chunk_chain;
+  st->max_local_depth = s->max_local_depth;
+  st->est_level_us = s->est_level_us;
+  st->est_chunk_us = s->est_chunk_us;
   return SF_OK;
 }
 
@@ -423,7 +424,8 @@ sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int3
   if (level) std::copy(s->level.begin(), s->level.end(), level);
   if (order) {
     if (s->kind == SF_TRSV_SPMV) {
-      std::copy(s->order.begin(), s->order.end(), order);
+      const std::vector<int32_t>& o = s->chunked ? s->corder : s->order;
+      std::copy(o.begin(), o.end(), order);
     } else {
       // each row contributes its SpIC0 iteration (id i) then its SpTRSV one (id n + i)
       for (size_t q = 0; q < s->order.size(); ++q) {
@@ -434,7 +436,22 @@ sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int3
   }
   if (item_ptr) {
     const int mult = s->kind == SF_TRSV_SPMV ? 1 : 2;
-    for (size_t t = 0; t < s->item_ptr.size(); ++t) item_ptr[t] = mult * s->item_ptr[t];
+    const std::vector<int32_t>& ip = s->chunked ? s->citem_ptr : s->item_ptr;
+    for (size_t t = 0; t < ip.size(); ++t) item_ptr[t] = mult * ip[t];
+  }
+  return SF_OK;
+}
+
+sf_status sf_schedule_export_local(sf_schedule s, uint8_t* local_level, uint8_t* entry_slot) {
+  if (!s) return SF_ERR_ARG;
+  const size_t npos = s->kind == SF_TRSV_SPMV ? size_t(s->n + s->m) : size_t(2 * s->n);
+  if (local_level) {
+    if (s->chunked) std::copy(s->clloc.begin(), s->clloc.end(), local_level);
+    else std::fill(local_level, local_level + npos, uint8_t(0));
+  }
+  if (entry_slot) {
+    if (s->chunked) std::copy(s->celoc.begin(), s->celoc.end(), entry_slot);
+    else std::fill(entry_slot, entry_slot + size_t(s->L.nnz()), uint8_t(0xFF));
   }
   return SF_OK;
 }
@@ -501,7 +518,6 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   a.pair_q = d.pair_q;
   a.order = d.order;
   a.item_ptr = d.item_ptr;
-  a.flags = d.flags;
   a.d_info = d_info;
   a.factor = 1;
   const int cus = std::max(1, device_cus());
@@ -545,7 +561,6 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   la.ts.item_ptr = d.item_ptr;
   la.ts.item_list = d.lvl_items;
   la.ts.n_work = a.n_work;
-  la.ts.flags = d.flags;
   la.lvl_item_ptr = d.lvl_item_ptr;
   la.depth = s->depth;
   r = next_epoch(s, st, la.ts.ls);
@@ -605,7 +620,6 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   a.order = d.border;
   a.item_ptr = d.bitem_ptr;
   a.n_work = int32_t(s->bitem_ptr.size() - 1);
-  a.flags = d.flags;
   r = next_epoch(s, st, a.ls);
   if (r != SF_OK) return r;
   const int grid = persistent_grid(s, occupancy_bwd(dt, s->lanes_trsv));
@@ -731,12 +745,14 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "claim_streams") {
     if (v < 1 || v > kStreams) return SF_ERR_ARG;
     s->claim_streams = int32_t(v);
-  } else if (k == "rows_per_item" || k == "max_item_nnz" || k == "spmv_delay") {
-    if (k == "spmv_delay" ? (v < 0 || v > (int64_t(1) << 30)) : (v < 1 || v > (int64_t(1) << 30)))
+  } else if (k == "rows_per_item" || k == "max_item_nnz" || k == "spmv_delay" || k == "coarsen") {
+    if (k == "coarsen" ? (v < 0 || v > 2 || s->kind != SF_TRSV_SPMV)
+        : k == "spmv_delay" ? (v < 0 || v > (int64_t(1) << 30)) : (v < 1 || v > (int64_t(1) << 30)))
       return SF_ERR_ARG;
     if (k == "rows_per_item" && v > 64) return SF_ERR_ARG;  // one lane finishes each row
     if (k == "rows_per_item") s->rows_per_item = int32_t(v);
     else if (k == "max_item_nnz") s->max_item_nnz = int32_t(v);
+    else if (k == "coarsen") s->coarsen = int32_t(v);
     else s->spmv_delay = int32_t(v);
     try {
       sf::cut_items(s);
@@ -767,7 +783,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
       s->trace = nullptr;
     }
     if (v) {
-      const size_t bytes = (s->item_ptr.size() + 1) * 4 * sizeof(unsigned long long);
+      const size_t bytes = (std::max(s->item_ptr.size(), s->citem_ptr.size()) + 1) * 4 * sizeof(unsigned long long);
       if (hipMalloc(&s->trace, bytes) != hipSuccess) return SF_ERR_OOM;
       if (hipMemset(s->trace, 0, bytes) != hipSuccess) return SF_ERR_HIP;
     }
@@ -789,6 +805,8 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "rows_per_item") *v = s->rows_per_item;
   else if (k == "max_item_nnz") *v = s->max_item_nnz;
   else if (k == "spmv_delay") *v = s->spmv_delay;
+  else if (k == "coarsen") *v = s->coarsen;
+  else if (k == "coarsened") *v = s->chunked ? 1 : 0;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "timing") *v = s->timing;
   else if (k == "trace") *v = s->trace ? 1 : 0;
@@ -826,7 +844,7 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   };
   double best = 1e30;
   r = time_once(best);
-  // coordinate search: lanes per row, rows per item, residency, RHS block
+  // coordinate search: plan, RHS block, SpMV delay, item size and budget, residency
   auto try_param = [&](const char* key, const std::vector<int64_t>& cands) -> sf_status {
     int64_t keep = 0;
     sf_get_param(s, key, &keep);
@@ -843,8 +861,9 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
     }
     return sf_set_param(s, key, keep);
   };
-  if (r == SF_OK && nrhs == 1) r = try_param("lanes_trsv", {2, 4, 8, 16, 32});
-  if (r == SF_OK && nrhs == 1 && Y) r = try_param("lanes_spmv", {4, 8, 16, 32});
+  // one right-hand side: level items vs coarsened items first (the entry
+  // stream makes lanes per row irrelevant there)
+  if (r == SF_OK && nrhs == 1) r = try_param("coarsen", {1, 2});
   if (r == SF_OK && nrhs > 1) r = try_param("rhs_block", {8, 16, 32, 64});
   if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 1 << 20});
   if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});
@@ -875,7 +894,7 @@ sf_status sf_sync_status(sf_schedule s, void* stream) {
 
 sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count) {
   if (!s || !out || !s->trace) return SF_ERR_ARG;
-  const int64_t have = int64_t(s->item_ptr.size() - 1) * 4;
+  const int64_t have = int64_t((s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1) * 4;
   if (count < have) return SF_ERR_SHAPE;
   if (hipDeviceSynchronize() != hipSuccess) return SF_ERR_HIP;
   if (hipMemcpy(out, s->trace, size_t(have) * 8, hipMemcpyDeviceToHost) != hipSuccess) return SF_ERR_HIP;

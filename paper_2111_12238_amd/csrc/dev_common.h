@@ -1,15 +1,15 @@
 // Device-side building blocks of the persistent executors (gfx950).
 //
-// Readiness protocol.  A row's result (x_i, L row i, lambda_i) is stored
-// with device-coherent (agent-scope) stores, the wavefront waits for its
-// stores to complete (s_waitcnt vmcnt(0)), then stores the row's flag =
-// launch epoch, also device-coherent.  A consumer polls the flags of the rows
-// it reads with device-coherent loads and then reads the values with
-// device-coherent loads.  Device-coherent accesses are served at the point of
-// coherence shared by the 8 XCDs, so no L2 writeback (buffer_wbl2) or
-// invalidate (buffer_inv) is needed; the completion wait orders value before
-// flag.  Read-only data (patterns, matrix values, right-hand sides) uses
-// ordinary cached loads.
+// Readiness protocol.  Every value another wavefront may wait for (x_i, the
+// values of L row i, lambda_i) lives in a buffer pre-filled with a "pending"
+// bit pattern; the producer publishes the value itself with one
+// device-coherent (agent-scope) store, and a consumer polls the value with
+// device-coherent loads until the pattern is gone (value-as-flag, below).
+// Device-coherent accesses are served at the point of coherence shared by
+// the 8 XCDs, so no L2 writeback or invalidate is needed.  Read-only data
+// (patterns, matrix values, right-hand sides) uses ordinary cached loads.
+// Claim counters, the done counter, the grid barrier and the watchdog status
+// live in a small per-schedule state block (schedule.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,25 +34,8 @@ __device__ __forceinline__ void st_co(T* p, T v) {
 __device__ __forceinline__ void stores_complete() {
   __asm__ __volatile__("s_waitcnt vmcnt(0)" ::: "memory");
 }
-// Compiler barrier: keep the value loads after the flag polls.
+// Compiler barrier: keep the loads after a barrier wait where they are.
 __device__ __forceinline__ void after_wait() { __asm__ __volatile__("" ::: "memory"); }
-
-// Poll flag *f until it equals epoch.  Returns false if the watchdog fired
-// (spin_limit polls) or another wavefront already reported a timeout; the
-// caller then proceeds with whatever value is there so the grid drains.
-__device__ __forceinline__ bool wait_flag(const int32_t* f, const LaunchState& ls) {
-  if (ld_co(f) == ls.epoch) return true;
-  int32_t spins = 0;
-  for (;;) {
-    __builtin_amdgcn_s_sleep(1);
-    if (ld_co(f) == ls.epoch) return true;
-    if (++spins >= ls.spin_limit) {
-      st_co(ls.state + kStatusOff, kStatusTimeout);
-      return false;
-    }
-    if ((spins & 255) == 0 && ld_co(ls.state + kStatusOff) != 0) return false;
-  }
-}
 
 // Clear the state fields the next launch on this schedule will use.
 __device__ __forceinline__ void reset_next_launch(const LaunchState& ls) {
@@ -147,7 +130,9 @@ template <typename T>
 __device__ __forceinline__ T publishable(T v) {
   return is_pending(v) ? __builtin_nan("") : v;
 }
-// Poll *p until it holds a published value (watchdog as in wait_flag).
+// Poll *p until it holds a published value.  After spin_limit polls, or once
+// another wavefront has reported a timeout, the watchdog gives up and the
+// caller proceeds with whatever value is there so the grid drains.
 // Three polls are kept in flight, staggered: each check waits only for the
 // oldest outstanding load (loads return in order) and then issues the next,
 // so readiness is observed a third of a memory round trip after it happens

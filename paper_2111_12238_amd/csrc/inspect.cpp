@@ -15,6 +15,8 @@
 #include <chrono>
 #include <cstring>
 #include <limits>
+#include <queue>
+#include <utility>
 
 #include "schedule.h"
 
@@ -122,6 +124,214 @@ static void cut_runs(const std::vector<int32_t>& order, const std::vector<int32_
   }
 }
 
+// Critical-path model used to choose between the two plans: a dependence
+// between items costs about one device-coherent round trip plus the item's
+// load round (kEstHop), and each wavefront inside an item one LDS-staged
+// step (kEstStep).  Both constants are rough MI355X measurements; the
+// autotuner times the two plans when the estimate is not trusted.
+constexpr double kEstHop = 1.5, kEstStep = 0.15;
+
+// Coarsened SpTRSV items by locality-greedy topological ordering.  Rows are
+// taken one at a time in a topological order (Kahn's algorithm); the
+// current item grows with the ready row that has the most predecessors
+// already in it (ties: lower level, then lower row), and closes at
+// rows_per_item rows, at the entry budget, or when no ready row touches it.
+// A new item starts from the lowest-level ready row.  Every item is a
+// contiguous run of one topological order, so every DAG edge goes from an
+// item to itself or to a later item.  On meshes this grows compact blocks
+// whose internal chains replace many dependent wavefronts.
+static void build_chunks(sf_schedule_s* s) {
+  const Pattern& L = s->L;
+  const int32_t n = L.nrows;
+  const int64_t m = s->m;
+  const int32_t R = std::max(1, std::min(s->rows_per_item, 64));
+  const int64_t budget = std::min<int64_t>(s->max_item_nnz, kChunkEntries);
+  std::vector<int32_t> sp(size_t(n) + 1, 0), si;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = L.rp[i]; p < L.rp[i + 1] - 1; ++p) sp[size_t(L.ci[p]) + 1]++;
+  for (int32_t i = 0; i < n; ++i) sp[size_t(i) + 1] += sp[i];
+  si.resize(size_t(sp[n]));
+  {
+    std::vector<int32_t> fill(sp.begin(), sp.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t p = L.rp[i]; p < L.rp[i + 1] - 1; ++p) si[size_t(fill[L.ci[p]]++)] = i;
+  }
+  std::vector<int32_t> indeg(static_cast<size_t>(n)), score(static_cast<size_t>(n), 0), chunk_of(static_cast<size_t>(n), -1), touched;
+  std::vector<uint8_t> lloc(size_t(n), 0);
+  using Key = std::pair<int64_t, int32_t>;  // (level, row)
+  std::priority_queue<Key, std::vector<Key>, std::greater<Key>> ready;
+  for (int32_t i = 0; i < n; ++i) {
+    indeg[i] = L.rp[i + 1] - L.rp[i] - 1;
+    if (indeg[i] == 0) ready.push({s->level[i], i});
+  }
+  struct Cand {
+    int32_t score, level, row;
+    bool operator<(const Cand& o) const {  // max-heap: more predecessors inside, then lower level, row
+      if (score != o.score) return score < o.score;
+      if (level != o.level) return level > o.level;
+      return row > o.row;
+    }
+  };
+  std::priority_queue<Cand> cand;
+  std::vector<int32_t> rows;       // rows in chunk order (topological)
+  std::vector<int32_t> chunk_ptr;  // into rows
+  rows.reserve(size_t(n));
+  chunk_ptr.push_back(0);
+  int32_t cid = 0;
+  int64_t done = 0;
+  auto add = [&](int32_t u) {
+    chunk_of[u] = cid;
+    int32_t d = 0;
+    for (int32_t p = L.rp[u]; p < L.rp[u + 1] - 1; ++p)
+      if (chunk_of[L.ci[p]] == cid) d = std::max<int32_t>(d, lloc[L.ci[p]] + 1);
+    lloc[u] = uint8_t(d);
+    rows.push_back(u);
+    ++done;
+    for (int32_t q = sp[u]; q < sp[u + 1]; ++q) {
+      const int32_t v = si[q];
+      if (score[v] == 0) touched.push_back(v);
+      ++score[v];
+      if (--indeg[v] == 0) ready.push({s->level[v], v});
+      if (indeg[v] == 0) cand.push({score[v], s->level[v], v});
+    }
+  };
+  while (done < n) {
+    while (chunk_of[ready.top().second] >= 0) ready.pop();
+    const int32_t seed = ready.top().second;
+    ready.pop();
+    int64_t cost = std::max(1, L.rp[seed + 1] - L.rp[seed] - 1);
+    int32_t size = 1;
+    add(seed);
+    while (size < R && !cand.empty()) {
+      const Cand c = cand.top();
+      if (chunk_of[c.row] >= 0 || score[c.row] != c.score) {  // stale heap entry
+        cand.pop();
+        continue;
+      }
+      const int64_t cr = std::max(1, L.rp[c.row + 1] - L.rp[c.row] - 1);
+      if (cost + cr > budget) break;
+      cand.pop();
+      cost += cr;
+      ++size;
+      add(c.row);
+    }
+    for (int32_t v : touched) score[v] = 0;
+    touched.clear();
+    cand = std::priority_queue<Cand>();
+    chunk_ptr.push_back(int32_t(rows.size()));
+    ++cid;
+  }
+  const int32_t nc = cid;
+
+  // Each item's rows sorted by (local wavefront, row); slot = position.
+  std::vector<int32_t> slot(size_t(n), 0);
+  int32_t maxloc = 0;
+  for (int32_t c = 0; c < nc; ++c) {
+    auto b = rows.begin() + chunk_ptr[c], e = rows.begin() + chunk_ptr[c + 1];
+    std::sort(b, e, [&](int32_t x, int32_t y) { return lloc[x] != lloc[y] ? lloc[x] < lloc[y] : x < y; });
+    for (int32_t k = chunk_ptr[c]; k < chunk_ptr[c + 1]; ++k) {
+      slot[rows[k]] = k - chunk_ptr[c];
+      maxloc = std::max<int32_t>(maxloc, lloc[rows[k]]);
+    }
+  }
+  // Critical-path estimate over the item graph (item ids are topological).
+  std::vector<double> cp(size_t(nc), 0.0);
+  std::vector<int32_t> chain(size_t(nc), 1);
+  double cp_trsv = 0.0;
+  int32_t longest = 0;
+  for (int32_t c = 0; c < nc; ++c) {
+    double in = 0.0;
+    int32_t ch = 0;
+    int32_t depth_c = 0;
+    for (int32_t k = chunk_ptr[c]; k < chunk_ptr[c + 1]; ++k) {
+      const int32_t u = rows[k];
+      depth_c = std::max<int32_t>(depth_c, lloc[u] + 1);
+      for (int32_t p = L.rp[u]; p < L.rp[u + 1] - 1; ++p) {
+        const int32_t pc = chunk_of[L.ci[p]];
+        if (pc != c) {
+          in = std::max(in, cp[pc]);
+          ch = std::max(ch, chain[pc]);
+        }
+      }
+    }
+    cp[c] = in + kEstHop + kEstStep * depth_c;
+    chain[c] = ch + 1;
+    cp_trsv = std::max(cp_trsv, cp[c]);
+    longest = std::max(longest, chain[c]);
+  }
+  // SpMV rows: after the item holding their last input (plus the slack
+  // delay, in items of a typical chain step).
+  std::vector<int32_t> skey(size_t(m), -1);
+  double cp_all = cp_trsv;
+  for (int64_t r = 0; r < m; ++r) {
+    double in = 0.0;
+    for (int32_t p = s->A.rp[r]; p < s->A.rp[r + 1]; ++p) {
+      const int32_t c = chunk_of[s->A.ci[p]];
+      skey[r] = std::max(skey[r], c);
+      in = std::max(in, cp[c]);
+    }
+    cp_all = std::max(cp_all, in + kEstHop);
+  }
+  if (s->spmv_delay > 0 && nc > 0) {
+    const int64_t per_step = std::max<int64_t>(1, nc / std::max(1, longest));
+    for (int64_t r = 0; r < m; ++r)
+      skey[r] = int32_t(std::min<int64_t>(int64_t(skey[r]) + int64_t(s->spmv_delay) * per_step, nc - 1));
+  }
+  // Claim order: [SpMV rows without inputs] item 0, its SpMV rows, item 1, ...
+  std::vector<int32_t> bucket(static_cast<size_t>(nc) + 2, 0), sorder(static_cast<size_t>(m));
+  for (int64_t r = 0; r < m; ++r) bucket[size_t(skey[r] + 1) + 1]++;
+  for (size_t k = 0; k + 1 < bucket.size(); ++k) bucket[k + 1] += bucket[k];
+  {
+    std::vector<int32_t> fill(bucket.begin(), bucket.end() - 1);
+    for (int64_t r = 0; r < m; ++r) sorder[size_t(fill[size_t(skey[r] + 1)]++)] = int32_t(r);
+  }
+  s->corder.clear();
+  s->citem_ptr.assign(1, 0);
+  s->ctrsv_items.clear();
+  s->clloc.clear();
+  s->corder.reserve(size_t(n + m));
+  s->clloc.reserve(size_t(n + m));
+  auto spmv_run = [&](int32_t b) {  // SpMV rows of bucket b, cut by rows and budget
+    int32_t q = bucket[b];
+    const int32_t e = bucket[b + 1];
+    while (q < e) {
+      int64_t c = 0;
+      int32_t k = q;
+      while (k < e && k - q < R) {
+        const int32_t r = sorder[k];
+        const int64_t cr = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
+        if (k > q && c + cr > s->max_item_nnz) break;
+        c += cr;
+        ++k;
+      }
+      for (int32_t t = q; t < k; ++t) {
+        s->corder.push_back(int32_t(n + sorder[t]));
+        s->clloc.push_back(0);
+      }
+      s->citem_ptr.push_back(int32_t(s->corder.size()));
+      q = k;
+    }
+  };
+  spmv_run(0);
+  for (int32_t c = 0; c < nc; ++c) {
+    for (int32_t k = chunk_ptr[c]; k < chunk_ptr[c + 1]; ++k) {
+      s->corder.push_back(rows[k]);
+      s->clloc.push_back(lloc[rows[k]]);
+    }
+    s->ctrsv_items.push_back(int32_t(s->citem_ptr.size()) - 1);
+    s->citem_ptr.push_back(int32_t(s->corder.size()));
+    spmv_run(c + 1);
+  }
+  // Per stored entry of L: slot of its column in the row's item, or 0xFF.
+  s->celoc.assign(size_t(L.nnz()), 0xFF);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = L.rp[i]; p < L.rp[i + 1] - 1; ++p)
+      if (chunk_of[L.ci[p]] == chunk_of[i]) s->celoc[size_t(p)] = uint8_t(slot[L.ci[p]]);
+  s->chunk_chain = longest;
+  s->max_local_depth = nc > 0 ? maxloc + 1 : 0;
+  s->est_chunk_us = cp_all;
+}
+
 void cut_items(sf_schedule_s* s) {
   const int64_t n = s->n, m = s->m;
   if (s->kind == SF_TRSV_SPMV) {
@@ -151,6 +361,19 @@ void cut_items(sf_schedule_s* s) {
       if (s->order[s->item_ptr[t]] < n) s->trsv_items.push_back(int32_t(t));
       else s->spmv_items.push_back(int32_t(t));
     }
+    // One hop per joint wavefront, one step inside each.
+    s->est_level_us = double(s->joint_depth) * (kEstHop + kEstStep);
+    s->corder.clear();
+    s->citem_ptr.clear();
+    s->ctrsv_items.clear();
+    s->clloc.clear();
+    s->celoc.clear();
+    s->chunk_chain = 0;
+    s->max_local_depth = 0;
+    s->est_chunk_us = 0.0;
+    if (s->coarsen != 1 && n > 0) build_chunks(s);
+    s->chunked = s->coarsen == 2 || (s->coarsen == 0 && n > 0 && s->est_chunk_us < 0.8 * s->est_level_us);
+    if (n == 0) s->chunked = false;
   } else {
     std::vector<int32_t> key(static_cast<size_t>(n)), cost(static_cast<size_t>(n));
     for (int64_t i = 0; i < n; ++i) {
@@ -310,32 +533,59 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
   s->max_item_nnz = o.max_item_nnz > 0 ? o.max_item_nnz : 512;
   s->rhs_block = o.rhs_block;
   s->no_fusion = o.no_fusion;
+  s->coarsen = o.coarsen;
   cut_items(s);
   return SF_OK;
 }
 
-int validate_forward(const sf_schedule_s* s) {
+// Check a forward plan against every DAG edge: each iteration appears once,
+// and every edge u -> v has item(u) < item(v), or (coarsened plans) u and v
+// share an item with u on an earlier local wavefront.
+static int validate_plan(const sf_schedule_s* s, const std::vector<int32_t>& order,
+                         const std::vector<int32_t>& item_ptr, const std::vector<uint8_t>* lloc) {
   const int64_t n = s->n, m = s->m;
   const int64_t N = s->kind == SF_TRSV_SPMV ? n + m : n;
-  std::vector<int32_t> item(size_t(N), -1);
-  const int64_t nitems = int64_t(s->item_ptr.size()) - 1;
-  if (s->item_ptr.empty() || s->item_ptr[0] != 0 || s->item_ptr.back() != N) return 1;
+  std::vector<int32_t> item(size_t(N), -1), pos(size_t(N), -1);
+  const int64_t nitems = int64_t(item_ptr.size()) - 1;
+  if (item_ptr.empty() || item_ptr[0] != 0 || item_ptr.back() != N) return 1;
   for (int64_t t = 0; t < nitems; ++t) {
-    if (s->item_ptr[t + 1] <= s->item_ptr[t]) return 2;
-    for (int32_t q = s->item_ptr[t]; q < s->item_ptr[t + 1]; ++q) {
-      const int32_t u = s->order[q];
+    if (item_ptr[t + 1] <= item_ptr[t]) return 2;
+    for (int32_t q = item_ptr[t]; q < item_ptr[t + 1]; ++q) {
+      const int32_t u = order[q];
       if (u < 0 || u >= N || item[u] >= 0) return 3;
       item[u] = int32_t(t);
+      pos[u] = q;
     }
   }
   for (int64_t i = 0; i < n; ++i)
-    for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p)
-      if (!(item[s->L.ci[p]] < item[i])) return 4;
+    for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p) {
+      const int32_t j = s->L.ci[p];
+      if (item[j] < item[i]) continue;
+      if (lloc && item[j] == item[i] && (*lloc)[pos[j]] < (*lloc)[pos[i]] &&
+          s->celoc[size_t(p)] == uint8_t(pos[j] - item_ptr[item[i]]))
+        continue;
+      return 4;
+    }
   if (s->kind == SF_TRSV_SPMV)
     for (int64_t r = 0; r < m; ++r)
       for (int32_t p = s->A.rp[r]; p < s->A.rp[r + 1]; ++p)
         if (!(item[s->A.ci[p]] < item[n + r])) return 5;
+  if (lloc) {
+    // item-local rows sorted by local wavefront; entries outside the item flagged external
+    for (int64_t t = 0; t < nitems; ++t)
+      for (int32_t q = item_ptr[t] + 1; q < item_ptr[t + 1]; ++q)
+        if ((*lloc)[q] < (*lloc)[q - 1]) return 6;
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p)
+        if (s->celoc[size_t(p)] != 0xFF && item[s->L.ci[p]] != item[i]) return 7;
+  }
   return 0;
+}
+
+int validate_forward(const sf_schedule_s* s) {
+  int r = validate_plan(s, s->order, s->item_ptr, nullptr);
+  if (r == 0 && s->chunked) r = validate_plan(s, s->corder, s->citem_ptr, &s->clloc);
+  return r;
 }
 
 }  // namespace sf

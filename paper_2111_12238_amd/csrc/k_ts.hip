@@ -77,23 +77,120 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
+// Coarsened SpTRSV item (rows on several local wavefronts, sorted by local
+// wavefront).  All off-diagonal entries are dealt to the lanes in one pass
+// (the inspector keeps an item's entries within one pass): an entry whose
+// column is a row of the same item (eloc = that row's slot) loads no x; the
+// others load x_j through the readiness protocol as in item_stream.  Then
+// the local wavefronts run in order: the owner lanes of the rows on local
+// wavefront s fold their entries in ascending column order -- a product
+// taken from LDS, or L_ij times the item's own x_j kept in LDS -- divide by
+// L_ii, keep x_i in LDS for the later wavefronts and publish it.  Every
+// product is rounded once and every row folds in ascending order, as in
+// forward substitution, so FP64 results stay bit-identical.
+template <typename T>
+__device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w, T* xl,
+                                           int it) {
+  static_assert(dev::kPass >= kChunkEntries, "a coarsened item must fit one stream pass");
+  const int nr = q1 - q0;
+  const bool mine = lane < nr;
+  const T* __restrict__ val = static_cast<const T*>(a.Lv);
+  T* X = static_cast<T*>(a.X);
+  unsigned long long* tr = trace_slots(a, it);
+  if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
+  const int row = mine ? a.order[q0 + lane] : 0;
+  const int r0 = mine ? a.Lrp[row] : 0;
+  const int r1 = mine ? a.Lrp[row + 1] - 1 : 0;
+  const int myloc = mine ? int(a.lloc[q0 + lane]) : 0;
+  const int maxloc = int(a.lloc[q1 - 1]);
+  T acc = mine ? static_cast<const T*>(a.B)[row] : T(0);
+  const T dii = mine ? ld_stream(val + r1) : T(1);
+  const int len = r1 - r0;
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  if (mine)
+    for (int t = off; t < off + len; ++t) w.pos[t] = r0 + (t - off);
+  __builtin_amdgcn_wave_barrier();
+  constexpr int R = dev::kRounds;
+  int j[R];
+  T v[R], xv[R];
+  int sl[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int k = lane + 64 * e;
+    j[e] = -1;
+    sl[e] = 0xFF;
+    v[e] = T(0);
+    if (k < total) {
+      const int p = w.pos[k];
+      sl[e] = int(ld_stream(a.eloc + p));
+      v[e] = ld_stream(val + p);
+      if (sl[e] == 0xFF) j[e] = ld_stream(a.Lci + p);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < R; ++e) xv[e] = j[e] >= 0 ? dev::ld_co(X + j[e]) : T(0);
+  if (tr && lane == 0) tr[1] = __builtin_amdgcn_s_memrealtime();
+  dev::wait_ready<T, R>(X, j, xv, lane, a.ls);
+  // LDS: prod[k] = rounded product (external entry) or L_ij (local entry);
+  // pos[k] = slot of the local column, or 0xFF
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int k = lane + 64 * e;
+    if (k < total) {
+      w.prod[k] = sl[e] == 0xFF ? v[e] * xv[e] : v[e];
+      w.pos[k] = sl[e];
+    }
+  }
+  if (tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();
+  __builtin_amdgcn_wave_barrier();
+  for (int s = 0; s <= maxloc; ++s) {
+    if (mine && myloc == s) {
+      for (int t = off; t < off + len; ++t) {
+        const int q = w.pos[t];
+        const T pr = q == 0xFF ? w.prod[t] : w.prod[t] * xl[q];
+        acc = acc - pr;
+      }
+      const T x = publishable(acc / dii);
+      xl[lane] = x;
+      st_co(X + row, x);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
+}
+
 // The next ticket is claimed before the current item is processed, so the
 // claim's round trip overlaps the item's loads.  Deadlock freedom still
 // holds: a wave's prefetched ticket is larger than the item it works on, so
 // the smallest claimed-but-unfinished item is always one being processed.
+// With a coarsened plan (a.lloc != nullptr) SpTRSV items whose rows span
+// several local wavefronts run through item_chunk.
 template <typename T>
 __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
   __shared__ WaveLds<T> lds[kWaves];
+  __shared__ T xloc[kWaves][64];
   const int lane = threadIdx.x & 63;
   WaveLds<T>& w = lds[threadIdx.x >> 6];
+  T* xl = xloc[threadIdx.x >> 6];
   dev::reset_next_launch(a.ls);
   int t = dev::claim(a.ls, lane);
   while (t < a.n_work) {
     const int tn = dev::claim(a.ls, lane);
     const int it = a.item_list ? a.item_list[t] : t;
     const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-    if (a.order[q0] < a.n) item_stream<T, true, 2>(a, q0, q1, lane, w, it);
-    else item_stream<T, false, 2>(a, q0, q1, lane, w, it);
+    if (a.order[q0] < a.n) {
+      if (a.lloc && a.lloc[q1 - 1] != 0) item_chunk<T>(a, q0, q1, lane, w, xl, it);
+      else item_stream<T, true, 2>(a, q0, q1, lane, w, it);
+    } else {
+      item_stream<T, false, 2>(a, q0, q1, lane, w, it);
+    }
     t = tn;
   }
 }

@@ -12,7 +12,7 @@ namespace sf {
 // Per-launch bookkeeping shared by every persistent kernel.
 struct LaunchState {
   int32_t* state;     // device state block (schedule.h layout)
-  int32_t epoch;      // readiness flags hold this value once a row is final
+  int32_t epoch;      // launch counter; its parity selects the state fields
   int32_t spin_limit; // polls before the watchdog fires
   int32_t streams;    // claim counters in use (1..kStreams)
 };
@@ -34,7 +34,8 @@ struct TsArgs {
   void* xi;                // nblk * n * kb interleaved solution workspace (nrhs > 1)
   const int32_t *order, *item_ptr, *item_list;
   int32_t n_work;          // items to run (entries of item_list, or all items)
-  int32_t* flags;          // n per right-hand-side block
+  const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
+  const uint8_t* eloc;     // coarsened plan: per L entry, slot of its column in the item or 0xFF
   unsigned long long* trace;  // optional: 4 timestamps per item (see k_ts.hip)
   LaunchState ls;
 };
@@ -72,7 +73,6 @@ struct Ic0Args {
   int32_t depth;
   int32_t solve;           // 1: also solve L x = b in the same item
   int32_t factor;          // 1: compute the factor (0: solve with a given factor)
-  int32_t* flags;
   int32_t* d_info;         // written by the last wave (may be nullptr)
   LaunchState ls;
 };
@@ -87,7 +87,6 @@ struct BwdArgs {
   void *lam, *gradL;
   const int32_t *order, *item_ptr;
   int32_t n_work;
-  int32_t* flags;
   LaunchState ls;
 };
 

@@ -29,6 +29,7 @@ inline constexpr int info_off(int p) { return (2 * kStreams + 2 + p) * kLine; }
 inline constexpr int bar_off(int p) { return (2 * kStreams + 4 + p) * kLine; }
 constexpr int kStatusOff = (2 * kStreams + 6) * kLine;
 constexpr int kStateWords = (2 * kStreams + 8) * kLine;
+constexpr int kChunkEntries = 512;        // off-diagonals of one coarsened item (one stream pass)
 constexpr int kInfoNone = 0x7f7f7f7f;     // "no failing row" (byte-fill value of the block)
 constexpr int kStatusTimeout = 1;
 
@@ -43,6 +44,10 @@ struct DeviceBuffers {
   int32_t *order = nullptr, *item_ptr = nullptr, *trsv_items = nullptr, *spmv_items = nullptr;
   int32_t *lvl_items = nullptr;     // item list of the level-set baseline
   int32_t *lvl_item_ptr = nullptr;  // per level, into lvl_items
+  // coarsened plan of the one-right-hand-side fused executor
+  int32_t *corder = nullptr, *citem_ptr = nullptr, *ctrsv_items = nullptr;
+  uint8_t *clloc = nullptr;         // local wavefront of each claim position
+  uint8_t *celoc = nullptr;         // per stored L entry: slot of its column in the row's item, or 0xFF
   // backward
   int32_t *LTrp = nullptr, *LTci = nullptr, *LTmap = nullptr;
   int32_t *ATrp = nullptr, *ATci = nullptr, *ATmap = nullptr;
@@ -51,8 +56,6 @@ struct DeviceBuffers {
   int32_t *pair_ptr = nullptr, *pair_u = nullptr, *pair_q = nullptr;
   // mutable state
   int32_t* state = nullptr;
-  int32_t* flags = nullptr;     // n * flag_blocks words
-  int64_t flag_blocks = 0;
   void* xi = nullptr;           // interleaved right-hand-side workspace
   size_t xi_bytes = 0;
   uint32_t epoch = 0;
@@ -79,6 +82,20 @@ struct sf_schedule_s {
   std::vector<int32_t> spmv_items;   // items holding SpMV rows, in claim order
   // Level-set baseline: items of SpTRSV rows grouped by level.
   std::vector<int32_t> lvl_items, lvl_item_ptr;
+
+  // Coarsened plan (SF_TRSV_SPMV, one right-hand side).  The SpTRSV rows
+  // are cut into items of up to 64 rows that may depend on each other
+  // inside the item (several wavefronts per item, the paper's w-partitions);
+  // an item's rows are sorted by their local wavefront (clloc).  The items
+  // are contiguous runs of one topological order, so the item graph is
+  // acyclic and claiming items in that order cannot deadlock.  SpMV rows
+  // follow the item that finishes their last input.
+  int32_t coarsen = 0;               // requested: 0 auto, 1 level items, 2 coarsened
+  bool chunked = false;              // the coarsened plan is in effect
+  std::vector<int32_t> corder, citem_ptr, ctrsv_items;
+  std::vector<uint8_t> clloc, celoc;
+  int32_t chunk_chain = 0, max_local_depth = 0;
+  double est_level_us = 0.0, est_chunk_us = 0.0;
 
   // Backward (transposed solve) schedule.
   bool has_back = false;

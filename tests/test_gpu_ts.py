@@ -241,9 +241,81 @@ def test_watchdog_reports_timeout_and_recovers(orc):
     assert np.array_equal(host(X), xt)
 
 
+def _coarsened_case(case):
+    if case == "lap3d7_20":
+        A = synth.laplacian_3d7(20, 20, 20, 6.0)
+    elif case == "lap2d9_64":
+        A = synth.laplacian_2d9(64, 64, 8.0)
+    elif case == "lap3d27_10":
+        A = synth.laplacian_3d27(10, 10, 10, 26.1)
+    elif case == "tridiag":
+        A = synth.laplacian_1d(700, 2.0)
+    elif case == "random":
+        A = synth.random_spd(20000, seed=4)
+    else:
+        return synth.workload("lap2d5_64")
+    return synth.lower(A), A
+
+
+@pytest.mark.parametrize("case", ["lap3d7_20", "lap2d9_64", "lap3d27_10", "tridiag", "random", "lap2d5_64"])
+def test_coarsened_bit_identical(orc, case):
+    """Coarsened items (rows of several wavefronts in one item, the item's
+    own x values kept in LDS) run the definition's arithmetic in its order:
+    FP64 x and y equal the oracle's bit for bit, with full and small items,
+    a tight cost budget and late SpMV rows.  The same schedule's multi-RHS and
+    unfused paths (level items) stay exact too."""
+    announce("ts coarsened bit-identical " + case)
+    L, A = _coarsened_case(case)
+    b = synth.vec_uniform(L.nrows, seed=2)
+    xr, yr = oracle_ts(orc, L, A, b)
+    for rows, budget, delay in ((64, 512, 0), (13, 40, 0), (64, 512, 2), (64, 512, 1 << 20)):
+        s = sfm.Schedule(L, A, rows_per_item=rows, max_item_nnz=budget, coarsen=2)
+        if delay:
+            s.set_param("spmv_delay", delay)
+        assert s.info().coarsened == 1
+        x, y = run(s, L, A, b)
+        assert np.array_equal(x, xr) and np.array_equal(y, yr), (rows, budget, delay)
+    x, y = run(s, L, A, b, unfused=True)
+    assert np.array_equal(x, xr) and np.array_equal(y, yr)
+    b3 = synth.vec_uniform(L.nrows, k=3, seed=5)
+    x3r, y3r = oracle_ts(orc, L, A, b3)
+    x3, y3 = run(s, L, A, b3)
+    assert np.array_equal(x3, x3r) and np.array_equal(y3, y3r)
+    # SpTRSV alone (no A product) through the coarsened items
+    import torch
+    X, _ = sfm.trsv_spmv(s, dev(L.val), dev(A.val), dev(b), want_y=False)
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    assert np.array_equal(host(X), xr)
+
+
+def test_coarsened_integer_and_fp32(orc):
+    """Integer manufactured solution through coarsened items (exact), and the
+    FP32 coarsened solve within the same bound as level items."""
+    announce("ts coarsened integer + fp32")
+    A = synth.laplacian_3d7(16, 16, 16, 6.0)
+    L = synth.lower(A)
+    # same pattern, integer values: 1 on the diagonal, -1 off it
+    Li = synth.from_scipy(sp.csr_matrix((np.where(L.col == np.repeat(np.arange(L.nrows), np.diff(L.rowptr)), 1.0, -1.0),
+                                         L.col, L.rowptr), shape=(L.nrows, L.nrows)))
+    xt = synth.int_vector(L.nrows, seed=3)
+    b = Li.to_scipy() @ xt
+    s = sfm.Schedule(Li, A, coarsen=2)
+    x, _ = run(s, Li, A, b)
+    assert np.array_equal(x, xt)
+    bf = synth.vec_uniform(L.nrows, seed=1)
+    xr, yr = oracle_ts(orc, L, A, bf)
+    s = sfm.Schedule(L, A, coarsen=2)
+    x32, y32 = run(s, L, A, bf, dtype="f32")
+    s1 = sfm.Schedule(L, A, coarsen=1)
+    x32l, y32l = run(s1, L, A, bf, dtype="f32")
+    assert np.array_equal(x32, x32l) and np.array_equal(y32, y32l)  # same FP32 operations in the same order
+
+
 @pytest.mark.parametrize("name", ["lap3d7_128", "randspd_1m"])
 def test_full_size_configs(orc, name):
-    """The benchmark's workloads at full size, whole vectors against the oracle."""
+    """The benchmark's workloads at full size, whole vectors against the
+    oracle (bit-identical in FP64), with the plan the inspector chose."""
     announce("ts fused full size " + name)
     L, A = synth.workload(name)
     b = synth.vec_uniform(L.nrows, seed=1)
@@ -251,7 +323,8 @@ def test_full_size_configs(orc, name):
     x, y = run(s, L, A, b)
     xr, yr = oracle_ts(orc, L, A, b)
     ex, ey = relerr(x, xr), relerr(y, yr)
-    print("%s fused: x err %.2e  y err %.2e" % (name, ex, ey))
+    print("%s fused (coarsened=%d): x err %.2e  y err %.2e" % (name, s.info().coarsened, ex, ey))
     assert ex <= TOL64 and ey <= TOL64
+    assert np.array_equal(x, xr) and np.array_equal(y, yr)
     xu, yu = run(s, L, A, b, unfused=True)
     assert relerr(xu, xr) <= TOL64 and relerr(yu, yr) <= TOL64

@@ -38,7 +38,7 @@ def _check_schedule(orc, L, A, s):
 @pytest.mark.parametrize("name", CASES)
 def test_stencil_schedules(orc, name):
     L, A = synth.workload(name)
-    s = sfm.Schedule(L, A, validate=True)
+    s = sfm.Schedule(L, A, validate=True, coarsen=1)
     _check_schedule(orc, L, A, s)
     assert abs(s.info().reuse_ratio - orc.reuse_ts(L.nrows, L.nnz, A.nrows, A.nnz)) < 1e-15
 
@@ -48,7 +48,7 @@ def test_stencil_schedules(orc, name):
 def test_random_schedules(orc, seed, n, m, empty):
     L, A = _random_pair(n, seed, m, empty)
     for rows in (1, 7, 64):
-        s = sfm.Schedule(L, A, rows_per_item=rows, max_item_nnz=50, validate=True)
+        s = sfm.Schedule(L, A, rows_per_item=rows, max_item_nnz=50, validate=True, coarsen=1)
         _check_schedule(orc, L, A, s)
         _, _, ip = s.export()
         sizes = np.diff(ip)
@@ -62,7 +62,7 @@ def test_spmv_delay_orders_stay_valid(orc, delay):
     validator), keeps the SpTRSV rows in canonical order, and puts no SpMV row
     before its joint level."""
     for L, A in (synth.workload("lap2d5_64"), _random_pair(1500, 7, 900, True)):
-        s = sfm.Schedule(L, A, rows_per_item=20, validate=True)
+        s = sfm.Schedule(L, A, rows_per_item=20, validate=True, coarsen=1)
         s.set_param("spmv_delay", delay)
         level, order, ip = s.export()
         assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, ip) == 0
@@ -79,6 +79,92 @@ def test_spmv_delay_orders_stay_valid(orc, delay):
                 assert pos[n + r] > pos[want_after].max()
         s.set_param("spmv_delay", 0)
         assert np.array_equal(s.export()[1], orc.joint_order_ts(level, ready))
+
+
+def _check_coarsened(orc, L, A, s):
+    """A coarsened plan: every DAG edge respected (the oracle's validator,
+    edges inside an item allowed), each item's rows sorted by local
+    wavefront, every edge inside an item going to a later local wavefront,
+    and the per-entry slots naming exactly the item-local columns."""
+    level, order, ip = s.export()
+    loc, slot = s.export_local()
+    n = L.nrows
+    assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, ip, allow_intra=True) == 0
+    item = np.repeat(np.arange(len(ip) - 1), np.diff(ip))
+    pos = np.empty(len(order), np.int64)
+    pos[order] = np.arange(len(order))
+    for t in range(len(ip) - 1):
+        seg = loc[ip[t]:ip[t + 1]]
+        assert np.all(np.diff(seg.astype(int)) >= 0)
+        if order[ip[t]] >= n:
+            assert not seg.any()  # SpMV items hold independent rows
+        else:
+            assert np.all(order[ip[t]:ip[t + 1]] < n)  # items are kind-pure
+            assert ip[t + 1] - ip[t] <= 64
+    rows = np.repeat(np.arange(n), np.diff(L.rowptr))
+    off = L.col != rows
+    u, v, pslot = L.col[off], rows[off], slot[off]
+    same = item[pos[u]] == item[pos[v]]
+    assert np.all(loc[pos[u][same]] < loc[pos[v][same]])
+    assert np.array_equal(pslot[same].astype(np.int64), pos[u][same] - ip[item[pos[v][same]]])
+    assert np.all(pslot[~same] == 255)
+    # one stream pass per coarsened item
+    for t in range(len(ip) - 1):
+        if order[ip[t]] < n and loc[ip[t + 1] - 1] > 0:
+            r = order[ip[t]:ip[t + 1]]
+            assert int(np.sum(np.diff(L.rowptr)[r] - 1)) <= 512
+
+
+@pytest.mark.parametrize("case", ["lap3d7_20", "lap2d9_64", "lap3d27_10", "random", "random_rect", "tridiag"])
+def test_coarsened_plans(orc, case):
+    if case == "lap3d7_20":
+        A = synth.laplacian_3d7(20, 20, 20, 6.0)
+        L = synth.lower(A)
+    elif case == "lap2d9_64":
+        A = synth.laplacian_2d9(64, 64, 8.0)
+        L = synth.lower(A)
+    elif case == "lap3d27_10":
+        A = synth.laplacian_3d27(10, 10, 10, 26.1)
+        L = synth.lower(A)
+    elif case == "random":
+        L, A = _random_pair(3000, 5, None, True)
+    elif case == "random_rect":
+        L, A = _random_pair(777, 6, 1300, True)
+    else:
+        A = synth.laplacian_1d(500, 2.0)
+        L = synth.lower(A)
+    for rows, budget, delay in ((64, 512, 0), (17, 40, 0), (64, 512, 3)):
+        s = sfm.Schedule(L, A, rows_per_item=rows, max_item_nnz=budget, coarsen=2, validate=True)
+        if delay:
+            s.set_param("spmv_delay", delay)
+        st = s.info()
+        assert st.coarsened == 1 and st.chunk_items > 0
+        _check_coarsened(orc, L, A, s)
+        _, _, ip = s.export()
+        assert np.diff(ip).max() <= rows
+    if case == "tridiag":
+        # a chain: every item is a run of consecutive rows, one wavefront each
+        s = sfm.Schedule(L, A, coarsen=2)
+        assert s.info().chunk_chain == (500 + 63) // 64 and s.info().max_local_depth == 64
+
+
+def test_coarsen_choice():
+    """The inspector keeps coarsened items where its critical-path estimate
+    is clearly lower (mesh-like DAGs) and level items otherwise."""
+    A = synth.laplacian_3d7(24, 24, 24, 6.0)
+    s = sfm.Schedule(synth.lower(A), A)
+    st = s.info()
+    assert st.coarsened == 1 and st.est_chunk_us < 0.8 * st.est_level_us
+    assert st.chunk_chain < st.depth
+    L, A = _random_pair(5000, 9)
+    st = sfm.Schedule(L, A).info()
+    assert st.coarsened == 0 and st.est_chunk_us >= 0.8 * st.est_level_us
+    st = sfm.Schedule(L, A, coarsen=1).info()
+    assert st.coarsened == 0 and st.chunk_items == 0
+    s = sfm.Schedule(L, A, coarsen=2)
+    assert s.info().coarsened == 1
+    s.set_param("coarsen", 1)
+    assert s.info().coarsened == 0 and s.get_param("coarsened") == 0
 
 
 def test_item_nnz_budget():
@@ -180,7 +266,7 @@ def test_degenerate_sizes(orc):
     # n = 1, A with one empty row and one full row
     L = (np.array([0, 1], np.int32), np.array([0], np.int32), 1)
     A = (np.array([0, 0, 1], np.int32), np.array([0], np.int32), 1)
-    s = sfm.Schedule(L, A, validate=True)
+    s = sfm.Schedule(L, A, validate=True, coarsen=1)
     level, order, ip = s.export()
     assert level.tolist() == [0]
     # empty SpMV row 0 has joint level 0 (after SpTRSV row 0 in the order), row 1 level 1
