@@ -371,9 +371,22 @@ void cut_items(sf_schedule_s* s) {
     s->chunk_chain = 0;
     s->max_local_depth = 0;
     s->est_chunk_us = 0.0;
-    if (s->coarsen != 1 && n > 0) build_chunks(s);
-    s->chunked = s->coarsen == 2 || (s->coarsen == 0 && n > 0 && s->est_chunk_us < 0.8 * s->est_level_us);
-    if (n == 0) s->chunked = false;
+    // Coarsening pays where most edges join consecutive wavefronts (mesh-like
+    // DAGs, whose chains a compact item can absorb); on DAGs whose edges skip
+    // many wavefronts the estimate is not even computed in auto mode.
+    bool try_chunks = s->coarsen == 2;
+    if (s->coarsen == 0 && n > 0) {
+      int64_t tight = 0, edges = 0;
+      for (int64_t i = 0; i < n; ++i)
+        for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p) {
+          ++edges;
+          tight += s->level[i] == s->level[s->L.ci[p]] + 1;
+        }
+      try_chunks = edges > 0 && double(tight) >= 0.35 * double(edges);
+    }
+    if (try_chunks && n > 0) build_chunks(s);
+    s->chunked = !s->ctrsv_items.empty() &&
+                 (s->coarsen == 2 || s->est_chunk_us < 0.8 * s->est_level_us);
   } else {
     std::vector<int32_t> key(static_cast<size_t>(n)), cost(static_cast<size_t>(n));
     for (int64_t i = 0; i < n; ++i) {

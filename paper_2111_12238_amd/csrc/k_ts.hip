@@ -77,6 +77,48 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
+// Local wavefront steps of a coarsened item.  The owner lane keeps its
+// row's first NT terms in registers: a factor pv (the rounded product for an
+// entry outside the item, L_ij for an item-local column, 0 for an unused
+// slot) and the LDS slot of the x it multiplies (xl[64] holds 1.0 for the
+// first and last kind), so a step is NT LDS reads, NT products and NT
+// subtractions with no selects; multiplying by 1.0 and subtracting +0.0 are
+// exact, so the terms and their order are still the definition's.
+template <typename T, int NT>
+__device__ __forceinline__ void chunk_steps(WaveLds<T>& w, T* xl, T* X, bool mine, int myloc, int maxloc,
+                                            int off, int len, int row, int lane, T acc, T dii) {
+  constexpr int kOne = 64;
+  T pv[NT];
+  int pq[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    pv[u] = T(0);
+    pq[u] = kOne;
+    if (u < len) {
+      const int q = w.pos[off + u];
+      pv[u] = w.prod[off + u];
+      pq[u] = q == 0xFF ? kOne : q;
+    }
+  }
+  for (int s = 0; s <= maxloc; ++s) {
+    if (mine && myloc == s) {
+      T xq[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) xq[u] = xl[pq[u]];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc = acc - pv[u] * xq[u];
+      for (int t = off + NT; t < off + len; ++t) {
+        const int q = w.pos[t];
+        acc = acc - (q == 0xFF ? w.prod[t] : w.prod[t] * xl[q]);
+      }
+      const T x = publishable(acc / dii);
+      xl[lane] = x;
+      st_co(X + row, x);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Coarsened SpTRSV item (rows on several local wavefronts, sorted by local
 // wavefront).  All off-diagonal entries are dealt to the lanes in one pass
 // (the inspector keeps an item's entries within one pass): an entry whose
@@ -150,19 +192,11 @@ __device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int 
   }
   if (tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();
   __builtin_amdgcn_wave_barrier();
-  for (int s = 0; s <= maxloc; ++s) {
-    if (mine && myloc == s) {
-      for (int t = off; t < off + len; ++t) {
-        const int q = w.pos[t];
-        const T pr = q == 0xFF ? w.prod[t] : w.prod[t] * xl[q];
-        acc = acc - pr;
-      }
-      const T x = publishable(acc / dii);
-      xl[lane] = x;
-      st_co(X + row, x);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
+  int maxlen = len;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, d, 64));
+  if (maxlen <= 4) chunk_steps<T, 4>(w, xl, X, mine, myloc, maxloc, off, len, row, lane, acc, dii);
+  else chunk_steps<T, 8>(w, xl, X, mine, myloc, maxloc, off, len, row, lane, acc, dii);
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
@@ -175,10 +209,11 @@ __device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int 
 template <typename T>
 __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
   __shared__ WaveLds<T> lds[kWaves];
-  __shared__ T xloc[kWaves][64];
+  __shared__ T xloc[kWaves][65];  // item-local x by slot; [64] = 1.0 (see chunk_steps)
   const int lane = threadIdx.x & 63;
   WaveLds<T>& w = lds[threadIdx.x >> 6];
   T* xl = xloc[threadIdx.x >> 6];
+  if (lane == 0) xl[64] = T(1);
   dev::reset_next_launch(a.ls);
   int t = dev::claim(a.ls, lane);
   while (t < a.n_work) {

@@ -29,33 +29,32 @@ struct WaveLds {
 };
 
 // Wait until every vec[j[e]] of the wavefront (j[e] < 0: unused slot) is
-// published, updating xv.  Only one lane polls at a time: the first lane
-// with a pending entry watches that entry; when it is published, every lane
-// re-reads all its still-pending entries in one round, and the election
-// repeats.  Dependences of an item come from earlier wavefronts that finish
-// close together, so this converges in a few rounds while keeping the
-// polling traffic of a waiting wavefront at one request instead of one per
-// pending entry.
+// published, updating xv.  Only one lane polls at a time: among the pending
+// entries the wavefront watches the one with the largest index -- producers
+// are claimed in topological order, so the largest index is usually the
+// last to be published -- and once it is, every lane re-reads all its
+// still-pending entries in one round; the election repeats if any remain.
+// This keeps the polling traffic of a waiting wavefront at one request
+// instead of one per pending entry, and usually needs a single round.
 template <typename T, int R>
 __device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&xv)[R], int lane,
                                            const LaunchState& ls) {
   for (;;) {
-    int first = -1;
+    int jmax = -1;
 #pragma unroll
-    for (int e = R - 1; e >= 0; --e)
-      if (j[e] >= 0 && is_pending(xv[e])) first = e;
-    const unsigned long long mask = __ballot(first >= 0);
+    for (int e = 0; e < R; ++e)
+      if (j[e] >= 0 && is_pending(xv[e])) jmax = max(jmax, j[e]);
+    const unsigned long long mask = __ballot(jmax >= 0);
     if (mask == 0) return;
-    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    int wmax = jmax;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, __shfl_xor(wmax, d, 64));
+    const int leader = __ffsll(static_cast<long long>(__ballot(jmax == wmax))) - 1;
     if (lane == leader) {
-      int jf = 0;  // select the watched index first so the poll loop is emitted once
+      const T got = poll_value(vec + wmax, ls);
 #pragma unroll
       for (int e = 0; e < R; ++e)
-        if (e == first) jf = j[e];
-      const T got = poll_value(vec + jf, ls);
-#pragma unroll
-      for (int e = 0; e < R; ++e)
-        if (e == first) xv[e] = got;
+        if (j[e] == wmax) xv[e] = got;
     }
     if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
 #pragma unroll

@@ -158,7 +158,10 @@ def test_coarsen_choice():
     assert st.chunk_chain < st.depth
     L, A = _random_pair(5000, 9)
     st = sfm.Schedule(L, A).info()
-    assert st.coarsened == 0 and st.est_chunk_us >= 0.8 * st.est_level_us
+    assert st.coarsened == 0 and (st.chunk_items == 0 or st.est_chunk_us >= 0.8 * st.est_level_us)
+    Ar = synth.random_spd(20000, seed=1)  # edges skip many wavefronts: not even estimated
+    st = sfm.Schedule(synth.lower(Ar), Ar).info()
+    assert st.coarsened == 0 and st.chunk_items == 0
     st = sfm.Schedule(L, A, coarsen=1).info()
     assert st.coarsened == 0 and st.chunk_items == 0
     s = sfm.Schedule(L, A, coarsen=2)
