@@ -723,6 +723,29 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   return SF_OK;
 }
 
+// Re-cut the work items after a parameter they depend on changed; the
+// device copy is rebuilt at the next executor call.
+sf_status recut(sf_schedule_s* s) {
+  try {
+    sf::cut_items(s);
+  } catch (const std::bad_alloc&) {
+    return SF_ERR_OOM;
+  }
+  if (s->trace) {  // sized for the old items
+    hipDeviceSynchronize();
+    hipFree(s->trace);
+    s->trace = nullptr;
+  }
+  if (s->dev.ready) {
+    // the item arrays changed size: rebuild the constant block
+    hipDeviceSynchronize();
+    if (s->dev.block) hipFree(s->dev.block);
+    s->dev.block = nullptr;
+    s->dev.ready = false;
+  }
+  return SF_OK;
+}
+
 sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   if (!s || !key) return SF_ERR_ARG;
   const std::string k(key);
@@ -730,6 +753,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     const int lo = s->kind == SF_IC0_TRSV ? 4 : 2;
     if (!pow2_in(int(v), lo, s->kind == SF_IC0_TRSV ? 64 : 32)) return SF_ERR_ARG;
     s->lanes_trsv = int32_t(v);
+    if (s->kind == SF_IC0_TRSV) return recut(s);  // SpIC0 items hold one batch of 64 / lanes rows
   } else if (k == "lanes_spmv") {
     if (!pow2_in(int(v), 4, 32)) return SF_ERR_ARG;
     s->lanes_spmv = int32_t(v);
@@ -754,23 +778,8 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     else if (k == "max_item_nnz") s->max_item_nnz = int32_t(v);
     else if (k == "coarsen") s->coarsen = int32_t(v);
     else s->spmv_delay = int32_t(v);
-    try {
-      sf::cut_items(s);
-    } catch (const std::bad_alloc&) {
-      return SF_ERR_OOM;
-    }
-    if (s->trace) {  // sized for the old items
-      hipDeviceSynchronize();
-      hipFree(s->trace);
-      s->trace = nullptr;
-    }
-    if (s->dev.ready) {
-      // the item arrays changed size: rebuild the constant block
-      hipDeviceSynchronize();
-      if (s->dev.block) hipFree(s->dev.block);
-      s->dev.block = nullptr;
-      s->dev.ready = false;
-    }
+    const sf_status rc = recut(s);
+    if (rc != SF_OK) return rc;
   } else if (k == "no_fusion") {
     s->no_fusion = v ? 1 : 0;
   } else if (k == "timing") {

@@ -396,7 +396,10 @@ void cut_items(sf_schedule_s* s) {
       for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1]; ++p) c += 1 + (s->pair_ptr.empty() ? 0 : s->pair_ptr[p + 1] - s->pair_ptr[p]);
       cost[i] = int32_t(std::min<int64_t>(c, std::numeric_limits<int32_t>::max()));
     }
-    cut_runs(s->order, key, cost, s->rows_per_item, s->max_item_nnz, s->item_ptr);
+    // one batch of 64 / lanes rows per item: the rows of a batch run side by
+    // side, batches of one item would run one after the other
+    const int32_t per_batch = std::max(1, 64 / std::max(1, s->lanes_trsv));
+    cut_runs(s->order, key, cost, std::min(s->rows_per_item, per_batch), s->max_item_nnz, s->item_ptr);
     s->trsv_items.clear();
     for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) s->trsv_items.push_back(int32_t(t));
   }

@@ -20,9 +20,11 @@
 // FP64 results therefore equal the sequential definition's bit for bit.
 //
 // Readiness (fused launch): the factor values and x are filled with the
-// pending pattern before the launch and every value is its own flag; a row
-// issues all its loads, then polls whichever came back pending.  The
-// level-set baseline reads them after a grid barrier instead.
+// pending pattern before the launch and every value is its own flag; a
+// batch of rows issues all its loads (kPairRegs pairs per lane at a time,
+// plus the pivots and x values), then waits for the pending ones together
+// (wait_values).  The level-set baseline reads them after a grid barrier
+// instead.
 #pragma clang fp contract(off)
 
 #include "dev_common.h"
@@ -45,13 +47,40 @@ __device__ __forceinline__ bool is_absent(double v) {
   return __builtin_bit_cast(unsigned long long, v) == kAbsentBits;
 }
 
-template <bool FUSED>
-__device__ __forceinline__ double ready(const double* p, double v, const LaunchState& ls) {
-  if constexpr (FUSED) {
-    if (is_pending(v)) v = poll_value(p, ls);
+// Wait until every value v[e] loaded from p[e] (p[e] == nullptr: unused) is
+// published.  As in the forward executor, one elected lane watches the
+// pending value at the highest address (factor rows and x are produced in
+// ascending row order, so it is usually the last to appear); once it is
+// published every lane re-reads all its still-pending values in one round,
+// and the election repeats if any remain.
+template <int R>
+__device__ __forceinline__ void wait_values(const double* (&p)[R], double (&v)[R], int lane, const LaunchState& ls) {
+  for (;;) {
+    unsigned long long best = 0;
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (p[e] && is_pending(v[e])) best = max(best, (unsigned long long)p[e]);
+    if (__ballot(best != 0) == 0) return;
+    unsigned long long wbest = best;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wbest = max(wbest, (unsigned long long)__shfl_xor((long long)wbest, d, 64));
+    const int leader = __ffsll(static_cast<long long>(__ballot(best == wbest))) - 1;
+    if (lane == leader) {
+      const double* w = reinterpret_cast<const double*>(wbest);
+      const double got = poll_value(w, ls);
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (p[e] == w) v[e] = got;
+    }
+    if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (p[e] && is_pending(v[e])) v[e] = ld_co(p[e]);
   }
-  return v;
 }
+
+// Pairs gathered per lane and round: kPairRegs per lane, G lanes per row.
+constexpr int kPairRegs = 8;
 
 template <int G, bool FUSED>
 __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* lds_row) {
@@ -71,35 +100,41 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     const int pjj = mine ? a.Lrp[j + 1] - 1 : 0;
     // the pairs of row i are contiguous: every entry's list, in entry order
     const int e0 = act ? a.pair_ptr[r0] : 0, e1 = act ? a.pair_ptr[rd] : 0;
-    // issue every load of the row before waiting on any of them
     double acc = mine ? a.Aval[p] : 0.0;
-    double djj = mine ? ld_co(a.Lval + pjj) : 1.0;
-    double xj = (mine && a.solve) ? ld_co(a.X + j) : 0.0;
     // M[t][u] = L_{j_t, k_u} where row j_t meets row i below column j_t, else absent
     for (int u = 0; u < G; ++u) lds_row[u] = kAbsent;
     __builtin_amdgcn_wave_barrier();
     double* group_rows = lds_row - size_t(sub) * G;  // LDS rows of this row's G lanes
-    for (int eb = e0; eb < e1; eb += G * 4) {
-      int tu[4];
-      double v[4];
+    // Rounds of kPairRegs pairs per lane; the pivot L_jj and x_j of the
+    // lane's entry ride along in the first round.  Every load of a round is
+    // issued before any is waited on.
+    int nround = (e1 - e0 + G * kPairRegs - 1) / (G * kPairRegs);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = eb + sub + G * k;
+    for (int off = 32; off >= 1; off >>= 1) nround = max(nround, __shfl_xor(nround, off, 64));
+    double djj = 1.0, xj = 0.0;
+    for (int rnd = 0; rnd < (nround > 0 ? nround : 1); ++rnd) {
+      constexpr int R = kPairRegs + 2;
+      const double* ptr[R];
+      double v[R];
+      int tu[kPairRegs];
+#pragma unroll
+      for (int k = 0; k < kPairRegs; ++k) {
+        const int e = e0 + rnd * G * kPairRegs + sub + G * k;
         tu[k] = e < e1 ? a.pair_u[e] : -1;
-        v[k] = e < e1 ? ld_co(a.Lval + a.pair_q[e]) : 0.0;
+        ptr[k] = e < e1 ? a.Lval + a.pair_q[e] : nullptr;
       }
+      ptr[kPairRegs] = (rnd == 0 && mine) ? a.Lval + pjj : nullptr;
+      ptr[kPairRegs + 1] = (rnd == 0 && mine && a.solve) ? a.X + j : nullptr;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (tu[k] < 0) continue;
-        if constexpr (FUSED) {
-          if (is_pending(v[k])) v[k] = poll_value(a.Lval + a.pair_q[eb + sub + G * k], a.ls);
-        }
-        group_rows[size_t(tu[k] >> 16) * G + (tu[k] & 0xffff)] = v[k];
+      for (int e = 0; e < R; ++e) v[e] = ptr[e] ? ld_co(ptr[e]) : 0.0;
+      if constexpr (FUSED) wait_values<R>(ptr, v, lane, a.ls);
+#pragma unroll
+      for (int k = 0; k < kPairRegs; ++k)
+        if (tu[k] >= 0) group_rows[size_t(tu[k] >> 16) * G + (tu[k] & 0xffff)] = v[k];
+      if (rnd == 0 && mine) {
+        djj = v[kPairRegs];
+        if (a.solve) xj = v[kPairRegs + 1];
       }
-    }
-    if (mine) {
-      djj = ready<FUSED>(a.Lval + pjj, djj, a.ls);
-      if (a.solve) xj = ready<FUSED>(a.X + j, xj, a.ls);
     }
     __builtin_amdgcn_wave_barrier();
     // longest row of this batch bounds the sweep (wave-uniform)
