@@ -68,6 +68,7 @@ void free_device(sf_schedule_s* s) {
     if (d.block) hipFree(d.block);
     if (d.state) hipFree(d.state);
     if (d.xi) hipFree(d.xi);
+    if (d.units) hipFree(d.units);
     hipSetDevice(cur);
   }
   d = DeviceBuffers();
@@ -218,6 +219,35 @@ TsArgs ts_args(sf_schedule_s* s, const void* Lv, const void* Av, const void* B, 
   return a;
 }
 
+// Multi-RHS plan for blocks of 64 / rpb rows: the level items split into
+// pieces of at most rpb rows (rows of a level item are independent, so the
+// pieces keep the claim order valid), kept on the device until the items
+// are re-cut or another block width is asked for.
+sf_status ensure_units(sf_schedule_s* s, int rpb, hipStream_t st) {
+  DeviceBuffers& d = s->dev;
+  if (d.units && d.units_rpb == rpb) return SF_OK;
+  std::vector<int32_t> ptr, trsv;
+  ptr.push_back(0);
+  for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t)
+    for (int32_t b = s->item_ptr[t]; b < s->item_ptr[t + 1]; b += rpb) {
+      if (s->order[b] < s->n) trsv.push_back(int32_t(ptr.size()) - 1);
+      ptr.push_back(std::min(b + rpb, s->item_ptr[t + 1]));
+    }
+  SF_HIP(hipStreamSynchronize(st));
+  if (d.units) SF_HIP(hipFree(d.units));
+  d.units = nullptr;
+  const size_t b0 = ptr.size() * 4, b1 = std::max<size_t>(trsv.size(), 1) * 4;
+  SF_HIP(hipMalloc(&d.units, b0 + b1));
+  d.unit_ptr = static_cast<int32_t*>(d.units);
+  d.unit_trsv = reinterpret_cast<int32_t*>(static_cast<char*>(d.units) + b0);
+  SF_HIP(hipMemcpy(d.unit_ptr, ptr.data(), b0, hipMemcpyHostToDevice));
+  if (!trsv.empty()) SF_HIP(hipMemcpy(d.unit_trsv, trsv.data(), trsv.size() * 4, hipMemcpyHostToDevice));
+  d.units_rpb = rpb;
+  d.n_units = int32_t(ptr.size()) - 1;
+  d.n_unit_trsv = int32_t(trsv.size());
+  return SF_OK;
+}
+
 sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
                         int ldb, int nrhs, void* X, int ldx, void* Y, int ldy, hipStream_t st) {
   const int dtype = dt == SF_F64 ? 0 : 1;
@@ -250,6 +280,12 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   const size_t xi_count = size_t(nblk) * size_t(s->n) * size_t(kb);
   sf_status r = ensure_xi(s, xi_count * es, st);
   if (r != SF_OK) return r;
+  r = ensure_units(s, std::max(1, 64 / kb), st);
+  if (r != SF_OK) return r;
+  a.item_ptr = s->dev.unit_ptr;
+  a.item_list = Y ? nullptr : s->dev.unit_trsv;
+  a.n_work = Y ? s->dev.n_units : s->dev.n_unit_trsv;
+  if (a.n_work == 0) return SF_OK;
   r = next_epoch(s, st, a.ls);
   if (r != SF_OK) return r;
   a.kb = kb;
@@ -742,6 +778,12 @@ sf_status recut(sf_schedule_s* s) {
     if (s->dev.block) hipFree(s->dev.block);
     s->dev.block = nullptr;
     s->dev.ready = false;
+  }
+  if (s->dev.units) {
+    hipDeviceSynchronize();
+    hipFree(s->dev.units);
+    s->dev.units = nullptr;
+    s->dev.units_rpb = 0;
   }
   return SF_OK;
 }

@@ -23,11 +23,11 @@
 // pending pattern before the launch and every value is its own flag; a
 // batch of rows issues all its loads (kPairRegs pairs per lane at a time,
 // plus the pivots and x values), then waits for the pending ones together
-// (wait_values).  The level-set baseline reads them after a grid barrier
-// instead.
+// (dev::wait_ptrs, stream.h).  The level-set baseline reads them after a
+// grid barrier instead.
 #pragma clang fp contract(off)
 
-#include "dev_common.h"
+#include "stream.h"
 
 namespace sf {
 namespace {
@@ -45,38 +45,6 @@ constexpr unsigned long long kAbsentBits = 0xFFF4000000000001ull;
 constexpr double kAbsent = __builtin_bit_cast(double, kAbsentBits);
 __device__ __forceinline__ bool is_absent(double v) {
   return __builtin_bit_cast(unsigned long long, v) == kAbsentBits;
-}
-
-// Wait until every value v[e] loaded from p[e] (p[e] == nullptr: unused) is
-// published.  As in the forward executor, one elected lane watches the
-// pending value at the highest address (factor rows and x are produced in
-// ascending row order, so it is usually the last to appear); once it is
-// published every lane re-reads all its still-pending values in one round,
-// and the election repeats if any remain.
-template <int R>
-__device__ __forceinline__ void wait_values(const double* (&p)[R], double (&v)[R], int lane, const LaunchState& ls) {
-  for (;;) {
-    unsigned long long best = 0;
-#pragma unroll
-    for (int e = 0; e < R; ++e)
-      if (p[e] && is_pending(v[e])) best = max(best, (unsigned long long)p[e]);
-    if (__ballot(best != 0) == 0) return;
-    unsigned long long wbest = best;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) wbest = max(wbest, (unsigned long long)__shfl_xor((long long)wbest, d, 64));
-    const int leader = __ffsll(static_cast<long long>(__ballot(best == wbest))) - 1;
-    if (lane == leader) {
-      const double* w = reinterpret_cast<const double*>(wbest);
-      const double got = poll_value(w, ls);
-#pragma unroll
-      for (int e = 0; e < R; ++e)
-        if (p[e] == w) v[e] = got;
-    }
-    if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
-#pragma unroll
-    for (int e = 0; e < R; ++e)
-      if (p[e] && is_pending(v[e])) v[e] = ld_co(p[e]);
-  }
 }
 
 // Pairs gathered per lane and round: kPairRegs per lane, G lanes per row.
@@ -127,7 +95,7 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
       ptr[kPairRegs + 1] = (rnd == 0 && mine && a.solve) ? a.X + j : nullptr;
 #pragma unroll
       for (int e = 0; e < R; ++e) v[e] = ptr[e] ? ld_co(ptr[e]) : 0.0;
-      if constexpr (FUSED) wait_values<R>(ptr, v, lane, a.ls);
+      if constexpr (FUSED) dev::wait_ptrs<double, R>(ptr, v, lane, a.ls);
 #pragma unroll
       for (int k = 0; k < kPairRegs; ++k)
         if (tu[k] >= 0) group_rows[size_t(tu[k] >> 16) * G + (tu[k] & 0xffff)] = v[k];

@@ -232,20 +232,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
 
 // ------------------------------------------------------------- k > 1 ------
 // KB lanes per row, one lane per right-hand side of the block; 64/KB rows
-// at a time.  The solution of block b is kept interleaved in a workspace,
+// at a time (the multi-RHS plan cuts items to that many rows).  The
+// solution of block b is kept interleaved in a workspace,
 // xi[(b * n + j) * KB + c] (filled with the pending pattern before the
 // launch), so the KB values a row reads from x_j are contiguous; X and Y are
 // column-major.  Work index t = item * nblk + block.  Each lane runs its
-// row's entries in ascending order (b_i minus each rounded product), loads
-// issued kU at a time.
-constexpr int kU = 4;
+// row's entries in ascending order (b_i minus each rounded product), kU
+// entries at a time: their indices and values, then their x, are loaded
+// together, and the pending x of the whole wavefront are waited for
+// together (dev::wait_ptrs).
+constexpr int kU = 8;
 
 template <typename T, int KB, bool TRSV, bool POLL>
 __device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T* __restrict__ val, const T* xi,
-                                       int p0, int p1, int c, T acc, const LaunchState& ls) {
-  for (int c0 = p0; c0 < p1; c0 += kU) {
+                                       int p0, int p1, int c, T acc, int lane, const LaunchState& ls) {
+  int nch = (p1 - p0 + kU - 1) / kU;
+  if constexpr (POLL) {  // the wait is wave-wide: every lane runs the same number of rounds
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nch = max(nch, __shfl_xor(nch, d, 64));
+  }
+  for (int ch = 0; ch < nch; ++ch) {
+    const int c0 = p0 + ch * kU;
     int j[kU];
     T v[kU], xv[kU];
+    const T* ptr[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int p = c0 + u;
@@ -254,12 +264,11 @@ __device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T*
       v[u] = h ? val[p] : T(0);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) xv[u] = j[u] >= 0 ? ld_co(xi + size_t(j[u]) * KB + c) : T(0);
-    if constexpr (POLL) {
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (j[u] >= 0 && is_pending(xv[u])) xv[u] = poll_value(xi + size_t(j[u]) * KB + c, ls);
+    for (int u = 0; u < kU; ++u) {
+      ptr[u] = j[u] >= 0 ? xi + size_t(j[u]) * KB + c : nullptr;
+      xv[u] = ptr[u] ? ld_co(ptr[u]) : T(0);
     }
+    if constexpr (POLL) dev::wait_ptrs<T, kU>(ptr, xv, lane, ls);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (j[u] < 0) break;
@@ -289,7 +298,7 @@ __device__ __forceinline__ void trsv_rows_multi(const TsArgs& a, int q0, int q1,
     const int rd = act ? a.Lrp[i + 1] - 1 : 0;
     const T bi = (act && colok) ? B[size_t(i) + size_t(cc) * a.ldb] : T(0);
     const T dii = act ? Lv[rd] : T(1);
-    const T s = row_multi<T, KB, true, POLL>(a.Lci, Lv, xi, r0, rd, c, bi, a.ls);
+    const T s = row_multi<T, KB, true, POLL>(a.Lci, Lv, xi, r0, rd, c, bi, lane, a.ls);
     if (act) {
       const T xv = publishable(s / dii);
       st_co(xi + size_t(i) * KB + c, xv);
@@ -313,7 +322,7 @@ __device__ __forceinline__ void spmv_rows_multi(const TsArgs& a, int q0, int q1,
     const int r = act ? a.order[q] - a.n : 0;
     const int p0 = act ? a.Arp[r] : 0;
     const int p1 = act ? a.Arp[r + 1] : 0;
-    const T s = row_multi<T, KB, false, true>(a.Aci, Av, xi, p0, p1, c, T(0), a.ls);
+    const T s = row_multi<T, KB, false, true>(a.Aci, Av, xi, p0, p1, c, T(0), lane, a.ls);
     if (act && colok) __builtin_nontemporal_store(s, Y + size_t(r) + size_t(cc) * a.ldy);
   }
 }

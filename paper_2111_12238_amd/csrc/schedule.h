@@ -58,6 +58,10 @@ struct DeviceBuffers {
   int32_t* state = nullptr;
   void* xi = nullptr;           // interleaved right-hand-side workspace
   size_t xi_bytes = 0;
+  // multi-RHS plan: the level items split into pieces of units_rpb rows
+  void* units = nullptr;
+  int32_t *unit_ptr = nullptr, *unit_trsv = nullptr;
+  int32_t units_rpb = 0, n_units = 0, n_unit_trsv = 0;
   uint32_t epoch = 0;
 };
 

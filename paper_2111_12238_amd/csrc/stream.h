@@ -63,6 +63,36 @@ __device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&
   }
 }
 
+// As wait_ready, for values at arbitrary addresses p[e] (nullptr: unused
+// slot), e.g. interleaved multi-column vectors or factor entries.  The
+// watched value is the pending one at the highest address.
+template <typename T, int R>
+__device__ __forceinline__ void wait_ptrs(const T* (&p)[R], T (&v)[R], int lane, const LaunchState& ls) {
+  for (;;) {
+    unsigned long long best = 0;
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (p[e] && is_pending(v[e])) best = max(best, (unsigned long long)p[e]);
+    if (__ballot(best != 0) == 0) return;
+    unsigned long long wbest = best;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1)
+      wbest = max(wbest, (unsigned long long)__shfl_xor((long long)wbest, d, 64));
+    const int leader = __ffsll(static_cast<long long>(__ballot(best == wbest))) - 1;
+    if (lane == leader) {
+      const T* w = reinterpret_cast<const T*>(wbest);
+      const T got = poll_value(w, ls);
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (p[e] == w) v[e] = got;
+    }
+    if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
+#pragma unroll
+    for (int e = 0; e < R; ++e)
+      if (p[e] && is_pending(v[e])) v[e] = ld_co(p[e]);
+  }
+}
+
 // VEC: 0 = vec final and read through the caches, 1 = vec final but written
 // in this launch by another kernel phase (device-coherent read), 2 = vec
 // produced concurrently (device-coherent read + readiness protocol).
