@@ -665,11 +665,21 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   return hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st));
 }
 
+// Right-hand sides per block of the multi-RHS solve (1 for a single one).
+int solve_kb(const sf_schedule_s* s, int nrhs) {
+  if (nrhs == 1) return 1;
+  return s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
+}
+
 size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs) {
   if (!s) return 0;
-  const size_t nk = size_t(std::max<int64_t>(s->n, 1)) * size_t(std::max(nrhs, 1));
-  // r32 | d32 | x ping | x pong | max-abs accumulators
-  return nk * 4 * 2 + nk * 8 * 2 + 2 * 64 * 8 + 4 * 256;
+  const int k = std::max(nrhs, 1);
+  const int kb = solve_kb(s, k);
+  const size_t n = size_t(std::max<int64_t>(s->n, 1));
+  const size_t nk = n * size_t(k), nkp = n * size_t((k + kb - 1) / kb * kb);
+  auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+  // r32 | d32 | x ping | x pong (interleaved, padded to whole blocks) | max-abs accumulators
+  return 2 * align(nk * 4) + 2 * align(nkp * 8) + 2 * 64 * 8;
 }
 
 sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64, const double* A64,
@@ -685,15 +695,21 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   hipStream_t st = static_cast<hipStream_t>(stream);
   sf_status r = upload(s, st);
   if (r != SF_OK) return r;
+  const int kb = solve_kb(s, nrhs);
   const size_t nk = size_t(s->n) * size_t(nrhs);
+  const size_t nkp = size_t(s->n) * size_t((nrhs + kb - 1) / kb * kb);
   auto align = [](size_t v) { return (v + 255) / 256 * 256; };
   char* w = static_cast<char*>(workspace);
   float* r32 = reinterpret_cast<float*>(w);
   float* d32 = reinterpret_cast<float*>(w + align(nk * 4));
   double* xa = reinterpret_cast<double*>(w + 2 * align(nk * 4));
-  double* xb = reinterpret_cast<double*>(w + 2 * align(nk * 4) + align(nk * 8));
-  unsigned long long* mx = reinterpret_cast<unsigned long long*>(w + 2 * align(nk * 4) + 2 * align(nk * 8));
+  double* xb = reinterpret_cast<double*>(w + 2 * align(nk * 4) + align(nkp * 8));
+  unsigned long long* mx = reinterpret_cast<unsigned long long*>(w + 2 * align(nk * 4) + 2 * align(nkp * 8));
   const int n = int32_t(s->n);
+  // The correction d of a solve, in the interleaved layout: a single
+  // right-hand side is its own layout; several are read from the solve's
+  // interleaved workspace, which holds the same values as X.
+  auto correction = [&]() -> const float* { return nrhs == 1 ? d32 : static_cast<const float*>(s->dev.xi); };
   // 1. x0 = L32^{-1} b in FP32 (b rounded to FP32)
   SF_HIP(launch_convert_f64_f32(B, ldb, r32, n, nrhs, st));
   r = exec_ts_fused(s, SF_F32, L32, nullptr, r32, n, nrhs, d32, n, nullptr, 0, st);
@@ -706,13 +722,14 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
     ra.n = n;
     ra.m = int32_t(s->m);
     ra.nrhs = nrhs;
+    ra.kb = kb;
     ra.Lrp = s->dev.Lrp;
     ra.Lci = s->dev.Lci;
     ra.L64 = L64;
     ra.B = B;
     ra.ldb = ldb;
     ra.xin = xin;
-    ra.d = d32;
+    ra.d = correction();
     ra.xout = xout;
     ra.ldxo = n;
     ra.r32 = r32;
@@ -728,6 +745,7 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   fa.n = n;
   fa.m = Y ? int32_t(s->m) : 0;
   fa.nrhs = nrhs;
+  fa.kb = kb;
   fa.Lrp = s->dev.Lrp;
   fa.Lci = s->dev.Lci;
   fa.L64 = L64;
@@ -737,7 +755,7 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   fa.B = B;
   fa.ldb = ldb;
   fa.xin = xin;
-  fa.d = d32;
+  fa.d = correction();
   fa.xout = X;
   fa.ldxo = ldx;
   fa.r32 = nullptr;

@@ -5,70 +5,99 @@
 //              buffer so rows never read a partly updated iterate.
 //   final:     x_final = x + d, y = A64 x_final and r = b - L64 x_final in
 //              FP64, plus max_i |r_i| and max_i |b_i| per column.
-// Eight lanes per row (a whole 8-lane group always shares one row, so the
-// group sums stay inside one branch); no dependences: all reads are of
-// finished data.
+// The iterate and the correction are kept in the interleaved block layout
+// of the multi-RHS solve (ResArgs), so one gather of a column index brings
+// the KB values of a block's right-hand sides together.  KB lanes per row,
+// one per right-hand side of the block, 64 / KB rows per wavefront; each
+// lane runs its row's entries kR at a time (indices and values, then the
+// iterate).  No dependences: every read is of finished data.
 #include "dev_common.h"
 
 namespace sf {
 namespace {
 
-constexpr int kG = 8;
-using dev::group_sum;
+constexpr int kR = 8;
 
-__device__ __forceinline__ double xval(const ResArgs& a, size_t k) {
+template <int KB>
+struct Layout {
+  int32_t n;
+  size_t boff;  // offset of (row 0, this lane's column) in the interleaved arrays
+  __device__ __forceinline__ size_t at(int j) const { return boff + size_t(j) * KB; }
+};
+
+template <int KB>
+__device__ __forceinline__ double xval(const ResArgs& a, const Layout<KB>& lay, int j) {
+  const size_t k = lay.at(j);
   double v = a.xin ? a.xin[k] : 0.0;
   if (a.d) v += double(a.d[k]);
   return v;
 }
 
-// Maxima of |r| and |b| are kept as bit patterns: non-negative doubles
-// order like their bit patterns.
+// sum_p val[p] * (x + d)(col[p]) over p in [p0, p1), ascending
+template <int KB>
+__device__ __forceinline__ double row_dot(const ResArgs& a, const Layout<KB>& lay, const int32_t* __restrict__ col,
+                                          const double* __restrict__ val, int p0, int p1) {
+  double s = 0.0;
+  for (int c0 = p0; c0 < p1; c0 += kR) {
+    int j[kR];
+    double v[kR], x[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      const bool h = c0 + u < p1;
+      j[u] = h ? col[c0 + u] : -1;
+      v[u] = h ? val[c0 + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kR; ++u) x[u] = j[u] >= 0 ? xval<KB>(a, lay, j[u]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < kR; ++u) s += v[u] * x[u];
+  }
+  return s;
+}
 
-// The final pass keeps the per-column maxima of a block in LDS and issues one
-// device atomic per column and block at the end (64 right-hand sides max).
-template <bool FINAL>
+// Maxima of |r| and |b| are kept as bit patterns (non-negative doubles order
+// like their bit patterns): per block in LDS, then one device atomic per
+// column and block (64 right-hand sides at most).
+template <bool FINAL, int KB>
 __global__ __launch_bounds__(kBlockThreads) void k_resid(ResArgs a) {
-  constexpr int RPB = 64 / kG;
+  constexpr int RPW = 64 / KB;
   __shared__ unsigned long long smax[FINAL ? 2 * 64 : 1];
   const int lane = threadIdx.x & 63;
-  const int sub = lane & (kG - 1);
+  const int c = lane % KB;
   const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
   const int rows = FINAL ? max(a.n, a.m) : a.n;
+  const int nblk = (a.nrhs + KB - 1) / KB;
+  const int ngroups = (rows + RPW - 1) / RPW;
   if (FINAL) {
     for (int k = threadIdx.x; k < 2 * 64; k += kBlockThreads) smax[k] = 0ull;
     __syncthreads();
   }
-  for (int base = wave * RPB; base < rows; base += nwaves * RPB) {
-    const int i = base + lane / kG;
-    for (int c = 0; c < a.nrhs; ++c) {
-      const size_t off = size_t(c) * size_t(a.n);
-      double rmax = 0.0, bmax = 0.0;
-      if (i < a.n) {
-        double s = 0.0;
-        for (int p = a.Lrp[i] + sub; p < a.Lrp[i + 1]; p += kG) s += a.L64[p] * xval(a, off + a.Lci[p]);
-        s = group_sum<kG>(s);
-        const double b = a.B[size_t(i) + size_t(c) * a.ldb];
-        const double r = b - s;
-        if (sub == 0) {
-          a.xout[size_t(i) + size_t(c) * a.ldxo] = xval(a, off + i);
-          if (a.r32) a.r32[off + i] = float(r);
-        }
-        rmax = r;
-        bmax = b;
-      }
+  for (int u = wave; u < ngroups * nblk; u += nwaves) {
+    const int blk = u % nblk;
+    const int i = (u / nblk) * RPW + lane / KB;
+    const int cc = blk * KB + c;
+    const bool colok = cc < a.nrhs;
+    Layout<KB> lay{a.n, size_t(blk) * size_t(a.n) * KB + c};
+    if (i < a.n) {
+      const double s = row_dot<KB>(a, lay, a.Lci, a.L64, a.Lrp[i], a.Lrp[i + 1]);
+      const double b = colok ? a.B[size_t(i) + size_t(cc) * a.ldb] : 0.0;
+      const double r = b - s;
+      const double xi = xval<KB>(a, lay, i);
       if (FINAL) {
-        double y = 0.0;
-        if (i < a.m)
-          for (int p = a.Arp[i] + sub; p < a.Arp[i + 1]; p += kG) y += a.A64[p] * xval(a, off + a.Aci[p]);
-        y = group_sum<kG>(y);
-        if (i < a.m && sub == 0) a.Y[size_t(i) + size_t(c) * a.ldy] = y;
-        if (i < a.n && sub == 0) {
-          atomicMax(&smax[2 * c], (unsigned long long)__double_as_longlong(fabs(rmax)));
-          atomicMax(&smax[2 * c + 1], (unsigned long long)__double_as_longlong(fabs(bmax)));
+        if (colok) {
+          a.xout[size_t(i) + size_t(cc) * a.ldxo] = xi;
+          atomicMax(&smax[2 * cc], (unsigned long long)__double_as_longlong(fabs(r)));
+          atomicMax(&smax[2 * cc + 1], (unsigned long long)__double_as_longlong(fabs(b)));
         }
+      } else {
+        a.xout[lay.at(i)] = xi;
+        if (colok) a.r32[size_t(i) + size_t(cc) * a.n] = float(r);
       }
+    }
+    if (FINAL && a.Y && i < a.m) {
+      const double y = row_dot<KB>(a, lay, a.Aci, a.A64, a.Arp[i], a.Arp[i + 1]);
+      if (colok) a.Y[size_t(i) + size_t(cc) * a.ldy] = y;
     }
   }
   if (FINAL) {
@@ -93,25 +122,29 @@ __global__ void k_fill_u64(unsigned long long* p, int32_t count) {
   if (k < count) p[k] = 0ull;
 }
 
-int grid_for(int rows) {
-  const int per_block = (kBlockThreads / 64) * (64 / kG);
-  int g = (rows + per_block - 1) / per_block;
-  return g < 1 ? 1 : (g > 8192 ? 8192 : g);
+template <bool FINAL>
+hipError_t launch_resid(const ResArgs& a, hipStream_t st) {
+  const int rows = FINAL ? (a.n > a.m ? a.n : a.m) : a.n;
+  const int kb = a.kb;
+  const size_t units = size_t((rows + 64 / kb - 1) / (64 / kb)) * size_t((a.nrhs + kb - 1) / kb);
+  size_t g = (units + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
+  // the final pass issues one maxima atomic per column and block: cap its grid
+  g = g < 1 ? 1 : (g > (FINAL ? 2048 : 8192) ? (FINAL ? 2048 : 8192) : g);
+#define SF_RS(KB)                                                                         \
+  if (kb == KB) {                                                                         \
+    hipLaunchKernelGGL((k_resid<FINAL, KB>), dim3(unsigned(g)), dim3(kBlockThreads), 0, st, a); \
+    return hipGetLastError();                                                             \
+  }
+  SF_RS(1) SF_RS(2) SF_RS(4) SF_RS(8) SF_RS(16) SF_RS(32) SF_RS(64)
+#undef SF_RS
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_residual(const ResArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_resid<false>), dim3(grid_for(a.n)), dim3(kBlockThreads), 0, st, a);
-  return hipGetLastError();
-}
+hipError_t launch_residual(const ResArgs& a, hipStream_t st) { return launch_resid<false>(a, st); }
 
-hipError_t launch_final(const ResArgs& a, hipStream_t st) {
-  int grid = grid_for(a.n > a.m ? a.n : a.m);
-  grid = grid > 2048 ? 2048 : grid;  // bounds the number of per-block maxima atomics
-  hipLaunchKernelGGL((k_resid<true>), dim3(grid), dim3(kBlockThreads), 0, st, a);
-  return hipGetLastError();
-}
+hipError_t launch_final(const ResArgs& a, hipStream_t st) { return launch_resid<true>(a, st); }
 
 hipError_t launch_convert_f64_f32(const double* src, int32_t lds, float* dst, int32_t n, int32_t nrhs,
                                   hipStream_t st) {

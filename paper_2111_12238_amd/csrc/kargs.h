@@ -91,19 +91,23 @@ struct BwdArgs {
 };
 
 // Refinement passes (FP64 residual, final product).
+// Interleaved blocks: element (j, c) of an n x (nblk * kb) array lives at
+// ((c / kb) * n + j) * kb + c % kb, so the kb columns of a block are
+// contiguous for each row (the multi-RHS solve keeps its solution so).
 struct ResArgs {
   int32_t n, m, nrhs;
+  int32_t kb;          // block width of the interleaved arrays = lanes per row
   const int32_t *Lrp, *Lci;
   const double* L64;
   const int32_t *Arp, *Aci;
   const double* A64;
-  const double* B;
+  const double* B;     // column-major, ld ldb
   int32_t ldb;
-  const double* xin;   // n x nrhs (ld n) current iterate, nullptr = 0
-  const float* d;      // n x nrhs (ld n) correction to add, nullptr = none
-  double* xout;        // n x nrhs updated iterate (ld = ldxo)
+  const double* xin;   // interleaved current iterate, nullptr = 0
+  const float* d;      // interleaved correction to add, nullptr = none
+  double* xout;        // residual pass: interleaved new iterate; final pass: X column-major (ld ldxo)
   int32_t ldxo;
-  float* r32;          // n x nrhs residual (ld n), nullptr = not needed
+  float* r32;          // n x nrhs residual, column-major (ld n); nullptr = not needed
   double* Y;           // final product (ld ldy), nullptr = none
   int32_t ldy;
   unsigned long long* maxabs;  // 2 * nrhs: max |r| and max |b| bit patterns
