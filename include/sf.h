@@ -126,6 +126,10 @@ typedef struct {
   int32_t max_local_depth; /* most wavefronts spanned by one coarsened item */
   double est_level_us;     /* critical-path estimates (microseconds) the inspector compares: */
   double est_chunk_us;     /*   one wavefront per item vs coarsened items */
+  int32_t back_coarsened;  /* the same choice for the backward (transposed) solve */
+  int32_t back_chunk_chain;
+  double est_back_level_us;
+  double est_back_chunk_us;
 } sf_schedule_stats;
 
 /*
@@ -183,9 +187,16 @@ sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int3
 sf_status sf_schedule_export_local(sf_schedule s, uint8_t* local_level, uint8_t* entry_slot);
 
 /* Backward (transposed-solve) schedule: rlevel[n], order[n] (rows),
- * item_ptr[n_back_items + 1].  SF_ERR_ARG if it was not built. */
+ * item_ptr[n_back_items + 1] of the plan sf_backward runs (coarsened items
+ * when sf_schedule_stats.back_coarsened is 1).  SF_ERR_ARG if it was not
+ * built. */
 sf_status sf_schedule_export_backward(sf_schedule s, int32_t* rlevel, int32_t* order,
                                       int32_t* item_ptr);
+
+/* Item-local structure of the backward plan, as sf_schedule_export_local:
+ * local_level[n] per claim position, entry_slot[nnz(L)] per stored entry of
+ * L^T in its CSR order (the diagonal first in each row; 0xFF outside). */
+sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level, uint8_t* entry_slot);
 
 /*
  * sf_exec_trsv_spmv — fused SpTRSV -> SpMV (Sec. 1; Table 2, comb. 4, with a

@@ -66,7 +66,9 @@ class ScheduleStats(ctypes.Structure):
                 ("reuse_ratio", ctypes.c_double), ("inspect_seconds", ctypes.c_double),
                 ("coarsened", ctypes.c_int32), ("chunk_items", ctypes.c_int32),
                 ("chunk_chain", ctypes.c_int32), ("max_local_depth", ctypes.c_int32),
-                ("est_level_us", ctypes.c_double), ("est_chunk_us", ctypes.c_double)]
+                ("est_level_us", ctypes.c_double), ("est_chunk_us", ctypes.c_double),
+                ("back_coarsened", ctypes.c_int32), ("back_chunk_chain", ctypes.c_int32),
+                ("est_back_level_us", ctypes.c_double), ("est_back_chunk_us", ctypes.c_double)]
 
 
 _LIB = None
@@ -79,6 +81,7 @@ _SIGS = {
     "sf_schedule_info": [_P, ctypes.POINTER(ScheduleStats)],
     "sf_schedule_export": [_P, _P, _P, _P],
     "sf_schedule_export_local": [_P, _P, _P],
+    "sf_schedule_export_backward_local": [_P, _P, _P],
     "sf_schedule_export_backward": [_P, _P, _P, _P],
     "sf_exec_trsv_spmv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P],
     "sf_exec_unfused_trsv_spmv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P],
@@ -202,6 +205,17 @@ class Schedule:
         _check(_lib().sf_schedule_export_local(self.handle, loc.ctypes.data, slot.ctypes.data),
                "sf_schedule_export_local")
         return loc[:nids], slot[:int(st.nnz_l)]
+
+    def export_backward_local(self):
+        """(local_level[n], entry_slot[nnz(L)]) of the backward plan; entry
+        slots are in the CSR order of L^T."""
+        st = self.info()
+        n = int(st.n)
+        loc = np.empty(max(n, 1), np.uint8)
+        slot = np.empty(max(int(st.nnz_l), 1), np.uint8)
+        _check(_lib().sf_schedule_export_backward_local(self.handle, loc.ctypes.data, slot.ctypes.data),
+               "sf_schedule_export_backward_local")
+        return loc[:n], slot[:int(st.nnz_l)]
 
     def export_backward(self):
         st = self.info()

@@ -95,6 +95,8 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oPp = pk.add(&s->pair_ptr), oPu = pk.add(&s->pair_u), oPq = pk.add(&s->pair_q);
   const size_t oCo = pk.add(&s->corder), oCip = pk.add(&s->citem_ptr), oCti = pk.add(&s->ctrsv_items);
   const size_t oCl = pk.add(&s->clloc), oCe = pk.add(&s->celoc);
+  const size_t oBco = pk.add(&s->bcorder), oBcip = pk.add(&s->bcitem_ptr);
+  const size_t oBcl = pk.add(&s->bclloc), oBce = pk.add(&s->bceloc);
   void* block = nullptr;
   SF_HIP(hipMalloc(&block, pk.off));
   char* b = static_cast<char*>(block);
@@ -117,6 +119,9 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.corder = P(oCo); d.citem_ptr = P(oCip); d.ctrsv_items = P(oCti);
   d.clloc = reinterpret_cast<uint8_t*>(b + oCl);
   d.celoc = reinterpret_cast<uint8_t*>(b + oCe);
+  d.bcorder = P(oBco); d.bcitem_ptr = P(oBcip);
+  d.bclloc = reinterpret_cast<uint8_t*>(b + oBcl);
+  d.bceloc = reinterpret_cast<uint8_t*>(b + oBce);
   if (!d.state) {
     std::vector<int32_t> init(kStateWords, 0);
     for (int p = 0; p < 2; ++p) init[info_off(p)] = kInfoNone;
@@ -440,7 +445,7 @@ sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st) {
   st->joint_depth = s->joint_depth;
   st->back_depth = s->back_depth;
   st->n_items = int32_t(s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
-  st->n_back_items = s->has_back ? int32_t(s->bitem_ptr.size()) - 1 : 0;
+  st->n_back_items = s->has_back ? int32_t((s->bchunked ? s->bcitem_ptr : s->bitem_ptr).size()) - 1 : 0;
   st->max_level_width = s->max_level_width;
   st->lanes_per_row = s->lanes_trsv;
   st->lanes_per_spmv = s->lanes_spmv;
@@ -452,6 +457,10 @@ sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st) {
   st->max_local_depth = s->max_local_depth;
   st->est_level_us = s->est_level_us;
   st->est_chunk_us = s->est_chunk_us;
+  st->back_coarsened = s->bchunked ? 1 : 0;
+  st->back_chunk_chain = s->back_chunk_chain;
+  st->est_back_level_us = s->est_back_level_us;
+  st->est_back_chunk_us = s->est_back_chunk_us;
   return SF_OK;
 }
 
@@ -494,9 +503,24 @@ sf_status sf_schedule_export_local(sf_schedule s, uint8_t* local_level, uint8_t*
 
 sf_status sf_schedule_export_backward(sf_schedule s, int32_t* rlevel, int32_t* order, int32_t* item_ptr) {
   if (!s || !s->has_back) return SF_ERR_ARG;
+  const std::vector<int32_t>& o = s->bchunked ? s->bcorder : s->border;
+  const std::vector<int32_t>& ip = s->bchunked ? s->bcitem_ptr : s->bitem_ptr;
   if (rlevel) std::copy(s->rlevel.begin(), s->rlevel.end(), rlevel);
-  if (order) std::copy(s->border.begin(), s->border.end(), order);
-  if (item_ptr) std::copy(s->bitem_ptr.begin(), s->bitem_ptr.end(), item_ptr);
+  if (order) std::copy(o.begin(), o.end(), order);
+  if (item_ptr) std::copy(ip.begin(), ip.end(), item_ptr);
+  return SF_OK;
+}
+
+sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level, uint8_t* entry_slot) {
+  if (!s || !s->has_back) return SF_ERR_ARG;
+  if (local_level) {
+    if (s->bchunked) std::copy(s->bclloc.begin(), s->bclloc.end(), local_level);
+    else std::fill(local_level, local_level + size_t(s->n), uint8_t(0));
+  }
+  if (entry_slot) {
+    if (s->bchunked) std::copy(s->bceloc.begin(), s->bceloc.end(), entry_slot);
+    else std::fill(entry_slot, entry_slot + size_t(s->LT.nnz()), uint8_t(0xFF));
+  }
   return SF_OK;
 }
 
@@ -653,9 +677,17 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   a.Lrp = d.Lrp; a.Lci = d.Lci;
   a.Lv = L_val; a.Av = A_val; a.X = x; a.G = G;
   a.lam = grad_B; a.gradL = grad_L_val;
-  a.order = d.border;
-  a.item_ptr = d.bitem_ptr;
-  a.n_work = int32_t(s->bitem_ptr.size() - 1);
+  if (s->bchunked) {
+    a.order = d.bcorder;
+    a.item_ptr = d.bcitem_ptr;
+    a.n_work = int32_t(s->bcitem_ptr.size() - 1);
+    a.lloc = d.bclloc;
+    a.eloc = d.bceloc;
+  } else {
+    a.order = d.border;
+    a.item_ptr = d.bitem_ptr;
+    a.n_work = int32_t(s->bitem_ptr.size() - 1);
+  }
   r = next_epoch(s, st, a.ls);
   if (r != SF_OK) return r;
   const int grid = persistent_grid(s, occupancy_bwd(dt, s->lanes_trsv));
@@ -876,6 +908,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "spmv_delay") *v = s->spmv_delay;
   else if (k == "coarsen") *v = s->coarsen;
   else if (k == "coarsened") *v = s->chunked ? 1 : 0;
+  else if (k == "back_coarsened") *v = s->bchunked ? 1 : 0;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "timing") *v = s->timing;
   else if (k == "trace") *v = s->trace ? 1 : 0;

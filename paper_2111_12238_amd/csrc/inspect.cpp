@@ -131,38 +131,50 @@ static void cut_runs(const std::vector<int32_t>& order, const std::vector<int32_
 // autotuner times the two plans when the estimate is not trusted.
 constexpr double kEstHop = 1.5, kEstStep = 0.15;
 
-// Coarsened SpTRSV items by locality-greedy topological ordering.  Rows are
-// taken one at a time in a topological order (Kahn's algorithm); the
-// current item grows with the ready row that has the most predecessors
-// already in it (ties: lower level, then lower row), and closes at
-// rows_per_item rows, at the entry budget, or when no ready row touches it.
-// A new item starts from the lowest-level ready row.  Every item is a
-// contiguous run of one topological order, so every DAG edge goes from an
-// item to itself or to a later item.  On meshes this grows compact blocks
-// whose internal chains replace many dependent wavefronts.
-static void build_chunks(sf_schedule_s* s) {
-  const Pattern& L = s->L;
-  const int32_t n = L.nrows;
-  const int64_t m = s->m;
-  const int32_t R = std::max(1, std::min(s->rows_per_item, 64));
-  const int64_t budget = std::min<int64_t>(s->max_item_nnz, kChunkEntries);
+// Coarsened items by locality-greedy topological ordering.  Rows are taken
+// one at a time in a topological order (Kahn's algorithm); the current item
+// grows with the ready row that has the most predecessors already in it
+// (ties: lower level, then lower row), and closes at R rows, at the entry
+// budget, or when no ready row touches it.  A new item starts from the
+// lowest-level ready row.  Every item is a contiguous run of one
+// topological order, so every DAG edge goes from an item to itself or to a
+// later item.  On meshes this grows compact blocks whose internal chains
+// replace many dependent wavefronts.
+//
+// The DAG: row i's predecessors are ci[p] for p in [rp[i] + lo, rp[i+1] - hi)
+// (lo = 1, hi = 0 when the diagonal is stored first; lo = 0, hi = 1 when
+// last).  Item rows come out sorted by (local wavefront, row).
+struct ChunkPlan {
+  std::vector<int32_t> rows, ptr, chunk_of, slot;  // rows in item order; item boundaries
+  std::vector<uint8_t> lloc;                       // local wavefront per row (indexed by row)
+  std::vector<double> cp;                          // critical-path estimate at each item's end
+  int32_t chain = 0, maxloc = 0;
+  double cp_max = 0.0;
+};
+
+static ChunkPlan chunk_dag(int32_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, int lo,
+                           int hi, const std::vector<int32_t>& level, int32_t R, int64_t budget) {
+  ChunkPlan c;
+  auto pb = [&](int32_t i) { return rp[i] + lo; };
+  auto pe = [&](int32_t i) { return rp[i + 1] - hi; };
   std::vector<int32_t> sp(size_t(n) + 1, 0), si;
   for (int32_t i = 0; i < n; ++i)
-    for (int32_t p = L.rp[i]; p < L.rp[i + 1] - 1; ++p) sp[size_t(L.ci[p]) + 1]++;
+    for (int32_t p = pb(i); p < pe(i); ++p) sp[size_t(ci[p]) + 1]++;
   for (int32_t i = 0; i < n; ++i) sp[size_t(i) + 1] += sp[i];
   si.resize(size_t(sp[n]));
   {
     std::vector<int32_t> fill(sp.begin(), sp.end() - 1);
     for (int32_t i = 0; i < n; ++i)
-      for (int32_t p = L.rp[i]; p < L.rp[i + 1] - 1; ++p) si[size_t(fill[L.ci[p]]++)] = i;
+      for (int32_t p = pb(i); p < pe(i); ++p) si[size_t(fill[ci[p]]++)] = i;
   }
-  std::vector<int32_t> indeg(static_cast<size_t>(n)), score(static_cast<size_t>(n), 0), chunk_of(static_cast<size_t>(n), -1), touched;
-  std::vector<uint8_t> lloc(size_t(n), 0);
+  std::vector<int32_t> indeg(static_cast<size_t>(n)), score(static_cast<size_t>(n), 0), touched;
+  c.chunk_of.assign(size_t(n), -1);
+  c.lloc.assign(size_t(n), 0);
   using Key = std::pair<int64_t, int32_t>;  // (level, row)
   std::priority_queue<Key, std::vector<Key>, std::greater<Key>> ready;
   for (int32_t i = 0; i < n; ++i) {
-    indeg[i] = L.rp[i + 1] - L.rp[i] - 1;
-    if (indeg[i] == 0) ready.push({s->level[i], i});
+    indeg[i] = pe(i) - pb(i);
+    if (indeg[i] == 0) ready.push({level[i], i});
   }
   struct Cand {
     int32_t score, level, row;
@@ -173,107 +185,124 @@ static void build_chunks(sf_schedule_s* s) {
     }
   };
   std::priority_queue<Cand> cand;
-  std::vector<int32_t> rows;       // rows in chunk order (topological)
-  std::vector<int32_t> chunk_ptr;  // into rows
-  rows.reserve(size_t(n));
-  chunk_ptr.push_back(0);
+  c.rows.reserve(size_t(n));
+  c.ptr.push_back(0);
   int32_t cid = 0;
   int64_t done = 0;
+  auto cost_of = [&](int32_t i) { return int64_t(std::max(1, pe(i) - pb(i))); };
   auto add = [&](int32_t u) {
-    chunk_of[u] = cid;
+    c.chunk_of[u] = cid;
     int32_t d = 0;
-    for (int32_t p = L.rp[u]; p < L.rp[u + 1] - 1; ++p)
-      if (chunk_of[L.ci[p]] == cid) d = std::max<int32_t>(d, lloc[L.ci[p]] + 1);
-    lloc[u] = uint8_t(d);
-    rows.push_back(u);
+    for (int32_t p = pb(u); p < pe(u); ++p)
+      if (c.chunk_of[ci[p]] == cid) d = std::max<int32_t>(d, c.lloc[ci[p]] + 1);
+    c.lloc[u] = uint8_t(d);
+    c.rows.push_back(u);
     ++done;
     for (int32_t q = sp[u]; q < sp[u + 1]; ++q) {
       const int32_t v = si[q];
       if (score[v] == 0) touched.push_back(v);
       ++score[v];
-      if (--indeg[v] == 0) ready.push({s->level[v], v});
-      if (indeg[v] == 0) cand.push({score[v], s->level[v], v});
+      if (--indeg[v] == 0) {
+        ready.push({level[v], v});
+        cand.push({score[v], level[v], v});
+      }
     }
   };
   while (done < n) {
-    while (chunk_of[ready.top().second] >= 0) ready.pop();
+    while (c.chunk_of[ready.top().second] >= 0) ready.pop();
     const int32_t seed = ready.top().second;
     ready.pop();
-    int64_t cost = std::max(1, L.rp[seed + 1] - L.rp[seed] - 1);
+    int64_t cost = cost_of(seed);
     int32_t size = 1;
     add(seed);
     while (size < R && !cand.empty()) {
-      const Cand c = cand.top();
-      if (chunk_of[c.row] >= 0 || score[c.row] != c.score) {  // stale heap entry
+      const Cand k = cand.top();
+      if (c.chunk_of[k.row] >= 0 || score[k.row] != k.score) {  // stale heap entry
         cand.pop();
         continue;
       }
-      const int64_t cr = std::max(1, L.rp[c.row + 1] - L.rp[c.row] - 1);
-      if (cost + cr > budget) break;
+      if (cost + cost_of(k.row) > budget) break;
       cand.pop();
-      cost += cr;
+      cost += cost_of(k.row);
       ++size;
-      add(c.row);
+      add(k.row);
     }
     for (int32_t v : touched) score[v] = 0;
     touched.clear();
     cand = std::priority_queue<Cand>();
-    chunk_ptr.push_back(int32_t(rows.size()));
+    c.ptr.push_back(int32_t(c.rows.size()));
     ++cid;
   }
   const int32_t nc = cid;
-
-  // Each item's rows sorted by (local wavefront, row); slot = position.
-  std::vector<int32_t> slot(size_t(n), 0);
-  int32_t maxloc = 0;
-  for (int32_t c = 0; c < nc; ++c) {
-    auto b = rows.begin() + chunk_ptr[c], e = rows.begin() + chunk_ptr[c + 1];
-    std::sort(b, e, [&](int32_t x, int32_t y) { return lloc[x] != lloc[y] ? lloc[x] < lloc[y] : x < y; });
-    for (int32_t k = chunk_ptr[c]; k < chunk_ptr[c + 1]; ++k) {
-      slot[rows[k]] = k - chunk_ptr[c];
-      maxloc = std::max<int32_t>(maxloc, lloc[rows[k]]);
+  c.slot.assign(size_t(n), 0);
+  for (int32_t k = 0; k < nc; ++k) {
+    auto b = c.rows.begin() + c.ptr[k], e = c.rows.begin() + c.ptr[k + 1];
+    std::sort(b, e, [&](int32_t x, int32_t y) { return c.lloc[x] != c.lloc[y] ? c.lloc[x] < c.lloc[y] : x < y; });
+    for (int32_t q = c.ptr[k]; q < c.ptr[k + 1]; ++q) {
+      c.slot[c.rows[q]] = q - c.ptr[k];
+      c.maxloc = std::max<int32_t>(c.maxloc, c.lloc[c.rows[q]]);
     }
   }
   // Critical-path estimate over the item graph (item ids are topological).
-  std::vector<double> cp(size_t(nc), 0.0);
+  c.cp.assign(size_t(nc), 0.0);
   std::vector<int32_t> chain(size_t(nc), 1);
-  double cp_trsv = 0.0;
-  int32_t longest = 0;
-  for (int32_t c = 0; c < nc; ++c) {
+  for (int32_t k = 0; k < nc; ++k) {
     double in = 0.0;
-    int32_t ch = 0;
-    int32_t depth_c = 0;
-    for (int32_t k = chunk_ptr[c]; k < chunk_ptr[c + 1]; ++k) {
-      const int32_t u = rows[k];
-      depth_c = std::max<int32_t>(depth_c, lloc[u] + 1);
-      for (int32_t p = L.rp[u]; p < L.rp[u + 1] - 1; ++p) {
-        const int32_t pc = chunk_of[L.ci[p]];
-        if (pc != c) {
-          in = std::max(in, cp[pc]);
+    int32_t ch = 0, depth_k = 0;
+    for (int32_t q = c.ptr[k]; q < c.ptr[k + 1]; ++q) {
+      const int32_t u = c.rows[q];
+      depth_k = std::max<int32_t>(depth_k, c.lloc[u] + 1);
+      for (int32_t p = pb(u); p < pe(u); ++p) {
+        const int32_t pc = c.chunk_of[ci[p]];
+        if (pc != k) {
+          in = std::max(in, c.cp[pc]);
           ch = std::max(ch, chain[pc]);
         }
       }
     }
-    cp[c] = in + kEstHop + kEstStep * depth_c;
-    chain[c] = ch + 1;
-    cp_trsv = std::max(cp_trsv, cp[c]);
-    longest = std::max(longest, chain[c]);
+    c.cp[k] = in + kEstHop + kEstStep * depth_k;
+    chain[k] = ch + 1;
+    c.cp_max = std::max(c.cp_max, c.cp[k]);
+    c.chain = std::max(c.chain, chain[k]);
   }
-  // SpMV rows: after the item holding their last input (plus the slack
-  // delay, in items of a typical chain step).
+  return c;
+}
+
+// Per stored entry p of a row: the slot of its column inside the row's item,
+// or 0xFF (other item, or the diagonal).
+static std::vector<uint8_t> entry_slots(const ChunkPlan& c, int32_t n, const std::vector<int32_t>& rp,
+                                        const std::vector<int32_t>& ci, int lo, int hi) {
+  std::vector<uint8_t> e(rp.empty() ? 0 : size_t(rp[n]), 0xFF);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = rp[i] + lo; p < rp[i + 1] - hi; ++p)
+      if (c.chunk_of[ci[p]] == c.chunk_of[i]) e[size_t(p)] = uint8_t(c.slot[ci[p]]);
+  return e;
+}
+
+// Forward coarsened plan: SpTRSV items from chunk_dag over L; SpMV rows
+// follow the item holding their last input (plus the slack delay, in items
+// of a typical chain step).
+static void build_chunks(sf_schedule_s* s) {
+  const Pattern& L = s->L;
+  const int32_t n = L.nrows;
+  const int64_t m = s->m;
+  const int32_t R = std::max(1, std::min(s->rows_per_item, 64));
+  const int64_t budget = std::min<int64_t>(s->max_item_nnz, kChunkEntries);
+  const ChunkPlan c = chunk_dag(n, L.rp, L.ci, 0, 1, s->level, R, budget);
+  const int32_t nc = int32_t(c.ptr.size()) - 1;
   std::vector<int32_t> skey(size_t(m), -1);
-  double cp_all = cp_trsv;
+  double cp_all = c.cp_max;
   for (int64_t r = 0; r < m; ++r) {
     double in = 0.0;
     for (int32_t p = s->A.rp[r]; p < s->A.rp[r + 1]; ++p) {
-      const int32_t c = chunk_of[s->A.ci[p]];
-      skey[r] = std::max(skey[r], c);
-      in = std::max(in, cp[c]);
+      const int32_t k = c.chunk_of[s->A.ci[p]];
+      skey[r] = std::max(skey[r], k);
+      in = std::max(in, c.cp[k]);
     }
     cp_all = std::max(cp_all, in + kEstHop);
   }
   if (s->spmv_delay > 0 && nc > 0) {
-    const int64_t per_step = std::max<int64_t>(1, nc / std::max(1, longest));
+    const int64_t per_step = std::max<int64_t>(1, nc / std::max(1, c.chain));
     for (int64_t r = 0; r < m; ++r)
       skey[r] = int32_t(std::min<int64_t>(int64_t(skey[r]) + int64_t(s->spmv_delay) * per_step, nc - 1));
   }
@@ -295,13 +324,13 @@ static void build_chunks(sf_schedule_s* s) {
     int32_t q = bucket[b];
     const int32_t e = bucket[b + 1];
     while (q < e) {
-      int64_t c = 0;
+      int64_t cost = 0;
       int32_t k = q;
       while (k < e && k - q < R) {
         const int32_t r = sorder[k];
         const int64_t cr = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
-        if (k > q && c + cr > s->max_item_nnz) break;
-        c += cr;
+        if (k > q && cost + cr > s->max_item_nnz) break;
+        cost += cr;
         ++k;
       }
       for (int32_t t = q; t < k; ++t) {
@@ -313,23 +342,50 @@ static void build_chunks(sf_schedule_s* s) {
     }
   };
   spmv_run(0);
-  for (int32_t c = 0; c < nc; ++c) {
-    for (int32_t k = chunk_ptr[c]; k < chunk_ptr[c + 1]; ++k) {
-      s->corder.push_back(rows[k]);
-      s->clloc.push_back(lloc[rows[k]]);
+  for (int32_t k = 0; k < nc; ++k) {
+    for (int32_t q = c.ptr[k]; q < c.ptr[k + 1]; ++q) {
+      s->corder.push_back(c.rows[q]);
+      s->clloc.push_back(c.lloc[c.rows[q]]);
     }
     s->ctrsv_items.push_back(int32_t(s->citem_ptr.size()) - 1);
     s->citem_ptr.push_back(int32_t(s->corder.size()));
-    spmv_run(c + 1);
+    spmv_run(k + 1);
   }
-  // Per stored entry of L: slot of its column in the row's item, or 0xFF.
-  s->celoc.assign(size_t(L.nnz()), 0xFF);
-  for (int32_t i = 0; i < n; ++i)
-    for (int32_t p = L.rp[i]; p < L.rp[i + 1] - 1; ++p)
-      if (chunk_of[L.ci[p]] == chunk_of[i]) s->celoc[size_t(p)] = uint8_t(slot[L.ci[p]]);
-  s->chunk_chain = longest;
-  s->max_local_depth = nc > 0 ? maxloc + 1 : 0;
+  s->celoc = entry_slots(c, n, L.rp, L.ci, 0, 1);
+  s->chunk_chain = c.chain;
+  s->max_local_depth = nc > 0 ? c.maxloc + 1 : 0;
   s->est_chunk_us = cp_all;
+}
+
+// Backward coarsened plan: chunk_dag over L^T (the transposed solve's
+// predecessors of row i are the rows j > i with L_ji stored; the diagonal is
+// stored first in each row of L^T).
+static void build_back_chunks(sf_schedule_s* s) {
+  const int32_t n = int32_t(s->n);
+  const int32_t R = std::max(1, std::min(s->rows_per_item, 64));
+  const int64_t budget = std::min<int64_t>(s->max_item_nnz, kChunkEntries);
+  const ChunkPlan c = chunk_dag(n, s->LT.rp, s->LT.ci, 1, 0, s->rlevel, R, budget);
+  s->bcorder = c.rows;
+  s->bcitem_ptr = c.ptr;
+  s->bclloc.resize(size_t(n));
+  for (int32_t q = 0; q < n; ++q) s->bclloc[q] = c.lloc[c.rows[q]];
+  s->bceloc = entry_slots(c, n, s->LT.rp, s->LT.ci, 1, 0);
+  s->back_chunk_chain = c.chain;
+  s->est_back_chunk_us = c.cp_max;
+}
+
+// Fraction test of the auto mode: coarsening pays where most edges join
+// consecutive wavefronts (mesh-like DAGs, whose chains a compact item can
+// absorb); on DAGs whose edges skip many wavefronts it is not estimated.
+static bool mesh_like(int64_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, int lo, int hi,
+                      const std::vector<int32_t>& level) {
+  int64_t tight = 0, edges = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t p = rp[i] + lo; p < rp[i + 1] - hi; ++p) {
+      ++edges;
+      tight += level[i] == level[ci[p]] + 1;
+    }
+  return edges > 0 && double(tight) >= 0.35 * double(edges);
 }
 
 void cut_items(sf_schedule_s* s) {
@@ -371,19 +427,7 @@ void cut_items(sf_schedule_s* s) {
     s->chunk_chain = 0;
     s->max_local_depth = 0;
     s->est_chunk_us = 0.0;
-    // Coarsening pays where most edges join consecutive wavefronts (mesh-like
-    // DAGs, whose chains a compact item can absorb); on DAGs whose edges skip
-    // many wavefronts the estimate is not even computed in auto mode.
-    bool try_chunks = s->coarsen == 2;
-    if (s->coarsen == 0 && n > 0) {
-      int64_t tight = 0, edges = 0;
-      for (int64_t i = 0; i < n; ++i)
-        for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p) {
-          ++edges;
-          tight += s->level[i] == s->level[s->L.ci[p]] + 1;
-        }
-      try_chunks = edges > 0 && double(tight) >= 0.35 * double(edges);
-    }
+    const bool try_chunks = s->coarsen == 2 || (s->coarsen == 0 && mesh_like(n, s->L.rp, s->L.ci, 0, 1, s->level));
     if (try_chunks && n > 0) build_chunks(s);
     s->chunked = !s->ctrsv_items.empty() &&
                  (s->coarsen == 2 || s->est_chunk_us < 0.8 * s->est_level_us);
@@ -421,6 +465,18 @@ void cut_items(sf_schedule_s* s) {
                 (s->L.rp[i + 1] - s->L.rp[i]);
     }
     cut_runs(s->border, key, cost, s->rows_per_item, s->max_item_nnz, s->bitem_ptr);
+    s->est_back_level_us = double(s->back_depth) * (kEstHop + kEstStep);
+    s->bcorder.clear();
+    s->bcitem_ptr.clear();
+    s->bclloc.clear();
+    s->bceloc.clear();
+    s->back_chunk_chain = 0;
+    s->est_back_chunk_us = 0.0;
+    const bool try_back = s->coarsen == 2 ||
+                          (s->coarsen == 0 && mesh_like(n, s->LT.rp, s->LT.ci, 1, 0, s->rlevel));
+    if (try_back && n > 0) build_back_chunks(s);
+    s->bchunked = !s->bcitem_ptr.empty() &&
+                  (s->coarsen == 2 || s->est_back_chunk_us < 0.8 * s->est_back_level_us);
   }
 }
 
@@ -598,9 +654,43 @@ static int validate_plan(const sf_schedule_s* s, const std::vector<int32_t>& ord
   return 0;
 }
 
+// The backward plan: every edge lambda_j -> lambda_i (L_ji stored, j > i)
+// has item(j) < item(i), or (coarsened) the same item with j on an earlier
+// local wavefront and the entry's slot naming j.
+static int validate_back_plan(const sf_schedule_s* s, const std::vector<int32_t>& order,
+                              const std::vector<int32_t>& item_ptr, const std::vector<uint8_t>* lloc) {
+  const int64_t n = s->n;
+  std::vector<int32_t> item(size_t(n), -1), pos(size_t(n), -1);
+  if (item_ptr.empty() || item_ptr[0] != 0 || item_ptr.back() != n) return 11;
+  for (size_t t = 0; t + 1 < item_ptr.size(); ++t) {
+    if (item_ptr[t + 1] <= item_ptr[t]) return 12;
+    for (int32_t q = item_ptr[t]; q < item_ptr[t + 1]; ++q) {
+      const int32_t u = order[q];
+      if (u < 0 || u >= n || item[u] >= 0) return 13;
+      item[u] = int32_t(t);
+      pos[u] = q;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t p = s->LT.rp[i] + 1; p < s->LT.rp[i + 1]; ++p) {
+      const int32_t j = s->LT.ci[p];
+      if (item[j] < item[i]) {
+        if (lloc && s->bceloc[size_t(p)] != 0xFF) return 15;
+        continue;
+      }
+      if (lloc && item[j] == item[i] && (*lloc)[pos[j]] < (*lloc)[pos[i]] &&
+          s->bceloc[size_t(p)] == uint8_t(pos[j] - item_ptr[item[i]]))
+        continue;
+      return 14;
+    }
+  return 0;
+}
+
 int validate_forward(const sf_schedule_s* s) {
   int r = validate_plan(s, s->order, s->item_ptr, nullptr);
   if (r == 0 && s->chunked) r = validate_plan(s, s->corder, s->citem_ptr, &s->clloc);
+  if (r == 0 && s->has_back) r = validate_back_plan(s, s->border, s->bitem_ptr, nullptr);
+  if (r == 0 && s->bchunked) r = validate_back_plan(s, s->bcorder, s->bcitem_ptr, &s->bclloc);
   return r;
 }
 

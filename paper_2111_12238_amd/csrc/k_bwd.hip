@@ -10,7 +10,8 @@
 //   2. subtracts L_ji lambda_j for j > i in ascending j, each lambda_j
 //      observed through the value-as-flag protocol (grad_B is filled with the
 //      pending pattern before the launch and is the lambda buffer),
-//   3. divides by L_ii and publishes lambda_i,
+//   3. divides by L_ii and publishes lambda_i (coarsened items resolve
+//      their own rows' lambda values in LDS, dev::chunk_solve),
 //   4. writes grad_L[p] = -lambda_i x_k for every stored L_ik of row i of L
 //      (x is final input data).
 // The arithmetic is the sequential definition's, term by term, so FP64
@@ -30,11 +31,16 @@ using dev::st_co;
 using dev::stream_accumulate;
 using dev::WaveLds;
 
+// With a coarsened plan (a.lloc != nullptr), items whose rows span several
+// local wavefronts solve their lambda values through dev::chunk_solve.
 template <typename T>
 __global__ __launch_bounds__(kBlockThreads) void k_bwd(BwdArgs a) {
   __shared__ WaveLds<T> lds[kWaves];
+  __shared__ T lloc_x[kWaves][65];  // item-local lambda by slot; [64] = 1.0
   const int lane = threadIdx.x & 63;
   WaveLds<T>& w = lds[threadIdx.x >> 6];
+  T* xl = lloc_x[threadIdx.x >> 6];
+  if (lane == 0) xl[64] = T(1);
   const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
   const T* __restrict__ Av = static_cast<const T*>(a.Av);
   const T* __restrict__ X = static_cast<const T*>(a.X);
@@ -54,13 +60,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_bwd(BwdArgs a) {
     const T lii = mine ? Lv[a.LTmap[e0]] : T(1);
     const T c = stream_accumulate<T, false, 0, true>(nr, c0, c1 - c0, T(0), a.ATci, a.ATmap, Av, Gv, lane, w,
                                                      a.ls);
-    const T acc = stream_accumulate<T, true, 2, true>(nr, e0 + 1, e1 - (e0 + 1), c, a.LTci, a.LTmap, Lv, lam,
-                                                      lane, w, a.ls);
-    if (mine) {
-      const T li = acc / lii;
-      st_co(lam + i, publishable(li));
-      for (int p = a.Lrp[i]; p < a.Lrp[i + 1]; ++p) __builtin_nontemporal_store(-li * X[a.Lci[p]], gL + p);
+    T li;
+    if (a.lloc && a.lloc[q1 - 1] != 0) {
+      const int myloc = mine ? int(a.lloc[q0 + lane]) : 0;
+      li = dev::chunk_solve<T, true>(nr, e0 + 1, e1 - (e0 + 1), myloc, int(a.lloc[q1 - 1]), c, lii, a.LTci,
+                                     a.LTmap, Lv, a.eloc, lam, i, lane, w, xl, a.ls, nullptr);
+    } else {
+      const T acc = stream_accumulate<T, true, 2, true>(nr, e0 + 1, e1 - (e0 + 1), c, a.LTci, a.LTmap, Lv, lam,
+                                                        lane, w, a.ls);
+      li = publishable(acc / lii);
+      if (mine) st_co(lam + i, li);
     }
+    if (mine)
+      for (int p = a.Lrp[i]; p < a.Lrp[i + 1]; ++p) __builtin_nontemporal_store(-li * X[a.Lci[p]], gL + p);
     t = tn;
   }
 }

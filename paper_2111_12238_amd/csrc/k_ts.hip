@@ -77,67 +77,14 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
-// Local wavefront steps of a coarsened item.  The owner lane keeps its
-// row's first NT terms in registers: a factor pv (the rounded product for an
-// entry outside the item, L_ij for an item-local column, 0 for an unused
-// slot) and the LDS slot of the x it multiplies (xl[64] holds 1.0 for the
-// first and last kind), so a step is NT LDS reads, NT products and NT
-// subtractions with no selects; multiplying by 1.0 and subtracting +0.0 are
-// exact, so the terms and their order are still the definition's.
-template <typename T, int NT>
-__device__ __forceinline__ void chunk_steps(WaveLds<T>& w, T* xl, T* X, bool mine, int myloc, int maxloc,
-                                            int off, int len, int row, int lane, T acc, T dii) {
-  constexpr int kOne = 64;
-  T pv[NT];
-  int pq[NT];
-#pragma unroll
-  for (int u = 0; u < NT; ++u) {
-    pv[u] = T(0);
-    pq[u] = kOne;
-    if (u < len) {
-      const int q = w.pos[off + u];
-      pv[u] = w.prod[off + u];
-      pq[u] = q == 0xFF ? kOne : q;
-    }
-  }
-  for (int s = 0; s <= maxloc; ++s) {
-    if (mine && myloc == s) {
-      T xq[NT];
-#pragma unroll
-      for (int u = 0; u < NT; ++u) xq[u] = xl[pq[u]];
-#pragma unroll
-      for (int u = 0; u < NT; ++u) acc = acc - pv[u] * xq[u];
-      for (int t = off + NT; t < off + len; ++t) {
-        const int q = w.pos[t];
-        acc = acc - (q == 0xFF ? w.prod[t] : w.prod[t] * xl[q]);
-      }
-      const T x = publishable(acc / dii);
-      xl[lane] = x;
-      st_co(X + row, x);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
 // Coarsened SpTRSV item (rows on several local wavefronts, sorted by local
-// wavefront).  All off-diagonal entries are dealt to the lanes in one pass
-// (the inspector keeps an item's entries within one pass): an entry whose
-// column is a row of the same item (eloc = that row's slot) loads no x; the
-// others load x_j through the readiness protocol as in item_stream.  Then
-// the local wavefronts run in order: the owner lanes of the rows on local
-// wavefront s fold their entries in ascending column order -- a product
-// taken from LDS, or L_ij times the item's own x_j kept in LDS -- divide by
-// L_ii, keep x_i in LDS for the later wavefronts and publish it.  Every
-// product is rounded once and every row folds in ascending order, as in
-// forward substitution, so FP64 results stay bit-identical.
+// wavefront): dev::chunk_solve (stream.h) over the rows' off-diagonals.
 template <typename T>
 __device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w, T* xl,
                                            int it) {
-  static_assert(dev::kPass >= kChunkEntries, "a coarsened item must fit one stream pass");
   const int nr = q1 - q0;
   const bool mine = lane < nr;
   const T* __restrict__ val = static_cast<const T*>(a.Lv);
-  T* X = static_cast<T*>(a.X);
   unsigned long long* tr = trace_slots(a, it);
   if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
   const int row = mine ? a.order[q0 + lane] : 0;
@@ -145,58 +92,10 @@ __device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int 
   const int r1 = mine ? a.Lrp[row + 1] - 1 : 0;
   const int myloc = mine ? int(a.lloc[q0 + lane]) : 0;
   const int maxloc = int(a.lloc[q1 - 1]);
-  T acc = mine ? static_cast<const T*>(a.B)[row] : T(0);
+  const T acc = mine ? static_cast<const T*>(a.B)[row] : T(0);
   const T dii = mine ? ld_stream(val + r1) : T(1);
-  const int len = r1 - r0;
-  int incl = len;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  const int off = incl - len;
-  const int total = __shfl(incl, 63, 64);
-  if (mine)
-    for (int t = off; t < off + len; ++t) w.pos[t] = r0 + (t - off);
-  __builtin_amdgcn_wave_barrier();
-  constexpr int R = dev::kRounds;
-  int j[R];
-  T v[R], xv[R];
-  int sl[R];
-#pragma unroll
-  for (int e = 0; e < R; ++e) {
-    const int k = lane + 64 * e;
-    j[e] = -1;
-    sl[e] = 0xFF;
-    v[e] = T(0);
-    if (k < total) {
-      const int p = w.pos[k];
-      sl[e] = int(ld_stream(a.eloc + p));
-      v[e] = ld_stream(val + p);
-      if (sl[e] == 0xFF) j[e] = ld_stream(a.Lci + p);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < R; ++e) xv[e] = j[e] >= 0 ? dev::ld_co(X + j[e]) : T(0);
-  if (tr && lane == 0) tr[1] = __builtin_amdgcn_s_memrealtime();
-  dev::wait_ready<T, R>(X, j, xv, lane, a.ls);
-  // LDS: prod[k] = rounded product (external entry) or L_ij (local entry);
-  // pos[k] = slot of the local column, or 0xFF
-#pragma unroll
-  for (int e = 0; e < R; ++e) {
-    const int k = lane + 64 * e;
-    if (k < total) {
-      w.prod[k] = sl[e] == 0xFF ? v[e] * xv[e] : v[e];
-      w.pos[k] = sl[e];
-    }
-  }
-  if (tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();
-  __builtin_amdgcn_wave_barrier();
-  int maxlen = len;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, d, 64));
-  if (maxlen <= 4) chunk_steps<T, 4>(w, xl, X, mine, myloc, maxloc, off, len, row, lane, acc, dii);
-  else chunk_steps<T, 8>(w, xl, X, mine, myloc, maxloc, off, len, row, lane, acc, dii);
+  dev::chunk_solve<T, false>(nr, r0, r1 - r0, myloc, maxloc, acc, dii, a.Lci, nullptr, val, a.eloc,
+                             static_cast<T*>(a.X), row, lane, w, xl, a.ls, tr);
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 

@@ -87,6 +87,8 @@ struct BwdArgs {
   void *lam, *gradL;
   const int32_t *order, *item_ptr;
   int32_t n_work;
+  const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
+  const uint8_t* eloc;     // coarsened plan: per L^T entry, slot of its column in the item or 0xFF
   LaunchState ls;
 };
 

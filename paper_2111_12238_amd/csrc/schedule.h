@@ -52,6 +52,8 @@ struct DeviceBuffers {
   int32_t *LTrp = nullptr, *LTci = nullptr, *LTmap = nullptr;
   int32_t *ATrp = nullptr, *ATci = nullptr, *ATmap = nullptr;
   int32_t *border = nullptr, *bitem_ptr = nullptr;
+  int32_t *bcorder = nullptr, *bcitem_ptr = nullptr;
+  uint8_t *bclloc = nullptr, *bceloc = nullptr;
   // SpIC0 intersection lists
   int32_t *pair_ptr = nullptr, *pair_u = nullptr, *pair_q = nullptr;
   // mutable state
@@ -107,6 +109,12 @@ struct sf_schedule_s {
   std::vector<int32_t> LT_map, AT_map;  // entry of the transpose -> entry of the source
   std::vector<int32_t> rlevel, border, bitem_ptr;
   int32_t back_depth = 0;
+  // coarsened backward plan (as the forward one, over L^T)
+  bool bchunked = false;
+  std::vector<int32_t> bcorder, bcitem_ptr;
+  std::vector<uint8_t> bclloc, bceloc;  // per claim position; per stored L^T entry
+  int32_t back_chunk_chain = 0;
+  double est_back_level_us = 0.0, est_back_chunk_us = 0.0;
 
   // SpIC0 intersection lists, one list per stored L entry (i, j), j < i:
   // pairs (t << 16 | u, q): t = index inside row i of the entry (i, j), u =

@@ -21,6 +21,7 @@ namespace dev {
 constexpr int kRounds = 8;           // entries per lane per pass
 constexpr int kPass = 64 * kRounds;  // entries per pass of one wavefront
 constexpr int kWaves = kBlockThreads / 64;
+static_assert(kPass >= kChunkEntries, "a coarsened item must fit one stream pass");
 
 template <typename T>
 struct WaveLds {
@@ -163,6 +164,123 @@ __device__ __forceinline__ T stream_accumulate(int nr, int r0, int len, T acc, c
     __builtin_amdgcn_wave_barrier();
   }
   return acc;
+}
+
+// ---- coarsened items: rows on several local wavefronts ----
+//
+// Local wavefront steps.  The owner lane keeps its row's first NT terms in
+// registers: a factor pv (the rounded product for an entry outside the
+// item, the matrix value for an item-local column, 0 for an unused slot)
+// and the LDS slot of the value it multiplies (xl[64] holds 1.0 for the
+// first and last kind), so a step is NT LDS reads, NT products and NT
+// subtractions with no selects; multiplying by 1.0 and subtracting +0.0 are
+// exact, so the terms and their order are still the definition's.
+template <typename T, int NT>
+__device__ __forceinline__ T chunk_steps(WaveLds<T>& w, T* xl, T* vec, bool mine, int myloc, int maxloc, int off,
+                                         int len, int row, int lane, T acc, T dii) {
+  constexpr int kOne = 64;
+  T pv[NT];
+  int pq[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    pv[u] = T(0);
+    pq[u] = kOne;
+    if (u < len) {
+      const int q = w.pos[off + u];
+      pv[u] = w.prod[off + u];
+      pq[u] = q == 0xFF ? kOne : q;
+    }
+  }
+  T mine_x = T(0);
+  for (int s = 0; s <= maxloc; ++s) {
+    if (mine && myloc == s) {
+      T xq[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) xq[u] = xl[pq[u]];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc = acc - pv[u] * xq[u];
+      for (int t = off + NT; t < off + len; ++t) {
+        const int q = w.pos[t];
+        acc = acc - (q == 0xFF ? w.prod[t] : w.prod[t] * xl[q]);
+      }
+      const T x = publishable(acc / dii);
+      xl[lane] = x;
+      st_co(vec + row, x);
+      mine_x = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return mine_x;
+}
+
+// Solve the rows of a coarsened item.  Row slot s (lane s < nr) owns the
+// entries [r0, r0 + len) of (col, val) -- val[map[p]] when MAPPED -- and
+// eloc[p] is the slot of the entry's column inside the item, or 0xFF.  All
+// the item's entries are dealt to the lanes in one pass (the inspector keeps
+// an item's entries within one pass): an item-local entry loads nothing
+// more; the others load vec[col] through the readiness protocol, waited for
+// together.  Then the local wavefronts run in order (chunk_steps): each row
+// folds its entries in ascending position -- a product taken from LDS, or
+// the value times the item's own result kept in LDS -- divides by dii,
+// keeps the result for the later wavefronts and publishes it in vec[row].
+// Every product is rounded once and every row folds in ascending order, as
+// in the sequential substitution.  Returns the lane's own result.  xl holds
+// 65 values: 64 slots and the constant 1.0 at [64].
+template <typename T, bool MAPPED>
+__device__ __forceinline__ T chunk_solve(int nr, int r0, int len, int myloc, int maxloc, T acc, T dii,
+                                         const int32_t* __restrict__ col, const int32_t* __restrict__ map,
+                                         const T* __restrict__ val, const uint8_t* __restrict__ eloc, T* vec,
+                                         int row, int lane, WaveLds<T>& w, T* xl, const LaunchState& ls,
+                                         unsigned long long* tr) {
+  const bool mine = lane < nr;
+  if (!mine) len = 0;
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  if (mine)
+    for (int t = off; t < off + len; ++t) w.pos[t] = r0 + (t - off);
+  __builtin_amdgcn_wave_barrier();
+  int j[kRounds], sl[kRounds];
+  T v[kRounds], xv[kRounds];
+#pragma unroll
+  for (int e = 0; e < kRounds; ++e) {
+    const int k = lane + 64 * e;
+    j[e] = -1;
+    sl[e] = 0xFF;
+    v[e] = T(0);
+    if (k < total) {
+      const int p = w.pos[k];
+      sl[e] = int(ld_stream(eloc + p));
+      v[e] = MAPPED ? val[ld_stream(map + p)] : ld_stream(val + p);
+      if (sl[e] == 0xFF) j[e] = ld_stream(col + p);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? ld_co(vec + j[e]) : T(0);
+  if (tr && lane == 0) tr[1] = __builtin_amdgcn_s_memrealtime();
+  wait_ready<T, kRounds>(vec, j, xv, lane, ls);
+  // LDS: prod[k] = rounded product (outside entry) or the value (local entry);
+  // pos[k] = slot of the local column, or 0xFF
+#pragma unroll
+  for (int e = 0; e < kRounds; ++e) {
+    const int k = lane + 64 * e;
+    if (k < total) {
+      w.prod[k] = sl[e] == 0xFF ? v[e] * xv[e] : v[e];
+      w.pos[k] = sl[e];
+    }
+  }
+  if (tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();
+  __builtin_amdgcn_wave_barrier();
+  int maxlen = len;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, d, 64));
+  if (maxlen <= 4) return chunk_steps<T, 4>(w, xl, vec, mine, myloc, maxloc, off, len, row, lane, acc, dii);
+  return chunk_steps<T, 8>(w, xl, vec, mine, myloc, maxloc, off, len, row, lane, acc, dii);
 }
 
 }  // namespace dev

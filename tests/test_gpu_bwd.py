@@ -63,6 +63,32 @@ def test_random_rectangular(orc, seed, n, m, lanes):
     assert relerr(gb, gbr) <= TOL64 and relerr(gl, glr) <= TOL64
 
 
+@pytest.mark.parametrize("case", ["lap3d7_16", "lap2d9_48", "lap2d5_16"])
+def test_coarsened_backward_bit_identical(orc, case):
+    """Coarsened items in the transposed solve (lambda values of an item
+    resolved in LDS) keep the definition's arithmetic: FP64 gradients equal
+    the oracle's bit for bit, also with a small item size."""
+    announce("bwd coarsened " + case)
+    if case == "lap3d7_16":
+        A = synth.laplacian_3d7(16, 16, 16, 6.0)
+        L = synth.lower(A)
+    elif case == "lap2d9_48":
+        A = synth.laplacian_2d9(48, 48, 8.0)
+        L = synth.lower(A)
+    else:
+        L, A = synth.workload("lap2d5_16")
+    b = synth.vec_uniform(L.nrows, seed=1)
+    w = synth.vec_normal(A.nrows, seed=2)
+    _, gbr, glr = oracle_grads(orc, L, A, b, w)
+    for rows in (64, 11):
+        s = sfm.Schedule(L, A, want_backward=True, coarsen=2, rows_per_item=rows)
+        assert s.info().back_coarsened == 1
+        gb, gl = gpu_grads(s, L, A, b, w)
+        assert np.array_equal(gb, gbr) and np.array_equal(gl, glr), rows
+        gb2, gl2 = gpu_grads(s, L, A, b, w, recompute=True)
+        assert np.array_equal(gb2, gbr) and np.array_equal(gl2, glr), rows
+
+
 def test_autograd_function(orc):
     announce("bwd autograd lap2d5_16")
     import torch
@@ -92,6 +118,7 @@ def test_s5_lap3d7_96(orc):
     b = synth.vec_uniform(L.nrows, seed=1)
     w = synth.vec_normal(A.nrows, seed=2)
     s = sfm.Schedule(L, A, want_backward=True)
+    print("96^3 plans: forward coarsened %d, backward coarsened %d" % (s.info().coarsened, s.info().back_coarsened))
     _, gbr, glr = oracle_grads(orc, L, A, b, w)
     gb, gl = gpu_grads(s, L, A, b, w)
     print("96^3 FP64 grad errors: b %.2e L %.2e" % (relerr(gb, gbr), relerr(gl, glr)))

@@ -186,7 +186,7 @@ def test_item_nnz_budget():
 
 def test_backward_schedule(orc):
     L, A = synth.workload("lap2d5_16")
-    s = sfm.Schedule(L, A, want_backward=True)
+    s = sfm.Schedule(L, A, want_backward=True, coarsen=1)
     rl, order, ip = s.export_backward()
     want, depth = orc.reverse_levels(L.rowptr, L.col)
     assert np.array_equal(rl, want)
@@ -203,6 +203,50 @@ def test_backward_schedule(orc):
     rows = np.repeat(np.arange(L.nrows), np.diff(L.rowptr))
     off = L.col < rows
     assert np.all(item[rows[off]] < item[L.col[off]])
+
+
+@pytest.mark.parametrize("case", ["lap3d7_16", "lap2d9_48", "random"])
+def test_coarsened_backward_plan(orc, case):
+    """The coarsened plan of the transposed solve: a permutation of the rows
+    in which every edge lambda_j -> lambda_i (L_ji stored, j > i) goes to a
+    later item or, inside an item, to a later local wavefront, with the
+    per-entry slots of L^T naming exactly the item-local columns."""
+    if case == "lap3d7_16":
+        A = synth.laplacian_3d7(16, 16, 16, 6.0)
+        L = synth.lower(A)
+    elif case == "lap2d9_48":
+        A = synth.laplacian_2d9(48, 48, 8.0)
+        L = synth.lower(A)
+    else:
+        L, A = _random_pair(2000, 3)
+    s = sfm.Schedule(L, A, want_backward=True, coarsen=2, validate=True)
+    st = s.info()
+    assert st.back_coarsened == 1
+    rl, order, ip = s.export_backward()
+    loc, slot = s.export_backward_local()
+    want, depth = orc.reverse_levels(L.rowptr, L.col)
+    assert np.array_equal(rl, want) and st.back_depth == depth
+    n = L.nrows
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.diff(ip).max() <= 64
+    item = np.repeat(np.arange(len(ip) - 1), np.diff(ip))
+    pos = np.empty(n, np.int64)
+    pos[order] = np.arange(n)
+    for t in range(len(ip) - 1):
+        assert np.all(np.diff(loc[ip[t]:ip[t + 1]].astype(int)) >= 0)
+    # L^T in CSR: row i holds i (diagonal first) then the rows j > i with L_ji stored
+    lt = L.to_scipy().T.tocsr()
+    lt.sort_indices()
+    rows = np.repeat(np.arange(n), np.diff(lt.indptr))
+    j = lt.indices
+    assert np.all(j[lt.indptr[:-1]] == np.arange(n))  # diagonal first
+    off = j != rows
+    u, v, ps = j[off], rows[off], slot[off]           # edge lambda_u -> lambda_v
+    same = item[pos[u]] == item[pos[v]]
+    assert np.all(item[pos[u]][~same] < item[pos[v]][~same])
+    assert np.all(loc[pos[u][same]] < loc[pos[v][same]])
+    assert np.array_equal(ps[same].astype(np.int64), pos[u][same] - ip[item[pos[v][same]]])
+    assert np.all(ps[~same] == 255) and np.all(slot[~off] == 255)
 
 
 def test_ic0_schedule(orc):
