@@ -127,9 +127,10 @@ def main():
         if not args.no_autotune:
             t0 = time.time()
             sfm.autotune(s, d["Lv"], d["Av"], d["B"])
-            log("autotuned %s in %.1fs: lanes_trsv=%d lanes_spmv=%d rows_per_item=%d waves_per_cu=%d" % (
-                name, time.time() - t0, s.get_param("lanes_trsv"), s.get_param("lanes_spmv"),
-                s.get_param("rows_per_item"), s.get_param("waves_per_cu")))
+            keys = ("coarsened", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu")
+            d["params"] = {k: s.get_param(k) for k in keys}
+            log("autotuned %s in %.1fs: %s" % (name, time.time() - t0,
+                                                " ".join("%s=%d" % kv for kv in d["params"].items())))
         work.append(d)
 
     def step(unfused=False, events=None):
@@ -194,6 +195,7 @@ def main():
             "unfused_ms": round(per_launch_u[k], 4), "unfused_GBps": round(gbs_u, 1),
             "speedup_vs_unfused": round(per_launch_u[k] / per_launch[k], 3),
             "inspect_s": round(d["inspect_s"], 3),
+            "params": d.get("params"),
             "NER_vs_unfused": round(d["inspect_s"] * 1e3 / (per_launch_u[k] - per_launch[k]), 1)
             if per_launch_u[k] > per_launch[k] else None,
             "critical_path_us_per_level": round(per_launch[k] * 1e3 / max(d["joint_depth"], 1), 3),

@@ -304,7 +304,14 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "spmv_delay"                place each SpMV row this many wavefronts after
  *                               the one where its inputs are final (0 = the
  *                               canonical joint order; any value keeps the
- *                               order topological);
+ *                               order topological); with coarsened items the
+ *                               unit is one step of the item chain; -1
+ *                               (default): 0 with level items, after every
+ *                               SpTRSV item with coarsened ones (Sec. 3.2's
+ *                               slack placement);
+ *   "coarsen"                   0 auto, 1 level items, 2 coarsened items
+ *                               (re-cuts; "coarsened", "back_coarsened" read
+ *                               the plans in effect);
  *   "no_fusion", "timing", "trace"   switches (0/1).
  */
 sf_status sf_set_param(sf_schedule s, const char* key, int64_t value);

@@ -863,7 +863,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     s->claim_streams = int32_t(v);
   } else if (k == "rows_per_item" || k == "max_item_nnz" || k == "spmv_delay" || k == "coarsen") {
     if (k == "coarsen" ? (v < 0 || v > 2 || s->kind != SF_TRSV_SPMV)
-        : k == "spmv_delay" ? (v < 0 || v > (int64_t(1) << 30)) : (v < 1 || v > (int64_t(1) << 30)))
+        : k == "spmv_delay" ? (v < -1 || v > (int64_t(1) << 30)) : (v < 1 || v > (int64_t(1) << 30)))
       return SF_ERR_ARG;
     if (k == "rows_per_item" && v > 64) return SF_ERR_ARG;  // one lane finishes each row
     if (k == "rows_per_item") s->rows_per_item = int32_t(v);

@@ -301,10 +301,14 @@ static void build_chunks(sf_schedule_s* s) {
     }
     cp_all = std::max(cp_all, in + kEstHop);
   }
-  if (s->spmv_delay > 0 && nc > 0) {
+  // by default SpMV rows go after every SpTRSV item here: interleaved with
+  // coarsened items they take wavefronts and memory bandwidth from the
+  // critical chain
+  const int64_t delay = s->spmv_delay < 0 ? (int64_t(1) << 30) : int64_t(s->spmv_delay);
+  if (delay > 0 && nc > 0) {
     const int64_t per_step = std::max<int64_t>(1, nc / std::max(1, c.chain));
     for (int64_t r = 0; r < m; ++r)
-      skey[r] = int32_t(std::min<int64_t>(int64_t(skey[r]) + int64_t(s->spmv_delay) * per_step, nc - 1));
+      skey[r] = int32_t(std::min<int64_t>(int64_t(skey[r]) + delay * per_step, nc - 1));
   }
   // Claim order: [SpMV rows without inputs] item 0, its SpMV rows, item 1, ...
   std::vector<int32_t> bucket(static_cast<size_t>(nc) + 2, 0), sorder(static_cast<size_t>(m));
@@ -405,7 +409,7 @@ void cut_items(sf_schedule_s* s) {
       cost[i] = std::max(1, s->L.rp[i + 1] - s->L.rp[i] - 1);
     }
     for (int64_t r = 0; r < m; ++r) {
-      const int64_t slot = std::min<int64_t>(int64_t(s->ready[r]) + s->spmv_delay, last);
+      const int64_t slot = std::min<int64_t>(int64_t(s->ready[r]) + std::max(0, s->spmv_delay), last);
       key[n + r] = int32_t(2 * slot + 1);
       cost[n + r] = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
     }

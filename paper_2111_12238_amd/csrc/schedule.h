@@ -125,7 +125,10 @@ struct sf_schedule_s {
   // Executor parameters.
   int32_t lanes_trsv = 4, lanes_spmv = 8, rhs_block = 0, waves_per_cu = 8;
   int32_t rows_per_item = 64, max_item_nnz = 4096;
-  int32_t spmv_delay = 0;            // wavefronts an SpMV row waits after its inputs are final
+  // wavefronts (level items) or item-chain steps (coarsened items) an SpMV
+  // row is placed after its inputs are final; -1: 0 for level items, after
+  // every SpTRSV item for coarsened ones
+  int32_t spmv_delay = -1;
   int64_t spin_limit = int64_t(1) << 22;
   int32_t claim_streams = 1;
   int32_t no_fusion = 0;
