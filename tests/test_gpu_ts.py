@@ -312,6 +312,30 @@ def test_coarsened_integer_and_fp32(orc):
     assert np.array_equal(x32, x32l) and np.array_equal(y32, y32l)  # same FP32 operations in the same order
 
 
+@pytest.mark.parametrize("coarsen", [1, 2])
+def test_alternating_rhs_bit_exact(orc, coarsen):
+    """Launches that alternate right-hand sides on one schedule: each result
+    equals the oracle's for its own b, so no value of an earlier launch is
+    ever taken for a final one (first reads of x go through the caches)."""
+    announce("ts alternating rhs coarsen=%d" % coarsen)
+    import torch
+    A = synth.laplacian_3d7(24, 24, 24, 6.0)
+    L = synth.lower(A)
+    bs = [synth.vec_uniform(L.nrows, seed=s) for s in (11, 12, 13)]
+    refs = [oracle_ts(orc, L, A, b) for b in bs]
+    s = sfm.Schedule(L, A, coarsen=coarsen)
+    Lv, Av = dev(L.val), dev(A.val)
+    Bs = [dev(b) for b in bs]
+    X = torch.empty(L.nrows, dtype=torch.float64, device="cuda")
+    Y = torch.empty(A.nrows, dtype=torch.float64, device="cuda")
+    for it in range(12):
+        k = it % 3
+        sfm.trsv_spmv(s, Lv, Av, Bs[k], X=X, Y=Y)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(X), refs[k][0]) and np.array_equal(host(Y), refs[k][1]), it
+    sfm.sync_status(s)
+
+
 @pytest.mark.parametrize("name", ["lap3d7_128", "randspd_1m"])
 def test_full_size_configs(orc, name):
     """The benchmark's workloads at full size, whole vectors against the
