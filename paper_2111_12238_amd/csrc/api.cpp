@@ -95,6 +95,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oPp = pk.add(&s->pair_ptr), oPu = pk.add(&s->pair_u), oPq = pk.add(&s->pair_q);
   const size_t oCo = pk.add(&s->corder), oCip = pk.add(&s->citem_ptr), oCti = pk.add(&s->ctrsv_items);
   const size_t oCl = pk.add(&s->clloc), oCe = pk.add(&s->celoc);
+  const size_t oQr = pk.add(&s->qrng), oCqr = pk.add(&s->cqrng);
   const size_t oBco = pk.add(&s->bcorder), oBcip = pk.add(&s->bcitem_ptr);
   const size_t oBcl = pk.add(&s->bclloc), oBce = pk.add(&s->bceloc);
   void* block = nullptr;
@@ -119,6 +120,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.corder = P(oCo); d.citem_ptr = P(oCip); d.ctrsv_items = P(oCti);
   d.clloc = reinterpret_cast<uint8_t*>(b + oCl);
   d.celoc = reinterpret_cast<uint8_t*>(b + oCe);
+  d.qrng = P(oQr); d.cqrng = P(oCqr);
   d.bcorder = P(oBco); d.bcitem_ptr = P(oBcip);
   d.bclloc = reinterpret_cast<uint8_t*>(b + oBcl);
   d.bceloc = reinterpret_cast<uint8_t*>(b + oBce);
@@ -213,6 +215,7 @@ TsArgs ts_args(sf_schedule_s* s, const void* Lv, const void* Av, const void* B, 
   a.B = B; a.ldb = ldb; a.X = X; a.ldx = ldx; a.Y = Y; a.ldy = ldy;
   a.nrhs = nrhs;
   a.order = d.order;
+  a.qrng = d.qrng;
   a.item_ptr = d.item_ptr;
   if (Y) {
     a.item_list = nullptr;
@@ -269,6 +272,7 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     a.trace = s->trace;
     if (s->chunked) {
       a.order = s->dev.corder;
+      a.qrng = s->dev.cqrng;
       a.item_ptr = s->dev.citem_ptr;
       a.item_list = Y ? nullptr : s->dev.ctrsv_items;
       a.n_work = Y ? int32_t(s->citem_ptr.size() - 1) : int32_t(s->ctrsv_items.size());

@@ -392,6 +392,21 @@ static bool mesh_like(int64_t n, const std::vector<int32_t>& rp, const std::vect
   return edges > 0 && double(tight) >= 0.35 * double(edges);
 }
 
+// Row ranges per claim position (see sf_schedule_s::qrng).
+static void position_ranges(const sf_schedule_s* s, const std::vector<int32_t>& order, std::vector<int32_t>& out) {
+  out.resize(2 * order.size());
+  for (size_t q = 0; q < order.size(); ++q) {
+    const int32_t id = order[q];
+    if (id < s->n) {
+      out[2 * q] = s->L.rp[id];
+      out[2 * q + 1] = s->L.rp[id + 1] - 1;
+    } else {
+      out[2 * q] = s->A.rp[id - s->n];
+      out[2 * q + 1] = s->A.rp[id - s->n + 1];
+    }
+  }
+}
+
 void cut_items(sf_schedule_s* s) {
   const int64_t n = s->n, m = s->m;
   if (s->kind == SF_TRSV_SPMV) {
@@ -432,7 +447,10 @@ void cut_items(sf_schedule_s* s) {
     s->max_local_depth = 0;
     s->est_chunk_us = 0.0;
     const bool try_chunks = s->coarsen == 2 || (s->coarsen == 0 && mesh_like(n, s->L.rp, s->L.ci, 0, 1, s->level));
+    s->cqrng.clear();
     if (try_chunks && n > 0) build_chunks(s);
+    position_ranges(s, s->order, s->qrng);
+    if (!s->corder.empty()) position_ranges(s, s->corder, s->cqrng);
     s->chunked = !s->ctrsv_items.empty() &&
                  (s->coarsen == 2 || s->est_chunk_us < 0.8 * s->est_level_us);
   } else {

@@ -54,15 +54,16 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
                                             int it = -1) {
   const int nr = q1 - q0;
   const bool mine = lane < nr;
-  const int32_t* __restrict__ rp = TRSV ? a.Lrp : a.Arp;
   const T* __restrict__ val = static_cast<const T*>(TRSV ? a.Lv : a.Av);
   T* X = static_cast<T*>(a.X);
   unsigned long long* tr = trace_slots(a, it);
   if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
   const int id = mine ? a.order[q0 + lane] : 0;
   const int row = TRSV ? id : id - a.n;
-  const int r0 = mine ? rp[row] : 0;
-  const int r1 = mine ? rp[row + 1] - (TRSV ? 1 : 0) : 0;  // SpTRSV: stop before the diagonal
+  // the row's range comes with its claim position (no row-pointer round trip);
+  // an SpTRSV range stops before the diagonal, which sits at r1
+  const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
+  const int r0 = rg.x, r1 = rg.y;
   T acc = T(0), dii = T(1);
   if (TRSV && mine) {
     acc = static_cast<const T*>(a.B)[row];
@@ -88,8 +89,8 @@ __device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int 
   unsigned long long* tr = trace_slots(a, it);
   if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
   const int row = mine ? a.order[q0 + lane] : 0;
-  const int r0 = mine ? a.Lrp[row] : 0;
-  const int r1 = mine ? a.Lrp[row + 1] - 1 : 0;
+  const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
+  const int r0 = rg.x, r1 = rg.y;  // off-diagonals; the diagonal sits at r1
   const int myloc = mine ? int(a.lloc[q0 + lane]) : 0;
   const int maxloc = int(a.lloc[q1 - 1]);
   const T acc = mine ? static_cast<const T*>(a.B)[row] : T(0);

@@ -33,6 +33,7 @@ struct TsArgs {
   int32_t nrhs, kb, nblk;  // right-hand sides, block width, number of blocks
   void* xi;                // nblk * n * kb interleaved solution workspace (nrhs > 1)
   const int32_t *order, *item_ptr, *item_list;
+  const int32_t* qrng;     // per claim position: CSR range of the row's dot product (pairs)
   int32_t n_work;          // items to run (entries of item_list, or all items)
   const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
   const uint8_t* eloc;     // coarsened plan: per L entry, slot of its column in the item or 0xFF

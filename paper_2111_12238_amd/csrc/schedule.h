@@ -46,6 +46,7 @@ struct DeviceBuffers {
   int32_t *lvl_item_ptr = nullptr;  // per level, into lvl_items
   // coarsened plan of the one-right-hand-side fused executor
   int32_t *corder = nullptr, *citem_ptr = nullptr, *ctrsv_items = nullptr;
+  int32_t *qrng = nullptr, *cqrng = nullptr;
   uint8_t *clloc = nullptr;         // local wavefront of each claim position
   uint8_t *celoc = nullptr;         // per stored L entry: slot of its column in the row's item, or 0xFF
   // backward
@@ -86,6 +87,11 @@ struct sf_schedule_s {
   std::vector<int32_t> order, item_ptr;
   std::vector<int32_t> trsv_items;   // items holding SpTRSV rows, in claim order
   std::vector<int32_t> spmv_items;   // items holding SpMV rows, in claim order
+  // Per claim position q, the CSR range the row's dot product runs over:
+  // [qrng[2q], qrng[2q+1]) -- the off-diagonals of an SpTRSV row (its
+  // diagonal sits at qrng[2q+1]), the whole row of an SpMV row -- so an
+  // item's loads do not wait for the row pointers (SF_TRSV_SPMV only).
+  std::vector<int32_t> qrng, cqrng;  // level plan, coarsened plan
   // Level-set baseline: items of SpTRSV rows grouped by level.
   std::vector<int32_t> lvl_items, lvl_item_ptr;
 
