@@ -313,6 +313,33 @@ def test_coarsened_integer_and_fp32(orc):
 
 
 @pytest.mark.parametrize("coarsen", [1, 2])
+def test_long_rows_bit_exact(orc, coarsen):
+    """Rows longer than one stream pass (512 entries): a few dense SpTRSV rows
+    (one reading every earlier row) and dense SpMV rows among short ones, so
+    items take several passes and coarsened plans keep such rows apart."""
+    announce("ts long rows coarsen=%d" % coarsen)
+    n = 3000
+    rng = np.random.default_rng(21)
+    L = sp.lil_matrix(sp.random(n, n, density=2.0 / n, random_state=rng, format="csr"))
+    L = sp.tril(L, -1).tolil()
+    for r in (1500, 2999):
+        L[r, :r] = rng.uniform(-1, 1, r) / r
+    L = (sp.tril(L, -1) + sp.diags(rng.uniform(1, 2, n))).tocsr()
+    A = sp.random(n + 7, n, density=3.0 / n, random_state=rng, format="lil")
+    A[5, :] = rng.uniform(-1, 1, n)
+    A[n + 6, : n // 2] = rng.uniform(-1, 1, n // 2)
+    Ls, As = synth.from_scipy(L), synth.from_scipy(A.tocsr())
+    b = synth.vec_uniform(n, seed=3)
+    xr, yr = oracle_ts(orc, Ls, As, b)
+    for rows, budget in ((64, 512), (5, 100)):
+        s = sfm.Schedule(Ls, As, coarsen=coarsen, rows_per_item=rows, max_item_nnz=budget)
+        x, y = run(s, Ls, As, b)
+        assert np.array_equal(x, xr) and np.array_equal(y, yr), (rows, budget)
+    xu, yu = run(s, Ls, As, b, unfused=True)
+    assert np.array_equal(xu, xr) and np.array_equal(yu, yr)
+
+
+@pytest.mark.parametrize("coarsen", [1, 2])
 def test_alternating_rhs_bit_exact(orc, coarsen):
     """Launches that alternate right-hand sides on one schedule: each result
     equals the oracle's for its own b, so no value of an earlier launch is
