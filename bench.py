@@ -53,6 +53,16 @@ def bwd_bytes(n, m, nnz_l, nnz_a, vb):
     return fwd + back
 
 
+def pair_bytes(n, nnz_l, nnz_a, mode, vb=8):
+    # combination 2: A and L (values, indices, row pointers), x read, y and z
+    # written; combination 1: L read once (the interleaved packing), b read,
+    # x and z written
+    lb = nnz_l * (vb + 4) + (n + 1) * 4
+    if mode == 2:
+        return lb + nnz_a * (vb + 4) + (n + 1) * 4 + 3 * n * vb
+    return lb + 3 * n * vb
+
+
 def sources_sha():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -237,8 +247,9 @@ def main():
 
 
 def run_extras(args, sfm, synth, torch, dev, stream):
-    """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted) and forward +
-    backward (7-point 96^3, FP64 and FP32): fused vs unfused times."""
+    """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted), the batched
+    refinement, kernel combinations 2 and 1 on the headline matrices, and
+    forward + backward (7-point 96^3, FP64 and FP32): fused vs unfused."""
     out = {}
 
     def time_it(fn, reps):
@@ -271,6 +282,28 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                                    "inspect_s": round(s.info().inspect_seconds, 3)}
         log("ic0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
     out.update(run_batched(args, sfm, synth, torch, dev, time_it))
+    # kernel combinations 2 (SpMV -> SpTRSV) and 1 (SpTRSV -> SpTRSV)
+    for name in ("lap3d7_128", "randspd_1m"):
+        L, A = synth.workload(name)
+        s = sfm.Schedule(L, A)
+        Lv, Av = torch.as_tensor(L.val, device=dev), torch.as_tensor(A.val, device=dev)
+        x = torch.as_tensor(synth.vec_uniform(L.nrows, seed=1), device=dev)
+        Y, Z = torch.empty_like(x), torch.empty_like(x)
+        for mode, tag in ((2, "spmv_trsv"), (1, "trsv_trsv")):
+            if mode == 2:
+                f = lambda: sfm.spmv_trsv(s, Av, Lv, x, Y=Y, Z=Z)
+                u = lambda: sfm.spmv_trsv(s, Av, Lv, x, Y=Y, Z=Z, unfused=True)
+            else:
+                f = lambda: sfm.trsv_trsv(s, Lv, x, X=Y, Z=Z)
+                u = lambda: sfm.trsv_trsv(s, Lv, x, X=Y, Z=Z, unfused=True)
+            tf, tu = time_it(f, reps), time_it(u, reps)
+            nb = pair_bytes(L.nrows, L.nnz, A.nnz, mode)
+            out["%s_%s" % (tag, name)] = {"fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
+                                          "speedup_vs_unfused": round(tu / tf, 3), "bytes": nb,
+                                          "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
+                                          "coarsened": s.info().coarsened}
+            log("%s %s fused %.3f ms unfused %.3f ms" % (tag, name, tf, tu))
+        sfm.sync_status(s)
     L, A = synth.workload("lap3d7_96")
     s = sfm.Schedule(L, A, want_backward=True)
     for dt, tname, vb in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):

@@ -229,6 +229,44 @@ sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L
                                     void* X, int32_t ldx, void* Y, int32_t ldy, void* stream);
 
 /*
+ * sf_exec_spmv_trsv — fused SpMV -> SpTRSV (Table 2, comb. 2):
+ *   y = A x, then z = L^{-1} y.
+ * The SpMV's row i feeds only the solve's row i (F = I), so the work item of
+ * SpTRSV row i computes y_i first (interleaved packing, Sec. 3.2 step 3).
+ * Uses a SF_TRSV_SPMV schedule whose A is square (m = n, else SF_ERR_SHAPE);
+ * its SpTRSV plan (level or coarsened items) orders the rows.  One
+ * right-hand side.  Device vectors: X (n, read), Y (n, written; NULL skips
+ * storing y), Z (n, written; must not alias X or Y).  FP64 results equal
+ * the sequential definitions' bit for bit (every sum in ascending order).
+ * Errors: SF_ERR_ARG (null pointers, aliasing, wrong kind or dtype),
+ * SF_ERR_SHAPE, SF_ERR_HIP.
+ */
+sf_status sf_exec_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val,
+                            const void* X, void* Y, void* Z, void* stream);
+
+/* Unfused baseline of sf_exec_spmv_trsv: the whole SpMV, then the level-set
+ * solve (Y must not be NULL: it carries y between the two launches). */
+sf_status sf_exec_unfused_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val,
+                                    const void* X, void* Y, void* Z, void* stream);
+
+/*
+ * sf_exec_trsv_trsv — fused SpTRSV -> SpTRSV with one L (Table 2, comb. 1):
+ *   x = L^{-1} b, then z = L^{-1} x.
+ * Row i of the second solve needs x_i and earlier z_j only, so one work item
+ * solves both for its rows and reads L once (reuse ratio >= 1: interleaved
+ * packing).  Uses the SpTRSV plan of a SF_TRSV_SPMV schedule (A unused).
+ * Device vectors: B (n, read), X (n, written), Z (n, written), pairwise
+ * distinct.  FP64 results equal two sequential forward substitutions bit
+ * for bit.  Errors as sf_exec_spmv_trsv.
+ */
+sf_status sf_exec_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X, void* Z,
+                            void* stream);
+
+/* Unfused baseline of sf_exec_trsv_trsv: two level-set solves. */
+sf_status sf_exec_unfused_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X,
+                                    void* Z, void* stream);
+
+/*
  * sf_exec_ic0_trsv — fused SpIC0 -> SpTRSV (Table 2, comb. 5), FP64.
  * The schedule must be of kind SF_IC0_TRSV.  Computes the zero fill-in
  * incomplete Cholesky factor L of A (pattern = lower(A)) by the up-looking

@@ -95,6 +95,10 @@ _SIGS = {
     "sf_sync_status": [_P, _P],
     "sf_last_kernel_ms": [_P, ctypes.POINTER(ctypes.c_double)],
     "sf_trace_export": [_P, _P, ctypes.c_int64],
+    "sf_exec_spmv_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
+    "sf_exec_unfused_spmv_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
+    "sf_exec_trsv_trsv": [_P, _I, _P, _P, _P, _P, _P],
+    "sf_exec_unfused_trsv_trsv": [_P, _I, _P, _P, _P, _P, _P],
 }
 
 
@@ -326,6 +330,39 @@ def trsv_spmv(sched: Schedule, L_val, A_val, B, *, X=None, Y=None, want_y=True, 
     _check(fn(sched.handle, dt, L_val.data_ptr(), _ptr(A_val), bp, ldb, k, xp, ldx, yp, ldy,
               _stream(stream)), "sf_exec_trsv_spmv")
     return X, (Y if want_y else None)
+
+
+def spmv_trsv(sched: Schedule, A_val, L_val, x, *, Y=None, Z=None, want_y=True, stream=None, unfused=False):
+    """y = A x, z = L^{-1} y (Table 2, combination 2).  Returns (y or None, z)."""
+    n = sched.n
+    xp, _, k = _vec_ptr(x, n, "x")
+    if k != 1:
+        raise ValueError("spmv_trsv takes one right-hand side")
+    torch = _torch()
+    if Z is None:
+        Z = torch.empty(n, dtype=L_val.dtype, device=L_val.device)
+    if (want_y or unfused) and Y is None:
+        Y = torch.empty(n, dtype=L_val.dtype, device=L_val.device)
+    yp = _vec_ptr(Y, n, "Y")[0] if (want_y or unfused) else None
+    fn = _lib().sf_exec_unfused_spmv_trsv if unfused else _lib().sf_exec_spmv_trsv
+    _check(fn(sched.handle, _dtype_code(L_val), _ptr(A_val), L_val.data_ptr(), xp, yp, _vec_ptr(Z, n, "Z")[0],
+              _stream(stream)), "sf_exec_spmv_trsv")
+    return (Y if (want_y or unfused) else None), Z
+
+
+def trsv_trsv(sched: Schedule, L_val, b, *, X=None, Z=None, stream=None, unfused=False):
+    """x = L^{-1} b, z = L^{-1} x (Table 2, combination 1).  Returns (x, z)."""
+    n = sched.n
+    bp, _, k = _vec_ptr(b, n, "b")
+    if k != 1:
+        raise ValueError("trsv_trsv takes one right-hand side")
+    torch = _torch()
+    X = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if X is None else X
+    Z = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if Z is None else Z
+    fn = _lib().sf_exec_unfused_trsv_trsv if unfused else _lib().sf_exec_trsv_trsv
+    _check(fn(sched.handle, _dtype_code(L_val), L_val.data_ptr(), bp, _vec_ptr(X, n, "X")[0],
+              _vec_ptr(Z, n, "Z")[0], _stream(stream)), "sf_exec_trsv_trsv")
+    return X, Z
 
 
 def ic0_trsv(sched: Schedule, A_lower_val, b=None, *, L_val=None, X=None, stream=None, unfused=False,

@@ -369,9 +369,104 @@ sf_status check_ts_args(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   return SF_OK;
 }
 
+// Kernel combinations 1 and 2 of Table 2 (see k_pair).  mode 2: B = x,
+// Y = y (may be null), Z = z; mode 1: B = b, Y = x, Z = z.
+sf_status exec_pair(sf_schedule_s* s, sf_dtype dt, int mode, const void* Lv, const void* Av, const void* B,
+                    void* Y, void* Z, bool fused, hipStream_t st) {
+  const int dtype = dt == SF_F64 ? 0 : 1;
+  const DeviceBuffers& d = s->dev;
+  if (!fused) {
+    // unfused baseline: the first kernel in full, then the level-set solve
+    void* mid = Y;  // y (combination 2) or x (combination 1): the second kernel's input
+    if (mode == 2) {
+      // the SpMV items of the level plan, entry-streamed, x read through the caches
+      TsArgs sa = ts_args(s, Lv, Av, nullptr, int32_t(s->n), 1, const_cast<void*>(B), int32_t(s->n), mid,
+                          int32_t(s->m));
+      sa.item_list = d.spmv_items;
+      sa.n_work = int32_t(s->spmv_items.size());
+      if (sa.n_work > 0) SF_HIP(launch_spmv_items(sa, dtype, st));
+    } else {
+      sf_status r = exec_ts_unfused(s, dt, Lv, nullptr, B, int32_t(s->n), 1, mid, int32_t(s->n), nullptr, 0, st);
+      if (r != SF_OK) return r;
+    }
+    return exec_ts_unfused(s, dt, Lv, nullptr, mid, int32_t(s->n), 1, Z, int32_t(s->n), nullptr, 0, st);
+  }
+  // k_pair: mode 2 writes z into X and y into Y; mode 1 writes x into X and z into Y
+  TsArgs a = ts_args(s, Lv, Av, B, int32_t(s->n), 1, mode == 2 ? Z : Y, int32_t(s->n), nullptr, 0);
+  if (s->chunked) {
+    a.order = d.corder;
+    a.qrng = d.cqrng;
+    a.item_ptr = d.citem_ptr;
+    a.item_list = d.ctrsv_items;
+    a.n_work = int32_t(s->ctrsv_items.size());
+    a.lloc = d.clloc;
+    a.eloc = d.celoc;
+  } else {
+    a.item_list = d.trsv_items;
+    a.n_work = int32_t(s->trsv_items.size());
+  }
+  a.Y = mode == 2 ? Y : Z;
+  a.kb = 1;
+  a.nblk = 1;
+  sf_status r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  const int grid = persistent_grid(s, occupancy_pair(dtype, mode));
+  Timer tm(s, st);
+  SF_HIP(launch_fill_pending(Z, size_t(s->n), dtype, st));
+  if (mode == 1) SF_HIP(launch_fill_pending(Y, size_t(s->n), dtype, st));
+  return hip_status(launch_pair(a, dtype, mode, grid, st));
+}
+
+sf_status check_pair_args(sf_schedule_s* s, sf_dtype dt, int mode, const void* Lv, const void* Av, const void* B,
+                          const void* Y, const void* Z, bool fused) {
+  if (!s || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+  if (dt != SF_F64 && dt != SF_F32) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (!Lv || !B || !Z) return SF_ERR_ARG;
+  if (mode == 2) {
+    if (s->m != s->n) return SF_ERR_SHAPE;  // row r of A x feeds row r of the solve
+    if (!Av) return SF_ERR_ARG;
+    if (!fused && !Y) return SF_ERR_ARG;  // the unfused baseline stores y between its kernels
+  } else if (!Y) {
+    return SF_ERR_ARG;
+  }
+  if (B == Z || (Y && (Y == Z || Y == B))) return SF_ERR_ARG;
+  return SF_OK;
+}
+
+sf_status pair_entry(sf_schedule s, sf_dtype dtype, int mode, const void* L_val, const void* A_val, const void* B,
+                     void* Y, void* Z, bool fused, void* stream) {
+  sf_status r = check_pair_args(s, dtype, mode, L_val, A_val, B, Y, Z, fused);
+  if (r != SF_OK || s->n == 0) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  r = upload(s, st);
+  if (r != SF_OK) return r;
+  return exec_pair(s, dtype, mode, L_val, A_val, B, Y, Z, fused && !s->no_fusion, st);
+}
+
 }  // namespace
 
 extern "C" {
+
+sf_status sf_exec_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val, const void* X,
+                            void* Y, void* Z, void* stream) {
+  return pair_entry(s, dtype, 2, L_val, A_val, X, Y, Z, true, stream);
+}
+
+sf_status sf_exec_unfused_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val,
+                                    const void* X, void* Y, void* Z, void* stream) {
+  return pair_entry(s, dtype, 2, L_val, A_val, X, Y, Z, false, stream);
+}
+
+sf_status sf_exec_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X, void* Z,
+                            void* stream) {
+  return pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, true, stream);
+}
+
+sf_status sf_exec_unfused_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X,
+                                    void* Z, void* stream) {
+  return pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, false, stream);
+}
 
 const char* sf_version(void) { return "sparsefusion-mi355x 0.1 (gfx950)"; }
 
@@ -622,6 +717,7 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   la.ts.kb = 1;
   la.ts.nblk = 1;
   la.ts.order = d.order;
+  la.ts.qrng = d.qrng;
   la.ts.item_ptr = d.item_ptr;
   la.ts.item_list = d.lvl_items;
   la.ts.n_work = a.n_work;

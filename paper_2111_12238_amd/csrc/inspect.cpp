@@ -392,7 +392,8 @@ static bool mesh_like(int64_t n, const std::vector<int32_t>& rp, const std::vect
   return edges > 0 && double(tight) >= 0.35 * double(edges);
 }
 
-// Row ranges per claim position (see sf_schedule_s::qrng).
+// Row ranges per claim position (see sf_schedule_s::qrng); SpIC0 schedules
+// get the SpTRSV ranges of their rows.
 static void position_ranges(const sf_schedule_s* s, const std::vector<int32_t>& order, std::vector<int32_t>& out) {
   out.resize(2 * order.size());
   for (size_t q = 0; q < order.size(); ++q) {
@@ -468,6 +469,7 @@ void cut_items(sf_schedule_s* s) {
     cut_runs(s->order, key, cost, std::min(s->rows_per_item, per_batch), s->max_item_nnz, s->item_ptr);
     s->trsv_items.clear();
     for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) s->trsv_items.push_back(int32_t(t));
+    position_ranges(s, s->order, s->qrng);  // for the level-set solve of the unfused baseline
   }
   // Level-set baseline: the SpTRSV items grouped by level.  Items are
   // level-pure, and in claim order the levels ascend.

@@ -130,6 +130,70 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
   }
 }
 
+// ---------------------------------------------- kernel combinations 1, 2 --
+// Table 2, combination 2: y = A x, z = L^{-1} y, and combination 1:
+// x = L^{-1} b, z = L^{-1} x.  In both the second kernel's row i needs only
+// row i of the first (F = I), so the item of SpTRSV row i computes both
+// (the paper's interleaved packing): row i of the product, or the first
+// solve's x_i, then z_i.  The SpTRSV plan (level or coarsened items) is the
+// one of the fused executor; every sum runs in the definition's order.
+
+// One triangular solve of an item's rows from the starting values acc;
+// publishes into out and returns the lane's own result.
+template <typename T>
+__device__ __forceinline__ T solve_rows(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w, T* xl, int row,
+                                        int r0, int r1, T acc, T dii, T* out) {
+  const int nr = q1 - q0;
+  const bool mine = lane < nr;
+  const T* __restrict__ val = static_cast<const T*>(a.Lv);
+  if (a.lloc && a.lloc[q1 - 1] != 0) {
+    const int myloc = mine ? int(a.lloc[q0 + lane]) : 0;
+    return dev::chunk_solve<T, false>(nr, r0, r1 - r0, myloc, int(a.lloc[q1 - 1]), acc, dii, a.Lci, nullptr, val,
+                                      a.eloc, out, row, lane, w, xl, a.ls, nullptr);
+  }
+  acc = stream_accumulate<T, true, 2, false>(nr, r0, r1 - r0, acc, a.Lci, nullptr, val, out, lane, w, a.ls);
+  const T v = publishable(acc / dii);
+  if (mine) st_co(out + row, v);
+  return v;
+}
+
+// MODE 2: B = x (input), Y = y (optional output), X = z.
+// MODE 1: B = b, X = x, Y = z.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlockThreads) void k_pair(TsArgs a) {
+  __shared__ WaveLds<T> lds[kWaves];
+  __shared__ T xloc[kWaves][65];  // item-local results by slot; [64] = 1.0
+  const int lane = threadIdx.x & 63;
+  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  T* xl = xloc[threadIdx.x >> 6];
+  if (lane == 0) xl[64] = T(1);
+  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
+  const T* __restrict__ B = static_cast<const T*>(a.B);
+  dev::reset_next_launch(a.ls);
+  int t = dev::claim(a.ls, lane);
+  while (t < a.n_work) {
+    const int tn = dev::claim(a.ls, lane);
+    const int it = a.item_list[t];
+    const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
+    const bool mine = lane < q1 - q0;
+    const int row = mine ? a.order[q0 + lane] : 0;
+    const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
+    const T dii = mine ? ld_stream(Lv + rg.y) : T(1);
+    if constexpr (MODE == 2) {
+      const int p0 = mine ? a.Arp[row] : 0, p1 = mine ? a.Arp[row + 1] : 0;
+      const T yi = stream_accumulate<T, false, 0, false>(q1 - q0, p0, p1 - p0, T(0), a.Aci, nullptr,
+                                                         static_cast<const T*>(a.Av), B, lane, w, a.ls);
+      if (mine && a.Y) __builtin_nontemporal_store(yi, static_cast<T*>(a.Y) + row);
+      solve_rows<T>(a, q0, q1, lane, w, xl, row, rg.x, rg.y, yi, dii, static_cast<T*>(a.X));
+    } else {
+      const T bi = mine ? B[row] : T(0);
+      const T xi = solve_rows<T>(a, q0, q1, lane, w, xl, row, rg.x, rg.y, bi, dii, static_cast<T*>(a.X));
+      solve_rows<T>(a, q0, q1, lane, w, xl, row, rg.x, rg.y, xi, dii, static_cast<T*>(a.Y));
+    }
+    t = tn;
+  }
+}
+
 // ------------------------------------------------------------- k > 1 ------
 // KB lanes per row, one lane per right-hand side of the block; 64/KB rows
 // at a time (the multi-RHS plan cuts items to that many rows).  The
@@ -356,18 +420,36 @@ int cu_count() {
 hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid, hipStream_t st) {
   (void)gt;
   (void)gs;
+  if (!a.qrng || !a.order || !a.item_ptr) return hipErrorInvalidValue;  // rows are streamed by claim position
   if (dtype == 0) hipLaunchKernelGGL(k_ts_fused<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   else hipLaunchKernelGGL(k_ts_fused<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
+}
+hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st) {
+  if (!a.qrng || !a.order || !a.item_ptr || !a.item_list) return hipErrorInvalidValue;
+  if (mode == 2) {
+    if (dtype == 0) hipLaunchKernelGGL((k_pair<double, 2>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_pair<float, 2>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+  } else {
+    if (dtype == 0) hipLaunchKernelGGL((k_pair<double, 1>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_pair<float, 1>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+  }
+  return hipGetLastError();
+}
+int occupancy_pair(int dtype, int mode) {
+  if (mode == 2) return dtype == 0 ? occ(k_pair<double, 2>) : occ(k_pair<float, 2>);
+  return dtype == 0 ? occ(k_pair<double, 1>) : occ(k_pair<float, 1>);
 }
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st) {
   return dtype == 0 ? ts_multi_dispatch<double>(a, kb, grid, st) : ts_multi_dispatch<float>(a, kb, grid, st);
 }
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st) {
   (void)gt;
+  if (a.ts.nrhs == 1 && (!a.ts.qrng || !a.ts.order || !a.ts.item_ptr)) return hipErrorInvalidValue;
   return dtype == 0 ? levelset_launch<double>(a, grid, st) : levelset_launch<float>(a, grid, st);
 }
 hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st) {
+  if (!a.qrng || !a.order || !a.item_ptr || !a.item_list) return hipErrorInvalidValue;
   const int grid = cu_count() * 8;
   if (dtype == 0) hipLaunchKernelGGL(k_spmv_items<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   else hipLaunchKernelGGL(k_spmv_items<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);

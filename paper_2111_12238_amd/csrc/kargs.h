@@ -119,6 +119,8 @@ struct ResArgs {
 // Launchers (return the HIP error of the launch).
 hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid, hipStream_t st);
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
+hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st);
+int occupancy_pair(int dtype, int mode);
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st);
 hipError_t launch_spmv(const SpmvArgs& a, int dtype, int gs, hipStream_t st);
 // SpMV items of a schedule (a.item_list / a.n_work), all inputs final.

@@ -90,7 +90,8 @@ struct sf_schedule_s {
   // Per claim position q, the CSR range the row's dot product runs over:
   // [qrng[2q], qrng[2q+1]) -- the off-diagonals of an SpTRSV row (its
   // diagonal sits at qrng[2q+1]), the whole row of an SpMV row -- so an
-  // item's loads do not wait for the row pointers (SF_TRSV_SPMV only).
+  // item's loads do not wait for the row pointers.  SF_IC0_TRSV: the
+  // ranges of the SpTRSV rows (used by the unfused baseline's solve).
   std::vector<int32_t> qrng, cqrng;  // level plan, coarsened plan
   // Level-set baseline: items of SpTRSV rows grouped by level.
   std::vector<int32_t> lvl_items, lvl_item_ptr;

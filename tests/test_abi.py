@@ -68,6 +68,19 @@ def test_executor_argument_checks_are_host_side():
     assert lib.sf_exec_ic0_trsv(s2.handle, 1, fake, fake, None, 256, 1, None, 256, None, None) == 10
     # backward without the transposed schedule
     assert lib.sf_backward(s.handle, 0, fake, fake, fake, None, fake, fake, fake, None, 0, None) == 1
+    # kernel combinations 1 and 2: aliasing, missing outputs, wrong kind, rectangular A
+    f2, f3 = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.sf_exec_spmv_trsv(s.handle, 0, fake, fake, fake, f2, fake, None) == 1    # z aliases x
+    assert lib.sf_exec_spmv_trsv(s.handle, 0, None, fake, fake, f2, f3, None) == 1      # no A values
+    assert lib.sf_exec_unfused_spmv_trsv(s.handle, 0, fake, fake, fake, None, f3, None) == 1  # y needed
+    assert lib.sf_exec_trsv_trsv(s.handle, 0, fake, fake, None, f3, None) == 1          # x needed
+    assert lib.sf_exec_trsv_trsv(s.handle, 0, fake, fake, f2, f2, None) == 1            # x aliases z
+    assert lib.sf_exec_trsv_trsv(s2.handle, 0, fake, fake, f2, f3, None) == 1           # IC0 schedule
+    assert lib.sf_exec_trsv_trsv(s.handle, 3, fake, fake, f2, f3, None) == 1            # bad dtype
+    Ar = synth.from_scipy(__import__("scipy.sparse", fromlist=["random"]).random(
+        300, L.nrows, density=0.01, random_state=1, format="csr"))
+    sr = sfm.Schedule(L, Ar)
+    assert lib.sf_exec_spmv_trsv(sr.handle, 0, fake, fake, fake, f2, f3, None) == 5     # A not square
 
 
 def test_params_roundtrip():
