@@ -248,8 +248,9 @@ def main():
 
 def run_extras(args, sfm, synth, torch, dev, stream):
     """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted), the batched
-    refinement, kernel combinations 2 and 1 on the headline matrices, and
-    forward + backward (7-point 96^3, FP64 and FP32): fused vs unfused."""
+    refinement, kernel combinations 2 and 1 and the preconditioner apply on
+    the headline matrices, and forward + backward (7-point 96^3, FP64 and
+    FP32): fused vs unfused."""
     out = {}
 
     def time_it(fn, reps):
@@ -304,6 +305,19 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                                           "coarsened": s.info().coarsened}
             log("%s %s fused %.3f ms unfused %.3f ms" % (tag, name, tf, tu))
         sfm.sync_status(s)
+        # preconditioner apply w = L^{-1} r, z = L^{-T} w (L's own values)
+        sb = sfm.Schedule(L, A, want_backward=True)
+        f = lambda: sfm.ic_apply(sb, Lv, x, W=Y, Z=Z)
+        u = lambda: sfm.ic_apply(sb, Lv, x, W=Y, Z=Z, unfused=True)
+        tf, tu = time_it(f, reps), time_it(u, reps)
+        nb = pair_bytes(L.nrows, L.nnz, A.nnz, 1) + L.nnz * 4 + (L.nrows + 1) * 4  # + the L^T pattern and map
+        out["ic_apply_%s" % name] = {"fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
+                                     "speedup_vs_unfused": round(tu / tf, 3), "bytes": nb,
+                                     "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
+                                     "coarsened": [sb.info().coarsened, sb.info().back_coarsened]}
+        log("ic_apply %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
+        sfm.sync_status(sb)
+        del sb
     L, A = synth.workload("lap3d7_96")
     s = sfm.Schedule(L, A, want_backward=True)
     for dt, tname, vb in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):

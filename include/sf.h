@@ -262,6 +262,27 @@ sf_status sf_exec_unfused_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A
 sf_status sf_exec_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X, void* Z,
                             void* stream);
 
+/*
+ * sf_exec_ic_apply — the incomplete-Cholesky preconditioner apply of a PCG
+ * iteration (Table 2's solve pairs with the transposed factor):
+ *   w = L^{-1} r, then z = L^{-T} w,
+ * in one launch: the SpTRSV plan's items, then the transposed solve's items
+ * (reversed wavefronts of L^T, Sec. 2.2 DAGs), each backward row reading
+ * its own w_i as soon as it is final (F = I).  Needs a SF_TRSV_SPMV schedule
+ * inspected with want_backward = 1 (else SF_ERR_ARG); L is the factor (for
+ * instance from sf_exec_ic0_trsv) in the inspected pattern.  One
+ * right-hand side; R, W, Z are distinct device vectors of length n.  FP64
+ * results equal forward then backward substitution done row by row, bit for
+ * bit.  Errors: SF_ERR_ARG, SF_ERR_HIP.
+ */
+sf_status sf_exec_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W, void* Z,
+                           void* stream);
+
+/* Unfused baseline of sf_exec_ic_apply: the forward solve, then the
+ * transposed solve, as two launches. */
+sf_status sf_exec_unfused_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W,
+                                   void* Z, void* stream);
+
 /* Unfused baseline of sf_exec_trsv_trsv: two level-set solves. */
 sf_status sf_exec_unfused_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X,
                                     void* Z, void* stream);

@@ -99,6 +99,8 @@ _SIGS = {
     "sf_exec_unfused_spmv_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
     "sf_exec_trsv_trsv": [_P, _I, _P, _P, _P, _P, _P],
     "sf_exec_unfused_trsv_trsv": [_P, _I, _P, _P, _P, _P, _P],
+    "sf_exec_ic_apply": [_P, _I, _P, _P, _P, _P, _P],
+    "sf_exec_unfused_ic_apply": [_P, _I, _P, _P, _P, _P, _P],
 }
 
 
@@ -363,6 +365,22 @@ def trsv_trsv(sched: Schedule, L_val, b, *, X=None, Z=None, stream=None, unfused
     _check(fn(sched.handle, _dtype_code(L_val), L_val.data_ptr(), bp, _vec_ptr(X, n, "X")[0],
               _vec_ptr(Z, n, "Z")[0], _stream(stream)), "sf_exec_trsv_trsv")
     return X, Z
+
+
+def ic_apply(sched: Schedule, L_val, r, *, W=None, Z=None, stream=None, unfused=False):
+    """w = L^{-1} r, z = L^{-T} w (the incomplete-Cholesky preconditioner
+    apply); the schedule needs want_backward=True.  Returns (w, z)."""
+    n = sched.n
+    rp, _, k = _vec_ptr(r, n, "r")
+    if k != 1:
+        raise ValueError("ic_apply takes one right-hand side")
+    torch = _torch()
+    W = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if W is None else W
+    Z = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if Z is None else Z
+    fn = _lib().sf_exec_unfused_ic_apply if unfused else _lib().sf_exec_ic_apply
+    _check(fn(sched.handle, _dtype_code(L_val), L_val.data_ptr(), rp, _vec_ptr(W, n, "W")[0],
+              _vec_ptr(Z, n, "Z")[0], _stream(stream)), "sf_exec_ic_apply")
+    return W, Z
 
 
 def ic0_trsv(sched: Schedule, A_lower_val, b=None, *, L_val=None, X=None, stream=None, unfused=False,

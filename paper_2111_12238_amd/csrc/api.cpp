@@ -444,9 +444,88 @@ sf_status pair_entry(sf_schedule s, sf_dtype dtype, int mode, const void* L_val,
   return exec_pair(s, dtype, mode, L_val, A_val, B, Y, Z, fused && !s->no_fusion, st);
 }
 
+// Preconditioner apply z = L^{-T} L^{-1} r (k_precond).  Fused: forward and
+// backward items in one launch; unfused: the forward solve as its own
+// launch, then a backward-only launch.
+sf_status exec_precond(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* R, void* W, void* Z, bool fused,
+                       hipStream_t st) {
+  const int dtype = dt == SF_F64 ? 0 : 1;
+  const DeviceBuffers& d = s->dev;
+  PrecondArgs a{};
+  a.n = int32_t(s->n);
+  a.Lci = d.Lci;
+  a.LTrp = d.LTrp;
+  a.LTci = d.LTci;
+  a.LTmap = d.LTmap;
+  a.Lv = Lv;
+  a.R = R;
+  a.W = W;
+  a.Z = Z;
+  if (s->bchunked) {
+    a.border = d.bcorder;
+    a.bitem_ptr = d.bcitem_ptr;
+    a.n_bwd = int32_t(s->bcitem_ptr.size() - 1);
+    a.blloc = d.bclloc;
+    a.beloc = d.bceloc;
+  } else {
+    a.border = d.border;
+    a.bitem_ptr = d.bitem_ptr;
+    a.n_bwd = int32_t(s->bitem_ptr.size() - 1);
+  }
+  if (fused) {
+    if (s->chunked) {
+      a.forder = d.corder;
+      a.fqrng = d.cqrng;
+      a.fitem_ptr = d.citem_ptr;
+      a.fitems = d.ctrsv_items;
+      a.n_fwd = int32_t(s->ctrsv_items.size());
+      a.flloc = d.clloc;
+      a.feloc = d.celoc;
+    } else {
+      a.forder = d.order;
+      a.fqrng = d.qrng;
+      a.fitem_ptr = d.item_ptr;
+      a.fitems = d.trsv_items;
+      a.n_fwd = int32_t(s->trsv_items.size());
+    }
+  } else {
+    sf_status r = exec_ts_fused(s, dt, Lv, nullptr, R, int32_t(s->n), 1, W, int32_t(s->n), nullptr, 0, st);
+    if (r != SF_OK) return r;
+  }
+  sf_status r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  const int grid = persistent_grid(s, occupancy_precond(dtype));
+  Timer tm(s, st);
+  if (fused) SF_HIP(launch_fill_pending(W, size_t(s->n), dtype, st));
+  SF_HIP(launch_fill_pending(Z, size_t(s->n), dtype, st));
+  return hip_status(launch_precond(a, dtype, grid, st));
+}
+
+sf_status precond_entry(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W, void* Z,
+                        bool fused, void* stream) {
+  if (!s || s->kind != SF_TRSV_SPMV || !s->has_back) return SF_ERR_ARG;
+  if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (!L_val || !R || !W || !Z || R == W || R == Z || W == Z) return SF_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sf_status r = upload(s, st);
+  if (r != SF_OK) return r;
+  return exec_precond(s, dtype, L_val, R, W, Z, fused && !s->no_fusion, st);
+}
+
 }  // namespace
 
 extern "C" {
+
+sf_status sf_exec_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W, void* Z,
+                           void* stream) {
+  return precond_entry(s, dtype, L_val, R, W, Z, true, stream);
+}
+
+sf_status sf_exec_unfused_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W,
+                                   void* Z, void* stream) {
+  return precond_entry(s, dtype, L_val, R, W, Z, false, stream);
+}
 
 sf_status sf_exec_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val, const void* X,
                             void* Y, void* Z, void* stream) {

@@ -77,6 +77,71 @@ __global__ __launch_bounds__(kBlockThreads) void k_bwd(BwdArgs a) {
   }
 }
 
+// Preconditioner apply, z = L^{-T} (L^{-1} r), the solve pair a PCG
+// iteration with an incomplete Cholesky factor needs.  Work tickets
+// [0, n_fwd) are the forward plan's SpTRSV items (w_i = (r_i - sum L_ij w_j)
+// / L_ii), tickets [n_fwd, n_fwd + n_bwd) the transposed plan's items
+// (z_i = (w_i - sum_{j>i} L_ji z_j) / L_ii, ascending j); a backward row
+// reads its own w_i through the readiness protocol (F = I).  Every backward
+// item follows every forward item in the claim order, so the order stays
+// topological; with only backward tickets (n_fwd = 0, w final) the same
+// kernel is the second launch of the unfused baseline.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void k_precond(PrecondArgs a) {
+  __shared__ WaveLds<T> lds[kWaves];
+  __shared__ T lloc_x[kWaves][65];  // item-local results by slot; [64] = 1.0
+  const int lane = threadIdx.x & 63;
+  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  T* xl = lloc_x[threadIdx.x >> 6];
+  if (lane == 0) xl[64] = T(1);
+  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
+  T* W = static_cast<T*>(a.W);
+  T* Z = static_cast<T*>(a.Z);
+  dev::reset_next_launch(a.ls);
+  int t = dev::claim(a.ls, lane);
+  while (t < a.n_fwd + a.n_bwd) {
+    const int tn = dev::claim(a.ls, lane);
+    if (t < a.n_fwd) {
+      const int it = a.fitems[t];
+      const int q0 = a.fitem_ptr[it], q1 = a.fitem_ptr[it + 1], nr = q1 - q0;
+      const bool mine = lane < nr;
+      const int row = mine ? a.forder[q0 + lane] : 0;
+      const int2 rg = mine ? reinterpret_cast<const int2*>(a.fqrng)[q0 + lane] : make_int2(0, 0);
+      const T ri = mine ? static_cast<const T*>(a.R)[row] : T(0);
+      const T dii = mine ? Lv[rg.y] : T(1);
+      if (a.flloc && a.flloc[q1 - 1] != 0) {
+        const int myloc = mine ? int(a.flloc[q0 + lane]) : 0;
+        dev::chunk_solve<T, false>(nr, rg.x, rg.y - rg.x, myloc, int(a.flloc[q1 - 1]), ri, dii, a.Lci, nullptr, Lv,
+                                   a.feloc, W, row, lane, w, xl, a.ls, nullptr);
+      } else {
+        const T acc = stream_accumulate<T, true, 2, false>(nr, rg.x, rg.y - rg.x, ri, a.Lci, nullptr, Lv, W, lane,
+                                                           w, a.ls);
+        if (mine) st_co(W + row, publishable(acc / dii));
+      }
+    } else {
+      const int it = t - a.n_fwd;
+      const int q0 = a.bitem_ptr[it], q1 = a.bitem_ptr[it + 1], nr = q1 - q0;
+      const bool mine = lane < nr;
+      const int i = mine ? a.border[q0 + lane] : 0;
+      const int e0 = mine ? a.LTrp[i] : 0, e1 = mine ? a.LTrp[i + 1] : 0;  // diagonal first
+      const T lii = mine ? Lv[a.LTmap[e0]] : T(1);
+      int j[1] = {mine ? i : -1};
+      T wi[1] = {mine ? dev::ld_co(W + i) : T(0)};
+      dev::wait_ready<T, 1>(W, j, wi, lane, a.ls);
+      if (a.blloc && a.blloc[q1 - 1] != 0) {
+        const int myloc = mine ? int(a.blloc[q0 + lane]) : 0;
+        dev::chunk_solve<T, true>(nr, e0 + 1, e1 - (e0 + 1), myloc, int(a.blloc[q1 - 1]), wi[0], lii, a.LTci,
+                                  a.LTmap, Lv, a.beloc, Z, i, lane, w, xl, a.ls, nullptr);
+      } else {
+        const T acc = stream_accumulate<T, true, 2, true>(nr, e0 + 1, e1 - (e0 + 1), wi[0], a.LTci, a.LTmap, Lv, Z,
+                                                          lane, w, a.ls);
+        if (mine) st_co(Z + i, publishable(acc / lii));
+      }
+    }
+    t = tn;
+  }
+}
+
 template <typename K>
 int occ(K kernel) {
   int b = 0;
@@ -94,6 +159,16 @@ hipError_t launch_bwd(const BwdArgs& a, int dtype, int g, int grid, hipStream_t 
   else hipLaunchKernelGGL(k_bwd<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
 }
+
+hipError_t launch_precond(const PrecondArgs& a, int dtype, int grid, hipStream_t st) {
+  if ((a.n_fwd > 0 && (!a.forder || !a.fqrng || !a.fitem_ptr || !a.fitems)) || !a.border || !a.bitem_ptr)
+    return hipErrorInvalidValue;
+  if (dtype == 0) hipLaunchKernelGGL(k_precond<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  else hipLaunchKernelGGL(k_precond<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+int occupancy_precond(int dtype) { return dtype == 0 ? occ(k_precond<double>) : occ(k_precond<float>); }
 
 int occupancy_bwd(int dtype, int g) {
   (void)g;

@@ -93,6 +93,25 @@ struct BwdArgs {
   LaunchState ls;
 };
 
+// Preconditioner apply z = L^{-T} (L^{-1} r): forward items of the SpTRSV
+// plan, then backward items of the transposed plan, in one claim sequence.
+struct PrecondArgs {
+  int32_t n;
+  const int32_t *Lci, *LTrp, *LTci, *LTmap;
+  const void* Lv;
+  const void* R;
+  void *W, *Z;             // w = L^{-1} r and z = L^{-T} w (both pending-filled)
+  // forward plan (level or coarsened SpTRSV items)
+  const int32_t *forder, *fqrng, *fitem_ptr, *fitems;
+  int32_t n_fwd;
+  const uint8_t *flloc, *feloc;
+  // backward plan over L^T
+  const int32_t *border, *bitem_ptr;
+  int32_t n_bwd;
+  const uint8_t *blloc, *beloc;
+  LaunchState ls;
+};
+
 // Refinement passes (FP64 residual, final product).
 // Interleaved blocks: element (j, c) of an n x (nblk * kb) array lives at
 // ((c / kb) * n + j) * kb + c % kb, so the kb columns of a block are
@@ -128,6 +147,8 @@ hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st);
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);
 hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st);
 hipError_t launch_bwd(const BwdArgs& a, int dtype, int g, int grid, hipStream_t st);
+hipError_t launch_precond(const PrecondArgs& a, int dtype, int grid, hipStream_t st);
+int occupancy_precond(int dtype);
 hipError_t launch_residual(const ResArgs& a, hipStream_t st);
 hipError_t launch_final(const ResArgs& a, hipStream_t st);
 hipError_t launch_convert_f64_f32(const double* src, int32_t lds, float* dst, int32_t n,

@@ -81,6 +81,12 @@ def test_executor_argument_checks_are_host_side():
         300, L.nrows, density=0.01, random_state=1, format="csr"))
     sr = sfm.Schedule(L, Ar)
     assert lib.sf_exec_spmv_trsv(sr.handle, 0, fake, fake, fake, f2, f3, None) == 5     # A not square
+    # preconditioner apply: needs the transposed schedule, distinct vectors
+    assert lib.sf_exec_ic_apply(s.handle, 0, fake, fake, f2, f3, None) == 1             # no L^T plan
+    sb = sfm.Schedule(L, A, want_backward=True)
+    assert lib.sf_exec_ic_apply(sb.handle, 0, fake, fake, f2, f2, None) == 1            # w aliases z
+    assert lib.sf_exec_ic_apply(sb.handle, 0, fake, f2, f2, f3, None) == 1              # r aliases w
+    assert lib.sf_exec_unfused_ic_apply(sb.handle, 2, fake, fake, f2, f3, None) == 1    # bad dtype
 
 
 def test_params_roundtrip():
