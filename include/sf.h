@@ -86,14 +86,15 @@ typedef struct sf_schedule_s* sf_schedule;
 /* Inspector options; 0 in any field selects the default. */
 typedef struct {
   int32_t kind;           /* sf_kind */
-  int32_t rows_per_item;  /* maximum rows in one work item (default: from lanes_per_row) */
+  int32_t rows_per_item;  /* maximum rows in one work item (default 64; SpIC0 items hold
+                             one batch of 64 / lanes_per_row rows) */
   int32_t max_item_nnz;   /* cost budget of one work item, summing the paper's vertex
                              cost c(v) (Sec. 3.1) = max(1, off-diagonals of the row);
                              default 512 */
   int32_t rhs_block;      /* right-hand sides walked together per DAG pass (default: autotuned
                              / all) */
-  int32_t lanes_per_row;  /* lanes of a 64-wide wavefront cooperating on one SpTRSV row
-                             (1, 2, 4, 8, 16, 32, 64; default from the mean row length) */
+  int32_t lanes_per_row;  /* lanes of a 64-wide wavefront per SpIC0 row, one per stored
+                             entry (4..64, a power of two; default: the longest row) */
   int32_t want_backward;  /* 1: also build the transposed (upper-solve) schedule for sf_backward */
   int32_t validate;       /* 1: check the built schedule against every DAG edge before returning */
   int32_t no_fusion;      /* 1: executor calls run the unfused two-phase baseline instead (the
@@ -354,7 +355,11 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
 
 /*
  * Tuning knobs of the executor (defaults are set by sf_inspect):
- *   "lanes_trsv", "lanes_spmv"  lanes per row (1..64, power of two);
+ *   "lanes_trsv"                lanes per SpIC0 row (SF_IC0_TRSV, 4..64, a
+ *                               power of two; re-cuts the items);
+ *   "lanes_spmv"                kept for compatibility: SpTRSV and SpMV rows
+ *                               deal their entries over all 64 lanes, so
+ *                               lanes per row no longer select a kernel;
  *   "rhs_block"                 right-hand sides per DAG pass (1..64);
  *   "waves_per_cu"              persistent-grid residency target (1..32);
  *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT;

@@ -279,10 +279,10 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
       a.lloc = s->dev.clloc;
       a.eloc = s->dev.celoc;
     }
-    const int grid = persistent_grid(s, occupancy_ts_fused(dtype, s->lanes_trsv, s->lanes_spmv));
+    const int grid = persistent_grid(s, occupancy_ts_fused(dtype));
     Timer tm(s, st);
     SF_HIP(launch_fill_pending(X, size_t(s->n), dtype, st));
-    return hip_status(launch_ts_fused(a, dtype, s->lanes_trsv, s->lanes_spmv, grid, st));
+    return hip_status(launch_ts_fused(a, dtype, grid, st));
   }
   const int kb = s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
   const int nblk = (nrhs + kb - 1) / kb;
@@ -331,9 +331,9 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
   Timer tm(s, st);
   if (s->n > 0 && s->depth > 0) {
     const int cus = std::max(1, device_cus());
-    const int occ = occupancy_trsv_levelset(dtype, s->lanes_trsv);
+    const int occ = occupancy_trsv_levelset(dtype);
     int grid = cus * std::min(occ, std::max(1, s->waves_per_cu * 64 / kBlockThreads));
-    SF_HIP(launch_trsv_levelset(la, dtype, s->lanes_trsv, grid, st));
+    SF_HIP(launch_trsv_levelset(la, dtype, grid, st));
   }
   if (Y && s->m > 0 && nrhs == 1) {
     TsArgs sa = ts_args(s, Lv, Av, B, ldb, nrhs, X, ldx, Y, ldy);
@@ -351,7 +351,7 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
     sa.ldx = ldx;
     sa.Y = Y;
     sa.ldy = ldy;
-    SF_HIP(launch_spmv(sa, dtype, s->lanes_spmv, st));
+    SF_HIP(launch_spmv(sa, dtype, st));
   }
   return SF_OK;
 }
@@ -805,8 +805,8 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   r = next_epoch(s, st, la.ts.ls);
   if (r != SF_OK) return r;
   const int g = std::min(s->lanes_trsv, 32);
-  grid = cus * std::min(occupancy_trsv_levelset(0, g), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
-  return hip_status(launch_trsv_levelset(la, 0, g, grid, st));
+  grid = cus * std::min(occupancy_trsv_levelset(0), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  return hip_status(launch_trsv_levelset(la, 0, grid, st));
 }
 
 sf_status sf_exec_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,

@@ -417,9 +417,7 @@ int cu_count() {
 
 }  // namespace
 
-hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid, hipStream_t st) {
-  (void)gt;
-  (void)gs;
+hipError_t launch_ts_fused(const TsArgs& a, int dtype, int grid, hipStream_t st) {
   if (!a.qrng || !a.order || !a.item_ptr) return hipErrorInvalidValue;  // rows are streamed by claim position
   if (dtype == 0) hipLaunchKernelGGL(k_ts_fused<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   else hipLaunchKernelGGL(k_ts_fused<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
@@ -443,8 +441,7 @@ int occupancy_pair(int dtype, int mode) {
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st) {
   return dtype == 0 ? ts_multi_dispatch<double>(a, kb, grid, st) : ts_multi_dispatch<float>(a, kb, grid, st);
 }
-hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st) {
-  (void)gt;
+hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st) {
   if (a.ts.nrhs == 1 && (!a.ts.qrng || !a.ts.order || !a.ts.item_ptr)) return hipErrorInvalidValue;
   return dtype == 0 ? levelset_launch<double>(a, grid, st) : levelset_launch<float>(a, grid, st);
 }
@@ -455,8 +452,7 @@ hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st) {
   else hipLaunchKernelGGL(k_spmv_items<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
 }
-hipError_t launch_spmv(const SpmvArgs& a, int dtype, int gs, hipStream_t st) {
-  (void)gs;
+hipError_t launch_spmv(const SpmvArgs& a, int dtype, hipStream_t st) {
   int grid = (a.m + kBlockThreads - 1) / kBlockThreads;
   grid = grid < 1 ? 1 : (grid > cu_count() * 32 ? cu_count() * 32 : grid);
   if (dtype == 0) hipLaunchKernelGGL(k_spmv<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
@@ -473,17 +469,14 @@ hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st)
     hipLaunchKernelGGL(k_fill_pending<float>, dim3(grid), dim3(256), 0, st, static_cast<float*>(p), count);
   return hipGetLastError();
 }
-int occupancy_ts_fused(int dtype, int gt, int gs) {
-  (void)gt;
-  (void)gs;
+int occupancy_ts_fused(int dtype) {
   return dtype == 0 ? occ(k_ts_fused<double>) : occ(k_ts_fused<float>);
 }
 int occupancy_ts_multi(int dtype, int kb) {
   (void)kb;
   return dtype == 0 ? occ(k_ts_multi<double, 8>) : occ(k_ts_multi<float, 8>);
 }
-int occupancy_trsv_levelset(int dtype, int gt) {
-  (void)gt;
+int occupancy_trsv_levelset(int dtype) {
   return dtype == 0 ? occ(k_trsv_levelset<double>) : occ(k_trsv_levelset<float>);
 }
 

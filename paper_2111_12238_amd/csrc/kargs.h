@@ -136,12 +136,12 @@ struct ResArgs {
 };
 
 // Launchers (return the HIP error of the launch).
-hipError_t launch_ts_fused(const TsArgs& a, int dtype, int gt, int gs, int grid, hipStream_t st);
+hipError_t launch_ts_fused(const TsArgs& a, int dtype, int grid, hipStream_t st);
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
 hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st);
 int occupancy_pair(int dtype, int mode);
-hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int gt, int grid, hipStream_t st);
-hipError_t launch_spmv(const SpmvArgs& a, int dtype, int gs, hipStream_t st);
+hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st);
+hipError_t launch_spmv(const SpmvArgs& a, int dtype, hipStream_t st);
 // SpMV items of a schedule (a.item_list / a.n_work), all inputs final.
 hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st);
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);
@@ -159,9 +159,9 @@ hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st)
 
 
 // Occupancy queries per kernel family (blocks per CU).
-int occupancy_ts_fused(int dtype, int gt, int gs);
+int occupancy_ts_fused(int dtype);
 int occupancy_ts_multi(int dtype, int kb);
-int occupancy_trsv_levelset(int dtype, int gt);
+int occupancy_trsv_levelset(int dtype);
 int occupancy_ic0(int g, int levelset);
 int occupancy_bwd(int dtype, int g);
 
