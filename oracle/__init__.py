@@ -47,6 +47,8 @@ def _bind(lib):
         "orc_spmv_t": (None, [_c_int, _c_int, _i32p, _i32p, _f64p, _f64p, _f64p]),
         "orc_trsv_upper_t": (None, [_c_int, _i32p, _i32p, _f64p, _f64p, _f64p]),
         "orc_ic0": (_c_int, [_c_int, _i32p, _i32p, _f64p, _f64p]),
+        "orc_ilu0": (_c_int, [_c_int, _i32p, _i32p, _f64p, _f64p]),
+        "orc_trsv_unit_lower": (None, [_c_int, _i32p, _i32p, _f64p, _f64p, _f64p]),
         "orc_backward": (None, [_c_int, _c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p,
                                 _f64p, _f64p, _f64p, _f64p]),
         "orc_levels": (_c_int, [_c_int, _i32p, _i32p, _i32p]),
@@ -145,6 +147,26 @@ class Oracle:
         l = np.zeros(len(a), np.float64)
         fail = self.lib.orc_ic0(n, rp, _ptr(ci), _ptr(a), _ptr(l))
         return l, int(fail)
+
+    def ilu0(self, rp, ci, a):
+        """Zero fill-in incomplete LU of A (Table 2, combination 6).
+
+        Returns (L and U values in A's pattern -- L strictly below the
+        diagonal with its unit diagonal implied, U on and above it --, first
+        row with a zero or NaN pivot or -1)."""
+        rp, ci, a = _i32(rp), _i32(ci), _f64(a)
+        n = len(rp) - 1
+        lu = np.zeros(len(a), np.float64)
+        fail = self.lib.orc_ilu0(n, rp, _ptr(ci), _ptr(a), _ptr(lu))
+        return lu, int(fail)
+
+    def trsv_unit_lower(self, rp, ci, v, b):
+        """y = L^{-1} b for the unit-lower L held in the strictly lower part."""
+        rp, ci, v, b = _i32(rp), _i32(ci), _f64(v), _f64(b)
+        n = len(rp) - 1
+        y = np.zeros(n, np.float64)
+        self.lib.orc_trsv_unit_lower(n, rp, _ptr(ci), _ptr(v), _ptr(b), _ptr(y))
+        return y
 
     def backward(self, lrp, lci, lv, arp, aci, av, x, g):
         """Adjoint of y = A L^{-1} b: returns (grad_b, grad_L values)."""

@@ -27,6 +27,11 @@
  *     pattern.
  *   - Reuse ratio = common accesses / max(accesses of each kernel)
  *     (Sec. 2.2, "Reuse Ratio"; Table 2 last column).
+ *   - SpILU0 is zero fill-in incomplete LU, L U ~= A (Table 2, combinations
+ *     3 and 6).  The paper gives no recurrence; the one used here is
+ *     row-wise Gaussian elimination restricted to the pattern of A (the IKJ
+ *     variant): the unique unit-lower L and upper U on pattern(A) with
+ *     (L U)_ij = A_ij on that pattern.
  *   - Adjoint of y = A L^{-1} b (not in the paper): with g = dloss/dy,
  *     lambda = L^{-T} (A^T g), grad_b = lambda, grad_L = -lambda x^T
  *     restricted to the pattern of L.
@@ -200,6 +205,55 @@ int orc_ic0(int n, const int32_t* rp, const int32_t* ci, const double* a, double
     l[pdiag] = sqrt(d);
   }
   return fail;
+}
+
+/* Zero fill-in incomplete LU by row-wise elimination on the pattern of A
+ * (columns sorted in each row).  lu starts as a copy of a; for row i and each
+ * stored k < i in ascending order: lu_ik /= u_kk, then lu_ij -= lu_ik * u_kj
+ * for every stored j > k of row i whose (k, j) is stored.  Afterwards the
+ * strictly lower part of lu is L (unit diagonal implied) and the rest is U.
+ * Returns the first row whose pivot u_ii is zero, NaN or not stored, -1 if
+ * none; elimination continues past it (its dependents get Inf/NaN). */
+int orc_ilu0(int n, const int32_t* rp, const int32_t* ci, const double* a, double* lu) {
+  int fail = -1;
+  for (int p = 0; p < rp[n]; ++p) lu[p] = a[p];
+  for (int i = 0; i < n; ++i) {
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int k = ci[p];
+      if (k >= i) break;
+      double ukk = 0.0;
+      int pk = rp[k + 1];
+      for (int q = rp[k]; q < rp[k + 1]; ++q) {
+        if (ci[q] == k) ukk = lu[q];
+        if (ci[q] > k) { pk = q; break; }
+      }
+      lu[p] = lu[p] / ukk;
+      /* merge the rest of row i with the part of row k right of k */
+      int pi = p + 1;
+      while (pi < rp[i + 1] && pk < rp[k + 1]) {
+        int ji = ci[pi], jk = ci[pk];
+        if (ji == jk) { lu[pi] -= lu[p] * lu[pk]; ++pi; ++pk; }
+        else if (ji < jk) ++pi;
+        else ++pk;
+      }
+    }
+    double d = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) if (ci[p] == i) d = lu[p];
+    if (!(d != 0.0) && fail < 0) fail = i;
+  }
+  return fail;
+}
+
+/* Forward substitution with a unit-lower L stored as the strictly lower part
+ * of a CSR matrix (other entries ignored): y_i = b_i - sum_{j<i} L_ij y_j. */
+void orc_trsv_unit_lower(int n, const int32_t* rp, const int32_t* ci, const double* v,
+                         const double* b, double* y) {
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (ci[p] < i) s -= v[p] * y[ci[p]];
+    y[i] = s;
+  }
 }
 
 /* Gradients of loss = <w, A L^{-1} b>: given x = L^{-1} b and g = w,

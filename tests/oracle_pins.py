@@ -399,4 +399,94 @@ def _golden(name):
     return out
 
 
+# ---------------------------------------------------------------- SpILU0 ----
+def _ilu_factors(orc, a):
+    lu, fail = orc.ilu0(a.rowptr, a.col, a.val)
+    d = sp.csr_matrix((lu, a.col, a.rowptr), shape=(a.nrows, a.nrows)).toarray()
+    n = a.nrows
+    return np.tril(d, -1) + np.eye(n), np.triu(d), fail
+
+
+def pin_ilu0_tridiagonal_is_lu(orc):
+    """A tridiagonal matrix has no fill, so ILU0 is its LU factorisation;
+    diagonal dominance makes LAPACK's partial pivoting pick no row swap, so
+    scipy.linalg.lu must return the same factors (nonsymmetric values)."""
+    import scipy.linalg as la
+    n = 40
+    rng = np.random.default_rng(4)
+    d = (np.diag(rng.uniform(4, 5, n)) + np.diag(rng.uniform(-1, 0, n - 1), -1)
+         + np.diag(rng.uniform(-2, 1, n - 1), 1))
+    a = _csr(d)
+    Lm, Um, fail = _ilu_factors(orc, a)
+    P, Lr, Ur = la.lu(d)
+    assert fail == -1 and np.array_equal(P, np.eye(n)), "no pivoting expected"
+    assert np.abs(Lm - Lr).max() <= 8 * U64 and np.abs(Um - Ur).max() <= 8 * U64 * np.abs(Ur).max()
+
+
+def pin_ilu0_product_matches_on_pattern(orc):
+    """The defining property: (L U)_ij = A_ij for every stored (i, j), with L
+    unit lower and U upper on the pattern of A (nonsymmetric patterns and
+    values, fill positions outside the pattern not constrained)."""
+    for seed, n in ((1, 60), (2, 200)):
+        rng = np.random.default_rng(seed)
+        m = sp.random(n, n, density=6.0 / n, random_state=rng, format="csr")
+        m.data = rng.uniform(-1, 1, m.nnz)
+        m = (m + sp.diags(np.abs(m).sum(1).A1 + 1.0)).tocsr()
+        m.sort_indices()
+        a = synth.from_scipy(m)
+        Lm, Um, fail = _ilu_factors(orc, a)
+        assert fail == -1
+        prod = Lm @ Um
+        mask = m.toarray() != 0
+        mask[np.diag_indices(n)] = True
+        err = np.abs(prod - m.toarray())[mask].max()
+        assert err <= 64 * U64 * np.abs(m.toarray()).max(), ("LU on pattern", seed, err)
+        assert np.all(Lm[~mask & (np.tril(np.ones((n, n)), -1) > 0)] == 0)
+        assert np.all(Um[~mask & (np.triu(np.ones((n, n))) > 0)] == 0)
+
+
+def pin_ilu0_symmetric_matches_ic0(orc):
+    """On a symmetric positive definite matrix with symmetric pattern, ILU0
+    and IC0 are the same factorisation up to scaling: with C the IC0 factor,
+    L = C diag(C)^{-1} and U = diag(C) C^T (the pinned IC0 above)."""
+    a = synth.laplacian_3d27(5, 4, 4, 26.1)
+    lower = synth.lower(a)
+    c, fail_c = orc.ic0(lower.rowptr, lower.col, lower.val)
+    Lm, Um, fail = _ilu_factors(orc, a)
+    assert fail == -1 and fail_c == -1
+    C = sp.csr_matrix((c, lower.col, lower.rowptr), shape=(a.nrows, a.nrows)).toarray()
+    dc = np.diag(C)
+    assert np.abs(Lm - C / dc[None, :]).max() <= 32 * U64
+    assert np.abs(Um - dc[:, None] * C.T).max() <= 64 * U64 * np.abs(Um).max()
+
+
+def pin_ilu0_zero_pivot_row(orc):
+    """A zero pivot (u_11 = 0 after elimination) is reported at its row;
+    the first of two failing rows is the one returned."""
+    d = np.array([[2.0, 1.0, 0.0, 0.0], [4.0, 2.0, 1.0, 0.0], [0.0, 1.0, 3.0, 1.0], [0.0, 0.0, 3.0, 1.0]])
+    # row 1: u_11 = 2 - (4/2) * 1 = 0
+    _, _, fail = _ilu_factors(orc, _csr(d))
+    assert fail == 1
+    # rows 2 and 4 have no stored diagonal: the first of them is reported
+    _, _, fail2 = _ilu_factors(orc, _csr(np.diag([1.0, 1.0, 0.0, 1.0, 0.0])))
+    assert fail2 == 2
+
+
+def pin_trsv_unit_lower(orc):
+    """Unit-lower solve: integer L below the diagonal (any stored diagonal or
+    upper entries are ignored) and integer y give integer b exactly; the
+    solve must return y bit for bit."""
+    rng = np.random.default_rng(5)
+    n = 300
+    m = sp.random(n, n, density=0.02, random_state=rng, format="csr")
+    m.data = rng.integers(-2, 3, m.nnz).astype(np.float64)
+    m = (m + sp.diags(np.full(n, 7.0))).tocsr()
+    m.sort_indices()
+    a = synth.from_scipy(m)
+    low = sp.tril(m, -1).toarray() + np.eye(n)
+    y = rng.integers(-5, 6, n).astype(np.float64)
+    b = low @ y
+    assert np.array_equal(orc.trsv_unit_lower(a.rowptr, a.col, a.val, b), y)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

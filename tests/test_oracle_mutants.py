@@ -39,6 +39,12 @@ MUTANTS = {
     "validate_nonstrict": ("int ok = item[j] < item[i] ||", "int ok = item[j] <= item[i] ||"),
     "reuse_dropped_term": ("double kl = (double)nnz_l + (double)n + (double)n;",
                            "double kl = (double)nnz_l + (double)n;"),
+    "ilu0_no_divide": ("lu[p] = lu[p] / ukk;", "lu[p] = lu[p];"),
+    "ilu0_sign": ("if (ji == jk) { lu[pi] -= lu[p] * lu[pk];", "if (ji == jk) { lu[pi] += lu[p] * lu[pk];"),
+    "ilu0_wrong_operand": ("if (ji == jk) { lu[pi] -= lu[p] * lu[pk];", "if (ji == jk) { lu[pi] -= lu[p] * lu[pi];"),
+    "ilu0_last_failure": ("if (!(d != 0.0) && fail < 0) fail = i;", "if (!(d != 0.0)) fail = i;"),
+    "unit_lower_divides": ("      if (ci[p] < i) s -= v[p] * y[ci[p]];\n    y[i] = s;",
+                           "      if (ci[p] < i) s -= v[p] * y[ci[p]];\n    y[i] = s / 7.0;"),
 }
 
 
