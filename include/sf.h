@@ -68,7 +68,8 @@ typedef enum { SF_F64 = 0, SF_F32 = 1 } sf_dtype;
 
 typedef enum {
   SF_TRSV_SPMV = 0, /* L and A given: x = L^{-1} b, y = A x */
-  SF_IC0_TRSV = 1   /* lower(A) given as L: L L^T ~= A, x = L^{-1} b */
+  SF_IC0_TRSV = 1,  /* lower(A) given as L: L L^T ~= A, x = L^{-1} b */
+  SF_ILU0_TRSV = 2  /* the whole square A given as L: L U ~= A, y = L^{-1} x (unit L) */
 } sf_kind;
 
 /* A sparsity pattern on the host: nrows x ncols, rowptr[nrows + 1],
@@ -287,6 +288,30 @@ sf_status sf_exec_unfused_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_
 /* Unfused baseline of sf_exec_trsv_trsv: two level-set solves. */
 sf_status sf_exec_unfused_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X,
                                     void* Z, void* stream);
+
+/*
+ * sf_exec_ilu0_trsv — fused SpILU0 -> SpTRSV (Table 2, comb. 6), FP64:
+ *   L U ~= A with zero fill-in (L unit lower, U upper, both on pattern(A)),
+ *   then y = L^{-1} x.
+ * The schedule must be of kind SF_ILU0_TRSV, inspected from the whole
+ * square pattern of A (sorted columns, every diagonal stored; A need not
+ * be symmetric).  Row i of the factors is row-wise elimination restricted
+ * to the pattern, each sum in ascending column order; row i of the solve
+ * runs in the same work item (F = I).  Device arrays: A_val (nnz, read),
+ * LU_val (nnz, written: L strictly below the diagonal, U on and above it,
+ * in A's CSR positions), X and Y (n; X = NULL skips the solve).  d_info
+ * (device int32, may be NULL) receives -1, or the smallest row whose pivot
+ * u_ii is zero or NaN; the launch completes either way.  FP64 results equal
+ * the sequential definition bit for bit.  Rows with more stored entries
+ * than lanes_per_row (at most 64) give SF_ERR_UNSUPPORTED.
+ */
+sf_status sf_exec_ilu0_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val, const void* X,
+                            void* Y, int32_t* d_info, void* stream);
+
+/* Unfused baseline of sf_exec_ilu0_trsv: a level-set factorisation (one
+ * grid barrier per level), then a level-set solve reading the factor. */
+sf_status sf_exec_unfused_ilu0_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val,
+                                    const void* X, void* Y, int32_t* d_info, void* stream);
 
 /*
  * sf_exec_ic0_trsv — fused SpIC0 -> SpTRSV (Table 2, comb. 5), FP64.

@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsparsefusion.so")
 
 SF_F64, SF_F32 = 0, 1
-SF_TRSV_SPMV, SF_IC0_TRSV = 0, 1
+SF_TRSV_SPMV, SF_IC0_TRSV, SF_ILU0_TRSV = 0, 1, 2
 
 STATUS = {
     0: "SF_OK", 1: "SF_ERR_ARG", 2: "SF_ERR_CSR", 3: "SF_ERR_NOT_LOWER", 4: "SF_ERR_ZERO_DIAG",
@@ -100,6 +100,8 @@ _SIGS = {
     "sf_exec_trsv_trsv": [_P, _I, _P, _P, _P, _P, _P],
     "sf_exec_unfused_trsv_trsv": [_P, _I, _P, _P, _P, _P, _P],
     "sf_exec_ic_apply": [_P, _I, _P, _P, _P, _P, _P],
+    "sf_exec_ilu0_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
+    "sf_exec_unfused_ilu0_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
     "sf_exec_unfused_ic_apply": [_P, _I, _P, _P, _P, _P, _P],
 }
 
@@ -381,6 +383,29 @@ def ic_apply(sched: Schedule, L_val, r, *, W=None, Z=None, stream=None, unfused=
     _check(fn(sched.handle, _dtype_code(L_val), L_val.data_ptr(), rp, _vec_ptr(W, n, "W")[0],
               _vec_ptr(Z, n, "Z")[0], _stream(stream)), "sf_exec_ic_apply")
     return W, Z
+
+
+def ilu0_trsv(sched: Schedule, A_val, x=None, *, LU_val=None, Y=None, stream=None, unfused=False,
+              check_info=True):
+    """L U ~= A (zero fill, Table 2 combination 6) and y = L^{-1} x in one
+    launch.  Returns (LU values in A's pattern, y or None, info tensor)."""
+    torch = _torch()
+    n = sched.n
+    LU_val = torch.empty_like(A_val) if LU_val is None else LU_val
+    info = torch.full((1,), -1, dtype=torch.int32, device=A_val.device)
+    xp = yp = None
+    if x is not None:
+        xp = _vec_ptr(x, n, "x")[0]
+        Y = torch.empty(n, dtype=A_val.dtype, device=A_val.device) if Y is None else Y
+        yp = _vec_ptr(Y, n, "Y")[0]
+    fn = _lib().sf_exec_unfused_ilu0_trsv if unfused else _lib().sf_exec_ilu0_trsv
+    _check(fn(sched.handle, _dtype_code(A_val), A_val.data_ptr(), LU_val.data_ptr(), xp, yp, info.data_ptr(),
+              _stream(stream)), "sf_exec_ilu0_trsv")
+    if check_info:
+        row = int(info.item())
+        if row >= 0:
+            raise SparseFusionError(6, "sf_exec_ilu0_trsv", row)
+    return LU_val, (Y if x is not None else None), info
 
 
 def ic0_trsv(sched: Schedule, A_lower_val, b=None, *, L_val=None, X=None, stream=None, unfused=False,

@@ -93,6 +93,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oATrp = pk.add(&s->AT.rp), oATci = pk.add(&s->AT.ci), oATm = pk.add(&s->AT_map);
   const size_t oBo = pk.add(&s->border), oBip = pk.add(&s->bitem_ptr);
   const size_t oPp = pk.add(&s->pair_ptr), oPu = pk.add(&s->pair_u), oPq = pk.add(&s->pair_q);
+  const size_t oDp = pk.add(&s->dpos);
   const size_t oCo = pk.add(&s->corder), oCip = pk.add(&s->citem_ptr), oCti = pk.add(&s->ctrsv_items);
   const size_t oCl = pk.add(&s->clloc), oCe = pk.add(&s->celoc);
   const size_t oQr = pk.add(&s->qrng), oCqr = pk.add(&s->cqrng);
@@ -117,6 +118,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.ATrp = P(oATrp); d.ATci = P(oATci); d.ATmap = P(oATm);
   d.border = P(oBo); d.bitem_ptr = P(oBip);
   d.pair_ptr = P(oPp); d.pair_u = P(oPu); d.pair_q = P(oPq);
+  d.dpos = P(oDp);
   d.corder = P(oCo); d.citem_ptr = P(oCip); d.ctrsv_items = P(oCti);
   d.clloc = reinterpret_cast<uint8_t*>(b + oCl);
   d.celoc = reinterpret_cast<uint8_t*>(b + oCe);
@@ -572,13 +574,13 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
   *out = nullptr;
   sf_inspect_opts o{};
   if (opts) o = *opts;
-  if (o.kind != SF_TRSV_SPMV && o.kind != SF_IC0_TRSV) return SF_ERR_ARG;
+  if (o.kind != SF_TRSV_SPMV && o.kind != SF_IC0_TRSV && o.kind != SF_ILU0_TRSV) return SF_ERR_ARG;
   if (o.lanes_per_row != 0 && !pow2_in(o.lanes_per_row, 2, 64)) return SF_ERR_ARG;
   if (o.rows_per_item < 0 || o.max_item_nnz < 0 || o.rhs_block < 0 || o.rhs_block > 64) return SF_ERR_ARG;
   if (o.coarsen < 0 || o.coarsen > 2) return SF_ERR_ARG;
   if (o.kind == SF_TRSV_SPMV && !A) return SF_ERR_ARG;
   const auto t0 = std::chrono::steady_clock::now();
-  sf_status st = sf::check_lower(L);
+  sf_status st = o.kind == SF_ILU0_TRSV ? sf::check_square_diag(L) : sf::check_lower(L);
   if (st != SF_OK) return st;
   if (o.kind == SF_TRSV_SPMV) {
     st = sf::check_general(A, L->nrows);
@@ -804,9 +806,72 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   la.depth = s->depth;
   r = next_epoch(s, st, la.ts.ls);
   if (r != SF_OK) return r;
-  const int g = std::min(s->lanes_trsv, 32);
   grid = cus * std::min(occupancy_trsv_levelset(0), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
   return hip_status(launch_trsv_levelset(la, 0, grid, st));
+}
+
+// Fused SpILU0 -> unit-lower SpTRSV (k_ilu.hip); unfused: level-set
+// factorisation, then a level-set solve reading the factor.
+static sf_status ilu0_common(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val, const void* X,
+                             void* Y, int32_t* d_info, bool fused, void* stream) {
+  if (!s || s->kind != SF_ILU0_TRSV) return SF_ERR_ARG;
+  if (dtype != SF_F64) return SF_ERR_UNSUPPORTED;
+  const bool solve = X != nullptr;
+  if (s->n > 0 && (!A_val || !LU_val)) return SF_ERR_ARG;
+  if (solve && (!Y || X == Y)) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (s->max_offdiag + 1 > s->lanes_trsv) return SF_ERR_UNSUPPORTED;  // one lane per stored entry
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sf_status r = upload(s, st);
+  if (r != SF_OK) return r;
+  const DeviceBuffers& d = s->dev;
+  Ic0Args a{};
+  a.n = int32_t(s->n);
+  a.Lrp = d.Lrp;
+  a.Lci = d.Lci;
+  a.Aval = static_cast<const double*>(A_val);
+  a.Lval = static_cast<double*>(LU_val);
+  a.B = static_cast<const double*>(X);
+  a.X = static_cast<double*>(Y);
+  a.pair_ptr = d.pair_ptr;
+  a.pair_u = d.pair_u;
+  a.pair_q = d.pair_q;
+  a.dpos = d.dpos;
+  a.order = d.order;
+  a.item_ptr = d.item_ptr;
+  a.d_info = d_info;
+  a.factor = 1;
+  const int cus = std::max(1, device_cus());
+  Timer tm(s, st);
+  if (fused) {
+    r = next_epoch(s, st, a.ls);
+    if (r != SF_OK) return r;
+    a.item_list = nullptr;
+    a.n_work = int32_t(s->item_ptr.size() - 1);
+    a.solve = solve ? 1 : 0;
+    const int grid = persistent_grid(s, occupancy_ilu0(s->lanes_trsv, 0));
+    // every factor value and y_i is its own readiness flag
+    SF_HIP(launch_fill_pending(LU_val, size_t(s->L.nnz()), 0, st));
+    if (solve) SF_HIP(launch_fill_pending(Y, size_t(s->n), 0, st));
+    return hip_status(launch_ilu0_fused(a, s->lanes_trsv, grid, st));
+  }
+  a.item_list = d.lvl_items;
+  a.n_work = int32_t(s->lvl_items.size());
+  a.lvl_item_ptr = d.lvl_item_ptr;
+  a.depth = s->depth;
+  const int grid =
+      cus * std::min(occupancy_ilu0(s->lanes_trsv, 1), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  a.solve = 0;
+  SF_HIP(launch_ilu0_levelset(a, s->lanes_trsv, grid, st));
+  if (!solve) return SF_OK;
+  r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  a.factor = 0;
+  a.solve = 1;
+  a.d_info = nullptr;
+  return hip_status(launch_ilu0_levelset(a, s->lanes_trsv, grid, st));
 }
 
 sf_status sf_exec_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
@@ -821,6 +886,16 @@ sf_status sf_exec_unfused_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_
                                    const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
                                    int32_t* d_info, void* stream) {
   return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, false, stream);
+}
+
+sf_status sf_exec_ilu0_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val, const void* X,
+                            void* Y, int32_t* d_info, void* stream) {
+  return ilu0_common(s, dtype, A_val, LU_val, X, Y, d_info, !(s && s->no_fusion), stream);
+}
+
+sf_status sf_exec_unfused_ilu0_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val,
+                                    const void* X, void* Y, int32_t* d_info, void* stream) {
+  return ilu0_common(s, dtype, A_val, LU_val, X, Y, d_info, false, stream);
 }
 
 size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs) {
@@ -1021,10 +1096,10 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   if (!s || !key) return SF_ERR_ARG;
   const std::string k(key);
   if (k == "lanes_trsv") {
-    const int lo = s->kind == SF_IC0_TRSV ? 4 : 2;
-    if (!pow2_in(int(v), lo, s->kind == SF_IC0_TRSV ? 64 : 32)) return SF_ERR_ARG;
+    const bool factor_kind = s->kind == SF_IC0_TRSV || s->kind == SF_ILU0_TRSV;
+    if (!pow2_in(int(v), factor_kind ? 4 : 2, factor_kind ? 64 : 32)) return SF_ERR_ARG;
     s->lanes_trsv = int32_t(v);
-    if (s->kind == SF_IC0_TRSV) return recut(s);  // SpIC0 items hold one batch of 64 / lanes rows
+    if (factor_kind) return recut(s);  // factorisation items hold one batch of 64 / lanes rows
   } else if (k == "lanes_spmv") {
     if (!pow2_in(int(v), 4, 32)) return SF_ERR_ARG;
     s->lanes_spmv = int32_t(v);
@@ -1087,6 +1162,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "spmv_delay") *v = s->spmv_delay;
   else if (k == "coarsen") *v = s->coarsen;
   else if (k == "coarsened") *v = s->chunked ? 1 : 0;
+  else if (k == "pairs") *v = int64_t(s->pair_u.size());  // SpIC0 / SpILU0 intersection pairs (read only)
   else if (k == "back_coarsened") *v = s->bchunked ? 1 : 0;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "timing") *v = s->timing;

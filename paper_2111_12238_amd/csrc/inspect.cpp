@@ -47,6 +47,21 @@ sf_status check_lower(const sf_csr_pattern* L) {
   return SF_OK;
 }
 
+// SpILU0 input: a square CSR pattern with sorted columns and a stored
+// diagonal in every row.
+sf_status check_square_diag(const sf_csr_pattern* A) {
+  if (!A || A->nrows < 0) return SF_ERR_ARG;
+  if (A->nrows != A->ncols) return SF_ERR_SHAPE;
+  const sf_status st = check_general(A, A->ncols);
+  if (st != SF_OK) return st;
+  for (int32_t i = 0; i < A->nrows; ++i) {
+    const int32_t* b = A->colind + A->rowptr[i];
+    const int32_t* e = A->colind + A->rowptr[i + 1];
+    if (!std::binary_search(b, e, i)) return SF_ERR_ZERO_DIAG;
+  }
+  return SF_OK;
+}
+
 sf_status check_general(const sf_csr_pattern* A, int32_t ncols) {
   if (!A || A->nrows < 0 || !A->rowptr) return SF_ERR_ARG;
   if (A->ncols != ncols) return SF_ERR_SHAPE;
@@ -469,7 +484,8 @@ void cut_items(sf_schedule_s* s) {
     cut_runs(s->order, key, cost, std::min(s->rows_per_item, per_batch), s->max_item_nnz, s->item_ptr);
     s->trsv_items.clear();
     for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) s->trsv_items.push_back(int32_t(t));
-    position_ranges(s, s->order, s->qrng);  // for the level-set solve of the unfused baseline
+    if (s->kind == SF_IC0_TRSV) position_ranges(s, s->order, s->qrng);  // the unfused baseline's level-set solve
+    else s->qrng.clear();
   }
   // Level-set baseline: the SpTRSV items grouped by level.  Items are
   // level-pure, and in claim order the levels ascend.
@@ -535,6 +551,37 @@ static void build_pairs(sf_schedule_s* s) {
   }
 }
 
+// SpILU0 intersection lists, one list per stored entry (i, j) of A: pairs
+// (t << 16 | u, q) for every stored k = column of entry u of row i with
+// k < min(i, j) and (k, j) stored at position q of row k (u_kj).  Lists of
+// a row's entries are contiguous, in entry order.
+static void build_pairs_ilu(sf_schedule_s* s) {
+  const Pattern& A = s->L;
+  const int64_t nnz = A.nnz();
+  s->pair_ptr.assign(size_t(nnz) + 1, 0);
+  s->pair_u.clear();
+  s->pair_q.clear();
+  for (int32_t i = 0; i < A.nrows; ++i) {
+    const int32_t r0 = A.rp[i], r1 = A.rp[i + 1];
+    for (int32_t p = r0; p < r1; ++p) {
+      const int32_t j = A.ci[p];
+      const int32_t lim = std::min(i, j);
+      for (int32_t pk = r0; pk < r1 && A.ci[pk] < lim; ++pk) {
+        const int32_t k = A.ci[pk];
+        // (k, j) in row k: binary search over its sorted columns
+        const int32_t* b = A.ci.data() + A.rp[k];
+        const int32_t* e = A.ci.data() + A.rp[k + 1];
+        const int32_t* f = std::lower_bound(b, e, j);
+        if (f != e && *f == j) {
+          s->pair_u.push_back(((p - r0) << 16) | (pk - r0));
+          s->pair_q.push_back(int32_t(f - A.ci.data()));
+        }
+      }
+      s->pair_ptr[size_t(p) + 1] = int32_t(s->pair_u.size());
+    }
+  }
+}
+
 sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_csr_pattern* Ap,
                          const sf_inspect_opts& o) {
   s->kind = o.kind;
@@ -549,12 +596,23 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
   }
   const int64_t m = s->m;
 
-  // Levels (wavefront numbers) of the SpTRSV DAG.
+  // SpILU0: the position of each row's diagonal (the pattern is the whole
+  // of A; the entries left of it are the row's dependences).
+  if (s->kind == SF_ILU0_TRSV) {
+    s->dpos.assign(size_t(n), 0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1]; ++p)
+        if (s->L.ci[p] == i) s->dpos[size_t(i)] = p;
+  }
+  // end of row i's dependences: its diagonal
+  auto dep_end = [&](int64_t i) { return s->kind == SF_ILU0_TRSV ? s->dpos[size_t(i)] : s->L.rp[i + 1] - 1; };
+
+  // Levels (wavefront numbers) of the SpTRSV (SpIC0, SpILU0) DAG.
   s->level.assign(size_t(n), 0);
   int32_t depth = 0;
   for (int64_t i = 0; i < n; ++i) {
     int32_t lv = 0;
-    for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p) lv = std::max(lv, s->level[s->L.ci[p]] + 1);
+    for (int32_t p = s->L.rp[i]; p < dep_end(i); ++p) lv = std::max(lv, s->level[s->L.ci[p]] + 1);
     s->level[i] = lv;
     depth = std::max(depth, lv + 1);
   }
@@ -585,8 +643,17 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
     s->joint_depth = depth;
     counting_order(s->level, std::max(depth, 1), s->order);
     const double nl = double(s->L.nnz());
-    s->reuse = nl > 0 ? 2.0 * nl / std::max(nl, nl + 2.0 * double(n)) : 0.0;
-    build_pairs(s);
+    if (s->kind == SF_ILU0_TRSV) {
+      // Table 2, combination 6: 2 size_A / max(size_A, size_L + 2n), size_L the
+      // stored entries left of the diagonal
+      double sl = 0.0;
+      for (int64_t i = 0; i < n; ++i) sl += double(s->dpos[size_t(i)] - s->L.rp[i]);
+      s->reuse = nl > 0 ? 2.0 * nl / std::max(nl, sl + 2.0 * double(n)) : 0.0;
+      build_pairs_ilu(s);
+    } else {
+      s->reuse = nl > 0 ? 2.0 * nl / std::max(nl, nl + 2.0 * double(n)) : 0.0;
+      build_pairs(s);
+    }
   }
 
   if (o.want_backward && s->kind == SF_TRSV_SPMV) {
@@ -616,8 +683,8 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_cs
   const double mean_a = m ? double(s->A.nnz()) / double(m) : 1.0;
   s->lanes_trsv = o.lanes_per_row > 0 ? o.lanes_per_row : pick(mean_l);
   s->lanes_spmv = std::max(4, pick(mean_a));  // SpMV kernels exist for 4..32 lanes
-  if (s->kind == SF_IC0_TRSV) {
-    // one lane per stored entry of an SpIC0 row
+  if (s->kind == SF_IC0_TRSV || s->kind == SF_ILU0_TRSV) {
+    // one lane per stored entry of an SpIC0 / SpILU0 row
     int32_t maxlen = 1;
     for (int64_t i = 0; i < n; ++i) maxlen = std::max(maxlen, s->L.rp[i + 1] - s->L.rp[i]);
     int g = 4;
@@ -710,7 +777,28 @@ static int validate_back_plan(const sf_schedule_s* s, const std::vector<int32_t>
   return 0;
 }
 
+// SpILU0 plans: each row once, and every dependence k -> i (a stored (i, k),
+// k < i) goes to a later item.
+static int validate_ilu_plan(const sf_schedule_s* s) {
+  const int64_t n = s->n;
+  std::vector<int32_t> item(size_t(n), -1);
+  if (s->item_ptr.empty() || s->item_ptr[0] != 0 || s->item_ptr.back() != n) return 21;
+  for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) {
+    if (s->item_ptr[t + 1] <= s->item_ptr[t]) return 22;
+    for (int32_t q = s->item_ptr[t]; q < s->item_ptr[t + 1]; ++q) {
+      const int32_t u = s->order[q];
+      if (u < 0 || u >= n || item[u] >= 0) return 23;
+      item[u] = int32_t(t);
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t p = s->L.rp[i]; p < s->dpos[size_t(i)]; ++p)
+      if (!(item[s->L.ci[p]] < item[i])) return 24;
+  return 0;
+}
+
 int validate_forward(const sf_schedule_s* s) {
+  if (s->kind == SF_ILU0_TRSV) return validate_ilu_plan(s);
   int r = validate_plan(s, s->order, s->item_ptr, nullptr);
   if (r == 0 && s->chunked) r = validate_plan(s, s->corder, s->citem_ptr, &s->clloc);
   if (r == 0 && s->has_back) r = validate_back_plan(s, s->border, s->bitem_ptr, nullptr);

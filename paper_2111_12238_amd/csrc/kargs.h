@@ -68,6 +68,7 @@ struct Ic0Args {
   const double* B;
   double* X;
   const int32_t *pair_ptr, *pair_u, *pair_q;
+  const int32_t* dpos;     // SpILU0: diagonal position of each row (nullptr for SpIC0)
   const int32_t *order, *item_ptr, *item_list;
   int32_t n_work;
   const int32_t* lvl_item_ptr;  // level-set variant
@@ -147,6 +148,9 @@ hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st);
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);
 hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st);
 hipError_t launch_bwd(const BwdArgs& a, int dtype, int g, int grid, hipStream_t st);
+hipError_t launch_ilu0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);
+hipError_t launch_ilu0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st);
+int occupancy_ilu0(int g, int levelset);
 hipError_t launch_precond(const PrecondArgs& a, int dtype, int grid, hipStream_t st);
 int occupancy_precond(int dtype);
 hipError_t launch_residual(const ResArgs& a, hipStream_t st);

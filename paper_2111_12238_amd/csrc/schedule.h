@@ -57,6 +57,7 @@ struct DeviceBuffers {
   uint8_t *bclloc = nullptr, *bceloc = nullptr;
   // SpIC0 intersection lists
   int32_t *pair_ptr = nullptr, *pair_u = nullptr, *pair_q = nullptr;
+  int32_t* dpos = nullptr;          // SpILU0: diagonal position of each row
   // mutable state
   int32_t* state = nullptr;
   void* xi = nullptr;           // interleaved right-hand-side workspace
@@ -128,6 +129,9 @@ struct sf_schedule_s {
   // index inside row i of a column k in both rows with k < j, q = position
   // of L_jk.  The lists of a row's entries are contiguous, in entry order.
   std::vector<int32_t> pair_ptr, pair_u, pair_q;
+  // SF_ILU0_TRSV: the pattern of A is held in L; dpos[i] is the position of
+  // row i's diagonal.  Pairs then follow build_pairs_ilu (inspect.cpp).
+  std::vector<int32_t> dpos;
 
   // Executor parameters.
   int32_t lanes_trsv = 4, lanes_spmv = 8, rhs_block = 0, waves_per_cu = 8;
@@ -152,6 +156,7 @@ namespace sf {
 // Host inspector entry points (inspect.cpp).
 sf_status check_lower(const sf_csr_pattern* L);
 sf_status check_general(const sf_csr_pattern* A, int32_t ncols);
+sf_status check_square_diag(const sf_csr_pattern* A);
 sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* L, const sf_csr_pattern* A,
                          const sf_inspect_opts& o);
 // Re-cut the work items after a change of rows_per_item / max_item_nnz.

@@ -114,6 +114,34 @@ def laplacian_1d(n, diag=2.0) -> CSR:
     return _stencil((n,), [(0,), (-1,), (1,)], diag)
 
 
+def convdiff_3d7(nx, ny, nz, diag=6.0, eps=0.4) -> CSR:
+    """Nonsymmetric 3D 7-point convection-diffusion operator, natural
+    ordering: off-diagonals -1 - eps toward lower coordinates (upwind) and
+    -1 + eps toward higher ones, constant diagonal (input of SpILU0)."""
+    a = laplacian_3d7(nx, ny, nz, diag)
+    rows = np.repeat(np.arange(a.nrows), np.diff(a.rowptr))
+    v = a.val.copy()
+    v[a.col < rows] = -1.0 - eps
+    v[a.col > rows] = -1.0 + eps
+    return CSR(a.rowptr, a.col, v, a.nrows, a.ncols)
+
+
+def random_nonsym(n, seed=0, lo=2, hi=12) -> CSR:
+    """Random sparse nonsymmetric, diagonally dominant matrix: lo..hi
+    off-diagonals per row at uniform columns (no self-loops, duplicates
+    merged), values U(-1, 1), diagonal 1 + the row's absolute sum."""
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(lo, hi + 1, size=n)
+    rows = np.repeat(np.arange(n, dtype=np.int64), counts)
+    c = rng.integers(0, n - 1, size=rows.size, dtype=np.int64)
+    c += (c >= rows)
+    m = sp.csr_matrix((rng.uniform(-1.0, 1.0, size=rows.size), (rows, c)), shape=(n, n))
+    m.sum_duplicates()
+    m = (m + sp.diags(np.abs(m).sum(axis=1).A1 + 1.0)).tocsr()
+    m.sort_indices()
+    return from_scipy(m)
+
+
 def random_spd(n, seed=0, lo=2, hi=30) -> CSR:
     """Random sparse SPD matrix (recipe in the module docstring)."""
     rng = np.random.default_rng(seed)
@@ -207,6 +235,15 @@ def workload(name: str):
         a = permute_sym(a0, permutation(a0.nrows, seed=3))
     elif name == "lap2d9_2048":
         a = laplacian_2d9(2048, 2048, 8.0)
+    elif name in ("convdiff3d7_64", "convdiff3d7_64_perm", "randnonsym_1m"):
+        # SpILU0 inputs: the whole nonsymmetric matrix is the pattern
+        if name == "randnonsym_1m":
+            a = random_nonsym(1_000_000, seed=0)
+        else:
+            a = convdiff_3d7(64, 64, 64, 6.0, 0.4)
+            if name.endswith("_perm"):
+                a = permute_sym(a, permutation(a.nrows, seed=3))
+        return a, a
     else:
         raise KeyError(name)
     return lower(a), a

@@ -329,3 +329,57 @@ def test_inspector_time_reported():
     L, A = synth.workload("lap2d5_64")
     s = sfm.Schedule(L, A, want_backward=True)
     assert 0.0 < s.info().inspect_seconds < 5.0
+
+
+def test_ilu0_schedule(orc):
+    """SpILU0 schedules: levels of the dependences left of the diagonal (the
+    oracle's levels of the lower triangle), every dependence to a later item,
+    one batch per item, and intersection lists equal to a brute-force count
+    of the triples (k, j) with k < min(i, j) stored in row i and (k, j)
+    stored in row k."""
+    for a in (synth.convdiff_3d7(6, 5, 4), synth.random_nonsym(400, seed=3)):
+        s = sfm.Schedule(a, None, sfm.SF_ILU0_TRSV, validate=True)
+        level, order, ip = s.export()
+        low = synth.lower(a)
+        lv, depth = orc.levels(low.rowptr, low.col)
+        assert np.array_equal(level, lv) and s.info().depth == depth
+        n = a.nrows
+        rows = order[0::2]
+        assert np.array_equal(order[1::2], rows + n)  # factor row i, then solve row i
+        assert np.array_equal(np.sort(rows), np.arange(n))
+        item = np.empty(n, int)
+        for t in range(len(ip) - 1):
+            item[order[ip[t]:ip[t + 1]:2]] = t
+        r = np.repeat(np.arange(n), np.diff(a.rowptr))
+        left = a.col < r
+        assert np.all(item[a.col[left]] < item[r[left]])
+        dense = a.to_scipy().toarray() != 0
+        want = sum(int(np.sum(dense[i, :min(i, j)] & dense[:min(i, j), j]))
+                   for i in range(n) for j in np.nonzero(dense[i])[0])
+        st = s.info()
+        assert st.lanes_per_row >= np.diff(a.rowptr).max()
+        assert want == _ilu_pair_count(s)
+
+
+def _ilu_pair_count(s):
+    # size of the schedule's intersection lists (read-only parameter)
+    import ctypes
+    lib = sfm._lib()
+    v = ctypes.c_int64(0)
+    assert lib.sf_get_param(s.handle, b"pairs", ctypes.byref(v)) == 0
+    return int(v.value)
+
+
+def test_ilu0_structural_errors():
+    a = synth.convdiff_3d7(4, 4, 3)
+    m = a.to_scipy().tolil()
+    m[5, 5] = 0
+    m = m.tocsr()
+    m.eliminate_zeros()
+    with pytest.raises(sfm.SparseFusionError) as e:
+        sfm.Schedule(synth.from_scipy(m), None, sfm.SF_ILU0_TRSV)
+    assert e.value.name == "SF_ERR_ZERO_DIAG"
+    r = synth.from_scipy(sp.random(30, 40, density=0.2, random_state=1, format="csr"))
+    with pytest.raises(sfm.SparseFusionError) as e:
+        sfm.Schedule(r, None, sfm.SF_ILU0_TRSV)
+    assert e.value.name == "SF_ERR_SHAPE"
