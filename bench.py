@@ -247,7 +247,8 @@ def main():
 
 
 def run_extras(args, sfm, synth, torch, dev, stream):
-    """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted), the batched
+    """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted), SpILU0 ->
+    SpTRSV (nonsymmetric 7-point 64^3, natural and permuted), the batched
     refinement, kernel combinations 2 and 1 and the preconditioner apply on
     the headline matrices, and forward + backward (7-point 96^3, FP64 and
     FP32): fused vs unfused."""
@@ -282,6 +283,23 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                                    "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
                                    "inspect_s": round(s.info().inspect_seconds, 3)}
         log("ic0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
+    for name in ("convdiff3d7_64", "convdiff3d7_64_perm"):
+        a, _ = synth.workload(name)
+        s = sfm.Schedule(a, None, sfm.SF_ILU0_TRSV)
+        Av = torch.as_tensor(a.val, device=dev)
+        xv = torch.as_tensor(synth.vec_normal(a.nrows, seed=1), device=dev)
+        LU = torch.empty_like(Av)
+        Yv = torch.empty_like(xv)
+        f = lambda: sfm.ilu0_trsv(s, Av, xv, LU_val=LU, Y=Yv, check_info=False)
+        u = lambda: sfm.ilu0_trsv(s, Av, xv, LU_val=LU, Y=Yv, check_info=False, unfused=True)
+        tf, tu = time_it(f, reps), time_it(u, reps)
+        sfm.sync_status(s)
+        nb = a.nnz * 12 + (a.nrows + 1) * 4 + a.nnz * 8 + 16 * a.nrows  # read A, write L and U, x in, y out
+        out["ilu0_trsv_" + name] = {"depth": s.info().depth, "fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
+                                    "speedup_vs_unfused": round(tu / tf, 3),
+                                    "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
+                                    "inspect_s": round(s.info().inspect_seconds, 3)}
+        log("ilu0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
     out.update(run_batched(args, sfm, synth, torch, dev, time_it))
     # kernel combinations 2 (SpMV -> SpTRSV) and 1 (SpTRSV -> SpTRSV)
     for name in ("lap3d7_128", "randspd_1m"):
