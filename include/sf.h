@@ -92,8 +92,9 @@ typedef struct {
   int32_t max_item_nnz;   /* cost budget of one work item, summing the paper's vertex
                              cost c(v) (Sec. 3.1) = max(1, off-diagonals of the row);
                              default 512 */
-  int32_t rhs_block;      /* right-hand sides walked together per DAG pass (default: autotuned
-                             / all) */
+  int32_t rhs_block;      /* right-hand sides walked together per DAG pass: 0 (the default:
+                             the smallest power of two >= nrhs, at most 64) or a power of
+                             two 2..64 */
   int32_t lanes_per_row;  /* lanes of a 64-wide wavefront per SpIC0 row, one per stored
                              entry (4..64, a power of two; default: the longest row) */
   int32_t want_backward;  /* 1: also build the transposed (upper-solve) schedule for sf_backward */
@@ -214,6 +215,11 @@ sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level,
  *   X:      device n x nrhs output, ldx >= n.  Must not alias B.
  *   Y:      device m x nrhs output, ldy >= m; NULL runs the solve only.
  *   nrhs:   1..64.
+ * Several right-hand sides run in blocks of rhs_block columns: B is packed
+ * into a library-owned device workspace (kept with the schedule, grown on
+ * demand, freed with it) in which each row of a block holds its columns
+ * contiguously, the solve and the product run there, and X and Y are
+ * unpacked at the end; only rows < n of X and < m of Y are written.
  * Errors: SF_ERR_ARG, SF_ERR_SHAPE, SF_ERR_HIP, SF_ERR_OOM.
  */
 sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
@@ -385,8 +391,9 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "lanes_spmv"                kept for compatibility: SpTRSV and SpMV rows
  *                               deal their entries over all 64 lanes, so
  *                               lanes per row no longer select a kernel;
- *   "rhs_block"                 right-hand sides per DAG pass (1..64);
- *   "waves_per_cu"              persistent-grid residency target (1..32);
+ *   "rhs_block"                 right-hand sides per DAG pass (0 = by nrhs,
+ *                               else a power of two 2..64);
+ *   "waves_per_cu"              persistent-grid residency target (4..32);
  *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT;
  *   "claim_streams"             work-claim counters (1..32);
  *   "rows_per_item", "max_item_nnz"  re-cut the work items (rows <= 64);

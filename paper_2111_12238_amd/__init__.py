@@ -299,8 +299,10 @@ def _vec_ptr(t, rows, name):
             raise ValueError("%s: expected a contiguous vector of length %d" % (name, rows))
         return t.data_ptr(), max(rows, 1), 1
     if t.dim() == 2 and t.shape[0] == rows and (t.stride(0) == 1 or t.shape[1] == 1):
+        if t.shape[1] > 1 and t.stride(1) < rows:
+            raise ValueError("%s: columns overlap (stride %d < %d rows)" % (name, t.stride(1), rows))
         ld = t.stride(1) if t.shape[1] > 1 else max(rows, 1)
-        return t.data_ptr(), max(ld, rows, 1), t.shape[1]
+        return t.data_ptr(), max(ld, 1), t.shape[1]
     raise ValueError("%s: expected shape (%d,) or column-major (%d, k)" % (name, rows, rows))
 
 

@@ -138,15 +138,36 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   return SF_OK;
 }
 
-sf_status ensure_xi(sf_schedule_s* s, size_t bytes, hipStream_t st) {
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Library-owned workspace of the multi-RHS executors, all in the
+// interleaved block layout (k_layout.hip): the solution xi (its own
+// readiness flags; the refinement reads it as the correction), the packed
+// right-hand sides bi and the packed SpMV result yi.
+struct MultiWs {
+  void* xi;
+  void* bi;
+  void* yi;
+};
+
+sf_status multi_ws(sf_schedule_s* s, int kb, int nrhs, size_t es, hipStream_t st, MultiWs& w) {
   DeviceBuffers& d = s->dev;
-  if (d.xi_bytes >= bytes) return SF_OK;
-  SF_HIP(hipStreamSynchronize(st));
-  if (d.xi) SF_HIP(hipFree(d.xi));
-  d.xi = nullptr;
-  d.xi_bytes = 0;
-  SF_HIP(hipMalloc(&d.xi, bytes));
-  d.xi_bytes = bytes;
+  const size_t cols = size_t((nrhs + kb - 1) / kb) * size_t(kb);
+  const size_t bx = align256(std::max<size_t>(size_t(s->n) * cols * es, 1));
+  const size_t by = align256(std::max<size_t>(size_t(s->m) * cols * es, 1));
+  const size_t bytes = 2 * bx + by;
+  if (d.xi_bytes < bytes) {
+    SF_HIP(hipStreamSynchronize(st));
+    if (d.xi) SF_HIP(hipFree(d.xi));
+    d.xi = nullptr;
+    d.xi_bytes = 0;
+    SF_HIP(hipMalloc(&d.xi, bytes));
+    d.xi_bytes = bytes;
+  }
+  char* b = static_cast<char*>(d.xi);
+  w.xi = b;
+  w.bi = b + bx;
+  w.yi = b + 2 * bx;
   return SF_OK;
 }
 
@@ -206,6 +227,12 @@ int default_kb(int nrhs) {
   return kb;
 }
 
+// Right-hand sides per block of the multi-RHS solve (1 for a single one).
+int solve_kb(const sf_schedule_s* s, int nrhs) {
+  if (nrhs == 1) return 1;
+  return s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
+}
+
 TsArgs ts_args(sf_schedule_s* s, const void* Lv, const void* Av, const void* B, int ldb, int nrhs,
                void* X, int ldx, void* Y, int ldy) {
   const DeviceBuffers& d = s->dev;
@@ -258,6 +285,27 @@ sf_status ensure_units(sf_schedule_s* s, int rpb, hipStream_t st) {
   return SF_OK;
 }
 
+// Fused multi-RHS executor on interleaved data: bi (n rows) -> xi, whose
+// every value must hold the pending pattern, and yi (m rows; nullptr = no
+// SpMV), nblk = ceil(nrhs / kb) blocks of kb columns.
+sf_status exec_multi_core(sf_schedule_s* s, int dtype, const void* Lv, const void* Av, const void* bi, void* xi,
+                          void* yi, int nrhs, int kb, hipStream_t st) {
+  TsArgs a = ts_args(s, Lv, Av, bi, int32_t(s->n), nrhs, nullptr, int32_t(s->n), yi, int32_t(s->m));
+  sf_status r = ensure_units(s, std::max(1, 64 / kb), st);
+  if (r != SF_OK) return r;
+  a.item_ptr = s->dev.unit_ptr;
+  a.item_list = yi ? nullptr : s->dev.unit_trsv;
+  a.n_work = yi ? s->dev.n_units : s->dev.n_unit_trsv;
+  if (a.n_work == 0) return SF_OK;
+  r = next_epoch(s, st, a.ls);
+  if (r != SF_OK) return r;
+  a.kb = kb;
+  a.nblk = (nrhs + kb - 1) / kb;
+  a.xi = xi;
+  const int grid = persistent_grid(s, occupancy_ts_multi(dtype, kb));
+  return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
+}
+
 sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
                         int ldb, int nrhs, void* X, int ldx, void* Y, int ldy, hipStream_t st) {
   const int dtype = dt == SF_F64 ? 0 : 1;
@@ -286,26 +334,19 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     SF_HIP(launch_fill_pending(X, size_t(s->n), dtype, st));
     return hip_status(launch_ts_fused(a, dtype, grid, st));
   }
-  const int kb = s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
-  const int nblk = (nrhs + kb - 1) / kb;
-  const size_t xi_count = size_t(nblk) * size_t(s->n) * size_t(kb);
-  sf_status r = ensure_xi(s, xi_count * es, st);
+  const int kb = solve_kb(s, nrhs);
+  MultiWs w{};
+  sf_status r = multi_ws(s, kb, nrhs, es, st, w);
+  if (r == SF_OK) r = ensure_units(s, std::max(1, 64 / kb), st);  // before the timed region
   if (r != SF_OK) return r;
-  r = ensure_units(s, std::max(1, 64 / kb), st);
-  if (r != SF_OK) return r;
-  a.item_ptr = s->dev.unit_ptr;
-  a.item_list = Y ? nullptr : s->dev.unit_trsv;
-  a.n_work = Y ? s->dev.n_units : s->dev.n_unit_trsv;
-  if (a.n_work == 0) return SF_OK;
-  r = next_epoch(s, st, a.ls);
-  if (r != SF_OK) return r;
-  a.kb = kb;
-  a.nblk = nblk;
-  a.xi = s->dev.xi;
-  const int grid = persistent_grid(s, occupancy_ts_multi(dtype, kb));
   Timer tm(s, st);
-  SF_HIP(launch_fill_pending(s->dev.xi, xi_count, dtype, st));
-  return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
+  // B -> interleaved blocks, the solution buffer filled with the pending pattern
+  SF_HIP(launch_pack(B, dtype, ldb, int32_t(s->n), nrhs, w.bi, dtype, w.xi, kb, st));
+  r = exec_multi_core(s, dtype, Lv, Av, w.bi, w.xi, Y ? w.yi : nullptr, nrhs, kb, st);
+  if (r != SF_OK) return r;
+  SF_HIP(launch_unpack(w.xi, dtype, int32_t(s->n), nrhs, X, ldx, kb, st));
+  if (Y) SF_HIP(launch_unpack(w.yi, dtype, int32_t(s->m), nrhs, Y, ldy, kb, st));
+  return SF_OK;
 }
 
 sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
@@ -318,22 +359,25 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
   la.ts.n_work = int32_t(s->lvl_items.size());
   la.lvl_item_ptr = s->dev.lvl_item_ptr;
   la.depth = s->depth;
-  int kb = 1, nblk = 1;
+  // several right-hand sides: the same interleaved blocks as the fused path
+  const int kb = solve_kb(s, nrhs);
+  MultiWs w{};
   if (nrhs > 1) {
-    kb = 8;  // the level-set multi-RHS path is compiled for blocks of 8
-    nblk = (nrhs + kb - 1) / kb;
-    sf_status r = ensure_xi(s, size_t(nblk) * size_t(s->n) * size_t(kb) * es, st);
+    sf_status r = multi_ws(s, kb, nrhs, es, st, w);
     if (r != SF_OK) return r;
-    la.ts.xi = s->dev.xi;
+    la.ts.B = w.bi;
+    la.ts.X = nullptr;
+    la.ts.xi = w.xi;
   }
   la.ts.kb = kb;
-  la.ts.nblk = nblk;
+  la.ts.nblk = (nrhs + kb - 1) / kb;
   sf_status r = next_epoch(s, st, la.ts.ls);
   if (r != SF_OK) return r;
   Timer tm(s, st);
+  if (nrhs > 1) SF_HIP(launch_pack(B, dtype, ldb, int32_t(s->n), nrhs, w.bi, dtype, nullptr, kb, st));
   if (s->n > 0 && s->depth > 0) {
     const int cus = std::max(1, device_cus());
-    const int occ = occupancy_trsv_levelset(dtype);
+    const int occ = occupancy_trsv_levelset(dtype, kb);
     int grid = cus * std::min(occ, std::max(1, s->waves_per_cu * 64 / kBlockThreads));
     SF_HIP(launch_trsv_levelset(la, dtype, grid, st));
   }
@@ -345,15 +389,19 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
   } else if (Y && s->m > 0) {
     SpmvArgs sa{};
     sa.m = int32_t(s->m);
-    sa.nrhs = nrhs;
+    sa.n = int32_t(s->n);
+    sa.kb = kb;
+    sa.nblk = la.ts.nblk;
     sa.Arp = s->dev.Arp;
     sa.Aci = s->dev.Aci;
     sa.Av = Av;
-    sa.X = X;
-    sa.ldx = ldx;
-    sa.Y = Y;
-    sa.ldy = ldy;
+    sa.X = w.xi;
+    sa.Y = w.yi;
     SF_HIP(launch_spmv(sa, dtype, st));
+  }
+  if (nrhs > 1) {
+    SF_HIP(launch_unpack(w.xi, dtype, int32_t(s->n), nrhs, X, ldx, kb, st));
+    if (Y) SF_HIP(launch_unpack(w.yi, dtype, int32_t(s->m), nrhs, Y, ldy, kb, st));
   }
   return SF_OK;
 }
@@ -576,7 +624,8 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
   if (opts) o = *opts;
   if (o.kind != SF_TRSV_SPMV && o.kind != SF_IC0_TRSV && o.kind != SF_ILU0_TRSV) return SF_ERR_ARG;
   if (o.lanes_per_row != 0 && !pow2_in(o.lanes_per_row, 2, 64)) return SF_ERR_ARG;
-  if (o.rows_per_item < 0 || o.max_item_nnz < 0 || o.rhs_block < 0 || o.rhs_block > 64) return SF_ERR_ARG;
+  if (o.rows_per_item < 0 || o.max_item_nnz < 0) return SF_ERR_ARG;
+  if (o.rhs_block != 0 && !pow2_in(o.rhs_block, 2, 64)) return SF_ERR_ARG;
   if (o.coarsen < 0 || o.coarsen > 2) return SF_ERR_ARG;
   if (o.kind == SF_TRSV_SPMV && !A) return SF_ERR_ARG;
   const auto t0 = std::chrono::steady_clock::now();
@@ -806,7 +855,7 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   la.depth = s->depth;
   r = next_epoch(s, st, la.ts.ls);
   if (r != SF_OK) return r;
-  grid = cus * std::min(occupancy_trsv_levelset(0), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  grid = cus * std::min(occupancy_trsv_levelset(0, 1), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
   return hip_status(launch_trsv_levelset(la, 0, grid, st));
 }
 
@@ -951,21 +1000,44 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   return hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st));
 }
 
-// Right-hand sides per block of the multi-RHS solve (1 for a single one).
-int solve_kb(const sf_schedule_s* s, int nrhs) {
-  if (nrhs == 1) return 1;
-  return s->rhs_block > 0 ? std::min(s->rhs_block, 64) : default_kb(nrhs);
+// Refinement workspace, in the interleaved block layout of the solve (a
+// plain vector per array for a single right-hand side):
+//   r32 | d32 | x ping | x pong | b64 | y64 | max-abs accumulators
+// r32 is the FP32 right-hand side of each solve, d32 the single-RHS
+// correction (several right-hand sides keep it in the solve's workspace),
+// b64 the packed FP64 right-hand sides and y64 the packed product
+// (the last two only with several right-hand sides).
+struct RefineWs {
+  float *r32, *d32;
+  double *xa, *xb, *b64, *y64;
+  unsigned long long* mx;
+  size_t bytes;
+};
+
+RefineWs refine_layout(const sf_schedule_s* s, int nrhs, void* base) {
+  const int kb = solve_kb(s, nrhs);
+  const size_t cols = size_t((nrhs + kb - 1) / kb) * size_t(kb);
+  const size_t n = size_t(std::max<int64_t>(s->n, 1)), m = size_t(std::max<int64_t>(s->m, 1));
+  const bool multi = kb > 1;
+  const size_t sizes[7] = {align256(n * cols * 4), align256(multi ? 256 : n * 4), align256(n * cols * 8),
+                           align256(n * cols * 8), align256(multi ? n * cols * 8 : 256),
+                           align256(multi ? m * cols * 8 : 256), 2 * 64 * 8};
+  char* p = static_cast<char*>(base);
+  void* at[7];
+  size_t off = 0;
+  for (int k = 0; k < 7; ++k) {
+    at[k] = p ? p + off : nullptr;
+    off += sizes[k];
+  }
+  RefineWs w{static_cast<float*>(at[0]),  static_cast<float*>(at[1]),  static_cast<double*>(at[2]),
+             static_cast<double*>(at[3]), static_cast<double*>(at[4]), static_cast<double*>(at[5]),
+             static_cast<unsigned long long*>(at[6]), off};
+  return w;
 }
 
 size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs) {
-  if (!s) return 0;
-  const int k = std::max(nrhs, 1);
-  const int kb = solve_kb(s, k);
-  const size_t n = size_t(std::max<int64_t>(s->n, 1));
-  const size_t nk = n * size_t(k), nkp = n * size_t((k + kb - 1) / kb * kb);
-  auto align = [](size_t v) { return (v + 255) / 256 * 256; };
-  // r32 | d32 | x ping | x pong (interleaved, padded to whole blocks) | max-abs accumulators
-  return 2 * align(nk * 4) + 2 * align(nkp * 8) + 2 * 64 * 8;
+  if (!s || nrhs < 1 || nrhs > 64) return 0;
+  return refine_layout(s, nrhs, nullptr).bytes;
 }
 
 sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64, const double* A64,
@@ -982,27 +1054,35 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   sf_status r = upload(s, st);
   if (r != SF_OK) return r;
   const int kb = solve_kb(s, nrhs);
-  const size_t nk = size_t(s->n) * size_t(nrhs);
-  const size_t nkp = size_t(s->n) * size_t((nrhs + kb - 1) / kb * kb);
-  auto align = [](size_t v) { return (v + 255) / 256 * 256; };
-  char* w = static_cast<char*>(workspace);
-  float* r32 = reinterpret_cast<float*>(w);
-  float* d32 = reinterpret_cast<float*>(w + align(nk * 4));
-  double* xa = reinterpret_cast<double*>(w + 2 * align(nk * 4));
-  double* xb = reinterpret_cast<double*>(w + 2 * align(nk * 4) + align(nkp * 8));
-  unsigned long long* mx = reinterpret_cast<unsigned long long*>(w + 2 * align(nk * 4) + 2 * align(nkp * 8));
+  const bool multi = kb > 1;
+  const RefineWs ws = refine_layout(s, nrhs, workspace);
   const int n = int32_t(s->n);
-  // The correction d of a solve, in the interleaved layout: a single
-  // right-hand side is its own layout; several are read from the solve's
-  // interleaved workspace, which holds the same values as X.
-  auto correction = [&]() -> const float* { return nrhs == 1 ? d32 : static_cast<const float*>(s->dev.xi); };
+  MultiWs mw{};
+  if (multi) {
+    r = multi_ws(s, kb, nrhs, 4, st, mw);
+    if (r == SF_OK) r = ensure_units(s, std::max(1, 64 / kb), st);
+    if (r != SF_OK) return r;
+  }
+  // One FP32 solve L32 d = r32: several right-hand sides stay interleaved
+  // (d in the solve's workspace, which the passes read as the correction).
+  auto solve32 = [&]() -> sf_status {
+    if (!multi) return exec_ts_fused(s, SF_F32, L32, nullptr, ws.r32, n, 1, ws.d32, n, nullptr, 0, st);
+    return exec_multi_core(s, 1, L32, nullptr, ws.r32, mw.xi, nullptr, nrhs, kb, st);
+  };
+  const float* corr = multi ? static_cast<const float*>(mw.xi) : ws.d32;
+  const double* b64 = multi ? ws.b64 : B;  // one right-hand side: B is its own layout
   // 1. x0 = L32^{-1} b in FP32 (b rounded to FP32)
-  SF_HIP(launch_convert_f64_f32(B, ldb, r32, n, nrhs, st));
-  r = exec_ts_fused(s, SF_F32, L32, nullptr, r32, n, nrhs, d32, n, nullptr, 0, st);
+  if (multi) {
+    SF_HIP(launch_pack(B, 0, ldb, n, nrhs, ws.b64, 0, nullptr, kb, st));
+    SF_HIP(launch_pack(B, 0, ldb, n, nrhs, ws.r32, 1, mw.xi, kb, st));
+  } else {
+    SF_HIP(launch_convert_f64_f32(B, ws.r32, n, st));
+  }
+  r = solve32();
   if (r != SF_OK) return r;
   // 2. corrections: x <- x + d, r = b - L64 x, d = L32^{-1} r
   const double* xin = nullptr;
-  double* xout = xa;
+  double* xout = ws.xa;
   for (int t = 0; t < n_corrections; ++t) {
     ResArgs ra{};
     ra.n = n;
@@ -1012,21 +1092,20 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
     ra.Lrp = s->dev.Lrp;
     ra.Lci = s->dev.Lci;
     ra.L64 = L64;
-    ra.B = B;
-    ra.ldb = ldb;
+    ra.B = b64;
     ra.xin = xin;
-    ra.d = correction();
+    ra.d = corr;
     ra.xout = xout;
-    ra.ldxo = n;
-    ra.r32 = r32;
+    ra.r32 = ws.r32;
     SF_HIP(launch_residual(ra, st));
-    r = exec_ts_fused(s, SF_F32, L32, nullptr, r32, n, nrhs, d32, n, nullptr, 0, st);
+    if (multi) SF_HIP(launch_fill_pending(mw.xi, size_t(n) * size_t((nrhs + kb - 1) / kb) * size_t(kb), 1, st));
+    r = solve32();
     if (r != SF_OK) return r;
     xin = xout;
-    xout = (xout == xa) ? xb : xa;
+    xout = (xout == ws.xa) ? ws.xb : ws.xa;
   }
   // 3. x_final = x + d; y = A64 x_final; r = b - L64 x_final (FP64)
-  SF_HIP(launch_fill_u64(mx, 2 * nrhs, st));
+  SF_HIP(launch_fill_u64(ws.mx, 2 * nrhs, st));
   ResArgs fa{};
   fa.n = n;
   fa.m = Y ? int32_t(s->m) : 0;
@@ -1038,17 +1117,19 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   fa.Arp = s->dev.Arp;
   fa.Aci = s->dev.Aci;
   fa.A64 = A64;
-  fa.B = B;
-  fa.ldb = ldb;
+  fa.B = b64;
   fa.xin = xin;
-  fa.d = correction();
-  fa.xout = X;
-  fa.ldxo = ldx;
+  fa.d = corr;
+  fa.xout = multi ? xout : X;
   fa.r32 = nullptr;
-  fa.Y = Y;
-  fa.ldy = ldy;
-  fa.maxabs = mx;
+  fa.Y = Y ? (multi ? ws.y64 : Y) : nullptr;
+  fa.maxabs = ws.mx;
   SF_HIP(launch_final(fa, st));
+  if (multi) {
+    SF_HIP(launch_unpack(xout, 0, n, nrhs, X, ldx, kb, st));
+    if (Y) SF_HIP(launch_unpack(ws.y64, 0, int32_t(s->m), nrhs, Y, ldy, kb, st));
+  }
+  const unsigned long long* mx = ws.mx;
   if (out_relres) {
     std::vector<unsigned long long> h(size_t(2 * nrhs));
     SF_HIP(hipMemcpyAsync(h.data(), mx, h.size() * 8, hipMemcpyDeviceToHost, st));

@@ -5,12 +5,13 @@
 //              buffer so rows never read a partly updated iterate.
 //   final:     x_final = x + d, y = A64 x_final and r = b - L64 x_final in
 //              FP64, plus max_i |r_i| and max_i |b_i| per column.
-// The iterate and the correction are kept in the interleaved block layout
-// of the multi-RHS solve (ResArgs), so one gather of a column index brings
-// the KB values of a block's right-hand sides together.  KB lanes per row,
-// one per right-hand side of the block, 64 / KB rows per wavefront; each
-// lane runs its row's entries kR at a time (indices and values, then the
-// iterate).  No dependences: every read is of finished data.
+// Every vector is kept in the interleaved block layout of the multi-RHS
+// solve (k_layout.hip), so one gather of a column index brings the KB values
+// of a block's right-hand sides together and each row's reads and writes
+// are contiguous.  KB lanes per row, one per right-hand side of the block,
+// 64 / KB rows per wavefront; each lane runs its row's entries kR at a time
+// (indices and values, then the iterate).  No dependences: every read is of
+// finished data.
 #include "dev_common.h"
 
 namespace sf {
@@ -81,23 +82,22 @@ __global__ __launch_bounds__(kBlockThreads) void k_resid(ResArgs a) {
     Layout<KB> lay{a.n, size_t(blk) * size_t(a.n) * KB + c};
     if (i < a.n) {
       const double s = row_dot<KB>(a, lay, a.Lci, a.L64, a.Lrp[i], a.Lrp[i + 1]);
-      const double b = colok ? a.B[size_t(i) + size_t(cc) * a.ldb] : 0.0;
+      const double b = a.B[lay.at(i)];  // zero in the padding columns of the last block
       const double r = b - s;
       const double xi = xval<KB>(a, lay, i);
+      a.xout[lay.at(i)] = xi;
       if (FINAL) {
         if (colok) {
-          a.xout[size_t(i) + size_t(cc) * a.ldxo] = xi;
           atomicMax(&smax[2 * cc], (unsigned long long)__double_as_longlong(fabs(r)));
           atomicMax(&smax[2 * cc + 1], (unsigned long long)__double_as_longlong(fabs(b)));
         }
       } else {
-        a.xout[lay.at(i)] = xi;
-        if (colok) a.r32[size_t(i) + size_t(cc) * a.n] = float(r);
+        a.r32[lay.at(i)] = float(r);
       }
     }
     if (FINAL && a.Y && i < a.m) {
       const double y = row_dot<KB>(a, lay, a.Aci, a.A64, a.Arp[i], a.Arp[i + 1]);
-      if (colok) a.Y[size_t(i) + size_t(cc) * a.ldy] = y;
+      a.Y[size_t(blk) * size_t(a.m) * KB + size_t(i) * KB + c] = y;
     }
   }
   if (FINAL) {
@@ -108,13 +108,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_resid(ResArgs a) {
   }
 }
 
-__global__ void k_convert(const double* src, int32_t lds, float* dst, int32_t n, int32_t nrhs) {
-  const size_t total = size_t(n) * size_t(nrhs);
-  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < total;
-       k += size_t(gridDim.x) * blockDim.x) {
-    const size_t c = k / size_t(n), i = k - c * size_t(n);
-    dst[k] = float(src[i + c * size_t(lds)]);
-  }
+__global__ void k_convert(const double* src, float* dst, int32_t n) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) dst[k] = float(src[k]);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int32_t count) {
@@ -146,12 +141,11 @@ hipError_t launch_residual(const ResArgs& a, hipStream_t st) { return launch_res
 
 hipError_t launch_final(const ResArgs& a, hipStream_t st) { return launch_resid<true>(a, st); }
 
-hipError_t launch_convert_f64_f32(const double* src, int32_t lds, float* dst, int32_t n, int32_t nrhs,
-                                  hipStream_t st) {
-  const size_t total = size_t(n) * size_t(nrhs);
-  int grid = int((total + 255) / 256);
-  grid = grid < 1 ? 1 : (grid > 8192 ? 8192 : grid);
-  hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, src, lds, dst, n, nrhs);
+hipError_t launch_convert_f64_f32(const double* src, float* dst, int32_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (n + 255) / 256;
+  grid = grid > 8192 ? 8192 : grid;
+  hipLaunchKernelGGL(k_convert, dim3(grid), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

@@ -196,22 +196,26 @@ __global__ __launch_bounds__(kBlockThreads) void k_pair(TsArgs a) {
 
 // ------------------------------------------------------------- k > 1 ------
 // KB lanes per row, one lane per right-hand side of the block; 64/KB rows
-// at a time (the multi-RHS plan cuts items to that many rows).  The
-// solution of block b is kept interleaved in a workspace,
-// xi[(b * n + j) * KB + c] (filled with the pending pattern before the
-// launch), so the KB values a row reads from x_j are contiguous; X and Y are
-// column-major.  Work index t = item * nblk + block.  Each lane runs its
-// row's entries in ascending order (b_i minus each rounded product), kU
-// entries at a time: their indices and values, then their x, are loaded
-// together, and the pending x of the whole wavefront are waited for
-// together (dev::wait_ptrs).
+// at a time (the multi-RHS plan cuts items to that many rows).  B, the
+// solution xi (filled with the pending pattern before the launch) and Y are
+// in the interleaved block layout: row j of block b holds its KB values
+// contiguously at [(b * rows + j) * KB], so a lane's gather of x_j and its
+// reads and writes of row i are coalesced across the row's lanes.  Work
+// index t = item * nblk + block.  Each lane runs its row's entries in
+// ascending order (b_i minus each rounded product), kU entries at a time:
+// their indices and values, then their x, are loaded together.  Load modes:
+// kPoll (fused executor) waits for the pending x of the whole wavefront
+// together (dev::wait_ptrs); kCoherent (level set: x written in this launch
+// before a grid barrier) reads device-coherent values without waiting;
+// kFinal (a later launch) reads through the caches.
 constexpr int kU = 8;
+enum LoadMode { kPoll, kCoherent, kFinal };
 
-template <typename T, int KB, bool TRSV, bool POLL>
+template <typename T, int KB, bool TRSV, LoadMode MODE>
 __device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T* __restrict__ val, const T* xi,
                                        int p0, int p1, int c, T acc, int lane, const LaunchState& ls) {
   int nch = (p1 - p0 + kU - 1) / kU;
-  if constexpr (POLL) {  // the wait is wave-wide: every lane runs the same number of rounds
+  if constexpr (MODE == kPoll) {  // the wait is wave-wide: every lane runs the same number of rounds
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) nch = max(nch, __shfl_xor(nch, d, 64));
   }
@@ -230,9 +234,10 @@ __device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T*
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       ptr[u] = j[u] >= 0 ? xi + size_t(j[u]) * KB + c : nullptr;
-      xv[u] = ptr[u] ? ld_co(ptr[u]) : T(0);
+      if constexpr (MODE == kFinal) xv[u] = ptr[u] ? *ptr[u] : T(0);
+      else xv[u] = ptr[u] ? ld_co(ptr[u]) : T(0);
     }
-    if constexpr (POLL) dev::wait_ptrs<T, kU>(ptr, xv, lane, ls);
+    if constexpr (MODE == kPoll) dev::wait_ptrs<T, kU>(ptr, xv, lane, ls);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (j[u] < 0) break;
@@ -244,30 +249,24 @@ __device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T*
   return acc;
 }
 
-template <typename T, int KB, bool POLL>
+template <typename T, int KB, LoadMode MODE>
 __device__ __forceinline__ void trsv_rows_multi(const TsArgs& a, int q0, int q1, int blk, int lane) {
   constexpr int RPB = 64 / KB;
   const int c = lane % KB;
-  const int cc = blk * KB + c;
-  const bool colok = cc < a.nrhs;
   const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
-  const T* __restrict__ B = static_cast<const T*>(a.B);
-  T* __restrict__ X = static_cast<T*>(a.X);
-  T* xi = static_cast<T*>(a.xi) + size_t(blk) * size_t(a.n) * KB;
+  const size_t boff = size_t(blk) * size_t(a.n) * KB;
+  const T* __restrict__ B = static_cast<const T*>(a.B) + boff;
+  T* xi = static_cast<T*>(a.xi) + boff;
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / KB;
     const bool act = q < q1;
     const int i = act ? a.order[q] : 0;
     const int r0 = act ? a.Lrp[i] : 0;
     const int rd = act ? a.Lrp[i + 1] - 1 : 0;
-    const T bi = (act && colok) ? B[size_t(i) + size_t(cc) * a.ldb] : T(0);
+    const T bi = act ? B[size_t(i) * KB + c] : T(0);
     const T dii = act ? Lv[rd] : T(1);
-    const T s = row_multi<T, KB, true, POLL>(a.Lci, Lv, xi, r0, rd, c, bi, lane, a.ls);
-    if (act) {
-      const T xv = publishable(s / dii);
-      st_co(xi + size_t(i) * KB + c, xv);
-      if (colok) __builtin_nontemporal_store(xv, X + size_t(i) + size_t(cc) * a.ldx);
-    }
+    const T s = row_multi<T, KB, true, MODE>(a.Lci, Lv, xi, r0, rd, c, bi, lane, a.ls);
+    if (act) st_co(xi + size_t(i) * KB + c, publishable(s / dii));
   }
 }
 
@@ -275,10 +274,8 @@ template <typename T, int KB>
 __device__ __forceinline__ void spmv_rows_multi(const TsArgs& a, int q0, int q1, int blk, int lane) {
   constexpr int RPB = 64 / KB;
   const int c = lane % KB;
-  const int cc = blk * KB + c;
-  const bool colok = cc < a.nrhs;
   const T* __restrict__ Av = static_cast<const T*>(a.Av);
-  T* __restrict__ Y = static_cast<T*>(a.Y);
+  T* __restrict__ Y = static_cast<T*>(a.Y) + size_t(blk) * size_t(a.m) * KB;
   const T* xi = static_cast<const T*>(a.xi) + size_t(blk) * size_t(a.n) * KB;
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / KB;
@@ -286,8 +283,8 @@ __device__ __forceinline__ void spmv_rows_multi(const TsArgs& a, int q0, int q1,
     const int r = act ? a.order[q] - a.n : 0;
     const int p0 = act ? a.Arp[r] : 0;
     const int p1 = act ? a.Arp[r + 1] : 0;
-    const T s = row_multi<T, KB, false, true>(a.Aci, Av, xi, p0, p1, c, T(0), lane, a.ls);
-    if (act && colok) __builtin_nontemporal_store(s, Y + size_t(r) + size_t(cc) * a.ldy);
+    const T s = row_multi<T, KB, false, kPoll>(a.Aci, Av, xi, p0, p1, c, T(0), lane, a.ls);
+    if (act) __builtin_nontemporal_store(s, Y + size_t(r) * KB + c);
   }
 }
 
@@ -303,7 +300,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_multi(TsArgs a) {
     const int blk = t - w * a.nblk;
     const int it = a.item_list ? a.item_list[w] : w;
     const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-    if (a.order[q0] < a.n) trsv_rows_multi<T, KB, true>(a, q0, q1, blk, lane);
+    if (a.order[q0] < a.n) trsv_rows_multi<T, KB, kPoll>(a, q0, q1, blk, lane);
     else spmv_rows_multi<T, KB>(a, q0, q1, blk, lane);
     t = tn;
   }
@@ -323,12 +320,12 @@ __global__ void k_fill_pending(T* p, size_t count) {
 // barrier (no readiness protocol); afterwards a separate launch runs the
 // SpMV items.  x is read and written with device-coherent accesses so the
 // barrier only has to wait for stores to complete (dev::grid_barrier).
-template <typename T>
+template <typename T, int KB>
 __global__ __launch_bounds__(kBlockThreads) void k_trsv_levelset(LevelArgs la) {
-  __shared__ WaveLds<T> lds[kWaves];
+  __shared__ WaveLds<T> lds[KB == 1 ? kWaves : 1];
   const TsArgs& a = la.ts;
   const int lane = threadIdx.x & 63;
-  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  WaveLds<T>& w = lds[KB == 1 ? (threadIdx.x >> 6) : 0];
   dev::reset_next_launch(a.ls);
   const int wave = int(blockIdx.x) * kWaves + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * kWaves;
@@ -338,8 +335,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_trsv_levelset(LevelArgs la) {
     for (int t = t0 + wave; t < t1; t += nwaves) {
       const int it = a.item_list[t];
       const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-      if (a.nrhs == 1) item_stream<T, true, 1>(a, q0, q1, lane, w);
-      else for (int blk = 0; blk < a.nblk; ++blk) trsv_rows_multi<T, 8, false>(a, q0, q1, blk, lane);
+      if constexpr (KB == 1) item_stream<T, true, 1>(a, q0, q1, lane, w);
+      else for (int blk = 0; blk < a.nblk; ++blk) trsv_rows_multi<T, KB, kCoherent>(a, q0, q1, blk, lane);
     }
     if (lv + 1 < la.depth) dev::grid_barrier(a.ls, gen);
   }
@@ -359,32 +356,40 @@ __global__ __launch_bounds__(kBlockThreads) void k_spmv_items(TsArgs a) {
   }
 }
 
-// Plain CSR SpMV over column-major blocks (multi-RHS baseline), one lane
-// per row, ascending entries.
-template <typename T>
-__global__ __launch_bounds__(kBlockThreads) void k_spmv(SpmvArgs a) {
+// Plain CSR SpMV over interleaved blocks (multi-RHS baseline): KB lanes per
+// row, one per right-hand side, 64 / KB rows per wavefront, ascending
+// entries; x is final (written by an earlier launch).
+template <typename T, int KB>
+__global__ __launch_bounds__(kBlockThreads) void k_spmv_multi(SpmvArgs a) {
+  constexpr int RPB = 64 / KB;
+  const int lane = threadIdx.x & 63;
+  const int c = lane % KB;
+  const int wave = int(blockIdx.x) * kWaves + int(threadIdx.x >> 6);
+  const int nwaves = int(gridDim.x) * kWaves;
+  const int groups = (a.m + RPB - 1) / RPB;
   const T* __restrict__ Av = static_cast<const T*>(a.Av);
-  const T* __restrict__ X = static_cast<const T*>(a.X);
-  T* __restrict__ Y = static_cast<T*>(a.Y);
-  for (int r = blockIdx.x * kBlockThreads + threadIdx.x; r < a.m; r += gridDim.x * kBlockThreads) {
-    const int p0 = a.Arp[r], p1 = a.Arp[r + 1];
-    for (int c = 0; c < a.nrhs; ++c) {
-      const T* x = X + size_t(c) * a.ldx;
-      T s = T(0);
-      for (int p = p0; p < p1; ++p) {
-        const T pr = Av[p] * x[a.Aci[p]];
-        s = s + pr;
-      }
-      Y[size_t(r) + size_t(c) * a.ldy] = s;
-    }
+  for (int u = wave; u < groups * a.nblk; u += nwaves) {
+    const int blk = u % a.nblk;
+    const int r = (u / a.nblk) * RPB + lane / KB;
+    const T* X = static_cast<const T*>(a.X) + size_t(blk) * size_t(a.n) * KB;
+    T* Y = static_cast<T*>(a.Y) + size_t(blk) * size_t(a.m) * KB;
+    const bool act = r < a.m;
+    const int p0 = act ? a.Arp[r] : 0, p1 = act ? a.Arp[r + 1] : 0;
+    const T s = row_multi<T, KB, false, kFinal>(a.Aci, Av, X, p0, p1, c, T(0), lane, LaunchState{});
+    if (act) __builtin_nontemporal_store(s, Y + size_t(r) * KB + c);
   }
 }
 
 template <typename T>
 hipError_t levelset_launch(const LevelArgs& a, int grid, hipStream_t st) {
   void* args[] = {const_cast<LevelArgs*>(&a)};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_trsv_levelset<T>), dim3(grid),
-                                    dim3(kBlockThreads), args, 0, st);
+#define SF_LS(KB)                                                                                          \
+  if (a.ts.kb == KB)                                                                                       \
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_trsv_levelset<T, KB>), dim3(grid), \
+                                      dim3(kBlockThreads), args, 0, st);
+  SF_LS(1) SF_LS(2) SF_LS(4) SF_LS(8) SF_LS(16) SF_LS(32) SF_LS(64)
+#undef SF_LS
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -439,10 +444,12 @@ int occupancy_pair(int dtype, int mode) {
   return dtype == 0 ? occ(k_pair<double, 1>) : occ(k_pair<float, 1>);
 }
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st) {
+  if (!a.order || !a.item_ptr || !a.xi || !a.B || a.nblk < 1 || (a.Y && !a.Arp)) return hipErrorInvalidValue;
   return dtype == 0 ? ts_multi_dispatch<double>(a, kb, grid, st) : ts_multi_dispatch<float>(a, kb, grid, st);
 }
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st) {
-  if (a.ts.nrhs == 1 && (!a.ts.qrng || !a.ts.order || !a.ts.item_ptr)) return hipErrorInvalidValue;
+  if (!a.ts.order || !a.ts.item_ptr || !a.ts.item_list || !a.lvl_item_ptr) return hipErrorInvalidValue;
+  if (a.ts.kb == 1 ? !a.ts.qrng : (!a.ts.xi || a.ts.nblk < 1)) return hipErrorInvalidValue;
   return dtype == 0 ? levelset_launch<double>(a, grid, st) : levelset_launch<float>(a, grid, st);
 }
 hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st) {
@@ -452,12 +459,24 @@ hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st) {
   else hipLaunchKernelGGL(k_spmv_items<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t spmv_multi_dispatch(const SpmvArgs& a, int grid, hipStream_t st) {
+#define SF_SM(KB)                                                                      \
+  if (a.kb == KB) {                                                                    \
+    hipLaunchKernelGGL((k_spmv_multi<T, KB>), dim3(grid), dim3(kBlockThreads), 0, st, a); \
+    return hipGetLastError();                                                          \
+  }
+  SF_SM(2) SF_SM(4) SF_SM(8) SF_SM(16) SF_SM(32) SF_SM(64)
+#undef SF_SM
+  return hipErrorInvalidValue;
+}
 hipError_t launch_spmv(const SpmvArgs& a, int dtype, hipStream_t st) {
-  int grid = (a.m + kBlockThreads - 1) / kBlockThreads;
+  if (a.m <= 0) return hipSuccess;
+  if (!a.Arp || !a.Aci || !a.Av || !a.X || !a.Y || a.kb < 2 || a.nblk < 1) return hipErrorInvalidValue;
+  const long units = long((a.m + 64 / a.kb - 1) / (64 / a.kb)) * a.nblk;
+  long grid = (units + kWaves - 1) / kWaves;
   grid = grid < 1 ? 1 : (grid > cu_count() * 32 ? cu_count() * 32 : grid);
-  if (dtype == 0) hipLaunchKernelGGL(k_spmv<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
-  else hipLaunchKernelGGL(k_spmv<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
-  return hipGetLastError();
+  return dtype == 0 ? spmv_multi_dispatch<double>(a, int(grid), st) : spmv_multi_dispatch<float>(a, int(grid), st);
 }
 hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st) {
   if (count == 0) return hipSuccess;
@@ -476,8 +495,9 @@ int occupancy_ts_multi(int dtype, int kb) {
   (void)kb;
   return dtype == 0 ? occ(k_ts_multi<double, 8>) : occ(k_ts_multi<float, 8>);
 }
-int occupancy_trsv_levelset(int dtype) {
-  return dtype == 0 ? occ(k_trsv_levelset<double>) : occ(k_trsv_levelset<float>);
+int occupancy_trsv_levelset(int dtype, int kb) {
+  if (kb > 1) return dtype == 0 ? occ(k_trsv_levelset<double, 8>) : occ(k_trsv_levelset<float, 8>);
+  return dtype == 0 ? occ(k_trsv_levelset<double, 1>) : occ(k_trsv_levelset<float, 1>);
 }
 
 }  // namespace sf

@@ -24,6 +24,10 @@ struct TsArgs {
   const void* Lv;
   const int32_t *Arp, *Aci;
   const void* Av;
+  // One right-hand side: plain vectors (B, X of length n, Y of length m).
+  // Several: B, xi and Y are in the interleaved block layout of k_layout.hip
+  // (nblk blocks of kb columns; B and xi of n rows, Y of m rows), X is unused
+  // and the ld fields are ignored.
   const void* B;
   int32_t ldb;
   void* X;
@@ -31,7 +35,7 @@ struct TsArgs {
   void* Y;
   int32_t ldy;
   int32_t nrhs, kb, nblk;  // right-hand sides, block width, number of blocks
-  void* xi;                // nblk * n * kb interleaved solution workspace (nrhs > 1)
+  void* xi;                // interleaved solution, also its readiness flags (nrhs > 1)
   const int32_t *order, *item_ptr, *item_list;
   const int32_t* qrng;     // per claim position: CSR range of the row's dot product (pairs)
   int32_t n_work;          // items to run (entries of item_list, or all items)
@@ -48,15 +52,14 @@ struct LevelArgs {
   int32_t depth;
 };
 
-// Standalone CSR SpMV: Y = A X (column-major blocks).
+// Standalone CSR SpMV over interleaved blocks (multi-RHS baseline):
+// Y = A X, X of n rows and Y of m rows, nblk blocks of kb columns each.
 struct SpmvArgs {
-  int32_t m, nrhs;
+  int32_t m, n, kb, nblk;
   const int32_t *Arp, *Aci;
   const void* Av;
   const void* X;
-  int32_t ldx;
   void* Y;
-  int32_t ldy;
 };
 
 // Fused SpIC0 -> SpTRSV (FP64).
@@ -124,15 +127,14 @@ struct ResArgs {
   const double* L64;
   const int32_t *Arp, *Aci;
   const double* A64;
-  const double* B;     // column-major, ld ldb
-  int32_t ldb;
-  const double* xin;   // interleaved current iterate, nullptr = 0
-  const float* d;      // interleaved correction to add, nullptr = none
-  double* xout;        // residual pass: interleaved new iterate; final pass: X column-major (ld ldxo)
-  int32_t ldxo;
-  float* r32;          // n x nrhs residual, column-major (ld n); nullptr = not needed
-  double* Y;           // final product (ld ldy), nullptr = none
-  int32_t ldy;
+  // Every vector below is in the interleaved block layout of k_layout.hip
+  // (a plain vector when kb == 1): n rows, except Y with m rows.
+  const double* B;     // right-hand sides
+  const double* xin;   // current iterate, nullptr = 0
+  const float* d;      // correction to add, nullptr = none
+  double* xout;        // new iterate (x + d)
+  float* r32;          // residual rounded to FP32 (residual pass); nullptr = not needed
+  double* Y;           // final product, nullptr = none
   unsigned long long* maxabs;  // 2 * nrhs: max |r| and max |b| bit patterns
 };
 
@@ -141,7 +143,7 @@ hipError_t launch_ts_fused(const TsArgs& a, int dtype, int grid, hipStream_t st)
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
 hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st);
 int occupancy_pair(int dtype, int mode);
-hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st);
+hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st);  // kb = a.ts.kb
 hipError_t launch_spmv(const SpmvArgs& a, int dtype, hipStream_t st);
 // SpMV items of a schedule (a.item_list / a.n_work), all inputs final.
 hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st);
@@ -155,8 +157,14 @@ hipError_t launch_precond(const PrecondArgs& a, int dtype, int grid, hipStream_t
 int occupancy_precond(int dtype);
 hipError_t launch_residual(const ResArgs& a, hipStream_t st);
 hipError_t launch_final(const ResArgs& a, hipStream_t st);
-hipError_t launch_convert_f64_f32(const double* src, int32_t lds, float* dst, int32_t n,
-                                  int32_t nrhs, hipStream_t st);
+// Column-major <-> interleaved block layout (k_layout.hip).  dtype 0 = f64,
+// 1 = f32; pack converts f64 -> f32 when asked and fills pend (optional,
+// same layout as dst) with the pending pattern.
+hipError_t launch_pack(const void* src, int src_dtype, int32_t lds, int32_t rows, int32_t ncols, void* dst,
+                       int dst_dtype, void* pend, int kb, hipStream_t st);
+hipError_t launch_unpack(const void* src, int dtype, int32_t rows, int32_t ncols, void* dst, int32_t ldd, int kb,
+                         hipStream_t st);
+hipError_t launch_convert_f64_f32(const double* src, float* dst, int32_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int32_t count, hipStream_t st);
 // Fill a solution buffer with the pending (not yet published) pattern.
 hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st);
@@ -165,7 +173,7 @@ hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st)
 // Occupancy queries per kernel family (blocks per CU).
 int occupancy_ts_fused(int dtype);
 int occupancy_ts_multi(int dtype, int kb);
-int occupancy_trsv_levelset(int dtype);
+int occupancy_trsv_levelset(int dtype, int kb);
 int occupancy_ic0(int g, int levelset);
 int occupancy_bwd(int dtype, int g);
 

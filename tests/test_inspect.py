@@ -383,3 +383,18 @@ def test_ilu0_structural_errors():
     with pytest.raises(sfm.SparseFusionError) as e:
         sfm.Schedule(r, None, sfm.SF_ILU0_TRSV)
     assert e.value.name == "SF_ERR_SHAPE"
+
+
+def test_rhs_block_must_be_a_kernel_width():
+    """The multi-RHS kernels exist for blocks of 2, 4, ..., 64 columns; other
+    widths are refused at inspection and by set_param, never at launch."""
+    L, A = synth.workload("lap2d5_16")
+    for bad in (1, 3, 12, 65, -2):
+        assert _err(lambda: sfm.Schedule(L, A, rhs_block=bad)) == "SF_ERR_ARG", bad
+    for good in (0, 2, 8, 64):
+        sfm.Schedule(L, A, rhs_block=good).free()
+    s = sfm.Schedule(L, A)
+    for bad in (1, 3, 128):
+        assert _err(lambda: s.set_param("rhs_block", bad)) == "SF_ERR_ARG", bad
+    s.set_param("rhs_block", 16)
+    assert s.get_param("rhs_block") == 16
