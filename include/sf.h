@@ -220,7 +220,8 @@ sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level,
  * demand, freed with it) in which each row of a block holds its columns
  * contiguously, the solve and the product run there, and X and Y are
  * unpacked at the end; only rows < n of X and < m of Y are written.
- * Errors: SF_ERR_ARG, SF_ERR_SHAPE, SF_ERR_HIP, SF_ERR_OOM.
+ * Several right-hand sides need n * rhs_block < 2^31 (else SF_ERR_UNSUPPORTED).
+ * Errors: SF_ERR_ARG, SF_ERR_SHAPE, SF_ERR_UNSUPPORTED, SF_ERR_HIP, SF_ERR_OOM.
  */
 sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
                             const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
@@ -394,6 +395,9 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "rhs_block"                 right-hand sides per DAG pass (0 = by nrhs,
  *                               else a power of two 2..64);
  *   "waves_per_cu"              persistent-grid residency target (4..32);
+ *   "multi_waves_per_cu"        the same for several right-hand sides
+ *                               (fused and level-set; 4..32, or 0, the
+ *                               default: 8, 16 or 32 by the units per level);
  *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT;
  *   "claim_streams"             work-claim counters (1..32);
  *   "rows_per_item", "max_item_nnz"  re-cut the work items (rows <= 64);

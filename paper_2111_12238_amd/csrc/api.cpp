@@ -152,6 +152,8 @@ struct MultiWs {
 
 sf_status multi_ws(sf_schedule_s* s, int kb, int nrhs, size_t es, hipStream_t st, MultiWs& w) {
   DeviceBuffers& d = s->dev;
+  // the executors address a block's interleaved x with 32-bit offsets
+  if (int64_t(s->n) * kb > int64_t(INT32_MAX)) return SF_ERR_UNSUPPORTED;
   const size_t cols = size_t((nrhs + kb - 1) / kb) * size_t(kb);
   const size_t bx = align256(std::max<size_t>(size_t(s->n) * cols * es, 1));
   const size_t by = align256(std::max<size_t>(size_t(s->m) * cols * es, 1));
@@ -186,9 +188,9 @@ sf_status next_epoch(sf_schedule_s* s, hipStream_t st, LaunchState& ls) {
   return SF_OK;
 }
 
-int persistent_grid(sf_schedule_s* s, int occupancy_blocks_per_cu) {
+int persistent_grid(sf_schedule_s* s, int occupancy_blocks_per_cu, int waves_per_cu = 0) {
   const int cus = std::max(1, device_cus());
-  const int want = std::max(1, s->waves_per_cu * 64 / kBlockThreads);
+  const int want = std::max(1, (waves_per_cu > 0 ? waves_per_cu : s->waves_per_cu) * 64 / kBlockThreads);
   const int per_cu = std::min(want, std::max(1, occupancy_blocks_per_cu));
   return std::max(cus * per_cu, kStreams);
 }
@@ -257,32 +259,54 @@ TsArgs ts_args(sf_schedule_s* s, const void* Lv, const void* Av, const void* B, 
 }
 
 // Multi-RHS plan for blocks of 64 / rpb rows: the level items split into
-// pieces of at most rpb rows (rows of a level item are independent, so the
-// pieces keep the claim order valid), kept on the device until the items
-// are re-cut or another block width is asked for.
+// units of at most rpb rows (rows of a level item are independent, so the
+// units keep the claim order valid), kept on the device until the items are
+// re-cut or another block width is asked for.  Per unit the range of its
+// claim positions; the SpTRSV units alone (in claim order, hence by level)
+// and, per level, the first of them for the level-set baseline.
 sf_status ensure_units(sf_schedule_s* s, int rpb, hipStream_t st) {
   DeviceBuffers& d = s->dev;
   if (d.units && d.units_rpb == rpb) return SF_OK;
-  std::vector<int32_t> ptr, trsv;
-  ptr.push_back(0);
+  std::vector<int32_t> all, trsv, lvl(size_t(std::max(s->depth, 0)) + 1, 0);
   for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t)
     for (int32_t b = s->item_ptr[t]; b < s->item_ptr[t + 1]; b += rpb) {
-      if (s->order[b] < s->n) trsv.push_back(int32_t(ptr.size()) - 1);
-      ptr.push_back(std::min(b + rpb, s->item_ptr[t + 1]));
+      const int32_t e = std::min(b + rpb, s->item_ptr[t + 1]);
+      all.push_back(b);
+      all.push_back(e);
+      const int32_t id = s->order[b];
+      if (id < s->n) {
+        trsv.push_back(b);
+        trsv.push_back(e);
+        ++lvl[size_t(s->level[id]) + 1];
+      }
     }
+  for (size_t l = 1; l < lvl.size(); ++l) lvl[l] += lvl[l - 1];
   SF_HIP(hipStreamSynchronize(st));
   if (d.units) SF_HIP(hipFree(d.units));
   d.units = nullptr;
-  const size_t b0 = ptr.size() * 4, b1 = std::max<size_t>(trsv.size(), 1) * 4;
-  SF_HIP(hipMalloc(&d.units, b0 + b1));
-  d.unit_ptr = static_cast<int32_t*>(d.units);
-  d.unit_trsv = reinterpret_cast<int32_t*>(static_cast<char*>(d.units) + b0);
-  SF_HIP(hipMemcpy(d.unit_ptr, ptr.data(), b0, hipMemcpyHostToDevice));
-  if (!trsv.empty()) SF_HIP(hipMemcpy(d.unit_trsv, trsv.data(), trsv.size() * 4, hipMemcpyHostToDevice));
+  const size_t b0 = std::max<size_t>(all.size(), 2) * 4, b1 = std::max<size_t>(trsv.size(), 2) * 4;
+  SF_HIP(hipMalloc(&d.units, b0 + b1 + lvl.size() * 4));
+  d.unit_rng = static_cast<int32_t*>(d.units);
+  d.unit_trsv_rng = reinterpret_cast<int32_t*>(static_cast<char*>(d.units) + b0);
+  d.lvl_unit_ptr = reinterpret_cast<int32_t*>(static_cast<char*>(d.units) + b0 + b1);
+  if (!all.empty()) SF_HIP(hipMemcpy(d.unit_rng, all.data(), all.size() * 4, hipMemcpyHostToDevice));
+  if (!trsv.empty()) SF_HIP(hipMemcpy(d.unit_trsv_rng, trsv.data(), trsv.size() * 4, hipMemcpyHostToDevice));
+  SF_HIP(hipMemcpy(d.lvl_unit_ptr, lvl.data(), lvl.size() * 4, hipMemcpyHostToDevice));
   d.units_rpb = rpb;
-  d.n_units = int32_t(ptr.size()) - 1;
-  d.n_unit_trsv = int32_t(trsv.size());
+  d.n_units = int32_t(all.size() / 2);
+  d.n_unit_trsv = int32_t(trsv.size() / 2);
   return SF_OK;
+}
+
+// Residency target of the multi-RHS executors.  Units of one level run in
+// parallel and a few levels overlap; wavefronts beyond that only poll, so
+// by default the target follows the units per level (mean level width over
+// the rows per unit, times the blocks).
+int multi_waves(const sf_schedule_s* s, int kb, int nrhs) {
+  if (s->multi_waves_per_cu > 0) return s->multi_waves_per_cu;
+  const double width = double(s->n) / double(std::max(s->depth, 1));
+  const double units = width / double(std::max(1, 64 / kb)) * double((nrhs + kb - 1) / kb);
+  return units < 256 ? 8 : (units < 4096 ? 16 : 32);
 }
 
 // Fused multi-RHS executor on interleaved data: bi (n rows) -> xi, whose
@@ -293,8 +317,9 @@ sf_status exec_multi_core(sf_schedule_s* s, int dtype, const void* Lv, const voi
   TsArgs a = ts_args(s, Lv, Av, bi, int32_t(s->n), nrhs, nullptr, int32_t(s->n), yi, int32_t(s->m));
   sf_status r = ensure_units(s, std::max(1, 64 / kb), st);
   if (r != SF_OK) return r;
-  a.item_ptr = s->dev.unit_ptr;
-  a.item_list = yi ? nullptr : s->dev.unit_trsv;
+  a.unit_rng = reinterpret_cast<const int2*>(yi ? s->dev.unit_rng : s->dev.unit_trsv_rng);
+  a.item_ptr = nullptr;
+  a.item_list = nullptr;
   a.n_work = yi ? s->dev.n_units : s->dev.n_unit_trsv;
   if (a.n_work == 0) return SF_OK;
   r = next_epoch(s, st, a.ls);
@@ -302,7 +327,7 @@ sf_status exec_multi_core(sf_schedule_s* s, int dtype, const void* Lv, const voi
   a.kb = kb;
   a.nblk = (nrhs + kb - 1) / kb;
   a.xi = xi;
-  const int grid = persistent_grid(s, occupancy_ts_multi(dtype, kb));
+  const int grid = persistent_grid(s, occupancy_ts_multi(dtype, kb), multi_waves(s, kb, nrhs));
   return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
 }
 
@@ -363,11 +388,15 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
   const int kb = solve_kb(s, nrhs);
   MultiWs w{};
   if (nrhs > 1) {
+    // the level's SpTRSV units (as in the fused path), spread over the grid
     sf_status r = multi_ws(s, kb, nrhs, es, st, w);
+    if (r == SF_OK) r = ensure_units(s, std::max(1, 64 / kb), st);
     if (r != SF_OK) return r;
     la.ts.B = w.bi;
     la.ts.X = nullptr;
     la.ts.xi = w.xi;
+    la.ts.unit_rng = reinterpret_cast<const int2*>(s->dev.unit_trsv_rng);
+    la.lvl_item_ptr = s->dev.lvl_unit_ptr;
   }
   la.ts.kb = kb;
   la.ts.nblk = (nrhs + kb - 1) / kb;
@@ -378,7 +407,8 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
   if (s->n > 0 && s->depth > 0) {
     const int cus = std::max(1, device_cus());
     const int occ = occupancy_trsv_levelset(dtype, kb);
-    int grid = cus * std::min(occ, std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+    const int waves = nrhs > 1 ? multi_waves(s, kb, nrhs) : s->waves_per_cu;
+    int grid = cus * std::min(occ, std::max(1, waves * 64 / kBlockThreads));
     SF_HIP(launch_trsv_levelset(la, dtype, grid, st));
   }
   if (Y && s->m > 0 && nrhs == 1) {
@@ -1190,6 +1220,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "waves_per_cu") {
     if (v < 4 || v > 32) return SF_ERR_ARG;
     s->waves_per_cu = int32_t(v);
+  } else if (k == "multi_waves_per_cu") {
+    if (v != 0 && (v < 4 || v > 32)) return SF_ERR_ARG;
+    s->multi_waves_per_cu = int32_t(v);
   } else if (k == "spin_limit") {
     if (v < 1) return SF_ERR_ARG;
     s->spin_limit = v;
@@ -1236,6 +1269,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "lanes_spmv") *v = s->lanes_spmv;
   else if (k == "rhs_block") *v = s->rhs_block;
   else if (k == "waves_per_cu") *v = s->waves_per_cu;
+  else if (k == "multi_waves_per_cu") *v = s->multi_waves_per_cu;
   else if (k == "spin_limit") *v = s->spin_limit;
   else if (k == "claim_streams") *v = s->claim_streams;
   else if (k == "rows_per_item") *v = s->rows_per_item;
@@ -1306,7 +1340,8 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 1 << 20});
   if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});
   if (r == SF_OK && nrhs == 1) r = try_param("max_item_nnz", {128, 256, 512, 1024, 2048});
-  if (r == SF_OK) r = try_param("waves_per_cu", {4, 8, 16});
+  if (r == SF_OK && nrhs == 1) r = try_param("waves_per_cu", {4, 8, 16});
+  if (r == SF_OK && nrhs > 1) r = try_param("multi_waves_per_cu", {8, 16, 32});
   if (r == SF_OK) r = upload(s, st);
   s->timing = saved_timing;
   hipEventDestroy(e0);

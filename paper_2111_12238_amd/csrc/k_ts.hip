@@ -23,6 +23,8 @@
 // contraction is allowed in this file.
 #pragma clang fp contract(off)
 
+#include <type_traits>
+
 #include "stream.h"
 
 namespace sf {
@@ -195,114 +197,175 @@ __global__ __launch_bounds__(kBlockThreads) void k_pair(TsArgs a) {
 }
 
 // ------------------------------------------------------------- k > 1 ------
-// KB lanes per row, one lane per right-hand side of the block; 64/KB rows
-// at a time (the multi-RHS plan cuts items to that many rows).  B, the
-// solution xi (filled with the pending pattern before the launch) and Y are
-// in the interleaved block layout: row j of block b holds its KB values
-// contiguously at [(b * rows + j) * KB], so a lane's gather of x_j and its
-// reads and writes of row i are coalesced across the row's lanes.  Work
-// index t = item * nblk + block.  Each lane runs its row's entries in
-// ascending order (b_i minus each rounded product), kU entries at a time:
-// their indices and values, then their x, are loaded together.  Load modes:
-// kPoll (fused executor) waits for the pending x of the whole wavefront
-// together (dev::wait_ptrs); kCoherent (level set: x written in this launch
-// before a grid barrier) reads device-coherent values without waiting;
-// kFinal (a later launch) reads through the caches.
-constexpr int kU = 8;
-enum LoadMode { kPoll, kCoherent, kFinal };
+// KB lanes per row, one lane per right-hand side of the block, 64 / KB rows
+// per wavefront.  B, the solution xi (filled with the pending pattern before
+// the launch) and Y are in the interleaved block layout: row j of block b
+// holds its KB values contiguously at [(b * rows + j) * KB], so a lane's
+// gather of x_j and its reads and writes of row i are coalesced across the
+// row's lanes.  Each lane folds its row's terms in ascending entry order
+// (b_i minus, or 0 plus, each rounded product).
 
-template <typename T, int KB, bool TRSV, LoadMode MODE>
-__device__ __forceinline__ T row_multi(const int32_t* __restrict__ col, const T* __restrict__ val, const T* xi,
-                                       int p0, int p1, int c, T acc, int lane, const LaunchState& ls) {
-  int nch = (p1 - p0 + kU - 1) / kU;
-  if constexpr (MODE == kPoll) {  // the wait is wave-wide: every lane runs the same number of rounds
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) nch = max(nch, __shfl_xor(nch, d, 64));
-  }
-  for (int ch = 0; ch < nch; ++ch) {
-    const int c0 = p0 + ch * kU;
+// One row of the unfused SpMV over finished x, kU entries at a time (their
+// indices and values, then their x, loaded together through the caches).
+constexpr int kU = 8;
+template <typename T, int KB>
+__device__ __forceinline__ T row_final(const int32_t* __restrict__ col, const T* __restrict__ val, const T* xi,
+                                       int p0, int p1, int c) {
+  T acc = T(0);
+  for (int c0 = p0; c0 < p1; c0 += kU) {
     int j[kU];
     T v[kU], xv[kU];
-    const T* ptr[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int p = c0 + u;
-      const bool h = p < p1;
-      j[u] = h ? col[p] : -1;
-      v[u] = h ? val[p] : T(0);
+      const bool h = c0 + u < p1;
+      j[u] = h ? col[c0 + u] : -1;
+      v[u] = h ? val[c0 + u] : T(0);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      ptr[u] = j[u] >= 0 ? xi + size_t(j[u]) * KB + c : nullptr;
-      if constexpr (MODE == kFinal) xv[u] = ptr[u] ? *ptr[u] : T(0);
-      else xv[u] = ptr[u] ? ld_co(ptr[u]) : T(0);
-    }
-    if constexpr (MODE == kPoll) dev::wait_ptrs<T, kU>(ptr, xv, lane, ls);
+    for (int u = 0; u < kU; ++u) xv[u] = j[u] >= 0 ? xi[size_t(j[u]) * KB + c] : T(0);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (j[u] < 0) break;
-      const T pr = v[u] * xv[u];
-      if constexpr (TRSV) acc = acc - pr;
-      else acc = acc + pr;
+      acc = acc + v[u] * xv[u];
     }
   }
   return acc;
 }
 
-template <typename T, int KB, LoadMode MODE>
-__device__ __forceinline__ void trsv_rows_multi(const TsArgs& a, int q0, int q1, int blk, int lane) {
-  constexpr int RPB = 64 / KB;
-  const int c = lane % KB;
-  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
-  const size_t boff = size_t(blk) * size_t(a.n) * KB;
-  const T* __restrict__ B = static_cast<const T*>(a.B) + boff;
-  T* xi = static_cast<T*>(a.xi) + boff;
-  for (int base = q0; base < q1; base += RPB) {
-    const int q = base + lane / KB;
-    const bool act = q < q1;
-    const int i = act ? a.order[q] : 0;
-    const int r0 = act ? a.Lrp[i] : 0;
-    const int rd = act ? a.Lrp[i + 1] - 1 : 0;
-    const T bi = act ? B[size_t(i) * KB + c] : T(0);
-    const T dii = act ? Lv[rd] : T(1);
-    const T s = row_multi<T, KB, true, MODE>(a.Lci, Lv, xi, r0, rd, c, bi, lane, a.ls);
-    if (act) st_co(xi + size_t(i) * KB + c, publishable(s / dii));
-  }
-}
-
+// A unit of the multi-RHS plan: up to 64 / KB rows of one kind, claim
+// positions [q0, q1).  Row meta (its index and CSR range, both with the
+// claim position) takes one round trip.  Units whose rows have at most
+// kShort entries load them directly in each lane; otherwise, a chunk of
+// S::CH entries per row at a time, the row's KB lanes stage its column
+// indices and values in LDS with one round of loads (lane c takes entries
+// c, c + KB, ...).  Every lane then gathers its column of x for up to kUx
+// entries at once and waits for the pending ones of the whole wavefront
+// together (dev::wait_ready on offsets into the block's interleaved x).  Products are folded in
+// ascending entry order.  POLL = false (level set): x was written before a
+// grid barrier and is read device-coherently without waiting.
+template <int KB>
+struct MultiShape {
+  static constexpr int NE = KB <= 8 ? 8 : 4;  // entries each lane stages per chunk
+  static constexpr int CH = KB * NE;          // entries of one row per chunk
+};
 template <typename T, int KB>
-__device__ __forceinline__ void spmv_rows_multi(const TsArgs& a, int q0, int q1, int blk, int lane) {
-  constexpr int RPB = 64 / KB;
-  const int c = lane % KB;
-  const T* __restrict__ Av = static_cast<const T*>(a.Av);
-  T* __restrict__ Y = static_cast<T*>(a.Y) + size_t(blk) * size_t(a.m) * KB;
-  const T* xi = static_cast<const T*>(a.xi) + size_t(blk) * size_t(a.n) * KB;
-  for (int base = q0; base < q1; base += RPB) {
-    const int q = base + lane / KB;
-    const bool act = q < q1;
-    const int r = act ? a.order[q] - a.n : 0;
-    const int p0 = act ? a.Arp[r] : 0;
-    const int p1 = act ? a.Arp[r + 1] : 0;
-    const T s = row_multi<T, KB, false, kPoll>(a.Aci, Av, xi, p0, p1, c, T(0), lane, a.ls);
-    if (act) __builtin_nontemporal_store(s, Y + size_t(r) * KB + c);
+struct MultiLds {
+  int32_t col[64 * MultiShape<KB>::NE];
+  T val[64 * MultiShape<KB>::NE];
+};
+constexpr int kUx = 8;     // x gathers per lane in flight per wait round
+constexpr int kShort = 8;  // rows up to this long skip the LDS staging
+
+template <typename T, int KB, bool POLL>
+__device__ __forceinline__ void unit_multi(const TsArgs& a, int q0, int q1, int blk, int lane,
+                                           MultiLds<T, KB>& w, int next = -1, int2* next_rg = nullptr) {
+  using S = MultiShape<KB>;
+  const int g = lane / KB, c = lane % KB;
+  const int q = q0 + g;
+  const bool act = q < q1;
+  const int id = act ? a.order[q] : 0;
+  // an SpTRSV range stops before the diagonal
+  const int2 rg = act ? reinterpret_cast<const int2*>(a.qrng)[q] : make_int2(0, 0);
+  // the next unit's range, loaded once its ticket has arrived (it returns
+  // before the row meta above) and used after this unit
+  if (next_rg) *next_rg = next >= 0 ? a.unit_rng[next] : make_int2(0, 0);
+  const bool trsv = __shfl(id, 0, 64) < a.n;  // a unit holds rows of one kind
+  const T* __restrict__ val = static_cast<const T*>(trsv ? a.Lv : a.Av);
+  const int32_t* __restrict__ col = trsv ? a.Lci : a.Aci;
+  const size_t xoff = size_t(blk) * size_t(a.n) * KB;
+  T* xb = static_cast<T*>(a.xi) + xoff;
+  T acc = T(0), dii = T(1);
+  if (trsv && act) {
+    acc = static_cast<const T*>(a.B)[xoff + size_t(id) * KB + c];
+    dii = ld_stream(val + rg.y);
+  }
+  const int len = rg.y - rg.x;
+  int maxlen = len;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, d, 64));
+  if (maxlen <= kShort) {
+    // short rows: each lane loads its row's indices and values itself (the
+    // row's lanes read the same addresses), then gathers its column of x
+    int idx[kShort];
+    T v[kShort], xv[kShort];
+#pragma unroll
+    for (int u = 0; u < kShort; ++u) {
+      const bool h = u < len;
+      idx[u] = h ? ld_stream(col + rg.x + u) : -1;
+      v[u] = h ? ld_stream(val + rg.x + u) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kShort; ++u) {
+      idx[u] = idx[u] >= 0 ? idx[u] * KB + c : -1;
+      xv[u] = idx[u] >= 0 ? ld_co(xb + idx[u]) : T(0);
+    }
+    if constexpr (POLL) dev::wait_ready<T, kShort>(xb, idx, xv, lane, a.ls);
+#pragma unroll
+    for (int u = 0; u < kShort; ++u) {
+      if (idx[u] < 0) break;
+      const T pr = v[u] * xv[u];
+      acc = trsv ? acc - pr : acc + pr;
+    }
+  }
+  const int slice = g * S::CH;
+  for (int base = 0; maxlen > kShort && base < maxlen; base += S::CH) {
+#pragma unroll
+    for (int e = 0; e < S::NE; ++e) {
+      const int u = base + c + KB * e;
+      if (u < len) {
+        w.col[slice + c + KB * e] = ld_stream(col + rg.x + u);
+        w.val[slice + c + KB * e] = ld_stream(val + rg.x + u);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(S::CH, len - base);  // this row's entries in the chunk (may be <= 0)
+    int wcnt = cnt;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wcnt = max(wcnt, __shfl_xor(wcnt, d, 64));
+    for (int r0 = 0; r0 < wcnt; r0 += kUx) {
+      int idx[kUx];
+      T xv[kUx];
+#pragma unroll
+      for (int u = 0; u < kUx; ++u) {
+        idx[u] = r0 + u < cnt ? w.col[slice + r0 + u] * KB + c : -1;
+        xv[u] = idx[u] >= 0 ? ld_co(xb + idx[u]) : T(0);
+      }
+      if constexpr (POLL) dev::wait_ready<T, kUx>(xb, idx, xv, lane, a.ls);
+#pragma unroll
+      for (int u = 0; u < kUx; ++u) {
+        if (idx[u] < 0) break;
+        const T pr = w.val[slice + r0 + u] * xv[u];
+        acc = trsv ? acc - pr : acc + pr;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (act) {
+    if (trsv) st_co(xb + size_t(id) * KB + c, publishable(acc / dii));
+    else __builtin_nontemporal_store(acc, static_cast<T*>(a.Y) + size_t(blk) * size_t(a.m) * KB +
+                                              size_t(id - a.n) * KB + c);
   }
 }
 
+// Work index t = unit * nblk + block.  The next ticket is claimed before
+// the current unit runs and its range is loaded inside it (see unit_multi),
+// so neither is a round trip on the next unit's chain; deadlock freedom is
+// as in k_ts_fused.
 template <typename T, int KB>
 __global__ __launch_bounds__(kBlockThreads) void k_ts_multi(TsArgs a) {
+  __shared__ MultiLds<T, KB> lds[kWaves];
   const int lane = threadIdx.x & 63;
+  MultiLds<T, KB>& w = lds[threadIdx.x >> 6];
   dev::reset_next_launch(a.ls);
   const int total = a.n_work * a.nblk;
   int t = dev::claim(a.ls, lane);
+  int2 rg = t < total ? a.unit_rng[t / a.nblk] : make_int2(0, 0);
   while (t < total) {
     const int tn = dev::claim(a.ls, lane);
-    const int w = t / a.nblk;
-    const int blk = t - w * a.nblk;
-    const int it = a.item_list ? a.item_list[w] : w;
-    const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-    if (a.order[q0] < a.n) trsv_rows_multi<T, KB, kPoll>(a, q0, q1, blk, lane);
-    else spmv_rows_multi<T, KB>(a, q0, q1, blk, lane);
+    int2 rgn;
+    unit_multi<T, KB, true>(a, rg.x, rg.y, t % a.nblk, lane, w, tn < total ? tn / a.nblk : -1, &rgn);
     t = tn;
+    rg = rgn;
   }
 }
 
@@ -315,28 +378,37 @@ __global__ void k_fill_pending(T* p, size_t count) {
 }
 
 // ---------------------------------------------------------- level set ----
-// Unfused baseline, same per-item arithmetic: the SpTRSV items of one level
-// are spread over all wavefronts of a cooperative grid, then a grid-wide
-// barrier (no readiness protocol); afterwards a separate launch runs the
-// SpMV items.  x is read and written with device-coherent accesses so the
-// barrier only has to wait for stores to complete (dev::grid_barrier).
+// Unfused baseline, same per-row arithmetic: the SpTRSV items of one level
+// (several right-hand sides: the level's units times the blocks) are spread
+// over all wavefronts of a cooperative grid, then a grid-wide barrier (no
+// readiness protocol); afterwards a separate launch runs the SpMV.  x is
+// read and written with device-coherent accesses so the barrier only has to
+// wait for stores to complete (dev::grid_barrier).
 template <typename T, int KB>
 __global__ __launch_bounds__(kBlockThreads) void k_trsv_levelset(LevelArgs la) {
-  __shared__ WaveLds<T> lds[KB == 1 ? kWaves : 1];
+  // one right-hand side: level items through item_stream; several: the
+  // level's units (la.lvl_item_ptr indexes a.unit_rng) times the blocks
+  using Lds = std::conditional_t<KB == 1, WaveLds<T>, MultiLds<T, (KB > 1 ? KB : 2)>>;
+  __shared__ Lds lds[kWaves];
   const TsArgs& a = la.ts;
   const int lane = threadIdx.x & 63;
-  WaveLds<T>& w = lds[KB == 1 ? (threadIdx.x >> 6) : 0];
+  Lds& w = lds[threadIdx.x >> 6];
   dev::reset_next_launch(a.ls);
   const int wave = int(blockIdx.x) * kWaves + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * kWaves;
   int32_t gen = 0;
   for (int lv = 0; lv < la.depth; ++lv) {
     const int t0 = la.lvl_item_ptr[lv], t1 = la.lvl_item_ptr[lv + 1];
-    for (int t = t0 + wave; t < t1; t += nwaves) {
-      const int it = a.item_list[t];
-      const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-      if constexpr (KB == 1) item_stream<T, true, 1>(a, q0, q1, lane, w);
-      else for (int blk = 0; blk < a.nblk; ++blk) trsv_rows_multi<T, KB, kCoherent>(a, q0, q1, blk, lane);
+    if constexpr (KB == 1) {
+      for (int t = t0 + wave; t < t1; t += nwaves) {
+        const int it = a.item_list[t];
+        item_stream<T, true, 1>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, w);
+      }
+    } else {
+      for (int t = t0 * a.nblk + wave; t < t1 * a.nblk; t += nwaves) {
+        const int2 rg = a.unit_rng[t / a.nblk];
+        unit_multi<T, KB, false>(a, rg.x, rg.y, t % a.nblk, lane, w);
+      }
     }
     if (lv + 1 < la.depth) dev::grid_barrier(a.ls, gen);
   }
@@ -375,7 +447,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_spmv_multi(SpmvArgs a) {
     T* Y = static_cast<T*>(a.Y) + size_t(blk) * size_t(a.m) * KB;
     const bool act = r < a.m;
     const int p0 = act ? a.Arp[r] : 0, p1 = act ? a.Arp[r + 1] : 0;
-    const T s = row_multi<T, KB, false, kFinal>(a.Aci, Av, X, p0, p1, c, T(0), lane, LaunchState{});
+    const T s = row_final<T, KB>(a.Aci, Av, X, p0, p1, c);
     if (act) __builtin_nontemporal_store(s, Y + size_t(r) * KB + c);
   }
 }
@@ -444,12 +516,14 @@ int occupancy_pair(int dtype, int mode) {
   return dtype == 0 ? occ(k_pair<double, 1>) : occ(k_pair<float, 1>);
 }
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st) {
-  if (!a.order || !a.item_ptr || !a.xi || !a.B || a.nblk < 1 || (a.Y && !a.Arp)) return hipErrorInvalidValue;
+  if (!a.order || !a.qrng || !a.unit_rng || !a.xi || !a.B || a.nblk < 1 || (a.Y && !a.Arp))
+    return hipErrorInvalidValue;
   return dtype == 0 ? ts_multi_dispatch<double>(a, kb, grid, st) : ts_multi_dispatch<float>(a, kb, grid, st);
 }
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st) {
-  if (!a.ts.order || !a.ts.item_ptr || !a.ts.item_list || !a.lvl_item_ptr) return hipErrorInvalidValue;
-  if (a.ts.kb == 1 ? !a.ts.qrng : (!a.ts.xi || a.ts.nblk < 1)) return hipErrorInvalidValue;
+  if (!a.ts.order || !a.ts.qrng || !a.lvl_item_ptr) return hipErrorInvalidValue;
+  if (a.ts.kb == 1 ? (!a.ts.item_ptr || !a.ts.item_list) : (!a.ts.unit_rng || !a.ts.xi || a.ts.nblk < 1))
+    return hipErrorInvalidValue;
   return dtype == 0 ? levelset_launch<double>(a, grid, st) : levelset_launch<float>(a, grid, st);
 }
 hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st) {
@@ -491,12 +565,20 @@ hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st)
 int occupancy_ts_fused(int dtype) {
   return dtype == 0 ? occ(k_ts_fused<double>) : occ(k_ts_fused<float>);
 }
-int occupancy_ts_multi(int dtype, int kb) {
-  (void)kb;
-  return dtype == 0 ? occ(k_ts_multi<double, 8>) : occ(k_ts_multi<float, 8>);
+template <typename T>
+int occ_multi(int kb, bool levelset) {
+  switch (kb) {
+    case 2: return levelset ? occ(k_trsv_levelset<T, 2>) : occ(k_ts_multi<T, 2>);
+    case 4: return levelset ? occ(k_trsv_levelset<T, 4>) : occ(k_ts_multi<T, 4>);
+    case 8: return levelset ? occ(k_trsv_levelset<T, 8>) : occ(k_ts_multi<T, 8>);
+    case 16: return levelset ? occ(k_trsv_levelset<T, 16>) : occ(k_ts_multi<T, 16>);
+    case 32: return levelset ? occ(k_trsv_levelset<T, 32>) : occ(k_ts_multi<T, 32>);
+    default: return levelset ? occ(k_trsv_levelset<T, 64>) : occ(k_ts_multi<T, 64>);
+  }
 }
+int occupancy_ts_multi(int dtype, int kb) { return dtype == 0 ? occ_multi<double>(kb, false) : occ_multi<float>(kb, false); }
 int occupancy_trsv_levelset(int dtype, int kb) {
-  if (kb > 1) return dtype == 0 ? occ(k_trsv_levelset<double, 8>) : occ(k_trsv_levelset<float, 8>);
+  if (kb > 1) return dtype == 0 ? occ_multi<double>(kb, true) : occ_multi<float>(kb, true);
   return dtype == 0 ? occ(k_trsv_levelset<double, 1>) : occ(k_trsv_levelset<float, 1>);
 }
 

@@ -37,6 +37,7 @@ struct TsArgs {
   int32_t nrhs, kb, nblk;  // right-hand sides, block width, number of blocks
   void* xi;                // interleaved solution, also its readiness flags (nrhs > 1)
   const int32_t *order, *item_ptr, *item_list;
+  const int2* unit_rng;    // multi-RHS: claim-position range of each unit (replaces item_ptr / item_list)
   const int32_t* qrng;     // per claim position: CSR range of the row's dot product (pairs)
   int32_t n_work;          // items to run (entries of item_list, or all items)
   const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
@@ -73,6 +74,7 @@ struct Ic0Args {
   const int32_t *pair_ptr, *pair_u, *pair_q;
   const int32_t* dpos;     // SpILU0: diagonal position of each row (nullptr for SpIC0)
   const int32_t *order, *item_ptr, *item_list;
+  const int2* unit_rng;    // multi-RHS: claim-position range of each unit (replaces item_ptr / item_list)
   int32_t n_work;
   const int32_t* lvl_item_ptr;  // level-set variant
   int32_t depth;

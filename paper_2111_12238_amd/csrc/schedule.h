@@ -62,9 +62,13 @@ struct DeviceBuffers {
   int32_t* state = nullptr;
   void* xi = nullptr;           // interleaved right-hand-side workspace
   size_t xi_bytes = 0;
-  // multi-RHS plan: the level items split into pieces of units_rpb rows
+  // multi-RHS plan: the level items split into units of at most units_rpb
+  // rows; per unit its range of claim positions (all units in claim order,
+  // and the SpTRSV units alone, which are sorted by level), and per level
+  // the first SpTRSV unit (level-set baseline)
   void* units = nullptr;
-  int32_t *unit_ptr = nullptr, *unit_trsv = nullptr;
+  int32_t *unit_rng = nullptr, *unit_trsv_rng = nullptr;  // (first, end) pairs
+  int32_t* lvl_unit_ptr = nullptr;
   int32_t units_rpb = 0, n_units = 0, n_unit_trsv = 0;
   uint32_t epoch = 0;
 };
@@ -135,6 +139,7 @@ struct sf_schedule_s {
 
   // Executor parameters.
   int32_t lanes_trsv = 4, lanes_spmv = 8, rhs_block = 0, waves_per_cu = 8;
+  int32_t multi_waves_per_cu = 0;  // residency target of the multi-RHS executors (0: by level width)
   int32_t rows_per_item = 64, max_item_nnz = 4096;
   // wavefronts (level items) or item-chain steps (coarsened items) an SpMV
   // row is placed after its inputs are final; -1: 0 for level items, after

@@ -93,10 +93,15 @@ def test_params_roundtrip():
     import synth
     L, A = synth.workload("lap2d5_16")
     s = sfm.Schedule(L, A)
+    assert s.get_param("multi_waves_per_cu") == 0  # by the units per level
     for k, v in (("lanes_trsv", 8), ("lanes_spmv", 16), ("rhs_block", 32), ("waves_per_cu", 16),
-                 ("spin_limit", 12345), ("claim_streams", 4), ("rows_per_item", 32), ("no_fusion", 1)):
+                 ("multi_waves_per_cu", 32), ("spin_limit", 12345), ("claim_streams", 4), ("rows_per_item", 32),
+                 ("no_fusion", 1)):
         s.set_param(k, v)
         assert s.get_param(k) == v
+    for k, bad in (("waves_per_cu", 2), ("multi_waves_per_cu", 64)):
+        with pytest.raises(sfm.SparseFusionError):
+            s.set_param(k, bad)
     with pytest.raises(sfm.SparseFusionError):
         s.set_param("lanes_trsv", 3)
     with pytest.raises(sfm.SparseFusionError):

@@ -407,3 +407,27 @@ def test_full_size_configs(orc, name):
     assert np.array_equal(x, xr) and np.array_equal(y, yr)
     xu, yu = run(s, L, A, b, unfused=True)
     assert relerr(xu, xr) <= TOL64 and relerr(yu, yr) <= TOL64
+
+
+@pytest.mark.parametrize("kb", [8, 64])
+def test_multi_rhs_alternating_bit_exact(orc, kb):
+    """Launches with different right-hand sides in turn, fused and unfused,
+    on one schedule (whose interleaved workspace is reused at the same
+    address): every result is exact, so no value of an earlier launch is
+    ever taken for a published one."""
+    announce("ts multi-rhs alternating kb=%d" % kb)
+    import torch
+    L, A = synth.workload("lap2d5_64")
+    Ls, As = L.to_scipy(), A.to_scipy()
+    sets = []
+    for t in range(3):
+        xt = np.stack([synth.int_vector(L.nrows, seed=10 * t + c) for c in range(kb)], 1)
+        sets.append((dev_colmajor(Ls @ xt), xt, As @ xt))
+    s = sfm.Schedule(L, A, rhs_block=kb)
+    Lv, Av = dev(L.val), dev(A.val)
+    for it in range(9):
+        B, xt, yt = sets[it % 3]
+        X, Y = sfm.trsv_spmv(s, Lv, Av, B, unfused=(it % 4 == 3))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(X), xt) and np.array_equal(host(Y), yt), it
+    sfm.sync_status(s)
