@@ -299,7 +299,7 @@ __device__ __forceinline__ void unit_multi(const TsArgs& a, int q0, int q1, int 
       idx[u] = idx[u] >= 0 ? idx[u] * KB + c : -1;
       xv[u] = idx[u] >= 0 ? ld_co(xb + idx[u]) : T(0);
     }
-    if constexpr (POLL) dev::wait_ready<T, kShort>(xb, idx, xv, lane, a.ls);
+    if constexpr (POLL) dev::wait_ready<T, kShort, 64>(xb, idx, xv, lane, a.ls);
 #pragma unroll
     for (int u = 0; u < kShort; ++u) {
       if (idx[u] < 0) break;
@@ -330,7 +330,7 @@ __device__ __forceinline__ void unit_multi(const TsArgs& a, int q0, int q1, int 
         idx[u] = r0 + u < cnt ? w.col[slice + r0 + u] * KB + c : -1;
         xv[u] = idx[u] >= 0 ? ld_co(xb + idx[u]) : T(0);
       }
-      if constexpr (POLL) dev::wait_ready<T, kUx>(xb, idx, xv, lane, a.ls);
+      if constexpr (POLL) dev::wait_ready<T, kUx, 64>(xb, idx, xv, lane, a.ls);
 #pragma unroll
       for (int u = 0; u < kUx; ++u) {
         if (idx[u] < 0) break;

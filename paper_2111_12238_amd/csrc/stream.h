@@ -30,16 +30,33 @@ struct WaveLds {
 };
 
 // Wait until every vec[j[e]] of the wavefront (j[e] < 0: unused slot) is
-// published, updating xv.  Only one lane polls at a time: among the pending
-// entries the wavefront watches the one with the largest index -- producers
-// are claimed in topological order, so the largest index is usually the
-// last to be published -- and once it is, every lane re-reads all its
-// still-pending entries in one round; the election repeats if any remain.
-// This keeps the polling traffic of a waiting wavefront at one request
-// instead of one per pending entry, and usually needs a single round.
-template <typename T, int R>
+// published, updating xv.  Two ways to wait, chosen per round by how many
+// lanes still wait (ALL_BELOW):
+//  - every lane re-reads all its pending entries (up to ALL_BELOW waiting
+//    lanes): the last value is seen within one round trip of its
+//    publication, at one request per pending entry and round;
+//  - one lane polls: among the pending entries the wavefront watches the
+//    one with the largest index -- producers are claimed in topological
+//    order, so it is usually the last to be published -- and once it is,
+//    every lane re-reads its still-pending entries; the election repeats if
+//    any remain.  One request per round keeps the traffic of many waiting
+//    wavefronts low, at about a third of a round trip more latency.
+// ALL_BELOW = 64 always takes the first way (latency-bound schedules: one
+// item waits on a few producers); 0 always the second.
+// One round of "every lane re-reads its pending entries"; false once the
+// watchdog has fired (the caller then drains).
+__device__ __forceinline__ bool all_poll_round(int32_t& spins, const LaunchState& ls) {
+  if (++spins >= ls.spin_limit) {
+    st_co(ls.state + kStatusOff, kStatusTimeout);
+    return false;
+  }
+  return (spins & 63) != 0 || ld_co(ls.state + kStatusOff) == 0;
+}
+
+template <typename T, int R, int ALL_BELOW = 32>
 __device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&xv)[R], int lane,
                                            const LaunchState& ls) {
+  int32_t spins = 0;
   for (;;) {
     int jmax = -1;
 #pragma unroll
@@ -47,6 +64,13 @@ __device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&
       if (j[e] >= 0 && is_pending(xv[e])) jmax = max(jmax, j[e]);
     const unsigned long long mask = __ballot(jmax >= 0);
     if (mask == 0) return;
+    if (ALL_BELOW >= 64 || __popcll(mask) <= ALL_BELOW) {
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (j[e] >= 0 && is_pending(xv[e])) xv[e] = ld_co(vec + j[e]);
+      if (!all_poll_round(spins, ls)) return;
+      continue;
+    }
     int wmax = jmax;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, __shfl_xor(wmax, d, 64));
@@ -65,16 +89,25 @@ __device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&
 }
 
 // As wait_ready, for values at arbitrary addresses p[e] (nullptr: unused
-// slot), e.g. interleaved multi-column vectors or factor entries.  The
-// watched value is the pending one at the highest address.
-template <typename T, int R>
+// slot), e.g. factor entries.  The watched value is the pending one at the
+// highest address.
+template <typename T, int R, int ALL_BELOW = 32>
 __device__ __forceinline__ void wait_ptrs(const T* (&p)[R], T (&v)[R], int lane, const LaunchState& ls) {
+  int32_t spins = 0;
   for (;;) {
     unsigned long long best = 0;
 #pragma unroll
     for (int e = 0; e < R; ++e)
       if (p[e] && is_pending(v[e])) best = max(best, (unsigned long long)p[e]);
-    if (__ballot(best != 0) == 0) return;
+    const unsigned long long mask = __ballot(best != 0);
+    if (mask == 0) return;
+    if (ALL_BELOW >= 64 || __popcll(mask) <= ALL_BELOW) {
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (p[e] && is_pending(v[e])) v[e] = ld_co(p[e]);
+      if (!all_poll_round(spins, ls)) return;
+      continue;
+    }
     unsigned long long wbest = best;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1)
@@ -263,7 +296,7 @@ __device__ __forceinline__ T chunk_solve(int nr, int r0, int len, int myloc, int
 #pragma unroll
   for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? ld_co(vec + j[e]) : T(0);
   if (tr && lane == 0) tr[1] = __builtin_amdgcn_s_memrealtime();
-  wait_ready<T, kRounds>(vec, j, xv, lane, ls);
+  wait_ready<T, kRounds, 64>(vec, j, xv, lane, ls);  // few producers, latency-bound
   // LDS: prod[k] = rounded product (outside entry) or the value (local entry);
   // pos[k] = slot of the local column, or 0xFF
 #pragma unroll
