@@ -57,6 +57,8 @@ def _bind(lib):
         "orc_joint_order_ts": (None, [_c_int, _i32p, _c_int, _i32p, _i32p]),
         "orc_validate_ts": (_c_int, [_c_int, _i32p, _i32p, _c_int, _i32p, _i32p, _i32p, _c_int,
                                      _i32p, _c_int]),
+        "orc_validate_static_ts": (_c_int, [_c_int, _i32p, _i32p, _c_int, _i32p, _i32p, _c_int, _i32p,
+                                            _c_int, _i32p, _i32p]),
         "orc_reuse_ts": (ctypes.c_double, [_c_int, _c_int, _c_int, _c_int]),
         "orc_reuse_it": (ctypes.c_double, [_c_int, _c_int]),
     }
@@ -219,6 +221,15 @@ class Oracle:
         order, item_ptr = _i32(order), _i32(item_ptr)
         return self.lib.orc_validate_ts(len(lrp) - 1, lrp, _ptr(lci), len(arp) - 1, arp, _ptr(aci),
                                        _ptr(order), len(item_ptr) - 1, item_ptr, int(allow_intra))
+
+    def validate_static_ts(self, lrp, lci, arp, aci, s_ptr, w_ptr, order) -> int:
+        """0 if the two-level static schedule (s-partitions in sequence,
+        independent w-partitions, each in its listed order) respects every
+        edge of the joint SpTRSV -> SpMV DAG, else a rule code."""
+        lrp, lci, arp, aci = _i32(lrp), _i32(lci), _i32(arp), _i32(aci)
+        s_ptr, w_ptr, order = _i32(s_ptr), _i32(w_ptr), _i32(order)
+        return self.lib.orc_validate_static_ts(len(lrp) - 1, lrp, _ptr(lci), len(arp) - 1, arp, _ptr(aci),
+                                               len(s_ptr) - 1, s_ptr, len(w_ptr) - 1, w_ptr, _ptr(order))
 
     def reuse_ts(self, n, nnz_l, m, nnz_a) -> float:
         return float(self.lib.orc_reuse_ts(n, nnz_l, m, nnz_a))

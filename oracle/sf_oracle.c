@@ -20,6 +20,9 @@
  *     i of the second loop (Sec. 2.2, "Dependency Matrix F"; Sec. 3.1).
  *   - Wavefront (level-set) parallelism over the DAG (Sec. 1; "fused
  *     wavefront" baseline, Sec. 4 setup).
+ *   - A fused partitioning runs its s-partitions in sequence and the
+ *     independent w-partitions of one s-partition in parallel, each
+ *     w-partition's iterations in order (Sec. 3.1, output of MSP).
  *   - SpIC0 is zero fill-in incomplete Cholesky, L L^T ~= A (Table 2,
  *     combinations 5 and 7).  The paper gives no recurrence; the one used
  *     here is the textbook up-looking row form: the unique lower-triangular
@@ -377,6 +380,57 @@ int orc_validate_ts(int n, const int32_t* lrp, const int32_t* lci, int m,
       if (!ok) { rc = 5; break; }
     }
   free(pos); free(item);
+  return rc;
+}
+
+/* Validity of a static two-level schedule of the SpTRSV -> SpMV pair, as
+ * a fused partitioning (Sec. 3.1) executes it: the nb s-partitions run one
+ * after another, with a synchronisation between them; the w-partitions of
+ * one s-partition are independent and run in parallel; the iterations of
+ * one w-partition run in their listed order.  s_ptr (nb + 1 entries) cuts
+ * the nw w-partitions into s-partitions, w_ptr (nw + 1 entries) cuts order
+ * into w-partitions; empty partitions are allowed.  Valid iff the pointers
+ * are monotone covers, order is a permutation of 0..n+m-1 (ids as in
+ * orc_joint_order_ts), and every DAG edge u -> v (L_ij: j -> i for j < i;
+ * A_rj: j -> n+r) has s(u) < s(v), or s(u) == s(v), w(u) == w(v) and u
+ * listed before v.  Returns 0 if valid, else a positive code naming the
+ * first violated rule. */
+int orc_validate_static_ts(int n, const int32_t* lrp, const int32_t* lci, int m,
+                           const int32_t* arp, const int32_t* aci, int nb, const int32_t* s_ptr,
+                           int nw, const int32_t* w_ptr, const int32_t* order) {
+  int N = n + m;
+  if (nb < 0 || nw < 0 || s_ptr[0] != 0 || s_ptr[nb] != nw || w_ptr[0] != 0 || w_ptr[nw] != N) return 1;
+  for (int b = 0; b < nb; ++b) if (s_ptr[b + 1] < s_ptr[b]) return 2;
+  for (int w = 0; w < nw; ++w) if (w_ptr[w + 1] < w_ptr[w]) return 2;
+  size_t cap = (size_t)(N > 0 ? N : 1);
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * cap);
+  int32_t* wof = (int32_t*)malloc(sizeof(int32_t) * cap);
+  int32_t* sof = (int32_t*)malloc(sizeof(int32_t) * cap);
+  for (int u = 0; u < N; ++u) pos[u] = -1;
+  int rc = 0;
+  for (int b = 0; b < nb && !rc; ++b)
+    for (int w = s_ptr[b]; w < s_ptr[b + 1] && !rc; ++w)
+      for (int q = w_ptr[w]; q < w_ptr[w + 1]; ++q) {
+        int u = order[q];
+        if (u < 0 || u >= N || pos[u] >= 0) { rc = 3; break; }
+        pos[u] = q;
+        wof[u] = w;
+        sof[u] = b;
+      }
+  /* an edge u -> v is respected if u's s-partition finishes first, or u
+     runs earlier in the same w-partition */
+#define ORC_BEFORE(u, v) (sof[u] < sof[v] || (wof[u] == wof[v] && pos[u] < pos[v]))
+  for (int i = 0; i < n && !rc; ++i)
+    for (int p = lrp[i]; p < lrp[i + 1]; ++p) {
+      int j = lci[p];
+      if (j >= i) continue;
+      if (!ORC_BEFORE(j, i)) { rc = 4; break; }
+    }
+  for (int r = 0; r < m && !rc; ++r)
+    for (int p = arp[r]; p < arp[r + 1]; ++p)
+      if (!ORC_BEFORE(aci[p], n + r)) { rc = 5; break; }
+#undef ORC_BEFORE
+  free(pos); free(wof); free(sof);
   return rc;
 }
 

@@ -63,3 +63,37 @@ def dense_gradients(ld, ad, b, w):
     lam = solve_upper_t(ld, ad.T @ w)
     gl = -np.outer(lam, x) * (ld != 0)
     return x, lam, gl
+
+
+def _merges(seqs):
+    """Every interleaving of the sequences that keeps each one's order."""
+    seqs = [list(s) for s in seqs if len(s)]
+    if not seqs:
+        yield []
+        return
+    for k, s in enumerate(seqs):
+        rest = seqs[:k] + [s[1:]] + seqs[k + 1:]
+        for tail in _merges(rest):
+            yield [s[0]] + tail
+
+
+def static_schedule_runs(n_vertices, preds, s_ptr, w_ptr, order):
+    """Simulate a two-level static schedule: the s-partitions in sequence,
+    the w-partitions of one s-partition in every possible interleaving.
+    True iff every vertex runs exactly once, after all of its predecessors,
+    in every execution."""
+    import itertools
+    if sorted(order) != list(range(n_vertices)):
+        return False
+    per_s = []
+    for b in range(len(s_ptr) - 1):
+        ws = [order[w_ptr[w]:w_ptr[w + 1]] for w in range(s_ptr[b], s_ptr[b + 1])]
+        per_s.append(list(_merges(ws)))
+    for choice in itertools.product(*per_s):
+        done = set()
+        for part in choice:
+            for v in part:
+                if any(u not in done for u in preds[v]):
+                    return False
+                done.add(v)
+    return True

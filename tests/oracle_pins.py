@@ -339,6 +339,62 @@ def pin_validator(orc):
     assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, merged, allow_intra=True) == 0
 
 
+def _random_static_case(rng):
+    """A tiny joint SpTRSV -> SpMV DAG and a two-level schedule of it: half
+    the time cut from a random topological order (often valid), otherwise
+    a random assignment (mostly invalid)."""
+    n, m = int(rng.integers(2, 6)), int(rng.integers(0, 4))
+    ld = np.tril((rng.random((n, n)) < 0.45).astype(float), -1) + np.eye(n)
+    ad = (rng.random((m, n)) < 0.4).astype(float)
+    L, A = synth.from_scipy(sp.csr_matrix(ld)), synth.from_scipy(sp.csr_matrix(ad, shape=(m, n)))
+    preds = [[j for j in range(i) if ld[i, j]] for i in range(n)] + [[j for j in range(n) if ad[r, j]]
+                                                                      for r in range(m)]
+    N = n + m
+    if rng.random() < 0.5:
+        # a topological order: every SpTRSV row in row order, each SpMV row
+        # after its last input, then random cuts
+        order = list(range(n))
+        for r in range(m):
+            at = max([order.index(j) + 1 for j in preds[n + r]] + [int(rng.integers(0, len(order) + 1))])
+            order.insert(at, n + r)
+    else:
+        order = [int(v) for v in rng.permutation(N)]
+    nb = int(rng.integers(1, 4))
+    scuts = sorted(int(c) for c in rng.integers(0, N + 1, nb - 1))
+    s_bounds = [0] + scuts + [N]
+    s_ptr, w_ptr, ords = [0], [0], []
+    for b in range(nb):
+        chunk = order[s_bounds[b]:s_bounds[b + 1]]
+        nw = int(rng.integers(1, 4))
+        owner = rng.integers(0, nw, len(chunk))
+        for w in range(nw):
+            part = [v for v, o in zip(chunk, owner) if o == w]
+            ords += part
+            w_ptr.append(len(ords))
+        s_ptr.append(s_ptr[-1] + nw)
+    return L, A, preds, N, np.array(s_ptr, np.int32), np.array(w_ptr, np.int32), np.array(ords, np.int32)
+
+
+def pin_static_validator_bruteforce(orc):
+    """The static-schedule check agrees with a simulation of every
+    interleaving of the w-partitions of each s-partition (s-partitions in
+    sequence) on 300 tiny random DAGs and schedules; dropped and duplicated
+    vertices are rejected."""
+    rng = np.random.default_rng(7)
+    n_valid = 0
+    for _ in range(300):
+        L, A, preds, N, s_ptr, w_ptr, order = _random_static_case(rng)
+        want = bf.static_schedule_runs(N, preds, list(s_ptr), list(w_ptr), list(order))
+        got = orc.validate_static_ts(L.rowptr, L.col, A.rowptr, A.col, s_ptr, w_ptr, order)
+        assert (got == 0) == want, (got, want, s_ptr, w_ptr, order)
+        n_valid += int(want)
+        if N >= 2:
+            dup = order.copy()
+            dup[-1] = dup[0]
+            assert orc.validate_static_ts(L.rowptr, L.col, A.rowptr, A.col, s_ptr, w_ptr, dup) != 0
+    assert 30 <= n_valid <= 270  # both verdicts are exercised
+
+
 def pin_reuse_ratio(orc):
     """Reuse ratios from the paper's formulas (Sec. 2.2; Table 2,
     combinations 4 and 5) against the hand-computed values stored in

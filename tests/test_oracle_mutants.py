@@ -37,6 +37,10 @@ MUTANTS = {
         "    for (int r = 0; r < m; ++r) if (ready[r] == lv) order[pos++] = n + r;\n"
         "    for (int i = 0; i < n; ++i) if (level[i] == lv) order[pos++] = i;"),
     "validate_nonstrict": ("int ok = item[j] < item[i] ||", "int ok = item[j] <= item[i] ||"),
+    "static_any_w": ("(sof[u] < sof[v] || (wof[u] == wof[v] && pos[u] < pos[v]))",
+                     "(sof[u] < sof[v] || (sof[u] == sof[v] && pos[u] < pos[v]))"),
+    "static_nonstrict_s": ("(sof[u] < sof[v] || (wof[u] == wof[v] && pos[u] < pos[v]))",
+                           "(sof[u] <= sof[v] || (wof[u] == wof[v] && pos[u] < pos[v]))"),
     "reuse_dropped_term": ("double kl = (double)nnz_l + (double)n + (double)n;",
                            "double kl = (double)nnz_l + (double)n;"),
     "ilu0_no_divide": ("lu[p] = lu[p] / ukk;", "lu[p] = lu[p];"),
