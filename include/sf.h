@@ -238,6 +238,48 @@ sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L
                                     void* X, int32_t ldx, void* Y, int32_t ldy, void* stream);
 
 /*
+ * Static schedules of the SpTRSV -> SpMV pair, measured beside the
+ * dynamic executor.
+ *   SF_STATIC_MSP: the paper's fused partitioning (Sec. 3.2, Algorithm 1)
+ *     with G1 = the SpTRSV DAG as head and forward pairing:
+ *     - consecutive wavefronts grouped into s-partitions, each s-partition's
+ *       connected components into at most msp_parts cost-balanced
+ *       w-partitions;
+ *     - the SpMV rows paired with the w-partition holding all their inputs;
+ *     - zero-slack pairs merged;
+ *     - slack SpMV rows dispersed to balance the w-partitions;
+ *     - separated packing (Table 2: reuse ratio below one).
+ *   SF_STATIC_WAVEFRONT: the paper's "fused wavefront" comparison (Sec. 4):
+ *     one s-partition per wavefront of the joint DAG.
+ * The plan is built on the host at first use (no device needed for the
+ * info and export calls) and kept with the schedule.  Execution: one
+ * cooperative launch, with a grid barrier between s-partitions; each
+ * w-partition runs on one wavefront, its rows in order.
+ */
+typedef enum { SF_STATIC_MSP = 0, SF_STATIC_WAVEFRONT = 1 } sf_static_plan;
+
+/* Sizes of a static plan: s-partitions, w-partitions, executor batches, and
+ * (MSP) the pair partitions merged and the slack rows placed by balancing.
+ * Any output pointer may be NULL.  Errors: SF_ERR_ARG (not SF_TRSV_SPMV, bad
+ * plan), SF_ERR_OOM. */
+sf_status sf_schedule_static_info(sf_schedule s, int32_t plan, int32_t* n_spart, int32_t* n_wpart,
+                                  int32_t* n_batches, int32_t* merged, int32_t* slack_moved);
+
+/* Host copies of a static plan: s_ptr[n_spart + 1] indexes w-partitions,
+ * w_ptr[n_wpart + 1] indexes order, order[n + m] lists iteration ids (id
+ * i < n: SpTRSV row i; id n + r: SpMV row r) in execution order within each
+ * w-partition.  NULL outputs are skipped.  Errors as sf_schedule_static_info. */
+sf_status sf_schedule_export_static(sf_schedule s, int32_t plan, int32_t* s_ptr, int32_t* w_ptr,
+                                    int32_t* order);
+
+/* x = L^{-1} b and y = A x (one right-hand side, FP64 or FP32) under a
+ * static plan.  B, X (length n) and Y (length m) are device vectors; X must
+ * not alias B.  Results equal sf_exec_trsv_spmv's bit for bit (same per-row
+ * arithmetic).  Errors: SF_ERR_ARG, SF_ERR_OOM, SF_ERR_HIP. */
+sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, const void* L_val,
+                                   const void* A_val, const void* B, void* X, void* Y, void* stream);
+
+/*
  * sf_exec_spmv_trsv — fused SpMV -> SpTRSV (Table 2, comb. 2):
  *   y = A x, then z = L^{-1} y.
  * The SpMV's row i feeds only the solve's row i (F = I), so the work item of
@@ -398,6 +440,8 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "multi_waves_per_cu"        the same for several right-hand sides
  *                               (fused and level-set; 4..32, or 0, the
  *                               default: 8, 16 or 32 by the units per level);
+ *   "msp_parts"                 w-partitions per s-partition of the MSP plan
+ *                               (its r; 1..2^20, default 1024; rebuilds it);
  *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT;
  *   "claim_streams"             work-claim counters (1..32);
  *   "rows_per_item", "max_item_nnz"  re-cut the work items (rows <= 64);

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libsparsefusion.so")
 
 SF_F64, SF_F32 = 0, 1
 SF_TRSV_SPMV, SF_IC0_TRSV, SF_ILU0_TRSV = 0, 1, 2
+SF_STATIC_MSP, SF_STATIC_WAVEFRONT = 0, 1
 
 STATUS = {
     0: "SF_OK", 1: "SF_ERR_ARG", 2: "SF_ERR_CSR", 3: "SF_ERR_NOT_LOWER", 4: "SF_ERR_ZERO_DIAG",
@@ -85,6 +86,9 @@ _SIGS = {
     "sf_schedule_export_backward": [_P, _P, _P, _P],
     "sf_exec_trsv_spmv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P],
     "sf_exec_unfused_trsv_spmv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P],
+    "sf_schedule_static_info": [_P, _I, _P, _P, _P, _P, _P],
+    "sf_schedule_export_static": [_P, _I, _P, _P, _P],
+    "sf_exec_static_trsv_spmv": [_P, _I, _I, _P, _P, _P, _P, _P, _P],
     "sf_exec_ic0_trsv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _P],
     "sf_exec_unfused_ic0_trsv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _P],
     "sf_backward": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
@@ -200,6 +204,24 @@ class Schedule:
         _check(_lib().sf_schedule_export(self.handle, level.ctypes.data, order.ctypes.data,
                                          item_ptr.ctypes.data), "sf_schedule_export")
         return level[:n], order[:nids], item_ptr
+
+    def static_info(self, plan: int) -> dict:
+        """Sizes of a static plan (SF_STATIC_MSP or SF_STATIC_WAVEFRONT)."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(_lib().sf_schedule_static_info(self.handle, plan, *[ctypes.byref(x) for x in v]),
+               "sf_schedule_static_info")
+        keys = ("n_spart", "n_wpart", "n_batches", "merged", "slack_moved")
+        return {k: int(x.value) for k, x in zip(keys, v)}
+
+    def export_static(self, plan: int):
+        """(s_ptr, w_ptr, order) of a static plan as numpy arrays."""
+        inf = self.static_info(plan)
+        s_ptr = np.empty(inf["n_spart"] + 1, np.int32)
+        w_ptr = np.empty(inf["n_wpart"] + 1, np.int32)
+        order = np.empty(max(self.n + self.m, 1), np.int32)
+        _check(_lib().sf_schedule_export_static(self.handle, plan, s_ptr.ctypes.data, w_ptr.ctypes.data,
+                                                order.ctypes.data), "sf_schedule_export_static")
+        return s_ptr, w_ptr, order[:self.n + self.m]
 
     def export_local(self):
         """(local_level[ids], entry_slot[nnz(L)]) of the exported plan: each
@@ -336,6 +358,24 @@ def trsv_spmv(sched: Schedule, L_val, A_val, B, *, X=None, Y=None, want_y=True, 
     _check(fn(sched.handle, dt, L_val.data_ptr(), _ptr(A_val), bp, ldb, k, xp, ldx, yp, ldy,
               _stream(stream)), "sf_exec_trsv_spmv")
     return X, (Y if want_y else None)
+
+
+def static_trsv_spmv(sched: Schedule, plan: int, L_val, A_val, b, *, X=None, Y=None, stream=None):
+    """x = L^{-1} b, y = A x (one right-hand side) under a static plan:
+    SF_STATIC_MSP (the paper's fused partitioning) or SF_STATIC_WAVEFRONT."""
+    n, m = sched.n, sched.m
+    bp, _, k = _vec_ptr(b, n, "b")
+    if k != 1:
+        raise ValueError("static plans take one right-hand side")
+    if X is None:
+        X = colmajor(n, 1, L_val.dtype, L_val.device)
+    if Y is None:
+        Y = colmajor(m, 1, L_val.dtype, L_val.device)
+    xp, _, _ = _vec_ptr(X, n, "X")
+    yp, _, _ = _vec_ptr(Y, m, "Y")
+    _check(_lib().sf_exec_static_trsv_spmv(sched.handle, plan, _dtype_code(L_val), L_val.data_ptr(),
+                                           _ptr(A_val), bp, xp, yp, _stream(stream)), "sf_exec_static_trsv_spmv")
+    return X, Y
 
 
 def spmv_trsv(sched: Schedule, A_val, L_val, x, *, Y=None, Z=None, want_y=True, stream=None, unfused=False):

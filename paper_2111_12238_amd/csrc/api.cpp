@@ -69,8 +69,11 @@ void free_device(sf_schedule_s* s) {
     if (d.state) hipFree(d.state);
     if (d.xi) hipFree(d.xi);
     if (d.units) hipFree(d.units);
+    for (StaticPlan* P : {&s->msp, &s->wavefront})
+      if (P->dev) hipFree(P->dev);
     hipSetDevice(cur);
   }
+  for (StaticPlan* P : {&s->msp, &s->wavefront}) P->dev = nullptr;
   d = DeviceBuffers();
 }
 
@@ -796,6 +799,88 @@ sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, co
   return exec_ts_fused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
 }
 
+// ---- static plans: the paper's fused partitioning (MSP) and the fused
+// wavefront baseline, run by one cooperative launch with a grid barrier
+// between s-partitions (static_plan.cpp, k_static)
+
+sf_status static_dev(sf_schedule_s* s, StaticPlan& P, hipStream_t st) {
+  if (P.dev) return SF_OK;
+  const size_t N = P.order.size();
+  const size_t parts[5] = {N, 2 * N, P.s_ptr.size(), P.w_batch.size(), P.batch_ptr.size()};
+  size_t total = 0;
+  for (size_t c : parts) total += align256(std::max<size_t>(c, 1) * 4);
+  SF_HIP(hipStreamSynchronize(st));
+  SF_HIP(hipMalloc(&P.dev, total));
+  char* b = static_cast<char*>(P.dev);
+  int32_t** dst[5] = {&P.d_order, &P.d_qrng, &P.d_s_ptr, &P.d_w_batch, &P.d_batch_ptr};
+  const std::vector<int32_t>* src[5] = {&P.order, &P.qrng, &P.s_ptr, &P.w_batch, &P.batch_ptr};
+  for (int k = 0; k < 5; ++k) {
+    *dst[k] = reinterpret_cast<int32_t*>(b);
+    if (!src[k]->empty()) SF_HIP(hipMemcpy(b, src[k]->data(), src[k]->size() * 4, hipMemcpyHostToDevice));
+    b += align256(std::max<size_t>(parts[k], 1) * 4);
+  }
+  (void)s;
+  return SF_OK;
+}
+
+sf_status sf_schedule_static_info(sf_schedule s, int32_t plan, int32_t* n_spart, int32_t* n_wpart,
+                                  int32_t* n_batches, int32_t* merged, int32_t* slack_moved) {
+  if (!s || s->kind != SF_TRSV_SPMV || (plan != SF_STATIC_MSP && plan != SF_STATIC_WAVEFRONT)) return SF_ERR_ARG;
+  sf_status r = build_static(s, plan);
+  if (r != SF_OK) return r;
+  const StaticPlan& P = static_plan(s, plan);
+  if (n_spart) *n_spart = int32_t(P.s_ptr.size()) - 1;
+  if (n_wpart) *n_wpart = int32_t(P.w_ptr.size()) - 1;
+  if (n_batches) *n_batches = int32_t(P.batch_ptr.size()) - 1;
+  if (merged) *merged = P.merged;
+  if (slack_moved) *slack_moved = P.slack_moved;
+  return SF_OK;
+}
+
+sf_status sf_schedule_export_static(sf_schedule s, int32_t plan, int32_t* s_ptr, int32_t* w_ptr, int32_t* order) {
+  if (!s || s->kind != SF_TRSV_SPMV || (plan != SF_STATIC_MSP && plan != SF_STATIC_WAVEFRONT)) return SF_ERR_ARG;
+  sf_status r = build_static(s, plan);
+  if (r != SF_OK) return r;
+  const StaticPlan& P = static_plan(s, plan);
+  if (s_ptr) std::copy(P.s_ptr.begin(), P.s_ptr.end(), s_ptr);
+  if (w_ptr) std::copy(P.w_ptr.begin(), P.w_ptr.end(), w_ptr);
+  if (order) std::copy(P.order.begin(), P.order.end(), order);
+  return SF_OK;
+}
+
+sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, const void* L_val,
+                                   const void* A_val, const void* B, void* X, void* Y, void* stream) {
+  if (!s || s->kind != SF_TRSV_SPMV || (plan != SF_STATIC_MSP && plan != SF_STATIC_WAVEFRONT)) return SF_ERR_ARG;
+  if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (!L_val || !B || !X || !Y || (s->m > 0 && !A_val) || B == X) return SF_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  sf_status r = upload(s, st);
+  if (r == SF_OK) r = build_static(s, plan);
+  StaticPlan& P = static_plan(s, plan);
+  if (r == SF_OK) r = static_dev(s, P, st);
+  if (r != SF_OK) return r;
+  const int dt = dtype == SF_F64 ? 0 : 1;
+  StaticArgs a{};
+  a.ts = ts_args(s, L_val, A_val, B, int32_t(s->n), 1, X, int32_t(s->n), Y, int32_t(std::max<int64_t>(s->m, 1)));
+  a.ts.order = P.d_order;
+  a.ts.qrng = P.d_qrng;
+  a.ts.item_ptr = nullptr;
+  a.ts.item_list = nullptr;
+  a.ts.kb = 1;
+  a.ts.nblk = 1;
+  a.s_ptr = P.d_s_ptr;
+  a.w_batch = P.d_w_batch;
+  a.batch_ptr = P.d_batch_ptr;
+  a.nb = int32_t(P.s_ptr.size()) - 1;
+  r = next_epoch(s, st, a.ts.ls);
+  if (r != SF_OK) return r;
+  const int cus = std::max(1, device_cus());
+  const int grid = cus * std::min(occupancy_static(dt), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  Timer tm(s, st);
+  return hip_status(launch_static(a, dt, grid, st));
+}
+
 sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
                                     const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
                                     void* Y, int32_t ldy, void* stream) {
@@ -1223,6 +1308,16 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "multi_waves_per_cu") {
     if (v != 0 && (v < 4 || v > 32)) return SF_ERR_ARG;
     s->multi_waves_per_cu = int32_t(v);
+  } else if (k == "msp_parts") {
+    if (v < 1 || v > (int64_t(1) << 20)) return SF_ERR_ARG;
+    if (s->msp_parts != int32_t(v)) {
+      s->msp_parts = int32_t(v);
+      if (s->msp.dev) {
+        hipDeviceSynchronize();
+        hipFree(s->msp.dev);
+      }
+      s->msp = StaticPlan();
+    }
   } else if (k == "spin_limit") {
     if (v < 1) return SF_ERR_ARG;
     s->spin_limit = v;
@@ -1271,6 +1366,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "waves_per_cu") *v = s->waves_per_cu;
   else if (k == "multi_waves_per_cu") *v = s->multi_waves_per_cu;
   else if (k == "spin_limit") *v = s->spin_limit;
+  else if (k == "msp_parts") *v = s->msp_parts;
   else if (k == "claim_streams") *v = s->claim_streams;
   else if (k == "rows_per_item") *v = s->rows_per_item;
   else if (k == "max_item_nnz") *v = s->max_item_nnz;

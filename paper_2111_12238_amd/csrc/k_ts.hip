@@ -414,6 +414,36 @@ __global__ __launch_bounds__(kBlockThreads) void k_trsv_levelset(LevelArgs la) {
   }
 }
 
+// ------------------------------------------------------ static plans ----
+// The paper's own schedule form (Sec. 3): a fused partitioning whose
+// s-partitions are separated by a grid barrier and whose w-partitions each
+// run on one wavefront, its rows in order (or the fused wavefront baseline,
+// one s-partition per wavefront of the joint DAG).  x is read and written
+// device-coherently, as in the level set; a wavefront waits for its own
+// stores before the next batch of its w-partition, which may read them.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void k_static(StaticArgs sa) {
+  __shared__ WaveLds<T> lds[kWaves];
+  const TsArgs& a = sa.ts;
+  const int lane = threadIdx.x & 63;
+  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  dev::reset_next_launch(a.ls);
+  const int wave = int(blockIdx.x) * kWaves + int(threadIdx.x >> 6);
+  const int nwaves = int(gridDim.x) * kWaves;
+  int32_t gen = 0;
+  for (int b = 0; b < sa.nb; ++b) {
+    for (int wp = sa.s_ptr[b] + wave; wp < sa.s_ptr[b + 1]; wp += nwaves) {
+      for (int bt = sa.w_batch[wp]; bt < sa.w_batch[wp + 1]; ++bt) {
+        const int q0 = sa.batch_ptr[bt], q1 = sa.batch_ptr[bt + 1];
+        if (a.order[q0] < a.n) item_stream<T, true, 1>(a, q0, q1, lane, w);
+        else item_stream<T, false, 1>(a, q0, q1, lane, w);
+        dev::stores_complete();
+      }
+    }
+    if (b + 1 < sa.nb) dev::grid_barrier(a.ls, gen);
+  }
+}
+
 // SpMV items (all inputs final), grid-stride over the item list.
 template <typename T>
 __global__ __launch_bounds__(kBlockThreads) void k_spmv_items(TsArgs a) {
@@ -552,6 +582,15 @@ hipError_t launch_spmv(const SpmvArgs& a, int dtype, hipStream_t st) {
   grid = grid < 1 ? 1 : (grid > cu_count() * 32 ? cu_count() * 32 : grid);
   return dtype == 0 ? spmv_multi_dispatch<double>(a, int(grid), st) : spmv_multi_dispatch<float>(a, int(grid), st);
 }
+hipError_t launch_static(const StaticArgs& a, int dtype, int grid, hipStream_t st) {
+  if (!a.ts.order || !a.ts.qrng || !a.s_ptr || !a.w_batch || !a.batch_ptr || a.nb < 0) return hipErrorInvalidValue;
+  if (a.nb == 0) return hipSuccess;
+  void* args[] = {const_cast<StaticArgs*>(&a)};
+  const void* fn = dtype == 0 ? reinterpret_cast<const void*>(&k_static<double>)
+                              : reinterpret_cast<const void*>(&k_static<float>);
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlockThreads), args, 0, st);
+}
+int occupancy_static(int dtype) { return dtype == 0 ? occ(k_static<double>) : occ(k_static<float>); }
 hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st) {
   if (count == 0) return hipSuccess;
   size_t g = (count + 255) / 256;

@@ -53,6 +53,17 @@ struct LevelArgs {
   int32_t depth;
 };
 
+// Static two-level plan (static_plan.cpp): the s-partitions run in sequence
+// with a grid barrier between them, the w-partitions of one s-partition are
+// spread over the grid, and a w-partition's batches (runs of up to 64 rows
+// of one kind and one wavefront; ts.order / ts.qrng are the plan's) run in
+// order.
+struct StaticArgs {
+  TsArgs ts;
+  const int32_t *s_ptr, *w_batch, *batch_ptr;
+  int32_t nb;
+};
+
 // Standalone CSR SpMV over interleaved blocks (multi-RHS baseline):
 // Y = A X, X of n rows and Y of m rows, nblk blocks of kb columns each.
 struct SpmvArgs {
@@ -147,6 +158,8 @@ hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream
 int occupancy_pair(int dtype, int mode);
 hipError_t launch_trsv_levelset(const LevelArgs& a, int dtype, int grid, hipStream_t st);  // kb = a.ts.kb
 hipError_t launch_spmv(const SpmvArgs& a, int dtype, hipStream_t st);
+hipError_t launch_static(const StaticArgs& a, int dtype, int grid, hipStream_t st);
+int occupancy_static(int dtype);
 // SpMV items of a schedule (a.item_list / a.n_work), all inputs final.
 hipError_t launch_spmv_items(const TsArgs& a, int dtype, hipStream_t st);
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st);

@@ -73,6 +73,28 @@ struct DeviceBuffers {
   uint32_t epoch = 0;
 };
 
+// Static two-level plan of the SpTRSV -> SpMV pair (static_plan.cpp): the
+// paper's fused partitioning (Sec. 3) or the fused-wavefront baseline.  The
+// s-partitions run in sequence with a grid barrier between them; the
+// w-partitions of one s-partition are independent; the rows of one
+// w-partition run in order, cut into batches of up to 64 rows of one kind
+// and one wavefront for the executor.
+struct StaticPlan {
+  bool built = false;
+  int32_t parts = 0;                // requested w-partitions per s-partition (MSP's r)
+  std::vector<int32_t> s_ptr;       // nb + 1: w-partitions of each s-partition
+  std::vector<int32_t> w_ptr;       // nw + 1: positions of each w-partition
+  std::vector<int32_t> order;       // n + m iteration ids (as the joint order)
+  std::vector<int32_t> w_batch;     // nw + 1: batches of each w-partition
+  std::vector<int32_t> batch_ptr;   // nbatch + 1: positions of each batch
+  std::vector<int32_t> qrng;        // 2 (n + m): CSR range per position (as qrng)
+  int32_t merged = 0;               // pair partitions merged (MSP)
+  int32_t slack_moved = 0;          // slack rows placed by balancing (MSP)
+  void* dev = nullptr;              // device copy: order | qrng | s_ptr | w_batch | batch_ptr
+  int32_t *d_order = nullptr, *d_qrng = nullptr, *d_s_ptr = nullptr, *d_w_batch = nullptr,
+          *d_batch_ptr = nullptr;
+};
+
 }  // namespace sf
 
 struct sf_schedule_s {
@@ -153,6 +175,11 @@ struct sf_schedule_s {
   double last_kernel_ms = -1.0;
   double reuse = 0.0, inspect_seconds = 0.0;
 
+  // static plans (SF_TRSV_SPMV): the paper's MSP partitioning and the fused
+  // wavefront baseline, built on first use
+  sf::StaticPlan msp, wavefront;
+  int32_t msp_parts = 1024;
+
   sf::DeviceBuffers dev;
 };
 
@@ -168,5 +195,8 @@ sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* L, const sf_csr
 void cut_items(sf_schedule_s* s);
 // Check every DAG edge of the built forward schedule (0 = valid).
 int validate_forward(const sf_schedule_s* s);
+// Static plans (static_plan.cpp); host only.  plan 0: MSP, 1: fused wavefront.
+sf_status build_static(sf_schedule_s* s, int plan);
+StaticPlan& static_plan(sf_schedule_s* s, int plan);
 
 }  // namespace sf

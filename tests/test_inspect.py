@@ -398,3 +398,81 @@ def test_rhs_block_must_be_a_kernel_width():
         assert _err(lambda: s.set_param("rhs_block", bad)) == "SF_ERR_ARG", bad
     s.set_param("rhs_block", 16)
     assert s.get_param("rhs_block") == 16
+
+
+def _static_cases(name):
+    import scipy.sparse as sp
+    if name == "random":
+        L = synth.random_lower(3001, 0.003, seed=5)
+        A = synth.from_scipy(sp.random(2000, 3001, density=0.002, random_state=np.random.default_rng(2),
+                                       format="csr"))
+        return L, A
+    if name == "chains":  # 8 independent bidiagonal chains of 50 rows
+        blk = sp.diags([np.full(49, -1.0), np.full(50, 2.0)], [-1, 0])
+        L = synth.from_scipy(sp.block_diag([blk] * 8, format="csr"))
+        return L, synth.from_scipy(sp.identity(400, format="csr"))
+    if name == "empty_rows":  # SpMV rows without entries
+        L, A = synth.workload("lap2d5_16")
+        a = A.to_scipy().tolil()
+        a[3, :] = 0
+        a[100, :] = 0
+        return L, synth.from_scipy(a.tocsr())
+    return synth.workload(name)
+
+
+@pytest.mark.parametrize("case", ["lap2d5_64", "random", "chains", "empty_rows"])
+def test_static_plans_respect_every_edge(orc, case):
+    """Both static plans -- the paper's fused partitioning and the fused
+    wavefront -- pass the oracle's two-level schedule check (every vertex
+    once; every edge across s-partitions or in order inside one
+    w-partition). The wavefront plan has one s-partition per wavefront of
+    the joint DAG, w-partitions of at most 64 rows of one kind and level."""
+    L, A = _static_cases(case)
+    s = sfm.Schedule(L, A)
+    n = L.nrows
+    for plan in (sfm.SF_STATIC_MSP, sfm.SF_STATIC_WAVEFRONT):
+        s_ptr, w_ptr, order = s.export_static(plan)
+        assert orc.validate_static_ts(L.rowptr, L.col, A.rowptr, A.col, s_ptr, w_ptr, order) == 0, plan
+    s_ptr, w_ptr, order = s.export_static(sfm.SF_STATIC_WAVEFRONT)
+    lv, _ = orc.levels(L.rowptr, L.col)
+    ready = orc.spmv_ready(A.rowptr, A.col, lv)
+    joint = np.concatenate([lv, ready])
+    assert len(s_ptr) - 1 == len(np.unique(joint))
+    for w in range(len(w_ptr) - 1):
+        ids = order[w_ptr[w]:w_ptr[w + 1]]
+        assert 1 <= len(ids) <= 64 and len(np.unique(joint[ids])) == 1 and len(np.unique(ids < n)) == 1
+
+
+def test_msp_windows_and_pairs(orc):
+    """MSP on independent chains: every wavefront keeps the same 8
+    components, so one window takes them all and each chain runs on one
+    w-partition. Each chain's SpMV rows form its pair partition, and both
+    sides have slack 0 (the chain is the critical path), so the merge step
+    puts the pair after the chain in its w-partition: one s-partition, no
+    barrier. With r = 1 the window puts all chains on one w-partition.
+    On a 2D 5-point grid one more wavefront joins every piece, so each
+    window is one wavefront (as many s-partitions as the level-set)."""
+    L, A = _static_cases("chains")
+    s = sfm.Schedule(L, A)
+    s_ptr, w_ptr, order = s.export_static(sfm.SF_STATIC_MSP)
+    assert len(s_ptr) - 1 == 1 and s.static_info(sfm.SF_STATIC_MSP)["merged"] == 8
+    for w in range(s_ptr[0], s_ptr[1]):
+        ids = order[w_ptr[w]:w_ptr[w + 1]]
+        # one whole chain in order, then its SpMV rows in order
+        c = ids[0] // 50
+        want = np.concatenate([np.arange(50 * c, 50 * c + 50), 400 + np.arange(50 * c, 50 * c + 50)])
+        assert np.array_equal(ids, want)
+    s.set_param("msp_parts", 1)
+    assert s.get_param("msp_parts") == 1
+    s_ptr, w_ptr, order = s.export_static(sfm.SF_STATIC_MSP)
+    assert s_ptr[1] - s_ptr[0] == 1
+    assert orc.validate_static_ts(L.rowptr, L.col, A.rowptr, A.col, s_ptr, w_ptr, order) == 0
+    L, A = synth.workload("lap2d5_64")
+    s = sfm.Schedule(L, A)
+    info = s.static_info(sfm.SF_STATIC_MSP)
+    assert info["n_spart"] == s.info().depth + 1 and info["slack_moved"] > 0
+    with pytest.raises(sfm.SparseFusionError):
+        s.set_param("msp_parts", 0)
+    lt = sfm.Schedule(L, None, sfm.SF_IC0_TRSV)
+    with pytest.raises(sfm.SparseFusionError):
+        lt.static_info(sfm.SF_STATIC_MSP)
