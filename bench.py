@@ -336,6 +336,25 @@ def run_extras(args, sfm, synth, torch, dev, stream):
         log("ic_apply %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
         sfm.sync_status(sb)
         del sb
+        # the paper's static schedules on the same pair: its fused partitioning
+        # (MSP) and the fused wavefront, one grid barrier per s-partition
+        B = torch.as_tensor(synth.vec_uniform(L.nrows, seed=1), device=dev)
+        Yt = torch.empty(A.nrows, dtype=B.dtype, device=dev)
+        nb = ts_bytes(L.nrows, A.nrows, L.nnz, A.nnz)
+        res = {"dynamic_fused_ms": round(time_it(lambda: sfm.trsv_spmv(s, Lv, Av, B, X=Z, Y=Yt), reps), 4),
+               "bytes": nb}
+        for plan, tag in ((sfm.SF_STATIC_MSP, "msp"), (sfm.SF_STATIC_WAVEFRONT, "wavefront")):
+            t = time_it(lambda: sfm.static_trsv_spmv(s, plan, Lv, Av, B, X=Z, Y=Yt), reps)
+            info = s.static_info(plan)
+            res[tag + "_ms"] = round(t, 4)
+            res[tag + "_s_partitions"] = info["n_spart"]
+            res[tag + "_w_partitions"] = info["n_wpart"]
+            res[tag + "_GBps"] = round(nb / (t * 1e-3) / 1e9, 1)
+        res["dynamic_vs_msp_speedup"] = round(res["msp_ms"] / res["dynamic_fused_ms"], 3)
+        out["static_plans_%s" % name] = res
+        sfm.sync_status(s)
+        log("static plans %s: msp %.3f ms (%d s-partitions), wavefront %.3f ms, dynamic %.3f ms" % (
+            name, res["msp_ms"], res["msp_s_partitions"], res["wavefront_ms"], res["dynamic_fused_ms"]))
     L, A = synth.workload("lap3d7_96")
     s = sfm.Schedule(L, A, want_backward=True)
     for dt, tname, vb in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
