@@ -96,7 +96,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oATrp = pk.add(&s->AT.rp), oATci = pk.add(&s->AT.ci), oATm = pk.add(&s->AT_map);
   const size_t oBo = pk.add(&s->border), oBip = pk.add(&s->bitem_ptr);
   const size_t oPp = pk.add(&s->pair_ptr), oPu = pk.add(&s->pair_u), oPq = pk.add(&s->pair_q);
-  const size_t oDp = pk.add(&s->dpos);
+  const size_t oDp = pk.add(&s->dpos), oPr = pk.add(&s->prng), oPv = pk.add(&s->piv);
   const size_t oCo = pk.add(&s->corder), oCip = pk.add(&s->citem_ptr), oCti = pk.add(&s->ctrsv_items);
   const size_t oCl = pk.add(&s->clloc), oCe = pk.add(&s->celoc);
   const size_t oQr = pk.add(&s->qrng), oCqr = pk.add(&s->cqrng);
@@ -122,6 +122,8 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.border = P(oBo); d.bitem_ptr = P(oBip);
   d.pair_ptr = P(oPp); d.pair_u = P(oPu); d.pair_q = P(oPq);
   d.dpos = P(oDp);
+  d.prng = P(oPr);
+  d.piv = P(oPv);
   d.corder = P(oCo); d.citem_ptr = P(oCip); d.ctrsv_items = P(oCti);
   d.clloc = reinterpret_cast<uint8_t*>(b + oCl);
   d.celoc = reinterpret_cast<uint8_t*>(b + oCe);
@@ -920,6 +922,9 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   a.pair_ptr = d.pair_ptr;
   a.pair_u = d.pair_u;
   a.pair_q = d.pair_q;
+  a.qrng = d.qrng;
+  a.prng = d.prng;
+  a.piv = d.piv;
   a.order = d.order;
   a.item_ptr = d.item_ptr;
   a.d_info = d_info;

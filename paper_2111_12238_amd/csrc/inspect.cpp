@@ -484,8 +484,18 @@ void cut_items(sf_schedule_s* s) {
     cut_runs(s->order, key, cost, std::min(s->rows_per_item, per_batch), s->max_item_nnz, s->item_ptr);
     s->trsv_items.clear();
     for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) s->trsv_items.push_back(int32_t(t));
-    if (s->kind == SF_IC0_TRSV) position_ranges(s, s->order, s->qrng);  // the unfused baseline's level-set solve
-    else s->qrng.clear();
+    if (s->kind == SF_IC0_TRSV) {
+      position_ranges(s, s->order, s->qrng);
+      s->prng.resize(2 * s->order.size());
+      for (size_t q = 0; q < s->order.size(); ++q) {
+        const int32_t i = s->order[q];
+        s->prng[2 * q] = s->pair_ptr[size_t(s->L.rp[i])];
+        s->prng[2 * q + 1] = s->pair_ptr[size_t(s->L.rp[i + 1] - 1)];
+      }
+    } else {
+      s->qrng.clear();
+      s->prng.clear();
+    }
   }
   // Level-set baseline: the SpTRSV items grouped by level.  Items are
   // level-pure, and in claim order the levels ascend.
@@ -526,10 +536,12 @@ static void build_pairs(sf_schedule_s* s) {
   s->pair_ptr.assign(size_t(nnz) + 1, 0);
   s->pair_u.clear();
   s->pair_q.clear();
+  s->piv.assign(size_t(nnz), -1);
   for (int32_t i = 0; i < L.nrows; ++i) {
     const int32_t r0 = L.rp[i], rd = L.rp[i + 1] - 1;
     for (int32_t p = r0; p < rd; ++p) {
       const int32_t j = L.ci[p];
+      s->piv[size_t(p)] = L.rp[j + 1] - 1;  // the pivot L_jj closes row j
       int32_t pi = r0, pj = L.rp[j];
       const int32_t ej = L.rp[j + 1] - 1;  // row j's off-diagonals end here
       while (pi < p && pj < ej) {

@@ -50,8 +50,15 @@ __device__ __forceinline__ bool is_absent(double v) {
 // Pairs gathered per lane and round: kPairRegs per lane, G lanes per row.
 constexpr int kPairRegs = 8;
 
+// The row, its entry range and its pair range come with the claim position
+// and each entry's pivot position with the entry (qrng, prng, piv), so a
+// batch issues its index loads in two dependent rounds.  next / next_rg:
+// the fused executor's next item, whose range is loaded here once its
+// ticket has arrived (it returns before the loads above) and used after
+// this item.
 template <int G, bool FUSED>
-__device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* lds_row) {
+__device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* lds_row,
+                                         int next = -1, int2* next_rg = nullptr) {
   constexpr int RPB = 64 / G;
   const int sub = lane & (G - 1);
   const int32_t par = a.ls.epoch & 1;
@@ -59,15 +66,17 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     const int q = base + lane / G;
     const bool act = q < q1;
     const int i = act ? a.order[q] : 0;
-    const int r0 = act ? a.Lrp[i] : 0;
-    const int rd = act ? a.Lrp[i + 1] - 1 : 0;  // diagonal position
+    const int2 rg = act ? reinterpret_cast<const int2*>(a.qrng)[q] : make_int2(0, 0);
+    // the pairs of row i are contiguous: every entry's list, in entry order
+    const int2 pr = act ? reinterpret_cast<const int2*>(a.prng)[q] : make_int2(0, 0);
+    if (next_rg && base == q0) *next_rg = next >= 0 ? make_int2(a.item_ptr[next], a.item_ptr[next + 1]) : make_int2(0, 0);
+    const int r0 = rg.x, rd = rg.y;              // off-diagonals [r0, rd); the diagonal at rd
     const int len = rd - r0;                     // off-diagonal entries (<= G)
     const bool mine = act && sub < len;
     const int p = r0 + sub;
     const int j = mine ? a.Lci[p] : 0;
-    const int pjj = mine ? a.Lrp[j + 1] - 1 : 0;
-    // the pairs of row i are contiguous: every entry's list, in entry order
-    const int e0 = act ? a.pair_ptr[r0] : 0, e1 = act ? a.pair_ptr[rd] : 0;
+    const int pjj = mine ? a.piv[p] : 0;
+    const int e0 = pr.x, e1 = pr.y;
     double acc = mine ? a.Aval[p] : 0.0;
     // M[t][u] = L_{j_t, k_u} where row j_t meets row i below column j_t, else absent
     for (int u = 0; u < G; ++u) lds_row[u] = kAbsent;
@@ -156,12 +165,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
   const int lane = threadIdx.x & 63;
   double* lds_row = lds + size_t(threadIdx.x) * G;
   dev::reset_next_launch(a.ls);
+  // every item, in claim order (no item list): the next ticket is claimed
+  // before an item runs and its range loaded inside it (see ic0_rows)
   int t = dev::claim(a.ls, lane);
+  int2 rg = t < a.n_work ? make_int2(a.item_ptr[t], a.item_ptr[t + 1]) : make_int2(0, 0);
   while (t < a.n_work) {
-    const int tn = dev::claim(a.ls, lane);  // prefetched (see k_ts_fused)
-    const int it = a.item_list ? a.item_list[t] : t;
-    ic0_rows<G, true>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, lds_row);
+    const int tn = dev::claim(a.ls, lane);
+    int2 rgn;
+    ic0_rows<G, true>(a, rg.x, rg.y, lane, lds_row, tn < a.n_work ? tn : -1, &rgn);
     t = tn;
+    rg = rgn;
   }
   write_info(a, lane);
 }
@@ -197,6 +210,8 @@ int occ(K kernel, size_t lds) {
 }  // namespace
 
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
+  if (!a.order || !a.item_ptr || a.item_list || !a.qrng || !a.prng || !a.piv || !a.pair_u || !a.pair_q)
+    return hipErrorInvalidValue;
   const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
 #define SF_IC(G)                                                                    \
   if (g == G) {                                                                     \
@@ -209,6 +224,8 @@ hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
 }
 
 hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st) {
+  if (!a.order || !a.item_ptr || !a.item_list || !a.lvl_item_ptr || !a.qrng || !a.prng || !a.piv)
+    return hipErrorInvalidValue;
   const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
   void* args[] = {const_cast<Ic0Args*>(&a)};
 #define SF_IL(G)                                                                               \

@@ -85,7 +85,9 @@ struct Ic0Args {
   const int32_t *pair_ptr, *pair_u, *pair_q;
   const int32_t* dpos;     // SpILU0: diagonal position of each row (nullptr for SpIC0)
   const int32_t *order, *item_ptr, *item_list;
-  const int2* unit_rng;    // multi-RHS: claim-position range of each unit (replaces item_ptr / item_list)
+  const int32_t* qrng;     // SpIC0: per claim position, the row's off-diagonal range (diagonal at its end)
+  const int32_t* prng;     // SpIC0: per claim position, the row's range of intersection pairs
+  const int32_t* piv;      // SpIC0: per stored entry (i, j), the position of L_jj
   int32_t n_work;
   const int32_t* lvl_item_ptr;  // level-set variant
   int32_t depth;

@@ -57,6 +57,7 @@ struct DeviceBuffers {
   uint8_t *bclloc = nullptr, *bceloc = nullptr;
   // SpIC0 intersection lists
   int32_t *pair_ptr = nullptr, *pair_u = nullptr, *pair_q = nullptr;
+  int32_t *prng = nullptr, *piv = nullptr;
   int32_t* dpos = nullptr;          // SpILU0: diagonal position of each row
   // mutable state
   int32_t* state = nullptr;
@@ -155,6 +156,10 @@ struct sf_schedule_s {
   // index inside row i of a column k in both rows with k < j, q = position
   // of L_jk.  The lists of a row's entries are contiguous, in entry order.
   std::vector<int32_t> pair_ptr, pair_u, pair_q;
+  // SF_IC0_TRSV: per claim position the range of the row's pairs (as qrng
+  // gives its entries), and per stored entry (i, j), j < i, the position of
+  // the pivot L_jj, so a batch's loads need no row-pointer round trips.
+  std::vector<int32_t> prng, piv;
   // SF_ILU0_TRSV: the pattern of A is held in L; dpos[i] is the position of
   // row i's diagonal.  Pairs then follow build_pairs_ilu (inspect.cpp).
   std::vector<int32_t> dpos;
