@@ -56,11 +56,19 @@ constexpr int kPairRegs = 8;
 // the fused executor's next item, whose range is loaded here once its
 // ticket has arrived (it returns before the loads above) and used after
 // this item.
+// LDS: the rows of one batch row's G lanes form a triangle -- lane t keeps
+// M[t][u] for u < t only (a pair's matching entry precedes its own entry) --
+// of G (G - 1) / 2 doubles, at group_lds.
+template <int G>
+constexpr int tri_size() { return G * (G - 1) / 2; }
+__device__ __forceinline__ int tri_row(int t) { return t * (t - 1) / 2; }
+
 template <int G, bool FUSED>
-__device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* lds_row,
+__device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* group_lds,
                                          int next = -1, int2* next_rg = nullptr) {
   constexpr int RPB = 64 / G;
   const int sub = lane & (G - 1);
+  double* lds_row = group_lds + tri_row(sub);
   const int32_t par = a.ls.epoch & 1;
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / G;
@@ -79,9 +87,9 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     const int e0 = pr.x, e1 = pr.y;
     double acc = mine ? a.Aval[p] : 0.0;
     // M[t][u] = L_{j_t, k_u} where row j_t meets row i below column j_t, else absent
-    for (int u = 0; u < G; ++u) lds_row[u] = kAbsent;
+    for (int u = 0; u < G; ++u)
+      if (u < sub) lds_row[u] = kAbsent;
     __builtin_amdgcn_wave_barrier();
-    double* group_rows = lds_row - size_t(sub) * G;  // LDS rows of this row's G lanes
     // Rounds of kPairRegs pairs per lane; the pivot L_jj and x_j of the
     // lane's entry ride along in the first round.  Every load of a round is
     // issued before any is waited on.
@@ -107,7 +115,7 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
       if constexpr (FUSED) dev::wait_ptrs<double, R>(ptr, v, lane, a.ls);
 #pragma unroll
       for (int k = 0; k < kPairRegs; ++k)
-        if (tu[k] >= 0) group_rows[size_t(tu[k] >> 16) * G + (tu[k] & 0xffff)] = v[k];
+        if (tu[k] >= 0) group_lds[tri_row(tu[k] >> 16) + (tu[k] & 0xffff)] = v[k];
       if (rnd == 0 && mine) {
         djj = v[kPairRegs];
         if (a.solve) xj = v[kPairRegs + 1];
@@ -163,7 +171,7 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  double* lds_row = lds + size_t(threadIdx.x) * G;
+  double* group_lds = lds + size_t(threadIdx.x / G) * tri_size<G>();
   dev::reset_next_launch(a.ls);
   // every item, in claim order (no item list): the next ticket is claimed
   // before an item runs and its range loaded inside it (see ic0_rows)
@@ -172,7 +180,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
   while (t < a.n_work) {
     const int tn = dev::claim(a.ls, lane);
     int2 rgn;
-    ic0_rows<G, true>(a, rg.x, rg.y, lane, lds_row, tn < a.n_work ? tn : -1, &rgn);
+    ic0_rows<G, true>(a, rg.x, rg.y, lane, group_lds, tn < a.n_work ? tn : -1, &rgn);
     t = tn;
     rg = rgn;
   }
@@ -183,7 +191,7 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_ic0_levelset(Ic0Args a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  double* lds_row = lds + size_t(threadIdx.x) * G;
+  double* group_lds = lds + size_t(threadIdx.x / G) * tri_size<G>();
   dev::reset_next_launch(a.ls);
   const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
@@ -191,7 +199,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_ic0_levelset(Ic0Args a) {
   for (int lv = 0; lv < a.depth; ++lv) {
     for (int t = a.lvl_item_ptr[lv] + wave; t < a.lvl_item_ptr[lv + 1]; t += nwaves) {
       const int it = a.item_list[t];
-      ic0_rows<G, false>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, lds_row);
+      ic0_rows<G, false>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, group_lds);
     }
     if (lv + 1 < a.depth) dev::grid_barrier(a.ls, gen);
   }
@@ -212,7 +220,7 @@ int occ(K kernel, size_t lds) {
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
   if (!a.order || !a.item_ptr || a.item_list || !a.qrng || !a.prng || !a.piv || !a.pair_u || !a.pair_q)
     return hipErrorInvalidValue;
-  const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
 #define SF_IC(G)                                                                    \
   if (g == G) {                                                                     \
     hipLaunchKernelGGL((k_ic0_fused<G>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
@@ -226,7 +234,7 @@ hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
 hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st) {
   if (!a.order || !a.item_ptr || !a.item_list || !a.lvl_item_ptr || !a.qrng || !a.prng || !a.piv)
     return hipErrorInvalidValue;
-  const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
   void* args[] = {const_cast<Ic0Args*>(&a)};
 #define SF_IL(G)                                                                               \
   if (g == G)                                                                                  \
@@ -238,7 +246,7 @@ hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st
 }
 
 int occupancy_ic0(int g, int levelset) {
-  const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
   switch (g) {
     case 4: return levelset ? occ(k_ic0_levelset<4>, lds) : occ(k_ic0_fused<4>, lds);
     case 8: return levelset ? occ(k_ic0_levelset<8>, lds) : occ(k_ic0_fused<8>, lds);

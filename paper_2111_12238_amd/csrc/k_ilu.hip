@@ -50,10 +50,18 @@ __device__ __forceinline__ bool is_absent(double v) {
 
 constexpr int kPairRegs = 8;  // pairs gathered per lane and round
 
+// LDS: lane t keeps M[t][u] for u < t only (a pair's lower entry precedes
+// the entry it serves, entries being in column order); the G lanes of a
+// row share a triangle of G (G - 1) / 2 doubles at group_lds.
+template <int G>
+constexpr int tri_size() { return G * (G - 1) / 2; }
+__device__ __forceinline__ int tri_row(int t) { return t * (t - 1) / 2; }
+
 template <int G, bool FUSED>
-__device__ __forceinline__ void ilu_rows(const Ic0Args& a, int q0, int q1, int lane, double* lds_row) {
+__device__ __forceinline__ void ilu_rows(const Ic0Args& a, int q0, int q1, int lane, double* group_lds) {
   constexpr int RPB = 64 / G;
   const int sub = lane & (G - 1);
+  double* lds_row = group_lds + tri_row(sub);
   const int32_t par = a.ls.epoch & 1;
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / G;
@@ -70,9 +78,9 @@ __device__ __forceinline__ void ilu_rows(const Ic0Args& a, int q0, int q1, int l
     const int nlow = act ? a.dpos[i] - r0 : 0;  // lower entries of row i come first
     const int e0 = act ? a.pair_ptr[r0] : 0, e1 = act ? a.pair_ptr[r1] : 0;
     double acc = (mine && a.factor) ? a.Aval[p] : 0.0;
-    for (int u = 0; u < G; ++u) lds_row[u] = kAbsent;
+    for (int u = 0; u < G; ++u)
+      if (u < sub) lds_row[u] = kAbsent;
     __builtin_amdgcn_wave_barrier();
-    double* group_rows = lds_row - size_t(sub) * G;  // LDS rows of this row's G lanes
     int nround = a.factor ? (e1 - e0 + G * kPairRegs - 1) / (G * kPairRegs) : 0;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) nround = max(nround, __shfl_xor(nround, off, 64));
@@ -97,7 +105,7 @@ __device__ __forceinline__ void ilu_rows(const Ic0Args& a, int q0, int q1, int l
       if constexpr (FUSED) dev::wait_ptrs<double, R, 64>(ptr, v, lane, a.ls);
 #pragma unroll
       for (int k = 0; k < kPairRegs; ++k)
-        if (tu[k] >= 0) group_rows[size_t(tu[k] >> 16) * G + (tu[k] & 0xffff)] = v[k];
+        if (tu[k] >= 0) group_lds[tri_row(tu[k] >> 16) + (tu[k] & 0xffff)] = v[k];
       if (rnd == 0 && lower) {
         if (a.factor) djj = v[kPairRegs];
         else lval = v[kPairRegs];
@@ -147,13 +155,13 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_ilu0_fused(Ic0Args a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  double* lds_row = lds + size_t(threadIdx.x) * G;
+  double* group_lds = lds + size_t(threadIdx.x / G) * tri_size<G>();
   dev::reset_next_launch(a.ls);
   int t = dev::claim(a.ls, lane);
   while (t < a.n_work) {
     const int tn = dev::claim(a.ls, lane);  // prefetched (see k_ts_fused)
     const int it = a.item_list ? a.item_list[t] : t;
-    ilu_rows<G, true>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, lds_row);
+    ilu_rows<G, true>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, group_lds);
     t = tn;
   }
   write_info(a, lane);
@@ -163,7 +171,7 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_ilu0_levelset(Ic0Args a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  double* lds_row = lds + size_t(threadIdx.x) * G;
+  double* group_lds = lds + size_t(threadIdx.x / G) * tri_size<G>();
   dev::reset_next_launch(a.ls);
   const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
@@ -171,7 +179,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_ilu0_levelset(Ic0Args a) {
   for (int lv = 0; lv < a.depth; ++lv) {
     for (int t = a.lvl_item_ptr[lv] + wave; t < a.lvl_item_ptr[lv + 1]; t += nwaves) {
       const int it = a.item_list[t];
-      ilu_rows<G, false>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, lds_row);
+      ilu_rows<G, false>(a, a.item_ptr[it], a.item_ptr[it + 1], lane, group_lds);
     }
     if (lv + 1 < a.depth) dev::grid_barrier(a.ls, gen);
   }
@@ -191,7 +199,7 @@ int occ(K kernel, size_t lds) {
 
 hipError_t launch_ilu0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
   if (!a.dpos || !a.order || !a.item_ptr || !a.pair_ptr) return hipErrorInvalidValue;
-  const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
 #define SF_IL(G)                                                                     \
   if (g == G) {                                                                      \
     hipLaunchKernelGGL((k_ilu0_fused<G>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
@@ -205,7 +213,7 @@ hipError_t launch_ilu0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) 
 hipError_t launch_ilu0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st) {
   if (!a.dpos || !a.order || !a.item_ptr || !a.pair_ptr || !a.item_list || !a.lvl_item_ptr)
     return hipErrorInvalidValue;
-  const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
   void* args[] = {const_cast<Ic0Args*>(&a)};
 #define SF_IL(G)                                                                                \
   if (g == G)                                                                                   \
@@ -217,7 +225,7 @@ hipError_t launch_ilu0_levelset(const Ic0Args& a, int g, int grid, hipStream_t s
 }
 
 int occupancy_ilu0(int g, int levelset) {
-  const size_t lds = size_t(kBlockThreads) * g * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
   switch (g) {
     case 4: return levelset ? occ(k_ilu0_levelset<4>, lds) : occ(k_ilu0_fused<4>, lds);
     case 8: return levelset ? occ(k_ilu0_levelset<8>, lds) : occ(k_ilu0_fused<8>, lds);
