@@ -168,11 +168,35 @@ def main():
         for d in work:
             sfm.sync_status(d["s"])
         total_ms = e_start.elapsed_time(e_end)
+        samples = [[] for _ in work]
         for k in range(args.steps):
             for j in range(len(work)):
-                per[j][0] += evs[k][j][0].elapsed_time(evs[k][j][1])
+                t = evs[k][j][0].elapsed_time(evs[k][j][1])
+                per[j][0] += t
                 per[j][1] += 1
+                samples[j].append(t)
+        WARM_SAMPLES[unfused] = samples
         return total_ms / args.steps, [p[0] / p[1] for p in per]
+
+    def cold(unfused, reps=10):
+        """Per-launch times with the 256 MB Infinity Cache evicted first: a
+        1 GiB scratch write before each launch, outside the timed region."""
+        scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        out = []
+        for d in work:
+            ts = []
+            for r in range(reps + 1):
+                scratch.fill_(float(r))
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sfm.trsv_spmv(d["s"], d["Lv"], d["Av"], d["B"], X=d["X"], Y=d["Y"], unfused=unfused)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r > 0:  # the first launch is a warm-up
+                    ts.append(e0.elapsed_time(e1))
+            out.append(ts)
+        del scratch
+        return out
 
     log("timing fused (%d warmup, %d steps)" % (args.warmup, args.steps))
     ms_step, per_launch = timed(False)
@@ -180,6 +204,8 @@ def main():
     ys = [d["Y"].cpu().numpy() for d in work]
     log("timing unfused level-set baseline")
     ms_step_u, per_launch_u = timed(True)
+    log("cold launches (Infinity Cache evicted before each)")
+    cold_f, cold_u = cold(False), cold(True)
     step_bytes = sum(d["bytes"] for d in work)
     value = step_bytes / (ms_step * 1e-3) / 1e9
 
@@ -209,6 +235,13 @@ def main():
             "NER_vs_unfused": round(d["inspect_s"] * 1e3 / (per_launch_u[k] - per_launch[k]), 1)
             if per_launch_u[k] > per_launch[k] else None,
             "critical_path_us_per_level": round(per_launch[k] * 1e3 / max(d["joint_depth"], 1), 3),
+            "warm_fused_ms_median": round(float(np.median(WARM_SAMPLES[False][k])), 4),
+            "warm_fused_ms_min": round(float(np.min(WARM_SAMPLES[False][k])), 4),
+            "cold_fused_ms_median": round(float(np.median(cold_f[k])), 4),
+            "cold_fused_ms_min": round(float(np.min(cold_f[k])), 4),
+            "cold_fused_GBps": round(d["bytes"] / (float(np.median(cold_f[k])) * 1e-3) / 1e9, 1),
+            "cold_unfused_ms_median": round(float(np.median(cold_u[k])), 4),
+            "cold_speedup_vs_unfused": round(float(np.median(cold_u[k])) / float(np.median(cold_f[k])), 3),
         }
 
     extras = {}
@@ -217,7 +250,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args, work, xs, ys, per_matrix)
+        cpu = cpu_baseline(args, work, xs, ys, per_matrix, extras)
 
     line = {
         "metric": "fused SpTRSV+SpMV GB/s & %HBM peak vs unfused GPU at 1e-10 err; fwd+bwd ms",
@@ -238,6 +271,11 @@ def main():
         "frac_peak": round(value / HBM_PEAK_GBPS, 4),
         "unfused_GBps": round(step_bytes / (ms_step_u * 1e-3) / 1e9, 1),
         "speedup_vs_unfused": round(ms_step_u / ms_step, 3),
+        # the same step with the Infinity Cache evicted before every launch
+        # (medians of per-launch times, eviction outside the timed region)
+        "cold": {"GBps": round(step_bytes / (sum(float(np.median(c)) for c in cold_f) * 1e-3) / 1e9, 1),
+                 "ms_per_step": round(sum(float(np.median(c)) for c in cold_f), 4),
+                 "unfused_ms_per_step": round(sum(float(np.median(c)) for c in cold_u), 4)},
         "per_matrix": per_matrix,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -276,6 +314,10 @@ def run_extras(args, sfm, synth, torch, dev, stream):
         f = lambda: sfm.ic0_trsv(s, Av, b, L_val=Lv, X=X, check_info=False)
         u = lambda: sfm.ic0_trsv(s, Av, b, L_val=Lv, X=X, check_info=False, unfused=True)
         tf, tu = time_it(f, reps), time_it(u, reps)
+        f()
+        torch.cuda.synchronize()
+        EXTRA_SAMPLES["ic0_trsv_" + name] = ("ic0", Lp, synth.vec_normal(Lp.nrows, seed=1), Lv.cpu().numpy(),
+                                             X.cpu().numpy())
         sfm.sync_status(s)
         nb = it_bytes(Lp.nrows, Lp.nnz)
         out["ic0_trsv_" + name] = {"depth": s.info().depth, "fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
@@ -293,6 +335,10 @@ def run_extras(args, sfm, synth, torch, dev, stream):
         f = lambda: sfm.ilu0_trsv(s, Av, xv, LU_val=LU, Y=Yv, check_info=False)
         u = lambda: sfm.ilu0_trsv(s, Av, xv, LU_val=LU, Y=Yv, check_info=False, unfused=True)
         tf, tu = time_it(f, reps), time_it(u, reps)
+        f()
+        torch.cuda.synchronize()
+        EXTRA_SAMPLES["ilu0_trsv_" + name] = ("ilu0", a, synth.vec_normal(a.nrows, seed=1), LU.cpu().numpy(),
+                                              Yv.cpu().numpy())
         sfm.sync_status(s)
         nb = a.nnz * 12 + (a.nrows + 1) * 4 + a.nnz * 8 + 16 * a.nrows  # read A, write L and U, x in, y out
         out["ilu0_trsv_" + name] = {"depth": s.info().depth, "fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
@@ -316,6 +362,10 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                 f = lambda: sfm.trsv_trsv(s, Lv, x, X=Y, Z=Z)
                 u = lambda: sfm.trsv_trsv(s, Lv, x, X=Y, Z=Z, unfused=True)
             tf, tu = time_it(f, reps), time_it(u, reps)
+            f()
+            torch.cuda.synchronize()
+            EXTRA_SAMPLES["%s_%s" % (tag, name)] = (tag, L, A, synth.vec_uniform(L.nrows, seed=1),
+                                                     Y.cpu().numpy(), Z.cpu().numpy())
             nb = pair_bytes(L.nrows, L.nnz, A.nnz, mode)
             out["%s_%s" % (tag, name)] = {"fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
                                           "speedup_vs_unfused": round(tu / tf, 3), "bytes": nb,
@@ -345,6 +395,8 @@ def run_extras(args, sfm, synth, torch, dev, stream):
                "bytes": nb}
         for plan, tag in ((sfm.SF_STATIC_MSP, "msp"), (sfm.SF_STATIC_WAVEFRONT, "wavefront")):
             t = time_it(lambda: sfm.static_trsv_spmv(s, plan, Lv, Av, B, X=Z, Y=Yt), reps)
+            EXTRA_SAMPLES["static_plans_%s/%s" % (name, tag)] = ("ts", L, A, synth.vec_uniform(L.nrows, seed=1),
+                                                                 Z.cpu().numpy(), Yt.cpu().numpy())
             info = s.static_info(plan)
             res[tag + "_ms"] = round(t, 4)
             res[tag + "_s_partitions"] = info["n_spart"]
@@ -379,6 +431,8 @@ def run_extras(args, sfm, synth, torch, dev, stream):
 
 
 REFINE_SAMPLES = {}  # (matrix, k) -> (L, A, B, X, Y) host copies for the oracle check
+EXTRA_SAMPLES = {}   # extras key -> (kind, inputs..., GPU results) host copies for the oracle check
+WARM_SAMPLES = {}    # unfused flag -> per-matrix per-launch times of the timed steps
 
 
 def refine_pass_bytes(n, m, nnz_l, nnz_a, k):
@@ -427,9 +481,63 @@ def run_batched(args, sfm, synth, torch, dev, time_it):
     return out
 
 
-def cpu_baseline(args, work, xs, ys, per_matrix):
+def _rel(got, want):
+    import numpy as np
+    den = float(np.abs(want).max()) if want.size else 0.0
+    return float(np.abs(got - want).max() / den) if den > 0 else float(np.abs(got - want).max() if got.size else 0.0)
+
+
+def extra_errors(oracle):
+    """Each sampled extra's GPU results against the oracle's sequential
+    definition on the same inputs: max relative error per output."""
+    errs = {}
+    for key, smp in EXTRA_SAMPLES.items():
+        kind = smp[0]
+        if kind == "ic0":
+            _, Lp, b, lg, xg = smp
+            lr, _ = oracle.ic0(Lp.rowptr, Lp.col, Lp.val)
+            xr = oracle.trsv_lower(Lp.rowptr, Lp.col, lr, b)
+            errs[key] = {"L_rel_err": _rel(lg, lr), "x_rel_err": _rel(xg, xr)}
+        elif kind == "ilu0":
+            _, a, xv, lug, yg = smp
+            lur, _ = oracle.ilu0(a.rowptr, a.col, a.val)
+            yr = oracle.trsv_unit_lower(a.rowptr, a.col, lur, xv)
+            errs[key] = {"LU_rel_err": _rel(lug, lur), "y_rel_err": _rel(yg, yr)}
+        elif kind == "spmv_trsv":
+            _, L, A, x, yg, zg = smp
+            yr = oracle.spmv(A.rowptr, A.col, A.val, x)
+            zr = oracle.trsv_lower(L.rowptr, L.col, L.val, yr)
+            errs[key] = {"y_rel_err": _rel(yg, yr), "z_rel_err": _rel(zg, zr)}
+        elif kind == "trsv_trsv":
+            _, L, A, b, xg, zg = smp
+            xr = oracle.trsv_lower(L.rowptr, L.col, L.val, b)
+            zr = oracle.trsv_lower(L.rowptr, L.col, L.val, xr)
+            errs[key] = {"x_rel_err": _rel(xg, xr), "z_rel_err": _rel(zg, zr)}
+        elif kind == "ts":
+            _, L, A, b, xg, yg = smp
+            xr = oracle.trsv_lower(L.rowptr, L.col, L.val, b)
+            yr = oracle.spmv(A.rowptr, A.col, A.val, xr)
+            errs[key] = {"x_rel_err": _rel(xg, xr), "y_rel_err": _rel(yg, yr)}
+    return errs
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(args, work, xs, ys, per_matrix, extras=None):
     """The sequential FP64 oracle on the host, single thread, on the same
-    matrices; also gives each GPU result's error against it."""
+    matrices; also gives each GPU result's error against it, and each
+    sampled extra's (stored beside that extra)."""
     import numpy as np
 
     import oracle
@@ -472,7 +580,13 @@ def cpu_baseline(args, work, xs, ys, per_matrix):
             total_s += time.perf_counter() - t0
             total_bytes += d["bytes"]
             runs += 1
+    for key, e in extra_errors(oracle).items():
+        errs[key] = e
+        base = key.split("/")[0]
+        if extras is not None and base in extras:
+            extras[base].setdefault("rel_err_vs_oracle", {})[key.split("/")[-1] if "/" in key else "all"] = e
     return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu(), "host_cores": os.cpu_count() or 0,
             "sample": "%d sequential oracle SpTRSV+SpMV passes over the two full workload matrices "
                       "(%.1f s, single thread of %d host cores)" % (runs, total_s, os.cpu_count() or 0),
             "errors_vs_oracle": errs}
