@@ -215,11 +215,15 @@ sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level,
  *   X:      device n x nrhs output, ldx >= n.  Must not alias B.
  *   Y:      device m x nrhs output, ldy >= m; NULL runs the solve only.
  *   nrhs:   1..64.
- * Several right-hand sides run in blocks of rhs_block columns: B is packed
- * into a library-owned device workspace (kept with the schedule, grown on
- * demand, freed with it) in which each row of a block holds its columns
- * contiguously, the solve and the product run there, and X and Y are
- * unpacked at the end; only rows < n of X and < m of Y are written.
+ * Several right-hand sides run one of two ways ("multi_path"):
+ *   - in blocks of rhs_block columns: B is packed into a library-owned
+ *     device workspace (kept with the schedule, grown on demand, freed with
+ *     it) in which each row of a block holds its columns contiguously, the
+ *     solve and the product run there, and X and Y are unpacked at the end;
+ *   - as one chain of the single-RHS work items per column, directly on
+ *     the caller's columns (by default for a few right-hand sides on deep,
+ *     narrow DAGs with the coarsened plan).
+ * Either way only rows < n of X and < m of Y are written.
  * Several right-hand sides need n * rhs_block < 2^31 (else SF_ERR_UNSUPPORTED).
  * Errors: SF_ERR_ARG, SF_ERR_SHAPE, SF_ERR_UNSUPPORTED, SF_ERR_HIP, SF_ERR_OOM.
  */
@@ -440,6 +444,13 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "multi_waves_per_cu"        the same for several right-hand sides
  *                               (fused and level-set; 4..32, or 0, the
  *                               default: 8, 16 or 32 by the units per level);
+ *   "multi_path"                several right-hand sides: 1 = interleaved
+ *                               blocks over the level units, 2 = one chain of
+ *                               the single-RHS items per column (on the
+ *                               caller's columns), 0 (default) = 2 for at most
+ *                               8 right-hand sides on a coarsened plan of a
+ *                               DAG whose mean wavefront is under 2048 rows,
+ *                               else 1;
  *   "msp_parts"                 w-partitions per s-partition of the MSP plan
  *                               (its r; 1..2^20, default 1024; rebuilds it);
  *   "spin_limit"                watchdog: polls before SF_ERR_TIMEOUT;

@@ -343,13 +343,25 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   TsArgs a = ts_args(s, Lv, Av, B, ldb, nrhs, X, ldx, Y, ldy);
   if (a.n_work == 0) return SF_OK;
   // x doubles as its own readiness flag: it is filled with the pending
-  // pattern first (part of the timed execution).
-  if (nrhs == 1) {
+  // pattern first (part of the timed execution).  Several right-hand sides
+  // run either in interleaved blocks over the level units (below) or, with
+  // column chains, as separate chains of the single-RHS items on the
+  // caller's columns (multi_path).  Chains gather one value per column and
+  // entry, so they pay only where the units' hop per level dominates: by
+  // default on a coarsened plan of a narrow DAG (mean wavefront under 2048
+  // rows) with at most 8 right-hand sides (2D 9-point 2048^2, k = 8: 9.3 ->
+  // 7.8 ms; at k >= 32, or on wide DAGs, the units are faster).
+  const bool narrow = s->n < 2048 * int64_t(std::max(s->depth, 1));
+  const bool chains = nrhs > 1 && (s->multi_path == 2 ||
+                                   (s->multi_path == 0 && s->chunked && nrhs <= 8 && narrow));
+  if (nrhs == 1 || chains) {
+    if (int64_t(a.n_work) * nrhs > int64_t(INT32_MAX) / 2) return SF_ERR_UNSUPPORTED;
     sf_status r = next_epoch(s, st, a.ls);
     if (r != SF_OK) return r;
     a.kb = 1;
     a.nblk = 1;
-    a.trace = s->trace;
+    a.col_units = nrhs;
+    a.trace = nrhs == 1 ? s->trace : nullptr;
     if (s->chunked) {
       a.order = s->dev.corder;
       a.qrng = s->dev.cqrng;
@@ -359,9 +371,11 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
       a.lloc = s->dev.clloc;
       a.eloc = s->dev.celoc;
     }
-    const int grid = persistent_grid(s, occupancy_ts_fused(dtype));
+    const int waves = nrhs == 1 ? s->waves_per_cu
+                                : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : (nrhs <= 8 ? 8 : 16));
+    const int grid = persistent_grid(s, occupancy_ts_fused(dtype), waves);
     Timer tm(s, st);
-    SF_HIP(launch_fill_pending(X, size_t(s->n), dtype, st));
+    SF_HIP(launch_fill_pending_cols(X, int32_t(s->n), ldx, nrhs, dtype, st));
     return hip_status(launch_ts_fused(a, dtype, grid, st));
   }
   const int kb = solve_kb(s, nrhs);
@@ -1313,6 +1327,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "multi_waves_per_cu") {
     if (v != 0 && (v < 4 || v > 32)) return SF_ERR_ARG;
     s->multi_waves_per_cu = int32_t(v);
+  } else if (k == "multi_path") {
+    if (v < 0 || v > 2) return SF_ERR_ARG;
+    s->multi_path = int32_t(v);
   } else if (k == "msp_parts") {
     if (v < 1 || v > (int64_t(1) << 20)) return SF_ERR_ARG;
     if (s->msp_parts != int32_t(v)) {
@@ -1372,6 +1389,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "multi_waves_per_cu") *v = s->multi_waves_per_cu;
   else if (k == "spin_limit") *v = s->spin_limit;
   else if (k == "msp_parts") *v = s->msp_parts;
+  else if (k == "multi_path") *v = s->multi_path;
   else if (k == "claim_streams") *v = s->claim_streams;
   else if (k == "rows_per_item") *v = s->rows_per_item;
   else if (k == "max_item_nnz") *v = s->max_item_nnz;
@@ -1437,6 +1455,7 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   // one right-hand side: level items vs coarsened items first (the entry
   // stream makes lanes per row irrelevant there)
   if (r == SF_OK && nrhs == 1) r = try_param("coarsen", {1, 2});
+  if (r == SF_OK && nrhs > 1) r = try_param("multi_path", {1, 2});
   if (r == SF_OK && nrhs > 1) r = try_param("rhs_block", {8, 16, 32, 64});
   if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 1 << 20});
   if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});

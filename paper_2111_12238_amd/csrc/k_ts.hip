@@ -117,16 +117,28 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
   T* xl = xloc[threadIdx.x >> 6];
   if (lane == 0) xl[64] = T(1);
   dev::reset_next_launch(a.ls);
+  // several right-hand sides as separate chains: ticket t is column t % nc of
+  // item t / nc, so all columns of an item come before the next item and the
+  // claim order stays topological
+  const int nc = a.col_units > 1 ? a.col_units : 1;
+  const int total = a.n_work * nc;
   int t = dev::claim(a.ls, lane);
-  while (t < a.n_work) {
+  while (t < total) {
     const int tn = dev::claim(a.ls, lane);
-    const int it = a.item_list ? a.item_list[t] : t;
+    const int u = t / nc, c = t - u * nc;
+    TsArgs ac = a;
+    if (nc > 1) {
+      ac.B = static_cast<const T*>(a.B) + size_t(c) * size_t(a.ldb);
+      ac.X = static_cast<T*>(a.X) + size_t(c) * size_t(a.ldx);
+      if (a.Y) ac.Y = static_cast<T*>(a.Y) + size_t(c) * size_t(a.ldy);
+    }
+    const int it = a.item_list ? a.item_list[u] : u;
     const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
     if (a.order[q0] < a.n) {
-      if (a.lloc && a.lloc[q1 - 1] != 0) item_chunk<T>(a, q0, q1, lane, w, xl, it);
-      else item_stream<T, true, 2>(a, q0, q1, lane, w, it);
+      if (a.lloc && a.lloc[q1 - 1] != 0) item_chunk<T>(ac, q0, q1, lane, w, xl, it);
+      else item_stream<T, true, 2>(ac, q0, q1, lane, w, it);
     } else {
-      item_stream<T, false, 2>(a, q0, q1, lane, w, it);
+      item_stream<T, false, 2>(ac, q0, q1, lane, w, it);
     }
     t = tn;
   }
@@ -376,6 +388,15 @@ __global__ void k_fill_pending(T* p, size_t count) {
   for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < count; k += size_t(gridDim.x) * blockDim.x)
     p[k] = v;
 }
+template <typename T>
+__global__ void k_fill_pending_cols(T* p, int32_t rows, int32_t ld, int32_t ncols) {
+  const T v = __builtin_bit_cast(T, dev::Pending<T>::bits);
+  const size_t count = size_t(rows) * size_t(ncols);
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < count; k += size_t(gridDim.x) * blockDim.x) {
+    const size_t c = k / size_t(rows), i = k - c * size_t(rows);
+    p[i + c * size_t(ld)] = v;
+  }
+}
 
 // ---------------------------------------------------------- level set ----
 // Unfused baseline, same per-row arithmetic: the SpTRSV items of one level
@@ -591,6 +612,17 @@ hipError_t launch_static(const StaticArgs& a, int dtype, int grid, hipStream_t s
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlockThreads), args, 0, st);
 }
 int occupancy_static(int dtype) { return dtype == 0 ? occ(k_static<double>) : occ(k_static<float>); }
+hipError_t launch_fill_pending_cols(void* p, int32_t rows, int32_t ld, int32_t ncols, int dtype, hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return hipSuccess;
+  if (!p || ld < rows) return hipErrorInvalidValue;
+  size_t g = (size_t(rows) * size_t(ncols) + 255) / 256;
+  const int grid = int(g > 16384 ? 16384 : g);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill_pending_cols<double>, dim3(grid), dim3(256), 0, st, static_cast<double*>(p), rows, ld, ncols);
+  else
+    hipLaunchKernelGGL(k_fill_pending_cols<float>, dim3(grid), dim3(256), 0, st, static_cast<float*>(p), rows, ld, ncols);
+  return hipGetLastError();
+}
 hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st) {
   if (count == 0) return hipSuccess;
   size_t g = (count + 255) / 256;

@@ -36,6 +36,8 @@ struct TsArgs {
   int32_t ldy;
   int32_t nrhs, kb, nblk;  // right-hand sides, block width, number of blocks
   void* xi;                // interleaved solution, also its readiness flags (nrhs > 1)
+  int32_t col_units;       // > 1: that many right-hand sides, each its own chain of the items, on
+                           // column-major B, X, Y (k_ts_fused; work index = item * col_units + column)
   const int32_t *order, *item_ptr, *item_list;
   const int2* unit_rng;    // multi-RHS: claim-position range of each unit (replaces item_ptr / item_list)
   const int32_t* qrng;     // per claim position: CSR range of the row's dot product (pairs)
@@ -185,6 +187,8 @@ hipError_t launch_convert_f64_f32(const double* src, float* dst, int32_t n, hipS
 hipError_t launch_fill_u64(unsigned long long* p, int32_t count, hipStream_t st);
 // Fill a solution buffer with the pending (not yet published) pattern.
 hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st);
+// The same for the first rows of each of ncols columns of leading dimension ld.
+hipError_t launch_fill_pending_cols(void* p, int32_t rows, int32_t ld, int32_t ncols, int dtype, hipStream_t st);
 
 
 // Occupancy queries per kernel family (blocks per CU).

@@ -431,3 +431,34 @@ def test_multi_rhs_alternating_bit_exact(orc, kb):
         torch.cuda.synchronize()
         assert np.array_equal(host(X), xt) and np.array_equal(host(Y), yt), it
     sfm.sync_status(s)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("coarsen", [1, 2])
+def test_multi_rhs_paths_bit_exact(orc, path, coarsen):
+    """Several right-hand sides through either path -- interleaved blocks over
+    the level units, or one chain of the single-RHS items per column on the
+    caller's columns -- on level and coarsened plans, with leading
+    dimensions past the rows: FP64 results equal the oracle's bit for bit
+    and the padding rows are never written."""
+    announce("ts multi-rhs path=%d coarsen=%d" % (path, coarsen))
+    import torch
+    n, k = 5003, 11
+    L = synth.random_lower(n, 0.002, seed=11)
+    A = synth.from_scipy(sp.random(4000, n, density=0.003, random_state=np.random.default_rng(3), format="csr"))
+    b = synth.vec_uniform(n, k=k, seed=6)
+    xr, yr = oracle_ts(orc, L, A, b)
+    s = sfm.Schedule(L, A, coarsen=coarsen)
+    s.set_param("multi_path", path)
+    assert s.get_param("multi_path") == path
+    Lv, Av = dev(L.val), dev(A.val)
+    for unfused in (False, True):
+        Bbuf = torch.full((k, n + 3), 5.0, dtype=torch.float64, device="cuda")
+        Bbuf[:, :n] = torch.as_tensor(b.T, device="cuda")
+        Xbuf = torch.full((k, n + 6), -7.0, dtype=torch.float64, device="cuda")
+        Ybuf = torch.full((k, 4000 + 2), -9.0, dtype=torch.float64, device="cuda")
+        X, Y = sfm.trsv_spmv(s, Lv, Av, Bbuf.t()[:n], X=Xbuf.t()[:n], Y=Ybuf.t()[:4000], unfused=unfused)
+        torch.cuda.synchronize()
+        sfm.sync_status(s)
+        assert np.array_equal(host(X), xr) and np.array_equal(host(Y), yr), unfused
+        assert bool((Xbuf[:, n:] == -7.0).all()) and bool((Ybuf[:, 4000:] == -9.0).all()), unfused
