@@ -277,8 +277,8 @@ sf_status sf_schedule_export_static(sf_schedule s, int32_t plan, int32_t* s_ptr,
                                     int32_t* order);
 
 /* x = L^{-1} b and y = A x (one right-hand side, FP64 or FP32) under a
- * static plan.  B, X (length n) and Y (length m) are device vectors; X must
- * not alias B.  Results equal sf_exec_trsv_spmv's bit for bit (same per-row
+ * static plan.  B, X (length n) and Y (length m; may be NULL when m = 0)
+ * are device vectors; X must not alias B.  Results equal sf_exec_trsv_spmv's bit for bit (same per-row
  * arithmetic).  Errors: SF_ERR_ARG, SF_ERR_OOM, SF_ERR_HIP. */
 sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, const void* L_val,
                                    const void* A_val, const void* B, void* X, void* Y, void* stream);

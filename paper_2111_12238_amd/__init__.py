@@ -369,10 +369,10 @@ def static_trsv_spmv(sched: Schedule, plan: int, L_val, A_val, b, *, X=None, Y=N
         raise ValueError("static plans take one right-hand side")
     if X is None:
         X = colmajor(n, 1, L_val.dtype, L_val.device)
-    if Y is None:
+    if Y is None and m > 0:
         Y = colmajor(m, 1, L_val.dtype, L_val.device)
     xp, _, _ = _vec_ptr(X, n, "X")
-    yp, _, _ = _vec_ptr(Y, m, "Y")
+    yp = _vec_ptr(Y, m, "Y")[0] if m > 0 else None
     _check(_lib().sf_exec_static_trsv_spmv(sched.handle, plan, _dtype_code(L_val), L_val.data_ptr(),
                                            _ptr(A_val), bp, xp, yp, _stream(stream)), "sf_exec_static_trsv_spmv")
     return X, Y

@@ -869,7 +869,7 @@ sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, 
   if (!s || s->kind != SF_TRSV_SPMV || (plan != SF_STATIC_MSP && plan != SF_STATIC_WAVEFRONT)) return SF_ERR_ARG;
   if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
   if (s->n == 0) return SF_OK;
-  if (!L_val || !B || !X || !Y || (s->m > 0 && !A_val) || B == X) return SF_ERR_ARG;
+  if (!L_val || !B || !X || (s->m > 0 && (!Y || !A_val)) || B == X) return SF_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   sf_status r = upload(s, st);
   if (r == SF_OK) r = build_static(s, plan);

@@ -84,3 +84,31 @@ def test_static_msp_parts_and_full_size(orc):
         torch.cuda.synchronize()
         sfm.sync_status(s)
         assert np.array_equal(host(X), xr) and np.array_equal(host(Y), yr), plan
+
+
+def test_static_degenerate(orc):
+    """One row; a diagonal L (one wavefront, one s-partition); an A without
+    rows (no Y): exact results under both plans."""
+    announce("static plans degenerate")
+    import torch
+    cases = [
+        (sp.csr_matrix(np.array([[2.0]])), sp.csr_matrix(np.array([[3.0]]))),
+        (sp.identity(50, format="csr") * 2.0, sp.random(30, 50, density=0.1, random_state=np.random.default_rng(1),
+                                                         format="csr")),
+        (sp.identity(20, format="csr") + sp.eye(20, k=-1, format="csr"), sp.csr_matrix((0, 20))),
+    ]
+    for ld, ad in cases:
+        L, A = synth.from_scipy(sp.csr_matrix(ld)), synth.from_scipy(sp.csr_matrix(ad))
+        b = synth.vec_uniform(L.nrows, seed=2)
+        xr = orc.trsv_lower(L.rowptr, L.col, L.val, b)
+        s = sfm.Schedule(L, A)
+        for plan in PLANS:
+            Av = dev(A.val) if A.nnz else None
+            X, Y = sfm.static_trsv_spmv(s, plan, dev(L.val), Av, dev(b))
+            torch.cuda.synchronize()
+            sfm.sync_status(s)
+            assert np.array_equal(host(X), xr), plan
+            if A.nrows:
+                assert np.array_equal(host(Y), orc.spmv(A.rowptr, A.col, A.val, xr)), plan
+            else:
+                assert Y is None
