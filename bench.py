@@ -235,6 +235,9 @@ def main():
             "NER_vs_unfused": round(d["inspect_s"] * 1e3 / (per_launch_u[k] - per_launch[k]), 1)
             if per_launch_u[k] > per_launch[k] else None,
             "critical_path_us_per_level": round(per_launch[k] * 1e3 / max(d["joint_depth"], 1), 3),
+            # single-value x gathers of one pass (off-diagonals of L, entries of A) and their rate
+            "gathers": d["L"].nnz - d["L"].nrows + d["A"].nnz,
+            "fused_Ggathers_per_s": round((d["L"].nnz - d["L"].nrows + d["A"].nnz) / (per_launch[k] * 1e-3) / 1e9, 1),
             "warm_fused_ms_median": round(float(np.median(WARM_SAMPLES[False][k])), 4),
             "warm_fused_ms_min": round(float(np.min(WARM_SAMPLES[False][k])), 4),
             "cold_fused_ms_median": round(float(np.median(cold_f[k])), 4),

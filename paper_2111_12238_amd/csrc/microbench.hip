@@ -5,7 +5,12 @@
 //             publication protocols the executor can use, on the same XCD
 //             and across XCDs;
 //   ticket    throughput of device-scope atomic work claiming on one
-//             counter versus one counter per XCD.
+//             counter versus one counter per XCD;
+//   gather    a dependence-free product sum over random columns (the random
+//             SPD workload's shape: 1M-entry FP64 vector, 50M random single
+//             gathers with their column and value streams), with plain and
+//             with device-coherent gathers: the floor of any schedule of
+//             that workload, set by the gather request rate.
 // Output: one JSON object per line on stdout.
 #include <hip/hip_runtime.h>
 
@@ -128,6 +133,53 @@ __global__ void tickets(int* counters, int per_wave, int mode) {
   if (acc == -1) counters[1] = acc;  // keep the result live
 }
 
+// Index k's column: a 64-bit mixing hash (multiply, xor-shift) of k, mod n.
+__global__ void fill_gather(int* col, double* val, double* x, long long nnz, int n) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < nnz; i += stride) {
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    col[i] = (int)(h % (unsigned long long)n);
+    val[i] = 1.0 / (double)(1 + (i & 15));
+    if (i < n) x[i] = (double)(i & 1023);
+  }
+}
+
+// Every wave takes chunks of 64 U entries, entry u * 64 + lane of a chunk on
+// each lane (coalesced column and value loads, streamed past the caches),
+// then U gathers of x per lane, all issued before use.
+template <int CO, int U>
+__global__ void gather_kernel(const int* __restrict__ col, const double* __restrict__ val,
+                              const double* x, double* out, long long nnz) {
+  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const long long wave = tid >> 6;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  double acc = 0.0;
+  for (long long chunk = wave * 64 * U; chunk < nnz; chunk += nwaves * 64 * U) {
+    int c[U];
+    double v[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long e = chunk + u * 64 + lane;
+      const bool in = e < nnz;
+      c[u] = in ? __builtin_nontemporal_load(col + e) : -1;
+      v[u] = in ? __builtin_nontemporal_load(val + e) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      xv[u] = c[u] < 0 ? 0.0
+                       : (CO ? __hip_atomic_load(x + c[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : x[c[u]]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u] * xv[u];
+  }
+  out[tid] = acc;
+}
+
 int main(int argc, char** argv) {
   const char* what = argc > 1 ? argv[1] : "all";
   hipDeviceProp_t prop;
@@ -221,6 +273,45 @@ int main(int argc, char** argv) {
       fflush(stdout);
     }
     CK(hipFree(counters));
+  }
+
+  if (!strcmp(what, "all") || !strcmp(what, "gather")) {
+    const int n = 1 << 20;
+    const long long nnz = 50000000;
+    int* col;
+    double *val, *x, *out;
+    const int max_threads = prop.multiProcessorCount * 32 * 64;
+    CK(hipMalloc(&col, nnz * sizeof(int)));
+    CK(hipMalloc(&val, nnz * sizeof(double)));
+    CK(hipMalloc(&x, n * sizeof(double)));
+    CK(hipMalloc(&out, (size_t)max_threads * sizeof(double)));
+    fill_gather<<<prop.multiProcessorCount * 8, 256>>>(col, val, x, nnz, n);
+    CK(hipDeviceSynchronize());
+    for (int co = 0; co < 2; ++co)
+      for (int waves : {8, 16, 32}) {
+        const int grid = prop.multiProcessorCount * waves / 4;  // 4 waves per 256-thread block
+        auto launch = [&]() {
+          if (co) gather_kernel<1, 8><<<grid, 256>>>(col, val, x, out, nnz);
+          else gather_kernel<0, 8><<<grid, 256>>>(col, val, x, out, nnz);
+        };
+        for (int w = 0; w < 3; ++w) launch();
+        const int reps = 20;
+        CK(hipEventRecord(e0));
+        for (int r = 0; r < reps; ++r) launch();
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        float ms;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        const double t = ms / reps;
+        printf("{\"bench\": \"gather\", \"coherent\": %d, \"waves_per_cu\": %d, \"n\": %d, \"gathers\": %lld, "
+               "\"ms_per_launch\": %.4f, \"Ggathers_per_s\": %.1f, \"stream_GBps\": %.1f}\n",
+               co, waves, n, nnz, t, nnz / (t * 1e-3) / 1e9, 12.0 * nnz / (t * 1e-3) / 1e9);
+        fflush(stdout);
+      }
+    CK(hipFree(col));
+    CK(hipFree(val));
+    CK(hipFree(x));
+    CK(hipFree(out));
   }
   return 0;
 }
