@@ -210,7 +210,8 @@ sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level,
  * each SpMV row as soon as the x entries it reads are final.
  *   dtype:  SF_F64 or SF_F32 (values, vectors and accumulation).
  *   L_val:  device, nnz(L) values in the inspected order.
- *   A_val:  device, nnz(A) values; may be NULL when Y is NULL.
+ *   A_val:  device, nnz(A) values; may be NULL when Y is NULL or A stores
+ *           no entries.
  *   B:      device n x nrhs, leading dimension ldb >= n.
  *   X:      device n x nrhs output, ldx >= n.  Must not alias B.
  *   Y:      device m x nrhs output, ldy >= m; NULL runs the solve only.
@@ -224,6 +225,8 @@ sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level,
  *     the caller's columns (by default for a few right-hand sides on deep,
  *     narrow DAGs with the coarsened plan).
  * Either way only rows < n of X and < m of Y are written.
+ * n = 0: B, X and L_val are not used (may be NULL) and every column of Y is
+ * set to zero (A has no columns, so y = A x = 0).
  * Several right-hand sides need n * rhs_block < 2^31 (else SF_ERR_UNSUPPORTED).
  * Errors: SF_ERR_ARG, SF_ERR_SHAPE, SF_ERR_UNSUPPORTED, SF_ERR_HIP, SF_ERR_OOM.
  */
@@ -278,7 +281,8 @@ sf_status sf_schedule_export_static(sf_schedule s, int32_t plan, int32_t* s_ptr,
 
 /* x = L^{-1} b and y = A x (one right-hand side, FP64 or FP32) under a
  * static plan.  B, X (length n) and Y (length m; may be NULL when m = 0)
- * are device vectors; X must not alias B.  Results equal sf_exec_trsv_spmv's bit for bit (same per-row
+ * are device vectors; X must not alias B.  A_val may be NULL when A stores
+ * no entries.  n = 0: Y is set to zero and nothing else is used.  Results equal sf_exec_trsv_spmv's bit for bit (same per-row
  * arithmetic).  Errors: SF_ERR_ARG, SF_ERR_OOM, SF_ERR_HIP. */
 sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, const void* L_val,
                                    const void* A_val, const void* B, void* X, void* Y, void* stream);

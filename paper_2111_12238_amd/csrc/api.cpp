@@ -462,10 +462,17 @@ sf_status check_ts_args(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   if (dt != SF_F64 && dt != SF_F32) return SF_ERR_ARG;
   if (nrhs < 1 || nrhs > 64) return SF_ERR_ARG;
   if (s->n > 0 && (!Lv || !B || !X)) return SF_ERR_ARG;
-  if (Y && s->m > 0 && !Av) return SF_ERR_ARG;
+  if (Y && s->A.nnz() > 0 && !Av) return SF_ERR_ARG;
   if (ldb < s->n || ldx < s->n || (Y && ldy < s->m)) return SF_ERR_SHAPE;
   if (B == X && s->n > 0) return SF_ERR_ARG;
   return SF_OK;
+}
+
+// No unknowns: x is empty and y = A x is zero in every row of A.
+sf_status empty_solve(sf_schedule_s* s, sf_dtype dt, void* Y, int32_t ldy, int32_t nrhs, void* stream) {
+  if (!Y || s->m == 0) return SF_OK;
+  return hip_status(launch_zero_cols(Y, int32_t(s->m), ldy, nrhs, dt == SF_F64 ? 0 : 1,
+                                     static_cast<hipStream_t>(stream)));
 }
 
 // Kernel combinations 1 and 2 of Table 2 (see k_pair).  mode 2: B = x,
@@ -807,7 +814,7 @@ sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, co
                             int32_t ldy, void* stream) {
   sf_status r = check_ts_args(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy);
   if (r != SF_OK) return r;
-  if (s->n == 0) return SF_OK;
+  if (s->n == 0) return empty_solve(s, dtype, Y, ldy, nrhs, stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   r = upload(s, st);
   if (r != SF_OK) return r;
@@ -868,8 +875,9 @@ sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, 
                                    const void* A_val, const void* B, void* X, void* Y, void* stream) {
   if (!s || s->kind != SF_TRSV_SPMV || (plan != SF_STATIC_MSP && plan != SF_STATIC_WAVEFRONT)) return SF_ERR_ARG;
   if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
-  if (s->n == 0) return SF_OK;
-  if (!L_val || !B || !X || (s->m > 0 && (!Y || !A_val)) || B == X) return SF_ERR_ARG;
+  if (s->m > 0 && (!Y || (s->A.nnz() > 0 && !A_val))) return SF_ERR_ARG;
+  if (s->n == 0) return empty_solve(s, dtype, Y, int32_t(s->m), 1, stream);
+  if (!L_val || !B || !X || B == X) return SF_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   sf_status r = upload(s, st);
   if (r == SF_OK) r = build_static(s, plan);
@@ -902,7 +910,7 @@ sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L
                                     void* Y, int32_t ldy, void* stream) {
   sf_status r = check_ts_args(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy);
   if (r != SF_OK) return r;
-  if (s->n == 0) return SF_OK;
+  if (s->n == 0) return empty_solve(s, dtype, Y, ldy, nrhs, stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   r = upload(s, st);
   if (r != SF_OK) return r;

@@ -120,7 +120,30 @@ hipError_t unpack_t(const void* src, int32_t rows, int32_t ncols, void* dst, int
   return hipErrorInvalidValue;
 }
 
+// Zero `ncols` columns of `rows` entries, column c at p + c * ld (a kernel,
+// not a memset, so that the call can sit in a captured graph).
+template <typename T>
+__global__ void k_zero_cols(T* p, int32_t rows, int32_t ld, int32_t ncols) {
+  const size_t count = size_t(rows) * size_t(ncols);
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < count; k += size_t(gridDim.x) * blockDim.x) {
+    const size_t c = k / size_t(rows), i = k - c * size_t(rows);
+    p[i + c * size_t(ld)] = T(0);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_zero_cols(void* p, int32_t rows, int32_t ld, int32_t ncols, int dtype, hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return hipSuccess;
+  if (!p || ld < rows) return hipErrorInvalidValue;
+  const size_t g = (size_t(rows) * size_t(ncols) + kThreads - 1) / kThreads;
+  const int grid = int(g > 16384 ? 16384 : g);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_zero_cols<double>, dim3(grid), dim3(kThreads), 0, st, static_cast<double*>(p), rows, ld, ncols);
+  else
+    hipLaunchKernelGGL(k_zero_cols<float>, dim3(grid), dim3(kThreads), 0, st, static_cast<float*>(p), rows, ld, ncols);
+  return hipGetLastError();
+}
 
 hipError_t launch_pack(const void* src, int src_dtype, int32_t lds, int32_t rows, int32_t ncols, void* dst,
                        int dst_dtype, void* pend, int kb, hipStream_t st) {

@@ -183,6 +183,8 @@ hipError_t launch_pack(const void* src, int src_dtype, int32_t lds, int32_t rows
                        int dst_dtype, void* pend, int kb, hipStream_t st);
 hipError_t launch_unpack(const void* src, int dtype, int32_t rows, int32_t ncols, void* dst, int32_t ldd, int kb,
                          hipStream_t st);
+// Zero ncols columns of rows entries at p + c * ld (dtype 0 = f64, 1 = f32).
+hipError_t launch_zero_cols(void* p, int32_t rows, int32_t ld, int32_t ncols, int dtype, hipStream_t st);
 hipError_t launch_convert_f64_f32(const double* src, float* dst, int32_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int32_t count, hipStream_t st);
 // Fill a solution buffer with the pending (not yet published) pattern.

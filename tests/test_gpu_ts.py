@@ -238,6 +238,42 @@ def test_degenerate(orc):
     assert np.array_equal(x, b / np.arange(1.0, 301.0))
 
 
+def test_empty_system_zeroes_y():
+    """No unknowns: x is empty and y = A x is zero for an A with rows but no
+    columns.  Y starts as NaN and must come back zero from every entry: fused,
+    unfused, three right-hand sides with a padded leading dimension, both
+    static plans; an A without rows leaves nothing to write."""
+    announce("ts empty system n=0 (m=5 and m=0)")
+    import torch
+    L = synth.from_scipy(sp.csr_matrix((0, 0)))
+    A = synth.from_scipy(sp.csr_matrix((5, 0)))
+    s = sfm.Schedule(L, A)
+    Lv = torch.empty(0, dtype=torch.float64, device="cuda")
+    for unfused in (False, True):
+        Y = torch.full((5,), float("nan"), dtype=torch.float64, device="cuda")
+        X, Y = sfm.trsv_spmv(s, Lv, None, torch.empty(0, dtype=torch.float64, device="cuda"), Y=Y,
+                             unfused=unfused)
+        torch.cuda.synchronize()
+        assert X.shape == (0,) and host(Y).tolist() == [0.0] * 5, unfused
+    big = torch.full((3, 8), float("nan"), dtype=torch.float32, device="cuda")
+    Yk = big.t()[:5]                      # column-major (5, 3), leading dimension 8
+    B = sfm.colmajor(0, 3, torch.float32)
+    sfm.trsv_spmv(s, Lv.float(), None, B, Y=Yk)
+    torch.cuda.synchronize()
+    got = host(big)
+    assert (got[:, :5] == 0).all() and np.isnan(got[:, 5:]).all()  # padding rows untouched
+    for plan in (sfm.SF_STATIC_MSP, sfm.SF_STATIC_WAVEFRONT):
+        Y = torch.full((5,), float("nan"), dtype=torch.float64, device="cuda")
+        _, Y = sfm.static_trsv_spmv(s, plan, Lv, None, torch.empty(0, dtype=torch.float64, device="cuda"), Y=Y)
+        torch.cuda.synchronize()
+        assert host(Y).tolist() == [0.0] * 5, plan
+    s0 = sfm.Schedule(L, synth.from_scipy(sp.csr_matrix((0, 0))))
+    X, Y = sfm.trsv_spmv(s0, Lv, None, torch.empty(0, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert X.numel() == 0 and Y.numel() == 0
+    sfm.sync_status(s)
+
+
 def test_watchdog_reports_timeout_and_recovers(orc):
     """A spin limit of one poll makes waits on not-yet-final rows give up:
     the launch drains, SF_ERR_TIMEOUT is reported, and the next launch with

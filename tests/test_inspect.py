@@ -479,18 +479,22 @@ def test_msp_windows_and_pairs(orc):
 
 
 def test_static_plans_degenerate(orc):
-    """One row; a diagonal L (one wavefront); an A without rows: both static
-    plans are built and pass the oracle's check."""
+    """One row; a diagonal L (one wavefront); an A without rows; no unknowns
+    at all (with and without rows of A): both static plans are built and
+    pass the oracle's check."""
     import scipy.sparse as sp
     cases = [
         (sp.csr_matrix(np.array([[2.0]])), sp.csr_matrix(np.array([[3.0]]))),
         (sp.identity(50, format="csr") * 2.0, sp.random(30, 50, density=0.1, random_state=np.random.default_rng(1),
                                                          format="csr")),
         (sp.identity(20, format="csr") + sp.eye(20, k=-1, format="csr"), sp.csr_matrix((0, 20))),
+        (sp.csr_matrix((0, 0)), sp.csr_matrix((0, 0))),
+        (sp.csr_matrix((0, 0)), sp.csr_matrix((5, 0))),
     ]
     for ld, ad in cases:
         L, A = synth.from_scipy(sp.csr_matrix(ld)), synth.from_scipy(sp.csr_matrix(ad))
         s = sfm.Schedule(L, A)
+        assert (s.info().depth == 0) == (L.nrows == 0)
         for plan in (sfm.SF_STATIC_MSP, sfm.SF_STATIC_WAVEFRONT):
             s_ptr, w_ptr, order = s.export_static(plan)
             assert orc.validate_static_ts(L.rowptr, L.col, A.rowptr, A.col, s_ptr, w_ptr, order) == 0, plan
