@@ -36,6 +36,35 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def bounds(d, fused_ms, probe):
+    """Lower bounds on one fused launch (ms) from the device probes:
+    - hbm_peak / copy_ceiling: algorithmic bytes at 8 TB/s / at the measured
+      stream-copy rate;
+    - gather_floor: every x read as one single-value gather at the measured
+      random-gather rate (level items only: coarsened items read in-item x
+      from LDS, so there it is no floor);
+    - critical_path: one cross-XCD hop per dependent step (joint wavefronts
+      of the level plan, items of the coarsened plan's longest chain).
+    `binding` is the largest; `frac_of_binding` = binding / fused time."""
+    if not probe:
+        return None
+    st = d["s"].info()
+    gathers = d["L"].nnz - d["L"].nrows + d["A"].nnz
+    hops = st.chunk_chain if st.coarsened else st.joint_depth
+    b = {"hbm_peak_ms": d["bytes"] / (HBM_PEAK_GBPS * 1e9) * 1e3,
+         "copy_ceiling_ms": d["bytes"] / (probe["copy_GBps"] * 1e9) * 1e3 if probe["copy_GBps"] > 0 else None,
+         "gather_floor_ms": None if st.coarsened or probe["gathers_per_s"] <= 0
+         else gathers / probe["gathers_per_s"] * 1e3,
+         "critical_path_ms": hops * probe["hop_us_cross_xcd"] * 1e-3 if probe["hop_us_cross_xcd"] > 0 else None,
+         "critical_path_hops": hops}
+    cands = {k: v for k, v in b.items() if k.endswith("_ms") and v is not None}
+    name = max(cands, key=cands.get)
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in b.items()}
+    out["binding"] = name[:-3]
+    out["frac_of_binding"] = round(cands[name] / fused_ms, 3)
+    return out
+
+
 def ts_bytes(n, m, nnz_l, nnz_a, vb=8):
     return nnz_l * (vb + 4) + nnz_a * (vb + 4) + (n + 1) * 4 + (m + 1) * 4 + (2 * n + m) * vb
 
@@ -101,11 +130,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="skip the device probes (no bounds)")
+    ap.add_argument("--probe-only", choices=("copy", "hop", "gather", "all"),
+                    help="run one device probe, print its JSON line and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (every GPU box here "
-              "has one GPU); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -115,6 +147,10 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.probe_only:
+        what = {"copy": sfm.SF_PROBE_COPY, "hop": sfm.SF_PROBE_HOP, "gather": sfm.SF_PROBE_GATHER, "all": 0}
+        print(json.dumps({"probe": sfm.device_probe(what[args.probe_only])}))
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -208,6 +244,10 @@ def main():
     cold_f, cold_u = cold(False), cold(True)
     step_bytes = sum(d["bytes"] for d in work)
     value = step_bytes / (ms_step * 1e-3) / 1e9
+    probe = None
+    if not args.no_probe:
+        log("device probes (copy ceiling, hop latency, gather rate)")
+        probe = sfm.device_probe(stream=stream)
 
     # roofline of the dominant kernel (the fused launch with the most time)
     j = int(np.argmax(per_launch))
@@ -245,6 +285,7 @@ def main():
             "cold_fused_GBps": round(d["bytes"] / (float(np.median(cold_f[k])) * 1e-3) / 1e9, 1),
             "cold_unfused_ms_median": round(float(np.median(cold_u[k])), 4),
             "cold_speedup_vs_unfused": round(float(np.median(cold_u[k])) / float(np.median(cold_f[k])), 3),
+            "bounds": bounds(d, per_launch[k], probe),
         }
 
     extras = {}
@@ -279,6 +320,7 @@ def main():
         "cold": {"GBps": round(step_bytes / (sum(float(np.median(c)) for c in cold_f) * 1e-3) / 1e9, 1),
                  "ms_per_step": round(sum(float(np.median(c)) for c in cold_f), 4),
                  "unfused_ms_per_step": round(sum(float(np.median(c)) for c in cold_u), 4)},
+        "probe": probe,
         "per_matrix": per_matrix,
         "roofline": roofline,
         "cpu_baseline": cpu,

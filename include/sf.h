@@ -503,6 +503,34 @@ sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count)
  * sf_set_param(s, "timing", 1); *ms is filled after a stream sync. */
 sf_status sf_last_kernel_ms(sf_schedule s, double* ms);
 
+/* Device probes: the machine constants that bound the executors, measured
+ * on the current device.  They calibrate the two bounds of a fused pass:
+ * bytes over the copy ceiling, and (for schedules whose x reads have no
+ * locality) gathers over the gather rate, beside the critical path of
+ * dependent hops times the hop latency.
+ *   what: bit mask of SF_PROBE_COPY (stream copy of 1 GiB into 1 GiB, read +
+ *         write bytes per second), SF_PROBE_HOP (one-way latency of a value
+ *         published with the executors' protocol, between two workgroups on
+ *         one XCD and across XCDs), SF_PROBE_GATHER (uniformly random
+ *         single-value FP64 gathers from a 2^20-entry vector, 5e7 per pass,
+ *         with coalesced column and value streams); 0 = all.
+ *   out:  HOST; fields not probed, and a hop pair that could not be placed,
+ *         are set to -1.
+ *   stream: the probes run on it and the call synchronises it.
+ * The probes allocate their own device buffers (up to 2 GiB, freed before
+ * return) and are not meant for graph capture.  Errors: SF_ERR_ARG (out is
+ * NULL or what has unknown bits), SF_ERR_OOM, SF_ERR_HIP. */
+#define SF_PROBE_COPY 1
+#define SF_PROBE_HOP 2
+#define SF_PROBE_GATHER 4
+typedef struct {
+  double copy_GBps;         /* GB/s, read + write bytes */
+  double hop_us_same_xcd;   /* microseconds per one-way hop */
+  double hop_us_cross_xcd;
+  double gathers_per_s;     /* single-value gathers per second */
+} sf_probe_result;
+sf_status sf_device_probe(int32_t what, sf_probe_result* out, void* stream);
+
 const char* sf_status_str(sf_status st);
 
 /* Library version string. */

@@ -58,6 +58,14 @@ class InspectOpts(ctypes.Structure):
                  "want_backward", "validate", "no_fusion", "coarsen")]
 
 
+SF_PROBE_COPY, SF_PROBE_HOP, SF_PROBE_GATHER = 1, 2, 4
+
+
+class ProbeResult(ctypes.Structure):
+    _fields_ = [("copy_GBps", ctypes.c_double), ("hop_us_same_xcd", ctypes.c_double),
+                ("hop_us_cross_xcd", ctypes.c_double), ("gathers_per_s", ctypes.c_double)]
+
+
 class ScheduleStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("nnz_l", ctypes.c_int64),
                 ("nnz_a", ctypes.c_int64), ("depth", ctypes.c_int32), ("joint_depth", ctypes.c_int32),
@@ -98,6 +106,7 @@ _SIGS = {
     "sf_autotune": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _I, _P, ctypes.POINTER(ctypes.c_double)],
     "sf_sync_status": [_P, _P],
     "sf_last_kernel_ms": [_P, ctypes.POINTER(ctypes.c_double)],
+    "sf_device_probe": [_I, _P, _P],
     "sf_trace_export": [_P, _P, ctypes.c_int64],
     "sf_exec_spmv_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
     "sf_exec_unfused_spmv_trsv": [_P, _I, _P, _P, _P, _P, _P, _P],
@@ -531,6 +540,15 @@ def autotune(sched: Schedule, L_val, A_val, B, *, want_y=True, stream=None):
 def sync_status(sched: Schedule, stream=None):
     """Synchronise and raise SparseFusionError(SF_ERR_TIMEOUT) if a watchdog fired."""
     _check(_lib().sf_sync_status(sched.handle, _stream(stream)), "sf_sync_status")
+
+
+def device_probe(what: int = 0, stream=None) -> dict:
+    """Machine constants of the current device (``sf_device_probe``): copy
+    ceiling (GB/s), one-way hop latency on one XCD and across XCDs (us), and
+    random single-value gathers per second; -1 for what was not probed."""
+    r = ProbeResult()
+    _check(_lib().sf_device_probe(what, ctypes.byref(r), _stream(stream)), "sf_device_probe")
+    return {k: getattr(r, k) for k, _ in ProbeResult._fields_}
 
 
 def version() -> str:

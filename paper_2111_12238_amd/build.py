@@ -26,7 +26,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
           "-Wno-unused-command-line-argument"]
 
-UNITS = ["inspect.cpp", "static_plan.cpp", "api.cpp", "k_ts.hip", "k_ic0.hip", "k_ilu.hip", "k_bwd.hip", "k_refine.hip", "k_layout.hip"]
+UNITS = ["inspect.cpp", "static_plan.cpp", "api.cpp", "k_ts.hip", "k_ic0.hip", "k_ilu.hip", "k_bwd.hip", "k_refine.hip",
+         "k_layout.hip", "k_probe.hip"]
 
 
 def _compile(src: str) -> str:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "kargs.h"
+#include "probe.h"
 #include "schedule.h"
 
 using namespace sf;
@@ -651,6 +652,20 @@ sf_status sf_exec_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, co
 sf_status sf_exec_unfused_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X,
                                     void* Z, void* stream) {
   return pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, false, stream);
+}
+
+sf_status sf_device_probe(int32_t what, sf_probe_result* out, void* stream) {
+  if (!out) return SF_ERR_ARG;
+  const int32_t all = SF_PROBE_COPY | SF_PROBE_HOP | SF_PROBE_GATHER;
+  if (what == 0) what = all;
+  if (what & ~all) return SF_ERR_ARG;
+  *out = sf_probe_result{-1.0, -1.0, -1.0, -1.0};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int cus = std::max(1, device_cus());
+  if (what & SF_PROBE_COPY) SF_HIP(probe_copy(cus, st, &out->copy_GBps));
+  if (what & SF_PROBE_HOP) SF_HIP(probe_hop(st, &out->hop_us_same_xcd, &out->hop_us_cross_xcd));
+  if (what & SF_PROBE_GATHER) SF_HIP(probe_gather(cus, st, &out->gathers_per_s));
+  return SF_OK;
 }
 
 const char* sf_version(void) { return "sparsefusion-mi355x 0.1 (gfx950)"; }

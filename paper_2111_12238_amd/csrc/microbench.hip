@@ -1,16 +1,11 @@
-// Microbenchmarks that calibrate the executor's cost model on the device:
-//   copy      HBM stream-copy bandwidth (the practical bandwidth ceiling, and
-//             the reference kernel for scaling rocprof byte counters);
-//   pingpong  readiness-flag hop latency between two workgroups, for the two
-//             publication protocols the executor can use, on the same XCD
-//             and across XCDs;
+// Microbenchmarks behind two design choices of the executors (the machine
+// constants that bound them -- copy ceiling, hop latency, gather rate -- are
+// measured by the library itself, sf_device_probe):
+//   pingpong  readiness-flag hop latency between two workgroups, for two
+//             publication protocols (data + fence + flag, and
+//             device-coherent data + flag), on the same XCD and across XCDs;
 //   ticket    throughput of device-scope atomic work claiming on one
-//             counter versus one counter per XCD;
-//   gather    a dependence-free product sum over random columns (the random
-//             SPD workload's shape: 1M-entry FP64 vector, 50M random single
-//             gathers with their column and value streams), with plain and
-//             with device-coherent gathers: the floor of any schedule of
-//             that workload, set by the gather request rate.
+//             counter versus one counter per XCD.
 // Output: one JSON object per line on stdout.
 #include <hip/hip_runtime.h>
 
@@ -33,12 +28,6 @@
 __device__ __forceinline__ unsigned xcc_id() {
   // HW_REG_XCC_ID (hardware register 20), bits [3:0]
   return __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));
-}
-
-__global__ void copy_kernel(const float4* __restrict__ a, float4* __restrict__ b, size_t n4) {
-  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n4; i += stride) b[i] = a[i];
 }
 
 // Protocol 0: plain data store, agent release fence, relaxed flag store;
@@ -133,53 +122,6 @@ __global__ void tickets(int* counters, int per_wave, int mode) {
   if (acc == -1) counters[1] = acc;  // keep the result live
 }
 
-// Index k's column: a 64-bit mixing hash (multiply, xor-shift) of k, mod n.
-__global__ void fill_gather(int* col, double* val, double* x, long long nnz, int n) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (; i < nnz; i += stride) {
-    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull;
-    h ^= h >> 29;
-    h *= 0xBF58476D1CE4E5B9ull;
-    h ^= h >> 32;
-    col[i] = (int)(h % (unsigned long long)n);
-    val[i] = 1.0 / (double)(1 + (i & 15));
-    if (i < n) x[i] = (double)(i & 1023);
-  }
-}
-
-// Every wave takes chunks of 64 U entries, entry u * 64 + lane of a chunk on
-// each lane (coalesced column and value loads, streamed past the caches),
-// then U gathers of x per lane, all issued before use.
-template <int CO, int U>
-__global__ void gather_kernel(const int* __restrict__ col, const double* __restrict__ val,
-                              const double* x, double* out, long long nnz) {
-  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const long long wave = tid >> 6;
-  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  double acc = 0.0;
-  for (long long chunk = wave * 64 * U; chunk < nnz; chunk += nwaves * 64 * U) {
-    int c[U];
-    double v[U], xv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long long e = chunk + u * 64 + lane;
-      const bool in = e < nnz;
-      c[u] = in ? __builtin_nontemporal_load(col + e) : -1;
-      v[u] = in ? __builtin_nontemporal_load(val + e) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      xv[u] = c[u] < 0 ? 0.0
-                       : (CO ? __hip_atomic_load(x + c[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                             : x[c[u]]);
-#pragma unroll
-    for (int u = 0; u < U; ++u) acc += v[u] * xv[u];
-  }
-  out[tid] = acc;
-}
-
 int main(int argc, char** argv) {
   const char* what = argc > 1 ? argv[1] : "all";
   hipDeviceProp_t prop;
@@ -192,30 +134,6 @@ int main(int argc, char** argv) {
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-
-  if (!strcmp(what, "all") || !strcmp(what, "copy")) {
-    size_t bytes = (size_t)1 << 30;
-    float4 *a, *b;
-    CK(hipMalloc(&a, bytes));
-    CK(hipMalloc(&b, bytes));
-    CK(hipMemset(a, 0, bytes));
-    size_t n4 = bytes / sizeof(float4);
-    int grid = prop.multiProcessorCount * 16;
-    for (int w = 0; w < 3; ++w) copy_kernel<<<grid, 256>>>(a, b, n4);
-    CK(hipEventRecord(e0));
-    const int reps = 20;
-    for (int r = 0; r < reps; ++r) copy_kernel<<<grid, 256>>>(a, b, n4);
-    CK(hipEventRecord(e1));
-    CK(hipEventSynchronize(e1));
-    float ms;
-    CK(hipEventElapsedTime(&ms, e0, e1));
-    double gbs = 2.0 * bytes * reps / (ms * 1e-3) / 1e9;
-    printf("{\"bench\": \"copy\", \"bytes_per_launch\": %zu, \"ms_per_launch\": %.4f, \"GBps\": %.1f}\n",
-           2 * bytes, ms / reps, gbs);
-    fflush(stdout);
-    CK(hipFree(a));
-    CK(hipFree(b));
-  }
 
   if (!strcmp(what, "all") || !strcmp(what, "pingpong")) {
     int* flags;
@@ -275,43 +193,5 @@ int main(int argc, char** argv) {
     CK(hipFree(counters));
   }
 
-  if (!strcmp(what, "all") || !strcmp(what, "gather")) {
-    const int n = 1 << 20;
-    const long long nnz = 50000000;
-    int* col;
-    double *val, *x, *out;
-    const int max_threads = prop.multiProcessorCount * 32 * 64;
-    CK(hipMalloc(&col, nnz * sizeof(int)));
-    CK(hipMalloc(&val, nnz * sizeof(double)));
-    CK(hipMalloc(&x, n * sizeof(double)));
-    CK(hipMalloc(&out, (size_t)max_threads * sizeof(double)));
-    fill_gather<<<prop.multiProcessorCount * 8, 256>>>(col, val, x, nnz, n);
-    CK(hipDeviceSynchronize());
-    for (int co = 0; co < 2; ++co)
-      for (int waves : {8, 16, 32}) {
-        const int grid = prop.multiProcessorCount * waves / 4;  // 4 waves per 256-thread block
-        auto launch = [&]() {
-          if (co) gather_kernel<1, 8><<<grid, 256>>>(col, val, x, out, nnz);
-          else gather_kernel<0, 8><<<grid, 256>>>(col, val, x, out, nnz);
-        };
-        for (int w = 0; w < 3; ++w) launch();
-        const int reps = 20;
-        CK(hipEventRecord(e0));
-        for (int r = 0; r < reps; ++r) launch();
-        CK(hipEventRecord(e1));
-        CK(hipEventSynchronize(e1));
-        float ms;
-        CK(hipEventElapsedTime(&ms, e0, e1));
-        const double t = ms / reps;
-        printf("{\"bench\": \"gather\", \"coherent\": %d, \"waves_per_cu\": %d, \"n\": %d, \"gathers\": %lld, "
-               "\"ms_per_launch\": %.4f, \"Ggathers_per_s\": %.1f, \"stream_GBps\": %.1f}\n",
-               co, waves, n, nnz, t, nnz / (t * 1e-3) / 1e9, 12.0 * nnz / (t * 1e-3) / 1e9);
-        fflush(stdout);
-      }
-    CK(hipFree(col));
-    CK(hipFree(val));
-    CK(hipFree(x));
-    CK(hipFree(out));
-  }
   return 0;
 }

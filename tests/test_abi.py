@@ -109,3 +109,12 @@ def test_params_roundtrip():
     n_items_32 = s.info().n_items
     s.set_param("rows_per_item", 8)
     assert s.info().n_items > n_items_32
+
+
+def test_device_probe_argument_checks_are_host_side():
+    """Unknown probe bits and a NULL result are rejected before any device work."""
+    lib = sfm._lib()
+    r = sfm.ProbeResult()
+    assert lib.sf_device_probe(8, ctypes.byref(r), None) == 1  # SF_ERR_ARG
+    assert lib.sf_device_probe(-1, ctypes.byref(r), None) == 1  # SF_ERR_ARG
+    assert lib.sf_device_probe(sfm.SF_PROBE_COPY, None, None) == 1  # SF_ERR_ARG
