@@ -65,6 +65,15 @@ def bounds(d, fused_ms, probe):
     return out
 
 
+def path_bound(hops, t_ms, probe):
+    """The critical-path bound of a latency-bound launch: one cross-XCD hop
+    (device probe) per dependent step, and the fraction of it reached."""
+    if not probe or probe["hop_us_cross_xcd"] <= 0:
+        return None
+    cp = hops * probe["hop_us_cross_xcd"] * 1e-3
+    return {"critical_path_ms": round(cp, 4), "hops": hops, "frac_of_critical_path": round(cp / t_ms, 3)}
+
+
 def ts_bytes(n, m, nnz_l, nnz_a, vb=8):
     return nnz_l * (vb + 4) + nnz_a * (vb + 4) + (n + 1) * 4 + (m + 1) * 4 + (2 * n + m) * vb
 
@@ -290,7 +299,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = run_extras(args, sfm, synth, torch, dev, stream)
+        extras = run_extras(args, sfm, synth, torch, dev, stream, probe)
 
     cpu = None
     if not args.no_cpu:
@@ -329,7 +338,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_extras(args, sfm, synth, torch, dev, stream):
+def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
     """SpIC0 -> SpTRSV (27-point 64^3, natural and permuted), SpILU0 ->
     SpTRSV (nonsymmetric 7-point 64^3, natural and permuted), the batched
     refinement, kernel combinations 2 and 1 and the preconditioner apply on
@@ -368,7 +377,8 @@ def run_extras(args, sfm, synth, torch, dev, stream):
         out["ic0_trsv_" + name] = {"depth": s.info().depth, "fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
                                    "speedup_vs_unfused": round(tu / tf, 3),
                                    "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
-                                   "inspect_s": round(s.info().inspect_seconds, 3)}
+                                   "inspect_s": round(s.info().inspect_seconds, 3),
+                                   "bound": path_bound(s.info().depth, tf, probe)}
         log("ic0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
     for name in ("convdiff3d7_64", "convdiff3d7_64_perm"):
         a, _ = synth.workload(name)
@@ -389,7 +399,8 @@ def run_extras(args, sfm, synth, torch, dev, stream):
         out["ilu0_trsv_" + name] = {"depth": s.info().depth, "fused_ms": round(tf, 4), "unfused_ms": round(tu, 4),
                                     "speedup_vs_unfused": round(tu / tf, 3),
                                     "fused_GBps": round(nb / (tf * 1e-3) / 1e9, 1),
-                                    "inspect_s": round(s.info().inspect_seconds, 3)}
+                                    "inspect_s": round(s.info().inspect_seconds, 3),
+                                    "bound": path_bound(s.info().depth, tf, probe)}
         log("ilu0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
     # the small cache-resident case (2D 5-point 64^2): latency only, so
     # microseconds and solves per second rather than a fraction of HBM peak
@@ -404,7 +415,9 @@ def run_extras(args, sfm, synth, torch, dev, stream):
     out["small_lap2d5_64"] = {"depth": s.info().depth, "fused_us": round(tf * 1e3, 2),
                               "solves_per_s": round(1e3 / tf, 1), "unfused_us": round(tu * 1e3, 2),
                               "speedup_vs_unfused": round(tu / tf, 3),
-                              "us_per_level": round(tf * 1e3 / max(s.info().joint_depth, 1), 3)}
+                              "us_per_level": round(tf * 1e3 / max(s.info().joint_depth, 1), 3),
+                              "bound": path_bound(s.info().chunk_chain if s.info().coarsened else s.info().joint_depth,
+                                                  tf, probe)}
     log("small 2D 5-point 64^2: fused %.1f us, unfused %.1f us" % (tf * 1e3, tu * 1e3))
     out.update(run_batched(args, sfm, synth, torch, dev, time_it))
     # kernel combinations 2 (SpMV -> SpTRSV) and 1 (SpTRSV -> SpTRSV)
