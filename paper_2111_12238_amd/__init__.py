@@ -156,11 +156,15 @@ def _pattern(rowptr, col, ncols):
 
 
 def _csr_parts(m):
-    """Accept a synth.CSR-like object (rowptr, col, nrows, ncols) or a tuple."""
+    """Accept a synth.CSR-like object (rowptr, col, nrows, ncols), a scipy
+    CSR matrix, a torch sparse CSR tensor, or a (rowptr, col, ncols) tuple.
+    Column indices must be sorted within each row (sf_inspect checks)."""
     if hasattr(m, "rowptr"):
         return m.rowptr, m.col, m.ncols
     if hasattr(m, "indptr"):
         return m.indptr, m.indices, m.shape[1]
+    if hasattr(m, "crow_indices"):
+        return m.crow_indices().cpu().numpy(), m.col_indices().cpu().numpy(), m.shape[1]
     rp, ci, ncols = m
     return rp, ci, ncols
 

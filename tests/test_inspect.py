@@ -499,3 +499,25 @@ def test_static_plans_degenerate(orc):
             s_ptr, w_ptr, order = s.export_static(plan)
             assert orc.validate_static_ts(L.rowptr, L.col, A.rowptr, A.col, s_ptr, w_ptr, order) == 0, plan
             assert len(order) == L.nrows + A.nrows
+
+
+@pytest.mark.filterwarnings("ignore:Sparse CSR tensor support is in beta")
+def test_schedule_accepts_scipy_torch_and_tuples():
+    """The same pattern given as scipy CSR, torch sparse CSR, the package's
+    CSR and a (rowptr, col, ncols) tuple inspects to the same schedule; an
+    unsorted row is rejected (values follow the inspected CSR order, so the
+    pattern is never reordered silently)."""
+    import scipy.sparse as sp
+    import torch
+    L, A = synth.workload("lap2d5_64")
+    ref = sfm.Schedule(L, A).export()
+    Ls, As = L.to_scipy(), A.to_scipy()
+    Lt, At = (torch.sparse_csr_tensor(torch.as_tensor(m.indptr.astype(np.int64)),
+                                      torch.as_tensor(m.indices.astype(np.int64)),
+                                      torch.as_tensor(m.data), size=m.shape) for m in (Ls, As))
+    for lp, ap in ((Ls, As), (Lt, At), ((L.rowptr, L.col, L.ncols), (A.rowptr, A.col, A.ncols))):
+        got = sfm.Schedule(lp, ap).export()
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref))
+    bad = sp.csr_matrix((np.ones(3), np.array([1, 0, 1]), np.array([0, 1, 3])), shape=(2, 2))
+    with pytest.raises(sfm.SparseFusionError):
+        sfm.Schedule(bad, None)
