@@ -444,9 +444,17 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *                               lanes per row no longer select a kernel;
  *   "rhs_block"                 right-hand sides per DAG pass (0 = by nrhs,
  *                               else a power of two 2..64);
- *   "waves_per_cu"              persistent-grid residency target (4..32);
- *   "multi_waves_per_cu"        the same for several right-hand sides
- *                               (fused and level-set; 4..32, or 0, the
+ *   "waves_per_cu"              persistent-grid residency target (4..32); default 8,
+ *                               and for SF_IC0_TRSV / SF_ILU0_TRSV schedules, chosen at
+ *                               inspection, the smallest power of two >= 4 that holds the
+ *                               mean work items of one wavefront per CU (256 CUs);
+ *   "levelset_waves_per_cu"     residency of the executors synchronised by
+ *                               grid-wide barriers: the level-set baselines
+ *                               (SpTRSV with any number of right-hand sides,
+ *                               SpIC0, SpILU0) and the static plans (4..32,
+ *                               default 4: a barrier costs more as the grid grows);
+ *   "multi_waves_per_cu"        residency target of the fused executor for
+ *                               several right-hand sides (4..32, or 0, the
  *                               default: 8, 16 or 32 by the units per level);
  *   "multi_path"                several right-hand sides: 1 = interleaved
  *                               blocks over the level units, 2 = one chain of

@@ -427,8 +427,7 @@ sf_status exec_ts_unfused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const v
   if (s->n > 0 && s->depth > 0) {
     const int cus = std::max(1, device_cus());
     const int occ = occupancy_trsv_levelset(dtype, kb);
-    const int waves = nrhs > 1 ? multi_waves(s, kb, nrhs) : s->waves_per_cu;
-    int grid = cus * std::min(occ, std::max(1, waves * 64 / kBlockThreads));
+    int grid = cus * std::min(occ, std::max(1, s->levelset_waves_per_cu * 64 / kBlockThreads));
     SF_HIP(launch_trsv_levelset(la, dtype, grid, st));
   }
   if (Y && s->m > 0 && nrhs == 1) {
@@ -687,6 +686,21 @@ const char* sf_status_str(sf_status st) {
   return "unknown status";
 }
 
+// Default residency of the factorisation executors (SpIC0 / SpILU0 ->
+// SpTRSV): the smallest power of two from 4 to 32 waves per CU that holds
+// the mean work items of one wavefront of the DAG per CU at once.  Their
+// items are single batches whose cost is one dependency chain, so waves
+// beyond a level's items only poll; fewer leave a level's items queued.
+// Taken for the 256 CUs of an MI355X (no device query at inspection).
+int32_t factor_waves(const sf_schedule_s* s) {
+  constexpr double kCus = 256.0;
+  const double items = double(s->item_ptr.empty() ? 0 : s->item_ptr.size() - 1);
+  const double per_cu = items / double(std::max(1, s->depth)) / kCus;
+  int32_t w = 4;
+  while (w < 32 && double(w) < per_cu) w *= 2;
+  return w;
+}
+
 sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_inspect_opts* opts,
                      sf_schedule* out) {
   if (!out) return SF_ERR_ARG;
@@ -719,6 +733,7 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
     return st;
   }
   s->claim_streams = kStreams;
+  if (o.kind != SF_TRSV_SPMV) s->waves_per_cu = factor_waves(s);
   s->inspect_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = s;
   return SF_OK;
@@ -915,7 +930,7 @@ sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, 
   r = next_epoch(s, st, a.ts.ls);
   if (r != SF_OK) return r;
   const int cus = std::max(1, device_cus());
-  const int grid = cus * std::min(occupancy_static(dt), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  const int grid = cus * std::min(occupancy_static(dt), std::max(1, s->levelset_waves_per_cu * 64 / kBlockThreads));
   Timer tm(s, st);
   return hip_status(launch_static(a, dt, grid, st));
 }
@@ -988,7 +1003,7 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   a.lvl_item_ptr = d.lvl_item_ptr;
   a.depth = s->depth;
   a.solve = 0;
-  int grid = cus * std::min(occupancy_ic0(s->lanes_trsv, 1), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  int grid = cus * std::min(occupancy_ic0(s->lanes_trsv, 1), std::max(1, s->levelset_waves_per_cu * 64 / kBlockThreads));
   SF_HIP(launch_ic0_levelset(a, s->lanes_trsv, grid, st));
   if (!solve) return SF_OK;
   LevelArgs la{};
@@ -1012,7 +1027,7 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
   la.depth = s->depth;
   r = next_epoch(s, st, la.ts.ls);
   if (r != SF_OK) return r;
-  grid = cus * std::min(occupancy_trsv_levelset(0, 1), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+  grid = cus * std::min(occupancy_trsv_levelset(0, 1), std::max(1, s->levelset_waves_per_cu * 64 / kBlockThreads));
   return hip_status(launch_trsv_levelset(la, 0, grid, st));
 }
 
@@ -1066,7 +1081,7 @@ static sf_status ilu0_common(sf_schedule s, sf_dtype dtype, const void* A_val, v
   a.lvl_item_ptr = d.lvl_item_ptr;
   a.depth = s->depth;
   const int grid =
-      cus * std::min(occupancy_ilu0(s->lanes_trsv, 1), std::max(1, s->waves_per_cu * 64 / kBlockThreads));
+      cus * std::min(occupancy_ilu0(s->lanes_trsv, 1), std::max(1, s->levelset_waves_per_cu * 64 / kBlockThreads));
   r = next_epoch(s, st, a.ls);
   if (r != SF_OK) return r;
   a.solve = 0;
@@ -1347,6 +1362,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "waves_per_cu") {
     if (v < 4 || v > 32) return SF_ERR_ARG;
     s->waves_per_cu = int32_t(v);
+  } else if (k == "levelset_waves_per_cu") {
+    if (v < 4 || v > 32) return SF_ERR_ARG;
+    s->levelset_waves_per_cu = int32_t(v);
   } else if (k == "multi_waves_per_cu") {
     if (v != 0 && (v < 4 || v > 32)) return SF_ERR_ARG;
     s->multi_waves_per_cu = int32_t(v);
@@ -1409,6 +1427,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "lanes_spmv") *v = s->lanes_spmv;
   else if (k == "rhs_block") *v = s->rhs_block;
   else if (k == "waves_per_cu") *v = s->waves_per_cu;
+  else if (k == "levelset_waves_per_cu") *v = s->levelset_waves_per_cu;
   else if (k == "multi_waves_per_cu") *v = s->multi_waves_per_cu;
   else if (k == "spin_limit") *v = s->spin_limit;
   else if (k == "msp_parts") *v = s->msp_parts;

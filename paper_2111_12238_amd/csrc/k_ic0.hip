@@ -112,7 +112,7 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
       ptr[kPairRegs + 1] = (rnd == 0 && mine && a.solve) ? a.X + j : nullptr;
 #pragma unroll
       for (int e = 0; e < R; ++e) v[e] = ptr[e] ? ld_co(ptr[e]) : 0.0;
-      if constexpr (FUSED) dev::wait_ptrs<double, R>(ptr, v, lane, a.ls);
+      if constexpr (FUSED) dev::wait_ptrs<double, R, 64>(ptr, v, lane, a.ls);
 #pragma unroll
       for (int k = 0; k < kPairRegs; ++k)
         if (tu[k] >= 0) group_lds[tri_row(tu[k] >> 16) + (tu[k] & 0xffff)] = v[k];

@@ -167,6 +167,7 @@ struct sf_schedule_s {
   // Executor parameters.
   int32_t lanes_trsv = 4, lanes_spmv = 8, rhs_block = 0, waves_per_cu = 8;
   int32_t multi_waves_per_cu = 0;  // residency target of the multi-RHS executors (0: by level width)
+  int32_t levelset_waves_per_cu = 4;  // residency of the barrier-synchronised executors (level sets, static plans)
   int32_t multi_path = 0;          // several RHS: 0 auto, 1 interleaved units, 2 one item chain per column
   int32_t rows_per_item = 64, max_item_nnz = 4096;
   // wavefronts (level items) or item-chain steps (coarsened items) an SpMV

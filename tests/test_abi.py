@@ -94,12 +94,13 @@ def test_params_roundtrip():
     L, A = synth.workload("lap2d5_16")
     s = sfm.Schedule(L, A)
     assert s.get_param("multi_waves_per_cu") == 0  # by the units per level
+    assert s.get_param("levelset_waves_per_cu") == 4
     for k, v in (("lanes_trsv", 8), ("lanes_spmv", 16), ("rhs_block", 32), ("waves_per_cu", 16),
-                 ("multi_waves_per_cu", 32), ("spin_limit", 12345), ("claim_streams", 4), ("rows_per_item", 32),
+                 ("multi_waves_per_cu", 32), ("levelset_waves_per_cu", 8), ("spin_limit", 12345), ("claim_streams", 4), ("rows_per_item", 32),
                  ("no_fusion", 1)):
         s.set_param(k, v)
         assert s.get_param(k) == v
-    for k, bad in (("waves_per_cu", 2), ("multi_waves_per_cu", 64)):
+    for k, bad in (("waves_per_cu", 2), ("multi_waves_per_cu", 64), ("levelset_waves_per_cu", 3)):
         with pytest.raises(sfm.SparseFusionError):
             s.set_param(k, bad)
     with pytest.raises(sfm.SparseFusionError):

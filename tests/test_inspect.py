@@ -521,3 +521,24 @@ def test_schedule_accepts_scipy_torch_and_tuples():
     bad = sp.csr_matrix((np.ones(3), np.array([1, 0, 1]), np.array([0, 1, 3])), shape=(2, 2))
     with pytest.raises(sfm.SparseFusionError):
         sfm.Schedule(bad, None)
+
+
+def test_factorisation_residency_default():
+    """SpIC0 / SpILU0 schedules default to the smallest power of two (4..32)
+    waves per CU that holds one wavefront's mean work items per CU (256
+    CUs); SpTRSV -> SpMV schedules keep 8; set_param still overrides."""
+    cases = [("lap3d27_64", sfm.SF_IC0_TRSV), ("lap3d27_64_perm", sfm.SF_IC0_TRSV),
+             ("convdiff3d7_64", sfm.SF_ILU0_TRSV), ("convdiff3d7_64_perm", sfm.SF_ILU0_TRSV)]
+    for name, kind in cases:
+        m, _ = synth.workload(name)
+        s = sfm.Schedule(m, None, kind)
+        st = s.info()
+        per_cu = st.n_items / st.depth / 256.0
+        w = s.get_param("waves_per_cu")
+        assert w in (4, 8, 16, 32) and (w == 4 or w / 2 < per_cu) and (w == 32 or w >= per_cu), (name, w, per_cu)
+        s.set_param("waves_per_cu", 8)
+        assert s.get_param("waves_per_cu") == 8
+    got = {name: sfm.Schedule(synth.workload(name)[0], None, kind).get_param("waves_per_cu") for name, kind in cases}
+    assert got == {"lap3d27_64": 4, "lap3d27_64_perm": 16, "convdiff3d7_64": 4, "convdiff3d7_64_perm": 8}
+    L, A = synth.workload("lap2d5_64")
+    assert sfm.Schedule(L, A).get_param("waves_per_cu") == 8
