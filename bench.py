@@ -43,7 +43,7 @@ def bounds(d, fused_ms, probe):
     - gather_floor: every x read as one single-value gather at the measured
       random-gather rate (level items only: coarsened items read in-item x
       from LDS, so there it is no floor);
-    - critical_path: one cross-XCD hop per dependent step (joint wavefronts
+    - critical_path: one hop (hop_us) per dependent step (joint wavefronts
       of the level plan, items of the coarsened plan's longest chain).
     `binding` is the largest; `frac_of_binding` = binding / fused time."""
     if not probe:
@@ -55,7 +55,7 @@ def bounds(d, fused_ms, probe):
          "copy_ceiling_ms": d["bytes"] / (probe["copy_GBps"] * 1e9) * 1e3 if probe["copy_GBps"] > 0 else None,
          "gather_floor_ms": None if st.coarsened or probe["gathers_per_s"] <= 0
          else gathers / probe["gathers_per_s"] * 1e3,
-         "critical_path_ms": hops * probe["hop_us_cross_xcd"] * 1e-3 if probe["hop_us_cross_xcd"] > 0 else None,
+         "critical_path_ms": hops * hop_us(probe) * 1e-3 if hop_us(probe) > 0 else None,
          "critical_path_hops": hops}
     cands = {k: v for k, v in b.items() if k.endswith("_ms") and v is not None}
     name = max(cands, key=cands.get)
@@ -65,12 +65,18 @@ def bounds(d, fused_ms, probe):
     return out
 
 
+def hop_us(probe):
+    """The hop a dependent step is charged: across XCDs, or on one XCD when
+    no cross-XCD pair could be placed (-1 when neither was measured)."""
+    return probe["hop_us_cross_xcd"] if probe["hop_us_cross_xcd"] > 0 else probe["hop_us_same_xcd"]
+
+
 def path_bound(hops, t_ms, probe):
-    """The critical-path bound of a latency-bound launch: one cross-XCD hop
-    (device probe) per dependent step, and the fraction of it reached."""
-    if not probe or probe["hop_us_cross_xcd"] <= 0:
+    """The critical-path bound of a latency-bound launch: one hop (device
+    probe, hop_us) per dependent step, and the fraction of it reached."""
+    if not probe or hop_us(probe) <= 0:
         return None
-    cp = hops * probe["hop_us_cross_xcd"] * 1e-3
+    cp = hops * hop_us(probe) * 1e-3
     return {"critical_path_ms": round(cp, 4), "hops": hops, "frac_of_critical_path": round(cp / t_ms, 3)}
 
 

@@ -45,7 +45,9 @@ def test_bounds_without_probe_and_path_bound():
     d = _work("lap2d5_64", 1)
     assert bench.bounds(d, 1.0, None) is None
     assert bench.path_bound(10, 1.0, None) is None
-    assert bench.path_bound(10, 1.0, dict(PROBE, hop_us_cross_xcd=-1.0)) is None
+    assert bench.path_bound(10, 1.0, dict(PROBE, hop_us_cross_xcd=-1.0, hop_us_same_xcd=-1.0)) is None
+    # no cross-XCD pair placed: the same-XCD hop is charged
+    assert bench.path_bound(10, 1.0, dict(PROBE, hop_us_cross_xcd=-1.0))["critical_path_ms"] == 0.004
     p = bench.path_bound(200, 0.5, PROBE)
     assert p == {"critical_path_ms": 0.1, "hops": 200, "frac_of_critical_path": 0.2}
 
