@@ -2,7 +2,7 @@
 
 Every translation unit under ``csrc/`` is compiled with hipcc for gfx950;
 kernels get ``-packed-fp32-ops`` disabled (packed FP32 instructions are not
-generated).  The result is placed next to this file so it travels with the
+generated) and the atomic optimizer off (see COMMON).  The result is placed next to this file so it travels with the
 source tree.
 """
 from __future__ import annotations
@@ -21,8 +21,12 @@ MICRO = os.path.join(BUILD, "sf_microbench")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
+# -amdgpu-atomic-optimizer-strategy=None: the executors' work-claiming
+# atomics are issued by one lane; the optimizer's wave-wide rewrite of them
+# would wait for each result at once instead of where it is first used.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
           "-Wno-unused-command-line-argument"]
 

@@ -53,14 +53,24 @@ __device__ __forceinline__ void reset_next_launch(const LaunchState& ls) {
 // its indices in increasing order and blocks 0..streams-1 are resident from
 // the start, so the smallest claimed-but-unfinished index only waits on
 // finished work: the claim order is deadlock-free at any grid size.
-__device__ __forceinline__ int32_t claim(const LaunchState& ls, int lane) {
+// A claim in two halves: claim_issue sends the atomic (lane 0) and returns
+// its still-pending result; claim_ticket turns that into the ticket and is
+// where the wavefront waits for it.  Loads issued in between overlap the
+// atomic's round trip.
+__device__ __forceinline__ int32_t claim_issue(const LaunchState& ls, int lane) {
   const int s = blockIdx.x % ls.streams;
   int32_t k = 0;
   if (lane == 0)
     k = __hip_atomic_fetch_add(ls.state + ctr_off(ls.epoch & 1, s), 1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-  k = __builtin_amdgcn_readfirstlane(k);
-  return k * ls.streams + s;
+  return k;
+}
+__device__ __forceinline__ int32_t claim_ticket(const LaunchState& ls, int32_t raw) {
+  const int s = blockIdx.x % ls.streams;
+  return __builtin_amdgcn_readfirstlane(raw) * ls.streams + s;
+}
+__device__ __forceinline__ int32_t claim(const LaunchState& ls, int lane) {
+  return claim_ticket(ls, claim_issue(ls, lane));
 }
 
 // Count finished wavefronts; true for the last one of the grid.

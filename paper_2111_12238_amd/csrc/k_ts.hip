@@ -51,20 +51,18 @@ __device__ __forceinline__ unsigned long long* trace_slots(const TsArgs& a, int 
 // (TRSV = true) or SpMV rows.  VEC selects how x is read (stream.h): 2 in
 // the fused executor (readiness protocol), 1 in the level-set baseline
 // (after a grid barrier), 0 in the unfused SpMV (x final before the launch).
+// item_stream_rows takes each lane's row id and CSR range (order[q0 + lane]
+// and qrng[q0 + lane]) already loaded; item_stream loads them itself.
 template <typename T, bool TRSV, int VEC>
-__device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
-                                            int it = -1) {
+__device__ __forceinline__ void item_stream_rows(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
+                                                 unsigned long long* tr, int id, int2 rg) {
   const int nr = q1 - q0;
   const bool mine = lane < nr;
   const T* __restrict__ val = static_cast<const T*>(TRSV ? a.Lv : a.Av);
   T* X = static_cast<T*>(a.X);
-  unsigned long long* tr = trace_slots(a, it);
-  if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
-  const int id = mine ? a.order[q0 + lane] : 0;
   const int row = TRSV ? id : id - a.n;
   // the row's range comes with its claim position (no row-pointer round trip);
   // an SpTRSV range stops before the diagonal, which sits at r1
-  const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
   const int r0 = rg.x, r1 = rg.y;
   T acc = T(0), dii = T(1);
   if (TRSV && mine) {
@@ -80,21 +78,28 @@ __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
+template <typename T, bool TRSV, int VEC>
+__device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
+                                            int it = -1) {
+  const bool mine = lane < q1 - q0;
+  unsigned long long* tr = trace_slots(a, it);
+  if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
+  const int id = mine ? a.order[q0 + lane] : 0;
+  const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
+  item_stream_rows<T, TRSV, VEC>(a, q0, q1, lane, w, tr, id, rg);
+}
+
 // Coarsened SpTRSV item (rows on several local wavefronts, sorted by local
 // wavefront): dev::chunk_solve (stream.h) over the rows' off-diagonals.
+// Each lane's row, CSR range and local wavefront come loaded, with the
+// item's last local wavefront.
 template <typename T>
-__device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w, T* xl,
-                                           int it) {
+__device__ __forceinline__ void item_chunk_rows(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w, T* xl,
+                                                unsigned long long* tr, int row, int2 rg, int myloc, int maxloc) {
   const int nr = q1 - q0;
   const bool mine = lane < nr;
   const T* __restrict__ val = static_cast<const T*>(a.Lv);
-  unsigned long long* tr = trace_slots(a, it);
-  if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
-  const int row = mine ? a.order[q0 + lane] : 0;
-  const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
   const int r0 = rg.x, r1 = rg.y;  // off-diagonals; the diagonal sits at r1
-  const int myloc = mine ? int(a.lloc[q0 + lane]) : 0;
-  const int maxloc = int(a.lloc[q1 - 1]);
   const T acc = mine ? static_cast<const T*>(a.B)[row] : T(0);
   const T dii = mine ? ld_stream(val + r1) : T(1);
   dev::chunk_solve<T, false>(nr, r0, r1 - r0, myloc, maxloc, acc, dii, a.Lci, nullptr, val, a.eloc,
@@ -102,12 +107,28 @@ __device__ __forceinline__ void item_chunk(const TsArgs& a, int q0, int q1, int 
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
-// The next ticket is claimed before the current item is processed, so the
-// claim's round trip overlaps the item's loads.  Deadlock freedom still
-// holds: a wave's prefetched ticket is larger than the item it works on, so
-// the smallest claimed-but-unfinished item is always one being processed.
-// With a coarsened plan (a.lloc != nullptr) SpTRSV items whose rows span
-// several local wavefronts run through item_chunk.
+// Work item `it` of a kernel whose items run in claim order (item_list
+// maps the claim index u to the item when given): its claim positions
+// [q0, q1).  Every lane loads them (uniform addresses).
+__device__ __forceinline__ void item_range(const TsArgs& a, int u, int& it, int& q0, int& q1) {
+  it = a.item_list ? a.item_list[u] : u;
+  q0 = a.item_ptr[it];
+  q1 = a.item_ptr[it + 1];
+}
+
+// Per item the wavefront runs one chain of dependent loads: the rows' ids,
+// ranges and local wavefronts (together), the rows' entries, then the x
+// values.  Around it:
+// - the next ticket is claimed right after the row loads are issued and
+//   waited for with them, so the claim's round trip overlaps theirs;
+// - the next item's range is loaded as soon as its ticket is known, during
+//   this item, so the next item starts with its row loads;
+// - the item's kind (SpTRSV or SpMV rows) is read off its first row's id.
+// Deadlock freedom still holds: a wave's prefetched ticket is larger than
+// the item it works on, so the smallest claimed-but-unfinished item is
+// always one being processed.  With a coarsened plan (a.lloc != nullptr)
+// SpTRSV items whose rows span several local wavefronts run through
+// item_chunk_rows.
 template <typename T>
 __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
   __shared__ WaveLds<T> lds[kWaves];
@@ -123,24 +144,46 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
   const int nc = a.col_units > 1 ? a.col_units : 1;
   const int total = a.n_work * nc;
   int t = dev::claim(a.ls, lane);
+  int it = 0, q0 = 0, q1 = 0;
+  if (t < total) item_range(a, t / nc, it, q0, q1);
   while (t < total) {
-    const int tn = dev::claim(a.ls, lane);
-    const int u = t / nc, c = t - u * nc;
+    const int c = t - (t / nc) * nc;
     TsArgs ac = a;
     if (nc > 1) {
       ac.B = static_cast<const T*>(a.B) + size_t(c) * size_t(a.ldb);
       ac.X = static_cast<T*>(a.X) + size_t(c) * size_t(a.ldx);
       if (a.Y) ac.Y = static_cast<T*>(a.Y) + size_t(c) * size_t(a.ldy);
     }
-    const int it = a.item_list ? a.item_list[u] : u;
-    const int q0 = a.item_ptr[it], q1 = a.item_ptr[it + 1];
-    if (a.order[q0] < a.n) {
-      if (a.lloc && a.lloc[q1 - 1] != 0) item_chunk<T>(ac, q0, q1, lane, w, xl, it);
-      else item_stream<T, true, 2>(ac, q0, q1, lane, w, it);
+    unsigned long long* tr = trace_slots(a, it);
+    if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
+    const bool mine = lane < q1 - q0;
+    const int id = mine ? a.order[q0 + lane] : 0;
+    const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
+    const int myloc = (a.lloc && mine) ? int(a.lloc[q0 + lane]) : 0;
+    // the item's last local wavefront, on lane 0 (a uniform load would be
+    // waited for at once, to move it to a scalar register)
+    const int lastloc = (a.lloc && lane == 0) ? int(a.lloc[q1 - 1]) : 0;
+    // the next ticket's atomic goes out after the row loads (a wait for
+    // anything issued before it would otherwise wait for it too) and is
+    // waited for with them: an empty asm statement ties its result to the
+    // row loads, so the conversion cannot be scheduled ahead of them
+    const int32_t raw = dev::claim_issue(a.ls, lane);
+    int32_t pending = raw;
+    __asm__ volatile("" : "+v"(pending) : "v"(id), "v"(lastloc));
+    const int tn = dev::claim_ticket(a.ls, pending);
+    const int maxloc = __shfl(lastloc, 0, 64);
+    int itn = 0, q0n = 0, q1n = 0;
+    if (tn < total) item_range(a, tn / nc, itn, q0n, q1n);
+    if (__shfl(id, 0, 64) < a.n) {  // lane 0 holds the item's first row (an item has >= 1 row)
+      if (maxloc != 0) item_chunk_rows<T>(ac, q0, q1, lane, w, xl, tr, id, rg, myloc, maxloc);
+      else item_stream_rows<T, true, 2>(ac, q0, q1, lane, w, tr, id, rg);
     } else {
-      item_stream<T, false, 2>(ac, q0, q1, lane, w, it);
+      item_stream_rows<T, false, 2>(ac, q0, q1, lane, w, tr, id, rg);
     }
     t = tn;
+    it = itn;
+    q0 = q0n;
+    q1 = q1n;
   }
 }
 
