@@ -51,6 +51,24 @@ def test_27pt_12cube(orc, perm):
     assert np.array_equal(lu, lr) and np.array_equal(xu, xr)
 
 
+@pytest.mark.parametrize("lanes,name", [(4, "lap2d5_64"), (8, "lap2d9_64")])
+def test_small_lane_groups_bit_identical(orc, lanes, name):
+    """Rows of at most 4 and 8 entries on groups of 4 and 8 lanes (several
+    groups share one 16-lane DPP row): L and x bit-identical to the oracle."""
+    announce("ic0 fused %s lanes=%d" % (name, lanes))
+    a = synth.laplacian_2d5(64, 64, 4.0) if name == "lap2d5_64" else synth.laplacian_2d9(64, 64, 8.0)
+    Lp = synth.lower(a)
+    assert np.diff(Lp.rowptr).max() <= lanes
+    b = synth.vec_normal(Lp.nrows, seed=4)
+    s = sfm.Schedule(Lp, None, sfm.SF_IC0_TRSV, lanes_per_row=lanes)
+    assert s.get_param("lanes_trsv") == lanes
+    lr, xr, fail = oracle_it(orc, Lp, b)
+    assert fail == -1
+    for unfused in (False, True):
+        l, x, info = run_ic0(s, Lp, b, unfused=unfused)
+        assert info == -1 and np.array_equal(l, lr) and np.array_equal(x, xr), unfused
+
+
 def test_tridiagonal_closed_form():
     """IC0 of tridiag(-1, 2, -1) is its exact Cholesky factor:
     L_ii = sqrt((i+1)/i), L_{i+1,i} = -sqrt(i/(i+1)) (1-based)."""
