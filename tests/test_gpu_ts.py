@@ -498,3 +498,25 @@ def test_multi_rhs_paths_bit_exact(orc, path, coarsen):
         sfm.sync_status(s)
         assert np.array_equal(host(X), xr) and np.array_equal(host(Y), yr), unfused
         assert bool((Xbuf[:, n:] == -7.0).all()) and bool((Ybuf[:, 4000:] == -9.0).all()), unfused
+
+
+def test_multi_rhs_offset_limit_reported():
+    """Several right-hand sides address a block's interleaved x with 32-bit
+    offsets: n * rhs_block >= 2^31 (here 2^25 rows and 64 right-hand sides)
+    is reported as SF_ERR_UNSUPPORTED by the fused and the level-set entry,
+    before anything is launched (the buffers passed are one element long and
+    are never touched)."""
+    announce("ts multi-RHS 32-bit offset limit (n = 2^25, 64 RHS)")
+    import torch
+    n = 1 << 25
+    rp = np.arange(n + 1, dtype=np.int32)
+    s = sfm.Schedule((rp, rp[:-1].copy(), n), (np.zeros(1, np.int32), np.zeros(0, np.int32), n))
+    assert s.info().coarsened == 0 and s.get_param("multi_path") == 0  # interleaved units for 64 RHS
+    lv, b, x = (torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(3))
+    lib = sfm._lib()
+    for fn in (lib.sf_exec_trsv_spmv, lib.sf_exec_unfused_trsv_spmv):
+        st = fn(s.handle, 0, lv.data_ptr(), None, b.data_ptr(), n, 64, x.data_ptr(), n, None, 0, None)
+        assert st == 10, st  # SF_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    s.free()
