@@ -57,6 +57,7 @@ def _bind(lib):
         "orc_joint_order_ts": (None, [_c_int, _i32p, _c_int, _i32p, _i32p]),
         "orc_validate_ts": (_c_int, [_c_int, _i32p, _i32p, _c_int, _i32p, _i32p, _i32p, _c_int,
                                      _i32p, _c_int]),
+        "orc_validate_factor_solve": (_c_int, [_c_int, _i32p, _i32p, _i32p, _c_int, _i32p]),
         "orc_validate_static_ts": (_c_int, [_c_int, _i32p, _i32p, _c_int, _i32p, _i32p, _c_int, _i32p,
                                             _c_int, _i32p, _i32p]),
         "orc_reuse_ts": (ctypes.c_double, [_c_int, _c_int, _c_int, _c_int]),
@@ -221,6 +222,15 @@ class Oracle:
         order, item_ptr = _i32(order), _i32(item_ptr)
         return self.lib.orc_validate_ts(len(lrp) - 1, lrp, _ptr(lci), len(arp) - 1, arp, _ptr(aci),
                                        _ptr(order), len(item_ptr) - 1, item_ptr, int(allow_intra))
+
+    def validate_factor_solve(self, rp, ci, order, item_ptr) -> int:
+        """0 if the (order, item_ptr) schedule of a factorisation -> SpTRSV
+        pair (ids 0..n-1 factor rows, n..2n-1 solve rows; F = I) respects
+        every edge of the stored entries below the diagonal, else a rule
+        code."""
+        rp, ci, order, item_ptr = _i32(rp), _i32(ci), _i32(order), _i32(item_ptr)
+        return self.lib.orc_validate_factor_solve(len(rp) - 1, rp, _ptr(ci), _ptr(order), len(item_ptr) - 1,
+                                                  item_ptr)
 
     def validate_static_ts(self, lrp, lci, arp, aci, s_ptr, w_ptr, order) -> int:
         """0 if the two-level static schedule (s-partitions in sequence,

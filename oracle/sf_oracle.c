@@ -383,6 +383,49 @@ int orc_validate_ts(int n, const int32_t* lrp, const int32_t* lci, int m,
   return rc;
 }
 
+/* Schedule validity for a factorisation -> SpTRSV pair whose second kernel
+ * reads only row i of the first at its row i (F = I: SpIC0 -> SpTRSV,
+ * Table 2 combination 5, and SpILU0 -> SpTRSV, combination 6).  Iteration
+ * ids: 0..n-1 are factor rows, n..2n-1 are solve rows.  Each stored entry
+ * (i, j) with j < i of the factor's pattern is two edges, factor row j ->
+ * factor row i (row i is eliminated against the final row j) and solve
+ * row j -> solve row i (x_j is read); F = I adds factor row i -> solve row
+ * i.  The iterations of one item run together, so an edge between two
+ * items must go from an earlier item to a later one; the only edge allowed
+ * inside an item is factor row i -> solve row i with the factor row listed
+ * first (the interleaved packing of Sec. 2.3).  Valid iff order is a
+ * permutation of 0..2n-1, item_ptr a cover of it by non-empty items, and
+ * every edge is respected.  Returns 0 if valid, else a positive code naming
+ * the first violated rule. */
+int orc_validate_factor_solve(int n, const int32_t* rp, const int32_t* ci, const int32_t* order,
+                              int n_items, const int32_t* item_ptr) {
+  int N = 2 * n;
+  if (n_items < 0 || item_ptr[0] != 0 || item_ptr[n_items] != N) return 1;
+  for (int t = 0; t < n_items; ++t) if (item_ptr[t + 1] <= item_ptr[t]) return 2;
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+  int32_t* item = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+  for (int u = 0; u < N; ++u) pos[u] = -1;
+  for (int t = 0; t < n_items; ++t)
+    for (int q = item_ptr[t]; q < item_ptr[t + 1]; ++q) {
+      int u = order[q];
+      if (u < 0 || u >= N || pos[u] >= 0) { free(pos); free(item); return 3; }
+      pos[u] = q;
+      item[u] = t;
+    }
+  int rc = 0;
+  for (int i = 0; i < n && !rc; ++i) {
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      if (j >= i) continue;
+      if (!(item[j] < item[i])) { rc = 4; break; }
+      if (!(item[n + j] < item[n + i])) { rc = 5; break; }
+    }
+    if (!rc && !(item[i] < item[n + i] || (item[i] == item[n + i] && pos[i] < pos[n + i]))) rc = 6;
+  }
+  free(pos); free(item);
+  return rc;
+}
+
 /* Validity of a static two-level schedule of the SpTRSV -> SpMV pair, as
  * a fused partitioning (Sec. 3.1) executes it: the nb s-partitions run one
  * after another, with a synchronisation between them; the w-partitions of

@@ -97,3 +97,57 @@ def static_schedule_runs(n_vertices, preds, s_ptr, w_ptr, order):
                     return False
                 done.add(v)
     return True
+
+
+def item_schedule_runs(n_vertices, preds, order, item_ptr, together):
+    """Simulate an item schedule: items run one after another; the
+    iterations of one item start together and read their inputs as the item
+    starts, except that ``together(u, v)`` names the pairs (u, v) one item
+    runs back to back on the same lanes (v then sees u's result if u is
+    listed first).  True iff every vertex runs exactly once and every
+    predecessor's result exists when it is read."""
+    if sorted(order) != list(range(n_vertices)):
+        return False
+    if item_ptr[0] != 0 or item_ptr[-1] != len(order):
+        return False
+    if any(item_ptr[t + 1] <= item_ptr[t] for t in range(len(item_ptr) - 1)):
+        return False
+    done = set()
+    for t in range(len(item_ptr) - 1):
+        members = order[item_ptr[t]:item_ptr[t + 1]]
+        for k, v in enumerate(members):
+            earlier_here = set(members[:k])
+            for u in preds[v]:
+                if u in done:
+                    continue
+                if u in earlier_here and together(u, v):
+                    continue
+                return False
+        done.update(members)
+    return True
+
+
+def csr_status(rp, ci, nrows, ncols, lower):
+    """Structural verdict of a CSR pattern through scipy's own format
+    checks: 1 malformed (row pointers, column range, order or duplicates),
+    2 an entry above the diagonal, 3 a row without its diagonal, 0 valid
+    (2 and 3 only when ``lower``)."""
+    import scipy.sparse as sp
+    rp = np.asarray(rp, np.int64)
+    ci = np.asarray(ci, np.int64)
+    if len(rp) != nrows + 1 or rp[0] != 0 or np.any(np.diff(rp) < 0) or rp[-1] > len(ci):
+        return 1
+    ci = ci[:rp[-1]]
+    try:
+        a = sp.csr_matrix((np.ones(len(ci)), ci, rp), shape=(nrows, ncols))
+        a.check_format(full_check=True)
+    except ValueError:
+        return 1
+    if not a.has_canonical_format:  # sorted columns without duplicates in every row
+        return 1
+    if lower:
+        if sp.triu(a, 1).nnz:
+            return 2
+        if np.any(a.diagonal() == 0):
+            return 3
+    return 0

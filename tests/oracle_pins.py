@@ -339,6 +339,145 @@ def pin_validator(orc):
     assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, merged, allow_intra=True) == 0
 
 
+def _broken_patterns(rng, n):
+    """A valid lower-triangular pattern (random, diagonal last in each row)
+    and copies of it with one planted structural fault each."""
+    d = np.tril((rng.random((n, n)) < 0.3).astype(float), -1) + np.eye(n)
+    a = sp.csr_matrix(d)
+    a.sort_indices()
+    rp, ci = a.indptr.astype(np.int32), a.indices.astype(np.int32)
+    out = [("valid", rp, ci)]
+    rows = [r for r in range(n) if rp[r + 1] - rp[r] >= 2]
+    if rows:
+        r = int(rng.choice(rows))
+        c = ci.copy()
+        c[rp[r]], c[rp[r] + 1] = c[rp[r] + 1], c[rp[r]]
+        out.append(("unsorted", rp, c))
+        c = ci.copy()
+        c[rp[r] + 1] = c[rp[r]]
+        out.append(("duplicate", rp, c))
+    c = ci.copy()
+    c[int(rng.integers(0, len(c)))] = n + int(rng.integers(0, 3))
+    out.append(("column_range", rp, c))
+    c = ci.copy()
+    c[int(rng.integers(0, len(c)))] = -1 - int(rng.integers(0, 3))
+    out.append(("negative_column", rp, c))
+    if n >= 2:
+        p = rp.copy()
+        k = int(rng.integers(1, n + 1))
+        p[k] = p[k - 1] - 1  # row k - 1 ends before it starts; the rows before it are untouched
+        out.append(("rowptr_decreasing", p, ci))
+    p = rp.copy()
+    p[0] = 1
+    out.append(("rowptr_start", p, ci))
+    # an entry above the diagonal: row r gets column n - 1 appended after its diagonal
+    r = int(rng.integers(0, n - 1)) if n >= 2 else None
+    if r is not None:
+        dd = d.copy()
+        dd[r, n - 1] = 1.0
+        b = sp.csr_matrix(dd)
+        b.sort_indices()
+        out.append(("upper", b.indptr.astype(np.int32), b.indices.astype(np.int32)))
+    # a row without its diagonal
+    dd = d.copy()
+    dd[int(rng.integers(0, n)), :] = 0.0
+    dd[:, :] = np.where(np.eye(n, dtype=bool) & (dd.sum(1, keepdims=True) == 0), 0.0, dd)
+    b = sp.csr_matrix(dd)
+    b.sort_indices()
+    out.append(("no_diagonal", b.indptr.astype(np.int32), b.indices.astype(np.int32)))
+    return out
+
+
+def pin_csr_checks_against_scipy(orc):
+    """The structural checks agree with scipy's CSR format checks
+    (row pointers, column range, sorted columns without duplicates) and with
+    the triangular and diagonal tests of the lower-triangular case, on
+    random patterns with one planted fault each: malformed CSR is 1, an
+    entry above the diagonal 2, a row without its diagonal 3, valid 0."""
+    rng = np.random.default_rng(11)
+    seen = set()
+    for _ in range(60):
+        n = int(rng.integers(1, 9))
+        for name, rp, ci in _broken_patterns(rng, n):
+            want_l = bf.csr_status(rp, ci, n, n, lower=True)
+            want_g = bf.csr_status(rp, ci, n, n, lower=False)
+            assert orc.check_lower(rp, ci) == want_l, (name, rp, ci)
+            assert orc.check_csr(rp, ci, n) == want_g, (name, rp, ci)
+            seen.add((name, want_l))
+            if name == "valid":
+                # the same pattern read as a general matrix with fewer columns
+                nc = int(ci.max()) if len(ci) else 0
+                assert orc.check_csr(rp, ci, nc) == bf.csr_status(rp, ci, n, nc, lower=False)
+    names = {k for k, _ in seen}
+    assert {"valid", "unsorted", "duplicate", "column_range", "upper", "no_diagonal"} <= names
+    assert {v for _, v in seen} == {0, 1, 2, 3}
+
+
+def _level_items_it(orc, L):
+    """Canonical factor -> solve schedule: per level, each row's factor
+    iteration directly followed by its solve iteration, one item per level."""
+    n = L.nrows
+    lv, depth = orc.levels(L.rowptr, L.col)
+    rows = np.argsort(lv, kind="stable")
+    order = np.empty(2 * n, np.int32)
+    order[0::2] = rows
+    order[1::2] = rows + n
+    counts = np.bincount(lv, minlength=depth)
+    item_ptr = np.concatenate([[0], 2 * np.cumsum(counts)]).astype(np.int32)
+    return order, item_ptr
+
+
+def pin_factor_solve_validator(orc):
+    """The factorisation -> SpTRSV schedule check (F = I) agrees with a
+    simulation of item-by-item execution on 400 tiny random DAGs and
+    schedules, accepts the canonical per-level schedule of a stencil and
+    rejects its mutations: dependent rows in one item, a solve row ahead of
+    its factor row, a dependent row moved ahead of its input, a dropped
+    iteration."""
+    rng = np.random.default_rng(5)
+    n_valid = 0
+    for _ in range(400):
+        n = int(rng.integers(1, 6))
+        ld = np.tril((rng.random((n, n)) < 0.4).astype(float), -1) + np.eye(n)
+        L = synth.from_scipy(sp.csr_matrix(ld))
+        preds = [[j for j in range(i) if ld[i, j]] for i in range(n)]
+        preds += [[j + n for j in range(i) if ld[i, j]] + [i] for i in range(n)]
+        if rng.random() < 0.5:
+            order, item_ptr = _level_items_it(orc, L)
+            order, item_ptr = list(order), list(item_ptr)
+            if rng.random() < 0.5:  # split or merge some items
+                cuts = sorted(set(int(c) for c in rng.integers(1, 2 * n, int(rng.integers(0, 3)))) |
+                              set(item_ptr[1:-1]))
+                if rng.random() < 0.5 and cuts:
+                    cuts.remove(cuts[int(rng.integers(0, len(cuts)))])
+                item_ptr = [0] + cuts + [2 * n]
+        else:
+            order = [int(v) for v in rng.permutation(2 * n)]
+            k = int(rng.integers(0, 2 * n))
+            item_ptr = [0] + sorted(set(int(c) for c in rng.integers(1, 2 * n, k))) + [2 * n]
+        want = bf.item_schedule_runs(2 * n, preds, order, item_ptr, lambda u, v: u < n and v == u + n)
+        got = orc.validate_factor_solve(L.rowptr, L.col, np.array(order, np.int32), np.array(item_ptr, np.int32))
+        assert (got == 0) == want, (got, want, order, item_ptr, ld)
+        n_valid += int(want)
+    assert 40 <= n_valid <= 360
+    a = synth.laplacian_3d27(4, 3, 3, 26.1)
+    L = synth.lower(a)
+    n = L.nrows
+    order, ip = _level_items_it(orc, L)
+    assert orc.validate_factor_solve(L.rowptr, L.col, order, ip) == 0
+    assert orc.validate_factor_solve(L.rowptr, L.col, order, np.array([0, 2 * n], np.int32)) != 0
+    sw = order.copy()
+    sw[0], sw[1] = sw[1], sw[0]                      # solve row before its factor row
+    assert orc.validate_factor_solve(L.rowptr, L.col, sw, ip) != 0
+    mv = order.copy()
+    k = int(np.nonzero(mv == n - 1)[0][0])           # the last row's factor iteration ...
+    mv[[0, k]] = mv[[k, 0]]                          # ... swapped into the first item
+    assert orc.validate_factor_solve(L.rowptr, L.col, mv, ip) != 0
+    dup = order.copy()
+    dup[-1] = dup[0]
+    assert orc.validate_factor_solve(L.rowptr, L.col, dup, ip) != 0
+
+
 def _random_static_case(rng):
     """A tiny joint SpTRSV -> SpMV DAG and a two-level schedule of it: half
     the time cut from a random topological order (often valid), otherwise

@@ -270,6 +270,33 @@ def test_ic0_schedule(orc):
     assert np.all(item[n + L.col[off]] < item[n + rows[off]])    # SpTRSV j -> SpTRSV i
     assert abs(s.info().reuse_ratio - orc.reuse_it(n, L.nnz)) < 1e-15
     assert s.info().reuse_ratio >= 1.0
+    assert orc.validate_factor_solve(L.rowptr, L.col, order, ip) == 0
+
+
+@pytest.mark.parametrize("case", ["lap3d27_8", "lap3d27_8_perm", "random_spd", "lanes_4", "lanes_64"])
+def test_factor_solve_schedules_oracle_valid(orc, case):
+    """Every SpIC0 -> SpTRSV and SpILU0 -> SpTRSV schedule the inspector
+    produces passes the oracle's factor -> solve check (every dependence to a
+    later item, each row's solve after its factor row in the same item), at
+    every lanes-per-row setting; the canonical levels equal the oracle's."""
+    if case.startswith("lap3d27"):
+        a = synth.laplacian_3d27(8, 8, 8, 26.1)
+        if case.endswith("perm"):
+            a = synth.permute_sym(a, synth.permutation(a.nrows, seed=3))
+    elif case == "random_spd":
+        a = synth.random_spd(3000, seed=4, lo=2, hi=6)
+    else:
+        a = synth.laplacian_3d27(6, 7, 5, 26.1)
+    L = synth.lower(a)
+    lanes = {"lanes_4": 4, "lanes_64": 64}.get(case, 0)
+    s = sfm.Schedule(L, None, sfm.SF_IC0_TRSV, lanes_per_row=lanes)
+    level, order, ip = s.export()
+    assert np.array_equal(level, orc.levels(L.rowptr, L.col)[0])
+    assert orc.validate_factor_solve(L.rowptr, L.col, order, ip) == 0
+    # the same pattern as a (symmetric) SpILU0 input, whole matrix
+    s2 = sfm.Schedule(a, None, sfm.SF_ILU0_TRSV, lanes_per_row=max(lanes, 32) if lanes else 0)
+    _, order2, ip2 = s2.export()
+    assert orc.validate_factor_solve(a.rowptr, a.col, order2, ip2) == 0
 
 
 def _err(fn):
@@ -359,6 +386,7 @@ def test_ilu0_schedule(orc):
         st = s.info()
         assert st.lanes_per_row >= np.diff(a.rowptr).max()
         assert want == _ilu_pair_count(s)
+        assert orc.validate_factor_solve(a.rowptr, a.col, order, ip) == 0
 
 
 def _ilu_pair_count(s):
@@ -542,3 +570,26 @@ def test_factorisation_residency_default():
     assert got == {"lap3d27_64": 4, "lap3d27_64_perm": 16, "convdiff3d7_64": 4, "convdiff3d7_64_perm": 8}
     L, A = synth.workload("lap2d5_64")
     assert sfm.Schedule(L, A).get_param("waves_per_cu") == 8
+
+
+def test_structural_verdicts_match_oracle(orc):
+    """sf_inspect's structural verdict on L equals the oracle's check on
+    random patterns with one planted fault each (malformed CSR, an entry
+    above the diagonal, a row without its diagonal, or none)."""
+    import oracle_pins
+    want_name = {0: None, 1: "SF_ERR_CSR", 2: "SF_ERR_NOT_LOWER", 3: "SF_ERR_ZERO_DIAG"}
+    rng = np.random.default_rng(23)
+    seen = set()
+    for _ in range(40):
+        n = int(rng.integers(1, 9))
+        for name, rp, ci in oracle_pins._broken_patterns(rng, n):
+            code = orc.check_lower(rp, ci)
+            A = synth.from_scipy(sp.identity(n, format="csr"))
+            try:
+                sfm.Schedule((rp, ci, n), A).free()
+                got = None
+            except sfm.SparseFusionError as e:
+                got = e.name
+            assert got == want_name[code], (name, rp, ci)
+            seen.add(code)
+    assert seen == {0, 1, 2, 3}

@@ -47,6 +47,16 @@ MUTANTS = {
     "ilu0_sign": ("if (ji == jk) { lu[pi] -= lu[p] * lu[pk];", "if (ji == jk) { lu[pi] += lu[p] * lu[pk];"),
     "ilu0_wrong_operand": ("if (ji == jk) { lu[pi] -= lu[p] * lu[pk];", "if (ji == jk) { lu[pi] -= lu[p] * lu[pi];"),
     "ilu0_last_failure": ("if (!(d != 0.0) && fail < 0) fail = i;", "if (!(d != 0.0)) fail = i;"),
+    "check_lower_upper_off_by_one": ("      if (j > i) return ORC_NOT_LOWER;", "      if (j > i + 1) return ORC_NOT_LOWER;"),
+    "check_lower_no_diag_test": ("    if (!has_diag) return ORC_NO_DIAG;", "    (void)has_diag;"),
+    "check_csr_range": ("if (j < 0 || j >= ncols) return ORC_BAD_CSR;", "if (j < 0 || j > ncols) return ORC_BAD_CSR;"),
+    "check_csr_accepts_duplicates": (
+        "if (j < 0 || j >= ncols) return ORC_BAD_CSR;\n      if (p > rp[i] && ci[p - 1] >= j)",
+        "if (j < 0 || j >= ncols) return ORC_BAD_CSR;\n      if (p > rp[i] && ci[p - 1] > j)"),
+    "factor_solve_intra_factor": ("if (!(item[j] < item[i])) { rc = 4; break; }",
+                                  "if (!(item[j] <= item[i])) { rc = 4; break; }"),
+    "factor_solve_no_solve_edge": ("if (!(item[n + j] < item[n + i])) { rc = 5; break; }", ""),
+    "factor_solve_no_f_edge": ("(item[i] == item[n + i] && pos[i] < pos[n + i])", "(item[i] == item[n + i])"),
     "unit_lower_divides": ("      if (ci[p] < i) s -= v[p] * y[ci[p]];\n    y[i] = s;",
                            "      if (ci[p] < i) s -= v[p] * y[ci[p]];\n    y[i] = s / 7.0;"),
 }
