@@ -157,7 +157,10 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A,
                      const sf_inspect_opts* opts, sf_schedule* out);
 
 /* Release a schedule and every host and device buffer it owns.  Waits for
- * the device to finish work that uses it.  NULL is accepted. */
+ * the work of the last executor call made with it (an event recorded on
+ * that call's stream), not for the whole device.  Call it before the HIP
+ * runtime is torn down (e.g. not from a static destructor).  NULL is
+ * accepted. */
 sf_status sf_schedule_free(sf_schedule s);
 
 /* Fill *st with the schedule's summary. */
@@ -486,8 +489,19 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* value);
 
 /*
  * sf_autotune — time executor variants on the device with the caller's
- * data and keep the fastest (lanes per row, RHS block width, residency).
- * Results are cached in the schedule.  Synchronises the stream.
+ * data and keep the fastest: a coordinate search over the plan (level or
+ * coarsened items), the several-RHS path and block width, the SpMV slack
+ * delay, rows per item, the item cost budget and the residency (waves per
+ * CU of the single- and multi-RHS executors).  The work done once per
+ * matrix is amortised over many executions (the paper's inspector-executor
+ * split, Sec. 2 and its NER metric, Sec. 4).  The chosen parameters are left
+ * set on the schedule (sf_get_param reads them) and cached for the process,
+ * keyed by the patterns' fingerprint (sizes, depth and a hash of both CSR
+ * patterns), dtype, nrhs and whether Y is given: a later call with an equal
+ * key -- on this or another schedule -- applies them without timing and sets
+ * the read-only parameter "tuned_from_cache" to 1.  sf_set_param(s,
+ * "autotune_cache", 0) makes this schedule tune afresh.  Runs the executor
+ * on B, X, Y (their contents are overwritten) and synchronises the stream.
  *   out_best_ms: HOST, the best time per execution (may be NULL).
  */
 sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
@@ -495,15 +509,25 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
                       int32_t ldy, void* stream, double* out_best_ms);
 
 /* Synchronise the stream and report a watchdog timeout of an earlier
- * execution on this schedule (SF_ERR_TIMEOUT), clearing it; SF_OK else. */
+ * execution on this schedule (SF_ERR_TIMEOUT), clearing the report; SF_OK
+ * else.  A timeout makes only the launch it happened in drain early: later
+ * launches wait normally, whether or not this call was made in between. */
 sf_status sf_sync_status(sf_schedule s, void* stream);
 
 /* Trace mode (sf_set_param(s, "trace", 1)): the fused single-RHS
- * SpTRSV -> SpMV executor records, per work item t, four timestamps of the
- * device's 100 MHz real-time counter in out[4t .. 4t+3]: processing start,
- * indices and values loaded, every x read ready, end.  out holds at least
- * 4 * n_items values (host); the call synchronises the device.  A debugging
- * and tuning aid: tracing adds stores to every item. */
+ * SpTRSV -> SpMV executor records a debug execution trace that shows every
+ * iteration ran exactly once and after its inputs (the validity of a fused
+ * schedule, Sec. 3.1: each DAG edge respected, each iteration executed once).
+ * out (HOST) receives, for work item t (export order), 8 words at out[8t]:
+ * stamps of the device's 100 MHz real-time counter at processing start,
+ * indices and values loaded, every input ready (after the item's last wait)
+ * and end, then the number of times the item ran, 3 zero words; then, at
+ * out[8 n_items + 2 g] for iteration id g (SpTRSV row i: g = i, SpMV row r:
+ * g = n + r), the stamp taken just before its value was published and the
+ * number of times it was published.  count must be >= 8 n_items + 2 (n + m);
+ * otherwise SF_ERR_SHAPE.  Waits for the last executor call on the schedule.
+ * Each traced launch starts from zeroed counts.  Tracing adds stores and
+ * atomics to every item: a debugging aid, not a timed mode. */
 sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count);
 
 /* Time of the last kernel launched by an executor call, measured with HIP

@@ -14,8 +14,11 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -169,6 +172,21 @@ def _csr_parts(m):
     return rp, ci, ncols
 
 
+# Every schedule not yet freed.  At interpreter exit they are released by an
+# atexit hook, which runs before torch and the HIP runtime are torn down; a
+# schedule collected later (during finalisation) makes no device call.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _free_live_schedules():
+    for sch in list(_LIVE):
+        try:
+            sch.free()
+        except Exception:
+            pass
+
+
 class Schedule:
     """Host-built schedule (``sf_inspect``); lives until ``free()`` or GC."""
 
@@ -191,6 +209,7 @@ class Schedule:
         del keep_l, keep_a
         self._h = h
         self.kind = kind
+        _LIVE.add(self)
         st = self.info()
         self.n, self.m = int(st.n), int(st.m)
         self.nnz_l, self.nnz_a = int(st.nnz_l), int(st.nnz_a)
@@ -284,19 +303,30 @@ class Schedule:
         return float(v.value)
 
     def trace(self):
-        """Per-item timestamps (n_items, 4) of the last traced fused launch, in
-        100 MHz real-time-counter ticks (needs set_param("trace", 1))."""
+        """Trace of the last traced fused single-RHS launch (needs
+        set_param("trace", 1)): items (n_items, 8) -- real-time-counter
+        stamps (100 MHz) at start, loads issued, inputs ready and end, then
+        the run count -- and iterations (n + m, 2): the stamp taken just
+        before each iteration's value was published and its publication
+        count (ids as in export(): SpTRSV row i, SpMV row n + r)."""
         n_items = int(self.info().n_items)
-        out = np.zeros(4 * max(n_items, 1), np.uint64)
+        nids = self.n + self.m
+        out = np.zeros(8 * n_items + 2 * nids, np.uint64)
         _check(_lib().sf_trace_export(self.handle, out.ctypes.data, out.size), "sf_trace_export")
-        return out[:4 * n_items].reshape(n_items, 4)
+        return out[:8 * n_items].reshape(n_items, 8), out[8 * n_items:].reshape(nids, 2)
 
     def free(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib().sf_schedule_free(self._h)
         self._h = None
+        _LIVE.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # during interpreter shutdown the HIP runtime may already be gone:
+        # the atexit hook has released every schedule that was still live
+        # (module globals may be cleared by now, hence the bound default)
+        if _finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -324,21 +354,64 @@ def _dtype_code(t):
     raise TypeError("values must be float64 or float32, got %s" % t.dtype)
 
 
-def _vec_ptr(t, rows, name):
-    """Device pointer and leading dimension of a 1-D (n) or column-major 2-D
-    (n, k) CUDA tensor."""
-    if not t.is_cuda:
-        raise ValueError("%s must be a device tensor" % name)
+def _vec_ptr(t, rows, name, dtype=None, device=None):
+    """Device pointer, leading dimension and column count of a 1-D (n) or
+    column-major 2-D (n, k) device tensor: unit stride down each column and
+    columns that do not overlap.  dtype / device, when given, must match."""
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s: dtype %s, expected %s" % (name, t.dtype, dtype))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
     if t.dim() == 1:
-        if t.stride(0) != 1 or t.shape[0] != rows:
+        if t.shape[0] != rows or (rows > 1 and t.stride(0) != 1):
             raise ValueError("%s: expected a contiguous vector of length %d" % (name, rows))
-        return t.data_ptr(), max(rows, 1), 1
-    if t.dim() == 2 and t.shape[0] == rows and (t.stride(0) == 1 or t.shape[1] == 1):
+        ld, k = max(rows, 1), 1
+    elif t.dim() == 2 and t.shape[0] == rows:
+        if rows > 1 and t.stride(0) != 1:
+            raise ValueError("%s: rows must be contiguous (stride(0) = %d, expected 1)" % (name, t.stride(0)))
         if t.shape[1] > 1 and t.stride(1) < rows:
             raise ValueError("%s: columns overlap (stride %d < %d rows)" % (name, t.stride(1), rows))
-        ld = t.stride(1) if t.shape[1] > 1 else max(rows, 1)
-        return t.data_ptr(), max(ld, 1), t.shape[1]
-    raise ValueError("%s: expected shape (%d,) or column-major (%d, k)" % (name, rows, rows))
+        ld, k = (t.stride(1) if t.shape[1] > 1 else max(rows, 1)), t.shape[1]
+    else:
+        raise ValueError("%s: expected shape (%d,) or column-major (%d, k)" % (name, rows, rows))
+    if device is None and not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    return t.data_ptr(), max(ld, 1), k
+
+
+def _val_ptr(t, count, name, dtype, device):
+    """Device pointer of a contiguous array of `count` matrix values in the
+    CSR order of the inspected pattern (None allowed only when count == 0)."""
+    if t is None:
+        if count == 0:
+            return None
+        raise ValueError("%s is required (%d stored entries)" % (name, count))
+    if t.dtype != dtype:
+        raise ValueError("%s: dtype %s, expected %s" % (name, t.dtype, dtype))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    if t.numel() != count:
+        raise ValueError("%s has %d values, the pattern stores %d" % (name, t.numel(), count))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _gpu(device):
+    """Every tensor of a call was checked to sit on `device`: it must be a GPU."""
+    if device is None or device.type != "cuda":
+        raise ValueError("the tensors must be on a GPU device, not %s" % device)
+
+
+def _float_dtype(t, name):
+    torch = _torch()
+    if t is None or not hasattr(t, "dtype"):
+        raise ValueError("%s is required" % name)
+    if t.dtype not in (torch.float64, torch.float32):
+        raise TypeError("%s must be float64 or float32, got %s" % (name, t.dtype))
+    return t.dtype
 
 
 def colmajor(n, k, dtype, device="cuda"):
@@ -355,20 +428,27 @@ def _ptr(t):
 
 def trsv_spmv(sched: Schedule, L_val, A_val, B, *, X=None, Y=None, want_y=True, stream=None,
               unfused=False):
-    """x = L^{-1} b, y = A x (fused unless ``unfused``).  B: (n,) or (n, k)."""
+    """x = L^{-1} b, y = A x (fused unless ``unfused``).  B: (n,) or (n, k).
+    L_val, A_val, B, X and Y share one dtype (float64 or float32) and device."""
     n, m = sched.n, sched.m
-    bp, ldb, k = _vec_ptr(B, n, "B")
-    dt = _dtype_code(L_val)
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    ap = _val_ptr(A_val, sched.nnz_a, "A_val", dt, dev) if want_y else None
+    bp, ldb, k = _vec_ptr(B, n, "B", dt, dev)
     if X is None:
-        X = colmajor(n, k, L_val.dtype, L_val.device)
+        X = colmajor(n, k, dt, dev)
     if want_y and Y is None:
-        Y = colmajor(m, k, L_val.dtype, L_val.device)
-    xp, ldx, _ = _vec_ptr(X, n, "X")
-    yp, ldy = (None, max(m, 1))
+        Y = colmajor(m, k, dt, dev)
+    xp, ldx, kx = _vec_ptr(X, n, "X", dt, dev)
+    yp, ldy, ky = (None, max(m, 1), k)
     if want_y:
-        yp, ldy, _ = _vec_ptr(Y, m, "Y")
+        yp, ldy, ky = _vec_ptr(Y, m, "Y", dt, dev)
+    if kx != k or ky != k:
+        raise ValueError("B, X and Y must have the same number of columns (%d, %d, %d)" % (k, kx, ky))
+    _gpu(dev)
     fn = _lib().sf_exec_unfused_trsv_spmv if unfused else _lib().sf_exec_trsv_spmv
-    _check(fn(sched.handle, dt, L_val.data_ptr(), _ptr(A_val), bp, ldb, k, xp, ldx, yp, ldy,
+    _check(fn(sched.handle, _dtype_code(L_val), lp, ap, bp, ldb, k, xp, ldx, yp, ldy,
               _stream(stream)), "sf_exec_trsv_spmv")
     return X, (Y if want_y else None)
 
@@ -377,34 +457,51 @@ def static_trsv_spmv(sched: Schedule, plan: int, L_val, A_val, b, *, X=None, Y=N
     """x = L^{-1} b, y = A x (one right-hand side) under a static plan:
     SF_STATIC_MSP (the paper's fused partitioning) or SF_STATIC_WAVEFRONT."""
     n, m = sched.n, sched.m
-    bp, _, k = _vec_ptr(b, n, "b")
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    ap = _val_ptr(A_val, sched.nnz_a, "A_val", dt, dev)
+    bp, _, k = _vec_ptr(b, n, "b", dt, dev)
     if k != 1:
         raise ValueError("static plans take one right-hand side")
     if X is None:
-        X = colmajor(n, 1, L_val.dtype, L_val.device)
+        X = colmajor(n, 1, dt, dev)
     if Y is None and m > 0:
-        Y = colmajor(m, 1, L_val.dtype, L_val.device)
-    xp, _, _ = _vec_ptr(X, n, "X")
-    yp = _vec_ptr(Y, m, "Y")[0] if m > 0 else None
-    _check(_lib().sf_exec_static_trsv_spmv(sched.handle, plan, _dtype_code(L_val), L_val.data_ptr(),
-                                           _ptr(A_val), bp, xp, yp, _stream(stream)), "sf_exec_static_trsv_spmv")
+        Y = colmajor(m, 1, dt, dev)
+    xp, _, kx = _vec_ptr(X, n, "X", dt, dev)
+    yp = _vec_ptr(Y, m, "Y", dt, dev)[0] if m > 0 else None
+    if kx != 1 or (m > 0 and Y.numel() != m):
+        raise ValueError("X and Y must be single vectors")
+    _gpu(dev)
+    _check(_lib().sf_exec_static_trsv_spmv(sched.handle, plan, _dtype_code(L_val), lp, ap, bp, xp, yp,
+                                           _stream(stream)), "sf_exec_static_trsv_spmv")
     return X, Y
+
+
+def _one_vec(t, n, name, dt, dev):
+    p, _, k = _vec_ptr(t, n, name, dt, dev)
+    if k != 1:
+        raise ValueError("%s: one right-hand side expected" % name)
+    return p
 
 
 def spmv_trsv(sched: Schedule, A_val, L_val, x, *, Y=None, Z=None, want_y=True, stream=None, unfused=False):
     """y = A x, z = L^{-1} y (Table 2, combination 2).  Returns (y or None, z)."""
     n = sched.n
-    xp, _, k = _vec_ptr(x, n, "x")
-    if k != 1:
-        raise ValueError("spmv_trsv takes one right-hand side")
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    ap = _val_ptr(A_val, sched.nnz_a, "A_val", dt, dev)
+    xp = _one_vec(x, n, "x", dt, dev)
     torch = _torch()
     if Z is None:
-        Z = torch.empty(n, dtype=L_val.dtype, device=L_val.device)
+        Z = torch.empty(n, dtype=dt, device=dev)
     if (want_y or unfused) and Y is None:
-        Y = torch.empty(n, dtype=L_val.dtype, device=L_val.device)
-    yp = _vec_ptr(Y, n, "Y")[0] if (want_y or unfused) else None
+        Y = torch.empty(n, dtype=dt, device=dev)
+    yp = _one_vec(Y, n, "Y", dt, dev) if (want_y or unfused) else None
+    _gpu(dev)
     fn = _lib().sf_exec_unfused_spmv_trsv if unfused else _lib().sf_exec_spmv_trsv
-    _check(fn(sched.handle, _dtype_code(L_val), _ptr(A_val), L_val.data_ptr(), xp, yp, _vec_ptr(Z, n, "Z")[0],
+    _check(fn(sched.handle, _dtype_code(L_val), ap, lp, xp, yp, _one_vec(Z, n, "Z", dt, dev),
               _stream(stream)), "sf_exec_spmv_trsv")
     return (Y if (want_y or unfused) else None), Z
 
@@ -412,15 +509,17 @@ def spmv_trsv(sched: Schedule, A_val, L_val, x, *, Y=None, Z=None, want_y=True, 
 def trsv_trsv(sched: Schedule, L_val, b, *, X=None, Z=None, stream=None, unfused=False):
     """x = L^{-1} b, z = L^{-1} x (Table 2, combination 1).  Returns (x, z)."""
     n = sched.n
-    bp, _, k = _vec_ptr(b, n, "b")
-    if k != 1:
-        raise ValueError("trsv_trsv takes one right-hand side")
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    bp = _one_vec(b, n, "b", dt, dev)
     torch = _torch()
-    X = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if X is None else X
-    Z = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if Z is None else Z
+    X = torch.empty(n, dtype=dt, device=dev) if X is None else X
+    Z = torch.empty(n, dtype=dt, device=dev) if Z is None else Z
+    _gpu(dev)
     fn = _lib().sf_exec_unfused_trsv_trsv if unfused else _lib().sf_exec_trsv_trsv
-    _check(fn(sched.handle, _dtype_code(L_val), L_val.data_ptr(), bp, _vec_ptr(X, n, "X")[0],
-              _vec_ptr(Z, n, "Z")[0], _stream(stream)), "sf_exec_trsv_trsv")
+    _check(fn(sched.handle, _dtype_code(L_val), lp, bp, _one_vec(X, n, "X", dt, dev),
+              _one_vec(Z, n, "Z", dt, dev), _stream(stream)), "sf_exec_trsv_trsv")
     return X, Z
 
 
@@ -428,34 +527,40 @@ def ic_apply(sched: Schedule, L_val, r, *, W=None, Z=None, stream=None, unfused=
     """w = L^{-1} r, z = L^{-T} w (the incomplete-Cholesky preconditioner
     apply); the schedule needs want_backward=True.  Returns (w, z)."""
     n = sched.n
-    rp, _, k = _vec_ptr(r, n, "r")
-    if k != 1:
-        raise ValueError("ic_apply takes one right-hand side")
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    rp = _one_vec(r, n, "r", dt, dev)
     torch = _torch()
-    W = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if W is None else W
-    Z = torch.empty(n, dtype=L_val.dtype, device=L_val.device) if Z is None else Z
+    W = torch.empty(n, dtype=dt, device=dev) if W is None else W
+    Z = torch.empty(n, dtype=dt, device=dev) if Z is None else Z
+    _gpu(dev)
     fn = _lib().sf_exec_unfused_ic_apply if unfused else _lib().sf_exec_ic_apply
-    _check(fn(sched.handle, _dtype_code(L_val), L_val.data_ptr(), rp, _vec_ptr(W, n, "W")[0],
-              _vec_ptr(Z, n, "Z")[0], _stream(stream)), "sf_exec_ic_apply")
+    _check(fn(sched.handle, _dtype_code(L_val), lp, rp, _one_vec(W, n, "W", dt, dev),
+              _one_vec(Z, n, "Z", dt, dev), _stream(stream)), "sf_exec_ic_apply")
     return W, Z
 
 
 def ilu0_trsv(sched: Schedule, A_val, x=None, *, LU_val=None, Y=None, stream=None, unfused=False,
               check_info=True):
     """L U ~= A (zero fill, Table 2 combination 6) and y = L^{-1} x in one
-    launch.  Returns (LU values in A's pattern, y or None, info tensor)."""
+    launch (float64).  Returns (LU values in A's pattern, y or None, info)."""
     torch = _torch()
     n = sched.n
+    f64 = torch.float64
+    dev = A_val.device if hasattr(A_val, "device") else None
+    ap = _val_ptr(A_val, sched.nnz_l, "A_val", f64, dev)
     LU_val = torch.empty_like(A_val) if LU_val is None else LU_val
-    info = torch.full((1,), -1, dtype=torch.int32, device=A_val.device)
+    lup = _val_ptr(LU_val, sched.nnz_l, "LU_val", f64, dev)
+    info = torch.full((1,), -1, dtype=torch.int32, device=dev)
     xp = yp = None
     if x is not None:
-        xp = _vec_ptr(x, n, "x")[0]
-        Y = torch.empty(n, dtype=A_val.dtype, device=A_val.device) if Y is None else Y
-        yp = _vec_ptr(Y, n, "Y")[0]
+        xp = _one_vec(x, n, "x", f64, dev)
+        Y = torch.empty(n, dtype=f64, device=dev) if Y is None else Y
+        yp = _one_vec(Y, n, "Y", f64, dev)
+    _gpu(dev)
     fn = _lib().sf_exec_unfused_ilu0_trsv if unfused else _lib().sf_exec_ilu0_trsv
-    _check(fn(sched.handle, _dtype_code(A_val), A_val.data_ptr(), LU_val.data_ptr(), xp, yp, info.data_ptr(),
-              _stream(stream)), "sf_exec_ilu0_trsv")
+    _check(fn(sched.handle, SF_F64, ap, lup, xp, yp, info.data_ptr(), _stream(stream)), "sf_exec_ilu0_trsv")
     if check_info:
         row = int(info.item())
         if row >= 0:
@@ -465,22 +570,30 @@ def ilu0_trsv(sched: Schedule, A_val, x=None, *, LU_val=None, Y=None, stream=Non
 
 def ic0_trsv(sched: Schedule, A_lower_val, b=None, *, L_val=None, X=None, stream=None, unfused=False,
              check_info=True):
-    """L L^T ~= A (zero fill) and x = L^{-1} b in one launch.  Returns (L_val, x, info)."""
+    """L L^T ~= A (zero fill) and x = L^{-1} b in one launch (float64).
+    Returns (L_val, x, info)."""
     torch = _torch()
     n = sched.n
+    f64 = torch.float64
+    dev = A_lower_val.device if hasattr(A_lower_val, "device") else None
+    ap = _val_ptr(A_lower_val, sched.nnz_l, "A_lower_val", f64, dev)
     if L_val is None:
         L_val = torch.empty_like(A_lower_val)
-    info = torch.empty(1, dtype=torch.int32, device=A_lower_val.device)
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", f64, dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
     bp, ldb = None, max(n, 1)
     xp, ldx = None, max(n, 1)
     if b is not None:
-        bp, ldb, _ = _vec_ptr(b, n, "b")
+        bp, ldb, kb = _vec_ptr(b, n, "b", f64, dev)
         if X is None:
-            X = torch.empty(n, dtype=torch.float64, device=b.device)
-        xp, ldx, _ = _vec_ptr(X, n, "X")
+            X = torch.empty(n, dtype=f64, device=dev)
+        xp, ldx, kx = _vec_ptr(X, n, "X", f64, dev)
+        if kb != 1 or kx != 1:
+            raise ValueError("ic0_trsv takes one right-hand side")
+    _gpu(dev)
     fn = _lib().sf_exec_unfused_ic0_trsv if unfused else _lib().sf_exec_ic0_trsv
-    _check(fn(sched.handle, _dtype_code(A_lower_val), A_lower_val.data_ptr(), L_val.data_ptr(), bp, ldb, 1,
-              xp, ldx, info.data_ptr(), _stream(stream)), "sf_exec_ic0_trsv")
+    _check(fn(sched.handle, SF_F64, ap, lp, bp, ldb, 1, xp, ldx, info.data_ptr(), _stream(stream)),
+           "sf_exec_ic0_trsv")
     row = None
     if check_info:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
@@ -491,52 +604,74 @@ def ic0_trsv(sched: Schedule, A_lower_val, b=None, *, L_val=None, X=None, stream
 
 
 def backward(sched: Schedule, L_val, A_val, G, *, X=None, B=None, stream=None):
-    """(grad_b, grad_L_val) of loss with dloss/dy = G; X or B (recompute) needed."""
+    """(grad_b, grad_L_val) of loss with dloss/dy = G; X or B (recompute) needed.
+    Every tensor shares L_val's dtype and device."""
     torch = _torch()
-    grad_b = torch.empty(sched.n, dtype=L_val.dtype, device=L_val.device)
+    n, m = sched.n, sched.m
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    ap = _val_ptr(A_val, sched.nnz_a, "A_val", dt, dev)
+    gp = _one_vec(G, m, "G", dt, dev)
+    xp = _one_vec(X, n, "X", dt, dev) if X is not None else None
+    bp = _one_vec(B, n, "B", dt, dev) if B is not None else None
+    if xp is None and bp is None:
+        raise ValueError("backward needs X (stored) or B (recompute x)")
+    grad_b = torch.empty(n, dtype=dt, device=dev)
     grad_l = torch.empty_like(L_val)
     ws, wsb = None, 0
     if X is None:
         wsb = int(_lib().sf_backward_workspace_bytes(sched.handle, _dtype_code(L_val), 1))
-        ws = torch.empty(wsb, dtype=torch.uint8, device=L_val.device)
-    _check(_lib().sf_backward(sched.handle, _dtype_code(L_val), L_val.data_ptr(), _ptr(A_val), _ptr(X),
-                              _ptr(B), G.data_ptr(), grad_b.data_ptr(), grad_l.data_ptr(), _ptr(ws), wsb,
-                              _stream(stream)), "sf_backward")
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    _gpu(dev)
+    _check(_lib().sf_backward(sched.handle, _dtype_code(L_val), lp, ap, xp, bp, gp, grad_b.data_ptr(),
+                              grad_l.data_ptr(), _ptr(ws), wsb, _stream(stream)), "sf_backward")
     return grad_b, grad_l
 
 
 def refine_trsv_spmv(sched: Schedule, L32, L64, A64, B, *, n_corrections=2, want_y=True, stream=None):
-    """FP32 fused solves + FP64 residual refinement.  Returns (X, Y, relres)."""
+    """FP32 fused solves + FP64 residual refinement.  L32 float32; L64, A64
+    and B float64, all on one device.  Returns (X, Y, relres)."""
     torch = _torch()
     n, m = sched.n, sched.m
-    bp, ldb, k = _vec_ptr(B, n, "B")
-    X = colmajor(n, k, torch.float64, B.device)
-    xp, ldx, _ = _vec_ptr(X, n, "X")
+    dev = B.device
+    l32 = _val_ptr(L32, sched.nnz_l, "L32", torch.float32, dev)
+    l64 = _val_ptr(L64, sched.nnz_l, "L64", torch.float64, dev)
+    a64 = _val_ptr(A64, sched.nnz_a, "A64", torch.float64, dev) if want_y else None
+    bp, ldb, k = _vec_ptr(B, n, "B", torch.float64, dev)
+    X = colmajor(n, k, torch.float64, dev)
+    xp, ldx, _ = _vec_ptr(X, n, "X", torch.float64, dev)
     Y, yp, ldy = None, None, max(m, 1)
     if want_y:
-        Y = colmajor(m, k, torch.float64, B.device)
-        yp, ldy, _ = _vec_ptr(Y, m, "Y")
+        Y = colmajor(m, k, torch.float64, dev)
+        yp, ldy, _ = _vec_ptr(Y, m, "Y", torch.float64, dev)
     wsb = int(_lib().sf_refine_workspace_bytes(sched.handle, k))
-    ws = torch.empty(wsb, dtype=torch.uint8, device=B.device)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     rel = (ctypes.c_double * k)()
-    _check(_lib().sf_refine_trsv_spmv(sched.handle, L32.data_ptr(), L64.data_ptr(), _ptr(A64), bp, ldb, k,
-                                      xp, ldx, yp, ldy, int(n_corrections), rel, ws.data_ptr(), wsb,
-                                      _stream(stream)), "sf_refine_trsv_spmv")
+    _gpu(dev)
+    _check(_lib().sf_refine_trsv_spmv(sched.handle, l32, l64, a64, bp, ldb, k, xp, ldx, yp, ldy,
+                                      int(n_corrections), rel, ws.data_ptr(), wsb, _stream(stream)),
+           "sf_refine_trsv_spmv")
     return X, Y, np.array(rel[:], dtype=np.float64)
 
 
 def autotune(sched: Schedule, L_val, A_val, B, *, want_y=True, stream=None):
     """Time executor variants on the caller's data and keep the fastest."""
     n, m = sched.n, sched.m
-    bp, ldb, k = _vec_ptr(B, n, "B")
-    X = colmajor(n, k, L_val.dtype, L_val.device)
-    xp, ldx, _ = _vec_ptr(X, n, "X")
+    dt = _float_dtype(L_val, "L_val")
+    dev = L_val.device
+    lp = _val_ptr(L_val, sched.nnz_l, "L_val", dt, dev)
+    ap = _val_ptr(A_val, sched.nnz_a, "A_val", dt, dev) if want_y else None
+    bp, ldb, k = _vec_ptr(B, n, "B", dt, dev)
+    X = colmajor(n, k, dt, dev)
+    xp, ldx, _ = _vec_ptr(X, n, "X", dt, dev)
     yp, ldy = None, max(m, 1)
     if want_y:
-        Y = colmajor(m, k, L_val.dtype, L_val.device)
-        yp, ldy, _ = _vec_ptr(Y, m, "Y")
+        Y = colmajor(m, k, dt, dev)
+        yp, ldy, _ = _vec_ptr(Y, m, "Y", dt, dev)
     best = ctypes.c_double()
-    _check(_lib().sf_autotune(sched.handle, _dtype_code(L_val), L_val.data_ptr(), _ptr(A_val), bp, ldb, k,
+    _gpu(dev)
+    _check(_lib().sf_autotune(sched.handle, _dtype_code(L_val), lp, ap, bp, ldb, k,
                               xp, ldx, yp, ldy, _stream(stream), ctypes.byref(best)), "sf_autotune")
     return float(best.value)
 

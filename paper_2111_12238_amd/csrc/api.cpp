@@ -8,7 +8,10 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "kargs.h"
@@ -59,13 +62,36 @@ struct Packer {
   }
 };
 
+uint64_t pattern_fingerprint(sf_schedule_s* s);  // autotuner cache key (below)
+
+// Record that every launch of an executor call is enqueued on `stream`
+// (the schedule's "done" event, created on first use) and pass r through.
+sf_status enqueued(sf_schedule_s* s, void* stream, sf_status r) {
+  if (r != SF_OK || !s || !s->dev.ready) return r;
+  hipEvent_t ev = static_cast<hipEvent_t>(s->dev.done);
+  if (!ev) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return SF_ERR_HIP;
+    s->dev.done = ev;
+  }
+  return hip_status(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
+}
+
+// Wait until the work of the last executor call on the schedule is done.
+void wait_done(sf_schedule_s* s) {
+  if (s->dev.done) hipEventSynchronize(static_cast<hipEvent_t>(s->dev.done));
+}
+
+// Release the device buffers once the last executor call's work is done.
 void free_device(sf_schedule_s* s) {
   DeviceBuffers& d = s->dev;
   if (d.device >= 0) {
     int cur = 0;
     hipGetDevice(&cur);
     hipSetDevice(d.device);
-    hipDeviceSynchronize();
+    if (d.done) {
+      hipEventSynchronize(static_cast<hipEvent_t>(d.done));
+      hipEventDestroy(static_cast<hipEvent_t>(d.done));
+    }
     if (d.block) hipFree(d.block);
     if (d.state) hipFree(d.state);
     if (d.xi) hipFree(d.xi);
@@ -166,6 +192,7 @@ sf_status multi_ws(sf_schedule_s* s, int kb, int nrhs, size_t es, hipStream_t st
   const size_t bytes = 2 * bx + by;
   if (d.xi_bytes < bytes) {
     SF_HIP(hipStreamSynchronize(st));
+    wait_done(s);
     if (d.xi) SF_HIP(hipFree(d.xi));
     d.xi = nullptr;
     d.xi_bytes = 0;
@@ -288,6 +315,7 @@ sf_status ensure_units(sf_schedule_s* s, int rpb, hipStream_t st) {
     }
   for (size_t l = 1; l < lvl.size(); ++l) lvl[l] += lvl[l - 1];
   SF_HIP(hipStreamSynchronize(st));
+  wait_done(s);
   if (d.units) SF_HIP(hipFree(d.units));
   d.units = nullptr;
   const size_t b0 = std::max<size_t>(all.size(), 2) * 4, b1 = std::max<size_t>(trsv.size(), 2) * 4;
@@ -337,6 +365,21 @@ sf_status exec_multi_core(sf_schedule_s* s, int dtype, const void* Lv, const voi
   return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
 }
 
+// 64-bit words of the trace buffer: the item records, then two words per
+// iteration id (trace mode, kTraceItemWords).
+size_t trace_words(const sf_schedule_s* s) {
+  return s->trace_items * kTraceItemWords + 2 * size_t(s->n + s->m);
+}
+
+// Several right-hand sides as one chain of the single-RHS items per column
+// (multi_path 2, or by default on a coarsened plan of a narrow DAG -- mean
+// wavefront under 2048 rows -- with at most 8 right-hand sides) instead of
+// interleaved blocks over the level units.
+bool column_chains(const sf_schedule_s* s, int nrhs) {
+  const bool narrow = s->n < 2048 * int64_t(std::max(s->depth, 1));
+  return nrhs > 1 && (s->multi_path == 2 || (s->multi_path == 0 && s->chunked && nrhs <= 8 && narrow));
+}
+
 sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* Av, const void* B,
                         int ldb, int nrhs, void* X, int ldx, void* Y, int ldy, hipStream_t st) {
   const int dtype = dt == SF_F64 ? 0 : 1;
@@ -352,10 +395,7 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   // default on a coarsened plan of a narrow DAG (mean wavefront under 2048
   // rows) with at most 8 right-hand sides (2D 9-point 2048^2, k = 8: 9.3 ->
   // 7.8 ms; at k >= 32, or on wide DAGs, the units are faster).
-  const bool narrow = s->n < 2048 * int64_t(std::max(s->depth, 1));
-  const bool chains = nrhs > 1 && (s->multi_path == 2 ||
-                                   (s->multi_path == 0 && s->chunked && nrhs <= 8 && narrow));
-  if (nrhs == 1 || chains) {
+  if (nrhs == 1 || column_chains(s, nrhs)) {
     if (int64_t(a.n_work) * nrhs > int64_t(INT32_MAX) / 2) return SF_ERR_UNSUPPORTED;
     sf_status r = next_epoch(s, st, a.ls);
     if (r != SF_OK) return r;
@@ -363,6 +403,7 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     a.nblk = 1;
     a.col_units = nrhs;
     a.trace = nrhs == 1 ? s->trace : nullptr;
+    a.rtrace = a.trace ? a.trace + s->trace_items * kTraceItemWords : nullptr;
     if (s->chunked) {
       a.order = s->dev.corder;
       a.qrng = s->dev.cqrng;
@@ -376,6 +417,7 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
                                 : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : (nrhs <= 8 ? 8 : 16));
     const int grid = persistent_grid(s, occupancy_ts_fused(dtype), waves);
     Timer tm(s, st);
+    if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));  // counts start at 0
     SF_HIP(launch_fill_pending_cols(X, int32_t(s->n), ldx, nrhs, dtype, st));
     return hip_status(launch_ts_fused(a, dtype, grid, st));
   }
@@ -461,6 +503,15 @@ sf_status check_ts_args(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
   if (s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
   if (dt != SF_F64 && dt != SF_F32) return SF_ERR_ARG;
   if (nrhs < 1 || nrhs > 64) return SF_ERR_ARG;
+  // size limits of the multi-RHS executors, checked before anything else
+  // touches the buffers: interleaved blocks are addressed with 32-bit
+  // offsets (n * block width), column chains index work as item * columns
+  if (nrhs > 1 && !s->no_fusion && column_chains(s, nrhs)) {
+    const size_t items = s->chunked ? s->citem_ptr.size() : s->item_ptr.size();
+    if (int64_t(items) * nrhs > int64_t(INT32_MAX) / 2) return SF_ERR_UNSUPPORTED;
+  } else if (nrhs > 1 && int64_t(s->n) * solve_kb(s, nrhs) > int64_t(INT32_MAX)) {
+    return SF_ERR_UNSUPPORTED;
+  }
   if (s->n > 0 && (!Lv || !B || !X)) return SF_ERR_ARG;
   if (Y && s->A.nnz() > 0 && !Av) return SF_ERR_ARG;
   if (ldb < s->n || ldx < s->n || (Y && ldy < s->m)) return SF_ERR_SHAPE;
@@ -625,32 +676,32 @@ extern "C" {
 
 sf_status sf_exec_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W, void* Z,
                            void* stream) {
-  return precond_entry(s, dtype, L_val, R, W, Z, true, stream);
+  return enqueued(s, stream, precond_entry(s, dtype, L_val, R, W, Z, true, stream));
 }
 
 sf_status sf_exec_unfused_ic_apply(sf_schedule s, sf_dtype dtype, const void* L_val, const void* R, void* W,
                                    void* Z, void* stream) {
-  return precond_entry(s, dtype, L_val, R, W, Z, false, stream);
+  return enqueued(s, stream, precond_entry(s, dtype, L_val, R, W, Z, false, stream));
 }
 
 sf_status sf_exec_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val, const void* X,
                             void* Y, void* Z, void* stream) {
-  return pair_entry(s, dtype, 2, L_val, A_val, X, Y, Z, true, stream);
+  return enqueued(s, stream, pair_entry(s, dtype, 2, L_val, A_val, X, Y, Z, true, stream));
 }
 
 sf_status sf_exec_unfused_spmv_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, const void* L_val,
                                     const void* X, void* Y, void* Z, void* stream) {
-  return pair_entry(s, dtype, 2, L_val, A_val, X, Y, Z, false, stream);
+  return enqueued(s, stream, pair_entry(s, dtype, 2, L_val, A_val, X, Y, Z, false, stream));
 }
 
 sf_status sf_exec_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X, void* Z,
                             void* stream) {
-  return pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, true, stream);
+  return enqueued(s, stream, pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, true, stream));
 }
 
 sf_status sf_exec_unfused_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* B, void* X,
                                     void* Z, void* stream) {
-  return pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, false, stream);
+  return enqueued(s, stream, pair_entry(s, dtype, 1, L_val, nullptr, B, X, Z, false, stream));
 }
 
 sf_status sf_device_probe(int32_t what, sf_probe_result* out, void* stream) {
@@ -742,7 +793,7 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
 sf_status sf_schedule_free(sf_schedule s) {
   if (!s) return SF_OK;
   if (s->trace) {
-    hipDeviceSynchronize();
+    wait_done(s);
     hipFree(s->trace);
   }
   free_device(s);
@@ -848,8 +899,8 @@ sf_status sf_exec_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, co
   hipStream_t st = static_cast<hipStream_t>(stream);
   r = upload(s, st);
   if (r != SF_OK) return r;
-  if (s->no_fusion) return exec_ts_unfused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
-  return exec_ts_fused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
+  if (s->no_fusion) return enqueued(s, stream, exec_ts_unfused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st));
+  return enqueued(s, stream, exec_ts_fused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st));
 }
 
 // ---- static plans: the paper's fused partitioning (MSP) and the fused
@@ -932,7 +983,7 @@ sf_status sf_exec_static_trsv_spmv(sf_schedule s, int32_t plan, sf_dtype dtype, 
   const int cus = std::max(1, device_cus());
   const int grid = cus * std::min(occupancy_static(dt), std::max(1, s->levelset_waves_per_cu * 64 / kBlockThreads));
   Timer tm(s, st);
-  return hip_status(launch_static(a, dt, grid, st));
+  return enqueued(s, stream, hip_status(launch_static(a, dt, grid, st)));
 }
 
 sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
@@ -944,7 +995,7 @@ sf_status sf_exec_unfused_trsv_spmv(sf_schedule s, sf_dtype dtype, const void* L
   hipStream_t st = static_cast<hipStream_t>(stream);
   r = upload(s, st);
   if (r != SF_OK) return r;
-  return exec_ts_unfused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st);
+  return enqueued(s, stream, exec_ts_unfused(s, dtype, L_val, A_val, B, ldb, nrhs, X, ldx, Y, ldy, st));
 }
 
 static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
@@ -1098,25 +1149,24 @@ static sf_status ilu0_common(sf_schedule s, sf_dtype dtype, const void* A_val, v
 sf_status sf_exec_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
                            const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
                            int32_t* d_info, void* stream) {
-  if (s && s->no_fusion)
-    return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, false, stream);
-  return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, true, stream);
+  const bool fused = !(s && s->no_fusion);
+  return enqueued(s, stream, ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, fused, stream));
 }
 
 sf_status sf_exec_unfused_ic0_trsv(sf_schedule s, sf_dtype dtype, const void* A_lower_val, void* L_val,
                                    const void* B, int32_t ldb, int32_t nrhs, void* X, int32_t ldx,
                                    int32_t* d_info, void* stream) {
-  return ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, false, stream);
+  return enqueued(s, stream, ic0_common(s, dtype, A_lower_val, L_val, B, ldb, nrhs, X, ldx, d_info, false, stream));
 }
 
 sf_status sf_exec_ilu0_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val, const void* X,
                             void* Y, int32_t* d_info, void* stream) {
-  return ilu0_common(s, dtype, A_val, LU_val, X, Y, d_info, !(s && s->no_fusion), stream);
+  return enqueued(s, stream, ilu0_common(s, dtype, A_val, LU_val, X, Y, d_info, !(s && s->no_fusion), stream));
 }
 
 sf_status sf_exec_unfused_ilu0_trsv(sf_schedule s, sf_dtype dtype, const void* A_val, void* LU_val,
                                     const void* X, void* Y, int32_t* d_info, void* stream) {
-  return ilu0_common(s, dtype, A_val, LU_val, X, Y, d_info, false, stream);
+  return enqueued(s, stream, ilu0_common(s, dtype, A_val, LU_val, X, Y, d_info, false, stream));
 }
 
 size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs) {
@@ -1169,7 +1219,7 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   Timer tm(s, st);
   // grad_B is the lambda buffer and its own readiness flag
   SF_HIP(launch_fill_pending(grad_B, size_t(s->n), dt, st));
-  return hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st));
+  return enqueued(s, stream, hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st)));
 }
 
 // Refinement workspace, in the interleaved block layout of the solve (a
@@ -1301,6 +1351,8 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
     SF_HIP(launch_unpack(xout, 0, n, nrhs, X, ldx, kb, st));
     if (Y) SF_HIP(launch_unpack(ws.y64, 0, int32_t(s->m), nrhs, Y, ldy, kb, st));
   }
+  r = enqueued(s, stream, SF_OK);
+  if (r != SF_OK) return r;
   const unsigned long long* mx = ws.mx;
   if (out_relres) {
     std::vector<unsigned long long> h(size_t(2 * nrhs));
@@ -1325,19 +1377,19 @@ sf_status recut(sf_schedule_s* s) {
     return SF_ERR_OOM;
   }
   if (s->trace) {  // sized for the old items
-    hipDeviceSynchronize();
+    wait_done(s);
     hipFree(s->trace);
     s->trace = nullptr;
   }
   if (s->dev.ready) {
     // the item arrays changed size: rebuild the constant block
-    hipDeviceSynchronize();
+    wait_done(s);
     if (s->dev.block) hipFree(s->dev.block);
     s->dev.block = nullptr;
     s->dev.ready = false;
   }
   if (s->dev.units) {
-    hipDeviceSynchronize();
+    wait_done(s);
     hipFree(s->dev.units);
     s->dev.units = nullptr;
     s->dev.units_rpb = 0;
@@ -1376,7 +1428,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     if (s->msp_parts != int32_t(v)) {
       s->msp_parts = int32_t(v);
       if (s->msp.dev) {
-        hipDeviceSynchronize();
+        wait_done(s);
         hipFree(s->msp.dev);
       }
       s->msp = StaticPlan();
@@ -1398,6 +1450,8 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     else s->spmv_delay = int32_t(v);
     const sf_status rc = recut(s);
     if (rc != SF_OK) return rc;
+  } else if (k == "autotune_cache") {
+    s->autotune_cache = v ? 1 : 0;
   } else if (k == "no_fusion") {
     s->no_fusion = v ? 1 : 0;
   } else if (k == "timing") {
@@ -1405,12 +1459,14 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "trace") {
     // trace mode: the fused single-RHS executor stamps every item (debug aid)
     if (s->trace) {
-      hipDeviceSynchronize();
+      wait_done(s);
       hipFree(s->trace);
       s->trace = nullptr;
     }
     if (v) {
-      const size_t bytes = (std::max(s->item_ptr.size(), s->citem_ptr.size()) + 1) * 4 * sizeof(unsigned long long);
+      s->trace_items = std::max(s->item_ptr.size(), s->citem_ptr.size()) + 1;
+      const size_t bytes = trace_words(s) * sizeof(unsigned long long);
+      if (trace_words(s) > size_t(INT32_MAX)) return SF_ERR_UNSUPPORTED;
       if (hipMalloc(&s->trace, bytes) != hipSuccess) return SF_ERR_OOM;
       if (hipMemset(s->trace, 0, bytes) != hipSuccess) return SF_ERR_HIP;
     }
@@ -1441,11 +1497,60 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "pairs") *v = int64_t(s->pair_u.size());  // SpIC0 / SpILU0 intersection pairs (read only)
   else if (k == "back_coarsened") *v = s->bchunked ? 1 : 0;
   else if (k == "no_fusion") *v = s->no_fusion;
+  else if (k == "autotune_cache") *v = s->autotune_cache;
+  else if (k == "tuned_from_cache") *v = s->tuned_from_cache;  // read only: last sf_autotune reused a result
+  else if (k == "fingerprint") *v = int64_t(pattern_fingerprint(s) & 0x7fffffffffffffffull);
   else if (k == "timing") *v = s->timing;
   else if (k == "trace") *v = s->trace ? 1 : 0;
   else return SF_ERR_ARG;
   return SF_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// ---- autotuner results, shared by every schedule of the process ----
+// Keyed by the pattern's fingerprint (sizes, depth and a 64-bit FNV-1a hash
+// of both CSR patterns), the value type, the right-hand-side count and
+// whether y is computed: a schedule inspected again from the same matrix
+// takes the tuned parameters without timing anything.
+const char* const kTuneKeys[] = {"coarsen",      "multi_path",   "rhs_block",    "spmv_delay",
+                                 "rows_per_item", "max_item_nnz", "waves_per_cu", "multi_waves_per_cu"};
+constexpr int kNTune = int(sizeof(kTuneKeys) / sizeof(kTuneKeys[0]));
+struct Tuned {
+  int64_t v[kNTune];
+  double best_ms;
+};
+using TuneKey = std::tuple<uint64_t, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuned>& tune_cache() {
+  static std::map<TuneKey, Tuned> m;
+  return m;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t bytes) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+uint64_t pattern_fingerprint(sf_schedule_s* s) {
+  if (s->fingerprint) return s->fingerprint;
+  uint64_t h = 14695981039346656037ull;
+  const int64_t head[6] = {s->n, s->m, s->L.nnz(), s->A.nnz(), s->depth, s->kind};
+  h = fnv1a(h, head, sizeof(head));
+  for (const sf::Pattern* P : {&s->L, &s->A}) {
+    h = fnv1a(h, P->rp.data(), P->rp.size() * 4);
+    h = fnv1a(h, P->ci.data(), P->ci.size() * 4);
+  }
+  s->fingerprint = h ? h : 1;
+  return s->fingerprint;
+}
+
+}  // namespace
+
+extern "C" {
 
 sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val, const void* B,
                       int32_t ldb, int32_t nrhs, void* X, int32_t ldx, void* Y, int32_t ldy, void* stream,
@@ -1454,6 +1559,33 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r != SF_OK) return r;
   if (s->n == 0) return SF_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  s->tuned_from_cache = 0;
+  const TuneKey key{pattern_fingerprint(s), int(dtype), int(nrhs), Y ? 1 : 0};
+  if (s->autotune_cache) {
+    Tuned hit{};
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = tune_cache().find(key);
+      if (it != tune_cache().end()) {
+        hit = it->second;
+        found = true;
+      }
+    }
+    if (found) {
+      for (int k = 0; k < kNTune; ++k) {
+        int64_t cur = 0;
+        sf_get_param(s, kTuneKeys[k], &cur);
+        if (cur != hit.v[k]) {
+          r = sf_set_param(s, kTuneKeys[k], hit.v[k]);
+          if (r != SF_OK) return r;
+        }
+      }
+      s->tuned_from_cache = 1;
+      if (out_best_ms) *out_best_ms = hit.best_ms;
+      return SF_OK;
+    }
+  }
   hipEvent_t e0, e1;
   SF_HIP(hipEventCreate(&e0));
   SF_HIP(hipEventCreate(&e1));
@@ -1505,10 +1637,18 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK && nrhs == 1) r = try_param("waves_per_cu", {4, 8, 16});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_waves_per_cu", {8, 16, 32});
   if (r == SF_OK) r = upload(s, st);
+  r = enqueued(s, stream, r);
   s->timing = saved_timing;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (out_best_ms) *out_best_ms = best;
+  if (r == SF_OK && s->autotune_cache) {
+    Tuned t{};
+    for (int k = 0; k < kNTune; ++k) sf_get_param(s, kTuneKeys[k], &t.v[k]);
+    t.best_ms = best;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache()[key] = t;
+  }
   return r;
 }
 
@@ -1529,10 +1669,15 @@ sf_status sf_sync_status(sf_schedule s, void* stream) {
 
 sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count) {
   if (!s || !out || !s->trace) return SF_ERR_ARG;
-  const int64_t have = int64_t((s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1) * 4;
-  if (count < have) return SF_ERR_SHAPE;
-  if (hipDeviceSynchronize() != hipSuccess) return SF_ERR_HIP;
-  if (hipMemcpy(out, s->trace, size_t(have) * 8, hipMemcpyDeviceToHost) != hipSuccess) return SF_ERR_HIP;
+  const size_t items = (s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
+  const size_t rows = 2 * size_t(s->n + s->m);
+  if (count < int64_t(items * kTraceItemWords + rows)) return SF_ERR_SHAPE;
+  wait_done(s);
+  const size_t at = s->trace_items * kTraceItemWords;
+  if (hipMemcpy(out, s->trace, items * kTraceItemWords * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return SF_ERR_HIP;
+  if (hipMemcpy(out + items * kTraceItemWords, s->trace + at, rows * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return SF_ERR_HIP;
   return SF_OK;
 }
 

@@ -45,7 +45,19 @@ __device__ __forceinline__ void reset_next_launch(const LaunchState& ls) {
     st_co(ls.state + done_off(np), 0);
     st_co(ls.state + info_off(np), kInfoNone);
     st_co(ls.state + bar_off(np), 0);
+    st_co(ls.state + status_off(np), 0);
   }
+}
+
+// Watchdog: a wait gave up.  The launch's own status makes every wave of
+// this launch drain; the sticky word is what sf_sync_status reports.
+__device__ __forceinline__ void report_timeout(const LaunchState& ls) {
+  st_co(ls.state + status_off(ls.epoch & 1), kStatusTimeout);
+  st_co(ls.state + kStatusOff, kStatusTimeout);
+}
+// True once a wait of this launch has given up.
+__device__ __forceinline__ bool timed_out(const LaunchState& ls) {
+  return ld_co(ls.state + status_off(ls.epoch & 1)) != 0;
 }
 
 // Work claiming.  Block b claims from counter b % streams; the k-th ticket of
@@ -100,10 +112,10 @@ __device__ __forceinline__ void grid_barrier(const LaunchState& ls, int32_t& gen
     while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins >= ls.spin_limit) {  // watchdog: report and let the grid drain
-        st_co(ls.state + kStatusOff, kStatusTimeout);
+        report_timeout(ls);
         break;
       }
-      if ((spins & 255) == 0 && ld_co(ls.state + kStatusOff) != 0) break;
+      if ((spins & 255) == 0 && timed_out(ls)) break;
     }
   }
   ++gen;
@@ -167,10 +179,21 @@ __device__ __forceinline__ T poll_value(const T* p, const LaunchState& ls) {
     v2 = ld_co(p);
     spins += 3;
     if (spins >= ls.spin_limit) {
-      st_co(ls.state + kStatusOff, kStatusTimeout);
+      report_timeout(ls);
       return v2;
     }
-    if ((spins & 255) == 0 && ld_co(ls.state + kStatusOff) != 0) return v2;
+    if ((spins & 255) == 0 && timed_out(ls)) return v2;
+  }
+}
+
+// Trace mode: record, for the iterations a wavefront is about to publish
+// (lanes with `mine`, iteration id `gid`), the real-time counter read just
+// before the stores and one more publication.
+__device__ __forceinline__ void stamp_publish(unsigned long long* rtr, bool mine, int gid) {
+  const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+  if (mine) {
+    rtr[2 * size_t(gid)] = t;
+    atomicAdd(rtr + 2 * size_t(gid) + 1, 1ull);
   }
 }
 

@@ -42,9 +42,14 @@ using dev::WaveLds;
 
 // Trace mode (a.trace != nullptr): per item, timestamps of the 100 MHz
 // real-time counter at the start of processing, once the item's indices and
-// values are loaded, once every x it reads is ready, and at the end.
+// values are loaded, once every x it reads is ready (after the last wait)
+// and at the end, and a count of its runs; per iteration, a stamp taken
+// just before its value is published and a count of its publications
+// (dev::stamp_publish).  The host checks from them that every item and every
+// iteration ran exactly once and that every value was published before the
+// wait of each item reading it returned.
 __device__ __forceinline__ unsigned long long* trace_slots(const TsArgs& a, int it) {
-  return (a.trace && it >= 0) ? a.trace + size_t(it) * 4 : nullptr;
+  return (a.trace && it >= 0) ? a.trace + size_t(it) * kTraceItemWords : nullptr;
 }
 
 // Process one item (rows order[q0..q1), q1 - q0 <= 64) of SpTRSV rows
@@ -71,6 +76,7 @@ __device__ __forceinline__ void item_stream_rows(const TsArgs& a, int q0, int q1
   }
   acc = stream_accumulate<T, TRSV, VEC, false>(nr, r0, r1 - r0, acc, TRSV ? a.Lci : a.Aci, nullptr, val, X,
                                                lane, w, a.ls, tr);
+  if (a.rtrace) dev::stamp_publish(a.rtrace, mine, id);
   if (mine) {
     if constexpr (TRSV) st_co(X + row, publishable(acc / dii));
     else __builtin_nontemporal_store(acc, static_cast<T*>(a.Y) + row);
@@ -103,7 +109,7 @@ __device__ __forceinline__ void item_chunk_rows(const TsArgs& a, int q0, int q1,
   const T acc = mine ? static_cast<const T*>(a.B)[row] : T(0);
   const T dii = mine ? ld_stream(val + r1) : T(1);
   dev::chunk_solve<T, false>(nr, r0, r1 - r0, myloc, maxloc, acc, dii, a.Lci, nullptr, val, a.eloc,
-                             static_cast<T*>(a.X), row, lane, w, xl, a.ls, tr);
+                             static_cast<T*>(a.X), row, lane, w, xl, a.ls, tr, a.rtrace);
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
@@ -155,7 +161,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
       if (a.Y) ac.Y = static_cast<T*>(a.Y) + size_t(c) * size_t(a.ldy);
     }
     unsigned long long* tr = trace_slots(a, it);
-    if (tr && lane == 0) tr[0] = __builtin_amdgcn_s_memrealtime();
+    if (tr && lane == 0) {
+      // an item without entries loads and waits for nothing: its "loaded"
+      // and "ready" stamps stay at its start
+      const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+      tr[0] = t0;
+      tr[1] = t0;
+      tr[2] = t0;
+      atomicAdd(tr + 4, 1ull);
+    }
     const bool mine = lane < q1 - q0;
     const int id = mine ? a.order[q0 + lane] : 0;
     const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);

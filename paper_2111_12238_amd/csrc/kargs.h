@@ -44,7 +44,9 @@ struct TsArgs {
   int32_t n_work;          // items to run (entries of item_list, or all items)
   const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
   const uint8_t* eloc;     // coarsened plan: per L entry, slot of its column in the item or 0xFF
-  unsigned long long* trace;  // optional: 4 timestamps per item (see k_ts.hip)
+  unsigned long long* trace;  // optional: kTraceItemWords words per item (see k_ts.hip)
+  unsigned long long* rtrace; // with trace: per iteration id (SpTRSV row i, SpMV row n + r) its
+                              // publication time and how many times it was published
   LaunchState ls;
 };
 

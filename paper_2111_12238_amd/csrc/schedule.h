@@ -27,11 +27,22 @@ inline constexpr int ctr_off(int p, int s) { return (p * kStreams + s) * kLine; 
 inline constexpr int done_off(int p) { return (2 * kStreams + p) * kLine; }
 inline constexpr int info_off(int p) { return (2 * kStreams + 2 + p) * kLine; }
 inline constexpr int bar_off(int p) { return (2 * kStreams + 4 + p) * kLine; }
-constexpr int kStatusOff = (2 * kStreams + 6) * kLine;
-constexpr int kStateWords = (2 * kStreams + 8) * kLine;
+// The watchdog status of the launch with parity p (it makes that launch's
+// waves drain; cleared for the next launch like the other per-parity
+// fields) and a sticky report that only sf_sync_status reads and clears, so
+// a timeout is reported but never shortens the waits of a later launch.
+inline constexpr int status_off(int p) { return (2 * kStreams + 6 + p) * kLine; }
+constexpr int kStatusOff = (2 * kStreams + 8) * kLine;
+constexpr int kStateWords = (2 * kStreams + 10) * kLine;
 constexpr int kChunkEntries = 512;        // off-diagonals of one coarsened item (one stream pass)
 constexpr int kInfoNone = 0x7f7f7f7f;     // "no failing row" (byte-fill value of the block)
 constexpr int kStatusTimeout = 1;
+// Trace mode: per work item kTraceItemWords 64-bit words -- real-time-counter
+// stamps at the start, once its indices and values are loaded, once every
+// input is ready and at the end, then how many times the item ran -- and,
+// after the items, two words per iteration id (stamp taken just before the
+// value was published, publication count).
+constexpr int kTraceItemWords = 8;
 
 struct DeviceBuffers {
   int device = -1;
@@ -72,6 +83,9 @@ struct DeviceBuffers {
   int32_t* lvl_unit_ptr = nullptr;
   int32_t units_rpb = 0, n_units = 0, n_unit_trsv = 0;
   uint32_t epoch = 0;
+  // recorded on the caller's stream after each executor call's launches:
+  // freeing the schedule waits for it instead of for the whole device
+  void* done = nullptr;  // hipEvent_t
 };
 
 // Static two-level plan of the SpTRSV -> SpMV pair (static_plan.cpp): the
@@ -178,7 +192,11 @@ struct sf_schedule_s {
   int32_t claim_streams = 1;
   int32_t no_fusion = 0;
   int32_t timing = 0;
-  unsigned long long* trace = nullptr;  // device buffer of 4 stamps per item (trace mode)
+  int32_t autotune_cache = 1;           // sf_autotune reuses results for an equal pattern
+  int32_t tuned_from_cache = 0;         // the last sf_autotune call did
+  uint64_t fingerprint = 0;             // of the patterns (computed on first use; 0: not yet)
+  unsigned long long* trace = nullptr;  // device trace buffer (trace mode, layout at kTraceItemWords)
+  size_t trace_items = 0;               // item records in it (rows follow them)
   double last_kernel_ms = -1.0;
   double reuse = 0.0, inspect_seconds = 0.0;
 

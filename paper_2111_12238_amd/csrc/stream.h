@@ -47,10 +47,10 @@ struct WaveLds {
 // watchdog has fired (the caller then drains).
 __device__ __forceinline__ bool all_poll_round(int32_t& spins, const LaunchState& ls) {
   if (++spins >= ls.spin_limit) {
-    st_co(ls.state + kStatusOff, kStatusTimeout);
+    report_timeout(ls);
     return false;
   }
-  return (spins & 63) != 0 || ld_co(ls.state + kStatusOff) == 0;
+  return (spins & 63) != 0 || !timed_out(ls);
 }
 
 template <typename T, int R, int ALL_BELOW = 32>
@@ -81,7 +81,7 @@ __device__ __forceinline__ void wait_ready(const T* vec, const int (&j)[R], T (&
       for (int e = 0; e < R; ++e)
         if (j[e] == wmax) xv[e] = got;
     }
-    if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
+    if (timed_out(ls)) return;  // watchdog fired in this launch: drain
 #pragma unroll
     for (int e = 0; e < R; ++e)
       if (j[e] >= 0 && is_pending(xv[e])) xv[e] = ld_co(vec + j[e]);
@@ -120,7 +120,7 @@ __device__ __forceinline__ void wait_ptrs(const T* (&p)[R], T (&v)[R], int lane,
       for (int e = 0; e < R; ++e)
         if (p[e] == w) v[e] = got;
     }
-    if (ld_co(ls.state + kStatusOff) != 0) return;  // watchdog fired somewhere: drain
+    if (timed_out(ls)) return;  // watchdog fired in this launch: drain
 #pragma unroll
     for (int e = 0; e < R; ++e)
       if (p[e] && is_pending(v[e])) v[e] = ld_co(p[e]);
@@ -210,7 +210,7 @@ __device__ __forceinline__ T stream_accumulate(int nr, int r0, int len, T acc, c
 // exact, so the terms and their order are still the definition's.
 template <typename T, int NT>
 __device__ __forceinline__ T chunk_steps(WaveLds<T>& w, T* xl, T* vec, bool mine, int myloc, int maxloc, int off,
-                                         int len, int row, int lane, T acc, T dii) {
+                                         int len, int row, int lane, T acc, T dii, unsigned long long* rtr) {
   constexpr int kOne = 64;
   T pv[NT];
   int pq[NT];
@@ -238,6 +238,7 @@ __device__ __forceinline__ T chunk_steps(WaveLds<T>& w, T* xl, T* vec, bool mine
       }
       const T x = publishable(acc / dii);
       xl[lane] = x;
+      if (rtr) stamp_publish(rtr, true, row);
       st_co(vec + row, x);
       mine_x = x;
     }
@@ -264,7 +265,7 @@ __device__ __forceinline__ T chunk_solve(int nr, int r0, int len, int myloc, int
                                          const int32_t* __restrict__ col, const int32_t* __restrict__ map,
                                          const T* __restrict__ val, const uint8_t* __restrict__ eloc, T* vec,
                                          int row, int lane, WaveLds<T>& w, T* xl, const LaunchState& ls,
-                                         unsigned long long* tr) {
+                                         unsigned long long* tr, unsigned long long* rtr = nullptr) {
   const bool mine = lane < nr;
   if (!mine) len = 0;
   int incl = len;
@@ -312,8 +313,8 @@ __device__ __forceinline__ T chunk_solve(int nr, int r0, int len, int myloc, int
   int maxlen = len;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, d, 64));
-  if (maxlen <= 4) return chunk_steps<T, 4>(w, xl, vec, mine, myloc, maxloc, off, len, row, lane, acc, dii);
-  return chunk_steps<T, 8>(w, xl, vec, mine, myloc, maxloc, off, len, row, lane, acc, dii);
+  if (maxlen <= 4) return chunk_steps<T, 4>(w, xl, vec, mine, myloc, maxloc, off, len, row, lane, acc, dii, rtr);
+  return chunk_steps<T, 8>(w, xl, vec, mine, myloc, maxloc, off, len, row, lane, acc, dii, rtr);
 }
 
 }  // namespace dev

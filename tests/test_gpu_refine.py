@@ -49,3 +49,81 @@ def test_refinement_reaches_1e10(orc, mat, k):
     assert relerr(x, xr) <= TOL_REFINED
     assert relerr(y, yr) <= TOL_REFINED
     assert rel.max() <= 1e-12
+
+
+# ---- the batched workloads at full size: random SPD n = 10^6 and the 2D
+# 9-point Laplacian on a 2048^2 grid, k in {1, 8, 32, 64} right-hand sides
+# (b ~ U(-1, 1), seed 1), every column compared with the FP64 oracle
+
+_FULL = {}
+
+
+def full_case(orc, mat):
+    """(L, A, b[:, :64], x_oracle, y_oracle) for a full-size batched
+    workload, computed once per session (64 sequential oracle solves)."""
+    if mat not in _FULL:
+        L, A = synth.workload("randspd_1m" if mat == "spd" else "lap2d9_2048")
+        b = synth.vec_uniform(L.nrows, k=64, seed=1)
+        xr, yr = oracle_cols(orc, L, A, b)
+        _FULL.clear()  # keep one matrix's arrays at a time
+        _FULL[mat] = (L, A, b, xr, yr)
+    return _FULL[mat]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mat", ["spd", "9pt"])
+def test_full_size_refinement_every_k(orc, mat):
+    """FP32 solves (block widths up to 64) + 2 FP64 corrections reach 1e-10
+    against the FP64 oracle in x and y, per column, at k = 1, 8, 32, 64 on
+    the full-size batched matrices; relative residuals <= 1e-12."""
+    L, A, b, xr, yr = full_case(orc, mat)
+    s = sfm.Schedule(L, A)
+    for k in (1, 8, 32, 64):
+        announce("refine full-size %s k=%d" % (mat, k))
+        bk = b[:, 0] if k == 1 else b[:, :k]
+        x, y, rel = run_refine(s, L, A, bk, 2)
+        xk = xr[:, 0] if k == 1 else xr[:, :k]
+        yk = yr[:, 0] if k == 1 else yr[:, :k]
+        ex, ey = relerr(x, xk), relerr(y, yk)
+        print("%s k=%d refined: x err %.2e  y err %.2e  relres %.2e" % (mat, k, ex, ey, rel.max()))
+        assert ex <= TOL_REFINED and ey <= TOL_REFINED, (k, ex, ey)
+        assert rel.max() <= 1e-12, (k, rel.max())
+    s.free()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mat", ["spd", "9pt"])
+def test_full_size_fp64_k64_bit_identical(orc, mat):
+    """FP64 fused SpTRSV -> SpMV with 64 right-hand sides in one launch
+    (interleaved blocks of 64 columns) and the unfused level-set baseline:
+    every column of x and y bit-identical to the oracle, full size."""
+    import torch
+    L, A, b, xr, yr = full_case(orc, mat)
+    s = sfm.Schedule(L, A)
+    Lv, Av, B = dev(L.val), dev(A.val), dev_colmajor(b)
+    for unfused in (False, True):
+        announce("fp64 k=64 full-size %s unfused=%s" % (mat, unfused))
+        X, Y = sfm.trsv_spmv(s, Lv, Av, B, unfused=unfused)
+        torch.cuda.synchronize()
+        sfm.sync_status(s)
+        assert np.array_equal(host(X), xr), unfused
+        assert np.array_equal(host(Y), yr), unfused
+        del X, Y
+    s.free()
+
+
+def test_fp32_kb64_refinement_small(orc):
+    """The 64-wide FP32 kernels (solve units, pack with conversion,
+    residual and final passes on 64-column blocks) on a small random SPD
+    matrix: refined x and y within 1e-10 of the oracle, per column."""
+    A = synth.random_spd(20_000, seed=4)
+    L = synth.lower(A)
+    b = synth.vec_uniform(L.nrows, k=64, seed=1)
+    s = sfm.Schedule(L, A)
+    assert s.get_param("rhs_block") == 0  # default block width for 64 columns is 64
+    xr, yr = oracle_cols(orc, L, A, b)
+    for nc in (1, 2, 3):
+        announce("refine fp32 kb=64 n=20000 corrections=%d" % nc)
+        x, y, rel = run_refine(s, L, A, b, nc)
+        assert relerr(x, xr) <= TOL_REFINED and relerr(y, yr) <= TOL_REFINED, nc
+        assert rel.max() <= 1e-12, nc

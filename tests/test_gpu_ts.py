@@ -305,6 +305,32 @@ def test_watchdog_reports_timeout_and_recovers(orc):
     assert np.array_equal(host(X), xt)
 
 
+def test_watchdog_timeout_stays_in_its_launch(orc):
+    """A launch whose waits gave up does not shorten the waits of the next
+    launch on the same schedule (each launch has its own status word), while
+    the timeout is still reported by sf_sync_status afterwards (sticky)."""
+    announce("ts watchdog: timed-out launches then an exact one, no sync between")
+    L, A = synth.workload("lap2d5_64")
+    xt = synth.int_vector(L.nrows, seed=3)
+    b = L.to_scipy() @ xt
+    s = sfm.Schedule(L, A)
+    default = s.get_param("spin_limit")
+    s.set_param("rows_per_item", 1)
+    import torch
+    Lv, Av, B = dev(L.val), dev(A.val), dev(b)
+    s.set_param("spin_limit", 1)
+    for _ in range(5):
+        sfm.trsv_spmv(s, Lv, Av, B)
+    s.set_param("spin_limit", default)
+    X, Y = sfm.trsv_spmv(s, Lv, Av, B)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(X), xt)
+    with pytest.raises(sfm.SparseFusionError) as e:
+        sfm.sync_status(s)
+    assert e.value.name == "SF_ERR_TIMEOUT"
+    sfm.sync_status(s)  # reported once, then clear
+
+
 def _coarsened_case(case):
     if case == "lap3d7_20":
         A = synth.laplacian_3d7(20, 20, 20, 6.0)
@@ -498,25 +524,3 @@ def test_multi_rhs_paths_bit_exact(orc, path, coarsen):
         sfm.sync_status(s)
         assert np.array_equal(host(X), xr) and np.array_equal(host(Y), yr), unfused
         assert bool((Xbuf[:, n:] == -7.0).all()) and bool((Ybuf[:, 4000:] == -9.0).all()), unfused
-
-
-def test_multi_rhs_offset_limit_reported():
-    """Several right-hand sides address a block's interleaved x with 32-bit
-    offsets: n * rhs_block >= 2^31 (here 2^25 rows and 64 right-hand sides)
-    is reported as SF_ERR_UNSUPPORTED by the fused and the level-set entry,
-    before anything is launched (the buffers passed are one element long and
-    are never touched)."""
-    announce("ts multi-RHS 32-bit offset limit (n = 2^25, 64 RHS)")
-    import torch
-    n = 1 << 25
-    rp = np.arange(n + 1, dtype=np.int32)
-    s = sfm.Schedule((rp, rp[:-1].copy(), n), (np.zeros(1, np.int32), np.zeros(0, np.int32), n))
-    assert s.info().coarsened == 0 and s.get_param("multi_path") == 0  # interleaved units for 64 RHS
-    lv, b, x = (torch.empty(1, dtype=torch.float64, device="cuda") for _ in range(3))
-    lib = sfm._lib()
-    for fn in (lib.sf_exec_trsv_spmv, lib.sf_exec_unfused_trsv_spmv):
-        st = fn(s.handle, 0, lv.data_ptr(), None, b.data_ptr(), n, 64, x.data_ptr(), n, None, 0, None)
-        assert st == 10, st  # SF_ERR_UNSUPPORTED
-    torch.cuda.synchronize()
-    sfm.sync_status(s)
-    s.free()
