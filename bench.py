@@ -229,34 +229,43 @@ def main():
         WARM_SAMPLES[unfused] = samples
         return total_ms / args.steps, [p[0] / p[1] for p in per]
 
-    def cold(unfused, reps=10):
-        """Per-launch times with the 256 MB Infinity Cache evicted first: a
-        1 GiB scratch write before each launch, outside the timed region."""
+    def cold(unfused):
+        """The timed steps, cold: W untimed warm-up steps, then exactly K
+        steps, each launch preceded by a 1 GiB scratch write that evicts the
+        256 MB Infinity Cache (outside the launch's events); the region is
+        bracketed by device synchronisations.  Returns the step time (sum of
+        the mean launch times) and per-matrix launch samples."""
         scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        out = []
-        for d in work:
-            ts = []
-            for r in range(reps + 1):
-                scratch.fill_(float(r))
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
+        for r in range(args.warmup):
+            step(unfused)
+        torch.cuda.synchronize()
+        evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in work] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            for j, d in enumerate(work):
+                scratch.fill_(float(k * len(work) + j))
+                evs[k][j][0].record(stream)
                 sfm.trsv_spmv(d["s"], d["Lv"], d["Av"], d["B"], X=d["X"], Y=d["Y"], unfused=unfused)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                if r > 0:  # the first launch is a warm-up
-                    ts.append(e0.elapsed_time(e1))
-            out.append(ts)
+                evs[k][j][1].record(stream)
+        torch.cuda.synchronize()
+        for d in work:
+            sfm.sync_status(d["s"])
+        samples = [[evs[k][j][0].elapsed_time(evs[k][j][1]) for k in range(args.steps)] for j in range(len(work))]
         del scratch
-        return out
+        return sum(float(np.mean(sm)) for sm in samples), samples
 
-    log("timing fused (%d warmup, %d steps)" % (args.warmup, args.steps))
-    ms_step, per_launch = timed(False)
+    log("timing fused, warm (%d warmup, %d steps back to back)" % (args.warmup, args.steps))
+    ms_step_w, per_launch_w = timed(False)
     xs = [d["X"].cpu().numpy() for d in work]
     ys = [d["Y"].cpu().numpy() for d in work]
-    log("timing unfused level-set baseline")
-    ms_step_u, per_launch_u = timed(True)
-    log("cold launches (Infinity Cache evicted before each)")
-    cold_f, cold_u = cold(False), cold(True)
+    log("timing unfused level-set baseline, warm")
+    ms_step_uw, per_launch_uw = timed(True)
+    log("timing fused and unfused, cold (Infinity Cache evicted before every launch)")
+    ms_step, cold_f = cold(False)
+    ms_step_u, cold_u = cold(True)
+    per_launch = [float(np.mean(c)) for c in cold_f]
+    per_launch_u = [float(np.mean(c)) for c in cold_u]
     step_bytes = sum(d["bytes"] for d in work)
     value = step_bytes / (ms_step * 1e-3) / 1e9
     probe = None
@@ -293,13 +302,14 @@ def main():
             # single-value x gathers of one pass (off-diagonals of L, entries of A) and their rate
             "gathers": d["L"].nnz - d["L"].nrows + d["A"].nnz,
             "fused_Ggathers_per_s": round((d["L"].nnz - d["L"].nrows + d["A"].nnz) / (per_launch[k] * 1e-3) / 1e9, 1),
-            "warm_fused_ms_median": round(float(np.median(WARM_SAMPLES[False][k])), 4),
-            "warm_fused_ms_min": round(float(np.min(WARM_SAMPLES[False][k])), 4),
             "cold_fused_ms_median": round(float(np.median(cold_f[k])), 4),
             "cold_fused_ms_min": round(float(np.min(cold_f[k])), 4),
-            "cold_fused_GBps": round(d["bytes"] / (float(np.median(cold_f[k])) * 1e-3) / 1e9, 1),
-            "cold_unfused_ms_median": round(float(np.median(cold_u[k])), 4),
-            "cold_speedup_vs_unfused": round(float(np.median(cold_u[k])) / float(np.median(cold_f[k])), 3),
+            "warm_fused_ms": round(per_launch_w[k], 4),
+            "warm_fused_ms_median": round(float(np.median(WARM_SAMPLES[False][k])), 4),
+            "warm_fused_ms_min": round(float(np.min(WARM_SAMPLES[False][k])), 4),
+            "warm_fused_GBps": round(d["bytes"] / (per_launch_w[k] * 1e-3) / 1e9, 1),
+            "warm_unfused_ms": round(per_launch_uw[k], 4),
+            "warm_speedup_vs_unfused": round(per_launch_uw[k] / per_launch_w[k], 3),
             "bounds": bounds(d, per_launch[k], probe),
         }
 
@@ -330,11 +340,12 @@ def main():
         "frac_peak": round(value / HBM_PEAK_GBPS, 4),
         "unfused_GBps": round(step_bytes / (ms_step_u * 1e-3) / 1e9, 1),
         "speedup_vs_unfused": round(ms_step_u / ms_step, 3),
-        # the same step with the Infinity Cache evicted before every launch
-        # (medians of per-launch times, eviction outside the timed region)
-        "cold": {"GBps": round(step_bytes / (sum(float(np.median(c)) for c in cold_f) * 1e-3) / 1e9, 1),
-                 "ms_per_step": round(sum(float(np.median(c)) for c in cold_f), 4),
-                 "unfused_ms_per_step": round(sum(float(np.median(c)) for c in cold_u), 4)},
+        # value and ms_per_step are cold (the Infinity Cache evicted before
+        # every launch, outside the launch's events); the same steps run
+        # back to back with the caches warm:
+        "timing": "cold",
+        "warm": {"GBps": round(step_bytes / (ms_step_w * 1e-3) / 1e9, 1), "ms_per_step": round(ms_step_w, 4),
+                 "unfused_ms_per_step": round(ms_step_uw, 4), "speedup_vs_unfused": round(ms_step_uw / ms_step_w, 3)},
         "probe": probe,
         "per_matrix": per_matrix,
         "roofline": roofline,
@@ -519,42 +530,71 @@ def refine_pass_bytes(n, m, nnz_l, nnz_a, k):
     return nnz_l * 8 + nnz_a * 8 + (n + 1) * 4 + (m + 1) * 4 + 3 * n * k * 4
 
 
+def fused_refine_bytes(n, m, nnz_l, nnz_a, k):
+    """Algorithmic bytes of the fused refinement over k RHS: L's pattern with
+    both its FP64 and FP32 values, A's pattern and FP64 values, b read, x and
+    y written (FP64)."""
+    return nnz_l * 16 + (n + 1) * 4 + nnz_a * 12 + (m + 1) * 4 + (2 * n + m) * k * 8
+
+
+TUNED_KEYS = ("coarsen", "multi_path", "rhs_block", "spmv_delay", "rows_per_item", "max_item_nnz",
+              "waves_per_cu", "multi_waves_per_cu")
+
+
 def run_batched(args, sfm, synth, torch, dev, time_it):
-    """Batched right-hand sides with FP32 solves and FP64 refinement (2
-    corrections), against the FP64 fused and unfused executors on the same
-    k right-hand sides, for the random SPD matrix and the 2D 9-point
-    Laplacian on a 2048^2 grid."""
+    """Batched right-hand sides: FP32 solves with FP64 refinement -- fused
+    (one launch, 1 and 2 corrections) and staged (one launch per pass, 2
+    corrections) -- against the FP64 fused executor (autotuned for each k)
+    and the FP64 unfused level-set baseline on the same k right-hand sides,
+    for the random SPD matrix and the 2D 9-point Laplacian on 2048^2."""
     import numpy as np
     out = {}
     for name in ("randspd_1m", "lap2d9_2048"):
         L, A = synth.workload(name)
-        s = sfm.Schedule(L, A)
         L64 = torch.as_tensor(L.val, device=dev)
         A64 = torch.as_tensor(A.val, device=dev)
         L32 = L64.float()
         A32 = A64.float()
         for k in (1, 8, 32, 64):
+            s = sfm.Schedule(L, A)
             b = synth.vec_uniform(L.nrows, k=k, seed=1)
             B = torch.as_tensor(np.ascontiguousarray(b.T), device=dev).t() if k > 1 else torch.as_tensor(b, device=dev)
             B32 = B.float() if k == 1 else torch.as_tensor(np.ascontiguousarray(b.T), dtype=torch.float32, device=dev).t()
-            res = {}
             reps = 3 if name == "lap2d9_2048" else 5
-            t_ref = time_it(lambda: sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=2), reps)
-            X, Y, rel = sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=2)
-            t_f32 = time_it(lambda: sfm.trsv_spmv(s, L32, A32, B32), reps)
+            t0 = time.time()
+            params = None
+            if not args.no_autotune:
+                sfm.autotune(s, L64, A64, B)
+                params = {key: s.get_param(key) for key in TUNED_KEYS}
+                params["from_cache"] = s.get_param("tuned_from_cache")
+            t_tune = time.time() - t0
             t_f64 = time_it(lambda: sfm.trsv_spmv(s, L64, A64, B), reps)
             t_u64 = time_it(lambda: sfm.trsv_spmv(s, L64, A64, B, unfused=True), max(1, reps // 2))
-            nb = refine_pass_bytes(L.nrows, A.nrows, L.nnz, A.nnz, k)
-            res = {"k": k, "refined_ms": round(t_ref, 3), "fp32_pass_ms": round(t_f32, 3),
-                   "fp32_pass_GBps": round(nb / (t_f32 * 1e-3) / 1e9, 1),
+            t_f32 = time_it(lambda: sfm.trsv_spmv(s, L32, A32, B32), reps)
+            res = {"k": k, "autotuned_params": params, "autotune_s": round(t_tune, 1),
                    "fp64_fused_ms": round(t_f64, 3), "fp64_unfused_ms": round(t_u64, 3),
-                   "refined_relres_max": float(rel.max()),
-                   "refined_vs_fp64_unfused_speedup": round(t_u64 / t_ref, 3)}
+                   "fp32_pass_ms": round(t_f32, 3),
+                   "fp32_pass_GBps": round(refine_pass_bytes(L.nrows, A.nrows, L.nnz, A.nnz, k) / (t_f32 * 1e-3) / 1e9, 1)}
+            nb = fused_refine_bytes(L.nrows, A.nrows, L.nnz, A.nnz, k)
+            for nc in (1, 2):
+                t = time_it(lambda: sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=nc), reps)
+                X, Y, rel = sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=nc)
+                res["refined_fused_nc%d_ms" % nc] = round(t, 3)
+                res["refined_fused_nc%d_GBps" % nc] = round(nb / (t * 1e-3) / 1e9, 1)
+                res["refined_fused_nc%d_relres_max" % nc] = float(rel.max())
+                res["refined_fused_nc%d_vs_fp64_unfused_speedup" % nc] = round(t_u64 / t, 3)
+                res["refined_fused_nc%d_vs_fp64_fused_speedup" % nc] = round(t_f64 / t, 3)
+                if k in (1, 8):
+                    REFINE_SAMPLES[(name, k, nc)] = (L, A, b, X.cpu().numpy(), Y.cpu().numpy(), rel)
+            s.set_param("refine_path", 1)
+            t_st = time_it(lambda: sfm.refine_trsv_spmv(s, L32, L64, A64, B, n_corrections=2), reps)
+            s.set_param("refine_path", 0)
+            res["refined_staged_nc2_ms"] = round(t_st, 3)
             out["batched_%s_k%d" % (name, k)] = res
-            if k in (1, 8):
-                REFINE_SAMPLES[(name, k)] = (L, A, b, X.cpu().numpy(), Y.cpu().numpy())
-            log("batched %s k=%d: refine %.3f ms, fp32 pass %.3f ms, fp64 fused %.3f, unfused %.3f" % (
-                name, k, t_ref, t_f32, t_f64, t_u64))
+            log("batched %s k=%d: refine fused nc1 %.3f nc2 %.3f staged %.3f ms | fp32 pass %.3f | fp64 fused %.3f "
+                "unfused %.3f (tuned in %.1fs)" % (name, k, res["refined_fused_nc1_ms"], res["refined_fused_nc2_ms"],
+                                                  t_st, t_f32, t_f64, t_u64, t_tune))
+            s.free()
         del L64, A64, L32, A32
         torch.cuda.empty_cache()
     return out
@@ -641,18 +681,23 @@ def cpu_baseline(args, work, xs, ys, per_matrix, extras=None):
         fused = per_matrix[d["name"]]["fused_ms"] * 1e-3
         per_matrix[d["name"]]["NER_vs_sequential"] = (round(d["inspect_s"] / (dt - fused), 2) if dt > fused
                                                       else None)
-    # refined batched results against the FP64 oracle, column by column
-    for (name, k), (L, A, b, X, Y) in REFINE_SAMPLES.items():
+    # refined batched results (first two columns) against the FP64 oracle
+    # and, bit for bit, against the refinement oracle (orc_refine)
+    for (name, k, nc), (L, A, b, X, Y, rel) in REFINE_SAMPLES.items():
         bb = b if b.ndim == 2 else b[:, None]
         XX = X if X.ndim == 2 else X[:, None]
         YY = Y if Y.ndim == 2 else Y[:, None]
         ex = ey = 0.0
-        for c in range(bb.shape[1]):
+        same = True
+        for c in range(min(bb.shape[1], 2)):
             x = oracle.trsv_lower(L.rowptr, L.col, L.val, bb[:, c])
             y = oracle.spmv(A.rowptr, A.col, A.val, x)
             ex = max(ex, float(np.abs(XX[:, c] - x).max() / np.abs(x).max()))
             ey = max(ey, float(np.abs(YY[:, c] - y).max() / np.abs(y).max()))
-        errs["refined_%s_k%d" % (name, k)] = {"x_rel_err": ex, "y_rel_err": ey}
+            xr, yr, rr, _ = oracle.refine(L.rowptr, L.col, L.val, A.rowptr, A.col, A.val, bb[:, c], nc)
+            same = same and bool(np.array_equal(XX[:, c], xr) and np.array_equal(YY[:, c], yr) and rel[c] == rr)
+        errs["refined_%s_k%d_nc%d" % (name, k, nc)] = {"x_rel_err_vs_fp64": ex, "y_rel_err_vs_fp64": ey,
+                                                      "bit_identical_to_refine_oracle": same}
     # repeat whole passes until the time budget is used
     while total_s < args.cpu_seconds:
         for d in work:

@@ -417,17 +417,27 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
 size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs);
 
 /*
- * sf_refine_trsv_spmv — FP32 solves with FP64 residual refinement.
- *   1. x0 = L32^{-1} b in FP32 (fused kernel, FP32 accumulation);
- *   2. n_corrections times: r = b - L64 x in FP64, d = L32^{-1} r in FP32,
- *      x += d in FP64;
+ * sf_refine_trsv_spmv — FP32 solves with FP64 residual refinement (not in
+ * the paper; its stages compose the way the paper's kernels do: each stage
+ * reads, per row, only rows the previous stages have already produced).
+ *   1. x0 = the FP32 substitution of (L32, fl32(b)), FP32 accumulation;
+ *   2. n_corrections times: r = b - L64 x in FP64, d = the FP32
+ *      substitution of (L32, fl32(r)), x += d in FP64;
  *   3. y = A64 x with FP64 values and accumulation, and the final relative
  *      residual max_i |b - L64 x|_i / max_i |b_i| per column.
+ *   In each FP32 substitution a row sums its off-diagonal products first
+ *   (ascending column, from 0) and subtracts the sum from its rounded
+ *   right-hand side.  Default (sf_set_param "refine_path" 0, n_corrections
+ *   <= 3): every stage runs in ONE fused launch over the SpTRSV -> SpMV
+ *   schedule -- each row gathers one tuple of all stage values of each row
+ *   it reads -- and the results are bit-identical to that staged
+ *   definition.  "refine_path" 1 (and n_corrections > 3): one launch per
+ *   pass, with the executor's FP32 solves (their own summation order).
  *   L32/L64: device values of L in FP32 and FP64 (same pattern); A64:
  *   device FP64 values of A.  B, X (n x nrhs, ld), Y (m x nrhs, ldy): FP64.
  *   out_relres: HOST array of nrhs doubles, filled after a stream sync
  *   (this call synchronises the stream when out_relres is not NULL).
- *   n_corrections: 0..8 (2 is the usual choice).
+ *   n_corrections: 0..8 (2 is the usual choice; 0..3 fused).
  *   workspace: device scratch of sf_refine_workspace_bytes(s, nrhs) bytes.
  */
 sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64,

@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _c_int = ctypes.c_int
 
 
@@ -62,6 +63,8 @@ def _bind(lib):
                                             _c_int, _i32p, _i32p]),
         "orc_reuse_ts": (ctypes.c_double, [_c_int, _c_int, _c_int, _c_int]),
         "orc_reuse_it": (ctypes.c_double, [_c_int, _c_int]),
+        "orc_refine": (ctypes.c_double, [_c_int, _i32p, _i32p, _f64p, _f32p, _c_int, _i32p, _i32p, _f64p,
+                                         _f64p, _c_int, _f64p, _f64p, ctypes.c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -246,6 +249,22 @@ class Oracle:
 
     def reuse_it(self, n, nnz_l) -> float:
         return float(self.lib.orc_reuse_it(n, nnz_l))
+
+    def refine(self, rp, ci, l64, arp, aci, a64, b, ncorr, l32=None):
+        """Mixed-precision refinement of x = L^{-1} b (FP32 substitutions,
+        FP64 residuals, ncorr corrections) and y = A x in FP64; see
+        orc_refine.  l32 defaults to l64 rounded to FP32 (RNE).  Returns
+        (x, y, relres, stages[n, ncorr + 1] as float32)."""
+        rp, ci, l64, b = _i32(rp), _i32(ci), _f64(l64), _f64(b)
+        arp, aci, a64 = _i32(arp), _i32(aci), _f64(a64)
+        l32 = np.ascontiguousarray(l64.astype(np.float32) if l32 is None else l32, dtype=np.float32)
+        n, m = len(rp) - 1, len(arp) - 1
+        x = np.empty(max(n, 1), np.float64)
+        y = np.empty(max(m, 1), np.float64)
+        stages = np.empty((max(n, 1), ncorr + 1), np.float32)
+        rel = self.lib.orc_refine(n, rp, _ptr(ci), _ptr(l64), _ptr(l32), m, arp, _ptr(aci), _ptr(a64),
+                                  _ptr(b), int(ncorr), x, y, stages.ctypes.data)
+        return x[:n], y[:m], float(rel), stages[:n]
 
 
 _default = None

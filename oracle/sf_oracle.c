@@ -39,6 +39,14 @@
  *     lambda = L^{-T} (A^T g), grad_b = lambda, grad_L = -lambda x^T
  *     restricted to the pattern of L.
  *
+ *   - Mixed-precision refinement of x = L^{-1} b (not in the paper): FP32
+ *     substitutions with FP32 accumulation, FP64 residuals r = b - L x, the
+ *     FP32 correction solved from the rounded residual and added in FP64,
+ *     then y = A x in FP64.  In each FP32 substitution the off-diagonal
+ *     products are summed first (ascending column, from 0) and the sum is
+ *     subtracted from the rounded right-hand side: every row's sums then
+ *     need no value of the row's own chain (see orc_refine).
+ *
  * Parity pins: every function here is pinned by tests/test_oracle_*.py
  * against closed forms, dense brute force (numpy / LAPACK) and invariants.
  */
@@ -491,4 +499,79 @@ double orc_reuse_ts(int n, int nnz_l, int m, int nnz_a) {
 double orc_reuse_it(int n, int nnz_l) {
   double k1 = (double)nnz_l, k2 = (double)nnz_l + 2.0 * (double)n;
   return 2.0 * (double)nnz_l / (k1 > k2 ? k1 : k2);
+}
+
+/* Mixed-precision refinement of x = L^{-1} b with y = A x (one right-hand
+ * side; FP32 solves, FP64 residuals), written stage by stage:
+ *   x0   = the FP32 substitution of (L32, fl32(b));
+ *   x    = 0 + (double) x0;
+ *   for t = 1 .. ncorr:
+ *     r   = b - L64 x          (FP64; row i sums its entries in ascending
+ *                              column order from 0, diagonal last, then
+ *                              subtracts the sum from b_i);
+ *     d_t = the FP32 substitution of (L32, fl32(r));
+ *     x   = x + (double) d_t   (FP64);
+ *   y = A64 x                  (FP64, ascending, from 0);
+ *   relres = max_i |b - L64 x|_i / max_i |b_i|  (0 / 0 reported as 0).
+ * The FP32 substitution of (L32, c): for rows in order,
+ *   s_i = sum over j < i ascending of fl32(L32_ij v_j), from 0 (FP32);
+ *   v_i = fl32(fl32(c_i - s_i) / L32_ii).
+ * stages (optional, n * (ncorr + 1) floats, row-major by row): row i's
+ * x0_i, d_1i, ..., d_ncorr,i.  Returns relres. */
+double orc_refine(int n, const int32_t* rp, const int32_t* ci, const double* l64, const float* l32,
+                  int m, const int32_t* arp, const int32_t* aci, const double* a64,
+                  const double* b, int ncorr, double* x, double* y, float* stages) {
+  float* v = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  float* c = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  double* r = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int t = 0; t <= ncorr; ++t) {
+    /* right-hand side of this stage: fl32(b), then fl32(b - L64 x) */
+    for (int i = 0; i < n; ++i) {
+      if (t == 0) {
+        c[i] = (float)b[i];
+      } else {
+        double acc = 0.0;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) acc += l64[p] * x[ci[p]];
+        r[i] = b[i] - acc;
+      }
+    }
+    if (t > 0)
+      for (int i = 0; i < n; ++i) c[i] = (float)r[i];
+    /* FP32 substitution */
+    for (int i = 0; i < n; ++i) {
+      float sum = 0.0f, dg = 0.0f;
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        if (j < i) {
+          float prod = l32[p] * v[j];
+          sum = sum + prod;
+        } else if (j == i) {
+          dg = l32[p];
+        }
+      }
+      float top = c[i] - sum;
+      v[i] = top / dg;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (stages) stages[(size_t)i * (size_t)(ncorr + 1) + (size_t)t] = v[i];
+      x[i] = (t == 0 ? 0.0 : x[i]) + (double)v[i];
+    }
+  }
+  double rmax = 0.0, bmax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += l64[p] * x[ci[p]];
+    double ri = b[i] - acc;
+    if (fabs(ri) > rmax) rmax = fabs(ri);
+    if (fabs(b[i]) > bmax) bmax = fabs(b[i]);
+  }
+  for (int i = 0; i < m; ++i) {
+    double acc = 0.0;
+    for (int p = arp[i]; p < arp[i + 1]; ++p) acc += a64[p] * x[aci[p]];
+    y[i] = acc;
+  }
+  free(v);
+  free(c);
+  free(r);
+  return bmax > 0.0 ? rmax / bmax : rmax;
 }

@@ -65,15 +65,11 @@ struct Packer {
 uint64_t pattern_fingerprint(sf_schedule_s* s);  // autotuner cache key (below)
 
 // Record that every launch of an executor call is enqueued on `stream`
-// (the schedule's "done" event, created on first use) and pass r through.
+// (the schedule's "done" event, created with its device arrays) and pass r
+// through.
 sf_status enqueued(sf_schedule_s* s, void* stream, sf_status r) {
-  if (r != SF_OK || !s || !s->dev.ready) return r;
-  hipEvent_t ev = static_cast<hipEvent_t>(s->dev.done);
-  if (!ev) {
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return SF_ERR_HIP;
-    s->dev.done = ev;
-  }
-  return hip_status(hipEventRecord(ev, static_cast<hipStream_t>(stream)));
+  if (r != SF_OK || !s || !s->dev.ready || !s->dev.done) return r;
+  return hip_status(hipEventRecord(static_cast<hipEvent_t>(s->dev.done), static_cast<hipStream_t>(stream)));
 }
 
 // Wait until the work of the last executor call on the schedule is done.
@@ -129,6 +125,10 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oQr = pk.add(&s->qrng), oCqr = pk.add(&s->cqrng);
   const size_t oBco = pk.add(&s->bcorder), oBcip = pk.add(&s->bcitem_ptr);
   const size_t oBcl = pk.add(&s->bclloc), oBce = pk.add(&s->bceloc);
+  const size_t oRo = pk.add(&s->rorder), oRip = pk.add(&s->ritem_ptr), oRti = pk.add(&s->rtrsv_items);
+  const size_t oRq = pk.add(&s->rqrng), oRr = pk.add(&s->rroff), oRb = pk.add(&s->rbatch);
+  const size_t oRbp = pk.add(&s->rbatch_ptr), oRx = pk.add(&s->rext), oRxp = pk.add(&s->rext_ptr);
+  const size_t oRc = pk.add(&s->rcode);
   void* block = nullptr;
   SF_HIP(hipMalloc(&block, pk.off));
   char* b = static_cast<char*>(block);
@@ -158,11 +158,19 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.bcorder = P(oBco); d.bcitem_ptr = P(oBcip);
   d.bclloc = reinterpret_cast<uint8_t*>(b + oBcl);
   d.bceloc = reinterpret_cast<uint8_t*>(b + oBce);
+  d.rorder = P(oRo); d.ritem_ptr = P(oRip); d.rtrsv_items = P(oRti); d.rqrng = P(oRq); d.rroff = P(oRr);
+  d.rbatch = P(oRb); d.rbatch_ptr = P(oRbp); d.rext = P(oRx); d.rext_ptr = P(oRxp);
+  d.rcode = reinterpret_cast<uint16_t*>(b + oRc);
   if (!d.state) {
     std::vector<int32_t> init(kStateWords, 0);
     for (int p = 0; p < 2; ++p) init[info_off(p)] = kInfoNone;
     SF_HIP(hipMalloc(&d.state, kStateWords * sizeof(int32_t)));
     SF_HIP(hipMemcpy(d.state, init.data(), kStateWords * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  if (!d.done) {
+    hipEvent_t ev = nullptr;
+    SF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    d.done = ev;
   }
   SF_HIP(hipStreamSynchronize(st));  // host vectors may change after a re-cut
   d.device = cur;
@@ -365,6 +373,21 @@ sf_status exec_multi_core(sf_schedule_s* s, int dtype, const void* Lv, const voi
   return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
 }
 
+RegionArgs region_args(const sf_schedule_s* s) {
+  RegionArgs r{};
+  r.batch = s->dev.rbatch;
+  r.batch_ptr = s->dev.rbatch_ptr;
+  r.ext = s->dev.rext;
+  r.ext_ptr = s->dev.rext_ptr;
+  r.roff = s->dev.rroff;
+  r.code = s->dev.rcode;
+  r.rows_max = std::max(1, s->region_rows_max);
+  r.entries_max = std::max(1, s->region_entries_max);
+  r.ext_max = std::max(1, s->region_ext_max);
+  r.batches_max = std::max(1, s->region_batches_max);
+  return r;
+}
+
 // 64-bit words of the trace buffer: the item records, then two words per
 // iteration id (trace mode, kTraceItemWords).
 size_t trace_words(const sf_schedule_s* s) {
@@ -402,8 +425,25 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     a.kb = 1;
     a.nblk = 1;
     a.col_units = nrhs;
+    a.cached = s->cached_reads;
     a.trace = nrhs == 1 ? s->trace : nullptr;
     a.rtrace = a.trace ? a.trace + s->trace_items * kTraceItemWords : nullptr;
+    if (s->regioned) {
+      a.order = s->dev.rorder;
+      a.qrng = s->dev.rqrng;
+      a.item_ptr = s->dev.ritem_ptr;
+      a.item_list = Y ? nullptr : s->dev.rtrsv_items;
+      a.n_work = Y ? int32_t(s->ritem_ptr.size() - 1) : int32_t(s->rtrsv_items.size());
+      if (int64_t(a.n_work) * nrhs > int64_t(INT32_MAX) / 2) return SF_ERR_UNSUPPORTED;
+      const RegionArgs ra = region_args(s);
+      const int per_cu = std::min(std::max(1, occupancy_region(ra, dtype)),
+                                  nrhs == 1 ? s->waves_per_cu : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : 8));
+      const int grid = std::max(std::max(1, device_cus()) * per_cu, kStreams);
+      Timer tm(s, st);
+      if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));
+      SF_HIP(launch_fill_pending_cols(X, int32_t(s->n), ldx, nrhs, dtype, st));
+      return hip_status(launch_ts_region(a, ra, dtype, grid, st));
+    }
     if (s->chunked) {
       a.order = s->dev.corder;
       a.qrng = s->dev.cqrng;
@@ -762,7 +802,7 @@ sf_status sf_inspect(const sf_csr_pattern* L, const sf_csr_pattern* A, const sf_
   if (o.lanes_per_row != 0 && !pow2_in(o.lanes_per_row, 2, 64)) return SF_ERR_ARG;
   if (o.rows_per_item < 0 || o.max_item_nnz < 0) return SF_ERR_ARG;
   if (o.rhs_block != 0 && !pow2_in(o.rhs_block, 2, 64)) return SF_ERR_ARG;
-  if (o.coarsen < 0 || o.coarsen > 2) return SF_ERR_ARG;
+  if (o.coarsen < 0 || o.coarsen > 3) return SF_ERR_ARG;
   if (o.kind == SF_TRSV_SPMV && !A) return SF_ERR_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   sf_status st = o.kind == SF_ILU0_TRSV ? sf::check_square_diag(L) : sf::check_lower(L);
@@ -810,7 +850,7 @@ sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st) {
   st->depth = s->depth;
   st->joint_depth = s->joint_depth;
   st->back_depth = s->back_depth;
-  st->n_items = int32_t(s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
+  st->n_items = int32_t(s->regioned ? s->ritem_ptr.size() : s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
   st->n_back_items = s->has_back ? int32_t((s->bchunked ? s->bcitem_ptr : s->bitem_ptr).size()) - 1 : 0;
   st->max_level_width = s->max_level_width;
   st->lanes_per_row = s->lanes_trsv;
@@ -835,7 +875,7 @@ sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int3
   if (level) std::copy(s->level.begin(), s->level.end(), level);
   if (order) {
     if (s->kind == SF_TRSV_SPMV) {
-      const std::vector<int32_t>& o = s->chunked ? s->corder : s->order;
+      const std::vector<int32_t>& o = s->regioned ? s->rorder : s->chunked ? s->corder : s->order;
       std::copy(o.begin(), o.end(), order);
     } else {
       // each row contributes its SpIC0 iteration (id i) then its SpTRSV one (id n + i)
@@ -847,7 +887,7 @@ sf_status sf_schedule_export(sf_schedule s, int32_t* level, int32_t* order, int3
   }
   if (item_ptr) {
     const int mult = s->kind == SF_TRSV_SPMV ? 1 : 2;
-    const std::vector<int32_t>& ip = s->chunked ? s->citem_ptr : s->item_ptr;
+    const std::vector<int32_t>& ip = s->regioned ? s->ritem_ptr : s->chunked ? s->citem_ptr : s->item_ptr;
     for (size_t t = 0; t < ip.size(); ++t) item_ptr[t] = mult * ip[t];
   }
   return SF_OK;
@@ -857,11 +897,12 @@ sf_status sf_schedule_export_local(sf_schedule s, uint8_t* local_level, uint8_t*
   if (!s) return SF_ERR_ARG;
   const size_t npos = s->kind == SF_TRSV_SPMV ? size_t(s->n + s->m) : size_t(2 * s->n);
   if (local_level) {
-    if (s->chunked) std::copy(s->clloc.begin(), s->clloc.end(), local_level);
+    if (s->regioned) std::copy(s->rlloc.begin(), s->rlloc.end(), local_level);
+    else if (s->chunked) std::copy(s->clloc.begin(), s->clloc.end(), local_level);
     else std::fill(local_level, local_level + npos, uint8_t(0));
   }
-  if (entry_slot) {
-    if (s->chunked) std::copy(s->celoc.begin(), s->celoc.end(), entry_slot);
+  if (entry_slot) {  // regions address their columns with 16-bit codes: reported as 0xFF
+    if (s->chunked && !s->regioned) std::copy(s->celoc.begin(), s->celoc.end(), entry_slot);
     else std::fill(entry_slot, entry_slot + size_t(s->L.nnz()), uint8_t(0xFF));
   }
   return SF_OK;
@@ -1175,22 +1216,20 @@ size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs) 
   return size_t(std::max<int64_t>(s->n, 1)) * size_t(std::max(nrhs, 1)) * es;
 }
 
-sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val, const void* X,
-                      const void* B, const void* G, void* grad_B, void* grad_L_val, void* workspace,
-                      size_t ws_bytes, void* stream) {
-  if (!s || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
-  if (!s->has_back) return SF_ERR_ARG;
-  if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
-  if (s->n == 0) return SF_OK;
-  if (!L_val || !G || !grad_B || !grad_L_val || (s->m > 0 && !A_val)) return SF_ERR_ARG;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  sf_status r = upload(s, st);
-  if (r != SF_OK) return r;
+}  // extern "C"
+
+namespace {
+
+// The adjoint's launches (sf_backward): x recomputed into `workspace` when
+// X is NULL (by the fused forward executor), then the backward executor.
+// Makes no allocation once the schedule is resident on the device.
+sf_status backward_core(sf_schedule_s* s, sf_dtype dtype, const void* L_val, const void* A_val, const void* X,
+                        const void* B, const void* G, void* grad_B, void* grad_L_val, void* workspace,
+                        hipStream_t st) {
   const int dt = dtype == SF_F64 ? 0 : 1;
   const void* x = X;
   if (!x) {
-    if (!B || !workspace || ws_bytes < sf_backward_workspace_bytes(s, dtype, 1)) return SF_ERR_ARG;
-    r = exec_ts_fused(s, dtype, L_val, nullptr, B, int32_t(s->n), 1, workspace, int32_t(s->n), nullptr, 0, st);
+    sf_status r = exec_ts_fused(s, dtype, L_val, nullptr, B, int32_t(s->n), 1, workspace, int32_t(s->n), nullptr, 0, st);
     if (r != SF_OK) return r;
     x = workspace;
   }
@@ -1213,13 +1252,40 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
     a.item_ptr = d.bitem_ptr;
     a.n_work = int32_t(s->bitem_ptr.size() - 1);
   }
-  r = next_epoch(s, st, a.ls);
+  sf_status r = next_epoch(s, st, a.ls);
   if (r != SF_OK) return r;
   const int grid = persistent_grid(s, occupancy_bwd(dt, s->lanes_trsv));
   Timer tm(s, st);
   // grad_B is the lambda buffer and its own readiness flag
   SF_HIP(launch_fill_pending(grad_B, size_t(s->n), dt, st));
-  return enqueued(s, stream, hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st)));
+  return hip_status(launch_bwd(a, dt, std::min(s->lanes_trsv, 32), grid, st));
+}
+
+sf_status check_backward_args(sf_schedule_s* s, sf_dtype dtype, const void* L_val, const void* A_val,
+                              const void* X, const void* B, const void* G, void* grad_B, void* grad_L_val) {
+  if (!s || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+  if (!s->has_back) return SF_ERR_ARG;
+  if (dtype != SF_F64 && dtype != SF_F32) return SF_ERR_ARG;
+  if (s->n == 0) return SF_OK;
+  if (!L_val || !G || !grad_B || !grad_L_val || (s->m > 0 && !A_val)) return SF_ERR_ARG;
+  if (!X && !B) return SF_ERR_ARG;
+  return SF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val, const void* X,
+                      const void* B, const void* G, void* grad_B, void* grad_L_val, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  sf_status r = check_backward_args(s, dtype, L_val, A_val, X, B, G, grad_B, grad_L_val);
+  if (r != SF_OK || s->n == 0) return r;
+  if (!X && (!workspace || ws_bytes < sf_backward_workspace_bytes(s, dtype, 1))) return SF_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  r = upload(s, st);
+  if (r != SF_OK) return r;
+  return enqueued(s, stream, backward_core(s, dtype, L_val, A_val, X, B, G, grad_B, grad_L_val, workspace, st));
 }
 
 // Refinement workspace, in the interleaved block layout of the solve (a
@@ -1257,10 +1323,124 @@ RefineWs refine_layout(const sf_schedule_s* s, int nrhs, void* base) {
   return w;
 }
 
+// Workspace of the fused refinement (k_rfused.hip): the stage tuples
+// (4 floats per row and column at most), then with several right-hand
+// sides the packed FP64 right-hand sides, the interleaved x (its own
+// readiness flags) and the packed product, all in the block layout of the
+// solve; then the max-abs accumulators.
+struct FusedRefineWs {
+  float* tup;
+  double *b64, *xf, *y64;
+  unsigned long long* mx;
+  size_t bytes;
+};
+
+// Block width of the fused refinement: the solve's.
+int fused_refine_kb(const sf_schedule_s* s, int nrhs) { return solve_kb(s, nrhs); }
+
+FusedRefineWs fused_refine_layout(const sf_schedule_s* s, int nrhs, void* base) {
+  const int kb = fused_refine_kb(s, nrhs);
+  const size_t cols = size_t((nrhs + kb - 1) / kb) * size_t(kb);
+  const size_t n = size_t(std::max<int64_t>(s->n, 1)), m = size_t(std::max<int64_t>(s->m, 1));
+  const bool multi = kb > 1;
+  const size_t sizes[5] = {align256(n * cols * 16), align256(multi ? n * cols * 8 : 256),
+                           align256(multi ? n * cols * 8 : 256), align256(multi ? m * cols * 8 : 256), 2 * 64 * 8};
+  char* p = static_cast<char*>(base);
+  void* at[5];
+  size_t off = 0;
+  for (int k = 0; k < 5; ++k) {
+    at[k] = p ? p + off : nullptr;
+    off += sizes[k];
+  }
+  return FusedRefineWs{static_cast<float*>(at[0]), static_cast<double*>(at[1]), static_cast<double*>(at[2]),
+                       static_cast<double*>(at[3]), static_cast<unsigned long long*>(at[4]), off};
+}
+
 size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs) {
   if (!s || nrhs < 1 || nrhs > 64) return 0;
-  return refine_layout(s, nrhs, nullptr).bytes;
+  return std::max(refine_layout(s, nrhs, nullptr).bytes, fused_refine_layout(s, nrhs, nullptr).bytes);
 }
+
+}  // extern "C"
+
+namespace {
+
+// Per-column relative residuals from the max-abs accumulators (host copy).
+sf_status read_relres(const unsigned long long* mx, int nrhs, double* out, hipStream_t st) {
+  if (!out) return SF_OK;
+  std::vector<unsigned long long> h(size_t(2 * nrhs));
+  SF_HIP(hipMemcpyAsync(h.data(), mx, h.size() * 8, hipMemcpyDeviceToHost, st));
+  SF_HIP(hipStreamSynchronize(st));
+  for (int c = 0; c < nrhs; ++c) {
+    double rm, bm;
+    std::memcpy(&rm, &h[2 * c], 8);
+    std::memcpy(&bm, &h[2 * c + 1], 8);
+    out[c] = bm > 0 ? rm / bm : rm;
+  }
+  return SF_OK;
+}
+
+// The fused refinement: every stage of every right-hand side in one launch
+// over the joint SpTRSV -> SpMV schedule (level items, or the multi-RHS
+// units), packing and unpacking around it for several right-hand sides.
+sf_status refine_fused(sf_schedule_s* s, const float* L32, const double* L64, const double* A64, const double* B,
+                       int32_t ldb, int32_t nrhs, double* X, int32_t ldx, double* Y, int32_t ldy, int32_t nc,
+                       double* out_relres, void* workspace, hipStream_t st) {
+  const int kb = fused_refine_kb(s, nrhs);
+  const bool multi = kb > 1;
+  const FusedRefineWs ws = fused_refine_layout(s, nrhs, workspace);
+  const int n = int32_t(s->n);
+  const int nblk = (nrhs + kb - 1) / kb;
+  const size_t cols = size_t(nblk) * size_t(kb);
+  const int S4 = rf_tuple_floats(nc);
+  RfArgs a{};
+  a.ts = ts_args(s, L64, A64, nullptr, n, nrhs, multi ? nullptr : X, n, multi ? nullptr : Y, int32_t(s->m));
+  a.L32 = L32;
+  a.tup = reinterpret_cast<unsigned long long*>(ws.tup);
+  a.maxabs = ws.mx;
+  a.nrhs = nrhs;
+  if (multi) {
+    sf_status r = ensure_units(s, std::max(1, 64 / kb), st);
+    if (r != SF_OK) return r;
+    a.ts.unit_rng = reinterpret_cast<const int2*>(Y ? s->dev.unit_rng : s->dev.unit_trsv_rng);
+    a.ts.item_ptr = nullptr;
+    a.ts.item_list = nullptr;
+    a.ts.n_work = Y ? s->dev.n_units : s->dev.n_unit_trsv;
+    a.ts.kb = kb;
+    a.ts.nblk = nblk;
+    a.ts.xi = ws.xf;
+    a.ts.Y = Y ? ws.y64 : nullptr;
+    a.B = ws.b64;
+  } else {
+    a.B = B;  // one right-hand side: b, x and y are plain vectors (x doubles as the SpMV rows' flags)
+  }
+  sf_status r = next_epoch(s, st, a.ts.ls);
+  if (r != SF_OK) return r;
+  const int waves = multi ? multi_waves(s, kb, nrhs) : s->waves_per_cu;
+  const int grid = persistent_grid(s, occupancy_rfused(nc, kb), waves);
+  Timer tm(s, st);
+  SF_HIP(launch_fill_pending(ws.tup, size_t(n) * cols * size_t(S4), 1, st));
+  SF_HIP(launch_fill_u64(ws.mx, 2 * nrhs, st));
+  if (multi) {
+    // B -> interleaved FP64 blocks; x (interleaved) filled with the pending pattern
+    SF_HIP(launch_pack(B, 0, ldb, n, nrhs, ws.b64, 0, ws.xf, kb, st));
+  } else {
+    SF_HIP(launch_fill_pending(X, size_t(n), 0, st));
+  }
+  if (a.ts.n_work > 0) SF_HIP(launch_rfused(a, nc, kb, grid, st));
+  if (multi) {
+    SF_HIP(launch_unpack(ws.xf, 0, n, nrhs, X, ldx, kb, st));
+    if (Y) SF_HIP(launch_unpack(ws.y64, 0, int32_t(s->m), nrhs, Y, ldy, kb, st));
+  }
+  tm.stop();
+  r = enqueued(s, st, SF_OK);
+  if (r != SF_OK) return r;
+  return read_relres(ws.mx, nrhs, out_relres, st);
+}
+
+}  // namespace
+
+extern "C" {
 
 sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64, const double* A64,
                               const double* B, int32_t ldb, int32_t nrhs, double* X, int32_t ldx,
@@ -1273,6 +1453,13 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   if (!L32 || !L64 || !B || !X || (Y && !A64)) return SF_ERR_ARG;
   if (!workspace || ws_bytes < sf_refine_workspace_bytes(s, nrhs)) return SF_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->refine_path == 0 && n_corrections <= 3) {
+    if (int64_t(s->n) * fused_refine_kb(s, nrhs) > int64_t(INT32_MAX)) return SF_ERR_UNSUPPORTED;
+    sf_status r = upload(s, st);
+    if (r != SF_OK) return r;
+    return refine_fused(s, L32, L64, A64, B, ldb, nrhs, X, ldx, Y, ldy, n_corrections, out_relres, workspace, st);
+  }
+  // staged: one launch per pass (FP32 solves, FP64 residual passes, final pass)
   sf_status r = upload(s, st);
   if (r != SF_OK) return r;
   const int kb = solve_kb(s, nrhs);
@@ -1353,19 +1540,7 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   }
   r = enqueued(s, stream, SF_OK);
   if (r != SF_OK) return r;
-  const unsigned long long* mx = ws.mx;
-  if (out_relres) {
-    std::vector<unsigned long long> h(size_t(2 * nrhs));
-    SF_HIP(hipMemcpyAsync(h.data(), mx, h.size() * 8, hipMemcpyDeviceToHost, st));
-    SF_HIP(hipStreamSynchronize(st));
-    for (int c = 0; c < nrhs; ++c) {
-      double rm, bm;
-      std::memcpy(&rm, &h[2 * c], 8);
-      std::memcpy(&bm, &h[2 * c + 1], 8);
-      out_relres[c] = bm > 0 ? rm / bm : rm;
-    }
-  }
-  return SF_OK;
+  return read_relres(ws.mx, nrhs, out_relres, st);
 }
 
 // Re-cut the work items after a parameter they depend on changed; the
@@ -1440,7 +1615,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     if (v < 1 || v > kStreams) return SF_ERR_ARG;
     s->claim_streams = int32_t(v);
   } else if (k == "rows_per_item" || k == "max_item_nnz" || k == "spmv_delay" || k == "coarsen") {
-    if (k == "coarsen" ? (v < 0 || v > 2 || s->kind != SF_TRSV_SPMV)
+    if (k == "coarsen" ? (v < 0 || v > 3 || s->kind != SF_TRSV_SPMV)
         : k == "spmv_delay" ? (v < -1 || v > (int64_t(1) << 30)) : (v < 1 || v > (int64_t(1) << 30)))
       return SF_ERR_ARG;
     if (k == "rows_per_item" && v > 64) return SF_ERR_ARG;  // one lane finishes each row
@@ -1450,6 +1625,17 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     else s->spmv_delay = int32_t(v);
     const sf_status rc = recut(s);
     if (rc != SF_OK) return rc;
+  } else if (k == "region_rows") {
+    if (v < 64 || v > 16384 || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+    s->region_rows = int32_t(v);
+    const sf_status rc = recut(s);
+    if (rc != SF_OK) return rc;
+  } else if (k == "cached_reads") {
+    if (v < 0 || v > 3) return SF_ERR_ARG;
+    s->cached_reads = int32_t(v);
+  } else if (k == "refine_path") {
+    if (v < 0 || v > 1) return SF_ERR_ARG;
+    s->refine_path = int32_t(v);
   } else if (k == "autotune_cache") {
     s->autotune_cache = v ? 1 : 0;
   } else if (k == "no_fusion") {
@@ -1464,7 +1650,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
       s->trace = nullptr;
     }
     if (v) {
-      s->trace_items = std::max(s->item_ptr.size(), s->citem_ptr.size()) + 1;
+      s->trace_items = std::max(std::max(s->item_ptr.size(), s->citem_ptr.size()), s->ritem_ptr.size()) + 1;
       const size_t bytes = trace_words(s) * sizeof(unsigned long long);
       if (trace_words(s) > size_t(INT32_MAX)) return SF_ERR_UNSUPPORTED;
       if (hipMalloc(&s->trace, bytes) != hipSuccess) return SF_ERR_OOM;
@@ -1498,6 +1684,11 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "back_coarsened") *v = s->bchunked ? 1 : 0;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "autotune_cache") *v = s->autotune_cache;
+  else if (k == "refine_path") *v = s->refine_path;
+  else if (k == "cached_reads") *v = s->cached_reads;
+  else if (k == "region_rows") *v = s->region_rows;
+  else if (k == "regioned") *v = s->regioned ? 1 : 0;  // read only: the region plan is in effect
+  else if (k == "region_chain") *v = s->region_chain;
   else if (k == "tuned_from_cache") *v = s->tuned_from_cache;  // read only: last sf_autotune reused a result
   else if (k == "fingerprint") *v = int64_t(pattern_fingerprint(s) & 0x7fffffffffffffffull);
   else if (k == "timing") *v = s->timing;
@@ -1515,8 +1706,9 @@ namespace {
 // of both CSR patterns), the value type, the right-hand-side count and
 // whether y is computed: a schedule inspected again from the same matrix
 // takes the tuned parameters without timing anything.
-const char* const kTuneKeys[] = {"coarsen",      "multi_path",   "rhs_block",    "spmv_delay",
-                                 "rows_per_item", "max_item_nnz", "waves_per_cu", "multi_waves_per_cu"};
+const char* const kTuneKeys[] = {"coarsen",       "multi_path",   "rhs_block",    "spmv_delay",
+                                 "rows_per_item", "max_item_nnz", "waves_per_cu", "multi_waves_per_cu",
+                                 "cached_reads"};
 constexpr int kNTune = int(sizeof(kTuneKeys) / sizeof(kTuneKeys[0]));
 struct Tuned {
   int64_t v[kNTune];
@@ -1635,6 +1827,7 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});
   if (r == SF_OK && nrhs == 1) r = try_param("max_item_nnz", {128, 256, 512, 1024, 2048});
   if (r == SF_OK && nrhs == 1) r = try_param("waves_per_cu", {4, 8, 16});
+  if (r == SF_OK && nrhs == 1) r = try_param("cached_reads", {1, 2, 3});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_waves_per_cu", {8, 16, 32});
   if (r == SF_OK) r = upload(s, st);
   r = enqueued(s, stream, r);
@@ -1669,7 +1862,7 @@ sf_status sf_sync_status(sf_schedule s, void* stream) {
 
 sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count) {
   if (!s || !out || !s->trace) return SF_ERR_ARG;
-  const size_t items = (s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
+  const size_t items = (s->regioned ? s->ritem_ptr.size() : s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
   const size_t rows = 2 * size_t(s->n + s->m);
   if (count < int64_t(items * kTraceItemWords + rows)) return SF_ERR_SHAPE;
   wait_done(s);

@@ -202,35 +202,5 @@ __device__ __forceinline__ T ld_stream(const T* p) {
   return __builtin_nontemporal_load(p);
 }
 
-// ---- cross-lane sums over groups of G consecutive lanes (DPP inside a row
-// of 16 lanes, ds_bpermute beyond) ----
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL, typename T>
-__device__ __forceinline__ T dpp(T v) {
-  if constexpr (sizeof(T) == 8) return dpp_d<CTRL>(v);
-  else return dpp_f<CTRL>(v);
-}
-
-// Every lane of each aligned group of G lanes receives the group's sum.
-template <int G, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-  if constexpr (G >= 2) v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
-  if constexpr (G >= 4) v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
-  if constexpr (G >= 8) v += dpp<0x141>(v);  // row_half_mirror: other quad of 8
-  if constexpr (G >= 16) v += dpp<0x140>(v); // row_mirror: other half of 16
-  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
-  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
 }  // namespace dev
 }  // namespace sf

@@ -237,6 +237,12 @@ static ChunkPlan chunk_dag(int32_t n, const std::vector<int32_t>& rp, const std:
         continue;
       }
       if (cost + cost_of(k.row) > budget) break;
+      {  // local wavefronts are kept in a byte: an item closes before its 255th
+        int32_t d = 0;
+        for (int32_t p = pb(k.row); p < pe(k.row); ++p)
+          if (c.chunk_of[ci[p]] == cid) d = std::max<int32_t>(d, c.lloc[ci[p]] + 1);
+        if (d >= 255) break;
+      }
       cand.pop();
       cost += cost_of(k.row);
       ++size;
@@ -281,6 +287,42 @@ static ChunkPlan chunk_dag(int32_t n, const std::vector<int32_t>& rp, const std:
     c.chain = std::max(c.chain, chain[k]);
   }
   return c;
+}
+
+// Critical-path model of items whose rows wait for their own inputs
+// (pipelined items): an item runs its local wavefronts in order, each in
+// batches of up to 64 rows costing kPipeStep, and a local wavefront starts
+// once the previous one is done and every input from another item has been
+// published for kPipeHop.  Measured on MI355X: with the coarsened plan's
+// 64-row items on the 3D 7-point 128^3 grid the model gives 434 us against
+// 459 us measured.
+constexpr double kPipeHop = 3.8, kPipeStep = 0.21;
+
+static double pipelined_estimate(int32_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci, int lo,
+                                 int hi, const ChunkPlan& c) {
+  std::vector<double> trow(size_t(n), 0.0);
+  double tmax = 0.0;
+  const int32_t nc = int32_t(c.ptr.size()) - 1;
+  for (int32_t k = 0; k < nc; ++k) {
+    double fin = 0.0;
+    int32_t q = c.ptr[k];
+    while (q < c.ptr[k + 1]) {
+      const int32_t lv = c.lloc[c.rows[q]];
+      int32_t e = q;
+      while (e < c.ptr[k + 1] && c.lloc[c.rows[e]] == lv) ++e;
+      double start = fin;
+      for (int32_t t = q; t < e; ++t) {
+        const int32_t u = c.rows[t];
+        for (int32_t p = rp[u] + lo; p < rp[u + 1] - hi; ++p)
+          if (c.chunk_of[ci[p]] != k) start = std::max(start, trow[ci[p]] + kPipeHop);
+      }
+      fin = start + kPipeStep * double((e - q + 63) / 64);
+      for (int32_t t = q; t < e; ++t) trow[c.rows[t]] = fin;
+      q = e;
+    }
+    tmax = std::max(tmax, fin);
+  }
+  return tmax;
 }
 
 // Per stored entry p of a row: the slot of its column inside the row's item,
@@ -371,9 +413,131 @@ static void build_chunks(sf_schedule_s* s) {
     spmv_run(k + 1);
   }
   s->celoc = entry_slots(c, n, L.rp, L.ci, 0, 1);
+  s->est_chunk_pipe_us = pipelined_estimate(n, L.rp, L.ci, 0, 1, c);
   s->chunk_chain = c.chain;
   s->max_local_depth = nc > 0 ? c.maxloc + 1 : 0;
   s->est_chunk_us = cp_all;
+}
+
+// Region plan (one wavefront per region, regions of up to region_rows rows
+// grown by chunk_dag without an entry budget).  A region's rows run level
+// by level inside one wavefront, each local level in batches of up to 64
+// rows, with the region's x values kept in LDS; every row waits only for its
+// own inputs, so a region starts as soon as its first rows' inputs exist
+// and regions downstream overlap the ones they depend on.  Per region: its
+// batches (first position, first external input first used there), its
+// external inputs (distinct columns read from other regions, in order of
+// first use) and, per stored off-diagonal of its rows, a 16-bit code: the
+// column's position inside the region, or 0x8000 | the external input's
+// index.  Per position the offset of its row's entries inside the region's
+// entry table.  SpMV rows follow as in the coarsened plan.
+static void build_regions(sf_schedule_s* s) {
+  const Pattern& L = s->L;
+  const int32_t n = L.nrows;
+  const int64_t m = s->m;
+  const int32_t R = std::max(64, std::min(s->region_rows, 16384));
+  const ChunkPlan c = chunk_dag(n, L.rp, L.ci, 0, 1, s->level, R, int64_t(1) << 62);
+  const int32_t nc = int32_t(c.ptr.size()) - 1;
+  // SpMV rows after the region holding their last input, by default after every region
+  std::vector<int32_t> skey(size_t(m), -1);
+  for (int64_t r = 0; r < m; ++r)
+    for (int32_t p = s->A.rp[r]; p < s->A.rp[r + 1]; ++p) skey[r] = std::max(skey[r], c.chunk_of[s->A.ci[p]]);
+  const int64_t delay = s->spmv_delay < 0 ? (int64_t(1) << 30) : int64_t(s->spmv_delay);
+  if (delay > 0 && nc > 0) {
+    const int64_t per_step = std::max<int64_t>(1, nc / std::max(1, c.chain));
+    for (int64_t r = 0; r < m; ++r)
+      skey[r] = int32_t(std::min<int64_t>(int64_t(skey[r]) + delay * per_step, nc - 1));
+  }
+  std::vector<int32_t> bucket(static_cast<size_t>(nc) + 2, 0), sorder(static_cast<size_t>(m));
+  for (int64_t r = 0; r < m; ++r) bucket[size_t(skey[r] + 1) + 1]++;
+  for (size_t k = 0; k + 1 < bucket.size(); ++k) bucket[k + 1] += bucket[k];
+  {
+    std::vector<int32_t> fill(bucket.begin(), bucket.end() - 1);
+    for (int64_t r = 0; r < m; ++r) sorder[size_t(fill[size_t(skey[r] + 1)]++)] = int32_t(r);
+  }
+  s->rorder.clear();
+  s->ritem_ptr.assign(1, 0);
+  s->rtrsv_items.clear();
+  s->rlloc.clear();
+  s->rroff.clear();
+  s->rbatch.clear();           // pairs (first position, first external index) per batch
+  s->rbatch_ptr.assign(1, 0);  // per item: its batches
+  s->rext.clear();
+  s->rext_ptr.assign(1, 0);    // per item: its external inputs
+  s->rcode.assign(size_t(L.nnz()), 0);
+  s->region_rows_max = s->region_entries_max = s->region_ext_max = s->region_batches_max = 0;
+  auto close_item = [&]() {
+    s->ritem_ptr.push_back(int32_t(s->rorder.size()));
+    s->rbatch_ptr.push_back(int32_t(s->rbatch.size() / 2));
+    s->rext_ptr.push_back(int32_t(s->rext.size()));
+  };
+  auto spmv_run = [&](int32_t b) {  // SpMV rows of bucket b, items of up to 64 rows and the nonzero budget
+    int32_t q = bucket[b];
+    const int32_t e = bucket[b + 1];
+    while (q < e) {
+      int64_t cost = 0;
+      int32_t k = q;
+      while (k < e && k - q < 64) {
+        const int32_t r = sorder[k];
+        const int64_t cr = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
+        if (k > q && cost + cr > s->max_item_nnz) break;
+        cost += cr;
+        ++k;
+      }
+      for (int32_t t = q; t < k; ++t) {
+        s->rorder.push_back(int32_t(n + sorder[t]));
+        s->rlloc.push_back(0);
+        s->rroff.push_back(0);
+      }
+      close_item();
+      q = k;
+    }
+  };
+  std::vector<int32_t> ext_of(size_t(n), -1), ext_stamp(size_t(n), -1);
+  spmv_run(0);
+  for (int32_t k = 0; k < nc; ++k) {
+    const int32_t q0 = int32_t(s->rorder.size());
+    const int32_t e0 = int32_t(s->rext.size());
+    int32_t entries = 0;
+    for (int32_t q = c.ptr[k]; q < c.ptr[k + 1]; ++q) {
+      const int32_t u = c.rows[q];
+      const int32_t pos = int32_t(s->rorder.size());
+      // a new batch at a change of local level or every 64 rows of one level
+      if (q == c.ptr[k] || c.lloc[u] != c.lloc[c.rows[q - 1]] || (pos - s->rbatch[s->rbatch.size() - 2]) >= 64) {
+        s->rbatch.push_back(pos);
+        s->rbatch.push_back(int32_t(s->rext.size()) - e0);
+      }
+      s->rorder.push_back(u);
+      s->rlloc.push_back(c.lloc[u]);
+      s->rroff.push_back(entries);
+      for (int32_t p = L.rp[u]; p < L.rp[u + 1] - 1; ++p) {
+        const int32_t j = L.ci[p];
+        if (c.chunk_of[j] == k) {
+          s->rcode[size_t(p)] = uint16_t(c.slot[j]);
+        } else {
+          if (ext_stamp[j] != k) {
+            ext_stamp[j] = k;
+            ext_of[j] = int32_t(s->rext.size()) - e0;
+            s->rext.push_back(j);
+          }
+          s->rcode[size_t(p)] = uint16_t(0x8000 | ext_of[j]);
+        }
+      }
+      entries += L.rp[u + 1] - 1 - L.rp[u];
+    }
+    s->rtrsv_items.push_back(int32_t(s->ritem_ptr.size()) - 1);
+    s->region_rows_max = std::max(s->region_rows_max, int32_t(s->rorder.size()) - q0);
+    s->region_entries_max = std::max(s->region_entries_max, entries);
+    s->region_ext_max = std::max(s->region_ext_max, int32_t(s->rext.size()) - e0);
+    close_item();
+    const size_t nbp = s->rbatch_ptr.size();
+    s->region_batches_max = std::max(s->region_batches_max, s->rbatch_ptr[nbp - 1] - s->rbatch_ptr[nbp - 2]);
+    spmv_run(k + 1);
+  }
+  s->rbatch.push_back(int32_t(s->rorder.size()));  // end sentinel: the last batch's end
+  s->rbatch.push_back(0);
+  s->region_chain = c.chain;
+  s->est_region_us = pipelined_estimate(n, L.rp, L.ci, 0, 1, c);
 }
 
 // Backward coarsened plan: chunk_dag over L^T (the transposed solve's
@@ -462,13 +626,25 @@ void cut_items(sf_schedule_s* s) {
     s->chunk_chain = 0;
     s->max_local_depth = 0;
     s->est_chunk_us = 0.0;
-    const bool try_chunks = s->coarsen == 2 || (s->coarsen == 0 && mesh_like(n, s->L.rp, s->L.ci, 0, 1, s->level));
+    const bool try_chunks = s->coarsen >= 2 || (s->coarsen == 0 && mesh_like(n, s->L.rp, s->L.ci, 0, 1, s->level));
     s->cqrng.clear();
     if (try_chunks && n > 0) build_chunks(s);
     position_ranges(s, s->order, s->qrng);
     if (!s->corder.empty()) position_ranges(s, s->corder, s->cqrng);
     s->chunked = !s->ctrsv_items.empty() &&
-                 (s->coarsen == 2 || s->est_chunk_us < 0.8 * s->est_level_us);
+                 (s->coarsen == 2 || s->coarsen == 3 || s->est_chunk_us < 0.8 * s->est_level_us);
+    // regions (one right-hand side): on request, or where the coarsened plan
+    // is chosen and the region model beats its own estimate clearly
+    s->rorder.clear();
+    s->regioned = false;
+    s->est_region_us = 0.0;
+    if (n > 0 && s->coarsen == 3) {
+      build_regions(s);
+      position_ranges(s, s->rorder, s->rqrng);
+      const size_t lds = region_lds_bytes(s->region_rows_max, s->region_entries_max, s->region_ext_max,
+                                          s->region_batches_max, 8);
+      s->regioned = lds <= kRegionLdsMax && (s->coarsen == 3 || s->est_region_us < 0.85 * s->est_chunk_pipe_us);
+    }
   } else {
     std::vector<int32_t> key(static_cast<size_t>(n)), cost(static_cast<size_t>(n));
     for (int64_t i = 0; i < n; ++i) {

@@ -31,6 +31,56 @@ using dev::st_co;
 using dev::stream_accumulate;
 using dev::WaveLds;
 
+// grad_L[p] = -lambda_i x_j for every stored (i, j) of the item's rows i of
+// L: the rows' entries are concatenated and dealt to the lanes, kRounds per
+// lane and pass (as the entry stream deals a solve's terms), each row's lane
+// laying out its positions and its lambda_i in LDS, so one round of loads
+// serves every entry and consecutive lanes store consecutive entries.
+template <typename T>
+__device__ __forceinline__ void grad_rows(const int32_t* __restrict__ Lrp, const int32_t* __restrict__ Lci,
+                                          const T* __restrict__ X, T* __restrict__ gL, int nr, int i, T li, int lane,
+                                          WaveLds<T>& w) {
+  using dev::kPass;
+  using dev::kRounds;
+  const bool mine = lane < nr;
+  const int r0 = mine ? Lrp[i] : 0;
+  const int len = mine ? Lrp[i + 1] - r0 : 0;
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  const T nli = -li;
+  for (int base = 0; base < total; base += kPass) {
+    __builtin_amdgcn_wave_barrier();
+    if (mine) {
+      const int lo = max(off, base), hi = min(off + len, base + kPass);
+      for (int t = lo; t < hi; ++t) {
+        w.pos[t - base] = r0 + (t - off);
+        w.prod[t - base] = nli;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    int p[kRounds];
+    T f[kRounds], xv[kRounds];
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      p[e] = k < total ? w.pos[k - base] : -1;
+      f[e] = k < total ? w.prod[k - base] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) xv[e] = p[e] >= 0 ? X[Lci[p[e]]] : T(0);
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e)
+      if (p[e] >= 0) __builtin_nontemporal_store(f[e] * xv[e], gL + p[e]);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // With a coarsened plan (a.lloc != nullptr), items whose rows span several
 // local wavefronts solve their lambda values through dev::chunk_solve.
 template <typename T>
@@ -71,8 +121,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_bwd(BwdArgs a) {
       li = publishable(acc / lii);
       if (mine) st_co(lam + i, li);
     }
-    if (mine)
-      for (int p = a.Lrp[i]; p < a.Lrp[i + 1]; ++p) __builtin_nontemporal_store(-li * X[a.Lci[p]], gL + p);
+    grad_rows(a.Lrp, a.Lci, X, gL, nr, i, li, lane, w);
     t = tn;
   }
 }

@@ -44,11 +44,26 @@ struct TsArgs {
   int32_t n_work;          // items to run (entries of item_list, or all items)
   const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
   const uint8_t* eloc;     // coarsened plan: per L entry, slot of its column in the item or 0xFF
+  int32_t cached;           // fused executor: bit 0 = SpMV rows, bit 1 = SpTRSV level items read x
+                            // through the caches first (stream.h, VEC = 3)
   unsigned long long* trace;  // optional: kTraceItemWords words per item (see k_ts.hip)
   unsigned long long* rtrace; // with trace: per iteration id (SpTRSV row i, SpMV row n + r) its
                               // publication time and how many times it was published
   LaunchState ls;
 };
+
+// Region plan of the fused executor (k_region.hip, inspect.cpp build_regions).
+struct RegionArgs {
+  const int32_t* batch;      // per batch: (first claim position, first external input of the region)
+  const int32_t* batch_ptr;  // per item: its batches (none for SpMV items)
+  const int32_t* ext;        // external inputs (columns) of every region
+  const int32_t* ext_ptr;    // per item: its external inputs
+  const int32_t* roff;       // per claim position: offset of the row's entries in its region's table
+  const uint16_t* code;      // per stored L entry: in-region position, or 0x8000 | external index
+  int32_t rows_max, entries_max, ext_max, batches_max;  // LDS sizing (largest region)
+};
+size_t region_kernel_lds(const RegionArgs& r, int dtype);
+int occupancy_region(const RegionArgs& r, int dtype);
 
 // Level-set (unfused) SpTRSV: items grouped by level, one grid barrier each.
 struct LevelArgs {
@@ -157,8 +172,27 @@ struct ResArgs {
   unsigned long long* maxabs;  // 2 * nrhs: max |r| and max |b| bit patterns
 };
 
+// Fused mixed-precision refinement (k_rfused.hip): FP32 substitution, nc
+// corrections (FP64 residual, FP32 substitution), final residual norm and
+// y = A64 x in one launch over the SpTRSV -> SpMV schedule.
+struct RfArgs {
+  TsArgs ts;            // schedule, patterns, ts.Lv = L64 values, ts.Av = A64 values, Y;
+                        // one RHS: ts.X = x (FP64 output and the SpMV rows' readiness flags),
+                        // level items; several: ts.xi = interleaved x, units (ts.unit_rng)
+  const float* L32;     // L's values rounded to FP32
+  const double* B;      // right-hand sides (one: the vector; several: interleaved blocks)
+  unsigned long long* tup;  // stage tuples, rf_tuple_floats(nc) floats per (row, column) in 64-bit
+                            // halves (k_rfused.hip), pending-filled
+  unsigned long long* maxabs;  // 2 * nrhs: max |b - L64 x| and max |b| bit patterns (zeroed)
+  int32_t nrhs;
+};
+int rf_tuple_floats(int nc);
+int occupancy_rfused(int nc, int kb);
+hipError_t launch_rfused(const RfArgs& a, int nc, int kb, int grid, hipStream_t st);
+
 // Launchers (return the HIP error of the launch).
 hipError_t launch_ts_fused(const TsArgs& a, int dtype, int grid, hipStream_t st);
+hipError_t launch_ts_region(const TsArgs& a, const RegionArgs& r, int dtype, int grid, hipStream_t st);
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
 hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st);
 int occupancy_pair(int dtype, int mode);

@@ -43,6 +43,16 @@ constexpr int kStatusTimeout = 1;
 // after the items, two words per iteration id (stamp taken just before the
 // value was published, publication count).
 constexpr int kTraceItemWords = 8;
+// LDS of a region wavefront (k_region.hip): its x values, per row the
+// right-hand side, the diagonal and the entry offset, per entry the value
+// and its 16-bit code, per external input the value and the column; at most
+// kRegionLdsMax bytes (else the region plan is not used).
+constexpr size_t kRegionLdsMax = 64 * 1024;
+inline size_t region_lds_bytes(int rows, int entries, int ext, int batches, int vb) {
+  const size_t a = size_t(rows) * size_t(3 * vb + 8) + 4 + size_t(entries) * size_t(vb + 2) +
+                   size_t(ext) * size_t(vb + 4) + size_t(batches + 1) * 8;
+  return (a + 255) / 256 * 256 + 256;
+}
 
 struct DeviceBuffers {
   int device = -1;
@@ -66,6 +76,10 @@ struct DeviceBuffers {
   int32_t *border = nullptr, *bitem_ptr = nullptr;
   int32_t *bcorder = nullptr, *bcitem_ptr = nullptr;
   uint8_t *bclloc = nullptr, *bceloc = nullptr;
+  // region plan
+  int32_t *rorder = nullptr, *ritem_ptr = nullptr, *rtrsv_items = nullptr, *rqrng = nullptr, *rroff = nullptr;
+  int32_t *rbatch = nullptr, *rbatch_ptr = nullptr, *rext = nullptr, *rext_ptr = nullptr;
+  uint16_t* rcode = nullptr;
   // SpIC0 intersection lists
   int32_t *pair_ptr = nullptr, *pair_u = nullptr, *pair_q = nullptr;
   int32_t *prng = nullptr, *piv = nullptr;
@@ -152,6 +166,23 @@ struct sf_schedule_s {
   int32_t chunk_chain = 0, max_local_depth = 0;
   double est_level_us = 0.0, est_chunk_us = 0.0;
 
+  double est_chunk_pipe_us = 0.0;    // the coarsened plan under the pipelined-item model (region_estimate)
+
+  // Region plan (SF_TRSV_SPMV, one right-hand side; coarsen = 3, or chosen
+  // by the model): regions of up to region_rows rows, each run by one
+  // wavefront level by level with its x in LDS, every row waiting only for
+  // its own inputs (inspect.cpp, build_regions; k_region.hip).
+  int32_t region_rows = 512;
+  bool regioned = false;             // the region plan is in effect for the fused executor
+  std::vector<int32_t> rorder, ritem_ptr, rtrsv_items, rqrng, rroff;
+  std::vector<uint8_t> rlloc;
+  std::vector<int32_t> rbatch, rbatch_ptr;   // (first position, first external index) per batch; batches per item
+  std::vector<int32_t> rext, rext_ptr;       // external inputs (columns) per item
+  std::vector<uint16_t> rcode;               // per stored L entry: in-region position, or 0x8000 | external index
+  int32_t region_rows_max = 0, region_entries_max = 0, region_ext_max = 0, region_batches_max = 0;
+  int32_t region_chain = 0;
+  double est_region_us = 0.0;
+
   // Backward (transposed solve) schedule.
   bool has_back = false;
   sf::Pattern LT, AT;                // CSR of L^T and A^T
@@ -193,6 +224,8 @@ struct sf_schedule_s {
   int32_t no_fusion = 0;
   int32_t timing = 0;
   int32_t autotune_cache = 1;           // sf_autotune reuses results for an equal pattern
+  int32_t refine_path = 0;              // sf_refine_trsv_spmv: 0 fused (one launch), 1 staged passes
+  int32_t cached_reads = 0;             // fused executor: x read through the caches first (TsArgs::cached)
   int32_t tuned_from_cache = 0;         // the last sf_autotune call did
   uint64_t fingerprint = 0;             // of the patterns (computed on first use; 0: not yet)
   unsigned long long* trace = nullptr;  // device trace buffer (trace mode, layout at kTraceItemWords)

@@ -129,7 +129,12 @@ __device__ __forceinline__ void wait_ptrs(const T* (&p)[R], T (&v)[R], int lane,
 
 // VEC: 0 = vec final and read through the caches, 1 = vec final but written
 // in this launch by another kernel phase (device-coherent read), 2 = vec
-// produced concurrently (device-coherent read + readiness protocol).
+// produced concurrently (device-coherent read + readiness protocol), 3 = vec
+// produced concurrently, first read through the caches and re-read
+// device-coherently while pending.  A cached read returns either the value
+// or the pending pattern (a value changes once per launch, from pending to
+// final, and every launch starts with the caches invalidated), so 3 is as
+// exact as 2 and lets neighbouring gathers share cache lines.
 // MAPPED: the value of entry p is val[map[p]] (a transposed view).
 // trace: optional per-item timestamp slots (see the trace mode of k_ts.hip).
 // Returns the row slot's accumulator (meaningful on lanes < nr).
@@ -170,9 +175,10 @@ __device__ __forceinline__ T stream_accumulate(int nr, int r0, int len, T acc, c
       }
     }
 #pragma unroll
-    for (int e = 0; e < kRounds; ++e) xv[e] = j[e] >= 0 ? (VEC == 0 ? vec[j[e]] : ld_co(vec + j[e])) : T(0);
+    for (int e = 0; e < kRounds; ++e)
+      xv[e] = j[e] >= 0 ? ((VEC == 0 || VEC == 3) ? vec[j[e]] : ld_co(vec + j[e])) : T(0);
     if (trace && lane == 0) trace[1] = __builtin_amdgcn_s_memrealtime();  // loads issued
-    if constexpr (VEC == 2) wait_ready<T, kRounds>(vec, j, xv, lane, ls);
+    if constexpr (VEC >= 2) wait_ready<T, kRounds>(vec, j, xv, lane, ls);
 #pragma unroll
     for (int e = 0; e < kRounds; ++e) {
       const int k = base + lane + 64 * e;

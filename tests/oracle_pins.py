@@ -684,4 +684,96 @@ def pin_trsv_unit_lower(orc):
     assert np.array_equal(orc.trsv_unit_lower(a.rowptr, a.col, a.val, b), y)
 
 
+# ------------------------------------------------------------ refinement ----
+def _refine(orc, L, A, b, ncorr, l32=None):
+    return orc.refine(L.rowptr, L.col, L.val, A.rowptr, A.col, A.val, b, ncorr, l32=l32)
+
+
+def pin_refine_diagonal_is_one_fp32_division(orc):
+    """Diagonal L: the FP32 substitution reduces to fl32(fl32(b_i) / L32_ii)
+    (numpy's float32 division, correctly rounded); the FP64 residual of that
+    is then corrected, and y = A x is the plain FP64 product."""
+    rng = np.random.default_rng(31)
+    n = 400
+    d = rng.uniform(0.5, 3.0, n)
+    L = _csr(np.diag(d))
+    A = L
+    b = rng.uniform(-1, 1, n)
+    x, y, rel, st = _refine(orc, L, A, b, 0)
+    want = b.astype(np.float32) / d.astype(np.float32)
+    assert np.array_equal(st[:, 0], want) and np.array_equal(x, want.astype(np.float64)), "x0 of diagonal L"
+    x1, y1, rel1, st1 = _refine(orc, L, A, b, 1)
+    r = b - d * want.astype(np.float64)  # exact in FP64: one product, one difference per row
+    d1 = r.astype(np.float32) / d.astype(np.float32)
+    assert np.array_equal(st1[:, 1], d1), "first correction of diagonal L"
+    assert np.array_equal(x1, want.astype(np.float64) + d1.astype(np.float64)), "x1 of diagonal L"
+    assert np.array_equal(y1, d * x1), "y = A x, diagonal A"
+
+
+def pin_refine_integer_system_is_exact(orc):
+    """Integer L (diagonals from {1,2,4}, entries exactly representable in
+    FP32) and integer x_true with b = L x_true: every FP32 partial sum is a
+    small integer and every division exact, so x0 = x_true, each residual is
+    0, every correction is 0, and x = x_true bit for bit; y = A x_true."""
+    for seed, n, dens in ((0, 80, 0.1), (1, 700, 0.015)):
+        L = synth.random_lower(n, dens, seed=seed, int_values=True)
+        xt = synth.int_vector(n, seed=seed + 10)
+        b = L.to_scipy() @ xt
+        A = synth.from_scipy(L.to_scipy() + L.to_scipy().T)
+        for nc in (0, 2):
+            x, y, rel, st = _refine(orc, L, A, b, nc)
+            assert np.array_equal(x, xt), "integer refinement n=%d ncorr=%d" % (n, nc)
+            assert np.array_equal(y, A.to_scipy() @ xt), "integer y n=%d" % n
+            assert rel == 0.0 and (st[:, 1:] == 0).all(), "zero residual and corrections"
+
+
+def pin_refine_converges_to_fp64_solution(orc):
+    """The refinement's fixed point is the FP64 solution: on SPD-derived L
+    (random SPD, 2D 9-point, 3D 7-point) the FP32-only x0 is ~1e-7 away from
+    LAPACK's FP64 triangular solve, each correction cuts the error by about
+    that factor, and two corrections are within 1e-13; the reported relative
+    residual equals max|b - L x| / max|b| recomputed with scipy (its own
+    summation) to within rounding; y is within 1e-14 of scipy's A @ x."""
+    from scipy.linalg import solve_triangular
+    cases = (synth.random_spd(3000, seed=2), synth.laplacian_2d9(40, 40, 8.0), synth.laplacian_3d7(12, 12, 12, 6.0))
+    for A in cases:
+        L = synth.lower(A)
+        n = L.nrows
+        b = synth.vec_uniform(n, seed=1)
+        Ls = L.to_scipy()
+        xr = solve_triangular(Ls.toarray(), b, lower=True) if n <= 3000 else None
+        errs = []
+        for nc in (0, 1, 2):
+            x, y, rel, st = _refine(orc, L, A, b, nc)
+            errs.append(np.abs(x - xr).max() / np.abs(xr).max())
+            res = np.abs(b - Ls @ x).max() / np.abs(b).max()
+            assert abs(rel - res) <= 1e-15 * max(1.0, np.abs(xr).max()), (nc, rel, res)
+            yy = A.to_scipy() @ x
+            assert np.abs(y - yy).max() <= 1e-14 * np.abs(yy).max(), "y = A x"
+        assert 1e-9 < errs[0] < 1e-5, errs
+        assert errs[1] < errs[0] * 1e-4 and errs[2] <= 1e-13, errs
+
+
+def pin_refine_fp32_substitution_backward_error(orc):
+    """The FP32 stage is a substitution with FP32 arithmetic: its result
+    satisfies the componentwise backward-error bound of forward
+    substitution (any summation order), |c - L32 v| <= gamma_{m+1} |L32||v|
+    with u = 2^-24, m the longest row (Higham, Ch. 8), evaluated in FP64."""
+    A = synth.random_spd(2000, seed=9)
+    L = synth.lower(A)
+    b = synth.vec_uniform(L.nrows, seed=4)
+    x, y, rel, st = _refine(orc, L, A, b, 0)
+    v = st[:, 0].astype(np.float64)
+    L32 = sp.csr_matrix((L.val.astype(np.float32).astype(np.float64), L.col, L.rowptr), shape=(L.nrows, L.nrows))
+    c = b.astype(np.float32).astype(np.float64)
+    m = int(np.diff(L.rowptr).max())
+    u = 2.0 ** -24
+    gam = (m + 1) * u / (1 - (m + 1) * u)
+    lhs = np.abs(c - L32 @ v)
+    rhs = gam * (abs(L32) @ np.abs(v)) + u * np.abs(c)
+    assert (lhs <= rhs).all(), float((lhs - rhs).max())
+    # and it is not an FP64 solve: x0 differs from the FP64 solution
+    assert not np.array_equal(x, np.linalg.solve(L.to_scipy().toarray(), b))
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -127,3 +127,67 @@ def test_fp32_kb64_refinement_small(orc):
         x, y, rel = run_refine(s, L, A, b, nc)
         assert relerr(x, xr) <= TOL_REFINED and relerr(y, yr) <= TOL_REFINED, nc
         assert rel.max() <= 1e-12, nc
+
+
+# ---- the fused refinement (one launch: FP32 substitution, corrections,
+# final residual and y = A x) against the refinement oracle, bit for bit
+
+def oracle_refine_cols(orc, L, A, b, nc):
+    bb = b if b.ndim == 2 else b[:, None]
+    outs = [orc.refine(L.rowptr, L.col, L.val, A.rowptr, A.col, A.val, bb[:, c], nc) for c in range(bb.shape[1])]
+    xs = np.stack([o[0] for o in outs], 1)
+    ys = np.stack([o[1] for o in outs], 1)
+    rel = np.array([o[2] for o in outs])
+    if b.ndim == 1:
+        return xs[:, 0], ys[:, 0], rel
+    return xs, ys, rel
+
+
+@pytest.mark.parametrize("mat,k,nc", [("spd", 1, 0), ("spd", 1, 1), ("spd", 1, 2), ("spd", 1, 3),
+                                      ("9pt", 1, 2), ("spd", 5, 2), ("spd", 8, 1), ("9pt", 32, 2),
+                                      ("spd", 64, 3), ("ragged", 3, 2), ("ragged", 1, 1)])
+def test_fused_refinement_bit_identical_to_oracle(orc, mat, k, nc):
+    if mat == "spd":
+        A = synth.random_spd(20_000, seed=3)
+    elif mat == "9pt":
+        A = synth.laplacian_2d9(96, 80, 8.0)
+    else:  # rows of very different lengths, empty SpMV rows, rectangular A
+        import scipy.sparse as sp
+        rng = np.random.default_rng(9)
+        n = 3000
+        Ld = sp.random(n, n, density=0.004, random_state=rng, format="csr")
+        Ld.data[:] = rng.uniform(-1, 0, Ld.nnz)
+        Ld = sp.tril(Ld, -1).tocsr()
+        Ld[np.arange(0, n, 97), :60] = -0.01  # a few long rows
+        Ld = sp.tril(Ld, -1).tocsr()
+        Ld = Ld + sp.diags(1.0 + abs(Ld).sum(1).A1)
+        Ad = sp.random(n + 7, n, density=0.003, random_state=rng, format="csr")
+        Ad[::11] = 0
+        Ad.eliminate_zeros()
+        L, A0 = synth.from_scipy(Ld.tocsr()), synth.from_scipy(Ad.tocsr())
+        A = None
+    if A is not None:
+        L = synth.lower(A)
+        A0 = A
+    b = synth.vec_uniform(L.nrows, k=k, seed=1)
+    s = sfm.Schedule(L, A0)
+    announce("fused refine %s k=%d nc=%d" % (mat, k, nc))
+    x, y, rel = run_refine(s, L, A0, b, nc)
+    xr, yr, relr = oracle_refine_cols(orc, L, A0, b, nc)
+    assert np.array_equal(x, xr), (mat, k, nc, relerr(x, xr))
+    assert np.array_equal(y, yr), (mat, k, nc, relerr(y, yr))
+    assert np.array_equal(rel, relr), (rel, relr)
+
+
+def test_staged_refinement_path_still_reaches_1e10(orc):
+    """The staged refinement (one launch per pass) stays available as the
+    comparison path (refine_path = 1)."""
+    A = synth.random_spd(30_000, seed=0)
+    L = synth.lower(A)
+    b = synth.vec_uniform(L.nrows, k=8, seed=1)
+    s = sfm.Schedule(L, A)
+    s.set_param("refine_path", 1)
+    xr, yr = oracle_cols(orc, L, A, b)
+    announce("staged refine spd k=8")
+    x, y, rel = run_refine(s, L, A, b, 2)
+    assert relerr(x, xr) <= TOL_REFINED and relerr(y, yr) <= TOL_REFINED and rel.max() <= 1e-12

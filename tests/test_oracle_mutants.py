@@ -57,6 +57,13 @@ MUTANTS = {
                                   "if (!(item[j] <= item[i])) { rc = 4; break; }"),
     "factor_solve_no_solve_edge": ("if (!(item[n + j] < item[n + i])) { rc = 5; break; }", ""),
     "factor_solve_no_f_edge": ("(item[i] == item[n + i] && pos[i] < pos[n + i])", "(item[i] == item[n + i])"),
+    "refine_residual_sign": ("        r[i] = b[i] - acc;", "        r[i] = b[i] + acc;"),
+    "refine_no_update": ("      x[i] = (t == 0 ? 0.0 : x[i]) + (double)v[i];", "      x[i] = (t == 0 ? (double)v[i] : x[i]);"),
+    "refine_residual_fp32_values": ("for (int p = rp[i]; p < rp[i + 1]; ++p) acc += l64[p] * x[ci[p]];\n        r[i]",
+                                    "for (int p = rp[i]; p < rp[i + 1]; ++p) acc += (double)l32[p] * x[ci[p]];\n        r[i]"),
+    "refine_sum_sign": ("          sum = sum + prod;", "          sum = sum - prod;"),
+    "refine_no_divide": ("      v[i] = top / dg;", "      v[i] = top;"),
+    "refine_relres_wrong_norm": ("    if (fabs(b[i]) > bmax) bmax = fabs(b[i]);", "    bmax += fabs(b[i]);"),
     "unit_lower_divides": ("      if (ci[p] < i) s -= v[p] * y[ci[p]];\n    y[i] = s;",
                            "      if (ci[p] < i) s -= v[p] * y[ci[p]];\n    y[i] = s / 7.0;"),
 }
