@@ -417,6 +417,26 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
 size_t sf_backward_workspace_bytes(sf_schedule s, sf_dtype dtype, int32_t nrhs);
 
 /*
+ * sf_backward_noalloc — sf_backward for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc.  Same arguments and results as
+ * sf_backward without the workspace: when X is NULL the recomputed x is kept
+ * in a fixed device scratch of the library (64 MiB per GPU, held from the
+ * library's load until the process ends), so n * sizeof(value) must be at
+ * most 64 MiB (8M FP64 or 16M FP32 rows), else SF_ERR_UNSUPPORTED, checked
+ * before anything else.  The call allocates nothing: the schedule's device
+ * arrays must already be resident on the current device, made by an earlier
+ * executor call with this schedule (typically the forward pass); otherwise
+ * SF_ERR_ARG.  The timing mode is ignored.  Every call on one GPU shares that
+ * GPU's scratch: calls that overlap on one GPU (different streams, or
+ * different threads without ordering) race and must be serialised by the
+ * caller.  Enqueues only; stream-ordered like sf_backward.
+ */
+sf_status sf_backward_noalloc(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val,
+                              const void* X, const void* B, const void* G, void* grad_B,
+                              void* grad_L_val, void* stream);
+
+/*
  * sf_refine_trsv_spmv — FP32 solves with FP64 residual refinement (not in
  * the paper; its stages compose the way the paper's kernels do: each stage
  * reads, per row, only rows the previous stages have already produced).

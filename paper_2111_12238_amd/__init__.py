@@ -103,6 +103,7 @@ _SIGS = {
     "sf_exec_ic0_trsv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _P],
     "sf_exec_unfused_ic0_trsv": [_P, _I, _P, _P, _P, _I, _I, _P, _I, _P, _P],
     "sf_backward": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
+    "sf_backward_noalloc": [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P],
     "sf_refine_trsv_spmv": [_P, _P, _P, _P, _P, _I, _I, _P, _I, _P, _I, _I, _P, _P, ctypes.c_size_t, _P],
     "sf_set_param": [_P, ctypes.c_char_p, ctypes.c_int64],
     "sf_get_param": [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],

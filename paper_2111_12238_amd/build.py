@@ -31,7 +31,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wno-unused-command-line-argument"]
 
 UNITS = ["inspect.cpp", "static_plan.cpp", "api.cpp", "k_ts.hip", "k_ic0.hip", "k_ilu.hip", "k_bwd.hip", "k_refine.hip",
-         "k_layout.hip", "k_probe.hip", "k_rfused.hip", "k_region.hip"]
+         "k_layout.hip", "k_probe.hip", "scratch.hip", "k_rfused.hip", "k_region.hip"]
 
 
 def _compile(src: str) -> str:

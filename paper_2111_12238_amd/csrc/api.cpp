@@ -1288,6 +1288,29 @@ sf_status sf_backward(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   return enqueued(s, stream, backward_core(s, dtype, L_val, A_val, X, B, G, grad_B, grad_L_val, workspace, st));
 }
 
+sf_status sf_backward_noalloc(sf_schedule s, sf_dtype dtype, const void* L_val, const void* A_val, const void* X,
+                              const void* B, const void* G, void* grad_B, void* grad_L_val, void* stream) {
+  sf_status r = check_backward_args(s, dtype, L_val, A_val, X, B, G, grad_B, grad_L_val);
+  if (r != SF_OK) return r;
+  // the recomputed x must fit the fixed scratch
+  if (!X && size_t(s->n) * (dtype == SF_F64 ? 8 : 4) > scratch_bytes()) return SF_ERR_UNSUPPORTED;
+  if (s->n == 0) return SF_OK;
+  // no allocation here: the schedule's device arrays (and its event) must
+  // already be resident on the current device, made by an earlier executor
+  // call with this schedule (e.g. the forward pass)
+  int cur = -1;
+  SF_HIP(hipGetDevice(&cur));
+  if (!s->dev.ready || s->dev.device != cur || !s->dev.done) return SF_ERR_ARG;
+  void* x = nullptr;
+  if (!X) SF_HIP(scratch_device_ptr(&x));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int saved_timing = s->timing;  // timing events would be created per call
+  s->timing = 0;
+  r = backward_core(s, dtype, L_val, A_val, X, B, G, grad_B, grad_L_val, x, st);
+  s->timing = saved_timing;
+  return enqueued(s, stream, r);
+}
+
 // Refinement workspace, in the interleaved block layout of the solve (a
 // plain vector per array for a single right-hand side):
 //   r32 | d32 | x ping | x pong | b64 | y64 | max-abs accumulators

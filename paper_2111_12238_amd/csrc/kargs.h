@@ -229,6 +229,12 @@ hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st)
 hipError_t launch_fill_pending_cols(void* p, int32_t rows, int32_t ld, int32_t ncols, int dtype, hipStream_t st);
 
 
+// Fixed device scratch of the allocation-free entry point (scratch.hip):
+// its size, and its address on the current device (looked up once per
+// device; no allocation).
+size_t scratch_bytes();
+hipError_t scratch_device_ptr(void** out);
+
 // Occupancy queries per kernel family (blocks per CU).
 int occupancy_ts_fused(int dtype);
 int occupancy_ts_multi(int dtype, int kb);

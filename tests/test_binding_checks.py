@@ -128,3 +128,21 @@ def test_autotune_fingerprint_tells_patterns_apart():
     A3 = synth.laplacian_2d9(20, 20, 8.0)
     f3 = sfm.Schedule(synth.lower(A3), A3).get_param("fingerprint")
     assert f1 == f2 and f1 != f3
+
+
+def test_noalloc_backward_size_limit_is_host_side():
+    """The allocation-free adjoint keeps a recomputed x in a fixed 64 MiB
+    device scratch: a system of more than 2^23 rows (FP64) is refused with
+    SF_ERR_UNSUPPORTED from the schedule alone, before any pointer or device
+    is looked at; FP32 fits twice as many rows."""
+    P, I = ctypes.c_void_p, ctypes.c_int32
+    lib = sfm._lib()
+    f = lib.sf_backward_noalloc
+    f.argtypes = [P, I, P, P, P, P, P, P, P, P]
+    f.restype = ctypes.c_int
+    n = (1 << 23) + 1
+    rp = np.arange(n + 1, dtype=np.int32)
+    s = sfm.Schedule((rp, rp[:-1].copy(), n), (rp, rp[:-1].copy(), n), want_backward=True)
+    fake = ctypes.c_void_p(0x1000)
+    assert f(s.handle, 0, fake, fake, None, fake, fake, fake, fake, None) == 10  # SF_ERR_UNSUPPORTED
+    s.free()
