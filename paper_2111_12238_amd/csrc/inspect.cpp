@@ -431,11 +431,11 @@ static void build_chunks(sf_schedule_s* s) {
 // column's position inside the region, or 0x8000 | the external input's
 // index.  Per position the offset of its row's entries inside the region's
 // entry table.  SpMV rows follow as in the coarsened plan.
-static void build_regions(sf_schedule_s* s) {
+static void build_regions(sf_schedule_s* s, int32_t rows) {
   const Pattern& L = s->L;
   const int32_t n = L.nrows;
   const int64_t m = s->m;
-  const int32_t R = std::max(64, std::min(s->region_rows, 16384));
+  const int32_t R = std::max(64, std::min(rows, 16384));
   const ChunkPlan c = chunk_dag(n, L.rp, L.ci, 0, 1, s->level, R, int64_t(1) << 62);
   const int32_t nc = int32_t(c.ptr.size()) - 1;
   // SpMV rows after the region holding their last input, by default after every region
@@ -639,10 +639,16 @@ void cut_items(sf_schedule_s* s) {
     s->regioned = false;
     s->est_region_us = 0.0;
     if (n > 0 && s->coarsen == 3) {
-      build_regions(s);
+      // regions of region_rows rows, halved while the largest one's LDS
+      // does not fit a wavefront's share
+      size_t lds = 0;
+      for (int32_t R = s->region_rows;; R /= 2) {
+        build_regions(s, R);
+        lds = region_lds_bytes(s->region_rows_max, s->region_entries_max, s->region_ext_max,
+                               s->region_batches_max, 8);
+        if (lds <= kRegionLdsMax || R <= 64) break;
+      }
       position_ranges(s, s->rorder, s->rqrng);
-      const size_t lds = region_lds_bytes(s->region_rows_max, s->region_entries_max, s->region_ext_max,
-                                          s->region_batches_max, 8);
       s->regioned = lds <= kRegionLdsMax && (s->coarsen == 3 || s->est_region_us < 0.85 * s->est_chunk_pipe_us);
     }
   } else {
@@ -985,10 +991,72 @@ static int validate_ilu_plan(const sf_schedule_s* s) {
   return 0;
 }
 
+// The region plan: every iteration once, edges between regions go forward,
+// edges inside a region to a later local wavefront through its in-region
+// code; each batch is level-pure, at most 64 rows, and the batches tile the
+// region; every external code names the column in the region's list, and a
+// batch uses no external input first used by a later batch.
+static int validate_region_plan(const sf_schedule_s* s) {
+  const int64_t n = s->n, m = s->m;
+  int r = validate_plan(s, s->rorder, s->ritem_ptr, nullptr);
+  if (r == 4) {  // in-region edges are checked below
+    r = 0;
+  }
+  if (r != 0) return r;
+  const int64_t N = n + m;
+  const int64_t nitems = int64_t(s->ritem_ptr.size()) - 1;
+  std::vector<int32_t> item(size_t(N), -1), pos(size_t(N), -1), batch_of(s->rorder.size(), -1);
+  for (int64_t t = 0; t < nitems; ++t)
+    for (int32_t q = s->ritem_ptr[t]; q < s->ritem_ptr[t + 1]; ++q) {
+      item[s->rorder[q]] = int32_t(t);
+      pos[s->rorder[q]] = q;
+    }
+  if (int64_t(s->rbatch_ptr.size()) != nitems + 1 || int64_t(s->rext_ptr.size()) != nitems + 1) return 10;
+  for (int64_t t = 0; t < nitems; ++t) {
+    const int32_t q0 = s->ritem_ptr[t], q1 = s->ritem_ptr[t + 1];
+    const int32_t b0 = s->rbatch_ptr[t], b1 = s->rbatch_ptr[t + 1];
+    if (b1 == b0) continue;  // SpMV item
+    if (q1 - q0 > 32767 || s->rext_ptr[t + 1] - s->rext_ptr[t] > 32767) return 11;
+    if (s->rbatch[2 * b0] != q0) return 12;
+    for (int32_t b = b0; b < b1; ++b) {
+      const int32_t pb = s->rbatch[2 * b], pe = b + 1 < b1 ? s->rbatch[2 * (b + 1)] : q1;
+      if (pe <= pb || pe - pb > 64) return 13;
+      for (int32_t q = pb; q < pe; ++q) {
+        if (s->rorder[q] >= n || s->rlloc[q] != s->rlloc[pb]) return 14;
+        batch_of[q] = b - b0;
+      }
+      if (b + 1 < b1 && (s->rlloc[pe] < s->rlloc[pb] || s->rbatch[2 * (b + 1) + 1] < s->rbatch[2 * b + 1])) return 15;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t t = item[i];
+    const int32_t b0 = s->rbatch_ptr[t];
+    for (int32_t p = s->L.rp[i]; p < s->L.rp[i + 1] - 1; ++p) {
+      const int32_t j = s->L.ci[p];
+      const int code = s->rcode[size_t(p)];
+      if (item[j] == t) {
+        if (code & 0x8000 || code != pos[j] - s->ritem_ptr[t] || !(s->rlloc[pos[j]] < s->rlloc[pos[i]])) return 16;
+      } else {
+        const int xi = code & 0x7fff;
+        if (!(code & 0x8000) || !(item[j] < t) || xi >= s->rext_ptr[t + 1] - s->rext_ptr[t]) return 17;
+        if (s->rext[size_t(s->rext_ptr[t] + xi)] != j) return 18;
+        if (xi >= (batch_of[pos[i]] + 1 < s->rbatch_ptr[t + 1] - b0 ? s->rbatch[2 * (b0 + batch_of[pos[i]] + 1) + 1]
+                                                                     : s->rext_ptr[t + 1] - s->rext_ptr[t]))
+          return 19;  // used before its first-use batch
+      }
+    }
+  }
+  for (int64_t r2 = 0; r2 < m; ++r2)
+    for (int32_t p = s->A.rp[r2]; p < s->A.rp[r2 + 1]; ++p)
+      if (!(item[s->A.ci[p]] < item[n + r2])) return 5;
+  return 0;
+}
+
 int validate_forward(const sf_schedule_s* s) {
   if (s->kind == SF_ILU0_TRSV) return validate_ilu_plan(s);
   int r = validate_plan(s, s->order, s->item_ptr, nullptr);
   if (r == 0 && s->chunked) r = validate_plan(s, s->corder, s->citem_ptr, &s->clloc);
+  if (r == 0 && s->regioned) r = validate_region_plan(s);
   if (r == 0 && s->has_back) r = validate_back_plan(s, s->border, s->bitem_ptr, nullptr);
   if (r == 0 && s->bchunked) r = validate_back_plan(s, s->bcorder, s->bcitem_ptr, &s->bclloc);
   return r;

@@ -593,3 +593,57 @@ def test_structural_verdicts_match_oracle(orc):
             assert got == want_name[code], (name, rp, ci)
             seen.add(code)
     assert seen == {0, 1, 2, 3}
+
+
+@pytest.mark.parametrize("case,rows", [("lap3d7_20", 512), ("lap3d7_20", 64), ("lap2d9_64", 512), ("lap2d5_64", 256),
+                                       ("lap3d27_10", 256), ("random", 512), ("random_rect", 128),
+                                       ("tridiag", 512)])
+def test_region_plans(orc, case, rows):
+    """The region plan (coarsen = 3): the inspector's own check (validate)
+    passes -- in-region codes, batches of one local wavefront and at most 64
+    rows, external inputs listed before their first use -- and the exported
+    order passes the oracle's validator with edges inside an item allowed,
+    each item's rows sorted by local wavefront and every in-item edge going
+    to a later one."""
+    if case == "lap3d7_20":
+        A = synth.laplacian_3d7(20, 20, 20, 6.0)
+        L = synth.lower(A)
+    elif case == "lap2d9_64":
+        A = synth.laplacian_2d9(64, 64, 8.0)
+        L = synth.lower(A)
+    elif case == "lap2d5_64":
+        A = synth.laplacian_2d5(64, 64, 4.0)
+        L = synth.lower(A)
+    elif case == "lap3d27_10":
+        A = synth.laplacian_3d27(10, 10, 10, 26.1)
+        L = synth.lower(A)
+    elif case == "random":
+        L, A = _random_pair(3000, 5, None, True)
+    elif case == "random_rect":
+        L, A = _random_pair(777, 6, 1300, True)
+    else:
+        A = synth.laplacian_1d(500, 2.0)
+        L = synth.lower(A)
+    s = sfm.Schedule(L, A, coarsen=3)
+    s.set_param("region_rows", rows)
+    s2 = sfm.Schedule(L, A, coarsen=3, validate=True)  # inspector's check at the default size
+    assert s2.get_param("regioned") == 1
+    assert s.get_param("regioned") == 1
+    level, order, ip = s.export()
+    loc, _ = s.export_local()
+    n = L.nrows
+    assert orc.validate_ts(L.rowptr, L.col, A.rowptr, A.col, order, ip, allow_intra=True) == 0
+    item = np.repeat(np.arange(len(ip) - 1), np.diff(ip))
+    pos = np.empty(len(order), np.int64)
+    pos[order] = np.arange(len(order))
+    for t in range(len(ip) - 1):
+        seg = loc[ip[t]:ip[t + 1]]
+        assert np.all(np.diff(seg.astype(int)) >= 0)
+        assert np.all(order[ip[t]:ip[t + 1]] < n) or np.all(order[ip[t]:ip[t + 1]] >= n)
+        if order[ip[t]] < n:
+            assert ip[t + 1] - ip[t] <= rows
+    r = np.repeat(np.arange(n), np.diff(L.rowptr))
+    off = L.col != r
+    u, v = L.col[off], r[off]
+    same = item[pos[u]] == item[pos[v]]
+    assert np.all(loc[pos[u][same]] < loc[pos[v][same]])
