@@ -449,10 +449,11 @@ sf_status sf_backward_noalloc(sf_schedule s, sf_dtype dtype, const void* L_val, 
  *   (ascending column, from 0) and subtracts the sum from its rounded
  *   right-hand side.  Default (sf_set_param "refine_path" 0, n_corrections
  *   <= 3): every stage runs in ONE fused launch over the SpTRSV -> SpMV
- *   schedule -- each row gathers one tuple of all stage values of each row
- *   it reads -- and the results are bit-identical to that staged
- *   definition.  "refine_path" 1 (and n_corrections > 3): one launch per
- *   pass, with the executor's FP32 solves (their own summation order).
+ *   schedule's level items -- each row gathers one tuple of all stage values
+ *   of each row it reads -- and the results are bit-identical to that staged
+ *   definition.  "refine_path" 1, n_corrections > 3, or one right-hand side
+ *   on a coarsened plan: one launch per pass, with the executor's FP32
+ *   solves (their own summation order).
  *   L32/L64: device values of L in FP32 and FP64 (same pattern); A64:
  *   device FP64 values of A.  B, X (n x nrhs, ld), Y (m x nrhs, ldy): FP64.
  *   out_relres: HOST array of nrhs doubles, filled after a stream sync

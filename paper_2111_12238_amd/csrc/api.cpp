@@ -385,6 +385,8 @@ RegionArgs region_args(const sf_schedule_s* s) {
   r.entries_max = std::max(1, s->region_entries_max);
   r.ext_max = std::max(1, s->region_ext_max);
   r.batches_max = std::max(1, s->region_batches_max);
+  r.poll_lanes = std::max(1, std::min(64, s->region_poll & 0xff));
+  r.poll_sleep = (s->region_poll >> 8) & 0xff;
   return r;
 }
 
@@ -436,8 +438,9 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
       a.n_work = Y ? int32_t(s->ritem_ptr.size() - 1) : int32_t(s->rtrsv_items.size());
       if (int64_t(a.n_work) * nrhs > int64_t(INT32_MAX) / 2) return SF_ERR_UNSUPPORTED;
       const RegionArgs ra = region_args(s);
-      const int per_cu = std::min(std::max(1, occupancy_region(ra, dtype)),
-                                  nrhs == 1 ? s->waves_per_cu : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : 8));
+      // blocks of two wavefronts (a computing and a polling one)
+      const int waves = nrhs == 1 ? s->waves_per_cu : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : 8);
+      const int per_cu = std::min(std::max(1, occupancy_region(ra, dtype)), std::max(1, waves / 2));
       const int grid = std::max(std::max(1, device_cus()) * per_cu, kStreams);
       Timer tm(s, st);
       if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));
@@ -1476,7 +1479,11 @@ sf_status sf_refine_trsv_spmv(sf_schedule s, const float* L32, const double* L64
   if (!L32 || !L64 || !B || !X || (Y && !A64)) return SF_ERR_ARG;
   if (!workspace || ws_bytes < sf_refine_workspace_bytes(s, nrhs)) return SF_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (s->refine_path == 0 && n_corrections <= 3) {
+  // fused by default; a single right-hand side on a coarsened plan (deep,
+  // narrow DAGs) runs the staged passes, whose FP32 solves use that plan
+  // while the fused refinement walks level items
+  const bool fused = s->refine_path == 0 && n_corrections <= 3 && !(nrhs == 1 && s->chunked);
+  if (fused) {
     if (int64_t(s->n) * fused_refine_kb(s, nrhs) > int64_t(INT32_MAX)) return SF_ERR_UNSUPPORTED;
     sf_status r = upload(s, st);
     if (r != SF_OK) return r;
@@ -1653,6 +1660,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     s->region_rows = int32_t(v);
     const sf_status rc = recut(s);
     if (rc != SF_OK) return rc;
+  } else if (k == "region_poll") {
+    if ((v & 0xff) < 1 || (v & 0xff) > 64 || v < 0 || v > 0xffff) return SF_ERR_ARG;
+    s->region_poll = int32_t(v);
   } else if (k == "cached_reads") {
     if (v < 0 || v > 3) return SF_ERR_ARG;
     s->cached_reads = int32_t(v);
@@ -1710,6 +1720,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "refine_path") *v = s->refine_path;
   else if (k == "cached_reads") *v = s->cached_reads;
   else if (k == "region_rows") *v = s->region_rows;
+  else if (k == "region_poll") *v = s->region_poll;
   else if (k == "regioned") *v = s->regioned ? 1 : 0;  // read only: the region plan is in effect
   else if (k == "region_chain") *v = s->region_chain;
   else if (k == "tuned_from_cache") *v = s->tuned_from_cache;  // read only: last sf_autotune reused a result

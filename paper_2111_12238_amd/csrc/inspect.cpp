@@ -471,13 +471,13 @@ static void build_regions(sf_schedule_s* s, int32_t rows) {
     s->rbatch_ptr.push_back(int32_t(s->rbatch.size() / 2));
     s->rext_ptr.push_back(int32_t(s->rext.size()));
   };
-  auto spmv_run = [&](int32_t b) {  // SpMV rows of bucket b, items of up to 64 rows and the nonzero budget
+  auto spmv_run = [&](int32_t b) {  // SpMV rows of bucket b, items of up to 128 rows (two wavefronts) and the budget
     int32_t q = bucket[b];
     const int32_t e = bucket[b + 1];
     while (q < e) {
       int64_t cost = 0;
       int32_t k = q;
-      while (k < e && k - q < 64) {
+      while (k < e && k - q < 128) {
         const int32_t r = sorder[k];
         const int64_t cr = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
         if (k > q && cost + cr > s->max_item_nnz) break;

@@ -162,7 +162,8 @@ struct RfLds {
 // with its index, both values and its column's tuple loaded in one round;
 // the terms go to LDS and each row's lane folds its own in ascending order.
 template <int NC>
-__device__ __forceinline__ void rf_rows(const RfArgs& a, int q0, int q1, int lane, RfLds<NC>& w, int id, int2 rg) {
+__device__ __forceinline__ void rf_rows(const RfArgs& a, int q0, int q1, int lane, RfLds<NC>& w, int id, int2 rg,
+                                       unsigned long long* smax) {
   const int nr = q1 - q0;
   const bool mine = lane < nr;
   int len = mine ? rg.y - rg.x : 0;  // off-diagonals; the diagonal sits at rg.y
@@ -227,7 +228,28 @@ __device__ __forceinline__ void rf_rows(const RfArgs& a, int q0, int q1, int lan
     if (mine) {
       const int lo = max(off, base) - base;
       const int hi = min(off + len, base + kPass) - base;
-      for (int t = lo; t < hi; ++t) {
+      // ascending order, one rounding per term; the LDS reads of four
+      // entries are issued before their additions
+      int t = lo;
+      for (; t + 4 <= hi; t += 4) {
+        float f[4][NC + 1];
+        double d[4][NC + 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int s = 0; s <= NC; ++s) {
+            f[u][s] = w.pf[s][t + u];
+            d[u][s] = w.pd[s][t + u];
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int s = 0; s <= NC; ++s) {
+            sg[s] = sg[s] + f[u][s];
+            rh[s] = rh[s] + d[u][s];
+          }
+      }
+      for (; t < hi; ++t) {
 #pragma unroll
         for (int s = 0; s <= NC; ++s) {
           sg[s] = sg[s] + w.pf[s][t];
@@ -259,10 +281,18 @@ __device__ __forceinline__ void rf_rows(const RfArgs& a, int q0, int q1, int lan
     ur = max(ur, (unsigned long long)__shfl_xor((long long)ur, d, 64));
     ub = max(ub, (unsigned long long)__shfl_xor((long long)ub, d, 64));
   }
-  if (lane == 0) {
-    if (ur) __hip_atomic_fetch_max(a.maxabs, ur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ub) __hip_atomic_fetch_max(a.maxabs + 1, ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0) {  // the block's maxima in LDS; one device atomic per block at the end
+    if (ur) atomicMax(smax, ur);
+    if (ub) atomicMax(smax + 1, ub);
   }
+}
+
+// A block's |r| and |b| maxima (2 per column, in LDS) into the device
+// accumulators: one atomic per word and block instead of one per row group.
+__device__ __forceinline__ void flush_maxima(unsigned long long* mx, const unsigned long long* smax, int words) {
+  __syncthreads();
+  for (int k = threadIdx.x; k < words; k += blockDim.x)
+    if (smax[k]) __hip_atomic_fetch_max(mx + k, smax[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int NC>
@@ -276,9 +306,12 @@ union RfWaveLds {
 template <int NC>
 __global__ __launch_bounds__(kBlockThreads) void k_rf_stream(RfArgs a) {
   __shared__ RfWaveLds<NC> lds[kWaves];
+  __shared__ unsigned long long smax[2];
   const int lane = threadIdx.x & 63;
   RfWaveLds<NC>& w = lds[threadIdx.x >> 6];
   const TsArgs& ts = a.ts;
+  if (threadIdx.x < 2) smax[threadIdx.x] = 0ull;
+  __syncthreads();
   dev::reset_next_launch(ts.ls);
   int t = dev::claim(ts.ls, lane);
   while (t < ts.n_work) {
@@ -288,10 +321,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_rf_stream(RfArgs a) {
     const bool mine = lane < q1 - q0;
     const int id = mine ? ts.order[q0 + lane] : 0;
     const int2 rg = mine ? reinterpret_cast<const int2*>(ts.qrng)[q0 + lane] : make_int2(0, 0);
-    if (__shfl(id, 0, 64) < ts.n) rf_rows<NC>(a, q0, q1, lane, w.rf, id, rg);
+    if (__shfl(id, 0, 64) < ts.n) rf_rows<NC>(a, q0, q1, lane, w.rf, id, rg, smax);
     else item_stream_rows<double, false, 2>(ts, q0, q1, lane, w.sp, nullptr, id, rg);
     t = tn;
   }
+  flush_maxima(a.maxabs, smax, 2);
 }
 
 // ------------------------------------------------ several right-hand sides --
@@ -299,8 +333,57 @@ __global__ __launch_bounds__(kBlockThreads) void k_rf_stream(RfArgs a) {
 // block blk): the lane walks its row's entries kUx at a time (indices and
 // both values, then the column tuples of its right-hand side, waited for
 // together) and folds the terms of every stage in ascending order.
+// Entries a row's KB lanes stage per chunk (lane c takes entries c, c + KB,
+// ...): the indices and both values of S::CH entries in one round of loads.
+template <int KB>
+struct RfShape {
+  static constexpr int NE = KB <= 8 ? 8 : 4;
+  static constexpr int CH = KB * NE;
+};
+template <int KB>
+struct RfMultiLds {
+  int32_t col[64 * RfShape<KB>::NE];
+  float v32[64 * RfShape<KB>::NE];
+  double v64[64 * RfShape<KB>::NE];
+};
+
 template <int NC, int KB>
-__device__ __forceinline__ void rf_unit(const RfArgs& a, int q0, int q1, int blk, int lane) {
+__device__ __forceinline__ void rf_fold_entries(const RfArgs& a, const unsigned long long* tb, int c, int cnt,
+                                                const int32_t* col, const float* v32, const double* v64,
+                                                float (&sg)[NC + 1], double (&rh)[NC + 1], int wmax) {
+  for (int r0 = 0; r0 < wmax; r0 += kUx) {
+    int j[kUx];
+    Tup<NC> tp[kUx];
+#pragma unroll
+    for (int u = 0; u < kUx; ++u) {
+      j[u] = r0 + u < cnt ? col[r0 + u] : -1;
+      if (j[u] >= 0) tp[u] = tup_load<NC, KB>(tb, j[u], c);
+    }
+    tup_wait<NC, KB, kUx>(tb, j, c, tp, a.ts.ls);
+#pragma unroll
+    for (int u = 0; u < kUx; ++u) {
+      if (j[u] < 0) break;
+      float pf[NC + 1];
+      double pd[NC + 1];
+      rf_terms<NC>(v32[r0 + u], v64[r0 + u], tp[u], pf, pd);
+#pragma unroll
+      for (int s = 0; s <= NC; ++s) {
+        sg[s] = sg[s] + pf[s];
+        rh[s] = rh[s] + pd[s];
+      }
+    }
+  }
+}
+
+// A unit of SpTRSV rows (64 / KB rows, KB lanes each, lane c = column c of
+// block blk): the row's entries are staged in LDS a chunk at a time (one
+// round of loads), then every lane gathers its column's tuples kUx at a
+// time, waits for the pending ones and folds the terms of every stage in
+// ascending order.
+template <int NC, int KB>
+__device__ __forceinline__ void rf_unit(const RfArgs& a, int q0, int q1, int blk, int lane, RfMultiLds<KB>& w,
+                                       unsigned long long* smax) {
+  using S = RfShape<KB>;
   const TsArgs& ts = a.ts;
   const int g = lane / KB, c = lane % KB;
   const int q = q0 + g;
@@ -321,34 +404,24 @@ __device__ __forceinline__ void rf_unit(const RfArgs& a, int q0, int q1, int blk
     sg[k] = 0.0f;
     rh[k] = 0.0;
   }
-  for (int c0 = 0; c0 < maxlen; c0 += kUx) {
-    int j[kUx];
-    float v32[kUx];
-    double v64[kUx];
-    Tup<NC> tp[kUx];
+  const int slice = g * S::CH;
+  for (int base = 0; base < maxlen; base += S::CH) {
 #pragma unroll
-    for (int u = 0; u < kUx; ++u) {
-      const bool h = c0 + u < len;
-      j[u] = h ? ld_stream(ts.Lci + rg.x + c0 + u) : -1;
-      v32[u] = h ? ld_stream(a.L32 + rg.x + c0 + u) : 0.0f;
-      v64[u] = h ? ld_stream(L64 + rg.x + c0 + u) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kUx; ++u)
-      if (j[u] >= 0) tp[u] = tup_load<NC, KB>(tb, j[u], c);
-    tup_wait<NC, KB, kUx>(tb, j, c, tp, ts.ls);
-#pragma unroll
-    for (int u = 0; u < kUx; ++u) {
-      if (j[u] < 0) break;
-      float pf[NC + 1];
-      double pd[NC + 1];
-      rf_terms<NC>(v32[u], v64[u], tp[u], pf, pd);
-#pragma unroll
-      for (int s = 0; s <= NC; ++s) {
-        sg[s] = sg[s] + pf[s];
-        rh[s] = rh[s] + pd[s];
+    for (int e = 0; e < S::NE; ++e) {
+      const int u = base + c + KB * e;
+      if (u < len) {
+        w.col[slice + c + KB * e] = ld_stream(ts.Lci + rg.x + u);
+        w.v32[slice + c + KB * e] = ld_stream(a.L32 + rg.x + u);
+        w.v64[slice + c + KB * e] = ld_stream(L64 + rg.x + u);
       }
     }
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(S::CH, len - base);
+    int wcnt = cnt;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) wcnt = max(wcnt, __shfl_xor(wcnt, d, 64));
+    rf_fold_entries<NC, KB>(a, tb, c, cnt, w.col + slice, w.v32 + slice, w.v64 + slice, sg, rh, wcnt);
+    __builtin_amdgcn_wave_barrier();
   }
   const size_t at = (row0 + size_t(id)) * KB + c;
   double bi = 0.0, l64d = 1.0;
@@ -365,7 +438,7 @@ __device__ __forceinline__ void rf_unit(const RfArgs& a, int q0, int q1, int blk
     st_co(static_cast<double*>(ts.xi) + at, publishable(X));
   }
   // maxima per column: reduce over the unit's rows of each column (lanes
-  // c, c + KB, ...), one atomic per column
+  // c, c + KB, ...) into the block's LDS maxima
   const int col = blk * KB + c;
   unsigned long long ur = act ? (unsigned long long)__double_as_longlong(fabs(rfin)) : 0ull;
   unsigned long long ub = act ? (unsigned long long)__double_as_longlong(fabs(bi)) : 0ull;
@@ -375,19 +448,28 @@ __device__ __forceinline__ void rf_unit(const RfArgs& a, int q0, int q1, int blk
     ub = max(ub, (unsigned long long)__shfl_xor((long long)ub, d, 64));
   }
   if (g == 0 && col < a.nrhs) {
-    if (ur) __hip_atomic_fetch_max(a.maxabs + 2 * col, ur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (ub) __hip_atomic_fetch_max(a.maxabs + 2 * col + 1, ub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ur) atomicMax(smax + 2 * col, ur);
+    if (ub) atomicMax(smax + 2 * col + 1, ub);
   }
 }
 
 // Work index t = unit * nblk + block, units in joint order (SpTRSV units
 // with their stages, SpMV units over the published interleaved x).
+template <int KB>
+union RfMultiWaveLds {
+  RfMultiLds<KB> rf;
+  MultiLds<double, KB> ml;
+};
+
 template <int NC, int KB>
 __global__ __launch_bounds__(kBlockThreads) void k_rf_multi(RfArgs a) {
-  __shared__ MultiLds<double, KB> lds[kWaves];
+  __shared__ RfMultiWaveLds<KB> lds[kWaves];
+  __shared__ unsigned long long smax[2 * 64];
   const int lane = threadIdx.x & 63;
-  MultiLds<double, KB>& w = lds[threadIdx.x >> 6];
+  RfMultiWaveLds<KB>& w = lds[threadIdx.x >> 6];
   const TsArgs& ts = a.ts;
+  for (int k = threadIdx.x; k < 2 * 64; k += blockDim.x) smax[k] = 0ull;
+  __syncthreads();
   dev::reset_next_launch(ts.ls);
   const int total = ts.n_work * ts.nblk;
   int t = dev::claim(ts.ls, lane);
@@ -396,10 +478,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_rf_multi(RfArgs a) {
     const int2 rg = ts.unit_rng[t / ts.nblk];
     const int blk = t % ts.nblk;
     const int id0 = ts.order[rg.x];
-    if (id0 < ts.n) rf_unit<NC, KB>(a, rg.x, rg.y, blk, lane);
-    else unit_multi<double, KB, true>(ts, rg.x, rg.y, blk, lane, w);
+    if (id0 < ts.n) rf_unit<NC, KB>(a, rg.x, rg.y, blk, lane, w.rf, smax);
+    else unit_multi<double, KB, true>(ts, rg.x, rg.y, blk, lane, w.ml);
     t = tn;
   }
+  flush_maxima(a.maxabs, smax, 2 * a.nrhs);
 }
 
 template <typename K>

@@ -61,6 +61,7 @@ struct RegionArgs {
   const int32_t* roff;       // per claim position: offset of the row's entries in its region's table
   const uint16_t* code;      // per stored L entry: in-region position, or 0x8000 | external index
   int32_t rows_max, entries_max, ext_max, batches_max;  // LDS sizing (largest region)
+  int32_t poll_lanes, poll_sleep;  // poller: lanes watching inputs, back-off (x 128 cycles) after an idle round
 };
 size_t region_kernel_lds(const RegionArgs& r, int dtype);
 int occupancy_region(const RegionArgs& r, int dtype);

@@ -173,6 +173,7 @@ struct sf_schedule_s {
   // wavefront level by level with its x in LDS, every row waiting only for
   // its own inputs (inspect.cpp, build_regions; k_region.hip).
   int32_t region_rows = 512;
+  int32_t region_poll = 64;          // poller lanes (bits 0-7) and back-off rounds (bits 8-15)
   bool regioned = false;             // the region plan is in effect for the fused executor
   std::vector<int32_t> rorder, ritem_ptr, rtrsv_items, rqrng, rroff;
   std::vector<uint8_t> rlloc;

@@ -170,7 +170,7 @@ def test_fused_refinement_bit_identical_to_oracle(orc, mat, k, nc):
         L = synth.lower(A)
         A0 = A
     b = synth.vec_uniform(L.nrows, k=k, seed=1)
-    s = sfm.Schedule(L, A0)
+    s = sfm.Schedule(L, A0, coarsen=1)  # level items: the fused refinement's plan
     announce("fused refine %s k=%d nc=%d" % (mat, k, nc))
     x, y, rel = run_refine(s, L, A0, b, nc)
     xr, yr, relr = oracle_refine_cols(orc, L, A0, b, nc)
