@@ -27,9 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ts_fused_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ts_spmv_fused_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_12238_amd", "csrc", f)
-                  for f in ("k_ts.hip", "stream.h", "dev_common.h", "kargs.h", "schedule.h", "inspect.cpp")]
+                  for f in ("k_ts.hip", "k_region.hip", "ts_items.h", "stream.h", "dev_common.h", "kargs.h",
+                            "schedule.h", "inspect.cpp")]
 
 
 def log(msg):
@@ -44,13 +45,15 @@ def bounds(d, fused_ms, probe):
       random-gather rate (level items only: coarsened items read in-item x
       from LDS, so there it is no floor);
     - critical_path: one hop (hop_us) per dependent step (joint wavefronts
-      of the level plan, items of the coarsened plan's longest chain).
+      of the level plan, items of the coarsened plan's longest chain,
+      regions of the region plan's longest chain).
     `binding` is the largest; `frac_of_binding` = binding / fused time."""
     if not probe:
         return None
     st = d["s"].info()
     gathers = d["L"].nnz - d["L"].nrows + d["A"].nnz
-    hops = st.chunk_chain if st.coarsened else st.joint_depth
+    regioned = d["s"].get_param("regioned") == 1
+    hops = d["s"].get_param("region_chain") if regioned else st.chunk_chain if st.coarsened else st.joint_depth
     b = {"hbm_peak_ms": d["bytes"] / (HBM_PEAK_GBPS * 1e9) * 1e3,
          "copy_ceiling_ms": d["bytes"] / (probe["copy_GBps"] * 1e9) * 1e3 if probe["copy_GBps"] > 0 else None,
          "gather_floor_ms": None if st.coarsened or probe["gathers_per_s"] <= 0
@@ -188,10 +191,14 @@ def main():
         if not args.no_autotune:
             t0 = time.time()
             sfm.autotune(s, d["Lv"], d["Av"], d["B"])
-            keys = ("coarsened", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu")
+            keys = ("coarsen", "coarsened", "regioned", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu",
+                    "cached_reads")
             d["params"] = {k: s.get_param(k) for k in keys}
             log("autotuned %s in %.1fs: %s" % (name, time.time() - t0,
                                                 " ".join("%s=%d" % kv for kv in d["params"].items())))
+        d["kernel"] = "k_ts_region" if s.get_param("regioned") else "k_ts_fused"
+        d["plan"] = ("regions" if s.get_param("regioned") else
+                     "coarsened items" if s.get_param("coarsened") else "level items")
         work.append(d)
 
     def step(unfused=False, events=None):
@@ -280,7 +287,7 @@ def main():
     traffic = load_traffic("bytes_per_launch_" + dk["name"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_ts_fused (%s)" % dk["name"], "algorithmic_bytes_per_launch": dk["bytes"],
+                "kernel": "%s (%s)" % (dk["kernel"], dk["name"]), "algorithmic_bytes_per_launch": dk["bytes"],
                 "avg_launch_ms": round(per_launch[j], 4)}
 
     per_matrix = {}
@@ -295,6 +302,7 @@ def main():
             "unfused_ms": round(per_launch_u[k], 4), "unfused_GBps": round(gbs_u, 1),
             "speedup_vs_unfused": round(per_launch_u[k] / per_launch[k], 3),
             "inspect_s": round(d["inspect_s"], 3),
+            "plan": d["plan"], "kernel": d["kernel"],
             "params": d.get("params"),
             "NER_vs_unfused": round(d["inspect_s"] * 1e3 / (per_launch_u[k] - per_launch[k]), 1)
             if per_launch_u[k] > per_launch[k] else None,

@@ -1085,6 +1085,9 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
     a.n_work = int32_t(s->item_ptr.size() - 1);
     a.solve = solve ? 1 : 0;
     const int grid = persistent_grid(s, occupancy_ic0(s->lanes_trsv, 0));
+    a.trace = s->trace;
+    a.rtrace = a.trace ? a.trace + s->trace_items * kTraceItemWords : nullptr;
+    if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));  // counts start at 0
     // every factor value and x_i is its own readiness flag
     SF_HIP(launch_fill_pending(L_val, size_t(s->L.nnz()), 0, st));
     if (solve) SF_HIP(launch_fill_pending(X, size_t(s->n), 0, st));
@@ -1713,7 +1716,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "spmv_delay") *v = s->spmv_delay;
   else if (k == "coarsen") *v = s->coarsen;
   else if (k == "coarsened") *v = s->chunked ? 1 : 0;
-  else if (k == "pairs") *v = int64_t(s->pair_u.size());  // SpIC0 / SpILU0 intersection pairs (read only)
+  else if (k == "pairs") *v = s->pair_ptr.empty() ? 0 : int64_t(s->pair_ptr.back());  // SpIC0 / SpILU0 intersection pairs (read only)
   else if (k == "back_coarsened") *v = s->bchunked ? 1 : 0;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "autotune_cache") *v = s->autotune_cache;
@@ -1854,7 +1857,7 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   };
   // one right-hand side: level items vs coarsened items first (the entry
   // stream makes lanes per row irrelevant there)
-  if (r == SF_OK && nrhs == 1) r = try_param("coarsen", {1, 2});
+  if (r == SF_OK && nrhs == 1) r = try_param("coarsen", {1, 2, 3});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_path", {1, 2});
   if (r == SF_OK && nrhs > 1) r = try_param("rhs_block", {8, 16, 32, 64});
   if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 1 << 20});

@@ -498,7 +498,7 @@ static void build_regions(sf_schedule_s* s, int32_t rows) {
   for (int32_t k = 0; k < nc; ++k) {
     const int32_t q0 = int32_t(s->rorder.size());
     const int32_t e0 = int32_t(s->rext.size());
-    int32_t entries = 0;
+    int32_t overflow = 0;  // entries past each row's first kRegionAhead
     for (int32_t q = c.ptr[k]; q < c.ptr[k + 1]; ++q) {
       const int32_t u = c.rows[q];
       const int32_t pos = int32_t(s->rorder.size());
@@ -509,7 +509,7 @@ static void build_regions(sf_schedule_s* s, int32_t rows) {
       }
       s->rorder.push_back(u);
       s->rlloc.push_back(c.lloc[u]);
-      s->rroff.push_back(entries);
+      s->rroff.push_back(overflow);
       for (int32_t p = L.rp[u]; p < L.rp[u + 1] - 1; ++p) {
         const int32_t j = L.ci[p];
         if (c.chunk_of[j] == k) {
@@ -523,11 +523,11 @@ static void build_regions(sf_schedule_s* s, int32_t rows) {
           s->rcode[size_t(p)] = uint16_t(0x8000 | ext_of[j]);
         }
       }
-      entries += L.rp[u + 1] - 1 - L.rp[u];
+      overflow += std::max(0, L.rp[u + 1] - 1 - L.rp[u] - kRegionAhead);
     }
     s->rtrsv_items.push_back(int32_t(s->ritem_ptr.size()) - 1);
     s->region_rows_max = std::max(s->region_rows_max, int32_t(s->rorder.size()) - q0);
-    s->region_entries_max = std::max(s->region_entries_max, entries);
+    s->region_entries_max = std::max(s->region_entries_max, overflow);
     s->region_ext_max = std::max(s->region_ext_max, int32_t(s->rext.size()) - e0);
     close_item();
     const size_t nbp = s->rbatch_ptr.size();
@@ -633,12 +633,12 @@ void cut_items(sf_schedule_s* s) {
     if (!s->corder.empty()) position_ranges(s, s->corder, s->cqrng);
     s->chunked = !s->ctrsv_items.empty() &&
                  (s->coarsen == 2 || s->coarsen == 3 || s->est_chunk_us < 0.8 * s->est_level_us);
-    // regions (one right-hand side): on request, or where the coarsened plan
-    // is chosen and the region model beats its own estimate clearly
+    // regions: on request, or by default on a mesh-like DAG where the
+    // region model beats the coarsened plan's pipelined estimate clearly
     s->rorder.clear();
     s->regioned = false;
     s->est_region_us = 0.0;
-    if (n > 0 && s->coarsen == 3) {
+    if (n > 0 && (s->coarsen == 3 || (s->coarsen == 0 && try_chunks && !s->ctrsv_items.empty()))) {
       // regions of region_rows rows, halved while the largest one's LDS
       // does not fit a wavefront's share
       size_t lds = 0;
@@ -743,6 +743,10 @@ static void build_pairs(sf_schedule_s* s) {
     }
     s->pair_ptr[rd + 1] = int32_t(s->pair_u.size());  // the diagonal has no list
   }
+  // a sentinel past the last list: a list's end position is always a valid
+  // index, so the executor's index loads need no bounds branch
+  s->pair_u.push_back(-1);
+  s->pair_q.push_back(0);
 }
 
 // SpILU0 intersection lists, one list per stored entry (i, j) of A: pairs
@@ -774,6 +778,8 @@ static void build_pairs_ilu(sf_schedule_s* s) {
       s->pair_ptr[size_t(p) + 1] = int32_t(s->pair_u.size());
     }
   }
+  s->pair_u.push_back(-1);  // sentinel, as for SpIC0
+  s->pair_q.push_back(0);
 }
 
 sf_status build_schedule(sf_schedule_s* s, const sf_csr_pattern* Lp, const sf_csr_pattern* Ap,
@@ -1018,6 +1024,13 @@ static int validate_region_plan(const sf_schedule_s* s) {
     if (b1 == b0) continue;  // SpMV item
     if (q1 - q0 > 32767 || s->rext_ptr[t + 1] - s->rext_ptr[t] > 32767) return 11;
     if (s->rbatch[2 * b0] != q0) return 12;
+    int32_t ovf = 0;  // overflow offsets: the entries past kRegionAhead of the earlier rows
+    for (int32_t q = q0; q < q1; ++q) {
+      const int32_t i = s->rorder[q];
+      if (i >= n || s->rroff[q] != ovf) return 20;
+      ovf += std::max(0, s->L.rp[i + 1] - 1 - s->L.rp[i] - kRegionAhead);
+    }
+    if (ovf > s->region_entries_max) return 20;
     for (int32_t b = b0; b < b1; ++b) {
       const int32_t pb = s->rbatch[2 * b], pe = b + 1 < b1 ? s->rbatch[2 * (b + 1)] : q1;
       if (pe <= pb || pe - pb > 64) return 13;

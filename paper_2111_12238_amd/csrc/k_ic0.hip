@@ -61,11 +61,22 @@ constexpr int kPairRegs = 8;
 // of G (G - 1) / 2 doubles, at group_lds.
 template <int G>
 constexpr int tri_size() { return G * (G - 1) / 2; }
+// A group's LDS: the triangle, then the row's entries L_iu and products
+// L_iu x_{j_u} by entry (G each), folded into the pivot and the right-hand
+// side after the sweep.
+template <int G>
+constexpr int grp_size() { return tri_size<G>() + 2 * G; }
+constexpr size_t grp_bytes(int g) { return size_t(g * (g - 1) / 2 + 2 * g) * sizeof(double); }
 __device__ __forceinline__ int tri_row(int t) { return t * (t - 1) / 2; }
 
+// Trace mode (fused launch, tr = the item's record): tr[1] once the
+// batch's index loads have returned, tr[2] once its last round of values
+// is final, tr[3] after its stores (the last batch's stamps stay); per row,
+// the stamp taken just before its first store and its publication count.
 template <int G, bool FUSED>
 __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* group_lds,
-                                         int next = -1, int2* next_rg = nullptr) {
+                                         int next = -1, int2* next_rg = nullptr,
+                                         unsigned long long* tr = nullptr) {
   constexpr int RPB = 64 / G;
   const int sub = lane & (G - 1);
   double* lds_row = group_lds + tri_row(sub);
@@ -86,6 +97,10 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     const int pjj = mine ? a.piv[p] : 0;
     const int e0 = pr.x, e1 = pr.y;
     double acc = mine ? a.Aval[p] : 0.0;
+    // pivot and right-hand side of the row, on its first lane (loaded with
+    // the indices: they wait for nothing)
+    double d = (act && sub == 0) ? a.Aval[rd] : 1.0;
+    double s = (act && sub == 0 && a.solve) ? a.B[i] : 0.0;
     // M[t][u] = L_{j_t, k_u} where row j_t meets row i below column j_t, else absent
     for (int u = 0; u < G; ++u)
       if (u < sub) lds_row[u] = kAbsent;
@@ -93,26 +108,40 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     // Rounds of kPairRegs pairs per lane; the pivot L_jj and x_j of the
     // lane's entry ride along in the first round.  Every load of a round is
     // issued before any is waited on.
-    int nround = (e1 - e0 + G * kPairRegs - 1) / (G * kPairRegs);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) nround = max(nround, __shfl_xor(nround, off, 64));
+    // (further rounds while any row of the batch has pairs left: a ballot)
     double djj = 1.0, xj = 0.0;
-    for (int rnd = 0; rnd < (nround > 0 ? nround : 1); ++rnd) {
+    for (int rnd = 0; rnd == 0 || __ballot(e0 + rnd * G * kPairRegs < e1) != 0; ++rnd) {
       constexpr int R = kPairRegs + 2;
       const double* ptr[R];
       double v[R];
-      int tu[kPairRegs];
+      int tu[kPairRegs], tq[kPairRegs];
+      // the round's index loads all go out, unconditionally (a list's end
+      // position is valid: the lists end with a sentinel), before any
+      // address is formed
 #pragma unroll
       for (int k = 0; k < kPairRegs; ++k) {
         const int e = e0 + rnd * G * kPairRegs + sub + G * k;
-        tu[k] = e < e1 ? a.pair_u[e] : -1;
-        ptr[k] = e < e1 ? a.Lval + a.pair_q[e] : nullptr;
+        const int ec = e < e1 ? e : e1;
+        tu[k] = a.pair_u[ec];
+        tq[k] = a.pair_q[ec];
+      }
+#pragma unroll
+      for (int k = 0; k < kPairRegs; ++k) {
+        const int e = e0 + rnd * G * kPairRegs + sub + G * k;
+        if (e >= e1) tu[k] = -1;
+        ptr[k] = e < e1 ? a.Lval + tq[k] : nullptr;
       }
       ptr[kPairRegs] = (rnd == 0 && mine) ? a.Lval + pjj : nullptr;
       ptr[kPairRegs + 1] = (rnd == 0 && mine && a.solve) ? a.X + j : nullptr;
+      if (FUSED && tr && rnd == 0) {
+        // the index loads have returned once their values are in registers
+        __asm__ volatile("" ::"v"(tu[0]), "v"(pjj), "v"(j));
+        if (lane == 0) tr[1] = __builtin_amdgcn_s_memrealtime();
+      }
 #pragma unroll
       for (int e = 0; e < R; ++e) v[e] = ptr[e] ? ld_co(ptr[e]) : 0.0;
       if constexpr (FUSED) dev::wait_ptrs<double, R, 64>(ptr, v, lane, a.ls);
+      if (FUSED && tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
       for (int k = 0; k < kPairRegs; ++k)
         if (tu[k] >= 0) group_lds[tri_row(tu[k] >> 16) + (tu[k] & 0xffff)] = v[k];
@@ -122,31 +151,36 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // longest row of this batch bounds the sweep (wave-uniform)
-    int maxlen = act ? len : 0;
-    for (int off = 32; off >= 1; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
     double l = 0.0;
-    double d = act ? a.Aval[rd] : 1.0;            // pivot, accumulated on the row's first lane
-    double s = (act && a.solve) ? a.B[i] : 0.0;   // right-hand side, same lane
 #pragma unroll
     for (int u = 0; u < G; ++u) {
-      if (u >= maxlen) break;
-      double pr = 0.0;
-      if (sub == u && mine) {  // entry u is final: every k < j_u has been subtracted
-        l = acc / djj;
-        pr = l * xj;
-      }
+      if (__ballot(act && u < len) == 0) break;  // past the batch's longest row
+      if (sub == u && mine) l = acc / djj;  // entry u is final: every k < j_u has been subtracted
       const double lu = __shfl(l, u, G);
-      const double pu = __shfl(pr, u, G);
       if (mine && sub > u) {
         const double m = lds_row[u];
         if (!is_absent(m)) acc = acc - m * lu;
       }
-      if (act && sub == 0 && u < len) {
-        d = d - lu * lu;
-        s = s - pu;
-      }
     }
+    // the pivot and the right-hand side fold the row's entries in order, on
+    // its first lane, off the sweep's chain
+    double* lv = group_lds + tri_size<G>();
+    double* pv = lv + G;
+    if (mine) {
+      lv[sub] = l;
+      pv[sub] = l * xj;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (act && sub == 0) {
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+        if (u < len) {
+          const double lu = lv[u];
+          d = d - lu * lu;
+          s = s - pv[u];
+        }
+    }
+    if (FUSED && a.rtrace) dev::stamp_publish(a.rtrace, act && sub == 0, i);
     if (mine) st_co(a.Lval + p, publishable(l));
     if (act && sub == 0) {
       const double lii = sqrt(d);
@@ -155,6 +189,7 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
       st_co(a.Lval + rd, publishable(lii));
       if (a.solve) st_co(a.X + i, publishable(s / lii));
     }
+    if (FUSED && tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
@@ -171,16 +206,24 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  double* group_lds = lds + size_t(threadIdx.x / G) * tri_size<G>();
+  double* group_lds = lds + size_t(threadIdx.x / G) * grp_size<G>();
   dev::reset_next_launch(a.ls);
   // every item, in claim order (no item list): the next ticket is claimed
   // before an item runs and its range loaded inside it (see ic0_rows)
   int t = dev::claim(a.ls, lane);
   int2 rg = t < a.n_work ? make_int2(a.item_ptr[t], a.item_ptr[t + 1]) : make_int2(0, 0);
   while (t < a.n_work) {
+    unsigned long long* tr = a.trace ? a.trace + size_t(t) * kTraceItemWords : nullptr;
+    if (tr && lane == 0) {
+      const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+      tr[0] = t0;
+      tr[1] = t0;
+      tr[2] = t0;
+      atomicAdd(tr + 4, 1ull);
+    }
     const int tn = dev::claim(a.ls, lane);
     int2 rgn;
-    ic0_rows<G, true>(a, rg.x, rg.y, lane, group_lds, tn < a.n_work ? tn : -1, &rgn);
+    ic0_rows<G, true>(a, rg.x, rg.y, lane, group_lds, tn < a.n_work ? tn : -1, &rgn, tr);
     t = tn;
     rg = rgn;
   }
@@ -191,7 +234,7 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_ic0_levelset(Ic0Args a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63;
-  double* group_lds = lds + size_t(threadIdx.x / G) * tri_size<G>();
+  double* group_lds = lds + size_t(threadIdx.x / G) * grp_size<G>();
   dev::reset_next_launch(a.ls);
   const int wave = int(blockIdx.x) * (kBlockThreads / 64) + int(threadIdx.x >> 6);
   const int nwaves = int(gridDim.x) * (kBlockThreads / 64);
@@ -220,7 +263,7 @@ int occ(K kernel, size_t lds) {
 hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
   if (!a.order || !a.item_ptr || a.item_list || !a.qrng || !a.prng || !a.piv || !a.pair_u || !a.pair_q)
     return hipErrorInvalidValue;
-  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * grp_bytes(g);
 #define SF_IC(G)                                                                    \
   if (g == G) {                                                                     \
     hipLaunchKernelGGL((k_ic0_fused<G>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
@@ -234,7 +277,7 @@ hipError_t launch_ic0_fused(const Ic0Args& a, int g, int grid, hipStream_t st) {
 hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st) {
   if (!a.order || !a.item_ptr || !a.item_list || !a.lvl_item_ptr || !a.qrng || !a.prng || !a.piv)
     return hipErrorInvalidValue;
-  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * grp_bytes(g);
   void* args[] = {const_cast<Ic0Args*>(&a)};
 #define SF_IL(G)                                                                               \
   if (g == G)                                                                                  \
@@ -246,7 +289,7 @@ hipError_t launch_ic0_levelset(const Ic0Args& a, int g, int grid, hipStream_t st
 }
 
 int occupancy_ic0(int g, int levelset) {
-  const size_t lds = size_t(kBlockThreads / g) * size_t(g * (g - 1) / 2) * sizeof(double);
+  const size_t lds = size_t(kBlockThreads / g) * grp_bytes(g);
   switch (g) {
     case 4: return levelset ? occ(k_ic0_levelset<4>, lds) : occ(k_ic0_fused<4>, lds);
     case 8: return levelset ? occ(k_ic0_levelset<8>, lds) : occ(k_ic0_fused<8>, lds);

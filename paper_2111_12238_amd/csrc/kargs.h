@@ -58,7 +58,7 @@ struct RegionArgs {
   const int32_t* batch_ptr;  // per item: its batches (none for SpMV items)
   const int32_t* ext;        // external inputs (columns) of every region
   const int32_t* ext_ptr;    // per item: its external inputs
-  const int32_t* roff;       // per claim position: offset of the row's entries in its region's table
+  const int32_t* roff;       // per claim position: offset of the row's overflow entries in its region
   const uint16_t* code;      // per stored L entry: in-region position, or 0x8000 | external index
   int32_t rows_max, entries_max, ext_max, batches_max;  // LDS sizing (largest region)
   int32_t poll_lanes, poll_sleep;  // poller: lanes watching inputs, back-off (x 128 cycles) after an idle round
@@ -114,6 +114,8 @@ struct Ic0Args {
   int32_t solve;           // 1: also solve L x = b in the same item
   int32_t factor;          // 1: compute the factor (0: solve with a given factor)
   int32_t* d_info;         // written by the last wave (may be nullptr)
+  unsigned long long* trace;   // optional (fused SpIC0): kTraceItemWords words per item
+  unsigned long long* rtrace;  // with trace: per row its publication stamp and count
   LaunchState ls;
 };
 

@@ -43,14 +43,20 @@ constexpr int kStatusTimeout = 1;
 // after the items, two words per iteration id (stamp taken just before the
 // value was published, publication count).
 constexpr int kTraceItemWords = 8;
-// LDS of a region wavefront (k_region.hip): its x values, per row the
-// right-hand side, the diagonal and the entry offset, per entry the value
-// and its 16-bit code, per external input the value and the column; at most
-// kRegionLdsMax bytes (else the region plan is not used).
+// LDS of a region (k_region.hip): per row a head record -- the first
+// kRegionAhead entries' values and input slots, the right-hand side, the
+// diagonal, the iteration id and the row's share of the overflow table --
+// then the x slots (the region's rows, its external inputs and a slot
+// holding 0), the overflow entries (values and slots of entries past the
+// first kRegionAhead), the external columns and the batch table; at most
+// kRegionLdsMax bytes (else the region plan is not used).  `ovf` counts the
+// region's overflow entries.
 constexpr size_t kRegionLdsMax = 64 * 1024;
-inline size_t region_lds_bytes(int rows, int entries, int ext, int batches, int vb) {
-  const size_t a = size_t(rows) * size_t(3 * vb + 8) + 4 + size_t(entries) * size_t(vb + 2) +
-                   size_t(ext) * size_t(vb + 4) + size_t(batches + 1) * 8;
+constexpr int kRegionAhead = 4;
+inline size_t region_head_bytes(int vb) { return vb == 8 ? 64 : 48; }
+inline size_t region_lds_bytes(int rows, int ovf, int ext, int batches, int vb) {
+  const size_t a = size_t(rows) * region_head_bytes(vb) + size_t(rows + ext + 1) * size_t(vb) +
+                   size_t(ovf) * size_t(vb + 2) + size_t(ext) * 4 + size_t(batches + 1) * 4;
   return (a + 255) / 256 * 256 + 256;
 }
 

@@ -107,6 +107,7 @@ def test_params_roundtrip():
         s.set_param("lanes_trsv", 3)
     with pytest.raises(sfm.SparseFusionError):
         s.set_param("no_such_knob", 1)
+    s.set_param("coarsen", 1)  # level items (a region plan does not cut by rows_per_item)
     n_items_32 = s.info().n_items
     s.set_param("rows_per_item", 8)
     assert s.info().n_items > n_items_32

@@ -69,3 +69,54 @@ def test_trace_every_iteration_once_after_its_inputs(orc, case, coarsen):
           % (case, coarsen, n_items, int((~same).sum()), int(cross_slack.min()) if cross_slack.size else -1,
              int(same.sum())))
     s.free()
+
+
+@pytest.mark.parametrize("case,coarsen", [("lap3d7_24", 3), ("lap2d5_64", 3)])
+def test_trace_region_plan(orc, case, coarsen):
+    """The region plan: every region and SpMV item ran once, every row was
+    published once; a row's input from another region was published before
+    that region's poller had observed all its inputs, an input from its own
+    region before the row's own publication."""
+    test_trace_every_iteration_once_after_its_inputs(orc, case, coarsen)
+
+
+@pytest.mark.parametrize("perm", [False, True])
+def test_trace_ic0_every_row_once_after_its_inputs(orc, perm):
+    """Fused SpIC0 -> SpTRSV in trace mode: every item ran once, every row
+    was published once, and for every stored L_ij (j < i) row j -- its
+    factor entries, pivot and x_j -- was published before the wait of
+    row i's item for its values returned; the stamps of an item are in
+    order (start <= indices loaded <= values final <= end)."""
+    import torch
+    a = synth.laplacian_3d27(12, 12, 12, 26.1)
+    if perm:
+        a = synth.permute_sym(a, synth.permutation(a.nrows, seed=3))
+    Lp = synth.lower(a)
+    n = Lp.nrows
+    b = synth.vec_normal(n, seed=1)
+    s = sfm.Schedule(Lp, None, sfm.SF_IC0_TRSV)
+    s.set_param("trace", 1)
+    announce("trace ic0 27pt 12^3 perm=%s" % perm)
+    Lv, X, info = sfm.ic0_trsv(s, dev(Lp.val), dev(b))
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    l, fail = orc.ic0(Lp.rowptr, Lp.col, Lp.val)
+    assert np.array_equal(host(Lv), l)
+    assert np.array_equal(host(X), orc.trsv_lower(Lp.rowptr, Lp.col, l, b))
+    items, rows = s.trace()
+    level, order, item_ptr = s.export()
+    n_items = len(item_ptr) - 1
+    assert (items[:, 4] == 1).all(), np.unique(items[:, 4])
+    assert (rows[:n, 1] == 1).all(), np.unique(rows[:n, 1])
+    start, loaded, ready, end = (items[:, c].astype(np.int64) for c in (0, 1, 2, 3))
+    assert (start > 0).all() and (start <= loaded).all() and (loaded <= ready).all() and (ready <= end).all()
+    pub = rows[:n, 0].astype(np.int64)
+    item_of = np.repeat(np.arange(n_items), np.diff(item_ptr))[np.argsort(order, kind="stable")]
+    ri = np.repeat(np.arange(n), np.diff(Lp.rowptr))
+    off = Lp.col != ri
+    i, j = ri[off], Lp.col[off]
+    assert not (item_of[i] == item_of[j]).any()  # items hold rows of one level
+    slack = ready[item_of[i]] - pub[j]
+    assert (slack >= 0).all(), int(slack.min())
+    print("ic0 perm=%s: %d items, %d edges, min slack %d ticks" % (perm, n_items, int(i.size), int(slack.min())))
+    s.free()

@@ -156,7 +156,10 @@ def test_coarsen_choice():
     st = s.info()
     assert st.coarsened == 1 and st.est_chunk_us < 0.8 * st.est_level_us
     assert st.chunk_chain < st.depth
+    # and the region plan over them where its estimate is lower still
+    assert s.get_param("regioned") == 1
     L, A = _random_pair(5000, 9)
+    assert sfm.Schedule(L, A).get_param("regioned") == 0
     st = sfm.Schedule(L, A).info()
     assert st.coarsened == 0 and (st.chunk_items == 0 or st.est_chunk_us >= 0.8 * st.est_level_us)
     Ar = synth.random_spd(20000, seed=1)  # edges skip many wavefronts: not even estimated
@@ -172,7 +175,7 @@ def test_coarsen_choice():
 
 def test_item_nnz_budget():
     L, A = synth.workload("lap2d5_64")
-    s = sfm.Schedule(L, A, rows_per_item=1000, max_item_nnz=40)
+    s = sfm.Schedule(L, A, rows_per_item=1000, max_item_nnz=40, coarsen=1)
     level, order, ip = s.export()
     n = L.nrows
     # cost c(v) = entries an iteration streams (SpTRSV: off-diagonals; at least 1)
