@@ -471,16 +471,20 @@ static void build_regions(sf_schedule_s* s, int32_t rows) {
     s->rbatch_ptr.push_back(int32_t(s->rbatch.size() / 2));
     s->rext_ptr.push_back(int32_t(s->rext.size()));
   };
-  auto spmv_run = [&](int32_t b) {  // SpMV rows of bucket b, items of up to 128 rows (two wavefronts) and the budget
+  // SpMV items of up to 256 rows (64 per wavefront and pass) and at least
+  // 2048 entries of budget: they run after the regions, where fewer, larger
+  // items measured faster (128^3: 0.38 -> 0.33 ms against 128-row items)
+  const int64_t spmv_budget = std::max<int64_t>(s->max_item_nnz, 2048);
+  auto spmv_run = [&](int32_t b) {  // SpMV rows of bucket b
     int32_t q = bucket[b];
     const int32_t e = bucket[b + 1];
     while (q < e) {
       int64_t cost = 0;
       int32_t k = q;
-      while (k < e && k - q < 128) {
+      while (k < e && k - q < 256) {
         const int32_t r = sorder[k];
         const int64_t cr = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
-        if (k > q && cost + cr > s->max_item_nnz) break;
+        if (k > q && cost + cr > spmv_budget) break;
         cost += cr;
         ++k;
       }

@@ -69,10 +69,41 @@ constexpr int grp_size() { return tri_size<G>() + 2 * G; }
 constexpr size_t grp_bytes(int g) { return size_t(g * (g - 1) / 2 + 2 * g) * sizeof(double); }
 __device__ __forceinline__ int tri_row(int t) { return t * (t - 1) / 2; }
 
+// Lane u of every 16-lane row to the whole row: DPP row_newbcast (a VALU
+// move, no LDS round trip), one 32-bit half at a time.
+template <int U>
+__device__ __forceinline__ double row_bcast16(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), 0x150 + U, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), 0x150 + U, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo));
+}
+
+// The value of lane u of the lane's G-lane group (u < G, a constant after
+// unrolling).
+template <int G>
+__device__ __forceinline__ double group_bcast(double v, int u) {
+  if constexpr (G == 16) {
+    switch (u) {
+#define SF_B(U) \
+  case U:       \
+    return row_bcast16<U>(v);
+      SF_B(0) SF_B(1) SF_B(2) SF_B(3) SF_B(4) SF_B(5) SF_B(6) SF_B(7)
+      SF_B(8) SF_B(9) SF_B(10) SF_B(11) SF_B(12) SF_B(13) SF_B(14) SF_B(15)
+#undef SF_B
+      default:
+        return v;
+    }
+  } else {
+    return __shfl(v, u, G);
+  }
+}
+
 // Trace mode (fused launch, tr = the item's record): tr[1] once the
 // batch's index loads have returned, tr[2] once its last round of values
-// is final, tr[3] after its stores (the last batch's stamps stay); per row,
-// the stamp taken just before its first store and its publication count.
+// is final, tr[5] after the sweep, tr[6] after the pivot fold, tr[3] after
+// its stores (the last batch's stamps stay); per row, the stamp taken just
+// before its first store and its publication count.
 template <int G, bool FUSED>
 __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* group_lds,
                                          int next = -1, int2* next_rg = nullptr,
@@ -151,17 +182,22 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
       }
     }
     __builtin_amdgcn_wave_barrier();
+    // the lane's row of M into registers first (one round of LDS reads;
+    // entries u >= sub are not its own and stay unused -- the last lane's
+    // row ends where the group's entry array starts, so every read is in
+    // the group's LDS)
+    double mrow[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) mrow[u] = lds_row[u];
     double l = 0.0;
 #pragma unroll
     for (int u = 0; u < G; ++u) {
       if (__ballot(act && u < len) == 0) break;  // past the batch's longest row
       if (sub == u && mine) l = acc / djj;  // entry u is final: every k < j_u has been subtracted
-      const double lu = __shfl(l, u, G);
-      if (mine && sub > u) {
-        const double m = lds_row[u];
-        if (!is_absent(m)) acc = acc - m * lu;
-      }
+      const double lu = group_bcast<G>(l, u);
+      if (mine && sub > u && !is_absent(mrow[u])) acc = acc - mrow[u] * lu;
     }
+    if (FUSED && tr && lane == 0) tr[5] = __builtin_amdgcn_s_memrealtime();
     // the pivot and the right-hand side fold the row's entries in order, on
     // its first lane, off the sweep's chain
     double* lv = group_lds + tri_size<G>();
@@ -172,14 +208,22 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     }
     __builtin_amdgcn_wave_barrier();
     if (act && sub == 0) {
+      // every slot read at once (slots past the row's end hold stale values:
+      // they enter as 0, and d - 0 * 0 and s - 0 leave d and s unchanged)
+      double lu[G], pu[G];
 #pragma unroll
-      for (int u = 0; u < G; ++u)
-        if (u < len) {
-          const double lu = lv[u];
-          d = d - lu * lu;
-          s = s - pv[u];
-        }
+      for (int u = 0; u < G; ++u) {
+        lu[u] = lv[u];
+        pu[u] = pv[u];
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const double x = u < len ? lu[u] : 0.0;
+        d = d - x * x;
+        s = s - (u < len ? pu[u] : 0.0);
+      }
     }
+    if (FUSED && tr && lane == 0) tr[6] = __builtin_amdgcn_s_memrealtime();
     if (FUSED && a.rtrace) dev::stamp_publish(a.rtrace, act && sub == 0, i);
     if (mine) st_co(a.Lval + p, publishable(l));
     if (act && sub == 0) {

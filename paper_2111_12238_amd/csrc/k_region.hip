@@ -244,7 +244,7 @@ __device__ void region_rows(const TsArgs& a, const RegionArgs& r, int item, int 
 }
 
 // Claim loop, one block of two wavefronts: regions in topological order,
-// SpMV items (up to 128 rows, 64 per wavefront) after them.  With col_units
+// SpMV items (up to 256 rows, 64 per wavefront and pass) after them.  With col_units
 // > 1, ticket t is column t % col_units of item t / col_units (one chain of
 // the items per right-hand side).
 template <typename T>
@@ -291,9 +291,10 @@ __global__ __launch_bounds__(kRegionThreads) void k_ts_region(TsArgs a, RegionAr
       __syncthreads();
       if (tr && tid == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
     } else {
-      // SpMV rows: the first 64 on wavefront 0, the rest on wavefront 1
-      const int s0 = q0 + 64 * wid, s1 = min(q1, s0 + 64);
-      if (s0 < s1) {
+      // SpMV rows, 64 per wavefront and pass: rows [0, 64) on wavefront 0,
+      // [64, 128) on wavefront 1, [128, 192) on wavefront 0, ...
+      for (int s0 = q0 + 64 * wid; s0 < q1; s0 += 128) {
+        const int s1 = min(q1, s0 + 64);
         const bool mine = lane < s1 - s0;
         const int id = mine ? a.order[s0 + lane] : 0;
         const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[s0 + lane] : make_int2(0, 0);

@@ -645,6 +645,8 @@ def test_region_plans(orc, case, rows):
         assert np.all(order[ip[t]:ip[t + 1]] < n) or np.all(order[ip[t]:ip[t + 1]] >= n)
         if order[ip[t]] < n:
             assert ip[t + 1] - ip[t] <= rows
+        else:
+            assert ip[t + 1] - ip[t] <= 256  # SpMV items: 64 rows per wavefront and pass
     r = np.repeat(np.arange(n), np.diff(L.rowptr))
     off = L.col != r
     u, v = L.col[off], r[off]
