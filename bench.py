@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of extras to run: ic0, ilu0, small, batched, pairs, fwdbwd (default all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the device probes (no bounds)")
@@ -192,7 +194,7 @@ def main():
             t0 = time.time()
             sfm.autotune(s, d["Lv"], d["Av"], d["B"])
             keys = ("coarsen", "coarsened", "regioned", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu",
-                    "cached_reads")
+                    "cached_reads", "spmv_prefix")
             d["params"] = {k: s.get_param(k) for k in keys}
             log("autotuned %s in %.1fs: %s" % (name, time.time() - t0,
                                                 " ".join("%s=%d" % kv for kv in d["params"].items())))
@@ -370,6 +372,10 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
     the headline matrices, and forward + backward (7-point 96^3, FP64 and
     FP32): fused vs unfused."""
     out = {}
+    sel = set(args.extras.split(",")) if args.extras != "all" else None
+
+    def want(key):
+        return sel is None or key in sel
 
     def time_it(fn, reps):
         fn()
@@ -383,7 +389,7 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
         return e0.elapsed_time(e1) / reps
 
     reps = max(3, args.steps // 2)
-    for name in ("lap3d27_64", "lap3d27_64_perm"):
+    for name in ("lap3d27_64", "lap3d27_64_perm") if want("ic0") else ():
         Lp, _ = synth.workload(name)
         s = sfm.Schedule(Lp, None, sfm.SF_IC0_TRSV)
         Av = torch.as_tensor(Lp.val, device=dev)
@@ -405,7 +411,7 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
                                    "inspect_s": round(s.info().inspect_seconds, 3),
                                    "bound": path_bound(s.info().depth, tf, probe)}
         log("ic0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
-    for name in ("convdiff3d7_64", "convdiff3d7_64_perm"):
+    for name in ("convdiff3d7_64", "convdiff3d7_64_perm") if want("ilu0") else ():
         a, _ = synth.workload(name)
         s = sfm.Schedule(a, None, sfm.SF_ILU0_TRSV)
         Av = torch.as_tensor(a.val, device=dev)
@@ -427,8 +433,30 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
                                     "inspect_s": round(s.info().inspect_seconds, 3),
                                     "bound": path_bound(s.info().depth, tf, probe)}
         log("ilu0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
-    # the small cache-resident case (2D 5-point 64^2): latency only, so
-    # microseconds and solves per second rather than a fraction of HBM peak
+    if want("small"):
+        out.update(run_small(sfm, synth, torch, dev, time_it, probe))
+    if want("batched"):
+        out.update(run_batched(args, sfm, synth, torch, dev, time_it))
+    if want("pairs"):
+        out.update(run_pairs(sfm, synth, torch, dev, time_it, reps))
+    if want("fwdbwd"):
+        out.update(run_fwd_bwd(sfm, synth, torch, dev, time_it, reps))
+    return out
+
+
+def plan_hops(s):
+    """Dependent steps of a schedule's plan: regions of the region plan's
+    longest chain, items of the coarsened plan's, else joint wavefronts."""
+    if s.get_param("regioned"):
+        return s.get_param("region_chain")
+    st = s.info()
+    return st.chunk_chain if st.coarsened else st.joint_depth
+
+
+def run_small(sfm, synth, torch, dev, time_it, probe):
+    """The small cache-resident case (2D 5-point 64^2): latency only, so
+    microseconds and solves per second rather than a fraction of HBM peak."""
+    out = {}
     L, A = synth.workload("lap2d5_64")
     s = sfm.Schedule(L, A)
     Lv, Av = torch.as_tensor(L.val, device=dev), torch.as_tensor(A.val, device=dev)
@@ -441,11 +469,15 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
                               "solves_per_s": round(1e3 / tf, 1), "unfused_us": round(tu * 1e3, 2),
                               "speedup_vs_unfused": round(tu / tf, 3),
                               "us_per_level": round(tf * 1e3 / max(s.info().joint_depth, 1), 3),
-                              "bound": path_bound(s.info().chunk_chain if s.info().coarsened else s.info().joint_depth,
-                                                  tf, probe)}
+                              "bound": path_bound(plan_hops(s), tf, probe)}
     log("small 2D 5-point 64^2: fused %.1f us, unfused %.1f us" % (tf * 1e3, tu * 1e3))
-    out.update(run_batched(args, sfm, synth, torch, dev, time_it))
-    # kernel combinations 2 (SpMV -> SpTRSV) and 1 (SpTRSV -> SpTRSV)
+    return out
+
+
+def run_pairs(sfm, synth, torch, dev, time_it, reps):
+    """Kernel combinations 2 (SpMV -> SpTRSV) and 1 (SpTRSV -> SpTRSV), the
+    preconditioner apply and the static plans on the headline matrices."""
+    out = {}
     for name in ("lap3d7_128", "randspd_1m"):
         L, A = synth.workload(name)
         s = sfm.Schedule(L, A)
@@ -505,6 +537,12 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
         sfm.sync_status(s)
         log("static plans %s: msp %.3f ms (%d s-partitions), wavefront %.3f ms, dynamic %.3f ms" % (
             name, res["msp_ms"], res["msp_s_partitions"], res["wavefront_ms"], res["dynamic_fused_ms"]))
+    return out
+
+
+def run_fwd_bwd(sfm, synth, torch, dev, time_it, reps):
+    """Forward + backward (loss <w, A L^-1 b>) on 3D 7-point 96^3, FP64 and FP32."""
+    out = {}
     L, A = synth.workload("lap3d7_96")
     s = sfm.Schedule(L, A, want_backward=True)
     for dt, tname, vb in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
@@ -546,7 +584,7 @@ def fused_refine_bytes(n, m, nnz_l, nnz_a, k):
 
 
 TUNED_KEYS = ("coarsen", "multi_path", "rhs_block", "spmv_delay", "rows_per_item", "max_item_nnz",
-              "waves_per_cu", "multi_waves_per_cu")
+              "waves_per_cu", "multi_waves_per_cu", "cached_reads", "spmv_prefix")
 
 
 def run_batched(args, sfm, synth, torch, dev, time_it):

@@ -129,6 +129,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oRq = pk.add(&s->rqrng), oRr = pk.add(&s->rroff), oRb = pk.add(&s->rbatch);
   const size_t oRbp = pk.add(&s->rbatch_ptr), oRx = pk.add(&s->rext), oRxp = pk.add(&s->rext_ptr);
   const size_t oRc = pk.add(&s->rcode);
+  const size_t oPqr = pk.add(&s->pqrng), oApre = pk.add(&s->apre);
   void* block = nullptr;
   SF_HIP(hipMalloc(&block, pk.off));
   char* b = static_cast<char*>(block);
@@ -161,6 +162,7 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.rorder = P(oRo); d.ritem_ptr = P(oRip); d.rtrsv_items = P(oRti); d.rqrng = P(oRq); d.rroff = P(oRr);
   d.rbatch = P(oRb); d.rbatch_ptr = P(oRbp); d.rext = P(oRx); d.rext_ptr = P(oRxp);
   d.rcode = reinterpret_cast<uint16_t*>(b + oRc);
+  d.pqrng = P(oPqr); d.apre = P(oApre);
   if (!d.state) {
     std::vector<int32_t> init(kStateWords, 0);
     for (int p = 0; p < 2; ++p) init[info_off(p)] = kInfoNone;
@@ -456,12 +458,20 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
       a.lloc = s->dev.clloc;
       a.eloc = s->dev.celoc;
     }
+    // prefix fusion on level items: SpMV rows' prefixes are folded by their
+    // SpTRSV rows and handed over through Y (filled with the pending pattern)
+    const bool prefix = !s->chunked && Y && s->spmv_prefix && !s->apre.empty();
+    if (prefix) {
+      a.qrng = s->dev.pqrng;
+      a.apre = s->dev.apre;
+    }
     const int waves = nrhs == 1 ? s->waves_per_cu
                                 : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : (nrhs <= 8 ? 8 : 16));
-    const int grid = persistent_grid(s, occupancy_ts_fused(dtype), waves);
+    const int grid = persistent_grid(s, prefix ? occupancy_ts_fused_pre(dtype) : occupancy_ts_fused(dtype), waves);
     Timer tm(s, st);
     if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));  // counts start at 0
     SF_HIP(launch_fill_pending_cols(X, int32_t(s->n), ldx, nrhs, dtype, st));
+    if (prefix) SF_HIP(launch_fill_pending_cols(Y, int32_t(s->m), ldy, nrhs, dtype, st));
     return hip_status(launch_ts_fused(a, dtype, grid, st));
   }
   const int kb = solve_kb(s, nrhs);
@@ -1678,6 +1688,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     s->no_fusion = v ? 1 : 0;
   } else if (k == "timing") {
     s->timing = v ? 1 : 0;
+  } else if (k == "spmv_prefix") {
+    if (v < 0 || v > 1) return SF_ERR_ARG;
+    s->spmv_prefix = int32_t(v);
   } else if (k == "trace") {
     // trace mode: the fused single-RHS executor stamps every item (debug aid)
     if (s->trace) {
@@ -1730,6 +1743,8 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "fingerprint") *v = int64_t(pattern_fingerprint(s) & 0x7fffffffffffffffull);
   else if (k == "timing") *v = s->timing;
   else if (k == "trace") *v = s->trace ? 1 : 0;
+  else if (k == "spmv_prefix") *v = s->spmv_prefix;
+  else if (k == "prefix_rows") *v = s->prefix_rows;  // read only: SpMV rows with a fusable prefix
   else return SF_ERR_ARG;
   return SF_OK;
 }
@@ -1745,7 +1760,7 @@ namespace {
 // takes the tuned parameters without timing anything.
 const char* const kTuneKeys[] = {"coarsen",       "multi_path",   "rhs_block",    "spmv_delay",
                                  "rows_per_item", "max_item_nnz", "waves_per_cu", "multi_waves_per_cu",
-                                 "cached_reads"};
+                                 "cached_reads",  "spmv_prefix"};
 constexpr int kNTune = int(sizeof(kTuneKeys) / sizeof(kTuneKeys[0]));
 struct Tuned {
   int64_t v[kNTune];
@@ -1865,6 +1880,7 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK && nrhs == 1) r = try_param("max_item_nnz", {128, 256, 512, 1024, 2048});
   if (r == SF_OK && nrhs == 1) r = try_param("waves_per_cu", {4, 8, 16});
   if (r == SF_OK && nrhs == 1) r = try_param("cached_reads", {1, 2, 3});
+  if (r == SF_OK && Y && s->prefix_rows > 0) r = try_param("spmv_prefix", {0, 1});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_waves_per_cu", {8, 16, 32});
   if (r == SF_OK) r = upload(s, st);
   r = enqueued(s, stream, r);

@@ -591,6 +591,42 @@ static void position_ranges(const sf_schedule_s* s, const std::vector<int32_t>& 
   }
 }
 
+// Prefix fusion (sf_schedule_s::apre, pqrng) over the level plan's claim
+// order: row r qualifies when A's row r starts with exactly L's row r
+// off-diagonal columns followed by the diagonal.  Its SpMV row then comes
+// after SpTRSV row r in claim order (it reads x_r), which the fold's
+// hand-over needs.
+static void prefix_ranges(sf_schedule_s* s) {
+  s->apre.clear();
+  s->pqrng.clear();
+  s->prefix_rows = 0;
+  if (s->kind != SF_TRSV_SPMV || s->m == 0 || s->A.rp.empty()) return;
+  const int64_t n = s->n, lim = std::min<int64_t>(s->n, s->m);
+  std::vector<int32_t> pre(size_t(lim), 0);
+  for (int64_t r = 0; r < lim; ++r) {
+    const int32_t l0 = s->L.rp[r], cnt = s->L.rp[r + 1] - 1 - l0, a0 = s->A.rp[r];
+    if (s->A.rp[r + 1] - a0 < cnt + 1) continue;
+    bool ok = s->A.ci[size_t(a0 + cnt)] == r;
+    for (int32_t t = 0; ok && t < cnt; ++t) ok = s->A.ci[size_t(a0 + t)] == s->L.ci[size_t(l0 + t)];
+    if (ok) {
+      pre[size_t(r)] = cnt + 1;
+      ++s->prefix_rows;
+    }
+  }
+  if (s->prefix_rows == 0) return;
+  s->apre.resize(s->order.size());
+  s->pqrng = s->qrng;
+  for (size_t q = 0; q < s->order.size(); ++q) {
+    const int32_t id = s->order[q];
+    s->apre[q] = -1;
+    if (id < n) {
+      if (id < lim && pre[size_t(id)] > 0) s->apre[q] = s->A.rp[id];
+    } else if (id - n < lim && pre[size_t(id - n)] > 0) {
+      s->pqrng[2 * q] = -(s->A.rp[id - n] + pre[size_t(id - n)]) - 1;
+    }
+  }
+}
+
 void cut_items(sf_schedule_s* s) {
   const int64_t n = s->n, m = s->m;
   if (s->kind == SF_TRSV_SPMV) {
@@ -634,6 +670,7 @@ void cut_items(sf_schedule_s* s) {
     s->cqrng.clear();
     if (try_chunks && n > 0) build_chunks(s);
     position_ranges(s, s->order, s->qrng);
+    prefix_ranges(s);
     if (!s->corder.empty()) position_ranges(s, s->corder, s->cqrng);
     s->chunked = !s->ctrsv_items.empty() &&
                  (s->coarsen == 2 || s->coarsen == 3 || s->est_chunk_us < 0.8 * s->est_level_us);

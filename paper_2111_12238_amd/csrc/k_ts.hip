@@ -43,12 +43,13 @@ namespace {
 // always one being processed.  With a coarsened plan (a.lloc != nullptr)
 // SpTRSV items whose rows span several local wavefronts run through
 // item_chunk_rows.
-template <typename T>
+template <typename T, bool PRE>
 __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
-  __shared__ WaveLds<T> lds[kWaves];
+  using W = std::conditional_t<PRE, dev::WaveLdsPre<T>, WaveLds<T>>;
+  __shared__ W lds[kWaves];
   __shared__ T xloc[kWaves][65];  // item-local x by slot; [64] = 1.0 (see chunk_steps)
   const int lane = threadIdx.x & 63;
-  WaveLds<T>& w = lds[threadIdx.x >> 6];
+  W& w = lds[threadIdx.x >> 6];
   T* xl = xloc[threadIdx.x >> 6];
   if (lane == 0) xl[64] = T(1);
   dev::reset_next_launch(a.ls);
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
     const int id = mine ? a.order[q0 + lane] : 0;
     const int2 rg = mine ? reinterpret_cast<const int2*>(a.qrng)[q0 + lane] : make_int2(0, 0);
     const int myloc = (a.lloc && mine) ? int(a.lloc[q0 + lane]) : 0;
+    const int a0 = (PRE && mine) ? a.apre[q0 + lane] : -1;  // prefix fusion: the row's prefix in A
     // the item's last local wavefront, on lane 0 (a uniform load would be
     // waited for at once, to move it to a scalar register)
     const int lastloc = (a.lloc && lane == 0) ? int(a.lloc[q1 - 1]) : 0;
@@ -96,7 +98,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_ts_fused(TsArgs a) {
     const int maxloc = __shfl(lastloc, 0, 64);
     int itn = 0, q0n = 0, q1n = 0;
     if (tn < total) item_range(a, tn / nc, itn, q0n, q1n);
-    if (__shfl(id, 0, 64) < a.n) {  // lane 0 holds the item's first row (an item has >= 1 row)
+    if constexpr (PRE) {
+      // level items only (no coarsened items with prefix fusion)
+      if (__shfl(id, 0, 64) < a.n) {
+        if (a.cached & 2) item_stream_rows_pre<T, 3>(ac, q0, q1, lane, w, tr, id, rg, a0);
+        else item_stream_rows_pre<T, 2>(ac, q0, q1, lane, w, tr, id, rg, a0);
+      } else if (a.cached & 1) {
+        item_spmv_rows_from<T, 3>(ac, q0, q1, lane, w, tr, id, rg);
+      } else {
+        item_spmv_rows_from<T, 2>(ac, q0, q1, lane, w, tr, id, rg);
+      }
+    } else if (__shfl(id, 0, 64) < a.n) {  // lane 0 holds the item's first row (an item has >= 1 row)
       if (maxloc != 0) item_chunk_rows<T>(ac, q0, q1, lane, w, xl, tr, id, rg, myloc, maxloc);
       else if (a.cached & 2) item_stream_rows<T, true, 3>(ac, q0, q1, lane, w, tr, id, rg);
       else item_stream_rows<T, true, 2>(ac, q0, q1, lane, w, tr, id, rg);
@@ -364,8 +376,15 @@ int cu_count() {
 
 hipError_t launch_ts_fused(const TsArgs& a, int dtype, int grid, hipStream_t st) {
   if (!a.qrng || !a.order || !a.item_ptr) return hipErrorInvalidValue;  // rows are streamed by claim position
-  if (dtype == 0) hipLaunchKernelGGL(k_ts_fused<double>, dim3(grid), dim3(kBlockThreads), 0, st, a);
-  else hipLaunchKernelGGL(k_ts_fused<float>, dim3(grid), dim3(kBlockThreads), 0, st, a);
+  if (a.apre) {
+    if (!a.Y || !a.Av || !a.Aci) return hipErrorInvalidValue;
+    if (dtype == 0) hipLaunchKernelGGL((k_ts_fused<double, true>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_ts_fused<float, true>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+  } else if (dtype == 0) {
+    hipLaunchKernelGGL((k_ts_fused<double, false>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_ts_fused<float, false>), dim3(grid), dim3(kBlockThreads), 0, st, a);
+  }
   return hipGetLastError();
 }
 hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st) {
@@ -451,7 +470,10 @@ hipError_t launch_fill_pending(void* p, size_t count, int dtype, hipStream_t st)
   return hipGetLastError();
 }
 int occupancy_ts_fused(int dtype) {
-  return dtype == 0 ? occ(k_ts_fused<double>) : occ(k_ts_fused<float>);
+  return dtype == 0 ? occ(k_ts_fused<double, false>) : occ(k_ts_fused<float, false>);
+}
+int occupancy_ts_fused_pre(int dtype) {
+  return dtype == 0 ? occ(k_ts_fused<double, true>) : occ(k_ts_fused<float, true>);
 }
 template <typename T>
 int occ_multi(int kb, bool levelset) {

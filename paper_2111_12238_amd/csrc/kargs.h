@@ -44,6 +44,10 @@ struct TsArgs {
   int32_t n_work;          // items to run (entries of item_list, or all items)
   const uint8_t* lloc;     // coarsened plan: local wavefront per claim position (else nullptr)
   const uint8_t* eloc;     // coarsened plan: per L entry, slot of its column in the item or 0xFF
+  const int32_t* apre;     // prefix fusion (level items, k_ts_fused<T, true>): per claim position of an
+                           // SpTRSV row i, A's first position of SpMV row i's prefix (its entries up to
+                           // the diagonal, columns those of L's row i), or -1; SpMV rows with a prefix
+                           // have qrng.x = -(first position past the prefix + 1) and start from Y
   int32_t cached;           // fused executor: bit 0 = SpMV rows, bit 1 = SpTRSV level items read x
                             // through the caches first (stream.h, VEC = 3)
   unsigned long long* trace;  // optional: kTraceItemWords words per item (see k_ts.hip)
@@ -195,6 +199,7 @@ hipError_t launch_rfused(const RfArgs& a, int nc, int kb, int grid, hipStream_t 
 
 // Launchers (return the HIP error of the launch).
 hipError_t launch_ts_fused(const TsArgs& a, int dtype, int grid, hipStream_t st);
+int occupancy_ts_fused_pre(int dtype);
 hipError_t launch_ts_region(const TsArgs& a, const RegionArgs& r, int dtype, int grid, hipStream_t st);
 hipError_t launch_ts_multi(const TsArgs& a, int dtype, int kb, int grid, hipStream_t st);
 hipError_t launch_pair(const TsArgs& a, int dtype, int mode, int grid, hipStream_t st);

@@ -82,6 +82,8 @@ struct DeviceBuffers {
   int32_t *border = nullptr, *bitem_ptr = nullptr;
   int32_t *bcorder = nullptr, *bcitem_ptr = nullptr;
   uint8_t *bclloc = nullptr, *bceloc = nullptr;
+  // prefix fusion (level plan)
+  int32_t *pqrng = nullptr, *apre = nullptr;
   // region plan
   int32_t *rorder = nullptr, *ritem_ptr = nullptr, *rtrsv_items = nullptr, *rqrng = nullptr, *rroff = nullptr;
   int32_t *rbatch = nullptr, *rbatch_ptr = nullptr, *rext = nullptr, *rext_ptr = nullptr;
@@ -178,6 +180,16 @@ struct sf_schedule_s {
   // by the model): regions of up to region_rows rows, each run by one
   // wavefront level by level with its x in LDS, every row waiting only for
   // its own inputs (inspect.cpp, build_regions; k_region.hip).
+  // Prefix fusion on the level plan: SpMV row r's entries up to its
+  // diagonal, when their columns are exactly SpTRSV row r's (L = lower(A)),
+  // are folded by SpTRSV row r's item from the x values it gathers anyway;
+  // the SpMV row continues the fold past them.  apre: per claim position of
+  // `order`, A's first position of the SpTRSV row's prefix or -1; pqrng:
+  // qrng with each such SpMV row's range starting past its prefix, encoded
+  // -(start + 1).
+  int32_t spmv_prefix = 1;              // 0: off
+  int64_t prefix_rows = 0;              // SpMV rows with a fused prefix
+  std::vector<int32_t> pqrng, apre;
   int32_t region_rows = 512;
   int32_t region_poll = 64;          // poller lanes (bits 0-7) and back-off rounds (bits 8-15)
   bool regioned = false;             // the region plan is in effect for the fused executor

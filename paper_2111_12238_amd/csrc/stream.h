@@ -205,6 +205,186 @@ __device__ __forceinline__ T stream_accumulate(int nr, int r0, int len, T acc, c
   return acc;
 }
 
+// ---- prefix fusion (level items) ----
+//
+// SpTRSV row i also folds SpMV row i's prefix -- its entries up to the
+// diagonal, whose columns are exactly L's row i off-diagonals -- from the x
+// values the row gathers anyway: y_i's partial sum, in A's entry order
+// from 0.  apos holds each stream entry's A position (-1: the row has no
+// prefix) and prod2 the prefix products.
+template <typename T>
+struct WaveLdsPre : WaveLds<T> {
+  int32_t apos[kPass];
+  T prod2[kPass];
+};
+
+// stream_accumulate for SpTRSV rows (SUB) with a prefix: as above, and for
+// rows with a0 >= 0 (the A position of the row's first prefix entry) also
+// acc2 += A[a0 + t] * vec[col] in entry order t (acc2 from 0).
+template <typename T, int VEC>
+__device__ __forceinline__ T stream_accumulate_pre(int nr, int r0, int len, int a0, T acc, T& acc2,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ aval, const T* vec, int lane,
+                                                   WaveLdsPre<T>& w, const LaunchState& ls,
+                                                   unsigned long long* trace = nullptr) {
+  const bool mine = lane < nr;
+  if (!mine) len = 0;
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  acc2 = T(0);
+  for (int base = 0; base < total; base += kPass) {
+    if (mine) {
+      const int lo = max(off, base), hi = min(off + len, base + kPass);
+      for (int t = lo; t < hi; ++t) {
+        w.pos[t - base] = r0 + (t - off);
+        w.apos[t - base] = a0 >= 0 ? a0 + (t - off) : -1;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    int j[kRounds];
+    T v[kRounds], av[kRounds], xv[kRounds];
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      j[e] = -1;
+      v[e] = T(0);
+      av[e] = T(0);
+      if (k < total) {
+        const int p = w.pos[k - base];
+        const int q = w.apos[k - base];
+        j[e] = ld_stream(col + p);
+        v[e] = ld_stream(val + p);
+        if (q >= 0) av[e] = ld_stream(aval + q);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e)
+      xv[e] = j[e] >= 0 ? ((VEC == 0 || VEC == 3) ? vec[j[e]] : ld_co(vec + j[e])) : T(0);
+    if (trace && lane == 0) trace[1] = __builtin_amdgcn_s_memrealtime();
+    if constexpr (VEC >= 2) wait_ready<T, kRounds>(vec, j, xv, lane, ls);
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      if (k < total) {
+        w.prod[k - base] = v[e] * xv[e];
+        w.prod2[k - base] = av[e] * xv[e];
+      }
+    }
+    if (trace && lane == 0) trace[2] = __builtin_amdgcn_s_memrealtime();
+    __builtin_amdgcn_wave_barrier();
+    if (mine) {
+      const int lo = max(off, base) - base;
+      const int hi = min(off + len, base + kPass) - base;
+      int t = lo;
+      for (; t + 8 <= hi; t += 8) {
+        T pr[8], pq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          pr[u] = w.prod[t + u];
+          pq[u] = w.prod2[t + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          acc = acc - pr[u];
+          acc2 = acc2 + pq[u];
+        }
+      }
+      for (; t < hi; ++t) {
+        acc = acc - w.prod[t];
+        acc2 = acc2 + w.prod2[t];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return acc;
+}
+
+// stream_accumulate for SpMV rows whose prefix was folded by their SpTRSV
+// row: the row's lane starts from y0 (its partial sum, published by the
+// SpTRSV row's item through the readiness protocol, read here device-
+// coherently and waited for with the entries' x) instead of 0; y0 == nullptr
+// for a row without a prefix.
+template <typename T, int VEC>
+__device__ __forceinline__ T stream_accumulate_from(int nr, int r0, int len, const T* y0,
+                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                    const T* vec, int lane, WaveLds<T>& w, const LaunchState& ls,
+                                                    unsigned long long* trace = nullptr) {
+  const bool mine = lane < nr;
+  if (!mine) len = 0;
+  T acc = (mine && y0) ? ld_co(y0) : T(0);  // in flight with the first pass
+  bool first = true;
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const int off = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  for (int base = 0; base == 0 || base < total; base += kPass) {
+    if (mine) {
+      const int lo = max(off, base), hi = min(off + len, base + kPass);
+      for (int t = lo; t < hi; ++t) w.pos[t - base] = r0 + (t - off);
+    }
+    __builtin_amdgcn_wave_barrier();
+    int j[kRounds];
+    T v[kRounds], xv[kRounds];
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      j[e] = -1;
+      v[e] = T(0);
+      if (k < total) {
+        const int p = w.pos[k - base];
+        j[e] = ld_stream(col + p);
+        v[e] = ld_stream(val + p);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e)
+      xv[e] = j[e] >= 0 ? ((VEC == 0 || VEC == 3) ? vec[j[e]] : ld_co(vec + j[e])) : T(0);
+    if (trace && lane == 0) trace[1] = __builtin_amdgcn_s_memrealtime();  // loads issued
+    if constexpr (VEC >= 2) wait_ready<T, kRounds>(vec, j, xv, lane, ls);
+    if (first) {
+      // the partial sum: re-read while pending (all lanes poll together)
+      int32_t spins = 0;
+      while (__ballot(mine && y0 && is_pending(acc)) != 0) {
+        if (mine && y0 && is_pending(acc)) acc = ld_co(y0);
+        if (!all_poll_round(spins, ls)) break;
+      }
+      first = false;
+    }
+    if (trace && lane == 0) trace[2] = __builtin_amdgcn_s_memrealtime();  // inputs ready
+#pragma unroll
+    for (int e = 0; e < kRounds; ++e) {
+      const int k = base + lane + 64 * e;
+      if (k < total) w.prod[k - base] = v[e] * xv[e];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (mine) {
+      const int lo = max(off, base) - base;
+      const int hi = min(off + len, base + kPass) - base;
+      int t = lo;
+      for (; t + 8 <= hi; t += 8) {
+        T pr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pr[u] = w.prod[t + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = acc + pr[u];
+      }
+      for (; t < hi; ++t) acc = acc + w.prod[t];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return acc;
+}
+
 // ---- coarsened items: rows on several local wavefronts ----
 //
 // Local wavefront steps.  The owner lane keeps its row's first NT terms in

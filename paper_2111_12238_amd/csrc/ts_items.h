@@ -65,6 +65,58 @@ __device__ __forceinline__ void item_stream_rows(const TsArgs& a, int q0, int q1
   if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
 }
 
+// Prefix fusion (level items; a.apre set): an SpTRSV item whose rows also
+// fold their SpMV row's prefix and publish it to Y (read back by the SpMV
+// row, which continues the fold: A's entry order is kept, so y is the
+// sequential definition's bit for bit).  a0: the lane's row's first prefix
+// position in A, or -1; the diagonal A_ii closes the prefix at a0 + (row's
+// off-diagonal count), multiplied by the published x_i.
+template <typename T, int VEC>
+__device__ __forceinline__ void item_stream_rows_pre(const TsArgs& a, int q0, int q1, int lane,
+                                                     dev::WaveLdsPre<T>& w, unsigned long long* tr, int id,
+                                                     int2 rg, int a0) {
+  const int nr = q1 - q0;
+  const bool mine = lane < nr;
+  const T* __restrict__ val = static_cast<const T*>(a.Lv);
+  const T* __restrict__ aval = static_cast<const T*>(a.Av);
+  T* X = static_cast<T*>(a.X);
+  const int r0 = rg.x, r1 = rg.y;
+  T acc = T(0), dii = T(1), acc2 = T(0);
+  if (mine) {
+    acc = static_cast<const T*>(a.B)[id];
+    dii = ld_stream(val + r1);
+  }
+  acc = dev::stream_accumulate_pre<T, VEC>(nr, r0, r1 - r0, mine ? a0 : -1, acc, acc2, a.Lci, val, aval, X, lane,
+                                           w, a.ls, tr);
+  if (a.rtrace) dev::stamp_publish(a.rtrace, mine, id);
+  if (mine) {
+    const T x = publishable(acc / dii);
+    st_co(X + id, x);
+    if (a0 >= 0) st_co(static_cast<T*>(a.Y) + id, publishable(acc2 + ld_stream(aval + a0 + (r1 - r0)) * x));
+  }
+  if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
+}
+
+// SpMV rows under prefix fusion: a row with a folded prefix (qrng.x < 0,
+// encoding -(first position past the prefix + 1)) starts from its partial
+// sum in Y; the others from 0, as item_stream_rows.
+template <typename T, int VEC>
+__device__ __forceinline__ void item_spmv_rows_from(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
+                                                    unsigned long long* tr, int id, int2 rg) {
+  const int nr = q1 - q0;
+  const bool mine = lane < nr;
+  const int row = id - a.n;
+  T* Y = static_cast<T*>(a.Y);
+  const bool pre = mine && rg.x < 0;
+  const int r0 = pre ? -rg.x - 1 : rg.x;
+  T acc = dev::stream_accumulate_from<T, VEC>(nr, r0, rg.y - r0, pre ? Y + row : nullptr, a.Aci,
+                                              static_cast<const T*>(a.Av), static_cast<const T*>(a.X), lane, w,
+                                              a.ls, tr);
+  if (a.rtrace) dev::stamp_publish(a.rtrace, mine, id);
+  if (mine) __builtin_nontemporal_store(acc, Y + row);
+  if (tr && lane == 0) tr[3] = __builtin_amdgcn_s_memrealtime();
+}
+
 template <typename T, bool TRSV, int VEC>
 __device__ __forceinline__ void item_stream(const TsArgs& a, int q0, int q1, int lane, WaveLds<T>& w,
                                             int it = -1) {

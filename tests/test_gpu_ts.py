@@ -524,3 +524,45 @@ def test_multi_rhs_paths_bit_exact(orc, path, coarsen):
         sfm.sync_status(s)
         assert np.array_equal(host(X), xr) and np.array_equal(host(Y), yr), unfused
         assert bool((Xbuf[:, n:] == -7.0).all()) and bool((Ybuf[:, 4000:] == -9.0).all()), unfused
+
+
+@pytest.mark.parametrize("case", ["spd", "partial", "spd_f32", "chains"])
+def test_prefix_fusion(orc, case):
+    """Prefix fusion on level items: SpMV row r's entries up to its diagonal
+    (their columns exactly L's row r) are folded by SpTRSV row r's item from
+    the x values it gathers, and the SpMV row continues the fold from that
+    partial sum -- A's entry order kept, so y equals the oracle's ordered
+    fold bit for bit, with the prefix on and off.  "partial": L misses some
+    of lower(A)'s entries, so only some rows qualify; "chains": three
+    right-hand sides as column chains of the level items."""
+    import torch
+    announce("ts prefix fusion " + case)
+    A = synth.random_spd(30000, seed=7)
+    L = synth.lower(A)
+    if case == "partial":
+        Ls = L.to_scipy().tocoo()
+        keep = (Ls.row == Ls.col) | (np.random.default_rng(4).random(Ls.nnz) < 0.7)
+        L = synth.from_scipy(sp.csr_matrix((Ls.data[keep], (Ls.row[keep], Ls.col[keep])), shape=Ls.shape))
+    k = 3 if case == "chains" else None
+    b = synth.vec_uniform(L.nrows, k=k or 1, seed=9)
+    s = sfm.Schedule(L, A, coarsen=1)
+    rows = s.get_param("prefix_rows")
+    if case == "partial":
+        assert 0 < rows < L.nrows
+    else:
+        assert rows == L.nrows
+    if case == "chains":
+        s.set_param("multi_path", 2)
+    dt = "f32" if case == "spd_f32" else "f64"
+    assert s.get_param("spmv_prefix") == 1
+    x1, y1 = run(s, L, A, b, dtype=dt)
+    s.set_param("spmv_prefix", 0)
+    x0, y0 = run(s, L, A, b, dtype=dt)
+    assert np.array_equal(x1, x0) and np.array_equal(y1, y0)
+    if dt == "f64":
+        xr, yr = oracle_ts(orc, L, A, b)
+        assert np.array_equal(x1, xr) and np.array_equal(y1, yr)
+    s.set_param("spmv_prefix", 1)
+    s.set_param("spmv_delay", 1 << 20)  # SpMV rows after every SpTRSV row
+    x2, y2 = run(s, L, A, b, dtype=dt)
+    assert np.array_equal(x2, x0) and np.array_equal(y2, y0)

@@ -652,3 +652,38 @@ def test_region_plans(orc, case, rows):
     u, v = L.col[off], r[off]
     same = item[pos[u]] == item[pos[v]]
     assert np.all(loc[pos[u][same]] < loc[pos[v][same]])
+
+
+def _prefix_rows_reference(L, A):
+    """Rows r < min(n, m) whose A row starts with exactly L's row r
+    off-diagonal columns followed by the diagonal (prefix fusion)."""
+    cnt = 0
+    for r in range(min(L.nrows, A.nrows)):
+        lc = L.col[L.rowptr[r]:L.rowptr[r + 1] - 1]
+        ac = A.col[A.rowptr[r]:A.rowptr[r + 1]]
+        if len(ac) >= len(lc) + 1 and np.array_equal(ac[:len(lc)], lc) and ac[len(lc)] == r:
+            cnt += 1
+    return cnt
+
+
+@pytest.mark.parametrize("case", ["lap2d5_64", "random", "random_rect", "spd_partial"])
+def test_prefix_rows(case):
+    """The inspector's prefix-fusion rows match the rule written out."""
+    if case == "lap2d5_64":
+        L, A = synth.workload("lap2d5_64")
+    elif case == "random":
+        L, A = _random_pair(1000, 3)
+    elif case == "random_rect":
+        L, A = _random_pair(777, 6, 1300, True)
+    else:
+        A = synth.random_spd(3000, seed=2)
+        Ls = synth.lower(A).to_scipy().tocoo()
+        keep = (Ls.row == Ls.col) | (np.random.default_rng(1).random(Ls.nnz) < 0.6)
+        L = synth.from_scipy(sp.csr_matrix((Ls.data[keep], (Ls.row[keep], Ls.col[keep])), shape=Ls.shape))
+    s = sfm.Schedule(L, A, coarsen=1)
+    want = _prefix_rows_reference(L, A)
+    assert s.get_param("prefix_rows") == want
+    if case in ("lap2d5_64",):
+        assert want == L.nrows
+    if case == "spd_partial":
+        assert 0 < want < L.nrows
