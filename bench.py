@@ -51,7 +51,7 @@ def bounds(d, fused_ms, probe):
     if not probe:
         return None
     st = d["s"].info()
-    gathers = d["L"].nnz - d["L"].nrows + d["A"].nnz
+    gathers = pass_gathers(d)
     regioned = d["s"].get_param("regioned") == 1
     hops = d["s"].get_param("region_chain") if regioned else st.chunk_chain if st.coarsened else st.joint_depth
     b = {"hbm_peak_ms": d["bytes"] / (HBM_PEAK_GBPS * 1e9) * 1e3,
@@ -66,6 +66,17 @@ def bounds(d, fused_ms, probe):
     out["binding"] = name[:-3]
     out["frac_of_binding"] = round(cands[name] / fused_ms, 3)
     return out
+
+
+def pass_gathers(d):
+    """Single-value x gathers of one fused pass: the off-diagonals of L and
+    the entries of A, less the SpMV prefixes folded by their SpTRSV rows
+    (prefix fusion, level items), which reuse the SpTRSV rows' gathers."""
+    s = d["s"]
+    g = d["L"].nnz - d["L"].nrows + d["A"].nnz
+    if s.get_param("spmv_prefix") and not s.info().coarsened and not s.get_param("regioned"):
+        g -= s.get_param("prefix_entries")
+    return g
 
 
 def hop_us(probe):
@@ -309,9 +320,9 @@ def main():
             "NER_vs_unfused": round(d["inspect_s"] * 1e3 / (per_launch_u[k] - per_launch[k]), 1)
             if per_launch_u[k] > per_launch[k] else None,
             "critical_path_us_per_level": round(per_launch[k] * 1e3 / max(d["joint_depth"], 1), 3),
-            # single-value x gathers of one pass (off-diagonals of L, entries of A) and their rate
-            "gathers": d["L"].nnz - d["L"].nrows + d["A"].nnz,
-            "fused_Ggathers_per_s": round((d["L"].nnz - d["L"].nrows + d["A"].nnz) / (per_launch[k] * 1e-3) / 1e9, 1),
+            # single-value x gathers of one pass and their rate (pass_gathers)
+            "gathers": pass_gathers(d),
+            "fused_Ggathers_per_s": round(pass_gathers(d) / (per_launch[k] * 1e-3) / 1e9, 1),
             "cold_fused_ms_median": round(float(np.median(cold_f[k])), 4),
             "cold_fused_ms_min": round(float(np.min(cold_f[k])), 4),
             "warm_fused_ms": round(per_launch_w[k], 4),

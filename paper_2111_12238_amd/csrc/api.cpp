@@ -1745,6 +1745,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "trace") *v = s->trace ? 1 : 0;
   else if (k == "spmv_prefix") *v = s->spmv_prefix;
   else if (k == "prefix_rows") *v = s->prefix_rows;  // read only: SpMV rows with a fusable prefix
+  else if (k == "prefix_entries") *v = s->prefix_entries;  // read only: A entries in those prefixes
   else return SF_ERR_ARG;
   return SF_OK;
 }

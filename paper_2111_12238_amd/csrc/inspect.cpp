@@ -600,6 +600,7 @@ static void prefix_ranges(sf_schedule_s* s) {
   s->apre.clear();
   s->pqrng.clear();
   s->prefix_rows = 0;
+  s->prefix_entries = 0;
   if (s->kind != SF_TRSV_SPMV || s->m == 0 || s->A.rp.empty()) return;
   const int64_t n = s->n, lim = std::min<int64_t>(s->n, s->m);
   std::vector<int32_t> pre(size_t(lim), 0);
@@ -611,6 +612,7 @@ static void prefix_ranges(sf_schedule_s* s) {
     if (ok) {
       pre[size_t(r)] = cnt + 1;
       ++s->prefix_rows;
+      s->prefix_entries += cnt + 1;
     }
   }
   if (s->prefix_rows == 0) return;

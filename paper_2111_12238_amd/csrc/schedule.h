@@ -189,6 +189,7 @@ struct sf_schedule_s {
   // -(start + 1).
   int32_t spmv_prefix = 1;              // 0: off
   int64_t prefix_rows = 0;              // SpMV rows with a fused prefix
+  int64_t prefix_entries = 0;           // A entries in those prefixes (diagonals included)
   std::vector<int32_t> pqrng, apre;
   int32_t region_rows = 512;
   int32_t region_poll = 64;          // poller lanes (bits 0-7) and back-off rounds (bits 8-15)

@@ -657,13 +657,14 @@ def test_region_plans(orc, case, rows):
 def _prefix_rows_reference(L, A):
     """Rows r < min(n, m) whose A row starts with exactly L's row r
     off-diagonal columns followed by the diagonal (prefix fusion)."""
-    cnt = 0
+    cnt = ent = 0
     for r in range(min(L.nrows, A.nrows)):
         lc = L.col[L.rowptr[r]:L.rowptr[r + 1] - 1]
         ac = A.col[A.rowptr[r]:A.rowptr[r + 1]]
         if len(ac) >= len(lc) + 1 and np.array_equal(ac[:len(lc)], lc) and ac[len(lc)] == r:
             cnt += 1
-    return cnt
+            ent += len(lc) + 1
+    return cnt, ent
 
 
 @pytest.mark.parametrize("case", ["lap2d5_64", "random", "random_rect", "spd_partial"])
@@ -681,8 +682,9 @@ def test_prefix_rows(case):
         keep = (Ls.row == Ls.col) | (np.random.default_rng(1).random(Ls.nnz) < 0.6)
         L = synth.from_scipy(sp.csr_matrix((Ls.data[keep], (Ls.row[keep], Ls.col[keep])), shape=Ls.shape))
     s = sfm.Schedule(L, A, coarsen=1)
-    want = _prefix_rows_reference(L, A)
+    want, entries = _prefix_rows_reference(L, A)
     assert s.get_param("prefix_rows") == want
+    assert s.get_param("prefix_entries") == entries
     if case in ("lap2d5_64",):
         assert want == L.nrows
     if case == "spd_partial":
