@@ -445,7 +445,7 @@ def run_extras(args, sfm, synth, torch, dev, stream, probe=None):
                                     "bound": path_bound(s.info().depth, tf, probe)}
         log("ilu0 %s fused %.3f ms unfused %.3f ms" % (name, tf, tu))
     if want("small"):
-        out.update(run_small(sfm, synth, torch, dev, time_it, probe))
+        out.update(run_small(args, sfm, synth, torch, dev, time_it, probe))
     if want("batched"):
         out.update(run_batched(args, sfm, synth, torch, dev, time_it))
     if want("pairs"):
@@ -464,7 +464,7 @@ def plan_hops(s):
     return st.chunk_chain if st.coarsened else st.joint_depth
 
 
-def run_small(sfm, synth, torch, dev, time_it, probe):
+def run_small(args, sfm, synth, torch, dev, time_it, probe):
     """The small cache-resident case (2D 5-point 64^2): latency only, so
     microseconds and solves per second rather than a fraction of HBM peak."""
     out = {}
@@ -473,6 +473,8 @@ def run_small(sfm, synth, torch, dev, time_it, probe):
     Lv, Av = torch.as_tensor(L.val, device=dev), torch.as_tensor(A.val, device=dev)
     B = torch.as_tensor(synth.vec_uniform(L.nrows, seed=1), device=dev)
     X, Yt = torch.empty_like(B), torch.empty(A.nrows, dtype=B.dtype, device=dev)
+    if not args.no_autotune:
+        sfm.autotune(s, Lv, Av, B)
     tf = time_it(lambda: sfm.trsv_spmv(s, Lv, Av, B, X=X, Y=Yt), 20)
     tu = time_it(lambda: sfm.trsv_spmv(s, Lv, Av, B, X=X, Y=Yt, unfused=True), 20)
     sfm.sync_status(s)
@@ -480,7 +482,9 @@ def run_small(sfm, synth, torch, dev, time_it, probe):
                               "solves_per_s": round(1e3 / tf, 1), "unfused_us": round(tu * 1e3, 2),
                               "speedup_vs_unfused": round(tu / tf, 3),
                               "us_per_level": round(tf * 1e3 / max(s.info().joint_depth, 1), 3),
-                              "bound": path_bound(plan_hops(s), tf, probe)}
+                              "bound": path_bound(plan_hops(s), tf, probe),
+                              "plan": ("regions" if s.get_param("regioned") else
+                                       "coarsened items" if s.get_param("coarsened") else "level items")}
     log("small 2D 5-point 64^2: fused %.1f us, unfused %.1f us" % (tf * 1e3, tu * 1e3))
     return out
 

@@ -130,6 +130,9 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   const size_t oRbp = pk.add(&s->rbatch_ptr), oRx = pk.add(&s->rext), oRxp = pk.add(&s->rext_ptr);
   const size_t oRc = pk.add(&s->rcode);
   const size_t oPqr = pk.add(&s->pqrng), oApre = pk.add(&s->apre);
+  const size_t oBro = pk.add(&s->brorder), oBrip = pk.add(&s->britem_ptr), oBrr = pk.add(&s->brroff);
+  const size_t oBrb = pk.add(&s->brbatch), oBrbp = pk.add(&s->brbatch_ptr), oBrx = pk.add(&s->brext);
+  const size_t oBrxp = pk.add(&s->brext_ptr), oBrc = pk.add(&s->brcode);
   void* block = nullptr;
   SF_HIP(hipMalloc(&block, pk.off));
   char* b = static_cast<char*>(block);
@@ -163,6 +166,9 @@ sf_status upload(sf_schedule_s* s, hipStream_t st) {
   d.rbatch = P(oRb); d.rbatch_ptr = P(oRbp); d.rext = P(oRx); d.rext_ptr = P(oRxp);
   d.rcode = reinterpret_cast<uint16_t*>(b + oRc);
   d.pqrng = P(oPqr); d.apre = P(oApre);
+  d.brorder = P(oBro); d.britem_ptr = P(oBrip); d.brroff = P(oBrr);
+  d.brbatch = P(oBrb); d.brbatch_ptr = P(oBrbp); d.brext = P(oBrx); d.brext_ptr = P(oBrxp);
+  d.brcode = reinterpret_cast<uint16_t*>(b + oBrc);
   if (!d.state) {
     std::vector<int32_t> init(kStateWords, 0);
     for (int p = 0; p < 2; ++p) init[info_off(p)] = kInfoNone;
@@ -387,6 +393,24 @@ RegionArgs region_args(const sf_schedule_s* s) {
   r.entries_max = std::max(1, s->region_entries_max);
   r.ext_max = std::max(1, s->region_ext_max);
   r.batches_max = std::max(1, s->region_batches_max);
+  r.poll_lanes = std::max(1, std::min(64, s->region_poll & 0xff));
+  r.poll_sleep = (s->region_poll >> 8) & 0xff;
+  return r;
+}
+
+// The backward region plan's arguments (k_bwd_region).
+RegionArgs back_region_args(const sf_schedule_s* s) {
+  RegionArgs r{};
+  r.batch = s->dev.brbatch;
+  r.batch_ptr = s->dev.brbatch_ptr;
+  r.ext = s->dev.brext;
+  r.ext_ptr = s->dev.brext_ptr;
+  r.roff = s->dev.brroff;
+  r.code = s->dev.brcode;
+  r.rows_max = std::max(1, s->back_region_rows_max);
+  r.entries_max = std::max(1, s->back_region_entries_max);
+  r.ext_max = std::max(1, s->back_region_ext_max);
+  r.batches_max = std::max(1, s->back_region_batches_max);
   r.poll_lanes = std::max(1, std::min(64, s->region_poll & 0xff));
   r.poll_sleep = (s->region_poll >> 8) & 0xff;
   return r;
@@ -864,7 +888,9 @@ sf_status sf_schedule_info(sf_schedule s, sf_schedule_stats* st) {
   st->joint_depth = s->joint_depth;
   st->back_depth = s->back_depth;
   st->n_items = int32_t(s->regioned ? s->ritem_ptr.size() : s->chunked ? s->citem_ptr.size() : s->item_ptr.size()) - 1;
-  st->n_back_items = s->has_back ? int32_t((s->bchunked ? s->bcitem_ptr : s->bitem_ptr).size()) - 1 : 0;
+  st->n_back_items = s->has_back
+                        ? int32_t((s->bregioned ? s->britem_ptr : s->bchunked ? s->bcitem_ptr : s->bitem_ptr).size()) - 1
+                        : 0;
   st->max_level_width = s->max_level_width;
   st->lanes_per_row = s->lanes_trsv;
   st->lanes_per_spmv = s->lanes_spmv;
@@ -923,8 +949,8 @@ sf_status sf_schedule_export_local(sf_schedule s, uint8_t* local_level, uint8_t*
 
 sf_status sf_schedule_export_backward(sf_schedule s, int32_t* rlevel, int32_t* order, int32_t* item_ptr) {
   if (!s || !s->has_back) return SF_ERR_ARG;
-  const std::vector<int32_t>& o = s->bchunked ? s->bcorder : s->border;
-  const std::vector<int32_t>& ip = s->bchunked ? s->bcitem_ptr : s->bitem_ptr;
+  const std::vector<int32_t>& o = s->bregioned ? s->brorder : s->bchunked ? s->bcorder : s->border;
+  const std::vector<int32_t>& ip = s->bregioned ? s->britem_ptr : s->bchunked ? s->bcitem_ptr : s->bitem_ptr;
   if (rlevel) std::copy(s->rlevel.begin(), s->rlevel.end(), rlevel);
   if (order) std::copy(o.begin(), o.end(), order);
   if (item_ptr) std::copy(ip.begin(), ip.end(), item_ptr);
@@ -934,11 +960,12 @@ sf_status sf_schedule_export_backward(sf_schedule s, int32_t* rlevel, int32_t* o
 sf_status sf_schedule_export_backward_local(sf_schedule s, uint8_t* local_level, uint8_t* entry_slot) {
   if (!s || !s->has_back) return SF_ERR_ARG;
   if (local_level) {
-    if (s->bchunked) std::copy(s->bclloc.begin(), s->bclloc.end(), local_level);
+    if (s->bregioned) std::copy(s->brlloc.begin(), s->brlloc.end(), local_level);
+    else if (s->bchunked) std::copy(s->bclloc.begin(), s->bclloc.end(), local_level);
     else std::fill(local_level, local_level + size_t(s->n), uint8_t(0));
   }
   if (entry_slot) {
-    if (s->bchunked) std::copy(s->bceloc.begin(), s->bceloc.end(), entry_slot);
+    if (s->bchunked && !s->bregioned) std::copy(s->bceloc.begin(), s->bceloc.end(), entry_slot);
     else std::fill(entry_slot, entry_slot + size_t(s->LT.nnz()), uint8_t(0xFF));
   }
   return SF_OK;
@@ -1257,6 +1284,20 @@ sf_status backward_core(sf_schedule_s* s, sf_dtype dtype, const void* L_val, con
   a.Lrp = d.Lrp; a.Lci = d.Lci;
   a.Lv = L_val; a.Av = A_val; a.X = x; a.G = G;
   a.lam = grad_B; a.gradL = grad_L_val;
+  if (s->bregioned) {
+    a.order = d.brorder;
+    a.item_ptr = d.britem_ptr;
+    a.n_work = int32_t(s->britem_ptr.size() - 1);
+    sf_status r = next_epoch(s, st, a.ls);
+    if (r != SF_OK) return r;
+    const RegionArgs ra = back_region_args(s);
+    // blocks of two wavefronts (a computing and a polling one)
+    const int per_cu = std::min(std::max(1, occupancy_bwd_region(ra, dt)), std::max(1, s->waves_per_cu / 2));
+    const int grid = std::max(std::max(1, device_cus()) * per_cu, kStreams);
+    Timer tm(s, st);
+    SF_HIP(launch_fill_pending(grad_B, size_t(s->n), dt, st));
+    return hip_status(launch_bwd_region(a, ra, dt, grid, st));
+  }
   if (s->bchunked) {
     a.order = d.bcorder;
     a.item_ptr = d.bcitem_ptr;
@@ -1731,6 +1772,8 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "coarsened") *v = s->chunked ? 1 : 0;
   else if (k == "pairs") *v = s->pair_ptr.empty() ? 0 : int64_t(s->pair_ptr.back());  // SpIC0 / SpILU0 intersection pairs (read only)
   else if (k == "back_coarsened") *v = s->bchunked ? 1 : 0;
+  else if (k == "back_regioned") *v = s->bregioned ? 1 : 0;  // read only: the backward region plan is in effect
+  else if (k == "back_region_chain") *v = s->back_region_chain;
   else if (k == "no_fusion") *v = s->no_fusion;
   else if (k == "autotune_cache") *v = s->autotune_cache;
   else if (k == "refine_path") *v = s->refine_path;

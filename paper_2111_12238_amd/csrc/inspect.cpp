@@ -547,6 +547,70 @@ static void build_regions(sf_schedule_s* s, int32_t rows) {
 // Backward coarsened plan: chunk_dag over L^T (the transposed solve's
 // predecessors of row i are the rows j > i with L_ji stored; the diagonal is
 // stored first in each row of L^T).
+// Backward region plan: regions of up to `rows` rows over the transposed
+// solve's DAG (rows of L^T, predecessors j > i with L_ji stored, diagonal
+// first in each row of L^T), laid out as the forward region plan
+// (build_regions) without SpMV rows.  brcode is indexed by L^T position.
+static void build_back_regions(sf_schedule_s* s, int32_t rows) {
+  const int32_t n = int32_t(s->n);
+  const int32_t R = std::max(64, std::min(rows, 1024));
+  const ChunkPlan c = chunk_dag(n, s->LT.rp, s->LT.ci, 1, 0, s->rlevel, R, int64_t(1) << 62);
+  const int32_t nc = int32_t(c.ptr.size()) - 1;
+  s->brorder.clear();
+  s->britem_ptr.assign(1, 0);
+  s->brlloc.clear();
+  s->brroff.clear();
+  s->brbatch.clear();
+  s->brbatch_ptr.assign(1, 0);
+  s->brext.clear();
+  s->brext_ptr.assign(1, 0);
+  s->brcode.assign(size_t(s->LT.nnz()), 0);
+  s->back_region_rows_max = s->back_region_entries_max = s->back_region_ext_max = s->back_region_batches_max = 0;
+  std::vector<int32_t> ext_of(size_t(n), -1), ext_stamp(size_t(n), -1);
+  for (int32_t k = 0; k < nc; ++k) {
+    const int32_t q0 = int32_t(s->brorder.size());
+    const int32_t e0 = int32_t(s->brext.size());
+    int32_t overflow = 0;
+    for (int32_t q = c.ptr[k]; q < c.ptr[k + 1]; ++q) {
+      const int32_t u = c.rows[q];
+      const int32_t pos = int32_t(s->brorder.size());
+      if (q == c.ptr[k] || c.lloc[u] != c.lloc[c.rows[q - 1]] || (pos - s->brbatch[s->brbatch.size() - 2]) >= 64) {
+        s->brbatch.push_back(pos);
+        s->brbatch.push_back(int32_t(s->brext.size()) - e0);
+      }
+      s->brorder.push_back(u);
+      s->brlloc.push_back(c.lloc[u]);
+      s->brroff.push_back(overflow);
+      for (int32_t p = s->LT.rp[u] + 1; p < s->LT.rp[u + 1]; ++p) {
+        const int32_t j = s->LT.ci[p];
+        if (c.chunk_of[j] == k) {
+          s->brcode[size_t(p)] = uint16_t(c.slot[j]);
+        } else {
+          if (ext_stamp[j] != k) {
+            ext_stamp[j] = k;
+            ext_of[j] = int32_t(s->brext.size()) - e0;
+            s->brext.push_back(j);
+          }
+          s->brcode[size_t(p)] = uint16_t(0x8000 | ext_of[j]);
+        }
+      }
+      overflow += std::max(0, s->LT.rp[u + 1] - 1 - s->LT.rp[u] - kRegionAhead);
+    }
+    s->back_region_rows_max = std::max(s->back_region_rows_max, int32_t(s->brorder.size()) - q0);
+    s->back_region_entries_max = std::max(s->back_region_entries_max, overflow);
+    s->back_region_ext_max = std::max(s->back_region_ext_max, int32_t(s->brext.size()) - e0);
+    s->britem_ptr.push_back(int32_t(s->brorder.size()));
+    s->brbatch_ptr.push_back(int32_t(s->brbatch.size() / 2));
+    s->brext_ptr.push_back(int32_t(s->brext.size()));
+    const size_t nbp = s->brbatch_ptr.size();
+    s->back_region_batches_max = std::max(s->back_region_batches_max, s->brbatch_ptr[nbp - 1] - s->brbatch_ptr[nbp - 2]);
+  }
+  s->brbatch.push_back(int32_t(s->brorder.size()));  // end sentinel
+  s->brbatch.push_back(0);
+  s->back_region_chain = c.chain;
+  s->est_back_region_us = pipelined_estimate(n, s->LT.rp, s->LT.ci, 1, 0, c);
+}
+
 static void build_back_chunks(sf_schedule_s* s) {
   const int32_t n = int32_t(s->n);
   const int32_t R = std::max(1, std::min(s->rows_per_item, 64));
@@ -559,6 +623,7 @@ static void build_back_chunks(sf_schedule_s* s) {
   s->bceloc = entry_slots(c, n, s->LT.rp, s->LT.ci, 1, 0);
   s->back_chunk_chain = c.chain;
   s->est_back_chunk_us = c.cp_max;
+  s->est_back_chunk_pipe_us = pipelined_estimate(n, s->LT.rp, s->LT.ci, 1, 0, c);
 }
 
 // Fraction test of the auto mode: coarsening pays where most edges join
@@ -747,11 +812,28 @@ void cut_items(sf_schedule_s* s) {
     s->bceloc.clear();
     s->back_chunk_chain = 0;
     s->est_back_chunk_us = 0.0;
-    const bool try_back = s->coarsen == 2 ||
+    const bool try_back = s->coarsen == 2 || s->coarsen == 3 ||
                           (s->coarsen == 0 && mesh_like(n, s->LT.rp, s->LT.ci, 1, 0, s->rlevel));
+    s->est_back_chunk_pipe_us = 0.0;
     if (try_back && n > 0) build_back_chunks(s);
     s->bchunked = !s->bcitem_ptr.empty() &&
-                  (s->coarsen == 2 || s->est_back_chunk_us < 0.8 * s->est_back_level_us);
+                  (s->coarsen == 2 || s->coarsen == 3 || s->est_back_chunk_us < 0.8 * s->est_back_level_us);
+    // backward regions, as the forward ones: on request, or on a mesh-like
+    // DAG where their estimate beats the coarsened plan's clearly
+    s->bregioned = false;
+    s->brorder.clear();
+    s->est_back_region_us = 0.0;
+    if (n > 0 && (s->coarsen == 3 || (s->coarsen == 0 && try_back && !s->bcitem_ptr.empty()))) {
+      size_t lds = 0;
+      for (int32_t R = std::min(s->region_rows, 1024);; R /= 2) {
+        build_back_regions(s, R);
+        lds = region_lds_bytes(s->back_region_rows_max, s->back_region_entries_max, s->back_region_ext_max,
+                               s->back_region_batches_max, 8);
+        if (lds <= kRegionLdsMax || R <= 64) break;
+      }
+      s->bregioned = lds <= kRegionLdsMax &&
+                     (s->coarsen == 3 || s->est_back_region_us < 0.85 * s->est_back_chunk_pipe_us);
+    }
   }
 }
 
@@ -1108,6 +1190,62 @@ static int validate_region_plan(const sf_schedule_s* s) {
   return 0;
 }
 
+// The backward region plan: every row once, batches of one local level and
+// at most 64 rows, overflow offsets, and for every transposed-solve edge
+// (L_ji stored, j > i) either an in-region code naming j's slot at an
+// earlier local level or an external input of the region listed under j,
+// with j's region claimed earlier.
+static int validate_back_region_plan(const sf_schedule_s* s) {
+  const int64_t n = s->n;
+  if (int64_t(s->brorder.size()) != n) return 30;
+  const int64_t nitems = int64_t(s->britem_ptr.size()) - 1;
+  if (int64_t(s->brbatch_ptr.size()) != nitems + 1 || int64_t(s->brext_ptr.size()) != nitems + 1) return 31;
+  std::vector<int32_t> item(size_t(n), -1), pos(size_t(n), -1);
+  for (int64_t t = 0; t < nitems; ++t)
+    for (int32_t q = s->britem_ptr[t]; q < s->britem_ptr[t + 1]; ++q) {
+      const int32_t i = s->brorder[q];
+      if (i < 0 || i >= n || item[i] >= 0) return 32;
+      item[i] = int32_t(t);
+      pos[i] = q;
+    }
+  for (int64_t t = 0; t < nitems; ++t) {
+    const int32_t q0 = s->britem_ptr[t], q1 = s->britem_ptr[t + 1];
+    const int32_t b0 = s->brbatch_ptr[t], b1 = s->brbatch_ptr[t + 1];
+    if (b1 <= b0 || s->brbatch[2 * b0] != q0) return 33;
+    for (int32_t b = b0; b < b1; ++b) {
+      const int32_t pb = s->brbatch[2 * b], pe = b + 1 < b1 ? s->brbatch[2 * (b + 1)] : q1;
+      if (pe <= pb || pe - pb > 64) return 34;
+      for (int32_t q = pb; q < pe; ++q)
+        if (s->brlloc[q] != s->brlloc[pb]) return 34;
+      if (b + 1 < b1 && s->brlloc[pe] < s->brlloc[pb]) return 34;
+    }
+    int32_t ovf = 0;
+    for (int32_t q = q0; q < q1; ++q) {
+      const int32_t i = s->brorder[q];
+      if (s->brroff[q] != ovf) return 35;
+      ovf += std::max(0, s->LT.rp[i + 1] - 1 - s->LT.rp[i] - kRegionAhead);
+    }
+    if (ovf > s->back_region_entries_max || q1 - q0 > s->back_region_rows_max) return 35;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t t = item[i];
+    for (int32_t p = s->LT.rp[i] + 1; p < s->LT.rp[i + 1]; ++p) {
+      const int32_t j = s->LT.ci[p];
+      const int code = s->brcode[size_t(p)];
+      if (j <= i) return 36;
+      if (item[j] == t) {
+        if ((code & 0x8000) || code != pos[j] - s->britem_ptr[t] || !(s->brlloc[pos[j]] < s->brlloc[pos[i]]))
+          return 37;
+      } else {
+        const int xi = code & 0x7fff;
+        if (!(code & 0x8000) || !(item[j] < t) || xi >= s->brext_ptr[t + 1] - s->brext_ptr[t]) return 38;
+        if (s->brext[size_t(s->brext_ptr[t] + xi)] != j) return 38;
+      }
+    }
+  }
+  return 0;
+}
+
 int validate_forward(const sf_schedule_s* s) {
   if (s->kind == SF_ILU0_TRSV) return validate_ilu_plan(s);
   int r = validate_plan(s, s->order, s->item_ptr, nullptr);
@@ -1115,6 +1253,7 @@ int validate_forward(const sf_schedule_s* s) {
   if (r == 0 && s->regioned) r = validate_region_plan(s);
   if (r == 0 && s->has_back) r = validate_back_plan(s, s->border, s->bitem_ptr, nullptr);
   if (r == 0 && s->bchunked) r = validate_back_plan(s, s->bcorder, s->bcitem_ptr, &s->bclloc);
+  if (r == 0 && s->bregioned) r = validate_back_region_plan(s);
   return r;
 }
 

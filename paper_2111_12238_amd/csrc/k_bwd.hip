@@ -20,7 +20,7 @@
 // order of L.
 #pragma clang fp contract(off)
 
-#include "stream.h"
+#include "region_core.h"
 
 namespace sf {
 namespace {
@@ -126,6 +126,96 @@ __global__ __launch_bounds__(kBlockThreads) void k_bwd(BwdArgs a) {
   }
 }
 
+// The backward region plan: regions of the transposed solve on blocks of a
+// computing and a polling wavefront (region_core.h).  A region row i stages
+// c_i = sum_r A_ri g_r (ascending r, from 0: the product interleaved into the
+// solve, as above) as its right-hand side and L's column i below the
+// diagonal as its entries; lambda is published through the readiness
+// protocol.  The grad_L rows follow every region in claim order, as items of
+// up to kGradRows rows of L in row order (64 per wavefront and pass), each
+// lambda_i read through the readiness protocol, so no region waits for them.
+constexpr int kGradRows = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kRegionThreads) void k_bwd_region(BwdArgs a, RegionArgs r) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int32_t ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
+  const T* __restrict__ Av = static_cast<const T*>(a.Av);
+  const T* __restrict__ Gv = static_cast<const T*>(a.G);
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  T* lam = static_cast<T*>(a.lam);
+  T* __restrict__ gL = static_cast<T*>(a.gradL);
+  const int R = r.rows_max;
+  const int total = a.n_work + (a.n + kGradRows - 1) / kGradRows;
+  dev::reset_next_launch(a.ls);
+  if (wid == 0) {
+    const int t = dev::claim(a.ls, lane);
+    if (lane == 0) ticket = t;
+  }
+  __syncthreads();
+  for (;;) {
+    const int t = ticket;
+    __syncthreads();
+    if (t >= total) break;
+    int32_t next_raw = 0;
+    if (wid == 0) next_raw = dev::claim_issue(a.ls, lane);
+    if (t < a.n_work) {
+      const int q0 = a.item_ptr[t], q1 = a.item_ptr[t + 1];
+      auto stage = [&](const RegionLds<T>& L, int k) {
+        const int i = a.order[q0 + k];
+        const int e0 = a.LTrp[i], e1 = a.LTrp[i + 1];  // diagonal first
+        // c_i: the row of A^T, eight entries' loads at a time, folded in order from 0
+        T c = T(0);
+        const int c0 = a.ATrp[i], c1 = a.ATrp[i + 1];
+        for (int p0 = c0; p0 < c1; p0 += 8) {
+          int mp[8], cp[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int p = min(p0 + e, c1 - 1);
+            mp[e] = a.ATmap[p];
+            cp[e] = a.ATci[p];
+          }
+          T av[8], gv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            av[e] = Av[mp[e]];
+            gv[e] = Gv[cp[e]];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (p0 + e < c1) c = c + av[e] * gv[e];
+        }
+        stage_row<T>(L, R, k, i, c, Lv[a.LTmap[e0]], r.roff[q0 + k], e1 - e0 - 1, Lv, a.LTmap, e0 + 1, r.code);
+      };
+      region_core<T>(r, t, q0, q1, r.batch_ptr[t], r.batch_ptr[t + 1], lds, nullptr, lam, a.ls, nullptr, stage);
+    } else {
+      // grad_L rows [g0, g1) of L: lambda_i through the readiness protocol
+      const int g0 = (t - a.n_work) * kGradRows, g1 = min(a.n, g0 + kGradRows);
+      auto* w = reinterpret_cast<WaveLds<T>*>(lds) + wid;
+      for (int s0 = g0 + 64 * wid; s0 < g1; s0 += 128) {
+        const int nr = min(64, g1 - s0);
+        const bool mine = lane < nr;
+        const int i = mine ? s0 + lane : 0;
+        T li = mine ? dev::ld_co(lam + i) : T(0);
+        int32_t spins = 0;
+        while (__ballot(mine && dev::is_pending(li)) != 0) {
+          if (mine && dev::is_pending(li)) li = dev::ld_co(lam + i);
+          if (!dev::all_poll_round(spins, a.ls)) break;
+        }
+        grad_rows(a.Lrp, a.Lci, X, gL, nr, i, li, lane, *w);
+      }
+    }
+    __syncthreads();
+    if (wid == 0) {
+      const int tn = dev::claim_ticket(a.ls, next_raw);
+      if (lane == 0) ticket = tn;
+    }
+    __syncthreads();
+  }
+}
+
 // Preconditioner apply, z = L^{-T} (L^{-1} r), the solve pair a PCG
 // iteration with an incomplete Cholesky factor needs.  Work tickets
 // [0, n_fwd) are the forward plan's SpTRSV items (w_i = (r_i - sum L_ij w_j)
@@ -218,6 +308,29 @@ hipError_t launch_precond(const PrecondArgs& a, int dtype, int grid, hipStream_t
 }
 
 int occupancy_precond(int dtype) { return dtype == 0 ? occ(k_precond<double>) : occ(k_precond<float>); }
+
+size_t bwd_region_lds(const RegionArgs& r, int dtype) {
+  const int vb = dtype == 0 ? 8 : 4;
+  const size_t reg = region_lds_bytes(r.rows_max, r.entries_max, r.ext_max, r.batches_max, vb);
+  const size_t sp = 2 * (dtype == 0 ? sizeof(WaveLds<double>) : sizeof(WaveLds<float>));
+  return reg > sp ? reg : sp;
+}
+hipError_t launch_bwd_region(const BwdArgs& a, const RegionArgs& r, int dtype, int grid, hipStream_t st) {
+  if (!a.order || !a.item_ptr || !r.batch || !r.batch_ptr || !r.ext_ptr || !r.roff || !r.code)
+    return hipErrorInvalidValue;
+  const size_t lds = bwd_region_lds(r, dtype);
+  if (dtype == 0) hipLaunchKernelGGL(k_bwd_region<double>, dim3(grid), dim3(kRegionThreads), lds, st, a, r);
+  else hipLaunchKernelGGL(k_bwd_region<float>, dim3(grid), dim3(kRegionThreads), lds, st, a, r);
+  return hipGetLastError();
+}
+int occupancy_bwd_region(const RegionArgs& r, int dtype) {
+  const size_t lds = bwd_region_lds(r, dtype);
+  int b = 0;
+  const void* k = dtype == 0 ? reinterpret_cast<const void*>(k_bwd_region<double>)
+                             : reinterpret_cast<const void*>(k_bwd_region<float>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kRegionThreads, lds) != hipSuccess) return 1;
+  return b < 1 ? 1 : b;
+}
 
 int occupancy_bwd(int dtype, int g) {
   (void)g;

@@ -82,6 +82,10 @@ struct DeviceBuffers {
   int32_t *border = nullptr, *bitem_ptr = nullptr;
   int32_t *bcorder = nullptr, *bcitem_ptr = nullptr;
   uint8_t *bclloc = nullptr, *bceloc = nullptr;
+  // backward region plan
+  int32_t *brorder = nullptr, *britem_ptr = nullptr, *brroff = nullptr;
+  int32_t *brbatch = nullptr, *brbatch_ptr = nullptr, *brext = nullptr, *brext_ptr = nullptr;
+  uint16_t* brcode = nullptr;
   // prefix fusion (level plan)
   int32_t *pqrng = nullptr, *apre = nullptr;
   // region plan
@@ -214,6 +218,15 @@ struct sf_schedule_s {
   std::vector<int32_t> bcorder, bcitem_ptr;
   std::vector<uint8_t> bclloc, bceloc;  // per claim position; per stored L^T entry
   int32_t back_chunk_chain = 0;
+  // Backward region plan (the transposed solve's regions, as the forward
+  // region plan over L^T; brcode indexed by L^T position).
+  bool bregioned = false;
+  std::vector<int32_t> brorder, britem_ptr, brroff, brbatch, brbatch_ptr, brext, brext_ptr;
+  std::vector<uint8_t> brlloc;
+  std::vector<uint16_t> brcode;
+  int32_t back_region_rows_max = 0, back_region_entries_max = 0, back_region_ext_max = 0,
+          back_region_batches_max = 0, back_region_chain = 0;
+  double est_back_region_us = 0.0, est_back_chunk_pipe_us = 0.0;
   double est_back_level_us = 0.0, est_back_chunk_us = 0.0;
 
   // SpIC0 intersection lists, one list per stored L entry (i, j), j < i:
