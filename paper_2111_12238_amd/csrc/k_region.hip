@@ -116,6 +116,92 @@ __global__ __launch_bounds__(kRegionThreads) void k_ts_region(TsArgs a, RegionAr
   }
 }
 
+// Kernel combinations 2 and 1 (Table 2) on the region plan's SpTRSV
+// regions (item_list, n_work regions).  MODE 2: y = A x, z = L^{-1} y -- a
+// region row stages y_i = sum_j A_ij x_j (A's row in order, from 0; x is
+// input) as its right-hand side, stores it to Y, and the regions publish z
+// into X.  MODE 1: x = L^{-1} b, z = L^{-1} x -- tickets [0, n_work) solve
+// x into X from B, tickets [n_work, 2 n_work) solve z into Y, a row staging
+// its x_i (F = I) through the readiness protocol; every z region follows
+// every x region in claim order.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kRegionThreads) void k_pair_region(TsArgs a, RegionArgs r) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int32_t ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
+  const T* __restrict__ B = static_cast<const T*>(a.B);
+  const int R = r.rows_max;
+  const int total = MODE == 1 ? 2 * a.n_work : a.n_work;
+  dev::reset_next_launch(a.ls);
+  if (wid == 0) {
+    const int t = dev::claim(a.ls, lane);
+    if (lane == 0) ticket = t;
+  }
+  __syncthreads();
+  for (;;) {
+    const int t = ticket;
+    __syncthreads();
+    if (t >= total) break;
+    int32_t next_raw = 0;
+    if (wid == 0) next_raw = dev::claim_issue(a.ls, lane);
+    const bool second = MODE == 1 && t >= a.n_work;
+    const int item = a.item_list[second ? t - a.n_work : t];
+    const int q0 = a.item_ptr[item], q1 = a.item_ptr[item + 1];
+    T* out = static_cast<T*>(second ? a.Y : a.X);
+    auto stage = [&](const RegionLds<T>& L, int k) {
+      const int id = a.order[q0 + k];
+      const int2 rg = reinterpret_cast<const int2*>(a.qrng)[q0 + k];
+      T bi;
+      if constexpr (MODE == 2) {
+        bi = T(0);
+        const int p0 = a.Arp[id], p1 = a.Arp[id + 1];
+        const T* __restrict__ Av = static_cast<const T*>(a.Av);
+        for (int c0 = p0; c0 < p1; c0 += 8) {
+          int cj[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) cj[e] = a.Aci[min(c0 + e, p1 - 1)];
+          T av[8], xv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            av[e] = dev::ld_stream(Av + min(c0 + e, p1 - 1));
+            xv[e] = B[cj[e]];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (c0 + e < p1) bi = bi + av[e] * xv[e];
+        }
+        if (a.Y) __builtin_nontemporal_store(bi, static_cast<T*>(a.Y) + id);
+      } else if (second) {
+        // x_i, published by the first solve's region of row i
+        const T* xp = static_cast<const T*>(a.X) + id;
+        bi = ld_co(xp);
+        int32_t spins = 0;
+        while (is_pending(bi)) {
+          __builtin_amdgcn_s_sleep(1);
+          bi = ld_co(xp);
+          if (++spins >= a.ls.spin_limit) {
+            dev::report_timeout(a.ls);
+            break;
+          }
+        }
+      } else {
+        bi = B[id];
+      }
+      stage_row<T>(L, R, k, id, bi, dev::ld_stream(Lv + rg.y), r.roff[q0 + k], rg.y - rg.x, Lv, nullptr, rg.x,
+                   r.code);
+    };
+    region_core<T>(r, item, q0, q1, r.batch_ptr[item], r.batch_ptr[item + 1], lds, nullptr, out, a.ls, nullptr,
+                   stage);
+    __syncthreads();
+    if (wid == 0) {
+      const int tn = dev::claim_ticket(a.ls, next_raw);
+      if (lane == 0) ticket = tn;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename K>
 int occ64(K kernel, size_t lds) {
   int b = 0;
@@ -137,6 +223,22 @@ size_t region_kernel_lds(const RegionArgs& r, int dtype) {
 int occupancy_region(const RegionArgs& r, int dtype) {
   const size_t lds = region_kernel_lds(r, dtype);
   return dtype == 0 ? occ64(k_ts_region<double>, lds) : occ64(k_ts_region<float>, lds);
+}
+
+hipError_t launch_pair_region(const TsArgs& a, const RegionArgs& r, int dtype, int mode, int grid, hipStream_t st) {
+  if (!a.order || !a.qrng || !a.item_ptr || !a.item_list || !r.batch || !r.batch_ptr || !r.ext_ptr || !r.roff ||
+      !r.code || (mode == 2 && (!a.Arp || !a.Aci)) || (mode == 1 && !a.Y))
+    return hipErrorInvalidValue;
+  const int vb = dtype == 0 ? 8 : 4;
+  const size_t lds = region_lds_bytes(r.rows_max, r.entries_max, r.ext_max, r.batches_max, vb);
+  if (mode == 2) {
+    if (dtype == 0) hipLaunchKernelGGL((k_pair_region<double, 2>), dim3(grid), dim3(kRegionThreads), lds, st, a, r);
+    else hipLaunchKernelGGL((k_pair_region<float, 2>), dim3(grid), dim3(kRegionThreads), lds, st, a, r);
+  } else {
+    if (dtype == 0) hipLaunchKernelGGL((k_pair_region<double, 1>), dim3(grid), dim3(kRegionThreads), lds, st, a, r);
+    else hipLaunchKernelGGL((k_pair_region<float, 1>), dim3(grid), dim3(kRegionThreads), lds, st, a, r);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_ts_region(const TsArgs& a, const RegionArgs& r, int dtype, int grid, hipStream_t st) {

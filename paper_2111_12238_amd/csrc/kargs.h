@@ -70,6 +70,8 @@ struct RegionArgs {
 size_t region_kernel_lds(const RegionArgs& r, int dtype);
 int occupancy_region(const RegionArgs& r, int dtype);
 hipError_t launch_bwd_region(const struct BwdArgs& a, const RegionArgs& r, int dtype, int grid, hipStream_t st);
+hipError_t launch_pair_region(const struct TsArgs& a, const RegionArgs& r, int dtype, int mode, int grid,
+                              hipStream_t st);
 int occupancy_bwd_region(const RegionArgs& r, int dtype);
 
 // Level-set (unfused) SpTRSV: items grouped by level, one grid barrier each.

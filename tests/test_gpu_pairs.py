@@ -1,7 +1,7 @@
 """GPU parity of the fused kernel combinations 1 (SpTRSV -> SpTRSV with one
 L) and 2 (SpMV -> SpTRSV) of the paper's Table 2, and of the preconditioner
-apply z = L^{-T} L^{-1} r, against the oracle's sequential kernels, on level
-and coarsened plans: FP64 results bit for bit."""
+apply z = L^{-T} L^{-1} r, against the oracle's sequential kernels, on level,
+coarsened and region plans: FP64 results bit for bit."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -34,7 +34,7 @@ CASES = ["lap2d5_64", "lap3d7_20", "lap2d9_64", "random_spd", "ragged"]
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("coarsen", [1, 2])
+@pytest.mark.parametrize("coarsen", [1, 2, 3])
 def test_spmv_trsv_bit_identical(orc, name, coarsen):
     announce("pair spmv->trsv %s coarsen=%d" % (name, coarsen))
     import torch
@@ -54,7 +54,7 @@ def test_spmv_trsv_bit_identical(orc, name, coarsen):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("coarsen", [1, 2])
+@pytest.mark.parametrize("coarsen", [1, 2, 3])
 def test_trsv_trsv_bit_identical(orc, name, coarsen):
     announce("pair trsv->trsv %s coarsen=%d" % (name, coarsen))
     import torch
