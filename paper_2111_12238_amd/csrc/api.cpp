@@ -1146,6 +1146,7 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
     const int grid = persistent_grid(s, occupancy_ic0(s->lanes_trsv, 0));
     a.trace = s->trace;
     a.rtrace = a.trace ? a.trace + s->trace_items * kTraceItemWords : nullptr;
+    a.cached = s->ic0_cached;
     if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));  // counts start at 0
     // every factor value and x_i is its own readiness flag
     SF_HIP(launch_fill_pending(L_val, size_t(s->L.nnz()), 0, st));
@@ -1751,6 +1752,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     s->no_fusion = v ? 1 : 0;
   } else if (k == "timing") {
     s->timing = v ? 1 : 0;
+  } else if (k == "ic0_cached") {
+    if (v < 0 || v > 1) return SF_ERR_ARG;
+    s->ic0_cached = int32_t(v);
   } else if (k == "spmv_prefix") {
     if (v < 0 || v > 1) return SF_ERR_ARG;
     s->spmv_prefix = int32_t(v);
@@ -1809,6 +1813,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "timing") *v = s->timing;
   else if (k == "trace") *v = s->trace ? 1 : 0;
   else if (k == "spmv_prefix") *v = s->spmv_prefix;
+  else if (k == "ic0_cached") *v = s->ic0_cached;
   else if (k == "prefix_rows") *v = s->prefix_rows;  // read only: SpMV rows with a fusable prefix
   else if (k == "prefix_entries") *v = s->prefix_entries;  // read only: A entries in those prefixes
   else return SF_ERR_ARG;

@@ -79,11 +79,41 @@ __device__ __forceinline__ double row_bcast16(double v) {
   return __builtin_bit_cast(double, (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo));
 }
 
+// Lane u (< 32) of every 32-lane group to the whole group: row_newbcast
+// of lane u mod 16 inside each 16-lane row, then v_permlane16_swap, which
+// exchanges the rows of each pair -- the even row's value for u < 16, the
+// odd row's for u >= 16.
+template <int U>
+__device__ __forceinline__ double row_bcast32(double v) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  int h[2] = {int(unsigned(bits)), int(unsigned(bits >> 32))};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int b = __builtin_amdgcn_update_dpp(0, h[k], 0x150 + (U & 15), 0xf, 0xf, false);
+    const auto sw = __builtin_amdgcn_permlane16_swap(b, b, false, false);
+    h[k] = int(U < 16 ? sw[0] : sw[1]);
+  }
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(unsigned(h[1])) << 32) | unsigned(h[0]));
+}
+
 // The value of lane u of the lane's G-lane group (u < G, a constant after
 // unrolling).
 template <int G>
 __device__ __forceinline__ double group_bcast(double v, int u) {
-  if constexpr (G == 16) {
+  if constexpr (G == 32) {
+    switch (u) {
+#define SF_B(U) \
+  case U:       \
+    return row_bcast32<U>(v);
+      SF_B(0) SF_B(1) SF_B(2) SF_B(3) SF_B(4) SF_B(5) SF_B(6) SF_B(7)
+      SF_B(8) SF_B(9) SF_B(10) SF_B(11) SF_B(12) SF_B(13) SF_B(14) SF_B(15)
+      SF_B(16) SF_B(17) SF_B(18) SF_B(19) SF_B(20) SF_B(21) SF_B(22) SF_B(23)
+      SF_B(24) SF_B(25) SF_B(26) SF_B(27) SF_B(28) SF_B(29) SF_B(30) SF_B(31)
+#undef SF_B
+      default:
+        return v;
+    }
+  } else if constexpr (G == 16) {
     switch (u) {
 #define SF_B(U) \
   case U:       \
@@ -104,10 +134,23 @@ __device__ __forceinline__ double group_bcast(double v, int u) {
 // is final, tr[5] after the sweep, tr[6] after the pivot fold, tr[3] after
 // its stores (the last batch's stamps stay); per row, the stamp taken just
 // before its first store and its publication count.
+// The fused executor's hand-over between consecutive items of a wavefront:
+// the next ticket's claim atomic (raw, issued before the item runs), then
+// the next ticket t and its claim-position range rg, and the next item's
+// first row indices of this lane (row id, off-diagonal range, pair range),
+// each loaded while the current item waits for something else anyway.
+struct Ic0Next {
+  int32_t raw;
+  int t;
+  int2 rg;
+  bool have;  // i, qr, pr hold the current item's row indices
+  int i;
+  int2 qr, pr;
+};
+
 template <int G, bool FUSED>
 __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int lane, double* group_lds,
-                                         int next = -1, int2* next_rg = nullptr,
-                                         unsigned long long* tr = nullptr) {
+                                         unsigned long long* tr = nullptr, Ic0Next* nx = nullptr) {
   constexpr int RPB = 64 / G;
   const int sub = lane & (G - 1);
   double* lds_row = group_lds + tri_row(sub);
@@ -115,11 +158,11 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
   for (int base = q0; base < q1; base += RPB) {
     const int q = base + lane / G;
     const bool act = q < q1;
-    const int i = act ? a.order[q] : 0;
-    const int2 rg = act ? reinterpret_cast<const int2*>(a.qrng)[q] : make_int2(0, 0);
+    const bool pre = nx && nx->have && base == q0;
+    const int i = pre ? nx->i : act ? a.order[q] : 0;
+    const int2 rg = pre ? nx->qr : act ? reinterpret_cast<const int2*>(a.qrng)[q] : make_int2(0, 0);
     // the pairs of row i are contiguous: every entry's list, in entry order
-    const int2 pr = act ? reinterpret_cast<const int2*>(a.prng)[q] : make_int2(0, 0);
-    if (next_rg && base == q0) *next_rg = next >= 0 ? make_int2(a.item_ptr[next], a.item_ptr[next + 1]) : make_int2(0, 0);
+    const int2 pr = pre ? nx->pr : act ? reinterpret_cast<const int2*>(a.prng)[q] : make_int2(0, 0);
     const int r0 = rg.x, rd = rg.y;              // off-diagonals [r0, rd); the diagonal at rd
     const int len = rd - r0;                     // off-diagonal entries (<= G)
     const bool mine = act && sub < len;
@@ -132,6 +175,12 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
     // the indices: they wait for nothing)
     double d = (act && sub == 0) ? a.Aval[rd] : 1.0;
     double s = (act && sub == 0 && a.solve) ? a.B[i] : 0.0;
+    if (nx && base == q0) {
+      // the next ticket (its atomic has been in flight since before this
+      // item) and its range: waited for while this item's loads are out
+      nx->t = dev::claim_ticket(a.ls, nx->raw);
+      nx->rg = nx->t < a.n_work ? make_int2(a.item_ptr[nx->t], a.item_ptr[nx->t + 1]) : make_int2(0, 0);
+    }
     // M[t][u] = L_{j_t, k_u} where row j_t meets row i below column j_t, else absent
     for (int u = 0; u < G; ++u)
       if (u < sub) lds_row[u] = kAbsent;
@@ -169,8 +218,25 @@ __device__ __forceinline__ void ic0_rows(const Ic0Args& a, int q0, int q1, int l
         __asm__ volatile("" ::"v"(tu[0]), "v"(pjj), "v"(j));
         if (lane == 0) tr[1] = __builtin_amdgcn_s_memrealtime();
       }
+      // (cached first: a cached read returns the value or the pending
+      // pattern -- a value changes once per launch and every launch starts
+      // with the caches invalidated -- and wait_ptrs re-reads pending ones
+      // device-coherently)
+      if (FUSED && a.cached) {
 #pragma unroll
-      for (int e = 0; e < R; ++e) v[e] = ptr[e] ? ld_co(ptr[e]) : 0.0;
+        for (int e = 0; e < R; ++e) v[e] = ptr[e] ? *ptr[e] : 0.0;
+      } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[e] = ptr[e] ? ld_co(ptr[e]) : 0.0;
+      }
+      if (nx && base == q0 && rnd == 0) {
+        // the next item's row indices, in flight with this item's values
+        const int qn = nx->rg.x + lane / G;
+        const bool an = qn < nx->rg.y;
+        nx->i = an ? a.order[qn] : 0;
+        nx->qr = an ? reinterpret_cast<const int2*>(a.qrng)[qn] : make_int2(0, 0);
+        nx->pr = an ? reinterpret_cast<const int2*>(a.prng)[qn] : make_int2(0, 0);
+      }
       if constexpr (FUSED) dev::wait_ptrs<double, R, 64>(ptr, v, lane, a.ls);
       if (FUSED && tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();
 #pragma unroll
@@ -252,10 +318,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
   const int lane = threadIdx.x & 63;
   double* group_lds = lds + size_t(threadIdx.x / G) * grp_size<G>();
   dev::reset_next_launch(a.ls);
-  // every item, in claim order (no item list): the next ticket is claimed
-  // before an item runs and its range loaded inside it (see ic0_rows)
+  // every item, in claim order (no item list): the next ticket's atomic
+  // goes out before an item runs; the ticket, its range and its rows'
+  // indices are loaded inside the item (ic0_rows, Ic0Next)
   int t = dev::claim(a.ls, lane);
   int2 rg = t < a.n_work ? make_int2(a.item_ptr[t], a.item_ptr[t + 1]) : make_int2(0, 0);
+  Ic0Next nx{};
+  nx.have = false;
   while (t < a.n_work) {
     unsigned long long* tr = a.trace ? a.trace + size_t(t) * kTraceItemWords : nullptr;
     if (tr && lane == 0) {
@@ -265,11 +334,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_ic0_fused(Ic0Args a) {
       tr[2] = t0;
       atomicAdd(tr + 4, 1ull);
     }
-    const int tn = dev::claim(a.ls, lane);
-    int2 rgn;
-    ic0_rows<G, true>(a, rg.x, rg.y, lane, group_lds, tn < a.n_work ? tn : -1, &rgn, tr);
-    t = tn;
-    rg = rgn;
+    nx.raw = dev::claim_issue(a.ls, lane);
+    ic0_rows<G, true>(a, rg.x, rg.y, lane, group_lds, tr, &nx);
+    nx.have = true;
+    t = nx.t;
+    rg = nx.rg;
   }
   write_info(a, lane);
 }

@@ -122,6 +122,8 @@ struct Ic0Args {
   int32_t solve;           // 1: also solve L x = b in the same item
   int32_t factor;          // 1: compute the factor (0: solve with a given factor)
   int32_t* d_info;         // written by the last wave (may be nullptr)
+  int32_t cached;          // fused SpIC0: 1 = pair values, pivots and x read through the caches first
+                           // (re-read device-coherently while pending, as stream.h's VEC = 3)
   unsigned long long* trace;   // optional (fused SpIC0): kTraceItemWords words per item
   unsigned long long* rtrace;  // with trace: per row its publication stamp and count
   LaunchState ls;
