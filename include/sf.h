@@ -102,9 +102,12 @@ typedef struct {
   int32_t no_fusion;      /* 1: executor calls run the unfused two-phase baseline instead (the
                              paper's fusion = False switch, Sec. 2.3) */
   int32_t coarsen;        /* work items of the one-right-hand-side fused SpTRSV -> SpMV
-                             executor: 0 = choose by the inspector's critical-path estimate,
-                             1 = one wavefront per item, 2 = coarsened items spanning several
-                             wavefronts (the paper's w-partitions of an s-partition, Sec. 3.2) */
+                             executor (and of sf_backward's transposed solve): 0 = choose by
+                             the inspector's critical-path estimates, 1 = one wavefront per
+                             item, 2 = coarsened items spanning several wavefronts (the
+                             paper's w-partitions of an s-partition, Sec. 3.2), 3 = regions of
+                             up to "region_rows" rows on a block of a computing and a polling
+                             wavefront, the region's data in LDS */
 } sf_inspect_opts;
 
 /* Summary of a schedule (host values). */
@@ -510,9 +513,29 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *                               (default): 0 with level items, after every
  *                               SpTRSV item with coarsened ones (Sec. 3.2's
  *                               slack placement);
- *   "coarsen"                   0 auto, 1 level items, 2 coarsened items
- *                               (re-cuts; "coarsened", "back_coarsened" read
- *                               the plans in effect);
+ *   "coarsen"                   0 auto, 1 level items, 2 coarsened items,
+ *                               3 regions (re-cuts; "coarsened", "regioned",
+ *                               "back_coarsened", "back_regioned" read the
+ *                               plans in effect, "region_chain" and
+ *                               "back_region_chain" the longest chains of
+ *                               dependent regions);
+ *   "region_rows"               rows per region (64..16384, default 512; halved
+ *                               at inspection until a region's LDS fits 64 KB);
+ *   "region_poll"               region poller: lanes watching inputs (bits 0-7,
+ *                               1..64, default 64) and back-off rounds after an
+ *                               idle round (bits 8-15, default 0);
+ *   "cached_reads"              fused executor: bit 0 = SpMV rows, bit 1 =
+ *                               SpTRSV level items read x through the caches
+ *                               first (default 0);
+ *   "spmv_prefix"               prefix fusion on level items (default 1): SpMV
+ *                               row r's entries up to its diagonal, when their
+ *                               columns are exactly L's row r, are folded by
+ *                               SpTRSV row r's item and the SpMV row continues
+ *                               the fold (bit-identical); "prefix_rows" and
+ *                               "prefix_entries" (read only) count the rows
+ *                               and entries that qualify;
+ *   "ic0_cached"                fused SpIC0: values read through the caches
+ *                               first (default 0);
  *   "no_fusion", "timing", "trace"   switches (0/1).
  */
 sf_status sf_set_param(sf_schedule s, const char* key, int64_t value);
@@ -546,7 +569,9 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
 sf_status sf_sync_status(sf_schedule s, void* stream);
 
 /* Trace mode (sf_set_param(s, "trace", 1)): the fused single-RHS
- * SpTRSV -> SpMV executor records a debug execution trace that shows every
+ * SpTRSV -> SpMV executor (and the fused SpIC0 -> SpTRSV executor, whose
+ * items also stamp words 5 and 6: the end of the sweep and of the pivot
+ * fold) records a debug execution trace that shows every
  * iteration ran exactly once and after its inputs (the validity of a fused
  * schedule, Sec. 3.1: each DAG edge respected, each iteration executed once).
  * out (HOST) receives, for work item t (export order), 8 words at out[8t]:
