@@ -129,11 +129,12 @@ def sources_sha():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_bytes_key):
+def load_traffic(name):
     """Measured bytes per launch beyond L2 (rocprofv3 --pmc FETCH_SIZE and
-    WRITE_SIZE, calibrated on a copy kernel) from the committed summary, or
-    None when the kernel or inspector sources changed since it was taken.
-    The summary holds "key: value" lines."""
+    WRITE_SIZE, calibrated on a copy kernel) of matrix `name` from the
+    committed summary, with the schedule parameters the counters were taken
+    at ({} if not recorded): (None, {}) when the kernel or inspector sources
+    changed since it was taken. The summary holds "key: value" lines."""
     t = {}
     try:
         with open(TRAFFIC_FILE) as f:
@@ -142,13 +143,15 @@ def load_traffic(kernel_bytes_key):
                     k, v = line.split(":", 1)
                     t[k.strip()] = v.strip()
     except OSError:
-        return None
-    if t.get("sources_sha") != sources_sha() or kernel_bytes_key not in t:
-        return None
+        return None, {}
+    key = "bytes_per_launch_" + name
+    if t.get("sources_sha") != sources_sha() or key not in t:
+        return None, {}
+    params = dict(kv.split("=") for kv in t.get("params_" + name, "").split(",") if "=" in kv)
     try:
-        return int(float(t[kernel_bytes_key]))
+        return int(float(t[key])), {k: int(v) for k, v in params.items()}
     except ValueError:
-        return None
+        return None, {}
 
 
 def main():
@@ -161,6 +164,9 @@ def main():
                     help="comma list of extras to run: ic0, ilu0, small, batched, pairs, fwdbwd (default all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--params", default=None,
+                    help="'matrix:key=value,...;matrix:...': set these on the headline schedules instead of "
+                         "autotuning them (the counter runs use the parameters of a timed run)")
     ap.add_argument("--no-probe", action="store_true", help="skip the device probes (no bounds)")
     ap.add_argument("--probe-only", choices=("copy", "hop", "gather", "all"),
                     help="run one device probe, print its JSON line and exit")
@@ -201,11 +207,24 @@ def main():
                  Y=torch.empty(A.nrows, dtype=torch.float64, device=dev),
                  bytes=ts_bytes(L.nrows, A.nrows, L.nnz, A.nnz), depth=st.depth, joint_depth=st.joint_depth,
                  inspect_s=st.inspect_seconds)
-        if not args.no_autotune:
+        keys = ("coarsen", "coarsened", "regioned", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu",
+                "cached_reads", "spmv_prefix")
+        if args.params:
+            given = {}
+            for part in args.params.split(";"):
+                mat, _, kvs = part.partition(":")
+                if mat.strip() == name:
+                    given = dict(kv.split("=") for kv in kvs.split(",") if kv)
+            for k in ("coarsen", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu", "cached_reads",
+                      "spmv_prefix"):
+                if k in given:
+                    s.set_param(k, int(given[k]))
+            d["params"] = {k: s.get_param(k) for k in keys}
+            log("parameters of %s from %s: %s" % (name, args.params,
+                                                   " ".join("%s=%d" % kv for kv in d["params"].items())))
+        elif not args.no_autotune:
             t0 = time.time()
             sfm.autotune(s, d["Lv"], d["Av"], d["B"])
-            keys = ("coarsen", "coarsened", "regioned", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu",
-                    "cached_reads", "spmv_prefix")
             d["params"] = {k: s.get_param(k) for k in keys}
             log("autotuned %s in %.1fs: %s" % (name, time.time() - t0,
                                                 " ".join("%s=%d" % kv for kv in d["params"].items())))
@@ -315,12 +334,19 @@ def main():
     j = int(np.argmax(kern_ms))
     dk = work[j]
     achieved = dk["bytes"] / (kern_ms[j] * 1e-3) / 1e9
-    traffic = load_traffic("bytes_per_launch_" + dk["name"])
+    traffic, traffic_params = load_traffic(dk["name"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "%s (%s)" % (dk["kernel"], dk["name"]), "algorithmic_bytes_per_launch": dk["bytes"],
                 "avg_launch_ms": round(kern_ms[j], 4),
                 "avg_call_ms": round(per_launch[j], 4)}  # the call: pending fills + kernel
+    if traffic is not None:
+        # the counters ran at fixed schedule parameters; say whether this
+        # run's (autotuned) schedule is the one they measured
+        mine = dk.get("params") or {}
+        roofline["traffic_params"] = traffic_params
+        roofline["traffic_params_match"] = bool(traffic_params) and all(
+            mine.get(k) == v for k, v in traffic_params.items())
 
     per_matrix = {}
     for k, d in enumerate(work):
