@@ -522,8 +522,10 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *   "region_rows"               rows per region (64..16384, default 512; halved
  *                               at inspection until a region's LDS fits 64 KB);
  *   "region_poll"               region poller: lanes watching inputs (bits 0-7,
- *                               1..64, default 64) and back-off rounds after an
- *                               idle round (bits 8-15, default 0);
+ *                               1..64, default 64), back-off rounds after an
+ *                               idle round (bits 8-15, default 0) and lanes
+ *                               reading until the region's first input is
+ *                               stored (bits 16-23, 0..64, 0 = all; default 2);
  *   "cached_reads"              fused executor: bit 0 = SpMV rows, bit 1 =
  *                               SpTRSV level items read x through the caches
  *                               first (default 0);
@@ -536,7 +538,7 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *                               and entries that qualify;
  *   "ic0_cached"                fused SpIC0: values read through the caches
  *                               first (default 0);
- *   "no_fusion", "timing", "trace"   switches (0/1).
+ *   "no_fusion", "timing", "trace"   switches (0/1; "trace" 2: items only).
  */
 sf_status sf_set_param(sf_schedule s, const char* key, int64_t value);
 sf_status sf_get_param(sf_schedule s, const char* key, int64_t* value);
@@ -571,7 +573,9 @@ sf_status sf_sync_status(sf_schedule s, void* stream);
 /* Trace mode (sf_set_param(s, "trace", 1)): the fused single-RHS
  * SpTRSV -> SpMV executor (and the fused SpIC0 -> SpTRSV executor, whose
  * items also stamp words 5 and 6: the end of the sweep and of the pivot
- * fold) records a debug execution trace that shows every
+ * fold; on the region plan a region stamps word 1 when staged, 5 when its
+ * first input from another region is stored and 6 when its first batch is
+ * published) records a debug execution trace that shows every
  * iteration ran exactly once and after its inputs (the validity of a fused
  * schedule, Sec. 3.1: each DAG edge respected, each iteration executed once).
  * out (HOST) receives, for work item t (export order), 8 words at out[8t]:
@@ -583,7 +587,9 @@ sf_status sf_sync_status(sf_schedule s, void* stream);
  * number of times it was published.  count must be >= 8 n_items + 2 (n + m);
  * otherwise SF_ERR_SHAPE.  Waits for the last executor call on the schedule.
  * Each traced launch starts from zeroed counts.  Tracing adds stores and
- * atomics to every item: a debugging aid, not a timed mode. */
+ * atomics to every item: a debugging aid, not a timed mode.  With "trace"
+ * set to 2 only the items are stamped (iteration words stay 0), which
+ * slows the launch far less. */
 sf_status sf_trace_export(sf_schedule s, unsigned long long* out, int64_t count);
 
 /* Time of the last kernel launched by an executor call, measured with HIP

@@ -381,6 +381,16 @@ sf_status exec_multi_core(sf_schedule_s* s, int dtype, const void* Lv, const voi
   return hip_status(launch_ts_multi(a, dtype, kb, grid, st));
 }
 
+// The region poller's settings from the "region_poll" parameter: lanes
+// (bits 0-7), back-off rounds (bits 8-15), lanes before the first input
+// (bits 16-23, 0 = all lanes).
+static void set_poll(RegionArgs& r, int32_t v) {
+  r.poll_lanes = std::max(1, std::min(64, v & 0xff));
+  r.poll_sleep = (v >> 8) & 0xff;
+  const int gate = (v >> 16) & 0xff;
+  r.poll_gate = gate == 0 ? r.poll_lanes : std::min(gate, r.poll_lanes);
+}
+
 RegionArgs region_args(const sf_schedule_s* s) {
   RegionArgs r{};
   r.batch = s->dev.rbatch;
@@ -393,8 +403,7 @@ RegionArgs region_args(const sf_schedule_s* s) {
   r.entries_max = std::max(1, s->region_entries_max);
   r.ext_max = std::max(1, s->region_ext_max);
   r.batches_max = std::max(1, s->region_batches_max);
-  r.poll_lanes = std::max(1, std::min(64, s->region_poll & 0xff));
-  r.poll_sleep = (s->region_poll >> 8) & 0xff;
+  set_poll(r, s->region_poll);
   return r;
 }
 
@@ -411,8 +420,7 @@ RegionArgs back_region_args(const sf_schedule_s* s) {
   r.entries_max = std::max(1, s->back_region_entries_max);
   r.ext_max = std::max(1, s->back_region_ext_max);
   r.batches_max = std::max(1, s->back_region_batches_max);
-  r.poll_lanes = std::max(1, std::min(64, s->region_poll & 0xff));
-  r.poll_sleep = (s->region_poll >> 8) & 0xff;
+  set_poll(r, s->region_poll);
   return r;
 }
 
@@ -455,7 +463,7 @@ sf_status exec_ts_fused(sf_schedule_s* s, sf_dtype dt, const void* Lv, const voi
     a.col_units = nrhs;
     a.cached = s->cached_reads;
     a.trace = nrhs == 1 ? s->trace : nullptr;
-    a.rtrace = a.trace ? a.trace + s->trace_items * kTraceItemWords : nullptr;
+    a.rtrace = a.trace && s->trace_level == 1 ? a.trace + s->trace_items * kTraceItemWords : nullptr;
     if (s->regioned) {
       a.order = s->dev.rorder;
       a.qrng = s->dev.rqrng;
@@ -1145,7 +1153,7 @@ static sf_status ic0_common(sf_schedule s, sf_dtype dtype, const void* A_lower_v
     a.solve = solve ? 1 : 0;
     const int grid = persistent_grid(s, occupancy_ic0(s->lanes_trsv, 0));
     a.trace = s->trace;
-    a.rtrace = a.trace ? a.trace + s->trace_items * kTraceItemWords : nullptr;
+    a.rtrace = a.trace && s->trace_level == 1 ? a.trace + s->trace_items * kTraceItemWords : nullptr;
     a.cached = s->ic0_cached;
     if (a.trace) SF_HIP(launch_fill_u64(a.trace, int32_t(trace_words(s)), st));  // counts start at 0
     // every factor value and x_i is its own readiness flag
@@ -1738,7 +1746,7 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     const sf_status rc = recut(s);
     if (rc != SF_OK) return rc;
   } else if (k == "region_poll") {
-    if ((v & 0xff) < 1 || (v & 0xff) > 64 || v < 0 || v > 0xffff) return SF_ERR_ARG;
+    if ((v & 0xff) < 1 || (v & 0xff) > 64 || ((v >> 16) & 0xff) > 64 || v < 0 || v > 0xffffff) return SF_ERR_ARG;
     s->region_poll = int32_t(v);
   } else if (k == "cached_reads") {
     if (v < 0 || v > 3) return SF_ERR_ARG;
@@ -1759,7 +1767,10 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
     if (v < 0 || v > 1) return SF_ERR_ARG;
     s->spmv_prefix = int32_t(v);
   } else if (k == "trace") {
-    // trace mode: the fused single-RHS executor stamps every item (debug aid)
+    // trace mode: the fused single-RHS executor stamps every item (debug
+    // aid); 2: items only, no per-iteration publication stamps
+    if (v < 0 || v > 2) return SF_ERR_ARG;
+    s->trace_level = int32_t(v);
     if (s->trace) {
       wait_done(s);
       hipFree(s->trace);
@@ -1811,7 +1822,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "tuned_from_cache") *v = s->tuned_from_cache;  // read only: last sf_autotune reused a result
   else if (k == "fingerprint") *v = int64_t(pattern_fingerprint(s) & 0x7fffffffffffffffull);
   else if (k == "timing") *v = s->timing;
-  else if (k == "trace") *v = s->trace ? 1 : 0;
+  else if (k == "trace") *v = s->trace ? s->trace_level : 0;
   else if (k == "spmv_prefix") *v = s->spmv_prefix;
   else if (k == "ic0_cached") *v = s->ic0_cached;
   else if (k == "prefix_rows") *v = s->prefix_rows;  // read only: SpMV rows with a fusable prefix

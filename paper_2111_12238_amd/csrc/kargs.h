@@ -66,6 +66,7 @@ struct RegionArgs {
   const uint16_t* code;      // per stored L entry: in-region position, or 0x8000 | external index
   int32_t rows_max, entries_max, ext_max, batches_max;  // LDS sizing (largest region)
   int32_t poll_lanes, poll_sleep;  // poller: lanes watching inputs, back-off (x 128 cycles) after an idle round
+  int32_t poll_gate;               // poller lanes reading until the region's first input is stored
 };
 size_t region_kernel_lds(const RegionArgs& r, int dtype);
 int occupancy_region(const RegionArgs& r, int dtype);

@@ -170,27 +170,39 @@ __device__ void region_core(const RegionArgs& r, int item, int q0, int q1, int b
     L.xa[L.zero] = T(0);
   }
   __syncthreads();
+  if (tr && tid == 0) tr[1] = __builtin_amdgcn_s_memrealtime();  // staged
   if (wid == 1) {
-    // the poller: its first W lanes watch inputs lane, lane + W, ... in
-    // first-use order (W = r.poll_lanes), backing off r.poll_sleep after a
-    // round in which none of them became final
-    const int W = r.poll_lanes;
-    int k = lane < W ? lane : nx;
+    // the poller: lane l watches input k_lo + l, where k_lo is the first
+    // input (in first-use order) not yet stored; each round the window
+    // slides past its stored prefix, so every lane moves on to a pending
+    // input at once.  At most r.poll_lanes lanes read per round, and until
+    // the region's first input is stored (a region claimed ahead of its
+    // producers waits there) only r.poll_gate: every read is one more
+    // request on the memory side, where the publications travel too.  After
+    // a round in which nothing became final it backs off r.poll_sleep.
+    uint64_t done = 0;  // bit l: input k_lo + l stored
+    int k_lo = 0;
     int32_t spins = 0;
-    for (;;) {
-      if (__ballot(k < nx) == 0) break;
-      const T v = k < nx ? ld_co(X + L.xc[k]) : T(0);
-      const bool got = k < nx && !is_pending(v);
-      if (got) {
-        lds_put(L.xa + R + k, v);
-        k += W;
-      }
+    while (k_lo < nx) {
+      const int k = k_lo + lane;
+      const int F = k_lo == 0 ? r.poll_gate : r.poll_lanes;
+      const bool want = lane < F && k < nx && !((done >> lane) & 1ull);
+      T v = pending_value<T>();
+      if (want) v = ld_co(X + L.xc[k]);
+      const bool got = want && !is_pending(v);
+      if (got) lds_put(L.xa + R + k, v);
+      const uint64_t g = __ballot(got);
+      if (tr && k_lo == 0 && g != 0 && lane == 0) tr[5] = __builtin_amdgcn_s_memrealtime();  // first input
+      done |= g;
+      const int sh = done == ~0ull ? 64 : __builtin_ctzll(~done);
+      k_lo += sh;
+      done = sh == 64 ? 0ull : done >> sh;
       if (!dev::all_poll_round(spins, ls)) {
         // watchdog: release every input still pending so the region drains
         for (int q = lane; q < nx; q += 64) lds_put(L.xa + R + q, T(0));
         break;
       }
-      if (__ballot(got) == 0)
+      if (g == 0)
         for (int z = 0; z < r.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
     }
     if (tr && lane == 0) tr[2] = __builtin_amdgcn_s_memrealtime();  // every input observed
@@ -243,6 +255,7 @@ __device__ void region_core(const RegionArgs& r, int item, int q0, int q1, int b
         if (rtrace) dev::stamp_publish(rtrace, true, c.id);
         st_co(X + c.id, xk);
       }
+      if (tr && bl == 0 && lane == 0) tr[6] = __builtin_amdgcn_s_memrealtime();  // first batch published
       __builtin_amdgcn_wave_barrier();
     }
   }

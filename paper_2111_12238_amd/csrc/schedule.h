@@ -197,7 +197,8 @@ struct sf_schedule_s {
   int64_t prefix_entries = 0;           // A entries in those prefixes (diagonals included)
   std::vector<int32_t> pqrng, apre;
   int32_t region_rows = 512;
-  int32_t region_poll = 64;          // poller lanes (bits 0-7) and back-off rounds (bits 8-15)
+  int32_t region_poll = 64 | (2 << 16);  // poller lanes (bits 0-7), back-off rounds (bits 8-15),
+                                         // lanes before the first input (bits 16-23)
   bool regioned = false;             // the region plan is in effect for the fused executor
   std::vector<int32_t> rorder, ritem_ptr, rtrsv_items, rqrng, rroff;
   std::vector<uint8_t> rlloc;
@@ -263,6 +264,7 @@ struct sf_schedule_s {
   int32_t tuned_from_cache = 0;         // the last sf_autotune call did
   uint64_t fingerprint = 0;             // of the patterns (computed on first use; 0: not yet)
   unsigned long long* trace = nullptr;  // device trace buffer (trace mode, layout at kTraceItemWords)
+  int32_t trace_level = 0;              // 1: items and iterations, 2: items only
   size_t trace_items = 0;               // item records in it (rows follow them)
   double last_kernel_ms = -1.0;
   double reuse = 0.0, inspect_seconds = 0.0;

@@ -100,7 +100,12 @@ def test_params_roundtrip():
                  ("no_fusion", 1)):
         s.set_param(k, v)
         assert s.get_param(k) == v
-    for k, bad in (("waves_per_cu", 2), ("multi_waves_per_cu", 64), ("levelset_waves_per_cu", 3)):
+    assert s.get_param("region_poll") == 64 | (2 << 16)
+    s.set_param("region_poll", 32 | (1 << 8) | (64 << 16))
+    assert s.get_param("region_poll") == 32 | (1 << 8) | (64 << 16)
+    for k, bad in (("waves_per_cu", 2), ("multi_waves_per_cu", 64), ("levelset_waves_per_cu", 3),
+                   ("region_poll", 0), ("region_poll", 65), ("region_poll", 64 | (65 << 16)), ("region_poll", 1 << 24),
+                   ("trace", 3)):
         with pytest.raises(sfm.SparseFusionError):
             s.set_param(k, bad)
     with pytest.raises(sfm.SparseFusionError):

@@ -68,6 +68,27 @@ def test_region_plan_bit_identical(orc, name, rows):
     assert np.array_equal(host(X2), xr), name
 
 
+@pytest.mark.parametrize("poll", [1, 7, 64 | (1 << 16), 64 | (64 << 16), 16 | (3 << 8) | (4 << 16), 64 | (2 << 16)])
+@pytest.mark.parametrize("delay", [-1, 0, 3])
+def test_region_poller_settings_bit_identical(orc, poll, delay):
+    """The poller's lanes, first-input gate and back-off, and the SpMV rows'
+    placement, change only when values are seen, never the results."""
+    import torch
+    L, A = _case("lap3d7_24")
+    b = synth.vec_uniform(L.nrows, seed=3)
+    s = sfm.Schedule(L, A, coarsen=3)
+    s.set_param("region_poll", poll)
+    s.set_param("spmv_delay", delay)
+    assert s.get_param("region_poll") == poll and s.get_param("regioned") == 1
+    announce("region poller %#x spmv_delay %d" % (poll, delay))
+    X, Y = sfm.trsv_spmv(s, dev(L.val), dev(A.val), dev(b))
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    xr, yr = _oracle(orc, L, A, b)
+    assert np.array_equal(host(X), xr)
+    assert np.array_equal(host(Y), yr)
+
+
 def test_region_plan_fp32_equals_level_plan():
     """FP32: the same per-row arithmetic as the level plan, so equal bits."""
     import torch
