@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ts_spmv_fused_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2111_12238_amd", "csrc", f)
-                  for f in ("k_ts.hip", "k_region.hip", "ts_items.h", "stream.h", "dev_common.h", "kargs.h",
-                            "schedule.h", "inspect.cpp")]
+                  for f in ("k_ts.hip", "k_region.hip", "region_core.h", "ts_items.h", "stream.h", "dev_common.h",
+                            "kargs.h", "schedule.h", "inspect.cpp")]
 
 
 def log(msg):
