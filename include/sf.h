@@ -545,10 +545,12 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* value);
 
 /*
  * sf_autotune — time executor variants on the device with the caller's
- * data and keep the fastest: a coordinate search over the plan (level or
- * coarsened items), the several-RHS path and block width, the SpMV slack
- * delay, rows per item, the item cost budget and the residency (waves per
- * CU of the single- and multi-RHS executors).  The work done once per
+ * data and keep the fastest: a coordinate search over the plan (level
+ * items, coarsened items or regions), the several-RHS path and block width,
+ * the SpMV slack delay, rows per item, the item cost budget, the residency
+ * (waves per CU of the single- and multi-RHS executors) and prefix fusion.
+ * A candidate replaces the current choice only when it is at least 2%
+ * faster.  Cached-first reads are not searched: they measured no different.  The work done once per
  * matrix is amortised over many executions (the paper's inspector-executor
  * split, Sec. 2 and its NER metric, Sec. 4).  The chosen parameters are left
  * set on the schedule (sf_get_param reads them) and cached for the process,

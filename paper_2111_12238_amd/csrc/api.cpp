@@ -1961,7 +1961,6 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});
   if (r == SF_OK && nrhs == 1) r = try_param("max_item_nnz", {128, 256, 512, 1024, 2048});
   if (r == SF_OK && nrhs == 1) r = try_param("waves_per_cu", {4, 8, 16});
-  if (r == SF_OK && nrhs == 1) r = try_param("cached_reads", {1, 2, 3});
   if (r == SF_OK && Y && s->prefix_rows > 0) r = try_param("spmv_prefix", {0, 1});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_waves_per_cu", {8, 16, 32});
   if (r == SF_OK) r = upload(s, st);
