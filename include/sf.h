@@ -333,7 +333,9 @@ sf_status sf_exec_trsv_trsv(sf_schedule s, sf_dtype dtype, const void* L_val, co
  *   w = L^{-1} r, then z = L^{-T} w,
  * in one launch: the SpTRSV plan's items, then the transposed solve's items
  * (reversed wavefronts of L^T, Sec. 2.2 DAGs), each backward row reading
- * its own w_i as soon as it is final (F = I).  Needs a SF_TRSV_SPMV schedule
+ * its own w_i as soon as it is final (F = I).  When the schedule has region
+ * plans for both solves, both run on them (a transposed region stages the
+ * w_i of its rows); "precond_regions" = 0 keeps items.  Needs a SF_TRSV_SPMV schedule
  * inspected with want_backward = 1 (else SF_ERR_ARG); L is the factor (for
  * instance from sf_exec_ic0_trsv) in the inspected pattern.  One
  * right-hand side; R, W, Z are distinct device vectors of length n.  FP64
@@ -538,6 +540,9 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *                               and entries that qualify;
  *   "ic0_cached"                fused SpIC0: values read through the caches
  *                               first (default 0);
+ *   "precond_regions"           sf_exec_ic_apply runs both solves on their
+ *                               region plans when the schedule has both
+ *                               ("regioned" and "back_regioned"; default 1);
  *   "no_fusion", "timing", "trace"   switches (0/1; "trace" 2: items only).
  */
 sf_status sf_set_param(sf_schedule s, const char* key, int64_t value);

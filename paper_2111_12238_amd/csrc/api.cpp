@@ -708,9 +708,10 @@ sf_status pair_entry(sf_schedule s, sf_dtype dtype, int mode, const void* L_val,
   return exec_pair(s, dtype, mode, L_val, A_val, B, Y, Z, fused && !s->no_fusion, st);
 }
 
-// Preconditioner apply z = L^{-T} L^{-1} r (k_precond).  Fused: forward and
-// backward items in one launch; unfused: the forward solve as its own
-// launch, then a backward-only launch.
+// Preconditioner apply z = L^{-T} L^{-1} r.  Fused: forward and backward
+// items in one launch -- on both region plans when the schedule has them
+// (k_precond_region), else level or coarsened items (k_precond); unfused:
+// the forward solve as its own launch, then a backward-only launch.
 sf_status exec_precond(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void* R, void* W, void* Z, bool fused,
                        hipStream_t st) {
   const int dtype = dt == SF_F64 ? 0 : 1;
@@ -735,6 +736,27 @@ sf_status exec_precond(sf_schedule_s* s, sf_dtype dt, const void* Lv, const void
     a.border = d.border;
     a.bitem_ptr = d.bitem_ptr;
     a.n_bwd = int32_t(s->bitem_ptr.size() - 1);
+  }
+  if (fused && s->regioned && s->bregioned && !s->rtrsv_items.empty() && s->precond_regions) {
+    // both solves on their region plans, in one launch
+    a.forder = d.rorder;
+    a.fqrng = d.rqrng;
+    a.fitem_ptr = d.ritem_ptr;
+    a.fitems = d.rtrsv_items;
+    a.n_fwd = int32_t(s->rtrsv_items.size());
+    a.border = d.brorder;
+    a.bitem_ptr = d.britem_ptr;
+    a.n_bwd = int32_t(s->britem_ptr.size() - 1);
+    sf_status r = next_epoch(s, st, a.ls);
+    if (r != SF_OK) return r;
+    const RegionArgs rf = region_args(s), rb = back_region_args(s);
+    const int per_cu =
+        std::min(std::max(1, occupancy_precond_region(rf, rb, dtype)), std::max(1, s->waves_per_cu / 2));
+    const int grid = std::max(std::max(1, device_cus()) * per_cu, kStreams);
+    Timer tm(s, st);
+    SF_HIP(launch_fill_pending(W, size_t(s->n), dtype, st));
+    SF_HIP(launch_fill_pending(Z, size_t(s->n), dtype, st));
+    return hip_status(launch_precond_region(a, rf, rb, dtype, grid, st));
   }
   if (fused) {
     if (s->chunked) {
@@ -1766,6 +1788,9 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "spmv_prefix") {
     if (v < 0 || v > 1) return SF_ERR_ARG;
     s->spmv_prefix = int32_t(v);
+  } else if (k == "precond_regions") {
+    if (v < 0 || v > 1) return SF_ERR_ARG;
+    s->precond_regions = int32_t(v);
   } else if (k == "trace") {
     // trace mode: the fused single-RHS executor stamps every item (debug
     // aid); 2: items only, no per-iteration publication stamps
@@ -1824,6 +1849,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "timing") *v = s->timing;
   else if (k == "trace") *v = s->trace ? s->trace_level : 0;
   else if (k == "spmv_prefix") *v = s->spmv_prefix;
+  else if (k == "precond_regions") *v = s->precond_regions;
   else if (k == "ic0_cached") *v = s->ic0_cached;
   else if (k == "prefix_rows") *v = s->prefix_rows;  // read only: SpMV rows with a fusable prefix
   else if (k == "prefix_entries") *v = s->prefix_entries;  // read only: A entries in those prefixes

@@ -281,6 +281,80 @@ __global__ __launch_bounds__(kBlockThreads) void k_precond(PrecondArgs a) {
   }
 }
 
+// Preconditioner apply z = L^{-T} (L^{-1} r) on the two region plans, one
+// block of a computing and a polling wavefront per region (region_core).
+// Tickets [0, n_fwd) are the forward solve's regions (fitems: their item
+// indices in the forward region plan; right-hand side r_i, w published into
+// W); tickets [n_fwd, n_fwd + n_bwd) are the transposed solve's regions over
+// L^T (right-hand side w_i, read through the readiness protocol while the
+// region is staged; z published into Z).  Every transposed region follows
+// every forward one in claim order, so the staging waits only on forward
+// regions that are already claimed.
+template <typename T>
+__global__ __launch_bounds__(kRegionThreads) void k_precond_region(PrecondArgs a, RegionArgs rf, RegionArgs rb) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int32_t ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const T* __restrict__ Lv = static_cast<const T*>(a.Lv);
+  const T* __restrict__ Rv = static_cast<const T*>(a.R);
+  T* W = static_cast<T*>(a.W);
+  T* Z = static_cast<T*>(a.Z);
+  const int total = a.n_fwd + a.n_bwd;
+  dev::reset_next_launch(a.ls);
+  if (wid == 0) {
+    const int t = dev::claim(a.ls, lane);
+    if (lane == 0) ticket = t;
+  }
+  __syncthreads();
+  for (;;) {
+    const int t = ticket;
+    __syncthreads();
+    if (t >= total) break;
+    int32_t next_raw = 0;
+    if (wid == 0) next_raw = dev::claim_issue(a.ls, lane);
+    if (t < a.n_fwd) {
+      const int item = a.fitems[t];
+      const int q0 = a.fitem_ptr[item], q1 = a.fitem_ptr[item + 1];
+      auto stage = [&](const RegionLds<T>& L, int k) {
+        const int id = a.forder[q0 + k];
+        const int2 rg = reinterpret_cast<const int2*>(a.fqrng)[q0 + k];
+        stage_row<T>(L, rf.rows_max, k, id, Rv[id], dev::ld_stream(Lv + rg.y), rf.roff[q0 + k], rg.y - rg.x, Lv,
+                     nullptr, rg.x, rf.code);
+      };
+      region_core<T>(rf, item, q0, q1, rf.batch_ptr[item], rf.batch_ptr[item + 1], lds, nullptr, W, a.ls, nullptr,
+                     stage);
+    } else {
+      const int it = t - a.n_fwd;
+      const int q0 = a.bitem_ptr[it], q1 = a.bitem_ptr[it + 1];
+      auto stage = [&](const RegionLds<T>& L, int k) {
+        const int i = a.border[q0 + k];
+        const int e0 = a.LTrp[i], e1 = a.LTrp[i + 1];  // diagonal first
+        // w_i, published by the forward region of row i
+        T wi = dev::ld_co(W + i);
+        int32_t spins = 0;
+        while (is_pending(wi)) {
+          __builtin_amdgcn_s_sleep(1);
+          wi = dev::ld_co(W + i);
+          if (++spins >= a.ls.spin_limit) {
+            dev::report_timeout(a.ls);
+            break;
+          }
+        }
+        stage_row<T>(L, rb.rows_max, k, i, wi, Lv[a.LTmap[e0]], rb.roff[q0 + k], e1 - e0 - 1, Lv, a.LTmap, e0 + 1,
+                     rb.code);
+      };
+      region_core<T>(rb, it, q0, q1, rb.batch_ptr[it], rb.batch_ptr[it + 1], lds, nullptr, Z, a.ls, nullptr,
+                     stage);
+    }
+    __syncthreads();
+    if (wid == 0) {
+      const int tn = dev::claim_ticket(a.ls, next_raw);
+      if (lane == 0) ticket = tn;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename K>
 int occ(K kernel) {
   int b = 0;
@@ -328,6 +402,32 @@ int occupancy_bwd_region(const RegionArgs& r, int dtype) {
   int b = 0;
   const void* k = dtype == 0 ? reinterpret_cast<const void*>(k_bwd_region<double>)
                              : reinterpret_cast<const void*>(k_bwd_region<float>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kRegionThreads, lds) != hipSuccess) return 1;
+  return b < 1 ? 1 : b;
+}
+
+size_t precond_region_lds(const RegionArgs& rf, const RegionArgs& rb, int dtype) {
+  const int vb = dtype == 0 ? 8 : 4;
+  const size_t f = region_lds_bytes(rf.rows_max, rf.entries_max, rf.ext_max, rf.batches_max, vb);
+  const size_t b = region_lds_bytes(rb.rows_max, rb.entries_max, rb.ext_max, rb.batches_max, vb);
+  return f > b ? f : b;
+}
+hipError_t launch_precond_region(const PrecondArgs& a, const RegionArgs& rf, const RegionArgs& rb, int dtype,
+                                 int grid, hipStream_t st) {
+  if (!a.forder || !a.fqrng || !a.fitem_ptr || !a.fitems || !a.border || !a.bitem_ptr || !rf.batch ||
+      !rf.batch_ptr || !rf.ext_ptr || !rf.roff || !rf.code || !rb.batch || !rb.batch_ptr || !rb.ext_ptr || !rb.roff ||
+      !rb.code)
+    return hipErrorInvalidValue;
+  const size_t lds = precond_region_lds(rf, rb, dtype);
+  if (dtype == 0) hipLaunchKernelGGL(k_precond_region<double>, dim3(grid), dim3(kRegionThreads), lds, st, a, rf, rb);
+  else hipLaunchKernelGGL(k_precond_region<float>, dim3(grid), dim3(kRegionThreads), lds, st, a, rf, rb);
+  return hipGetLastError();
+}
+int occupancy_precond_region(const RegionArgs& rf, const RegionArgs& rb, int dtype) {
+  const size_t lds = precond_region_lds(rf, rb, dtype);
+  int b = 0;
+  const void* k = dtype == 0 ? reinterpret_cast<const void*>(k_precond_region<double>)
+                             : reinterpret_cast<const void*>(k_precond_region<float>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kRegionThreads, lds) != hipSuccess) return 1;
   return b < 1 ? 1 : b;
 }

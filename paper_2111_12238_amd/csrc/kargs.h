@@ -225,6 +225,10 @@ hipError_t launch_ilu0_levelset(const Ic0Args& a, int g, int grid, hipStream_t s
 int occupancy_ilu0(int g, int levelset);
 hipError_t launch_precond(const PrecondArgs& a, int dtype, int grid, hipStream_t st);
 int occupancy_precond(int dtype);
+// the apply on the forward and the transposed region plans (k_precond_region)
+hipError_t launch_precond_region(const PrecondArgs& a, const RegionArgs& rf, const RegionArgs& rb, int dtype,
+                                 int grid, hipStream_t st);
+int occupancy_precond_region(const RegionArgs& rf, const RegionArgs& rb, int dtype);
 hipError_t launch_residual(const ResArgs& a, hipStream_t st);
 hipError_t launch_final(const ResArgs& a, hipStream_t st);
 // Column-major <-> interleaved block layout (k_layout.hip).  dtype 0 = f64,

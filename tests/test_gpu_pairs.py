@@ -118,11 +118,12 @@ def test_pairs_full_size(orc, name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("coarsen", [1, 2])
+@pytest.mark.parametrize("coarsen", [1, 2, 3])
 def test_ic_apply_bit_identical(orc, name, coarsen):
     """w = L^{-1} r, z = L^{-T} w with the factor's own IC0 values where the
     pattern admits one (else L's values): forward and backward substitution
-    row by row, bit for bit, fused and unfused."""
+    row by row, bit for bit, fused and unfused; with coarsen = 3 the fused
+    apply on both region plans and on items."""
     announce("ic apply %s coarsen=%d" % (name, coarsen))
     import torch
     L, A = _case(name)
@@ -133,11 +134,15 @@ def test_ic_apply_bit_identical(orc, name, coarsen):
     wr = orc.trsv_lower(L.rowptr, L.col, lv, r)
     zr = orc.trsv_upper_t(L.rowptr, L.col, lv, wr)
     s = sfm.Schedule(L, A, coarsen=coarsen, want_backward=True)
-    for unfused in (False, True):
-        W, Z = sfm.ic_apply(s, dev(lv), dev(r), unfused=unfused)
-        torch.cuda.synchronize()
-        sfm.sync_status(s)
-        assert np.array_equal(host(W), wr) and np.array_equal(host(Z), zr), unfused
+    if coarsen == 3:
+        assert s.get_param("regioned") == 1 and s.get_param("back_regioned") == 1
+    for pr in ((1, 0) if coarsen == 3 else (1,)):
+        s.set_param("precond_regions", pr)
+        for unfused in (False, True):
+            W, Z = sfm.ic_apply(s, dev(lv), dev(r), unfused=unfused)
+            torch.cuda.synchronize()
+            sfm.sync_status(s)
+            assert np.array_equal(host(W), wr) and np.array_equal(host(Z), zr), (pr, unfused)
 
 
 def test_ic_apply_full_size(orc):
@@ -150,7 +155,9 @@ def test_ic_apply_full_size(orc):
     wr = orc.trsv_lower(L.rowptr, L.col, lv, r)
     zr = orc.trsv_upper_t(L.rowptr, L.col, lv, wr)
     s = sfm.Schedule(L, A, want_backward=True)
-    W, Z = sfm.ic_apply(s, dev(lv), dev(r))
-    torch.cuda.synchronize()
-    sfm.sync_status(s)
-    assert np.array_equal(host(W), wr) and np.array_equal(host(Z), zr)
+    assert s.get_param("regioned") == 1 and s.get_param("back_regioned") == 1  # the region apply
+    for rep in range(2):
+        W, Z = sfm.ic_apply(s, dev(lv), dev(r))
+        torch.cuda.synchronize()
+        sfm.sync_status(s)
+        assert np.array_equal(host(W), wr) and np.array_equal(host(Z), zr), rep
