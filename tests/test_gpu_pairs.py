@@ -145,6 +145,31 @@ def test_ic_apply_bit_identical(orc, name, coarsen):
             assert np.array_equal(host(W), wr) and np.array_equal(host(Z), zr), (pr, unfused)
 
 
+def test_ic_apply_fp32_regions_equal_items():
+    """FP32: the apply on the region plans does each row's arithmetic in the
+    same order as on items, so equal bits; both within FP32 rounding of the
+    FP64 result."""
+    announce("ic apply fp32 regions vs items lap3d7_20")
+    import torch
+    L, A = _case("lap3d7_20")
+    r = synth.vec_normal(L.nrows, seed=5)
+    s = sfm.Schedule(L, A, coarsen=3, want_backward=True)
+    assert s.get_param("regioned") == 1 and s.get_param("back_regioned") == 1
+    out = {}
+    for pr in (1, 0):
+        s.set_param("precond_regions", pr)
+        W, Z = sfm.ic_apply(s, dev(L.val, torch.float32), dev(r, torch.float32))
+        torch.cuda.synchronize()
+        sfm.sync_status(s)
+        out[pr] = (host(W), host(Z))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    s.set_param("precond_regions", 1)
+    W64, Z64 = sfm.ic_apply(s, dev(L.val), dev(r))
+    torch.cuda.synchronize()
+    z64 = host(Z64)
+    assert np.max(np.abs(out[1][1] - z64)) <= 1e-4 * np.max(np.abs(z64))
+
+
 def test_ic_apply_full_size(orc):
     announce("ic apply full size lap3d7_96")
     import torch
