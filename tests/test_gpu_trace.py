@@ -132,3 +132,39 @@ def test_trace_ic0_every_row_once_after_its_inputs(orc, perm):
     assert (slack >= 0).all(), int(slack.min())
     print("ic0 perm=%s: %d items, %d edges, min slack %d ticks" % (perm, n_items, int(i.size), int(slack.min())))
     s.free()
+
+
+@pytest.mark.parametrize("case,coarsen", [("lap3d7_24", 3), ("spd_30k", 1)])
+def test_trace_items_only(orc, case, coarsen):
+    """Trace level 2 stamps the items alone: every item ran exactly once
+    with ordered stamps, no iteration word is written, and the results stay
+    the oracle's.  On the region plan a region's stamps follow its steps:
+    claimed, staged, first input stored (when it has external inputs), first
+    batch published, ended."""
+    import torch
+    A = case_matrix(case)
+    L = synth.lower(A)
+    b = synth.vec_uniform(L.nrows, seed=2)
+    s = sfm.Schedule(L, A, coarsen=coarsen)
+    s.set_param("trace", 2)
+    assert s.get_param("trace") == 2
+    announce("trace items only %s coarsen=%d" % (case, coarsen))
+    X, Y = sfm.trsv_spmv(s, dev(L.val), dev(A.val), dev(b))
+    torch.cuda.synchronize()
+    sfm.sync_status(s)
+    xr = orc.trsv_lower(L.rowptr, L.col, L.val, b)
+    assert np.array_equal(host(X), xr)
+    assert np.array_equal(host(Y), orc.spmv(A.rowptr, A.col, A.val, xr))
+    items, rows = s.trace()
+    assert np.all(items[:, 4] == 1), "every item runs exactly once"
+    assert not rows.any(), "no iteration stamps at level 2"
+    it = items.astype(np.int64)
+    assert np.all(it[:, 0] <= it[:, 3]) and np.all(it[:, 0] <= it[:, 1])
+    if coarsen == 3:
+        assert s.get_param("regioned") == 1
+        reg = it[it[:, 6] > 0]  # regions (SpMV items publish no first batch)
+        assert len(reg) > 0
+        assert np.all(reg[:, 0] <= reg[:, 1]) and np.all(reg[:, 1] <= reg[:, 6]) and np.all(reg[:, 6] <= reg[:, 3])
+        ext = reg[reg[:, 5] > 0]
+        assert len(ext) > 0 and np.all(ext[:, 1] <= ext[:, 5])
+    s.set_param("trace", 0)
