@@ -208,7 +208,7 @@ def main():
                  bytes=ts_bytes(L.nrows, A.nrows, L.nnz, A.nnz), depth=st.depth, joint_depth=st.joint_depth,
                  inspect_s=st.inspect_seconds)
         keys = ("coarsen", "coarsened", "regioned", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu",
-                "cached_reads", "spmv_prefix")
+                "cached_reads", "spmv_prefix", "spmv_item_scale")
         if args.params:
             given = {}
             for part in args.params.split(";"):
@@ -216,7 +216,7 @@ def main():
                 if mat.strip() == name:
                     given = dict(kv.split("=") for kv in kvs.split(",") if kv)
             for k in ("coarsen", "spmv_delay", "rows_per_item", "max_item_nnz", "waves_per_cu", "cached_reads",
-                      "spmv_prefix"):
+                      "spmv_prefix", "spmv_item_scale"):
                 if k in given:
                     s.set_param(k, int(given[k]))
             d["params"] = {k: s.get_param(k) for k in keys}

@@ -540,6 +540,11 @@ size_t sf_refine_workspace_bytes(sf_schedule s, int32_t nrhs);
  *                               and entries that qualify;
  *   "ic0_cached"                fused SpIC0: values read through the caches
  *                               first (default 0);
+ *   "spmv_item_scale"           level items: an SpMV item takes up to this
+ *                               many times rows_per_item rows (at most 64)
+ *                               and max_item_nnz (1..8, default 4): they are
+ *                               off the critical path, and fewer, longer
+ *                               items stream faster;
  *   "precond_regions"           sf_exec_ic_apply runs both solves on their
  *                               region plans when the schedule has both
  *                               ("regioned" and "back_regioned"; default 1);
@@ -553,7 +558,8 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* value);
  * data and keep the fastest: a coordinate search over the plan (level
  * items, coarsened items or regions), the several-RHS path and block width,
  * the SpMV slack delay, rows per item, the item cost budget, the residency
- * (waves per CU of the single- and multi-RHS executors) and prefix fusion.
+ * (waves per CU of the single- and multi-RHS executors), the SpMV items'
+ * size on level items and prefix fusion.
  * A candidate replaces the current choice only when it is at least 2%
  * faster.  Cached-first reads are not searched: they measured no different.  The work done once per
  * matrix is amortised over many executions (the paper's inspector-executor

@@ -1788,6 +1788,11 @@ sf_status sf_set_param(sf_schedule s, const char* key, int64_t v) {
   } else if (k == "spmv_prefix") {
     if (v < 0 || v > 1) return SF_ERR_ARG;
     s->spmv_prefix = int32_t(v);
+  } else if (k == "spmv_item_scale") {
+    if (v < 1 || v > 8 || s->kind != SF_TRSV_SPMV) return SF_ERR_ARG;
+    s->spmv_item_scale = int32_t(v);
+    const sf_status rc = recut(s);
+    if (rc != SF_OK) return rc;
   } else if (k == "precond_regions") {
     if (v < 0 || v > 1) return SF_ERR_ARG;
     s->precond_regions = int32_t(v);
@@ -1850,6 +1855,7 @@ sf_status sf_get_param(sf_schedule s, const char* key, int64_t* v) {
   else if (k == "trace") *v = s->trace ? s->trace_level : 0;
   else if (k == "spmv_prefix") *v = s->spmv_prefix;
   else if (k == "precond_regions") *v = s->precond_regions;
+  else if (k == "spmv_item_scale") *v = s->spmv_item_scale;
   else if (k == "ic0_cached") *v = s->ic0_cached;
   else if (k == "prefix_rows") *v = s->prefix_rows;  // read only: SpMV rows with a fusable prefix
   else if (k == "prefix_entries") *v = s->prefix_entries;  // read only: A entries in those prefixes
@@ -1868,7 +1874,7 @@ namespace {
 // takes the tuned parameters without timing anything.
 const char* const kTuneKeys[] = {"coarsen",       "multi_path",   "rhs_block",    "spmv_delay",
                                  "rows_per_item", "max_item_nnz", "waves_per_cu", "multi_waves_per_cu",
-                                 "cached_reads",  "spmv_prefix"};
+                                 "cached_reads",  "spmv_prefix", "spmv_item_scale"};
 constexpr int kNTune = int(sizeof(kTuneKeys) / sizeof(kTuneKeys[0]));
 struct Tuned {
   int64_t v[kNTune];
@@ -1983,10 +1989,11 @@ sf_status sf_autotune(sf_schedule s, sf_dtype dtype, const void* L_val, const vo
   if (r == SF_OK && nrhs == 1) r = try_param("coarsen", {1, 2, 3});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_path", {1, 2});
   if (r == SF_OK && nrhs > 1) r = try_param("rhs_block", {8, 16, 32, 64});
-  if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 1 << 20});
+  if (r == SF_OK && Y) r = try_param("spmv_delay", {1, 2, 4, 8, 16, 32, 1 << 20});
   if (r == SF_OK) r = try_param("rows_per_item", {8, 16, 32, 64});
   if (r == SF_OK && nrhs == 1) r = try_param("max_item_nnz", {128, 256, 512, 1024, 2048});
   if (r == SF_OK && nrhs == 1) r = try_param("waves_per_cu", {4, 8, 16});
+  if (r == SF_OK && nrhs == 1 && Y && !s->chunked && !s->regioned) r = try_param("spmv_item_scale", {1, 2, 4});
   if (r == SF_OK && Y && s->prefix_rows > 0) r = try_param("spmv_prefix", {0, 1});
   if (r == SF_OK && nrhs > 1) r = try_param("multi_waves_per_cu", {8, 16, 32});
   if (r == SF_OK) r = upload(s, st);

@@ -117,20 +117,24 @@ static void counting_order(const std::vector<int32_t>& key, int32_t nkeys, std::
 
 // Cut `order` into items: a new item starts when the (level, kind) key
 // changes, when rows_per_item rows are reached, or when adding the next row
-// would exceed the nonzero budget (a single row always fits).
+// would exceed the nonzero budget (a single row always fits).  Runs of odd
+// keys (SpMV rows of the joint order) may take `odd_scale` times the rows
+// (at most 64) and the budget.
 static void cut_runs(const std::vector<int32_t>& order, const std::vector<int32_t>& key,
                      const std::vector<int32_t>& cost, int32_t rows_per_item, int32_t nnz_budget,
-                     std::vector<int32_t>& item_ptr) {
+                     std::vector<int32_t>& item_ptr, int32_t odd_scale = 1) {
   item_ptr.clear();
   item_ptr.push_back(0);
   const size_t N = order.size();
   size_t q = 0;
   while (q < N) {
     const int32_t k = key[order[q]];
+    const bool odd = (k & 1) != 0 && odd_scale > 1;
+    const int32_t rows = odd ? std::min(64, rows_per_item * odd_scale) : rows_per_item;
+    const int64_t budget = odd ? int64_t(nnz_budget) * odd_scale : int64_t(nnz_budget);
     int64_t c = cost[order[q]];
     size_t e = q + 1;
-    while (e < N && key[order[e]] == k && int32_t(e - q) < rows_per_item &&
-           c + cost[order[e]] <= nnz_budget) {
+    while (e < N && key[order[e]] == k && int32_t(e - q) < rows && c + cost[order[e]] <= budget) {
       c += cost[order[e]];
       ++e;
     }
@@ -716,7 +720,7 @@ void cut_items(sf_schedule_s* s) {
       cost[n + r] = std::max(1, s->A.rp[r + 1] - s->A.rp[r]);
     }
     counting_order(key, 2 * (last + 1), s->order);
-    cut_runs(s->order, key, cost, s->rows_per_item, s->max_item_nnz, s->item_ptr);
+    cut_runs(s->order, key, cost, s->rows_per_item, s->max_item_nnz, s->item_ptr, s->spmv_item_scale);
     s->trsv_items.clear();
     s->spmv_items.clear();
     for (size_t t = 0; t + 1 < s->item_ptr.size(); ++t) {

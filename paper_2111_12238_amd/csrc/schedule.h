@@ -193,6 +193,7 @@ struct sf_schedule_s {
   // -(start + 1).
   int32_t spmv_prefix = 1;              // 0: off
   int32_t precond_regions = 1;          // fused preconditioner apply on the region plans when both exist
+  int32_t spmv_item_scale = 4;          // level items: SpMV items take this many times the rows and budget
   int32_t ic0_cached = 0;               // fused SpIC0 reads its values through the caches first (Ic0Args::cached)
   int64_t prefix_rows = 0;              // SpMV rows with a fused prefix
   int64_t prefix_entries = 0;           // A entries in those prefixes (diagonals included)

@@ -102,13 +102,17 @@ def test_params_roundtrip():
         assert s.get_param(k) == v
     assert s.get_param("region_poll") == 64 | (2 << 16)
     assert s.get_param("precond_regions") == 1
+    assert s.get_param("spmv_item_scale") == 4
+    s.set_param("spmv_item_scale", 2)
+    assert s.get_param("spmv_item_scale") == 2
     s.set_param("precond_regions", 0)
     assert s.get_param("precond_regions") == 0
     s.set_param("region_poll", 32 | (1 << 8) | (64 << 16))
     assert s.get_param("region_poll") == 32 | (1 << 8) | (64 << 16)
     for k, bad in (("waves_per_cu", 2), ("multi_waves_per_cu", 64), ("levelset_waves_per_cu", 3),
                    ("region_poll", 0), ("region_poll", 65), ("region_poll", 64 | (65 << 16)), ("region_poll", 1 << 24),
-                   ("trace", 3), ("precond_regions", 2)):
+                   ("trace", 3), ("precond_regions", 2),
+                   ("spmv_item_scale", 0), ("spmv_item_scale", 9)):
         with pytest.raises(sfm.SparseFusionError):
             s.set_param(k, bad)
     with pytest.raises(sfm.SparseFusionError):

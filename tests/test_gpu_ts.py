@@ -566,3 +566,22 @@ def test_prefix_fusion(orc, case):
     s.set_param("spmv_delay", 1 << 20)  # SpMV rows after every SpTRSV row
     x2, y2 = run(s, L, A, b, dtype=dt)
     assert np.array_equal(x2, x0) and np.array_equal(y2, y0)
+
+
+@pytest.mark.parametrize("scale", [1, 2, 4, 8])
+def test_spmv_item_scale_bit_identical(orc, scale):
+    """Larger SpMV items on level items (spmv_item_scale) change only which
+    rows a wavefront claims together, never a row's terms or their order:
+    x and y equal the oracle's, with prefix fusion on and off."""
+    announce("ts spmv_item_scale %d" % scale)
+    A = synth.random_spd(30000, seed=11)
+    L = synth.lower(A)
+    b = synth.vec_uniform(L.nrows, seed=3)
+    s = sfm.Schedule(L, A, coarsen=1, rows_per_item=16)
+    s.set_param("spmv_item_scale", scale)
+    xr = orc.trsv_lower(L.rowptr, L.col, L.val, b)
+    yr = orc.spmv(A.rowptr, A.col, A.val, xr)
+    for prefix in (1, 0):
+        s.set_param("spmv_prefix", prefix)
+        x, y = run(s, L, A, b)
+        assert np.array_equal(x, xr) and np.array_equal(y, yr), prefix

@@ -49,10 +49,16 @@ def test_random_schedules(orc, seed, n, m, empty):
     L, A = _random_pair(n, seed, m, empty)
     for rows in (1, 7, 64):
         s = sfm.Schedule(L, A, rows_per_item=rows, max_item_nnz=50, validate=True, coarsen=1)
-        _check_schedule(orc, L, A, s)
-        _, _, ip = s.export()
-        sizes = np.diff(ip)
-        assert sizes.max() <= rows
+        for scale in (s.get_param("spmv_item_scale"), 1):
+            s.set_param("spmv_item_scale", scale)
+            _check_schedule(orc, L, A, s)
+            _, order, ip = s.export()
+            sizes = np.diff(ip)
+            spmv = order[ip[:-1]] >= L.nrows
+            # SpTRSV items hold at most rows_per_item rows, SpMV items (off
+            # the critical path) up to spmv_item_scale times that, at most 64
+            assert sizes[~spmv].max(initial=0) <= rows
+            assert sizes[spmv].max(initial=0) <= min(64, rows * scale)
 
 
 @pytest.mark.parametrize("delay", [1, 3, 1000])
@@ -176,15 +182,18 @@ def test_coarsen_choice():
 def test_item_nnz_budget():
     L, A = synth.workload("lap2d5_64")
     s = sfm.Schedule(L, A, rows_per_item=1000, max_item_nnz=40, coarsen=1)
+    scale = s.get_param("spmv_item_scale")
+    assert scale == 4
     level, order, ip = s.export()
     n = L.nrows
-    # cost c(v) = entries an iteration streams (SpTRSV: off-diagonals; at least 1)
+    # cost c(v) = entries an iteration streams (SpTRSV: off-diagonals; at least 1);
+    # SpMV items get spmv_item_scale times the budget
     cost = np.concatenate([np.maximum(1, np.diff(L.rowptr) - 1), np.maximum(1, np.diff(A.rowptr))])
     for t in range(len(ip) - 1):
         ids = order[ip[t]:ip[t + 1]]
-        assert len(ids) == 1 or cost[ids].sum() <= 40
         kinds = ids >= n
         assert kinds.all() or not kinds.any(), "an item mixes SpTRSV and SpMV rows"
+        assert len(ids) == 1 or cost[ids].sum() <= (40 * scale if kinds.all() else 40)
 
 
 def test_backward_schedule(orc):
